@@ -1,0 +1,197 @@
+/*
+ * cdi.h -- C ABI of the MI355X (gfx950) CDI + GNBC time step.
+ *
+ * One time step of the conservative diffuse-interface two-phase flow solver
+ * with the mass-conserving GNBC contact-line treatment of Brown, Mirjalili,
+ * Khanwale & Mani (arXiv:2412.16843):
+ *   - CDI phase-field equation with the regularisation (sharpening) flux
+ *     R = gamma [eps grad(phi) - phi(1-phi) n]            (Sec. 2, eq. CDI)
+ *   - no-flux phase-field walls and no-penetration walls   (Sec. 2, no-flux BC)
+ *   - mixture momentum with the consistent mass flux rho u - S,
+ *     S = (rho1 - rho2) R, variable viscosity               (Sec. 2, eq. NS_momentum)
+ *   - energy-based surface tension F = mu_c grad(phi) with the psi-form
+ *     chemical potential                                    (Sec. 2, eqs. EB surface
+ *                                                            tension, chemical potential)
+ *   - GNBC slip u_slip = (mu/beta) du/dn + u^Y, Model 4A u^Y (Sec. 2 eq. u_slip_Y,
+ *                                                            Sec. 3.1.2 eq. Model 4A)
+ *   - one-sided wall-normal stencils and linear extrapolation to the wall,
+ *     no phase-field ghost values                           (Sec. 4)
+ *   - RK4 with a variable-density pressure projection after every stage,
+ *     pressure by multigrid-preconditioned flexible CG      (Sec. 4; the paper
+ *                                                            defers the coupling
+ *                                                            to its references)
+ *
+ * Grid: uniform staggered, nx x ny cells of size h = lx/nx = ly/ny, x periodic,
+ * walls at y = 0 and y = ly.  All arrays are row-major with x fastest:
+ *   phi, p : ny * nx      cell centres ((i+1/2)h, (j+1/2)h)
+ *   u      : ny * nx      x-faces (i h, (j+1/2)h)
+ *   v      : (ny+1) * nx  y-faces ((i+1/2)h, j h); rows 0 and ny are the walls
+ *                         and must hold 0 (no penetration)
+ * phi = 1 is fluid 1.  The pressure p is the solution of
+ *   sum_faces (p_nb - p) / (rho_face h^2) = div(u*) / tau,  mean(p) = 0.
+ *
+ * Memory ownership: every device pointer (fields, workspace, RHS buffers) is
+ * owned by the caller and only borrowed for the lifetime of the context; the
+ * library allocates no device memory.  The context itself (host memory) is
+ * created by cdi_init / cdi_init_batch and freed by cdi_destroy.  All work is
+ * enqueued on the caller's HIP stream.
+ *
+ * Errors: every function returns a cdi_status (0 = success, < 0 = error) and
+ * never aborts; cdi_last_error() returns a thread-local message describing
+ * the last error.  Arguments are validated before any device work.
+ */
+#ifndef CDI_H
+#define CDI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CDI_ABI_VERSION 1
+
+typedef enum {
+  CDI_OK = 0,
+  CDI_ERR_ARG = -1,       /* invalid parameter value or null pointer            */
+  CDI_ERR_SHAPE = -2,     /* grid not supported (see cdi_init)                  */
+  CDI_ERR_DEVICE = -3,    /* a HIP runtime call failed                          */
+  CDI_ERR_NOCONV = -4,    /* pressure solve hit poisson_maxit before poisson_rtol */
+  CDI_ERR_NONFINITE = -5, /* a NaN / Inf appeared in the state                  */
+  CDI_ERR_STATE = -6      /* call not valid in the context's current state      */
+} cdi_status;
+
+enum { CDI_SLIP_1A = 0, CDI_SLIP_1B, CDI_SLIP_2A, CDI_SLIP_2B,
+       CDI_SLIP_3A, CDI_SLIP_3B, CDI_SLIP_4A, CDI_SLIP_4B };
+enum { CDI_FP64 = 0, CDI_MIXED = 1 };
+enum { CDI_GUESS_ZERO = 0, CDI_GUESS_PREV = 1, CDI_GUESS_LEARNED = 2 };
+
+/* Problem statement (Sec. 2 and Sec. 4 of the paper).  Any field left 0 where
+ * a default is stated takes that default. */
+typedef struct {
+  int32_t abi_version;   /* must be CDI_ABI_VERSION                                  */
+  int32_t nx, ny;        /* cells; nx >= 8, ny >= 8, both even                        */
+  double lx, ly;         /* domain; lx/nx must equal ly/ny (uniform h)                */
+  double eps;            /* interface thickness eps > 0               (eq. CDI)       */
+  double gamma;          /* regularisation velocity gamma > 0         (eq. CDI)       */
+  double sigma;          /* surface tension sigma >= 0                (eq. chem. pot.)*/
+  double theta_eq;       /* equilibrium contact angle in (0, pi), radians, measured
+                            inside fluid 1                              (eq. u_slip_Y) */
+  double rho1, rho2;     /* densities of fluid 1 (phi = 1) and fluid 2, > 0          */
+  double mu1, mu2;       /* viscosities, >= 0                                         */
+  double beta1, beta2;   /* wall friction, > 0; beta = (beta1-beta2) phi + beta2      */
+  double u_wall_bot;     /* tangential (+x) speed of the wall y = 0                   */
+  double u_wall_top;     /* tangential (+x) speed of the wall y = ly                  */
+  double dt;             /* > 0: fixed step; 0: cfl * min(h/|U|, h^2/nu, capillary,
+                            h^2/(gamma eps)) fixed at init                            */
+  double cfl;            /* used when dt == 0; 0 -> 0.2                               */
+  int32_t slip_model;    /* CDI_SLIP_4A (paper's choice); 1A..4B also accepted        */
+  int32_t precision;     /* CDI_FP64 or CDI_MIXED (FP32 stencils and V-cycle, FP64
+                            phase field, flux accumulation, CG vectors, residual)     */
+  int32_t guess;         /* initial guess of each pressure solve                      */
+  double poisson_rtol;   /* stop when ||f - K x||_2 <= rtol ||f||_2; 0 -> 1e-10       */
+  int32_t poisson_maxit; /* 0 -> 200                                                  */
+  int32_t mg_smooth;     /* red-black Gauss-Seidel sweeps before and after the coarse
+                            correction on every level; 0 -> 1                         */
+} cdi_params;
+
+/* Device pointers of one instance's state, layouts as above (caller-owned,
+ * FP64).  On cdi_init phi holds the initial phase field, u and v the initial
+ * velocity (walls of v = 0), p the initial pressure guess (may be zero). */
+typedef struct {
+  double* phi;
+  double* u;
+  double* v;
+  double* p;
+} cdi_fields;
+
+typedef struct cdi_ctx cdi_ctx;
+
+typedef struct {
+  int32_t iterations;  /* flexible-CG iterations of the solve                    */
+  int32_t converged;   /* 1 if relres <= poisson_rtol                            */
+  int32_t guess_used;  /* CDI_GUESS_* actually used                              */
+  int32_t pad;
+  double relres;       /* ||f - K x|| / ||f|| (recursive residual)               */
+  double bnorm;        /* ||f||                                                  */
+  double ms;           /* device time of the solve, milliseconds                 */
+} cdi_solve_info;
+
+typedef struct {
+  double t;            /* simulated time                                         */
+  int64_t step;        /* steps taken                                            */
+  double mass;         /* sum(phi) h^2 (FP64)                                    */
+  double mass0;        /* mass at init                                           */
+  double phi_min, phi_max;
+  double max_div;      /* max |div u| over cells                                 */
+  double max_uslip[2]; /* max |u_wall - U_wall| per wall (0 bottom, 1 top)       */
+  double max_uY[2];    /* max |u^Y| per wall                                     */
+  double ke;           /* kinetic energy 1/2 sum rho_f |u|^2 h^2                 */
+  int32_t last_iters;  /* iterations of the last pressure solve                  */
+  int32_t nonfinite;   /* 1 if a NaN / Inf was found                             */
+  double last_relres;
+} cdi_diag;
+
+/* Bytes of caller-provided device workspace for `n` instances described by
+ * params[0..n-1] (same layout as cdi_init_batch).  Returns 0 on invalid
+ * parameters (cdi_last_error() tells why). */
+size_t cdi_workspace_bytes(const cdi_params* params, int32_t n);
+
+/* Time step that cdi_init would fix for these parameters (dt, or the CFL rule
+ * when dt == 0).  Host-only; no device work.  Returns a negative value on
+ * invalid parameters. */
+double cdi_default_dt(const cdi_params* params);
+
+/* Create a context for one instance.  `workspace` must point to at least
+ * cdi_workspace_bytes(params, 1) bytes of device memory, 256-byte aligned.
+ * `hip_stream` is a hipStream_t (NULL = default stream).  The initial state
+ * in `fields` is read when cdi_step runs.  Supported grids: nx, ny even,
+ * nx, ny >= 8, and the multigrid hierarchy (halving both directions while
+ * both stay even) must end on a grid of at most 1024 cells. */
+cdi_status cdi_init(const cdi_params* params, const cdi_fields* fields, void* workspace,
+                    size_t workspace_bytes, void* hip_stream, cdi_ctx** out);
+
+/* Same for an ensemble of n independent instances (uneven grids allowed);
+ * every kernel of a step covers all instances in one launch, and each
+ * instance's pressure solve stops on its own convergence test. */
+cdi_status cdi_init_batch(const cdi_params* params, int32_t n, const cdi_fields* fields,
+                          void* workspace, size_t workspace_bytes, void* hip_stream,
+                          cdi_ctx** out);
+
+/* Advance every instance by nsteps RK4 steps (4 stage evaluations and 4
+ * projections each).  Returns CDI_ERR_NOCONV if a pressure solve did not reach
+ * poisson_rtol within poisson_maxit (the fields then hold the best iterate);
+ * CDI_ERR_NONFINITE if a non-finite value was detected. */
+cdi_status cdi_step(cdi_ctx* ctx, int32_t nsteps);
+
+/* Standalone pressure solve of instance 0 with the density of its current
+ * phase field: sum_faces (p_nb - p)/(rho_f h^2) = b - mean(b).  b: device,
+ * ny*nx (NULL = the right-hand side of the last projection); p: device,
+ * ny*nx, in: initial guess when params.guess == CDI_GUESS_PREV, out: the
+ * mean-free solution.  info may be NULL. */
+cdi_status cdi_solve_pressure(cdi_ctx* ctx, const double* b, double* p, cdi_solve_info* info);
+
+/* Diagnostics of instance `idx` for its current state (FP64 reductions on the
+ * device).  Synchronises the stream. */
+cdi_status cdi_diagnostics(cdi_ctx* ctx, int32_t idx, cdi_diag* out);
+
+/* Stage operator of instance 0 on its current fields (no time update, no
+ * projection): writes L_phi (ny*nx), L_mx (ny*nx) and L_my ((ny+1)*nx, wall
+ * rows 0) to the caller's device buffers, and the wall values per corner
+ * (2*nx each, bottom then top) of u^Y and u_wall - U_wall when the optional
+ * pointers are non-NULL.  The right-hand side of eq. CDI and of the momentum
+ * equation without the pressure gradient. */
+cdi_status cdi_eval_rhs(cdi_ctx* ctx, double* l_phi, double* l_mx, double* l_my,
+                        double* u_y, double* u_slip);
+
+/* Release the context (host memory only; caller buffers are untouched). */
+void cdi_destroy(cdi_ctx* ctx);
+
+/* Message of the last error on this thread ("" if none). */
+const char* cdi_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CDI_H */

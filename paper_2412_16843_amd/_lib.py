@@ -1,0 +1,116 @@
+"""ctypes binding of libcdi.so (include/cdi.h): argument marshalling only.
+
+Every step of the CDI + GNBC time step runs in the HIP kernels of the
+library; this module converts Python values into the C structs and checks
+return codes.  It fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcdi.so")
+
+CDI_ABI_VERSION = 1
+STATUS = {0: "CDI_OK", -1: "CDI_ERR_ARG", -2: "CDI_ERR_SHAPE", -3: "CDI_ERR_DEVICE",
+          -4: "CDI_ERR_NOCONV", -5: "CDI_ERR_NONFINITE", -6: "CDI_ERR_STATE"}
+SLIP = {"1A": 0, "1B": 1, "2A": 2, "2B": 3, "3A": 4, "3B": 5, "4A": 6, "4B": 7}
+CDI_FP64, CDI_MIXED = 0, 1
+GUESS = {"zero": 0, "prev": 1, "learned": 2}
+
+EXPORTS = ("cdi_workspace_bytes", "cdi_default_dt", "cdi_init", "cdi_init_batch", "cdi_step",
+           "cdi_solve_pressure", "cdi_diagnostics", "cdi_eval_rhs", "cdi_destroy",
+           "cdi_last_error")
+
+
+class cdi_params(C.Structure):
+    _fields_ = [("abi_version", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32),
+                ("lx", C.c_double), ("ly", C.c_double), ("eps", C.c_double),
+                ("gamma", C.c_double), ("sigma", C.c_double), ("theta_eq", C.c_double),
+                ("rho1", C.c_double), ("rho2", C.c_double), ("mu1", C.c_double),
+                ("mu2", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double),
+                ("u_wall_bot", C.c_double), ("u_wall_top", C.c_double), ("dt", C.c_double),
+                ("cfl", C.c_double), ("slip_model", C.c_int32), ("precision", C.c_int32),
+                ("guess", C.c_int32), ("poisson_rtol", C.c_double),
+                ("poisson_maxit", C.c_int32), ("mg_smooth", C.c_int32)]
+
+
+class cdi_fields(C.Structure):
+    _fields_ = [("phi", C.c_void_p), ("u", C.c_void_p), ("v", C.c_void_p), ("p", C.c_void_p)]
+
+
+class cdi_solve_info(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("converged", C.c_int32), ("guess_used", C.c_int32),
+                ("pad", C.c_int32), ("relres", C.c_double), ("bnorm", C.c_double),
+                ("ms", C.c_double)]
+
+
+class cdi_diag(C.Structure):
+    _fields_ = [("t", C.c_double), ("step", C.c_int64), ("mass", C.c_double),
+                ("mass0", C.c_double), ("phi_min", C.c_double), ("phi_max", C.c_double),
+                ("max_div", C.c_double), ("max_uslip", C.c_double * 2),
+                ("max_uY", C.c_double * 2), ("ke", C.c_double), ("last_iters", C.c_int32),
+                ("nonfinite", C.c_int32), ("last_relres", C.c_double)]
+
+
+class CDIError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """Load libcdi.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} not found: build it with "
+                           "`python -m paper_2412_16843_amd.build` (or __graft_entry__.build())")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, f64 = C.c_void_p, C.c_int32, C.c_double
+    P = C.POINTER
+    L.cdi_workspace_bytes.argtypes = [P(cdi_params), i32]
+    L.cdi_workspace_bytes.restype = C.c_size_t
+    L.cdi_default_dt.argtypes = [P(cdi_params)]
+    L.cdi_default_dt.restype = f64
+    L.cdi_init.argtypes = [P(cdi_params), P(cdi_fields), vp, C.c_size_t, vp, P(vp)]
+    L.cdi_init.restype = i32
+    L.cdi_init_batch.argtypes = [P(cdi_params), i32, P(cdi_fields), vp, C.c_size_t, vp, P(vp)]
+    L.cdi_init_batch.restype = i32
+    L.cdi_step.argtypes = [vp, i32]
+    L.cdi_step.restype = i32
+    L.cdi_solve_pressure.argtypes = [vp, vp, vp, P(cdi_solve_info)]
+    L.cdi_solve_pressure.restype = i32
+    L.cdi_diagnostics.argtypes = [vp, i32, P(cdi_diag)]
+    L.cdi_diagnostics.restype = i32
+    L.cdi_eval_rhs.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.cdi_eval_rhs.restype = i32
+    L.cdi_destroy.argtypes = [vp]
+    L.cdi_destroy.restype = None
+    L.cdi_last_error.argtypes = []
+    L.cdi_last_error.restype = C.c_char_p
+    _lib = L
+    return L
+
+
+def check(status: int, allow=()) -> int:
+    if status != 0 and status not in allow:
+        raise CDIError(status, lib().cdi_last_error().decode())
+    return status
+
+
+def make_params(p, precision: str = "fp64", guess: str = "prev", rtol: float = 0.0,
+                maxit: int = 0, mg_smooth: int = 0) -> cdi_params:
+    """Marshal a parameter object (attributes as in workloads.Params)."""
+    return cdi_params(
+        abi_version=CDI_ABI_VERSION, nx=p.nx, ny=p.ny, lx=p.lx, ly=p.ly, eps=p.eps,
+        gamma=p.gamma, sigma=p.sigma, theta_eq=p.theta_eq, rho1=p.rho1, rho2=p.rho2,
+        mu1=p.mu1, mu2=p.mu2, beta1=p.beta1, beta2=p.beta2, u_wall_bot=p.u_wall_bot,
+        u_wall_top=p.u_wall_top, dt=p.dt, cfl=0.0, slip_model=SLIP[p.slip_model],
+        precision=CDI_MIXED if precision == "mixed" else CDI_FP64, guess=GUESS[guess],
+        poisson_rtol=rtol, poisson_maxit=maxit, mg_smooth=mg_smooth)

@@ -1,0 +1,636 @@
+// Host side of the C ABI: parameter validation, multigrid hierarchy and
+// workspace layout, tile lists spanning every instance of a batch, and the
+// stream-ordered launch sequence of one RK4 step (4 stage evaluations, 4
+// variable-density projections by multigrid-preconditioned flexible CG).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/cdi.h"
+#include "diag_kernels.h"
+
+using namespace cdi;
+
+namespace {
+
+thread_local std::string g_err;
+
+cdi_status fail(cdi_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+#define HIPCHK(x)                                                                 \
+  do {                                                                            \
+    hipError_t e_ = (x);                                                          \
+    if (e_ != hipSuccess)                                                         \
+      return fail(CDI_ERR_DEVICE, "%s failed: %s", #x, hipGetErrorString(e_));    \
+  } while (0)
+
+constexpr double RK_C[4] = {0.0, 0.5, 0.5, 1.0};
+constexpr double RK_B[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
+
+struct Resolved {
+  cdi_params p;
+  double h, dt, rtol;
+  int maxit, nlev, lc;
+  int lnx[kMaxLevels], lny[kMaxLevels];
+};
+
+double cfl_dt(const cdi_params& p, double h) {
+  const double cfl = p.cfl > 0 ? p.cfl : 0.2;
+  double m = INFINITY;
+  const double uw = std::max(std::fabs(p.u_wall_bot), std::fabs(p.u_wall_top));
+  if (uw > 0) m = std::min(m, h / uw);
+  const double nu = std::max(p.mu1 / p.rho1, p.mu2 / p.rho2);
+  if (nu > 0) m = std::min(m, h * h / nu);
+  if (p.sigma > 0) m = std::min(m, std::sqrt((p.rho1 + p.rho2) * h * h * h / (4.0 * M_PI * p.sigma)));
+  if (p.gamma * p.eps > 0) m = std::min(m, h * h / (p.gamma * p.eps));
+  return cfl * m;
+}
+
+cdi_status resolve(const cdi_params* in, Resolved& r) {
+  if (!in) return fail(CDI_ERR_ARG, "params is NULL");
+  const cdi_params& p = *in;
+  if (p.abi_version != CDI_ABI_VERSION)
+    return fail(CDI_ERR_ARG, "abi_version %d != %d", p.abi_version, CDI_ABI_VERSION);
+  if (p.nx < 8 || p.ny < 8 || (p.nx & 1) || (p.ny & 1))
+    return fail(CDI_ERR_SHAPE, "nx=%d ny=%d: both must be even and >= 8", p.nx, p.ny);
+  if (!(p.lx > 0) || !(p.ly > 0)) return fail(CDI_ERR_ARG, "lx, ly must be > 0");
+  const double hx = p.lx / p.nx, hy = p.ly / p.ny;
+  if (std::fabs(hx - hy) > 1e-12 * hx) return fail(CDI_ERR_SHAPE, "lx/nx=%g != ly/ny=%g", hx, hy);
+  if (!(p.eps > 0)) return fail(CDI_ERR_ARG, "eps must be > 0");
+  if (!(p.gamma > 0)) return fail(CDI_ERR_ARG, "gamma must be > 0");
+  if (!(p.sigma >= 0)) return fail(CDI_ERR_ARG, "sigma must be >= 0");
+  if (!(p.theta_eq > 0 && p.theta_eq < M_PI)) return fail(CDI_ERR_ARG, "theta_eq must be in (0, pi)");
+  if (!(p.rho1 > 0 && p.rho2 > 0)) return fail(CDI_ERR_ARG, "densities must be > 0");
+  if (!(p.mu1 >= 0 && p.mu2 >= 0)) return fail(CDI_ERR_ARG, "viscosities must be >= 0");
+  if (!(p.beta1 > 0 && p.beta2 > 0)) return fail(CDI_ERR_ARG, "beta1, beta2 must be > 0");
+  if (!std::isfinite(p.u_wall_bot) || !std::isfinite(p.u_wall_top))
+    return fail(CDI_ERR_ARG, "wall speeds must be finite");
+  if (p.dt < 0 || !std::isfinite(p.dt)) return fail(CDI_ERR_ARG, "dt must be >= 0");
+  if (p.cfl < 0) return fail(CDI_ERR_ARG, "cfl must be >= 0");
+  if (p.slip_model < CDI_SLIP_1A || p.slip_model > CDI_SLIP_4B) return fail(CDI_ERR_ARG, "bad slip_model");
+  if (p.precision != CDI_FP64 && p.precision != CDI_MIXED) return fail(CDI_ERR_ARG, "bad precision");
+  if (p.guess < CDI_GUESS_ZERO || p.guess > CDI_GUESS_LEARNED) return fail(CDI_ERR_ARG, "bad guess");
+  if (p.guess == CDI_GUESS_LEARNED) return fail(CDI_ERR_ARG, "learned guess is not available in this build");
+  if (p.poisson_rtol < 0 || p.poisson_maxit < 0 || p.mg_smooth < 0) return fail(CDI_ERR_ARG, "bad solver limits");
+  r.p = p;
+  r.h = hx;
+  r.dt = p.dt > 0 ? p.dt : cfl_dt(p, hx);
+  if (!(r.dt > 0) || !std::isfinite(r.dt)) return fail(CDI_ERR_ARG, "time step could not be determined");
+  r.rtol = p.poisson_rtol > 0 ? p.poisson_rtol : 1e-10;
+  r.maxit = p.poisson_maxit > 0 ? p.poisson_maxit : 200;
+  // multigrid hierarchy: halve both directions while both stay even and the
+  // level has more than 64 cells
+  int nx = p.nx, ny = p.ny, l = 0;
+  r.lnx[0] = nx; r.lny[0] = ny;
+  while ((nx % 2 == 0) && (ny % 2 == 0) && nx * ny > 64 && l + 1 < kMaxLevels) {
+    nx /= 2; ny /= 2; ++l;
+    r.lnx[l] = nx; r.lny[l] = ny;
+  }
+  r.nlev = l + 1;
+  if ((long)r.lnx[r.nlev - 1] * r.lny[r.nlev - 1] > 1024)
+    return fail(CDI_ERR_SHAPE, "coarsest multigrid grid %dx%d exceeds 1024 cells", r.lnx[r.nlev - 1],
+                r.lny[r.nlev - 1]);
+  r.lc = r.nlev - 1;
+  for (int k = 0; k < r.nlev; ++k)
+    if ((long)r.lnx[k] * r.lny[k] <= kCoarseCells) { r.lc = k; break; }
+  return CDI_OK;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+int ceil_div(int a, int b) { return (a + b - 1) / b; }
+
+struct Layout {
+  size_t inst_bytes;        // per instance (sum over instances in `offs`)
+};
+
+// Carve one instance's arrays out of `base` (device) starting at offset `off`;
+// with base == nullptr only the size is computed.
+size_t carve(const Resolved& R, int ntiles_cell, int ntiles_mg0, char* base, size_t off, Inst* I) {
+  const int nx = R.p.nx, ny = R.p.ny;
+  const size_t nc = (size_t)nx * ny, nf = (size_t)(ny + 1) * nx;
+  const bool mixed = R.p.precision == CDI_MIXED;
+  const size_t S = mixed ? sizeof(float) : sizeof(double);
+  auto take = [&](size_t bytes) -> void* {
+    void* p = base ? (void*)(base + off) : nullptr;
+    off = align256(off + bytes);
+    return p;
+  };
+  Inst tmp;
+  Inst& D = I ? *I : tmp;
+  D.phi_a = (double*)take(nc * 8);
+  D.phi_b = (double*)take(nc * 8);
+  D.us = (double*)take(nc * 8);
+  D.vs = (double*)take(nf * 8);
+  D.mx = (double*)take(nc * 8);
+  D.my = (double*)take(nf * 8);
+  D.ustar = (double*)take(nc * 8);
+  D.vstar = (double*)take(nf * 8);
+  D.acc_phi = (double*)take(nc * 8);
+  D.acc_mx = (double*)take(nc * 8);
+  D.acc_my = (double*)take(nf * 8);
+  D.nhx = take(nc * S);
+  D.nhy = take(nc * S);
+  D.muc = take(nc * S);
+  D.wall = (double*)take((size_t)10 * nx * 8);
+  D.uY = (double*)take((size_t)2 * nx * 8);
+  D.uslip = (double*)take((size_t)2 * nx * 8);
+  D.ax0 = (double*)take(nc * 8);
+  D.ay0 = (double*)take(nf * 8);
+  D.b = (double*)take(nc * 8);
+  D.x = (double*)take(nc * 8);
+  D.rr = (double*)take(nc * 8);
+  D.d0 = (double*)take(nc * 8);
+  D.d1 = (double*)take(nc * 8);
+  D.q = (double*)take(nc * 8);
+  D.zf = (double*)take(nc * 8);
+  D.part = (double*)take((size_t)8 * std::max(ntiles_cell, ntiles_mg0) * 8);
+  D.pcg = (PcgScalars*)take(sizeof(PcgScalars));
+  for (int l = 0; l < R.nlev; ++l) {
+    Level& L = D.lev[l];
+    L.nx = R.lnx[l];
+    L.ny = R.lny[l];
+    const size_t lc = (size_t)L.nx * L.ny, lf = (size_t)(L.ny + 1) * L.nx;
+    if (l == 0 && !mixed) {
+      L.ax = D.ax0;
+      L.ay = D.ay0;
+    } else {
+      L.ax = take(lc * S);
+      L.ay = take(lf * S);
+    }
+    L.r = (l == 0) ? nullptr : take(lc * S);
+    L.z = take(lc * S);
+  }
+  const size_t nlc = (size_t)R.lnx[R.lc] * R.lny[R.lc];
+  const size_t ncs = (size_t)R.lnx[R.nlev - 1] * R.lny[R.nlev - 1];
+  D.coarse_ws = (double*)take(std::max(nlc, 4 * ncs) * 8);
+  return off;
+}
+
+struct Batch {
+  int n;
+  std::vector<Resolved> R;
+  std::vector<Inst> inst;               // host copies
+  // tile lists (host), concatenated into one device array
+  std::vector<Tile> cell;               // level-0 cell tiles of every instance
+  std::vector<std::vector<Tile>> mg;    // per level: multigrid tiles of instances with level < lc
+  int max_lc = 0, max_nlev = 0;
+  size_t shared_bytes = 0;
+};
+
+void build_tiles(Batch& B) {
+  B.cell.clear();
+  B.max_lc = 0;
+  B.max_nlev = 0;
+  for (int k = 0; k < B.n; ++k) {
+    B.max_lc = std::max(B.max_lc, B.R[k].lc);
+    B.max_nlev = std::max(B.max_nlev, B.R[k].nlev);
+  }
+  B.mg.assign(std::max(B.max_lc, 1), {});
+  for (int k = 0; k < B.n; ++k) {
+    const Resolved& R = B.R[k];
+    Inst& I = B.inst[k];
+    I.first_tile = (int)B.cell.size();
+    int local = 0;
+    for (int j0 = 0; j0 < R.p.ny; j0 += TY)
+      for (int i0 = 0; i0 < R.p.nx; i0 += TX) B.cell.push_back(Tile{k, i0, j0, 0, local++, {0, 0, 0}});
+    I.ntiles = local;
+    for (int l = 0; l < R.lc; ++l) {
+      Level& L = I.lev[l];
+      L.first_tile = (int)B.mg[l].size();
+      int loc = 0;
+      for (int j0 = 0; j0 < L.ny; j0 += FY)
+        for (int i0 = 0; i0 < L.nx; i0 += FX) B.mg[l].push_back(Tile{k, i0, j0, l, loc++, {0, 0, 0}});
+      L.ntiles = loc;
+    }
+    for (int l = R.lc; l < R.nlev; ++l) { I.lev[l].first_tile = 0; I.lev[l].ntiles = 0; }
+  }
+}
+
+int mg0_tiles(const Resolved& R) { return ceil_div(R.p.nx, FX) * ceil_div(R.p.ny, FY); }
+int cell_tiles(const Resolved& R) { return ceil_div(R.p.nx, TX) * ceil_div(R.p.ny, TY); }
+
+size_t batch_bytes(const std::vector<Resolved>& Rs, Batch* B, char* base) {
+  const int n = (int)Rs.size();
+  // shared header: instances, diag outputs, tile lists
+  size_t ntile_cell = 0, ntile_mg = 0;
+  for (auto& R : Rs) {
+    ntile_cell += cell_tiles(R);
+    int nx = R.p.nx, ny = R.p.ny;
+    for (int l = 0; l < R.lc; ++l) { ntile_mg += (size_t)ceil_div(nx, FX) * ceil_div(ny, FY); nx /= 2; ny /= 2; }
+  }
+  size_t off = 0;
+  off = align256(off + sizeof(Inst) * n);
+  off = align256(off + sizeof(DiagOut) * n);
+  off = align256(off + sizeof(Tile) * (ntile_cell + ntile_mg + 1));
+  for (int k = 0; k < n; ++k)
+    off = carve(Rs[k], cell_tiles(Rs[k]), mg0_tiles(Rs[k]), base, off, B ? &B->inst[k] : nullptr);
+  (void)B;
+  return off;
+}
+
+void fill_inst(const Resolved& R, const cdi_fields& f, Inst& I) {
+  const cdi_params& p = R.p;
+  I.nx = p.nx; I.ny = p.ny;
+  I.nlev = R.nlev; I.lc = R.lc;
+  I.slip_model = p.slip_model;
+  I.mixed = p.precision == CDI_MIXED;
+  I.h = R.h; I.inv_h = 1.0 / R.h;
+  I.eps = p.eps; I.gamma = p.gamma; I.sigma = p.sigma; I.cos_eq = std::cos(p.theta_eq);
+  I.rho1 = p.rho1; I.rho2 = p.rho2; I.mu1 = p.mu1; I.mu2 = p.mu2;
+  I.beta1 = p.beta1; I.beta2 = p.beta2;
+  I.uw_bot = p.u_wall_bot; I.uw_top = p.u_wall_top;
+  I.dt = R.dt;
+  I.phi = f.phi; I.u = f.u; I.v = f.v; I.p = f.p;
+}
+
+}  // namespace
+
+struct cdi_ctx {
+  Batch B;
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;
+  Inst* d_inst = nullptr;
+  DiagOut* d_diag = nullptr;
+  Tile* d_cell = nullptr;
+  std::vector<Tile*> d_mg;
+  bool mixed = false;
+  bool uniform_rho = true;
+  bool coef_ready = false;
+  double t = 0.0;
+  long step = 0;
+  std::vector<double> mass0;
+  PcgScalars* h_pcg = nullptr;   // pinned
+  int pred_iters = 4;
+  std::vector<int> last_iters;
+  std::vector<double> last_relres;
+  std::vector<int> last_conv;
+  int guess = CDI_GUESS_PREV;
+  double rtol = 1e-10;
+  int maxit = 200;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+// ---------------------------------------------------------------- launches
+namespace {
+
+template <typename S>
+void launch_vcycle(cdi_ctx* c) {
+  Batch& B = c->B;
+  for (int l = 0; l < B.max_lc; ++l)
+    if (!B.mg[l].empty())
+      k_mg_down<S><<<(unsigned)B.mg[l].size(), kNT, 0, c->stream>>>(c->d_mg[l], c->d_inst, l);
+  k_mg_coarse<S><<<(unsigned)B.n, kCoarseNT, 0, c->stream>>>(c->d_inst);
+  for (int l = B.max_lc - 1; l >= 0; --l)
+    if (!B.mg[l].empty())
+      k_mg_up<S><<<(unsigned)B.mg[l].size(), kNT, 0, c->stream>>>(c->d_mg[l], c->d_inst, l);
+}
+
+template <typename S>
+void launch_coef(cdi_ctx* c) {
+  for (int l = 1; l < c->B.max_nlev; ++l) {
+    int maxc = 0;
+    for (int k = 0; k < c->B.n; ++k)
+      if (l < c->B.R[k].nlev) maxc = std::max(maxc, c->B.R[k].lnx[l] * (c->B.R[k].lny[l] + 1));
+    const unsigned grid = (unsigned)std::max(1, std::min(1024, ceil_div(maxc, kNT)));
+    k_mg_coef<S><<<grid, kNT, 0, c->stream>>>(c->d_inst, c->B.n, l);
+  }
+}
+
+// Flexible-CG loop after the right-hand side is in place.  Returns NOCONV
+// if an instance stopped at maxit.
+template <typename S>
+cdi_status solve_loop(cdi_ctx* c, int guess) {
+  Batch& B = c->B;
+  const unsigned ncell = (unsigned)B.cell.size();
+  if (!c->uniform_rho || !c->coef_ready) {
+    launch_coef<S>(c);
+    c->coef_ready = true;
+  }
+  k_pcg_init<<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, guess);
+  int it = 0;
+  int next_check = std::max(1, c->pred_iters - 1);
+  bool all_done = false;
+  while (it < c->maxit) {
+    launch_vcycle<S>(c);
+    k_pcg_spmv<<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, it & 1);
+    k_pcg_update<<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, it & 1);
+    ++it;
+    if (it >= next_check || it >= c->maxit) {
+      HIPCHK(hipMemcpyAsync(c->h_pcg, B.inst[0].pcg, sizeof(PcgScalars), hipMemcpyDeviceToHost, c->stream));
+      for (int k = 1; k < B.n; ++k)
+        HIPCHK(hipMemcpyAsync(c->h_pcg + k, B.inst[k].pcg, sizeof(PcgScalars), hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(hipStreamSynchronize(c->stream));
+      all_done = true;
+      for (int k = 0; k < B.n; ++k) all_done = all_done && c->h_pcg[k].done;
+      if (all_done) break;
+      next_check = it + 1;
+    }
+  }
+  if (!all_done) {
+    for (int k = 0; k < B.n; ++k)
+      HIPCHK(hipMemcpyAsync(c->h_pcg + k, B.inst[k].pcg, sizeof(PcgScalars), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+  }
+  k_pcg_xmean<<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst);
+  int maxi = 0;
+  bool noconv = false;
+  for (int k = 0; k < B.n; ++k) {
+    c->last_iters[k] = c->h_pcg[k].iters;
+    c->last_relres[k] = c->h_pcg[k].relres;
+    c->last_conv[k] = c->h_pcg[k].converged;
+    maxi = std::max(maxi, c->h_pcg[k].iters);
+    if (!c->h_pcg[k].converged) noconv = true;
+  }
+  c->pred_iters = std::max(1, maxi);
+  HIPCHK(hipGetLastError());
+  if (noconv) return fail(CDI_ERR_NOCONV, "pressure solve did not reach rtol within maxit");
+  return CDI_OK;
+}
+
+template <typename S>
+cdi_status run_step(cdi_ctx* c) {
+  Batch& B = c->B;
+  const unsigned ncell = (unsigned)B.cell.size();
+  const double dt = B.R[0].dt;   // every instance carries its own dt in Inst
+  cdi_status st = CDI_OK;
+  for (int k = 0; k < 4; ++k) {
+    const int src = k == 0 ? 0 : (k == 2 ? 2 : 1);
+    const int dst = (k == 0 || k == 2) ? 1 : 2;
+    k_phase_prep<S><<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, src);
+    // per-instance dt: c_next and tau are passed as multiples of the instance dt
+    k_stage<S><<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, k, src, dst,
+                                              k < 3 ? RK_C[k + 1] : 1.0, RK_B[k], k == 3);
+    const double tfac = k < 3 ? RK_C[k + 1] : 1.0;
+    k_rhs<S><<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, dst, tfac, c->rtol, c->maxit);
+    cdi_status s = solve_loop<S>(c, c->guess == CDI_GUESS_ZERO ? 0 : 1);
+    if (s == CDI_ERR_NOCONV) st = s;
+    else if (s != CDI_OK) return s;
+    k_project<<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, tfac, k == 3, dst);
+  }
+  (void)dt;
+  HIPCHK(hipGetLastError());
+  return st;
+}
+
+}  // namespace
+
+// ================================================================ C ABI
+extern "C" {
+
+const char* cdi_last_error(void) { return g_err.c_str(); }
+
+double cdi_default_dt(const cdi_params* params) {
+  Resolved R;
+  if (resolve(params, R) != CDI_OK) return -1.0;
+  return R.dt;
+}
+
+size_t cdi_workspace_bytes(const cdi_params* params, int32_t n) {
+  if (!params || n < 1) { fail(CDI_ERR_ARG, "bad arguments"); return 0; }
+  std::vector<Resolved> Rs(n);
+  for (int k = 0; k < n; ++k)
+    if (resolve(params + k, Rs[k]) != CDI_OK) return 0;
+  return batch_bytes(Rs, nullptr, nullptr);
+}
+
+cdi_status cdi_init_batch(const cdi_params* params, int32_t n, const cdi_fields* fields,
+                          void* workspace, size_t workspace_bytes, void* hip_stream, cdi_ctx** out) {
+  if (!out) return fail(CDI_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (!params || !fields || n < 1) return fail(CDI_ERR_ARG, "params/fields NULL or n < 1");
+  if (!workspace) return fail(CDI_ERR_ARG, "workspace is NULL");
+  if (((uintptr_t)workspace) & 255) return fail(CDI_ERR_ARG, "workspace must be 256-byte aligned");
+  std::vector<Resolved> Rs(n);
+  for (int k = 0; k < n; ++k) {
+    cdi_status s = resolve(params + k, Rs[k]);
+    if (s != CDI_OK) return s;
+    if (!fields[k].phi || !fields[k].u || !fields[k].v || !fields[k].p)
+      return fail(CDI_ERR_ARG, "instance %d: a field pointer is NULL", k);
+    if (Rs[k].p.precision != Rs[0].p.precision)
+      return fail(CDI_ERR_ARG, "all instances of a batch must use the same precision");
+  }
+  const size_t need = batch_bytes(Rs, nullptr, nullptr);
+  if (workspace_bytes < need)
+    return fail(CDI_ERR_ARG, "workspace too small: %zu < %zu bytes", workspace_bytes, need);
+
+  cdi_ctx* c = new cdi_ctx();
+  c->stream = (hipStream_t)hip_stream;
+  c->ws = (char*)workspace;
+  Batch& B = c->B;
+  B.n = n;
+  B.R = Rs;
+  B.inst.assign(n, Inst{});
+  c->mixed = Rs[0].p.precision == CDI_MIXED;
+  c->guess = Rs[0].p.guess;
+  c->rtol = Rs[0].rtol;
+  c->maxit = Rs[0].maxit;
+  for (int k = 0; k < n; ++k) {
+    fill_inst(Rs[k], fields[k], B.inst[k]);
+    if (Rs[k].p.rho1 != Rs[k].p.rho2) c->uniform_rho = false;
+  }
+  batch_bytes(Rs, &B, c->ws);
+  build_tiles(B);
+  // shared header
+  size_t off = 0;
+  c->d_inst = (Inst*)(c->ws + off);
+  off = align256(off + sizeof(Inst) * n);
+  c->d_diag = (DiagOut*)(c->ws + off);
+  off = align256(off + sizeof(DiagOut) * n);
+  Tile* tl = (Tile*)(c->ws + off);
+  std::vector<Tile> all = B.cell;
+  c->d_cell = tl;
+  c->d_mg.assign(B.mg.size(), nullptr);
+  size_t pos = all.size();
+  for (size_t l = 0; l < B.mg.size(); ++l) {
+    c->d_mg[l] = tl + pos;
+    all.insert(all.end(), B.mg[l].begin(), B.mg[l].end());
+    pos += B.mg[l].size();
+  }
+  c->h_pcg = nullptr;
+  hipError_t e = hipHostMalloc((void**)&c->h_pcg, sizeof(PcgScalars) * n, hipHostMallocDefault);
+  if (e != hipSuccess) { delete c; return fail(CDI_ERR_DEVICE, "hipHostMalloc: %s", hipGetErrorString(e)); }
+  c->last_iters.assign(n, 0);
+  c->last_relres.assign(n, 0.0);
+  c->last_conv.assign(n, 1);
+  c->mass0.assign(n, 0.0);
+  auto cleanup_fail = [&](hipError_t err, const char* what) {
+    (void)hipHostFree(c->h_pcg);
+    delete c;
+    return fail(CDI_ERR_DEVICE, "%s: %s", what, hipGetErrorString(err));
+  };
+  if ((e = hipMemcpyAsync(c->d_inst, B.inst.data(), sizeof(Inst) * n, hipMemcpyHostToDevice, c->stream)) != hipSuccess)
+    return cleanup_fail(e, "copy instances");
+  if ((e = hipMemcpyAsync(tl, all.data(), sizeof(Tile) * all.size(), hipMemcpyHostToDevice, c->stream)) != hipSuccess)
+    return cleanup_fail(e, "copy tiles");
+  // zero the whole per-instance workspace once (walls of v-type arrays,
+  // counters, flags); every later write stays inside the domain
+  const size_t hdr = (size_t)((char*)B.inst[0].phi_a - c->ws);
+  if ((e = hipMemsetAsync(c->ws + hdr, 0, need - hdr, c->stream)) != hipSuccess)
+    return cleanup_fail(e, "clear workspace");
+  if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return cleanup_fail(e, "init sync");
+  if ((e = hipEventCreate(&c->ev0)) != hipSuccess) return cleanup_fail(e, "event");
+  if ((e = hipEventCreate(&c->ev1)) != hipSuccess) return cleanup_fail(e, "event");
+  // initial diagnostics: mass0
+  *out = c;
+  for (int k = 0; k < n; ++k) {
+    cdi_diag d;
+    cdi_status s = cdi_diagnostics(c, k, &d);
+    if (s != CDI_OK) { cdi_destroy(c); *out = nullptr; return s; }
+    c->mass0[k] = d.mass;
+  }
+  return CDI_OK;
+}
+
+cdi_status cdi_init(const cdi_params* params, const cdi_fields* fields, void* workspace,
+                    size_t workspace_bytes, void* hip_stream, cdi_ctx** out) {
+  return cdi_init_batch(params, 1, fields, workspace, workspace_bytes, hip_stream, out);
+}
+
+cdi_status cdi_step(cdi_ctx* c, int32_t nsteps) {
+  if (!c) return fail(CDI_ERR_ARG, "ctx is NULL");
+  if (nsteps < 0) return fail(CDI_ERR_ARG, "nsteps < 0");
+  cdi_status st = CDI_OK;
+  for (int s = 0; s < nsteps; ++s) {
+    cdi_status r = c->mixed ? run_step<float>(c) : run_step<double>(c);
+    if (r == CDI_ERR_NOCONV) st = r;
+    else if (r != CDI_OK) return r;
+    c->t += c->B.R[0].dt;
+    c->step += 1;
+  }
+  return st;
+}
+
+cdi_status cdi_solve_pressure(cdi_ctx* c, const double* b, double* p, cdi_solve_info* info) {
+  if (!c) return fail(CDI_ERR_ARG, "ctx is NULL");
+  if (!p) return fail(CDI_ERR_ARG, "p is NULL");
+  Batch& B = c->B;
+  if (B.n != 1) return fail(CDI_ERR_STATE, "standalone solve needs a single-instance context");
+  const unsigned ncell = (unsigned)B.cell.size();
+  // the solve uses the caller p as guess buffer: point the instance at it
+  Inst I = B.inst[0];
+  double* saved_p = I.p;
+  I.p = p;
+  HIPCHK(hipMemcpyAsync(c->d_inst, &I, sizeof(Inst), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  HIPCHK(hipEventRecord(c->ev0, c->stream));
+  if (c->mixed)
+    k_solve_setup<float><<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, b, c->rtol, c->maxit);
+  else
+    k_solve_setup<double><<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, b, c->rtol, c->maxit);
+  c->coef_ready = false;
+  const int guess = c->guess == CDI_GUESS_ZERO ? 0 : 1;
+  cdi_status s = c->mixed ? solve_loop<float>(c, guess) : solve_loop<double>(c, guess);
+  c->coef_ready = false;   // coefficients now follow the caller phase field
+  k_solve_out<<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, p);
+  HIPCHK(hipEventRecord(c->ev1, c->stream));
+  I.p = saved_p;
+  HIPCHK(hipMemcpyAsync(c->d_inst, &I, sizeof(Inst), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (info) {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    info->iterations = c->last_iters[0];
+    info->converged = c->last_conv[0];
+    info->guess_used = guess ? CDI_GUESS_PREV : CDI_GUESS_ZERO;
+    info->relres = c->last_relres[0];
+    info->bnorm = c->h_pcg[0].fnorm;
+    info->ms = ms;
+  }
+  return s;
+}
+
+cdi_status cdi_eval_rhs(cdi_ctx* c, double* l_phi, double* l_mx, double* l_my, double* u_y,
+                        double* u_slip) {
+  if (!c) return fail(CDI_ERR_ARG, "ctx is NULL");
+  if (!l_phi || !l_mx || !l_my) return fail(CDI_ERR_ARG, "output pointer is NULL");
+  Batch& B = c->B;
+  const unsigned ncell = (unsigned)B.cell.size();
+  const Inst& I = B.inst[0];
+  const size_t nc = (size_t)I.nx * I.ny;
+  if (c->mixed) {
+    k_phase_prep<float><<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, 0);
+    k_stage<float><<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, -1, 0, 0, 0.0, 0.0, 1);
+  } else {
+    k_phase_prep<double><<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, 0);
+    k_stage<double><<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, -1, 0, 0, 0.0, 0.0, 1);
+  }
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(l_phi, I.acc_phi, nc * 8, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(l_mx, I.acc_mx, nc * 8, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(hipMemsetAsync(l_my, 0, (size_t)(I.ny + 1) * I.nx * 8, c->stream));
+  HIPCHK(hipMemcpyAsync(l_my + I.nx, I.acc_my + I.nx, (size_t)(I.ny - 1) * I.nx * 8,
+                        hipMemcpyDeviceToDevice, c->stream));
+  if (u_y) HIPCHK(hipMemcpyAsync(u_y, I.uY, (size_t)2 * I.nx * 8, hipMemcpyDeviceToDevice, c->stream));
+  if (u_slip) HIPCHK(hipMemcpyAsync(u_slip, I.uslip, (size_t)2 * I.nx * 8, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return CDI_OK;
+}
+
+cdi_status cdi_diagnostics(cdi_ctx* c, int32_t idx, cdi_diag* out) {
+  if (!c || !out) return fail(CDI_ERR_ARG, "NULL argument");
+  Batch& B = c->B;
+  if (idx < 0 || idx >= B.n) return fail(CDI_ERR_ARG, "instance %d out of range", idx);
+  const unsigned ncell = (unsigned)B.cell.size();
+  if (c->mixed) k_phase_prep<float><<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, 0);
+  else k_phase_prep<double><<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, 0);
+  k_wall<<<(unsigned)B.n, kNT, 0, c->stream>>>(c->d_inst);
+  k_diag<<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, c->d_diag);
+  HIPCHK(hipGetLastError());
+  const Inst& I = B.inst[idx];
+  DiagOut d;
+  std::vector<double> w((size_t)4 * I.nx + I.nx);
+  HIPCHK(hipMemcpyAsync(&d, c->d_diag + idx, sizeof d, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipMemcpyAsync(w.data(), I.uY, (size_t)2 * I.nx * 8, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipMemcpyAsync(w.data() + 2 * I.nx, I.uslip, (size_t)2 * I.nx * 8, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipMemcpyAsync(w.data() + 4 * I.nx, I.wall, (size_t)I.nx * 8, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  std::memset(out, 0, sizeof *out);
+  out->t = c->t;
+  out->step = c->step;
+  out->mass = d.mass;
+  out->mass0 = c->mass0[idx];
+  out->phi_min = d.phi_min;
+  out->phi_max = d.phi_max;
+  out->max_div = d.max_div;
+  out->ke = d.ke;
+  out->nonfinite = d.nonfinite > 0 ? 1 : 0;
+  for (int wl = 0; wl < 2; ++wl) {
+    double mu = 0.0, ms = 0.0;
+    for (int i = 0; i < I.nx; ++i) {
+      mu = std::max(mu, std::fabs(w[(size_t)wl * I.nx + i]));
+      ms = std::max(ms, std::fabs(w[(size_t)2 * I.nx + wl * I.nx + i]));
+    }
+    out->max_uY[wl] = mu;
+    out->max_uslip[wl] = ms;
+  }
+  out->last_iters = c->last_iters[idx];
+  out->last_relres = c->last_relres[idx];
+  return out->nonfinite ? fail(CDI_ERR_NONFINITE, "non-finite value in the state") : CDI_OK;
+}
+
+void cdi_destroy(cdi_ctx* c) {
+  if (!c) return;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  else (void)hipDeviceSynchronize();
+  if (c->h_pcg) (void)hipHostFree(c->h_pcg);
+  if (c->ev0) (void)hipEventDestroy(c->ev0);
+  if (c->ev1) (void)hipEventDestroy(c->ev1);
+  delete c;
+}
+
+}  // extern "C"

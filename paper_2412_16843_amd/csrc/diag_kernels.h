@@ -1,0 +1,176 @@
+// Diagnostics and operator-evaluation kernels: FP64 reductions of the state
+// (mass, phase-field bounds, divergence, kinetic energy, finiteness) and the
+// GNBC wall values of the current state (Sec. 5.1 metrics).
+#pragma once
+#include "poisson_kernels.h"
+
+namespace cdi {
+
+struct DiagOut {
+  double mass, phi_min, phi_max, max_div, ke, nonfinite;
+  double pad[2];
+};
+
+template <int NV, int NT = kNT>
+__device__ __forceinline__ void block_max(double (&v)[NV], double* sh) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = wave_max(v[k]);
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) sh[k * (NT / 64) + w] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      double s = sh[k * (NT / 64)];
+      for (int ww = 1; ww < NT / 64; ++ww) s = fmax(s, sh[k * (NT / 64) + ww]);
+      v[k] = s;
+    }
+  }
+  __syncthreads();
+}
+
+// Cell reductions of instance state: sum(phi), -min(phi), max(phi),
+// max |div u|, kinetic energy, non-finite count.
+__global__ void __launch_bounds__(kNT) k_diag(const Tile* __restrict__ tiles,
+                                              const Inst* __restrict__ insts, DiagOut* out) {
+  __shared__ double sh[3 * kNT / 64];
+  const Tile t = tiles[blockIdx.x];
+  const Inst& I = insts[t.inst];
+  const int nx = I.nx, ny = I.ny;
+  const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+  const int i = t.i0 + tx, j = t.j0 + ty;
+  double s[3] = {0.0, 0.0, 0.0};      // sum phi, ke, nonfinite
+  double m[3] = {-1e300, -1e300, 0.0}; // -min phi, max phi, max |div|
+  if (i < nx && j < ny) {
+    const size_t o = (size_t)j * nx + i;
+    const double ph = I.phi[o];
+    const double u = I.u[o], v = I.v[o];
+    const double ue = I.u[(size_t)j * nx + wrap(i + 1, nx)], vn = I.v[o + nx];
+    s[0] = ph;
+    const double r1 = I.rho1, r2 = I.rho2;
+    const double rc = (r1 - r2) * ph + r2;
+    const double rw = (r1 - r2) * I.phi[(size_t)j * nx + wrap(i - 1, nx)] + r2;
+    double ke = 0.5 * (rw + rc) * u * u;
+    if (j >= 1) ke += 0.5 * ((r1 - r2) * I.phi[o - nx] + r2 + rc) * v * v;
+    s[1] = 0.5 * ke * I.h * I.h;
+    const double pr = I.p[o];
+    s[2] = (isfinite(ph) && isfinite(u) && isfinite(v) && isfinite(pr)) ? 0.0 : 1.0;
+    m[0] = -ph;
+    m[1] = ph;
+    m[2] = fabs(((ue - u) + (vn - v)) * I.inv_h);
+  }
+  block_sum<3>(s, sh);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    I.part[t.local] = s[0];
+    I.part[I.ntiles + t.local] = s[1];
+    I.part[2 * I.ntiles + t.local] = s[2];
+  }
+  block_max<3>(m, sh);
+  if (threadIdx.x == 0) {
+    I.part[3 * I.ntiles + t.local] = m[0];
+    I.part[4 * I.ntiles + t.local] = m[1];
+    I.part[5 * I.ntiles + t.local] = m[2];
+  }
+  if (arrive_last(&I.pcg->counter[5], I.ntiles)) {
+    if (threadIdx.x == 0) {
+      double a = 0.0, b = 0.0, c = 0.0, mn = -1e300, mx = -1e300, md = 0.0;
+      for (int k = 0; k < I.ntiles; ++k) {
+        a += ld_agent(&I.part[k]);
+        b += ld_agent(&I.part[I.ntiles + k]);
+        c += ld_agent(&I.part[2 * I.ntiles + k]);
+        mn = fmax(mn, ld_agent(&I.part[3 * I.ntiles + k]));
+        mx = fmax(mx, ld_agent(&I.part[4 * I.ntiles + k]));
+        md = fmax(md, ld_agent(&I.part[5 * I.ntiles + k]));
+      }
+      DiagOut& D = out[t.inst];
+      D.mass = a * I.h * I.h;
+      D.ke = b;
+      D.nonfinite = c;
+      D.phi_min = -mn;
+      D.phi_max = mx;
+      D.max_div = md;
+    }
+  }
+}
+
+// GNBC wall values (u^Y, u_wall - U) of the current state at every wall
+// corner; needs the wall arrays of k_phase_prep on the caller phase field.
+__global__ void __launch_bounds__(kNT) k_wall(const Inst* __restrict__ insts) {
+  const Inst& I = insts[blockIdx.x];
+  const int nx = I.nx, ny = I.ny;
+  for (int c = threadIdx.x; c < 2 * nx; c += kNT) {
+    const int wall = c / nx, i = c - wall * nx;
+    const double ur = I.u[(size_t)(wall == 0 ? 0 : ny - 1) * nx + i];
+    double uY, usl;
+    (void)gnbc_corner(I, wall, i, ur, uY, usl);
+    I.uY[c] = uY;
+    I.uslip[c] = usl;
+  }
+}
+
+// Copy a user right-hand side into the solver and build the operator from
+// the caller phase field (standalone pressure solve); also resets the CG.
+template <typename S>
+__global__ void __launch_bounds__(kNT) k_solve_setup(const Tile* __restrict__ tiles,
+                                                     const Inst* __restrict__ insts,
+                                                     const double* __restrict__ bin, double rtol,
+                                                     int maxit) {
+  __shared__ double sh[kNT / 64];
+  const Tile t = tiles[blockIdx.x];
+  const Inst& I = insts[t.inst];
+  const int nx = I.nx, ny = I.ny;
+  const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+  const int i = t.i0 + tx, j = t.j0 + ty;
+  double bs[1] = {0.0};
+  if (i < nx && j < ny) {
+    const size_t o = (size_t)j * nx + i;
+    const double r1 = I.rho1, r2 = I.rho2;
+    const double rc = (r1 - r2) * I.phi[o] + r2;
+    const double rw = (r1 - r2) * I.phi[(size_t)j * nx + wrap(i - 1, nx)] + r2;
+    const double ih2 = I.inv_h * I.inv_h;
+    const double ax = ih2 / (0.5 * (rw + rc));
+    double ay = 0.0;
+    if (j >= 1) ay = ih2 / (0.5 * ((r1 - r2) * I.phi[o - nx] + r2 + rc));
+    I.ax0[o] = ax;
+    I.ay0[o] = ay;
+    if (I.mixed) {
+      ((S*)I.lev[0].ax)[o] = (S)ax;
+      ((S*)I.lev[0].ay)[o] = (S)ay;
+    }
+    const double b = bin ? bin[o] : I.b[o];
+    I.b[o] = b;
+    bs[0] = b;
+  }
+  block_sum<1>(bs, sh);
+  if (threadIdx.x == 0) I.part[t.local] = bs[0];
+  if (arrive_last(&I.pcg->counter[0], I.ntiles)) {
+    if (threadIdx.x == 0) {
+      double s = 0.0;
+      for (int k = 0; k < I.ntiles; ++k) s += ld_agent(&I.part[k]);
+      PcgScalars* P = I.pcg;
+      P->bmean = s / ((double)nx * ny);
+      P->done = 0; P->iters = 0; P->first = 1; P->converged = 0; P->pad = 0;
+      P->rtol = rtol; P->maxit = maxit;
+    }
+  }
+}
+
+// Mean-free solution of a standalone solve into the caller's buffer.
+__global__ void __launch_bounds__(kNT) k_solve_out(const Tile* __restrict__ tiles,
+                                                   const Inst* __restrict__ insts, double* pout) {
+  const Tile t = tiles[blockIdx.x];
+  const Inst& I = insts[t.inst];
+  const int nx = I.nx, ny = I.ny;
+  const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+  const int i = t.i0 + tx, j = t.j0 + ty;
+  if (i >= nx || j >= ny) return;
+  const size_t o = (size_t)j * nx + i;
+  const bool zero = I.pcg->pad != 0;
+  pout[o] = zero ? 0.0 : I.x[o] - I.pcg->xmean;
+}
+
+}  // namespace cdi

@@ -1,0 +1,402 @@
+// Stage kernels of the CDI + GNBC step: phase-field preparation, the fused
+// CDI-flux / momentum / surface-tension / GNBC stage operator with its RK4
+// update, the projection right-hand side and the projection itself.
+//
+// S is the stencil precision (double on the FP64 path, float on the mixed
+// path).  The phase field, its RK accumulation, the flux differences of the
+// phi update and every reduction stay in FP64 on both paths.
+#pragma once
+#include "cdi_dev.h"
+
+namespace cdi {
+
+// tile of the cell kernels: TX x TY cells, one cell per thread
+constexpr int TX = 64, TY = 4;
+static_assert(TX * TY == kNT, "cell tile must match the block size");
+
+// ---------------------------------------------------------------- wall GNBC
+// Contact-line slip u^Y at wall corner i (Sec. 2 eq. u_slip_Y; Sec. 3 Models
+// 1A..4B).  Wall quantities are linear extrapolations per column (Sec. 4)
+// averaged to the corner; n points into the fluid, tau = +x on both walls.
+__device__ __forceinline__ double slip_uY(const Inst& I, int wall, int i, double& phc_out,
+                                          double& beta_out) {
+  const int nx = I.nx;
+  const double* W = I.wall + (size_t)wall * 5 * nx;
+  const int im = wrap(i - 1, nx);
+  const double sgn = wall == 0 ? 1.0 : -1.0;
+  double phc = 0.5 * (W[im] + W[i]);
+  phc = fmin(fmax(phc, 0.0), 1.0);
+  const double psc = 0.5 * (W[nx + im] + W[nx + i]);
+  const double dpn = sgn * 0.5 * (W[2 * nx + im] + W[2 * nx + i]);
+  const double kac = 0.5 * (W[3 * nx + im] + W[3 * nx + i]);
+  const double dphn = sgn * 0.5 * (W[4 * nx + im] + W[4 * nx + i]);
+  const double dpt = (W[nx + i] - W[nx + im]) * I.inv_h;
+  const double dpht = (W[i] - W[im]) * I.inv_h;
+  const double g = phc * (1.0 - phc);
+  const double beta = I.beta2 + (I.beta1 - I.beta2) * phc;
+  const double ce = I.cos_eq;
+  const double corr = 1.0 + kac * psc;
+  const double pre = -6.0 * I.sigma / beta;
+  const double eps = I.eps;
+  double uY;
+  switch (I.slip_model) {
+    case 0:  uY = pre * (eps * dphn + g * ce) * dpht; break;                                   // 1A
+    case 1:  uY = pre * (eps * dphn + eps * sqrt(dphn * dphn + dpht * dpht) * ce) * dpht; break; // 1B
+    case 2:  uY = pre * (g * dpn + g * ce) * g / eps * dpt; break;                             // 2A
+    case 3:  uY = pre * (g * dpn + g * sqrt(dpn * dpn + dpt * dpt) * ce) * g / eps * dpt; break; // 2B
+    case 4:  uY = pre * (eps * dphn + g * corr * ce) * dpht; break;                            // 3A
+    case 5:  uY = pre * (eps * dphn + eps * sqrt(dphn * dphn + dpht * dpht) * corr * ce) * dpht; break; // 3B
+    case 7:  uY = pre * (g * dpn + g * sqrt(dpn * dpn + dpt * dpt) * corr * ce) * g / eps * dpt; break; // 4B
+    default: uY = pre * (g * dpn + g * corr * ce) * g / eps * dpt; break;                     // 4A
+  }
+  phc_out = phc;
+  beta_out = beta;
+  return uY;
+}
+
+// Robin form of the slip condition: u_wall - U = (mu/beta) du/dn + u^Y with
+// du/dn = 2 (u_row - u_wall)/h along the inward normal.  Returns the wall
+// shear stress mu du/dy at the corner.
+__device__ __forceinline__ double gnbc_corner(const Inst& I, int wall, int i, double urow,
+                                              double& uY, double& uslip) {
+  double phc, beta;
+  uY = slip_uY(I, wall, i, phc, beta);
+  const double U = wall == 0 ? I.uw_bot : I.uw_top;
+  const double muw = I.mu2 + (I.mu1 - I.mu2) * phc;
+  const double lam = 2.0 * muw / (beta * I.h);
+  const double uw = (U + uY + lam * urow) / (1.0 + lam);
+  uslip = uw - U;
+  return wall == 0 ? 2.0 * muw * (urow - uw) * I.inv_h : 2.0 * muw * (uw - urow) * I.inv_h;
+}
+
+template <typename T>
+__device__ __forceinline__ T ddy_cell(const T* q, int stride, int j, int ny, T inv2h) {
+  // q points at the cell; stride = LDS row pitch
+  if (j == 0) return (T(-3) * q[0] + T(4) * q[stride] - q[2 * stride]) * inv2h;
+  if (j == ny - 1) return (T(3) * q[0] - T(4) * q[-stride] + q[-2 * stride]) * inv2h;
+  return (q[stride] - q[-stride]) * inv2h;
+}
+template <typename T>
+__device__ __forceinline__ T d2dy2_cell(const T* q, int stride, int j, int ny, T inv_h2) {
+  if (j == 0) return (T(2) * q[0] - T(5) * q[stride] + T(4) * q[2 * stride] - q[3 * stride]) * inv_h2;
+  if (j == ny - 1) return (T(2) * q[0] - T(5) * q[-stride] + T(4) * q[-2 * stride] - q[-3 * stride]) * inv_h2;
+  return (q[stride] - T(2) * q[0] + q[-stride]) * inv_h2;
+}
+
+// ------------------------------------------------------------ phase prep
+// n = G/(|G| + dN), psi, kappa, mu_c (Sec. 2, eqs. CDI, psi, curvature,
+// chemical potential) with one-sided rows at the walls (Sec. 4); the wall
+// rows also publish the extrapolated wall quantities of the slip models.
+// src: 0 caller phi, 1 phi_a, 2 phi_b.
+template <typename S>
+__global__ void __launch_bounds__(kNT) k_phase_prep(const Tile* __restrict__ tiles,
+                                                     const Inst* __restrict__ insts, int src) {
+  constexpr int RY = TY + 6, RX = TX + 2;   // rows j0-3 .. j0+TY+2, cols i0-1 .. i0+TX
+  __shared__ double s_phi[RY * RX];
+  __shared__ S s_psi[RY * RX];
+  const Tile t = tiles[blockIdx.x];
+  const Inst& I = insts[t.inst];
+  const int nx = I.nx, ny = I.ny;
+  const double* __restrict__ phi = src == 0 ? I.phi : (src == 1 ? I.phi_a : I.phi_b);
+  for (int k = threadIdx.x; k < RY * RX; k += kNT) {
+    const int rj = k / RX, ri = k - rj * RX;
+    const int j = t.j0 - 3 + rj, i = wrap(t.i0 - 1 + ri, nx);
+    double f = 0.0, ps = 0.0;
+    if (j >= 0 && j < ny) {
+      f = phi[(size_t)j * nx + i];
+      const double c = fmin(fmax(f, 0.0), 1.0);
+      ps = I.eps * log((c + kDeltaPsi) / (1.0 - c + kDeltaPsi));   // psi from FP64 phi
+    }
+    s_phi[k] = f;
+    s_psi[k] = (S)ps;
+  }
+  __syncthreads();
+  const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+  const int i = t.i0 + tx, j = t.j0 + ty;
+  if (i >= nx || j >= ny) return;
+  const int c = (ty + 3) * RX + (tx + 1);
+  const S inv2h = (S)(0.5 * I.inv_h), inv_h2 = (S)(I.inv_h * I.inv_h);
+  const S eps = (S)I.eps;
+  // normal from phi
+  const S gx = ((S)s_phi[c + 1] - (S)s_phi[c - 1]) * inv2h;
+  S gy;
+  {
+    if (j == 0) gy = (S(-3) * (S)s_phi[c] + S(4) * (S)s_phi[c + RX] - (S)s_phi[c + 2 * RX]) * inv2h;
+    else if (j == ny - 1) gy = (S(3) * (S)s_phi[c] - S(4) * (S)s_phi[c - RX] + (S)s_phi[c - 2 * RX]) * inv2h;
+    else gy = ((S)s_phi[c + RX] - (S)s_phi[c - RX]) * inv2h;
+  }
+  const S mag = sqrt(gx * gx + gy * gy) + (S)kDeltaN;
+  // psi derivatives, curvature, chemical potential
+  const S* q = s_psi + c;
+  const S px = (q[1] - q[-1]) * inv2h;
+  const S py = ddy_cell<S>(q, RX, j, ny, inv2h);
+  const S lap = (q[1] - S(2) * q[0] + q[-1]) * inv_h2 + d2dy2_cell<S>(q, RX, j, ny, inv_h2);
+  const S ph = (S)s_phi[c];
+  const S g = ph * (S(1) - ph);
+  const S grad2 = px * px + py * py;
+  const S mu = S(6) * (S)I.sigma * (g * (S(1) - S(2) * ph) * (S(1) - grad2) / eps - g * lap);
+  const size_t o = (size_t)j * nx + i;
+  ((S*)I.nhx)[o] = gx / mag;
+  ((S*)I.nhy)[o] = gy / mag;
+  ((S*)I.muc)[o] = mu;
+  // wall rows: extrapolate phi, psi, d psi/dy, kappa, d phi/dy to the wall (per column)
+  if (j == 0 || j == ny - 1) {
+    const int wall = j == 0 ? 0 : 1;
+    const int dj = j == 0 ? 1 : -1;          // second cell row from the wall
+    const int c2 = c + dj * RX;
+    const int j2 = j + dj;
+    double vals[2][5];
+    for (int r = 0; r < 2; ++r) {
+      const int cc = r == 0 ? c : c2, jj = r == 0 ? j : j2;
+      // FP64 wall quantities from the psi tile
+      const S* qs = s_psi + cc;
+      const double i2h = 0.5 * I.inv_h, ih2 = I.inv_h * I.inv_h;
+      const double p0 = (double)qs[0];
+      double pyd, d2y;
+      if (jj == 0) {
+        pyd = (-3.0 * p0 + 4.0 * (double)qs[RX] - (double)qs[2 * RX]) * i2h;
+        d2y = (2.0 * p0 - 5.0 * (double)qs[RX] + 4.0 * (double)qs[2 * RX] - (double)qs[3 * RX]) * ih2;
+      } else if (jj == ny - 1) {
+        pyd = (3.0 * p0 - 4.0 * (double)qs[-RX] + (double)qs[-2 * RX]) * i2h;
+        d2y = (2.0 * p0 - 5.0 * (double)qs[-RX] + 4.0 * (double)qs[-2 * RX] - (double)qs[-3 * RX]) * ih2;
+      } else {
+        pyd = ((double)qs[RX] - (double)qs[-RX]) * i2h;
+        d2y = ((double)qs[RX] - 2.0 * p0 + (double)qs[-RX]) * ih2;
+      }
+      const double pxd = ((double)qs[1] - (double)qs[-1]) * i2h;
+      const double lapd = ((double)qs[1] - 2.0 * p0 + (double)qs[-1]) * ih2 + d2y;
+      const double phd = s_phi[cc];
+      const double kap = (1.0 - 2.0 * phd) * (1.0 - pxd * pxd - pyd * pyd) / I.eps - lapd;
+      double phy;
+      if (jj == 0) phy = (-3.0 * phd + 4.0 * s_phi[cc + RX] - s_phi[cc + 2 * RX]) * i2h;
+      else if (jj == ny - 1) phy = (3.0 * phd - 4.0 * s_phi[cc - RX] + s_phi[cc - 2 * RX]) * i2h;
+      else phy = (s_phi[cc + RX] - s_phi[cc - RX]) * i2h;
+      vals[r][0] = phd; vals[r][1] = p0; vals[r][2] = pyd; vals[r][3] = kap; vals[r][4] = phy;
+    }
+    double* W = I.wall + (size_t)wall * 5 * nx;
+    for (int qk = 0; qk < 5; ++qk) W[qk * nx + i] = 0.5 * (3.0 * vals[0][qk] - vals[1][qk]);
+  }
+}
+
+// ------------------------------------------------------------ stage operator
+// One RK4 stage: CDI face fluxes F = u phi_f - gamma[eps dphi/h - phi_f(1-phi_f) n_f]
+// (eq. CDI; wall y-faces F = 0 by the no-flux and no-penetration BCs), the
+// phase-field right-hand side -div F accumulated in FP64, the mass flux
+// m = rho2 u + (rho1-rho2) F (consistent transport, eq. NS_momentum), the
+// momentum right-hand side (advection of m u, variable-viscosity stress with
+// the GNBC wall stress, EB surface tension mu_c grad phi at the faces), then
+// the RK4 combination and the stage (rho u)*.
+//
+// k: stage index 0..3 (k < 0: evaluate the operator only); src/dst:
+// phase-field buffers (0 caller, 1 phi_a, 2 phi_b); c_next = RK c_{k+1}
+// (multiplied by each instance's dt), b_k the RK4 weight of stage k.
+template <typename S>
+__global__ void __launch_bounds__(kNT) k_stage(const Tile* __restrict__ tiles,
+                                                const Inst* __restrict__ insts, int k, int src,
+                                                int dst, double c_next, double b_k, int write_wall) {
+  constexpr int CY = TY + 3, CX = TX + 3;   // cells: rows j0-2..j0+TY, cols i0-2..i0+TX
+  constexpr int UY = TY + 2, UX = TX + 2;   // u/v: rows j0-1..j0+TY, cols i0-1..i0+TX
+  constexpr int XY = TY + 1, XX = TX + 2;   // x-faces: rows j0-1..j0+TY-1, cols i0-1..i0+TX
+  constexpr int YY = TY + 2, YX = TX + 1;   // y-faces: rows j0-1..j0+TY, cols i0-1..i0+TX-1
+  constexpr int CRY = TY + 1, CRX = TX + 1; // corners: rows j0..j0+TY, cols i0..i0+TX
+  __shared__ S s_phi[CY * CX], s_nx[CY * CX], s_ny[CY * CX], s_mc[CY * CX];
+  __shared__ S s_u[UY * UX], s_v[UY * UX];
+  __shared__ S s_fx[XY * XX], s_mx[XY * XX];
+  __shared__ S s_fy[YY * YX], s_my[YY * YX];
+  __shared__ S s_txy[CRY * CRX];
+
+  const Tile t = tiles[blockIdx.x];
+  const Inst& I = insts[t.inst];
+  const int nx = I.nx, ny = I.ny;
+  const int i0 = t.i0, j0 = t.j0;
+  const double* __restrict__ phs = src == 0 ? I.phi : (src == 1 ? I.phi_a : I.phi_b);
+  const double* __restrict__ us = k <= 0 ? I.u : I.us;
+  const double* __restrict__ vs = k <= 0 ? I.v : I.vs;
+  const S* __restrict__ gnx = (const S*)I.nhx;
+  const S* __restrict__ gny = (const S*)I.nhy;
+  const S* __restrict__ gmc = (const S*)I.muc;
+
+  for (int q = threadIdx.x; q < CY * CX; q += kNT) {
+    const int rj = q / CX, ri = q - rj * CX;
+    const int j = j0 - 2 + rj, i = wrap(i0 - 2 + ri, nx);
+    S a = 0, b = 0, c = 0, d = 0;
+    if (j >= 0 && j < ny) {
+      const size_t o = (size_t)j * nx + i;
+      a = (S)phs[o]; b = gnx[o]; c = gny[o]; d = gmc[o];
+    }
+    s_phi[q] = a; s_nx[q] = b; s_ny[q] = c; s_mc[q] = d;
+  }
+  for (int q = threadIdx.x; q < UY * UX; q += kNT) {
+    const int rj = q / UX, ri = q - rj * UX;
+    const int j = j0 - 1 + rj, i = wrap(i0 - 1 + ri, nx);
+    s_u[q] = (j >= 0 && j < ny) ? (S)us[(size_t)j * nx + i] : S(0);
+    s_v[q] = (j >= 0 && j <= ny) ? (S)vs[(size_t)j * nx + i] : S(0);
+  }
+  __syncthreads();
+  const S gam = (S)I.gamma, eps = (S)I.eps, inv_h = (S)I.inv_h;
+  const S drho = (S)(I.rho1 - I.rho2), rho2 = (S)I.rho2;
+  // x-face fluxes (each face computed once per block by this one code path)
+  for (int q = threadIdx.x; q < XY * XX; q += kNT) {
+    const int rj = q / XX, ri = q - rj * XX;
+    const int j = j0 - 1 + rj;
+    S F = 0, m = 0;
+    if (j >= 0 && j < ny) {
+      const int cR = (rj + 1) * CX + (ri + 1);   // cell i  (face i between cells i-1 and i)
+      const int cL = cR - 1;
+      const S pl = s_phi[cL], pr = s_phi[cR];
+      const S pf = S(0.5) * (pl + pr);
+      const S nf = S(0.5) * (s_nx[cL] + s_nx[cR]);
+      const S R = gam * (eps * (pr - pl) * inv_h - pf * (S(1) - pf) * nf);
+      const S u = s_u[rj * UX + ri];
+      F = u * pf - R;
+      m = rho2 * u + drho * F;
+    }
+    s_fx[q] = F; s_mx[q] = m;
+  }
+  // y-face fluxes; wall faces carry no flux
+  for (int q = threadIdx.x; q < YY * YX; q += kNT) {
+    const int rj = q / YX, ri = q - rj * YX;
+    const int f = j0 - 1 + rj;   // y-face index
+    S F = 0, m = 0;
+    if (f >= 1 && f <= ny - 1) {
+      const int cT = (rj + 1) * CX + (ri + 1);   // cell row f
+      const int cB = cT - CX;                     // cell row f-1
+      const S pb = s_phi[cB], pt = s_phi[cT];
+      const S pf = S(0.5) * (pb + pt);
+      const S nf = S(0.5) * (s_ny[cB] + s_ny[cT]);
+      const S R = gam * (eps * (pt - pb) * inv_h - pf * (S(1) - pf) * nf);
+      const S v = s_v[rj * UX + ri];
+      F = v * pf - R;
+      m = rho2 * v + drho * F;
+    }
+    s_fy[q] = F; s_my[q] = m;
+  }
+  // corner shear stress: interior corners mu4 (du/dy + dv/dx); wall corners GNBC
+  {
+    const S mud = (S)(I.mu1 - I.mu2), mu2 = (S)I.mu2;
+    for (int q = threadIdx.x; q < CRY * CRX; q += kNT) {
+      const int rj = q / CRX, ri = q - rj * CRX;
+      const int jc = j0 + rj, ic = i0 + ri;
+      S tau = 0;
+      if (jc >= 1 && jc <= ny - 1) {
+        const int cT = (rj + 2) * CX + (ri + 2);   // cell (jc, ic)
+        const int cB = cT - CX;
+        const S mu4 = S(0.25) * ((mud * s_phi[cB] + mu2) + (mud * s_phi[cB - 1] + mu2) +
+                                 (mud * s_phi[cT] + mu2) + (mud * s_phi[cT - 1] + mu2));
+        const int uo = (rj + 1) * UX + (ri + 1);   // u[jc, ic]
+        const S dudy = (s_u[uo] - s_u[uo - UX]) * inv_h;
+        const S dvdx = (s_v[uo] - s_v[uo - 1]) * inv_h;  // v[jc, ic] - v[jc, ic-1]
+        tau = mu4 * (dudy + dvdx);
+      } else if ((jc == 0 || jc == ny) && ic <= nx) {
+        const int wall = jc == 0 ? 0 : 1;
+        const int ii = wrap(ic, nx);
+        const int urow = wall == 0 ? 0 : ny - 1;
+        const double ur = (double)s_u[(urow - (j0 - 1)) * UX + (ri + 1)];
+        double uY, usl;
+        tau = (S)gnbc_corner(I, wall, ii, ur, uY, usl);
+        if (write_wall && ri < TX && ic < nx) {
+          I.uY[wall * nx + ic] = uY;
+          I.uslip[wall * nx + ic] = usl;
+        }
+      }
+      s_txy[q] = tau;
+    }
+  }
+  __syncthreads();
+
+  const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+  const int i = i0 + tx, j = j0 + ty;
+  if (i >= nx || j >= ny) return;
+  const size_t o = (size_t)j * nx + i;
+  const double* __restrict__ phn = I.phi;   // base phase field of the step
+  double* __restrict__ pdst = dst == 0 ? I.phi : (dst == 1 ? I.phi_a : I.phi_b);
+
+  // ---- phase field: L_phi = -div F, face values differenced in FP64
+  const int fxo = (ty + 1) * XX + (tx + 1);   // x-face i at row j
+  const int fyo = (ty + 1) * YX + (tx + 1);   // y-face j at column i
+  const double Lphi = -(((double)s_fx[fxo + 1] - (double)s_fx[fxo]) +
+                        ((double)s_fy[fyo + YX] - (double)s_fy[fyo])) * I.inv_h;
+
+  const int cc = (ty + 2) * CX + (tx + 2);   // cell (j, i) in the cell region
+  const int uo = (ty + 1) * UX + (tx + 1);   // u[j,i] / v[j,i]
+  const S mud = (S)(I.mu1 - I.mu2), mu2 = (S)I.mu2;
+
+  // ---- x-momentum at u[j, i]
+  S Lmx;
+  {
+    const S fcE = S(0.5) * (s_mx[fxo] + s_mx[fxo + 1]) * S(0.5) * (s_u[uo] + s_u[uo + 1]);
+    const S fcW = S(0.5) * (s_mx[fxo - 1] + s_mx[fxo]) * S(0.5) * (s_u[uo - 1] + s_u[uo]);
+    // corner (i, j+1) and (i, j): y-faces j+1 / j, columns i-1, i
+    const int jt = j + 1;
+    const S fcN = (jt >= ny) ? S(0)
+        : S(0.5) * (s_my[fyo + YX - 1] + s_my[fyo + YX]) * S(0.5) * (s_u[uo] + s_u[uo + UX]);
+    const S fcS = (j == 0) ? S(0)
+        : S(0.5) * (s_my[fyo - 1] + s_my[fyo]) * S(0.5) * (s_u[uo - UX] + s_u[uo]);
+    const S muE = mud * s_phi[cc] + mu2, muW = mud * s_phi[cc - 1] + mu2;
+    const S txxE = S(2) * muE * (s_u[uo + 1] - s_u[uo]) * inv_h;
+    const S txxW = S(2) * muW * (s_u[uo] - s_u[uo - 1]) * inv_h;
+    const int co = ty * CRX + tx;   // corner (i, j)
+    const S tN = s_txy[co + CRX], tS = s_txy[co];
+    const S st = S(0.5) * (s_mc[cc - 1] + s_mc[cc]) * (s_phi[cc] - s_phi[cc - 1]) * inv_h;
+    Lmx = -((fcE - fcW) + (fcN - fcS)) * inv_h + (txxE - txxW) * inv_h + (tN - tS) * inv_h + st;
+  }
+  // ---- y-momentum at interior v[j, i]
+  S Lmy = 0;
+  if (j >= 1) {
+    const S gN = S(0.5) * (s_my[fyo] + s_my[fyo + YX]) * S(0.5) * (s_v[uo] + s_v[uo + UX]);
+    const S gS = S(0.5) * (s_my[fyo - YX] + s_my[fyo]) * S(0.5) * (s_v[uo - UX] + s_v[uo]);
+    // corners (i+1, j) and (i, j): x-faces i+1 / i, rows j-1, j
+    const S fcE = S(0.5) * (s_mx[fxo + 1 - XX] + s_mx[fxo + 1]) * S(0.5) * (s_v[uo] + s_v[uo + 1]);
+    const S fcW = S(0.5) * (s_mx[fxo - XX] + s_mx[fxo]) * S(0.5) * (s_v[uo - 1] + s_v[uo]);
+    const S muN = mud * s_phi[cc] + mu2, muS = mud * s_phi[cc - CX] + mu2;
+    const S tyyN = S(2) * muN * (s_v[uo + UX] - s_v[uo]) * inv_h;
+    const S tyyS = S(2) * muS * (s_v[uo] - s_v[uo - UX]) * inv_h;
+    const int co = ty * CRX + tx;
+    const S tE = s_txy[co + 1], tW = s_txy[co];
+    const S st = S(0.5) * (s_mc[cc - CX] + s_mc[cc]) * (s_phi[cc] - s_phi[cc - CX]) * inv_h;
+    Lmy = -((fcE - fcW) + (gN - gS)) * inv_h + (tyyN - tyyS) * inv_h + (tE - tW) * inv_h + st;
+  }
+
+  if (k < 0) {   // operator evaluation only: publish L_phi, L_mx, L_my
+    I.acc_phi[o] = Lphi;
+    I.acc_mx[o] = (double)Lmx;
+    I.acc_my[o] = (double)Lmy;
+    return;
+  }
+  // ---- RK4 accumulation and next stage
+  double ap, am, an;
+  if (k == 0) {
+    ap = b_k * Lphi; am = b_k * (double)Lmx; an = b_k * (double)Lmy;
+  } else {
+    ap = I.acc_phi[o] + b_k * Lphi;
+    am = I.acc_mx[o] + b_k * (double)Lmx;
+    an = I.acc_my[o] + b_k * (double)Lmy;
+  }
+  const double cn = c_next * I.dt;   // RK c_{k+1} dt of this instance
+  const double r1 = I.rho1, r2 = I.rho2;
+  const double rl = (r1 - r2) * phn[(size_t)j * nx + wrap(i - 1, nx)] + r2;
+  const double rc = (r1 - r2) * phn[o] + r2;
+  const double rfx0 = 0.5 * (rl + rc);
+  const double mx0 = rfx0 * I.u[o];
+  if (k < 3) {
+    I.acc_phi[o] = ap; I.acc_mx[o] = am;
+    pdst[o] = phn[o] + cn * Lphi;
+    I.mx[o] = mx0 + cn * (double)Lmx;
+  } else {
+    pdst[o] = phn[o] + I.dt * ap;
+    I.mx[o] = mx0 + I.dt * am;
+  }
+  if (j >= 1) {
+    const double rb = (r1 - r2) * phn[o - nx] + r2;
+    const double rfy0 = 0.5 * (rb + rc);
+    const double my0 = rfy0 * I.v[o];
+    if (k < 3) {
+      I.acc_my[o] = an;
+      I.my[o] = my0 + cn * (double)Lmy;
+    } else {
+      I.my[o] = my0 + I.dt * an;
+    }
+  }
+}
+
+}  // namespace cdi

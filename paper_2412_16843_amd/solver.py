@@ -1,0 +1,133 @@
+"""Python front end of libcdi: device memory and streams come from PyTorch,
+every computation runs in the library's HIP kernels."""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Dict, List, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+def _ptr(t: torch.Tensor) -> int:
+    return t.data_ptr()
+
+
+class CDISolver:
+    """One instance, or a batch of independent instances, of the CDI + GNBC
+    step on one GPU.
+
+    params: parameter objects (attributes as in workloads.Params);
+    phi0:   initial phase fields, arrays of shape (ny, nx).
+    """
+
+    def __init__(self, params, phi0, precision: str = "fp64", guess: str = "prev",
+                 rtol: float = 0.0, maxit: int = 0, device: str = "cuda:0", u0=None, v0=None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("CDISolver needs a GPU (the HIP library has no CPU path)")
+        single = not isinstance(params, (list, tuple))
+        self.params: List = [params] if single else list(params)
+        phis = [phi0] if single else list(phi0)
+        us = [u0] if single else (u0 if u0 is not None else [None] * len(phis))
+        vs = [v0] if single else (v0 if v0 is not None else [None] * len(phis))
+        if len(phis) != len(self.params):
+            raise ValueError("one phase field per instance is required")
+        self.n = len(self.params)
+        self.device = torch.device(device)
+        self.lib = L.lib()
+        self.cparams = (L.cdi_params * self.n)(*[
+            L.make_params(p, precision, guess, rtol, maxit) for p in self.params])
+        self.fields: List[Dict[str, torch.Tensor]] = []
+        cf = (L.cdi_fields * self.n)()
+        for k, p in enumerate(self.params):
+            f = dict(
+                phi=torch.as_tensor(np.ascontiguousarray(phis[k], dtype=np.float64),
+                                    device=self.device).clone(),
+                u=torch.zeros((p.ny, p.nx), dtype=torch.float64, device=self.device),
+                v=torch.zeros((p.ny + 1, p.nx), dtype=torch.float64, device=self.device),
+                p=torch.zeros((p.ny, p.nx), dtype=torch.float64, device=self.device))
+            if us[k] is not None:
+                f["u"].copy_(torch.as_tensor(np.asarray(us[k], dtype=np.float64)))
+            if vs[k] is not None:
+                f["v"].copy_(torch.as_tensor(np.asarray(vs[k], dtype=np.float64)))
+            self.fields.append(f)
+            cf[k] = L.cdi_fields(_ptr(f["phi"]), _ptr(f["u"]), _ptr(f["v"]), _ptr(f["p"]))
+        self.cfields = cf
+        nbytes = self.lib.cdi_workspace_bytes(self.cparams, self.n)
+        if nbytes == 0:
+            raise L.CDIError(-1, self.lib.cdi_last_error().decode())
+        raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-raw.data_ptr()) % 256
+        self._ws_raw = raw
+        self.ws_ptr = raw.data_ptr() + off
+        self.ws_bytes = nbytes
+        self.stream = torch.cuda.current_stream(self.device)
+        ctx = C.c_void_p()
+        torch.cuda.synchronize(self.device)
+        L.check(self.lib.cdi_init_batch(self.cparams, self.n, self.cfields, self.ws_ptr, nbytes,
+                                        self.stream.cuda_stream, C.byref(ctx)))
+        self.ctx = ctx
+
+    # ------------------------------------------------------------------ run
+    def step(self, nsteps: int = 1, allow_noconv: bool = False) -> int:
+        return L.check(self.lib.cdi_step(self.ctx, int(nsteps)),
+                       allow=(-4,) if allow_noconv else ())
+
+    def diagnostics(self, idx: int = 0) -> Dict[str, float]:
+        d = L.cdi_diag()
+        L.check(self.lib.cdi_diagnostics(self.ctx, idx, C.byref(d)), allow=(-5,))
+        return dict(t=d.t, step=d.step, mass=d.mass, mass0=d.mass0, phi_min=d.phi_min,
+                    phi_max=d.phi_max, max_div=d.max_div, max_uslip_bot=d.max_uslip[0],
+                    max_uslip_top=d.max_uslip[1], max_uY_bot=d.max_uY[0],
+                    max_uY_top=d.max_uY[1], ke=d.ke, last_iters=d.last_iters,
+                    last_relres=d.last_relres, nonfinite=d.nonfinite)
+
+    def eval_rhs(self):
+        """Stage operator on the current fields of instance 0."""
+        p = self.params[0]
+        dev = self.device
+        lphi = torch.empty((p.ny, p.nx), dtype=torch.float64, device=dev)
+        lmx = torch.empty((p.ny, p.nx), dtype=torch.float64, device=dev)
+        lmy = torch.empty((p.ny + 1, p.nx), dtype=torch.float64, device=dev)
+        uy = torch.empty((2, p.nx), dtype=torch.float64, device=dev)
+        us = torch.empty((2, p.nx), dtype=torch.float64, device=dev)
+        L.check(self.lib.cdi_eval_rhs(self.ctx, _ptr(lphi), _ptr(lmx), _ptr(lmy), _ptr(uy),
+                                      _ptr(us)))
+        return lphi, lmx, lmy, uy, us
+
+    def solve_pressure(self, b: torch.Tensor, p0: torch.Tensor | None = None):
+        p = self.params[0]
+        out = torch.zeros((p.ny, p.nx), dtype=torch.float64, device=self.device)
+        if p0 is not None:
+            out.copy_(p0)
+        info = L.cdi_solve_info()
+        bb = b.to(device=self.device, dtype=torch.float64).contiguous()
+        st = self.lib.cdi_solve_pressure(self.ctx, _ptr(bb), _ptr(out), C.byref(info))
+        L.check(st, allow=(-4,))
+        return out, dict(iterations=info.iterations, converged=info.converged,
+                         relres=info.relres, bnorm=info.bnorm, ms=info.ms, status=st)
+
+    def state(self, idx: int = 0):
+        torch.cuda.synchronize(self.device)
+        f = self.fields[idx]
+        return {k: v.detach().cpu().numpy().copy() for k, v in f.items()}
+
+    def set_state(self, idx: int, phi=None, u=None, v=None, p=None):
+        f = self.fields[idx]
+        for k, val in (("phi", phi), ("u", u), ("v", v), ("p", p)):
+            if val is not None:
+                f[k].copy_(torch.as_tensor(np.asarray(val, dtype=np.float64)))
+        torch.cuda.synchronize(self.device)
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None and self.ctx.value:
+            self.lib.cdi_destroy(self.ctx)
+            self.ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

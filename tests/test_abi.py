@@ -1,0 +1,104 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol the
+header declares, and validates parameters on the host before any device work
+(error codes of include/cdi.h)."""
+import ctypes as C
+import math
+import os
+import re
+
+import pytest
+
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cdi.h")
+
+
+def _lib():
+    from paper_2412_16843_amd import _lib as L
+    if not os.path.exists(L.LIB_PATH):
+        pytest.skip("libcdi.so not built")
+    return L
+
+
+def test_header_declarations_are_exported():
+    L = _lib()
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    decl = set(re.findall(r"\b(cdi_[a-z_]+)\s*\(", text))
+    assert {"cdi_init", "cdi_step", "cdi_solve_pressure", "cdi_diagnostics"} <= decl
+    lib = L.lib()
+    for name in sorted(decl):
+        assert hasattr(lib, name), name
+    assert set(L.EXPORTS) == decl
+
+
+def test_struct_layouts_match_header():
+    """The ctypes mirrors list the header's struct members in order."""
+    L = _lib()
+    text = open(HEADER).read()
+    structs = {m.group(2): m.group(1)
+               for m in re.finditer(r"typedef struct \{([^}]*)\}\s*(\w+);", text)}
+    for cname, py in (("cdi_params", L.cdi_params), ("cdi_fields", L.cdi_fields),
+                      ("cdi_solve_info", L.cdi_solve_info), ("cdi_diag", L.cdi_diag)):
+        body = structs[cname]
+        body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+        names = []
+        for stmt in body.split(";"):
+            stmt = stmt.strip()
+            if not stmt:
+                continue
+            parts = stmt.replace("*", " ").split()
+            for tok in " ".join(parts[1:]).split(","):
+                names.append(re.sub(r"\[.*\]", "", tok).strip())
+        assert names == [f[0] for f in py._fields_], (cname, names)
+
+
+def _params(**kw):
+    c = W.config1()
+    p = c.params.replace(**kw) if kw else c.params
+    return p
+
+
+def test_workspace_and_default_dt_host_only():
+    L = _lib()
+    lib = L.lib()
+    p = _params(dt=0.0)
+    cp = L.make_params(p)
+    assert lib.cdi_workspace_bytes(C.byref(cp), 1) > 64 * 32 * 8 * 20
+    # the library's CFL rule equals the set-up rule of the workloads
+    assert math.isclose(lib.cdi_default_dt(C.byref(cp)), W.dt_from_cfl(p), rel_tol=1e-14)
+    c2 = W.config2()
+    cp2 = L.make_params(c2.params.replace(dt=0.0))
+    assert math.isclose(lib.cdi_default_dt(C.byref(cp2)), W.dt_from_cfl(c2.params), rel_tol=1e-14)
+    two = (L.cdi_params * 2)(cp, cp2)
+    assert lib.cdi_workspace_bytes(two, 2) > lib.cdi_workspace_bytes(C.byref(cp), 1)
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(nx=63), -2), (dict(ny=6), -2), (dict(eps=0.0), -1), (dict(theta_eq=0.0), -1),
+    (dict(theta_eq=math.pi), -1), (dict(beta1=0.0), -1), (dict(gamma=-1.0), -1),
+    (dict(rho2=0.0), -1), (dict(lx=3.0), -2), (dict(dt=-1.0), -1)])
+def test_invalid_parameters_rejected_before_device_work(kw, status):
+    L = _lib()
+    lib = L.lib()
+    cp = L.make_params(_params(**kw))
+    ctx = C.c_void_p()
+    f = L.cdi_fields(1, 1, 1, 1)   # never dereferenced: validation comes first
+    st = lib.cdi_init(C.byref(cp), C.byref(f), 256, 1 << 30, None, C.byref(ctx))
+    assert st == status, (st, lib.cdi_last_error())
+    assert ctx.value is None
+    assert len(lib.cdi_last_error()) > 0
+
+
+def test_null_and_small_workspace_rejected():
+    L = _lib()
+    lib = L.lib()
+    cp = L.make_params(_params())
+    f = L.cdi_fields(1, 1, 1, 1)
+    ctx = C.c_void_p()
+    assert lib.cdi_init(C.byref(cp), C.byref(f), None, 1 << 30, None, C.byref(ctx)) == -1
+    assert lib.cdi_init(C.byref(cp), C.byref(f), 256, 16, None, C.byref(ctx)) == -1
+    assert lib.cdi_init(C.byref(cp), C.byref(f), 257, 1 << 30, None, C.byref(ctx)) == -1
+    nf = L.cdi_fields(None, 1, 1, 1)
+    assert lib.cdi_init(C.byref(cp), C.byref(nf), 256, 1 << 30, None, C.byref(ctx)) == -1
+    assert lib.cdi_step(None, 1) == -1
