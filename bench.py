@@ -1,0 +1,195 @@
+#!/usr/bin/env python3
+"""Throughput of the CDI + GNBC time step on one MI355X.
+
+One "step" is one full RK4 time step of the workload: 4 stage evaluations
+(phase-field preparation, fused CDI-flux / momentum / GNBC stage kernel,
+projection right-hand side) and 4 variable-density pressure projections by
+multigrid-preconditioned flexible CG to a relative residual of 1e-10.
+
+Prints one JSON line:
+  metric/value/unit       Mcell-steps/s = nx * ny * steps / wall time / 1e6,
+                          inputs resident in HBM, timed between two device
+                          synchronisations
+  roofline                the dominant kernel's algorithmic bytes per launch
+                          over its average launch time (HIP events on the
+                          library stream), against the 8 TB/s HBM peak
+  cpu_baseline            the FP64 CPU oracle on a bounded sample of the same
+                          workload on this host
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import workloads as W  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic HBM bytes per cell and launch of each kernel family (FP64
+# path): every array element the kernel must read or write, counted once.
+ALGO_BYTES_PER_CELL = {
+    # phi read; n_x, n_y, mu_c written
+    "phase_prep": 8 + 3 * 8,
+    # stage phi, n, mu_c, u, v; base phi, u, v; RK accumulators read+write
+    # (stages 1-2), next phi and (rho u)* written: mean over the 4 stages
+    "stage": (96 + 144 + 144 + 120) / 4,
+    # (rho u)*, next phi read; u*, v*, b, a_x, a_y written
+    "rhs": 3 * 8 + 5 * 8,
+    # CG step fused in (x, d, r, q read; x, r written), then r, a_x, a_y read,
+    # z written, coarse r written (1/4 cell); counted for level 0
+    "mg_down": 4 * 8 + 2 * 8 + 2 * 8 + 8 + 2,
+    # r, a_x, a_y, z, q read, coarse z (1/4); z written
+    "mg_up": 5 * 8 + 2 + 8,
+    # z, d_old, a_x, a_y, r read; d, q written
+    "pcg_spmv": 5 * 8 + 2 * 8,
+    # u*, v*, x, a_x, a_y read; u, v, p written
+    "project": 5 * 8 + 3 * 8,
+}
+
+
+def mg_levels(nx: int, ny: int, coarse_cells: int = 1024):
+    """Multigrid hierarchy of the library: halve while both sizes are even and
+    the level has more than 64 cells; levels at or below `coarse_cells` cells
+    run in the single-block coarse kernel."""
+    levels = [(nx, ny)]
+    while nx % 2 == 0 and ny % 2 == 0 and nx * ny > 64:
+        nx //= 2
+        ny //= 2
+        levels.append((nx, ny))
+    lc = next(k for k, (a, b) in enumerate(levels) if a * b <= coarse_cells)
+    return levels, lc
+
+
+def algo_bytes_per_launch(fam: str, p) -> float:
+    """Algorithmic bytes of one launch of kernel family `fam` on workload p."""
+    cells = p.nx * p.ny
+    if fam in ALGO_BYTES_PER_CELL:
+        return ALGO_BYTES_PER_CELL[fam] * cells
+    levels, lc = mg_levels(p.nx, p.ny)
+    if fam == "mg_coarse":
+        # level-lc right-hand side read and correction written, coefficients of
+        # every coarse level read (x- and y-faces)
+        n = sum(a * b for a, b in levels[lc:])
+        return 8 * (2 * levels[lc][0] * levels[lc][1] + 2 * n)
+    raise KeyError(fam)
+
+
+def workload(name: str):
+    if name in ("couette256x64", "config2"):
+        return W.config2()
+    if name in ("drop64x32", "config1"):
+        return W.config1()
+    if name.startswith("drop") and "x" in name:
+        nx = int(name[4:].split("x")[0])
+        return W.drop_case(nx, nx // 2, 60.0, 10.0, steps=200, name=f"drop{nx}x{nx // 2}_r10")
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(case, budget_s: float = 12.0, max_steps: int = 2000):
+    """The oracle as it stands, single-threaded NumPy/SciPy, on the first
+    steps of the same workload until `budget_s` of CPU time is used."""
+    from oracle import cdi
+    s = cdi.initial_state(case.phi0)
+    t0 = time.perf_counter()
+    n = 0
+    while n < max_steps:
+        s = cdi.step(s, case.params)
+        n += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    cells = case.params.nx * case.params.ny
+    return dict(value=cells * n / dt / 1e6, unit="Mcell-steps/s", cores=1, kind="oracle",
+                sample=f"first {n} steps of {case.name} from its initial state "
+                       f"({dt:.1f} s, NumPy/SciPy FP64, one thread)")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="couette256x64")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--kernel", default="auto",
+                    help="kernel family for the roofline entry (auto: largest device time)")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "decomposition is a design described in DESIGN.md, not part of this build.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2412_16843_amd.solver import CDISolver
+
+    case = workload(args.workload)
+    p = case.params
+    s = CDISolver(p, case.phi0, precision=args.precision, guess="prev", rtol=1e-10)
+    s.step(args.warmup)
+    torch.cuda.synchronize()
+
+    # dominant kernel: device time per family over a short probe run
+    fam = args.kernel
+    if fam == "auto":
+        best = (-1.0, None)
+        for k in list(ALGO_BYTES_PER_CELL) + ["mg_coarse"]:
+            s.timing_enable(k)
+            s.step(5)
+            ms, n = s.timing_read()
+            if ms > best[0]:
+                best = (ms, k)
+        fam = best[1]
+    s.timing_enable(fam)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    k_ms, k_n = s.timing_read()
+    s.timing_enable(None)
+    d = s.diagnostics()
+    elapsed = t1 - t0
+    cells = p.nx * p.ny
+    value = cells * args.steps / elapsed / 1e6
+    per_launch_bytes = algo_bytes_per_launch(fam, p)
+    avg_s = (k_ms / max(k_n, 1)) * 1e-3
+    achieved = per_launch_bytes / avg_s / 1e9 if avg_s > 0 else 0.0
+    out = {
+        "metric": "Mcell-steps/s per CDI-GNBC step",
+        "value": round(value, 4),
+        "unit": "Mcell-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": case.name, "nx": p.nx, "ny": p.ny,
+                   "precision": args.precision, "poisson_rtol": 1e-10,
+                   "last_pcg_iters": d["last_iters"], "parallelism": "single-gpu"},
+        "roofline": {"bound": "hbm", "kernel": fam, "achieved": round(achieved, 2),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                     "launches": k_n, "avg_launch_us": round(avg_s * 1e6, 3),
+                     "algo_bytes_per_launch": per_launch_bytes},
+    }
+    s.close()
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(case)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -148,7 +148,8 @@ double cdi_default_dt(const cdi_params* params);
  * `hip_stream` is a hipStream_t (NULL = default stream).  The initial state
  * in `fields` is read when cdi_step runs.  Supported grids: nx, ny even,
  * nx, ny >= 8, and the multigrid hierarchy (halving both directions while
- * both stay even) must end on a grid of at most 1024 cells. */
+ * both stay even and the level has more than 64 cells) must end on a grid of
+ * at most 1024 cells. */
 cdi_status cdi_init(const cdi_params* params, const cdi_fields* fields, void* workspace,
                     size_t workspace_bytes, void* hip_stream, cdi_ctx** out);
 
@@ -184,6 +185,17 @@ cdi_status cdi_diagnostics(cdi_ctx* ctx, int32_t idx, cdi_diag* out);
  * equation without the pressure gradient. */
 cdi_status cdi_eval_rhs(cdi_ctx* ctx, double* l_phi, double* l_mx, double* l_my,
                         double* u_y, double* u_slip);
+
+/* Measurement hook.  While enabled, every launch of the named kernel family
+ * ("phase_prep", "stage", "rhs", "pcg_init", "mg_down" (finest level, with the
+ * fused CG update), "mg_down_other", "mg_coarse", "mg_up" (finest level),
+ * "mg_up_other", "mg_coef", "pcg_spmv", "pcg_xmean", "project") is bracketed
+ * by HIP events on the context stream; NULL disables.  Resets the totals. */
+cdi_status cdi_timing_enable(cdi_ctx* ctx, const char* kernel);
+
+/* Summed device time (ms) and number of the measured launches since
+ * cdi_timing_enable.  Synchronises the stream. */
+cdi_status cdi_timing_read(cdi_ctx* ctx, double* total_ms, int64_t* launches);
 
 /* Release the context (host memory only; caller buffers are untouched). */
 void cdi_destroy(cdi_ctx* ctx);

@@ -20,8 +20,8 @@ CDI_FP64, CDI_MIXED = 0, 1
 GUESS = {"zero": 0, "prev": 1, "learned": 2}
 
 EXPORTS = ("cdi_workspace_bytes", "cdi_default_dt", "cdi_init", "cdi_init_batch", "cdi_step",
-           "cdi_solve_pressure", "cdi_diagnostics", "cdi_eval_rhs", "cdi_destroy",
-           "cdi_last_error")
+           "cdi_solve_pressure", "cdi_diagnostics", "cdi_eval_rhs", "cdi_timing_enable",
+           "cdi_timing_read", "cdi_destroy", "cdi_last_error")
 
 
 class cdi_params(C.Structure):
@@ -90,6 +90,10 @@ def lib() -> C.CDLL:
     L.cdi_diagnostics.restype = i32
     L.cdi_eval_rhs.argtypes = [vp, vp, vp, vp, vp, vp]
     L.cdi_eval_rhs.restype = i32
+    L.cdi_timing_enable.argtypes = [vp, C.c_char_p]
+    L.cdi_timing_enable.restype = i32
+    L.cdi_timing_read.argtypes = [vp, P(f64), P(C.c_int64)]
+    L.cdi_timing_read.restype = i32
     L.cdi_destroy.argtypes = [vp]
     L.cdi_destroy.restype = None
     L.cdi_last_error.argtypes = []

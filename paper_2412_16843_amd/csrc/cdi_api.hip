@@ -101,12 +101,19 @@ cdi_status resolve(const cdi_params* in, Resolved& r) {
     r.lnx[l] = nx; r.lny[l] = ny;
   }
   r.nlev = l + 1;
-  if ((long)r.lnx[r.nlev - 1] * r.lny[r.nlev - 1] > 1024)
-    return fail(CDI_ERR_SHAPE, "coarsest multigrid grid %dx%d exceeds 1024 cells", r.lnx[r.nlev - 1],
-                r.lny[r.nlev - 1]);
+  if ((long)r.lnx[r.nlev - 1] * r.lny[r.nlev - 1] > kCoarseCells)
+    return fail(CDI_ERR_SHAPE, "coarsest multigrid grid %dx%d exceeds %d cells", r.lnx[r.nlev - 1],
+                r.lny[r.nlev - 1], kCoarseCells);
   r.lc = r.nlev - 1;
   for (int k = 0; k < r.nlev; ++k)
     if ((long)r.lnx[k] * r.lny[k] <= kCoarseCells) { r.lc = k; break; }
+  long cells = 0, yfaces = 0;   // LDS footprint of the single-block coarse cycle
+  for (int k = r.lc; k < r.nlev; ++k) {
+    cells += (long)r.lnx[k] * r.lny[k];
+    yfaces += (long)(r.lny[k] + 1) * r.lnx[k];
+  }
+  if (cells > kCLX || yfaces > kCLY)
+    return fail(CDI_ERR_SHAPE, "coarse multigrid levels too large for one block");
   return CDI_OK;
 }
 
@@ -154,12 +161,14 @@ size_t carve(const Resolved& R, int ntiles_cell, int ntiles_mg0, char* base, siz
   D.b = (double*)take(nc * 8);
   D.x = (double*)take(nc * 8);
   D.rr = (double*)take(nc * 8);
+  D.rr2 = (double*)take(nc * 8);
   D.d0 = (double*)take(nc * 8);
   D.d1 = (double*)take(nc * 8);
   D.q = (double*)take(nc * 8);
   D.zf = (double*)take(nc * 8);
   D.part = (double*)take((size_t)8 * std::max(ntiles_cell, ntiles_mg0) * 8);
   D.pcg = (PcgScalars*)take(sizeof(PcgScalars));
+  D.counters = (unsigned*)take(sizeof(unsigned) * 8 * kCounterStride);
   for (int l = 0; l < R.nlev; ++l) {
     Level& L = D.lev[l];
     L.nx = R.lnx[l];
@@ -175,9 +184,9 @@ size_t carve(const Resolved& R, int ntiles_cell, int ntiles_mg0, char* base, siz
     L.r = (l == 0) ? nullptr : take(lc * S);
     L.z = take(lc * S);
   }
-  const size_t nlc = (size_t)R.lnx[R.lc] * R.lny[R.lc];
   const size_t ncs = (size_t)R.lnx[R.nlev - 1] * R.lny[R.nlev - 1];
-  D.coarse_ws = (double*)take(std::max(nlc, 4 * ncs) * 8);
+  D.cdense = ncs <= (size_t)kDenseMax ? 1 : 0;
+  D.cinv = D.cdense ? (double*)take(ncs * ncs * 8) : nullptr;
   return off;
 }
 
@@ -283,32 +292,78 @@ struct cdi_ctx {
   double rtol = 1e-10;
   int maxit = 200;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  // measurement hook: events around every launch of one kernel family
+  std::string timed;
+  std::vector<hipEvent_t> tev;
+  int tev_used = 0;
+  double timed_ms = 0.0;
+  long timed_launches = 0;
 };
 
 // ---------------------------------------------------------------- launches
 namespace {
 
+constexpr int kTimedPairs = 512;
+
+hipError_t timing_flush(cdi_ctx* c) {
+  if (c->tev_used == 0) return hipSuccess;
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return e;
+  for (int k = 0; k < c->tev_used; ++k) {
+    float ms = 0.f;
+    e = hipEventElapsedTime(&ms, c->tev[2 * k], c->tev[2 * k + 1]);
+    if (e != hipSuccess) return e;
+    c->timed_ms += ms;
+  }
+  c->timed_launches += c->tev_used;
+  c->tev_used = 0;
+  return hipSuccess;
+}
+
+// Launch `body` and, when `name` is the kernel family being measured,
+// bracket it with events on the context stream.
+template <typename F>
+void timed(cdi_ctx* c, const char* name, F&& body) {
+  if (c->timed.empty() || c->timed != name) { body(); return; }
+  if (c->tev_used == kTimedPairs) (void)timing_flush(c);
+  (void)hipEventRecord(c->tev[2 * c->tev_used], c->stream);
+  body();
+  (void)hipEventRecord(c->tev[2 * c->tev_used + 1], c->stream);
+  c->tev_used += 1;
+}
+
+// V-cycle z = M r over every instance.  update: the first kernel applies the
+// CG step (d from buffer dpar) and the stopping test; rsel: residual buffer
+// holding the V-cycle's input.
 template <typename S>
-void launch_vcycle(cdi_ctx* c) {
+void launch_vcycle(cdi_ctx* c, int update, int dpar, int rsel) {
   Batch& B = c->B;
   for (int l = 0; l < B.max_lc; ++l)
     if (!B.mg[l].empty())
-      k_mg_down<S><<<(unsigned)B.mg[l].size(), kNT, 0, c->stream>>>(c->d_mg[l], c->d_inst, l);
-  k_mg_coarse<S><<<(unsigned)B.n, kCoarseNT, 0, c->stream>>>(c->d_inst);
+      timed(c, (l == 0 && update) ? "mg_down" : "mg_down_other", [&] {
+        k_mg_down<S><<<(unsigned)B.mg[l].size(), kNT, 0, c->stream>>>(c->d_mg[l], c->d_inst, l,
+                                                                      update, dpar, rsel);
+      });
+  timed(c, "mg_coarse", [&] {
+    k_mg_coarse<S><<<(unsigned)B.n, kCoarseNT, 0, c->stream>>>(c->d_inst, update, dpar, rsel);
+  });
   for (int l = B.max_lc - 1; l >= 0; --l)
     if (!B.mg[l].empty())
-      k_mg_up<S><<<(unsigned)B.mg[l].size(), kNT, 0, c->stream>>>(c->d_mg[l], c->d_inst, l);
+      timed(c, l == 0 ? "mg_up" : "mg_up_other", [&] {
+        k_mg_up<S><<<(unsigned)B.mg[l].size(), kNT, 0, c->stream>>>(c->d_mg[l], c->d_inst, l, rsel);
+      });
 }
 
 template <typename S>
 void launch_coef(cdi_ctx* c) {
-  for (int l = 1; l < c->B.max_nlev; ++l) {
-    int maxc = 0;
-    for (int k = 0; k < c->B.n; ++k)
-      if (l < c->B.R[k].nlev) maxc = std::max(maxc, c->B.R[k].lnx[l] * (c->B.R[k].lny[l] + 1));
-    const unsigned grid = (unsigned)std::max(1, std::min(1024, ceil_div(maxc, kNT)));
-    k_mg_coef<S><<<grid, kNT, 0, c->stream>>>(c->d_inst, c->B.n, l);
+  int maxc = 0;
+  for (int k = 0; k < c->B.n; ++k)
+    if (c->B.R[k].nlev > 1) maxc = std::max(maxc, c->B.R[k].lnx[1] * (c->B.R[k].lny[1] + 1));
+  if (maxc > 0) {
+    const dim3 grid((unsigned)std::max(1, std::min(256, ceil_div(maxc, kNT))), (unsigned)c->B.n);
+    timed(c, "mg_coef", [&] { k_mg_coef<S><<<grid, kNT, 0, c->stream>>>(c->d_inst); });
   }
+  timed(c, "mg_coef", [&] { k_coarse_inv<S><<<(unsigned)c->B.n, kCoarseNT, 0, c->stream>>>(c->d_inst); });
 }
 
 // Flexible-CG loop after the right-hand side is in place.  Returns NOCONV
@@ -321,14 +376,16 @@ cdi_status solve_loop(cdi_ctx* c, int guess) {
     launch_coef<S>(c);
     c->coef_ready = true;
   }
-  k_pcg_init<<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, guess);
+  timed(c, "pcg_init", [&] { k_pcg_init<<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, guess); });
+  // z0 = M r0 (residual in buffer 0)
+  launch_vcycle<S>(c, 0, 0, 0);
   int it = 0;
   int next_check = std::max(1, c->pred_iters - 1);
   bool all_done = false;
   while (it < c->maxit) {
-    launch_vcycle<S>(c);
-    k_pcg_spmv<<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, it & 1);
-    k_pcg_update<<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, it & 1);
+    const int par = it & 1;
+    timed(c, "pcg_spmv", [&] { k_pcg_spmv<<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, par, par); });
+    launch_vcycle<S>(c, 1, par, par ^ 1);
     ++it;
     if (it >= next_check || it >= c->maxit) {
       HIPCHK(hipMemcpyAsync(c->h_pcg, B.inst[0].pcg, sizeof(PcgScalars), hipMemcpyDeviceToHost, c->stream));
@@ -346,7 +403,7 @@ cdi_status solve_loop(cdi_ctx* c, int guess) {
       HIPCHK(hipMemcpyAsync(c->h_pcg + k, B.inst[k].pcg, sizeof(PcgScalars), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
   }
-  k_pcg_xmean<<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst);
+  timed(c, "pcg_xmean", [&] { k_pcg_xmean<<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst); });
   int maxi = 0;
   bool noconv = false;
   for (int k = 0; k < B.n; ++k) {
@@ -371,16 +428,18 @@ cdi_status run_step(cdi_ctx* c) {
   for (int k = 0; k < 4; ++k) {
     const int src = k == 0 ? 0 : (k == 2 ? 2 : 1);
     const int dst = (k == 0 || k == 2) ? 1 : 2;
-    k_phase_prep<S><<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, src);
+    timed(c, "phase_prep", [&] { k_phase_prep<S><<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, src); });
     // per-instance dt: c_next and tau are passed as multiples of the instance dt
-    k_stage<S><<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, k, src, dst,
-                                              k < 3 ? RK_C[k + 1] : 1.0, RK_B[k], k == 3);
+    timed(c, "stage", [&] {
+      k_stage<S><<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, k, src, dst,
+                                                k < 3 ? RK_C[k + 1] : 1.0, RK_B[k], k == 3);
+    });
     const double tfac = k < 3 ? RK_C[k + 1] : 1.0;
-    k_rhs<S><<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, dst, tfac, c->rtol, c->maxit);
+    timed(c, "rhs", [&] { k_rhs<S><<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, dst, tfac, c->rtol, c->maxit); });
     cdi_status s = solve_loop<S>(c, c->guess == CDI_GUESS_ZERO ? 0 : 1);
     if (s == CDI_ERR_NOCONV) st = s;
     else if (s != CDI_OK) return s;
-    k_project<<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, tfac, k == 3, dst);
+    timed(c, "project", [&] { k_project<<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, tfac, k == 3, dst); });
   }
   (void)dt;
   HIPCHK(hipGetLastError());
@@ -623,6 +682,35 @@ cdi_status cdi_diagnostics(cdi_ctx* c, int32_t idx, cdi_diag* out) {
   return out->nonfinite ? fail(CDI_ERR_NONFINITE, "non-finite value in the state") : CDI_OK;
 }
 
+cdi_status cdi_timing_enable(cdi_ctx* c, const char* kernel) {
+  if (!c) return fail(CDI_ERR_ARG, "ctx is NULL");
+  static const char* known[] = {"phase_prep", "stage", "rhs", "pcg_init", "mg_down",
+                                "mg_down_other", "mg_coarse", "mg_up", "mg_up_other", "mg_coef",
+                                "pcg_spmv", "pcg_xmean", "project"};
+  HIPCHK(hipStreamSynchronize(c->stream));
+  c->tev_used = 0;
+  c->timed_ms = 0.0;
+  c->timed_launches = 0;
+  if (!kernel) { c->timed.clear(); return CDI_OK; }
+  bool ok = false;
+  for (const char* k : known) ok = ok || std::strcmp(k, kernel) == 0;
+  if (!ok) return fail(CDI_ERR_ARG, "unknown kernel family '%s'", kernel);
+  if (c->tev.empty()) {
+    c->tev.assign(2 * kTimedPairs, nullptr);
+    for (auto& e : c->tev) HIPCHK(hipEventCreate(&e));
+  }
+  c->timed = kernel;
+  return CDI_OK;
+}
+
+cdi_status cdi_timing_read(cdi_ctx* c, double* total_ms, int64_t* launches) {
+  if (!c || !total_ms || !launches) return fail(CDI_ERR_ARG, "NULL argument");
+  HIPCHK(timing_flush(c));
+  *total_ms = c->timed_ms;
+  *launches = c->timed_launches;
+  return CDI_OK;
+}
+
 void cdi_destroy(cdi_ctx* c) {
   if (!c) return;
   if (c->stream) (void)hipStreamSynchronize(c->stream);
@@ -630,6 +718,7 @@ void cdi_destroy(cdi_ctx* c) {
   if (c->h_pcg) (void)hipHostFree(c->h_pcg);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
+  for (auto e : c->tev) if (e) (void)hipEventDestroy(e);
   delete c;
 }
 

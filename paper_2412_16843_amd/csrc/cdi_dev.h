@@ -42,7 +42,7 @@ struct PcgScalars {
   int first;                // 1 before the first direction is formed
   int converged;
   int pad;
-  unsigned counter[8];      // arrival counters of the last-block reductions
+  int pad2;
 };
 
 struct Inst {
@@ -68,12 +68,15 @@ struct Inst {
   // level-0 FP64 coefficients a = 1/(rho_f h^2) of the pressure operator
   double* ax0; double* ay0;
   // pressure (FP64 CG vectors)
-  double* b; double* x; double* rr; double* d0; double* d1; double* q;
+  double* b; double* x; double* rr; double* rr2; double* d0; double* d1; double* q;
   double* zf;                          // FP64 copy of level-0 correction (mixed path)
   double* part;                        // reduction partials, [8][ntiles]
   PcgScalars* pcg;
+  unsigned* counters;                  // [8 kinds][kCounterStride] arrival counters
   Level lev[kMaxLevels];
-  double* coarse_ws;                   // coarse CG vectors
+  double* cinv;                        // dense inverse of the coarsest operator (n <= 64)
+  int cdense;                          // 1 if cinv is used for the coarsest solve
+  int pad_;
 };
 
 struct Tile {
@@ -126,29 +129,66 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* sh /* >= NV*N
       v[k] = s;
     }
   }
+  __syncthreads();   // sh may be reused right after
 }
 
-// Coherent load of a value published by another block of the same launch.
+// Coherent load / store of a value exchanged between blocks of one launch.
+// Both bypass the per-XCD L2 (device-coherent access), so publishing a
+// partial needs no L2 write-back or invalidation (an agent-scope fence would
+// flush and invalidate the whole L2 of the block's XCD).
 __device__ __forceinline__ double ld_agent(const double* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ __forceinline__ void st_agent(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
-// Last-block-done: every block of an instance publishes its partial, then
-// counts itself in; the last one to arrive sees all partials.
-__device__ __forceinline__ bool arrive_last(unsigned* counter, int nblocks) {
+// Last-block-done: every block of an instance publishes its partial (thread 0,
+// st_agent), then counts itself in once that store has completed; the last
+// one to arrive reads all partials with ld_agent.  Arrivals are
+// spread over kSubCounters counters (block `local` uses counter local % k)
+// whose last arrivals count into counter 0, so no single address takes more
+// than ~nblocks/kSubCounters + kSubCounters serialised atomics.
+constexpr int kSubCounters = 64;
+constexpr int kCounterStride = kSubCounters + 1;   // counters per reduction kind
+
+__device__ __forceinline__ bool arrive_last(unsigned* counters, int nblocks, int local) {
   __shared__ int s_last;
   __syncthreads();
   if (threadIdx.x == 0) {
-    __threadfence();
-    unsigned prev = atomicAdd(counter, 1u);
-    s_last = (prev == (unsigned)(nblocks - 1));
-    if (s_last) {
-      __threadfence();
-      atomicExch(counter, 0u);
+    __builtin_amdgcn_s_waitcnt(0);   // the partial store is complete (acknowledged)
+    bool last;
+    if (nblocks <= 2 * kSubCounters) {
+      const unsigned prev = atomicAdd(&counters[0], 1u);
+      last = prev == (unsigned)(nblocks - 1);
+      if (last) atomicExch(&counters[0], 0u);
+    } else {
+      const int sub = local % kSubCounters;
+      const int members = (nblocks - sub + kSubCounters - 1) / kSubCounters;
+      const unsigned prev = atomicAdd(&counters[1 + sub], 1u);
+      last = false;
+      if (prev == (unsigned)(members - 1)) {
+        atomicExch(&counters[1 + sub], 0u);
+        const unsigned top = atomicAdd(&counters[0], 1u);
+        last = top == (unsigned)(kSubCounters - 1);
+        if (last) atomicExch(&counters[0], 0u);
+      }
     }
+    s_last = last;
   }
   __syncthreads();
   return s_last != 0;
+}
+
+// Sum of n per-block partials, read by every thread of the last block in a
+// fixed thread/partial mapping and combined by a fixed-order tree: the result
+// (valid in thread 0) does not depend on block completion order.
+template <int NT = kNT>
+__device__ __forceinline__ double sum_partials(const double* src, int n, double* sh) {
+  double v[1] = {0.0};
+  for (int k = threadIdx.x; k < n; k += NT) v[0] += ld_agent(&src[k]);
+  block_sum<1, NT>(v, sh);
+  return v[0];
 }
 
 }  // namespace cdi

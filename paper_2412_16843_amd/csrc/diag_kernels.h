@@ -65,34 +65,36 @@ __global__ void __launch_bounds__(kNT) k_diag(const Tile* __restrict__ tiles,
   block_sum<3>(s, sh);
   __syncthreads();
   if (threadIdx.x == 0) {
-    I.part[t.local] = s[0];
-    I.part[I.ntiles + t.local] = s[1];
-    I.part[2 * I.ntiles + t.local] = s[2];
+    st_agent(&I.part[t.local], s[0]);
+    st_agent(&I.part[I.ntiles + t.local], s[1]);
+    st_agent(&I.part[2 * I.ntiles + t.local], s[2]);
   }
   block_max<3>(m, sh);
   if (threadIdx.x == 0) {
-    I.part[3 * I.ntiles + t.local] = m[0];
-    I.part[4 * I.ntiles + t.local] = m[1];
-    I.part[5 * I.ntiles + t.local] = m[2];
+    st_agent(&I.part[3 * I.ntiles + t.local], m[0]);
+    st_agent(&I.part[4 * I.ntiles + t.local], m[1]);
+    st_agent(&I.part[5 * I.ntiles + t.local], m[2]);
   }
-  if (arrive_last(&I.pcg->counter[5], I.ntiles)) {
+  if (arrive_last(I.counters + 5 * kCounterStride, I.ntiles, t.local)) {
+    const int n = I.ntiles;
+    const double a = sum_partials(I.part, n, sh);
+    const double b = sum_partials(I.part + n, n, sh);
+    const double c = sum_partials(I.part + 2 * n, n, sh);
+    double mm[3] = {-1e300, -1e300, 0.0};
+    for (int k = threadIdx.x; k < n; k += kNT) {
+      mm[0] = fmax(mm[0], ld_agent(&I.part[3 * n + k]));
+      mm[1] = fmax(mm[1], ld_agent(&I.part[4 * n + k]));
+      mm[2] = fmax(mm[2], ld_agent(&I.part[5 * n + k]));
+    }
+    block_max<3>(mm, sh);
     if (threadIdx.x == 0) {
-      double a = 0.0, b = 0.0, c = 0.0, mn = -1e300, mx = -1e300, md = 0.0;
-      for (int k = 0; k < I.ntiles; ++k) {
-        a += ld_agent(&I.part[k]);
-        b += ld_agent(&I.part[I.ntiles + k]);
-        c += ld_agent(&I.part[2 * I.ntiles + k]);
-        mn = fmax(mn, ld_agent(&I.part[3 * I.ntiles + k]));
-        mx = fmax(mx, ld_agent(&I.part[4 * I.ntiles + k]));
-        md = fmax(md, ld_agent(&I.part[5 * I.ntiles + k]));
-      }
       DiagOut& D = out[t.inst];
       D.mass = a * I.h * I.h;
       D.ke = b;
       D.nonfinite = c;
-      D.phi_min = -mn;
-      D.phi_max = mx;
-      D.max_div = md;
+      D.phi_min = -mm[0];
+      D.phi_max = mm[1];
+      D.max_div = mm[2];
     }
   }
 }
@@ -146,11 +148,10 @@ __global__ void __launch_bounds__(kNT) k_solve_setup(const Tile* __restrict__ ti
     bs[0] = b;
   }
   block_sum<1>(bs, sh);
-  if (threadIdx.x == 0) I.part[t.local] = bs[0];
-  if (arrive_last(&I.pcg->counter[0], I.ntiles)) {
+  if (threadIdx.x == 0) st_agent(&I.part[t.local], bs[0]);
+  if (arrive_last(I.counters + 0 * kCounterStride, I.ntiles, t.local)) {
+    const double s = sum_partials(I.part, I.ntiles, sh);
     if (threadIdx.x == 0) {
-      double s = 0.0;
-      for (int k = 0; k < I.ntiles; ++k) s += ld_agent(&I.part[k]);
       PcgScalars* P = I.pcg;
       P->bmean = s / ((double)nx * ny);
       P->done = 0; P->iters = 0; P->first = 1; P->converged = 0; P->pad = 0;

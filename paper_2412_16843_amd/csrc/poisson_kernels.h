@@ -12,25 +12,33 @@
 // walls), restriction R = P^T / 4, coarse coefficients averaged from the two
 // fine faces covering each coarse face and scaled by 1/4 (h doubles), one
 // red-black Gauss-Seidel sweep before (red, black) and after (black, red)
-// the coarse correction so that the V-cycle is symmetric; the coarsest grid
-// is solved by CG inside one block.  Levels at or below kCoarseCells cells
-// run inside a single-block kernel; finer levels use LDS-tiled kernels whose
+// the coarse correction so that the V-cycle is symmetric.  Levels at or
+// below kCoarseCells cells live in the LDS of one block per instance; the
+// coarsest grid is solved exactly (dense inverse of K + s 11^T/n, or CG when
+// it is larger than kDenseMax).  Finer levels use LDS-tiled kernels whose
 // tiles span every instance of a batch.
+//
+// One flexible-CG iteration is: k_pcg_spmv (d, q = K d, alpha) then the
+// V-cycle, whose first kernel also applies x += alpha d, r -= alpha q and
+// takes the stopping test, and whose last kernel forms beta.
 #pragma once
 #include "stage_kernels.h"
 
 namespace cdi {
 
-constexpr int kCoarseCells = 4096;
-constexpr int kCoarseNT = 512;
+constexpr int kCoarseCells = 1024;   // levels at or below this size run in one block
+constexpr int kCoarseNT = 1024;
+constexpr int kDenseMax = 64;        // coarsest grids up to this size use a dense inverse
+constexpr int kCLX = 1376;           // LDS cells of all coarse levels (<= 1024 * 4/3)
+constexpr int kCLY = 2432;           // LDS y-faces of all coarse levels
 constexpr int FX = 32, FY = 16;            // fine tile of the multigrid kernels
 static_assert(FX * FY == 2 * kNT, "MG tile = 2 cells per thread");
 
 // ------------------------------------------------------------ projection RHS
 // u* = (rho u)* / rho_f(phi_next) on the faces of every cell, b = div(u*)/tau
-// (tau given as a multiple of the instance time step),
-// the FP64 face coefficients of the pressure operator (and their S copy for
-// the V-cycle), and the instance's sum of b.  Resets the CG state.
+// (tau given as a multiple of the instance time step), the FP64 face
+// coefficients of the pressure operator (and their S copy for the V-cycle),
+// and the instance's mean of b.  Resets the CG state.
 template <typename S>
 __global__ void __launch_bounds__(kNT) k_rhs(const Tile* __restrict__ tiles,
                                               const Inst* __restrict__ insts, int src, double tau,
@@ -53,7 +61,7 @@ __global__ void __launch_bounds__(kNT) k_rhs(const Tile* __restrict__ tiles,
     const double rfw = 0.5 * (rw + rc), rfe = 0.5 * (rc + re);
     const double uw = I.mx[o] / rfw;
     const double ue = I.mx[(size_t)j * nx + ie] / rfe;
-    double vs = 0.0, vn = 0.0, rfs = 0.0, rfn = 0.0;
+    double vs = 0.0, vn = 0.0, rfs = 0.0;
     if (j >= 1) {
       const double rs = (r1 - r2) * ph[o - nx] + r2;
       rfs = 0.5 * (rs + rc);
@@ -61,8 +69,7 @@ __global__ void __launch_bounds__(kNT) k_rhs(const Tile* __restrict__ tiles,
     }
     if (j + 1 <= ny - 1) {
       const double rn = (r1 - r2) * ph[o + nx] + r2;
-      rfn = 0.5 * (rc + rn);
-      vn = I.my[o + nx] / rfn;
+      vn = I.my[o + nx] / (0.5 * (rc + rn));
     }
     const double b = ((ue - uw) + (vn - vs)) * I.inv_h / (tau * I.dt);
     I.ustar[o] = uw;
@@ -80,11 +87,10 @@ __global__ void __launch_bounds__(kNT) k_rhs(const Tile* __restrict__ tiles,
     }
   }
   block_sum<1>(bsum, sh);
-  if (threadIdx.x == 0) I.part[t.local] = bsum[0];
-  if (arrive_last(&I.pcg->counter[0], I.ntiles)) {
+  if (threadIdx.x == 0) st_agent(&I.part[t.local], bsum[0]);
+  if (arrive_last(I.counters + 0 * kCounterStride, I.ntiles, t.local)) {
+    const double s = sum_partials(I.part, I.ntiles, sh);
     if (threadIdx.x == 0) {
-      double s = 0.0;
-      for (int k = 0; k < I.ntiles; ++k) s += ld_agent(&I.part[k]);
       PcgScalars* P = I.pcg;
       P->bmean = s / ((double)nx * ny);
       P->done = 0; P->iters = 0; P->first = 1; P->converged = 0; P->pad = 0;
@@ -132,14 +138,13 @@ __global__ void __launch_bounds__(kNT) k_pcg_init(const Tile* __restrict__ tiles
   }
   block_sum<2>(s, sh);
   if (threadIdx.x == 0) {
-    I.part[t.local] = s[0];
-    I.part[I.ntiles + t.local] = s[1];
+    st_agent(&I.part[t.local], s[0]);
+    st_agent(&I.part[I.ntiles + t.local], s[1]);
   }
-  if (arrive_last(&I.pcg->counter[1], I.ntiles)) {
+  if (arrive_last(I.counters + 1 * kCounterStride, I.ntiles, t.local)) {
+    const double ff = sum_partials(I.part, I.ntiles, sh);
+    const double rr = sum_partials(I.part + I.ntiles, I.ntiles, sh);
     if (threadIdx.x == 0) {
-      double ff = 0.0, rr = 0.0;
-      for (int k = 0; k < I.ntiles; ++k) ff += ld_agent(&I.part[k]);
-      for (int k = 0; k < I.ntiles; ++k) rr += ld_agent(&I.part[I.ntiles + k]);
       PcgScalars* P = I.pcg;
       P->fnorm = sqrt(ff);
       P->rr = rr;
@@ -156,7 +161,8 @@ __global__ void __launch_bounds__(kNT) k_pcg_init(const Tile* __restrict__ tiles
 // d = z + beta d_old (d = z on the first iteration), q = K d, (d, r), (d, q);
 // last block: alpha = (d, r)/(d, q).
 __global__ void __launch_bounds__(kNT) k_pcg_spmv(const Tile* __restrict__ tiles,
-                                                  const Inst* __restrict__ insts, int parity) {
+                                                  const Inst* __restrict__ insts, int parity,
+                                                  int rsel) {
   __shared__ double sh[2 * kNT / 64];
   const Tile t = tiles[blockIdx.x];
   const Inst& I = insts[t.inst];
@@ -181,19 +187,18 @@ __global__ void __launch_bounds__(kNT) k_pcg_spmv(const Tile* __restrict__ tiles
     if (j + 1 < ny) q += I.ay0[o + nx] * (dc - dval(o + nx));
     dnew[o] = dc;
     I.q[o] = q;
-    s[0] = dc * I.rr[o];
+    s[0] = dc * (rsel ? I.rr2 : I.rr)[o];
     s[1] = dc * q;
   }
   block_sum<2>(s, sh);
   if (threadIdx.x == 0) {
-    I.part[t.local] = s[0];
-    I.part[I.ntiles + t.local] = s[1];
+    st_agent(&I.part[t.local], s[0]);
+    st_agent(&I.part[I.ntiles + t.local], s[1]);
   }
-  if (arrive_last(&I.pcg->counter[2], I.ntiles)) {
+  if (arrive_last(I.counters + 2 * kCounterStride, I.ntiles, t.local)) {
+    const double dr = sum_partials(I.part, I.ntiles, sh);
+    const double dq = sum_partials(I.part + I.ntiles, I.ntiles, sh);
     if (threadIdx.x == 0) {
-      double dr = 0.0, dq = 0.0;
-      for (int k = 0; k < I.ntiles; ++k) dr += ld_agent(&I.part[k]);
-      for (int k = 0; k < I.ntiles; ++k) dq += ld_agent(&I.part[I.ntiles + k]);
       PcgScalars* P = I.pcg;
       P->dr = dr; P->dq = dq;
       P->alpha = dq != 0.0 ? dr / dq : 0.0;
@@ -202,47 +207,15 @@ __global__ void __launch_bounds__(kNT) k_pcg_spmv(const Tile* __restrict__ tiles
   }
 }
 
-// x += alpha d, r -= alpha q; last block: relres = ||r|| / ||f||, stop test.
-__global__ void __launch_bounds__(kNT) k_pcg_update(const Tile* __restrict__ tiles,
-                                                    const Inst* __restrict__ insts, int parity) {
-  __shared__ double sh[2 * kNT / 64];
-  const Tile t = tiles[blockIdx.x];
-  const Inst& I = insts[t.inst];
-  if (I.pcg->done) return;
-  const int nx = I.nx, ny = I.ny;
-  const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
-  const int i = t.i0 + tx, j = t.j0 + ty;
-  const double* __restrict__ d = parity ? I.d1 : I.d0;
-  const double alpha = I.pcg->alpha;
-  double s[2] = {0.0, 0.0};
-  if (i < nx && j < ny) {
-    const size_t o = (size_t)j * nx + i;
-    const double x = I.x[o] + alpha * d[o];
-    const double r = I.rr[o] - alpha * I.q[o];
-    I.x[o] = x;
-    I.rr[o] = r;
-    s[0] = r * r;
-    s[1] = x;
-  }
-  block_sum<2>(s, sh);
-  if (threadIdx.x == 0) {
-    I.part[t.local] = s[0];
-    I.part[I.ntiles + t.local] = s[1];
-  }
-  if (arrive_last(&I.pcg->counter[3], I.ntiles)) {
-    if (threadIdx.x == 0) {
-      double rr = 0.0, sx = 0.0;
-      for (int k = 0; k < I.ntiles; ++k) rr += ld_agent(&I.part[k]);
-      for (int k = 0; k < I.ntiles; ++k) sx += ld_agent(&I.part[I.ntiles + k]);
-      PcgScalars* P = I.pcg;
-      P->rr = rr;
-      P->xmean = sx / ((double)nx * ny);
-      P->iters += 1;
-      P->relres = sqrt(rr) / P->fnorm;
-      if (P->relres <= P->rtol) { P->done = 1; P->converged = 1; }
-      else if (P->iters >= P->maxit) { P->done = 1; }
-    }
-  }
+// Stopping test after the update x += alpha d, r -= alpha q (run by the
+// last block of the kernel that applied it).
+__device__ __forceinline__ void pcg_stop_test(PcgScalars* P, double rr, double sx, double n) {
+  P->rr = rr;
+  P->xmean = sx / n;
+  P->iters += 1;
+  P->relres = sqrt(rr) / P->fnorm;
+  if (P->relres <= P->rtol) { P->done = 1; P->converged = 1; }
+  else if (P->iters >= P->maxit) { P->done = 1; }
 }
 
 // Mean of the solution when the solve ended before any CG update.
@@ -258,20 +231,17 @@ __global__ void __launch_bounds__(kNT) k_pcg_xmean(const Tile* __restrict__ tile
   double s[1] = {0.0};
   if (i < nx && j < ny) s[0] = I.x[(size_t)j * nx + i];
   block_sum<1>(s, sh);
-  if (threadIdx.x == 0) I.part[t.local] = s[0];
-  if (arrive_last(&I.pcg->counter[6], I.ntiles)) {
-    if (threadIdx.x == 0) {
-      double sx = 0.0;
-      for (int k = 0; k < I.ntiles; ++k) sx += ld_agent(&I.part[k]);
-      I.pcg->xmean = sx / ((double)nx * ny);
-    }
+  if (threadIdx.x == 0) st_agent(&I.part[t.local], s[0]);
+  if (arrive_last(I.counters + 6 * kCounterStride, I.ntiles, t.local)) {
+    const double sx = sum_partials(I.part, I.ntiles, sh);
+    if (threadIdx.x == 0) I.pcg->xmean = sx / ((double)nx * ny);
   }
 }
 
 // u = u* - tau grad(p)/rho_f on interior faces (tau a multiple of the
-// instance time step); the pressure is stored
-// mean-free.  final_stage: the result is the new state (caller fields) and
-// the new phase field is copied from phi_next.
+// instance time step); the pressure is stored mean-free.  final_stage: the
+// result is the new state (caller fields) and the new phase field is copied
+// from phi_next.
 __global__ void __launch_bounds__(kNT) k_project(const Tile* __restrict__ tiles,
                                                  const Inst* __restrict__ insts, double tau,
                                                  int final_stage, int src) {
@@ -309,22 +279,54 @@ __device__ __forceinline__ S ldS(const void* p, size_t o) { return ((const S*)p)
 
 // Pre-smoothing from z = 0 (red z = r/D, black Gauss-Seidel), residual
 // r - K z and restriction R = P^T/4 to the next level, on one fine tile.
-// Level 0 reads the FP64 CG residual.
+// Level 0 reads the FP64 CG residual; with `update` it first applies the CG
+// step x += alpha d, r -= alpha q (d from buffer `parity`) and takes the
+// stopping test.
 template <typename S>
 __global__ void __launch_bounds__(kNT) k_mg_down(const Tile* __restrict__ tiles,
-                                                  const Inst* __restrict__ insts, int level) {
+                                                  const Inst* __restrict__ insts, int level,
+                                                  int update, int parity, int rsel) {
   constexpr int H = 3;
   constexpr int RY = FY + 2 * H, RX = FX + 2 * H;       // 22 x 38 (r, z)
   constexpr int PY = FY + 2, PX = FX + 2;                // residual, halo 1
   __shared__ S s_r[RY * RX], s_z[RY * RX];
   __shared__ S s_ax[RY * (RX + 1)], s_ay[(RY + 1) * RX];
   __shared__ S s_rp[PY * PX];
+  __shared__ double sh[2 * kNT / 64];
   const Tile t = tiles[blockIdx.x];
   const Inst& I = insts[t.inst];
   if (I.pcg->done) return;
   const Level& L = I.lev[level];
   const int nx = L.nx, ny = L.ny;
   const int i0 = t.i0, j0 = t.j0;
+  const bool upd = update && level == 0;
+  const double alpha = upd ? I.pcg->alpha : 0.0;
+  // level-0 residual: read the previous buffer when updating, write the current one
+  const double* __restrict__ rin = (upd ? (rsel ? I.rr : I.rr2) : (rsel ? I.rr2 : I.rr));
+  double* __restrict__ rout = rsel ? I.rr2 : I.rr;
+  // CG update on the tile (FP64), partial ||r||^2 and sum(x)
+  double red[2] = {0.0, 0.0};
+  if (upd) {
+    const double* __restrict__ d = parity ? I.d1 : I.d0;
+    for (int k = threadIdx.x; k < FX * FY; k += kNT) {
+      const int ty = k / FX, tx = k - ty * FX;
+      const int j = j0 + ty, i = i0 + tx;
+      if (j < ny && i < nx) {
+        const size_t o = (size_t)j * nx + i;
+        const double x = I.x[o] + alpha * d[o];
+        const double r = rin[o] - alpha * I.q[o];
+        I.x[o] = x;
+        rout[o] = r;
+        red[0] += r * r;
+        red[1] += x;
+      }
+    }
+    block_sum<2>(red, sh);
+    if (threadIdx.x == 0) {
+      st_agent(&I.part[t.local], red[0]);
+      st_agent(&I.part[L.ntiles + t.local], red[1]);
+    }
+  }
   // loads (rows outside the grid hold zeros and are never used as cells)
   for (int k = threadIdx.x; k < RY * (RX + 1); k += kNT) {
     const int rj = k / (RX + 1), ri = k - rj * (RX + 1);
@@ -342,7 +344,7 @@ __global__ void __launch_bounds__(kNT) k_mg_down(const Tile* __restrict__ tiles,
     S r = 0;
     if (j >= 0 && j < ny) {
       const size_t o = (size_t)j * nx + i;
-      r = level == 0 ? (S)I.rr[o] : ldS<S>(L.r, o);
+      r = level == 0 ? (S)(upd ? rin[o] - alpha * I.q[o] : rin[o]) : ldS<S>(L.r, o);
     }
     s_r[k] = r;
   }
@@ -416,6 +418,11 @@ __global__ void __launch_bounds__(kNT) k_mg_down(const Tile* __restrict__ tiles,
     }
     ((S*)C.r)[(size_t)J * C.nx + Ic] = S(0.25) * acc;
   }
+  if (upd && arrive_last(I.counters + 3 * kCounterStride, L.ntiles, t.local)) {
+    const double rr = sum_partials(I.part, L.ntiles, sh);
+    const double sx = sum_partials(I.part + L.ntiles, L.ntiles, sh);
+    if (threadIdx.x == 0) pcg_stop_test(I.pcg, rr, sx, (double)nx * ny);
+  }
 }
 
 // Bilinear prolongation of the coarse correction at fine cell (j, i).
@@ -431,10 +438,11 @@ __device__ __forceinline__ S prolong(const S* e, int cnx, int cny, int j, int i)
 }
 
 // z += P e, then post-smoothing (black, then red).  Level 0 writes the FP64
-// preconditioned residual and the partial (z, q) of the flexible-CG beta.
+// preconditioned residual and forms the flexible-CG beta.
 template <typename S>
 __global__ void __launch_bounds__(kNT) k_mg_up(const Tile* __restrict__ tiles,
-                                                const Inst* __restrict__ insts, int level) {
+                                                const Inst* __restrict__ insts, int level,
+                                                int rsel) {
   constexpr int H = 2;
   constexpr int RY = FY + 2 * H, RX = FX + 2 * H;       // 20 x 36
   __shared__ S s_r[RY * RX], s_z[RY * RX];
@@ -464,7 +472,7 @@ __global__ void __launch_bounds__(kNT) k_mg_up(const Tile* __restrict__ tiles,
     S r = 0, z = 0;
     if (j >= 0 && j < ny) {
       const size_t o = (size_t)j * nx + i;
-      r = level == 0 ? (S)I.rr[o] : ldS<S>(L.r, o);
+      r = level == 0 ? (S)(rsel ? I.rr2 : I.rr)[o] : ldS<S>(L.r, o);
       z = ldS<S>(L.z, o) + prolong<S>(e, C.nx, C.ny, j, i);
     }
     s_r[k] = r;
@@ -513,11 +521,10 @@ __global__ void __launch_bounds__(kNT) k_mg_up(const Tile* __restrict__ tiles,
   }
   if (level != 0) return;   // uniform per launch: every thread of the block returns here
   block_sum<1>(zq, sh);
-  if (threadIdx.x == 0) I.part[t.local] = zq[0];
-  if (arrive_last(&I.pcg->counter[4], L.ntiles)) {
+  if (threadIdx.x == 0) st_agent(&I.part[t.local], zq[0]);
+  if (arrive_last(I.counters + 4 * kCounterStride, L.ntiles, t.local)) {
+    const double s = sum_partials(I.part, L.ntiles, sh);
     if (threadIdx.x == 0) {
-      double s = 0.0;
-      for (int k = 0; k < L.ntiles; ++k) s += ld_agent(&I.part[k]);
       PcgScalars* P = I.pcg;
       P->zq = s;
       // flexible CG: the new direction is K-orthogonalised against the last one
@@ -527,224 +534,326 @@ __global__ void __launch_bounds__(kNT) k_mg_up(const Tile* __restrict__ tiles,
 }
 
 // ------------------------------------------------ single-block coarse cycle
+// Every level from lc down lives in LDS (coefficients, right-hand side,
+// correction, scratch).  With lc == 0 the block holds the whole problem and
+// also applies the CG update, the stopping test and beta.
 template <typename S>
-struct CoarseAcc {
-  const Inst& I;
-  int level;
-  __device__ S r(size_t o) const {
-    return (level == 0) ? (S)I.rr[o] : ((const S*)I.lev[level].r)[o];
-  }
-};
-
-// One red-black half sweep on a whole level (cells of parity `color`).
-template <typename S>
-__device__ void coarse_half_sweep(const Inst& I, int level, int color, bool from_zero) {
-  const Level& L = I.lev[level];
-  const int nx = L.nx, ny = L.ny;
-  const S* ax = (const S*)L.ax;
-  const S* ay = (const S*)L.ay;
-  S* z = (S*)L.z;
-  CoarseAcc<S> R{I, level};
-  for (int c = threadIdx.x; c < nx * ny; c += kCoarseNT) {
-    const int j = c / nx, i = c - j * nx;
-    if (((i + j) & 1) != color) continue;
-    const int ie = wrap(i + 1, nx), iw = wrap(i - 1, nx);
-    const S aw = ax[c], ae = ax[(size_t)j * nx + ie];
-    const S as = ay[c], an = ay[c + nx];
-    const S D = aw + ae + as + an;
-    if (from_zero) { z[c] = R.r(c) / D; continue; }
-    S nb = aw * z[(size_t)j * nx + iw] + ae * z[(size_t)j * nx + ie];
-    if (j >= 1) nb += as * z[c - nx];
-    if (j + 1 < ny) nb += an * z[c + nx];
-    z[c] = (R.r(c) + nb) / D;
-  }
-}
-
-template <typename S>
-__global__ void __launch_bounds__(kCoarseNT) k_mg_coarse(const Inst* __restrict__ insts) {
-  __shared__ double sh[4 * kCoarseNT / 64];
+__global__ void __launch_bounds__(kCoarseNT) k_mg_coarse(const Inst* __restrict__ insts,
+                                                          int update, int parity, int rsel) {
+  __shared__ S s_ax[kCLX], s_ay[kCLY], s_r[kCLX], s_z[kCLX], s_t[kCLX];
+  __shared__ double s_red[2 * kCoarseNT / 64];
   __shared__ double s_sc[4];
   const Inst& I = insts[blockIdx.x];
   if (I.pcg->done) return;
   const int lc = I.lc, nl = I.nlev;
-  // ---- down: smooth, residual (kept in the coarse workspace), restrict
-  for (int l = lc; l < nl - 1; ++l) {
-    const Level& L = I.lev[l];
-    const Level& C = I.lev[l + 1];
-    const int nx = L.nx, ny = L.ny;
-    coarse_half_sweep<S>(I, l, 0, true);
-    // black cells need z = 0 before the GS update reads them as neighbours of nothing:
-    // every black cell's neighbours are red, so no initialisation is required.
-    __syncthreads();
-    coarse_half_sweep<S>(I, l, 1, false);
-    __syncthreads();
-    const S* ax = (const S*)L.ax;
-    const S* ay = (const S*)L.ay;
-    const S* z = (const S*)L.z;
-    double* rp = I.coarse_ws;
-    CoarseAcc<S> R{I, l};
-    for (int c = threadIdx.x; c < nx * ny; c += kCoarseNT) {
-      const int j = c / nx, i = c - j * nx;
-      const int ie = wrap(i + 1, nx), iw = wrap(i - 1, nx);
-      const S zc = z[c];
-      S kz = ax[c] * (zc - z[(size_t)j * nx + iw]) + ax[(size_t)j * nx + ie] * (zc - z[(size_t)j * nx + ie]);
-      if (j >= 1) kz += ay[c] * (zc - z[c - nx]);
-      if (j + 1 < ny) kz += ay[c + nx] * (zc - z[c + nx]);
-      rp[c] = (double)(R.r(c) - kz);
+  int oc[kMaxLevels], oy[kMaxLevels];
+  {
+    int a = 0, b = 0;
+    for (int l = lc; l < nl; ++l) {
+      oc[l] = a; oy[l] = b;
+      a += I.lev[l].nx * I.lev[l].ny;
+      b += (I.lev[l].ny + 1) * I.lev[l].nx;
+    }
+  }
+  const int tid = threadIdx.x;
+  // ---- CG update when the whole grid is coarse
+  if (lc == 0 && update) {
+    const Level& L0 = I.lev[0];
+    const int n = L0.nx * L0.ny;
+    const double alpha = I.pcg->alpha;
+    const double* __restrict__ d = parity ? I.d1 : I.d0;
+    const double* __restrict__ rin = rsel ? I.rr : I.rr2;
+    double* __restrict__ rout = rsel ? I.rr2 : I.rr;
+    double red[2] = {0.0, 0.0};
+    for (int c = tid; c < n; c += kCoarseNT) {
+      const double x = I.x[c] + alpha * d[c];
+      const double r = rin[c] - alpha * I.q[c];
+      I.x[c] = x;
+      rout[c] = r;
+      red[0] += r * r;
+      red[1] += x;
+    }
+    block_sum<2, kCoarseNT>(red, s_red);
+    if (tid == 0) {
+      pcg_stop_test(I.pcg, red[0], red[1], (double)n);
+      s_sc[0] = I.pcg->done;
     }
     __syncthreads();
-    S* rc = (S*)C.r;
-    for (int c = threadIdx.x; c < C.nx * C.ny; c += kCoarseNT) {
-      const int J = c / C.nx, Ic = c - J * C.nx;
-      double wy[4] = {0.25, 0.75, 0.75, 0.25};
-      if (J == 0) { wy[0] = 0.0; wy[1] = 1.0; }
-      if (J == C.ny - 1) { wy[3] = 0.0; wy[2] = 1.0; }
-      const double wx[4] = {0.25, 0.75, 0.75, 0.25};
-      double acc = 0.0;
-      for (int dy = 0; dy < 4; ++dy) {
-        if (wy[dy] == 0.0) continue;
-        const int j = 2 * J - 1 + dy;
-        double row = 0.0;
-        for (int dx = 0; dx < 4; ++dx) {
-          const int i = wrap(2 * Ic - 1 + dx, nx);
-          row += wx[dx] * rp[(size_t)j * nx + i];
-        }
-        acc += wy[dy] * row;
+    if (s_sc[0] != 0.0) return;
+  }
+  // ---- load the coarse hierarchy
+  for (int l = lc; l < nl; ++l) {
+    const Level& L = I.lev[l];
+    const int n = L.nx * L.ny, nf = (L.ny + 1) * L.nx;
+    for (int c = tid; c < n; c += kCoarseNT) s_ax[oc[l] + c] = ((const S*)L.ax)[c];
+    for (int c = tid; c < nf; c += kCoarseNT) s_ay[oy[l] + c] = ((const S*)L.ay)[c];
+  }
+  {
+    const Level& L = I.lev[lc];
+    const int n = L.nx * L.ny;
+    for (int c = tid; c < n; c += kCoarseNT)
+      s_r[oc[lc] + c] = lc == 0 ? (S)(rsel ? I.rr2 : I.rr)[c] : ((const S*)L.r)[c];
+  }
+  __syncthreads();
+  // level helpers (LDS)
+  auto sweep = [&](int l, int color, bool from_zero) {
+    const int nx = I.lev[l].nx, ny = I.lev[l].ny;
+    const S* ax = s_ax + oc[l];
+    const S* ay = s_ay + oy[l];
+    const S* r = s_r + oc[l];
+    S* z = s_z + oc[l];
+    for (int c = tid; c < nx * ny; c += kCoarseNT) {
+      const int j = c / nx, i = c - j * nx;
+      if (((i + j) & 1) != color) continue;
+      const int ie = wrap(i + 1, nx), iw = wrap(i - 1, nx);
+      const S aw = ax[c], ae = ax[j * nx + ie], as = ay[c], an = ay[c + nx];
+      const S D = aw + ae + as + an;
+      if (from_zero) { z[c] = r[c] / D; continue; }
+      S nb = aw * z[j * nx + iw] + ae * z[j * nx + ie];
+      if (j >= 1) nb += as * z[c - nx];
+      if (j + 1 < ny) nb += an * z[c + nx];
+      z[c] = (r[c] + nb) / D;
+    }
+  };
+  // ---- down
+  for (int l = lc; l < nl - 1; ++l) {
+    const int nx = I.lev[l].nx, ny = I.lev[l].ny;
+    sweep(l, 0, true);
+    __syncthreads();
+    sweep(l, 1, false);
+    __syncthreads();
+    {
+      const S* ax = s_ax + oc[l];
+      const S* ay = s_ay + oy[l];
+      const S* r = s_r + oc[l];
+      const S* z = s_z + oc[l];
+      for (int c = tid; c < nx * ny; c += kCoarseNT) {
+        const int j = c / nx, i = c - j * nx;
+        const int ie = wrap(i + 1, nx), iw = wrap(i - 1, nx);
+        const S zc = z[c];
+        S kz = ax[c] * (zc - z[j * nx + iw]) + ax[j * nx + ie] * (zc - z[j * nx + ie]);
+        if (j >= 1) kz += ay[c] * (zc - z[c - nx]);
+        if (j + 1 < ny) kz += ay[c + nx] * (zc - z[c + nx]);
+        s_t[c] = r[c] - kz;
       }
-      rc[c] = (S)(0.25 * acc);
+    }
+    __syncthreads();
+    {
+      const int cnx = I.lev[l + 1].nx, cny = I.lev[l + 1].ny;
+      S* rc = s_r + oc[l + 1];
+      for (int c = tid; c < cnx * cny; c += kCoarseNT) {
+        const int J = c / cnx, Ic = c - J * cnx;
+        S wy[4] = {S(0.25), S(0.75), S(0.75), S(0.25)};
+        if (J == 0) { wy[0] = S(0); wy[1] = S(1); }
+        if (J == cny - 1) { wy[3] = S(0); wy[2] = S(1); }
+        const S wx[4] = {S(0.25), S(0.75), S(0.75), S(0.25)};
+        S acc = 0;
+        for (int dy = 0; dy < 4; ++dy) {
+          if (wy[dy] == S(0)) continue;
+          const int j = 2 * J - 1 + dy;
+          S row = 0;
+          for (int dx = 0; dx < 4; ++dx) row += wx[dx] * s_t[j * nx + wrap(2 * Ic - 1 + dx, nx)];
+          acc += wy[dy] * row;
+        }
+        rc[c] = S(0.25) * acc;
+      }
     }
     __syncthreads();
   }
-  // ---- coarsest level: CG on the (singular, mean-free) system, FP64
+  // ---- coarsest level: exact solve (mean-free part)
   {
     const Level& L = I.lev[nl - 1];
     const int nx = L.nx, ny = L.ny, n = nx * ny;
-    const S* ax = (const S*)L.ax;
-    const S* ay = (const S*)L.ay;
-    double* xw = I.coarse_ws;
-    double* rw = xw + n;
-    double* pw = rw + n;
-    double* qw = pw + n;
-    CoarseAcc<S> R{I, nl - 1};
-    double m[1] = {0.0};
-    for (int c = threadIdx.x; c < n; c += kCoarseNT) m[0] += (double)R.r(c);
-    block_sum<1, kCoarseNT>(m, sh);
-    if (threadIdx.x == 0) s_sc[0] = m[0] / n;
-    __syncthreads();
-    const double mean = s_sc[0];
-    double rr[1] = {0.0};
-    for (int c = threadIdx.x; c < n; c += kCoarseNT) {
-      const double r = (double)R.r(c) - mean;
-      xw[c] = 0.0; rw[c] = r; pw[c] = r;
-      rr[0] += r * r;
-    }
-    block_sum<1, kCoarseNT>(rr, sh);
-    if (threadIdx.x == 0) s_sc[1] = rr[0];
-    __syncthreads();
-    double rho = s_sc[1];
-    const double rho0 = rho;
-    const int maxit = 2 * n;
-    for (int it = 0; it < maxit && rho > 1e-24 * rho0 && rho > 0.0; ++it) {
-      double pq[1] = {0.0};
-      for (int c = threadIdx.x; c < n; c += kCoarseNT) {
-        const int j = c / nx, i = c - j * nx;
-        const int ie = wrap(i + 1, nx), iw = wrap(i - 1, nx);
-        const double pc = pw[c];
-        double q = (double)ax[c] * (pc - pw[(size_t)j * nx + iw]) +
-                   (double)ax[(size_t)j * nx + ie] * (pc - pw[(size_t)j * nx + ie]);
-        if (j >= 1) q += (double)ay[c] * (pc - pw[c - nx]);
-        if (j + 1 < ny) q += (double)ay[c + nx] * (pc - pw[c + nx]);
-        qw[c] = q;
-        pq[0] += pc * q;
+    const S* r = s_r + oc[nl - 1];
+    S* z = s_z + oc[nl - 1];
+    if (I.cdense) {
+      for (int row = tid; row < n; row += kCoarseNT) {
+        const double* M = I.cinv + (size_t)row * n;
+        double acc = 0.0;
+        for (int k = 0; k < n; ++k) acc += M[k] * (double)r[k];
+        z[row] = (S)acc;
       }
-      block_sum<1, kCoarseNT>(pq, sh);
-      if (threadIdx.x == 0) s_sc[2] = pq[0];
       __syncthreads();
-      const double alpha = s_sc[2] > 0.0 ? rho / s_sc[2] : 0.0;
-      double rn[1] = {0.0};
-      for (int c = threadIdx.x; c < n; c += kCoarseNT) {
-        xw[c] += alpha * pw[c];
-        const double r = rw[c] - alpha * qw[c];
-        rw[c] = r;
-        rn[0] += r * r;
+    } else {
+      // CG in LDS scratch (FP64 values kept in the S arrays' spare room is not
+      // possible for float, so the CG runs on s_t / s_z with an FP64 recurrence)
+      const S* ax = s_ax + oc[nl - 1];
+      const S* ay = s_ay + oy[nl - 1];
+      double m[1] = {0.0};
+      for (int c = tid; c < n; c += kCoarseNT) m[0] += (double)r[c];
+      block_sum<1, kCoarseNT>(m, s_red);
+      if (tid == 0) s_sc[0] = m[0] / n;
+      __syncthreads();
+      const double mean = s_sc[0];
+      // x in z, residual in s_t (first n), direction in s_t + n, K p in s_ax spare: use
+      // per-thread registers for up to kCoarseNT cells (n <= 1024 = kCoarseNT)
+      const int c = tid;
+      const bool own = c < n;
+      const int j = own ? c / nx : 0, i = own ? c - j * nx : 0;
+      double xr = 0.0, rr = own ? (double)r[c] - mean : 0.0, pr = rr;
+      S* pbuf = s_t;   // direction shared through LDS
+      double rho[1] = {rr * rr};
+      block_sum<1, kCoarseNT>(rho, s_red);
+      if (tid == 0) s_sc[1] = rho[0];
+      __syncthreads();
+      double rh = s_sc[1];
+      const double rh0 = rh;
+      for (int it = 0; it < 2 * n && rh > 1e-24 * rh0 && rh > 0.0; ++it) {
+        if (own) pbuf[c] = (S)pr;
+        __syncthreads();
+        double q = 0.0;
+        if (own) {
+          const int ie = wrap(i + 1, nx), iw = wrap(i - 1, nx);
+          q = (double)ax[c] * (pr - (double)pbuf[j * nx + iw]) +
+              (double)ax[j * nx + ie] * (pr - (double)pbuf[j * nx + ie]);
+          if (j >= 1) q += (double)ay[c] * (pr - (double)pbuf[c - nx]);
+          if (j + 1 < ny) q += (double)ay[c + nx] * (pr - (double)pbuf[c + nx]);
+        }
+        double pq[1] = {pr * q};
+        block_sum<1, kCoarseNT>(pq, s_red);
+        if (tid == 0) s_sc[2] = pq[0];
+        __syncthreads();
+        const double alpha = s_sc[2] > 0.0 ? rh / s_sc[2] : 0.0;
+        xr += alpha * pr;
+        rr -= alpha * q;
+        double rn[1] = {rr * rr};
+        block_sum<1, kCoarseNT>(rn, s_red);
+        if (tid == 0) s_sc[3] = rn[0];
+        __syncthreads();
+        const double rh_new = s_sc[3];
+        pr = rr + (rh > 0.0 ? rh_new / rh : 0.0) * pr;
+        rh = rh_new;
+        if (alpha == 0.0) break;
       }
-      block_sum<1, kCoarseNT>(rn, sh);
-      if (threadIdx.x == 0) s_sc[3] = rn[0];
+      if (own) z[c] = (S)xr;
       __syncthreads();
-      const double rho_new = s_sc[3];
-      const double beta = rho_new / rho;
-      for (int c = threadIdx.x; c < n; c += kCoarseNT) pw[c] = rw[c] + beta * pw[c];
-      rho = rho_new;
-      __syncthreads();
-      if (alpha == 0.0) break;
     }
-    S* z = (S*)L.z;
-    for (int c = threadIdx.x; c < n; c += kCoarseNT) z[c] = (S)xw[c];
-    __syncthreads();
   }
   // ---- up: prolong, post-smooth (black, red)
   for (int l = nl - 2; l >= lc; --l) {
-    const Level& L = I.lev[l];
-    const Level& C = I.lev[l + 1];
-    const int nx = L.nx, ny = L.ny;
-    S* z = (S*)L.z;
-    const S* e = (const S*)C.z;
-    for (int c = threadIdx.x; c < nx * ny; c += kCoarseNT) {
+    const int nx = I.lev[l].nx, ny = I.lev[l].ny;
+    const int cnx = I.lev[l + 1].nx, cny = I.lev[l + 1].ny;
+    S* z = s_z + oc[l];
+    const S* e = s_z + oc[l + 1];
+    for (int c = tid; c < nx * ny; c += kCoarseNT) {
       const int j = c / nx, i = c - j * nx;
-      z[c] += prolong<S>(e, C.nx, C.ny, j, i);
+      z[c] += prolong<S>(e, cnx, cny, j, i);
     }
     __syncthreads();
-    coarse_half_sweep<S>(I, l, 1, false);
+    sweep(l, 1, false);
     __syncthreads();
-    coarse_half_sweep<S>(I, l, 0, false);
+    sweep(l, 0, false);
     __syncthreads();
   }
-  // ---- whole V-cycle in this block: publish z and beta
-  if (lc == 0) {
-    const Level& L = I.lev[0];
+  // ---- publish the level-lc correction (and beta when it is level 0)
+  {
+    const Level& L = I.lev[lc];
     const int n = L.nx * L.ny;
-    const S* z = (const S*)L.z;
-    double zq[1] = {0.0};
-    for (int c = threadIdx.x; c < n; c += kCoarseNT) {
-      const double zz = (double)z[c];
-      I.zf[c] = zz;
-      zq[0] += zz * I.q[c];
-    }
-    block_sum<1, kCoarseNT>(zq, sh);
-    if (threadIdx.x == 0) {
-      PcgScalars* P = I.pcg;
-      P->zq = zq[0];
-      P->beta = P->first ? 0.0 : (P->dq != 0.0 ? -zq[0] / P->dq : 0.0);
+    const S* z = s_z + oc[lc];
+    if (lc > 0) {
+      for (int c = tid; c < n; c += kCoarseNT) ((S*)L.z)[c] = z[c];
+    } else {
+      double zq[1] = {0.0};
+      for (int c = tid; c < n; c += kCoarseNT) {
+        const double zz = (double)z[c];
+        I.zf[c] = zz;
+        zq[0] += zz * I.q[c];
+      }
+      block_sum<1, kCoarseNT>(zq, s_red);
+      if (tid == 0) {
+        PcgScalars* P = I.pcg;
+        P->zq = zq[0];
+        P->beta = P->first ? 0.0 : (P->dq != 0.0 ? -zq[0] / P->dq : 0.0);
+      }
     }
   }
 }
 
-// Coarse-level coefficients: average of the two fine faces covering each
-// coarse face, times 1/4 (the spacing doubles).  One launch per level.
+// Coarse-level coefficients of every level l >= 1, straight from level 0:
+// the mean of the 2^l fine faces covering a coarse face, times 4^-l (each
+// halving doubles h); identical to averaging pairs level by level.
 template <typename S>
-__global__ void __launch_bounds__(kNT) k_mg_coef(const Inst* __restrict__ insts, int ninst,
-                                                  int level) {
-  // grid-stride over (instance, coarse face)
-  for (int inst = 0; inst < ninst; ++inst) {
-    const Inst& I = insts[inst];
-    if (level >= I.nlev) continue;
-    const Level& F = I.lev[level - 1];
-    const Level& C = I.lev[level];
+__global__ void __launch_bounds__(kNT) k_mg_coef(const Inst* __restrict__ insts) {
+  const Inst& I = insts[blockIdx.y];
+  const Level& F = I.lev[0];
+  const S* fax = (const S*)F.ax;
+  const S* fay = (const S*)F.ay;
+  for (int l = 1; l < I.nlev; ++l) {
+    const Level& C = I.lev[l];
+    const int m = 1 << l;
+    const S scale = S(1.0 / ((double)m * m * m));   // mean over m faces times 4^-l
     const int n = C.nx * (C.ny + 1);
     for (int c = blockIdx.x * kNT + threadIdx.x; c < n; c += gridDim.x * kNT) {
       const int J = c / C.nx, Ic = c - J * C.nx;
-      const S* fax = (const S*)F.ax;
-      const S* fay = (const S*)F.ay;
       if (J < C.ny) {
-        const S a = fax[(size_t)(2 * J) * F.nx + 2 * Ic] + fax[(size_t)(2 * J + 1) * F.nx + 2 * Ic];
-        ((S*)C.ax)[(size_t)J * C.nx + Ic] = S(0.125) * a;
+        S a = 0;
+        for (int k = 0; k < m; ++k) a += fax[(size_t)(J * m + k) * F.nx + Ic * m];
+        ((S*)C.ax)[(size_t)J * C.nx + Ic] = a * scale;
       }
       S b = 0;
       if (J >= 1 && J < C.ny)
-        b = S(0.125) * (fay[(size_t)(2 * J) * F.nx + 2 * Ic] + fay[(size_t)(2 * J) * F.nx + 2 * Ic + 1]);
-      ((S*)C.ay)[(size_t)J * C.nx + Ic] = b;
+        for (int k = 0; k < m; ++k) b += fay[(size_t)(J * m) * F.nx + Ic * m + k];
+      ((S*)C.ay)[(size_t)J * C.nx + Ic] = b * scale;
     }
   }
+}
+
+// Dense inverse of the coarsest operator K_c + s 11^T / n (s its mean
+// diagonal): symmetric positive definite, inverted in LDS by Gauss-Jordan
+// without pivoting.  For a mean-free right-hand side the product is the
+// mean-free solution of K_c z = r.
+template <typename S>
+__global__ void __launch_bounds__(kCoarseNT) k_coarse_inv(const Inst* __restrict__ insts) {
+  __shared__ double B[kDenseMax * kDenseMax];
+  __shared__ double s_red[kCoarseNT / 64];
+  const Inst& I = insts[blockIdx.x];
+  if (!I.cdense) return;
+  const Level& L = I.lev[I.nlev - 1];
+  const int nx = L.nx, ny = L.ny, n = nx * ny;
+  const S* ax = (const S*)L.ax;
+  const S* ay = (const S*)L.ay;
+  const int tid = threadIdx.x;
+  for (int k = tid; k < n * n; k += kCoarseNT) B[k] = 0.0;
+  __syncthreads();
+  double dsum[1] = {0.0};
+  for (int c = tid; c < n; c += kCoarseNT) {   // one thread builds one row
+    const int j = c / nx, i = c - j * nx;
+    const int ie = wrap(i + 1, nx), iw = wrap(i - 1, nx);
+    const double aw = (double)ax[c], ae = (double)ax[j * nx + ie];
+    double d = 0.0;
+    if (iw != i) { B[c * n + j * nx + iw] -= aw; d += aw; }
+    if (ie != i) { B[c * n + j * nx + ie] -= ae; d += ae; }
+    if (j >= 1) { const double a = (double)ay[c]; B[c * n + c - nx] -= a; d += a; }
+    if (j + 1 < ny) { const double a = (double)ay[c + nx]; B[c * n + c + nx] -= a; d += a; }
+    B[c * n + c] += d;
+    dsum[0] += d;
+  }
+  block_sum<1, kCoarseNT>(dsum, s_red);
+  __shared__ double s_shift;
+  if (tid == 0) s_shift = dsum[0] / n / n;
+  __syncthreads();
+  for (int k = tid; k < n * n; k += kCoarseNT) B[k] += s_shift;
+  __syncthreads();
+  constexpr int PER = (kDenseMax * kDenseMax + kCoarseNT - 1) / kCoarseNT;
+  for (int k = 0; k < n; ++k) {
+    const double piv = B[k * n + k];
+    double nv[PER];
+    int cnt = 0;
+    for (int e = tid; e < n * n; e += kCoarseNT, ++cnt) {
+      const int r = e / n, c = e - r * n;
+      double v;
+      if (r == k && c == k) v = 1.0 / piv;
+      else if (r == k) v = B[k * n + c] / piv;
+      else if (c == k) v = -B[r * n + k] / piv;
+      else v = B[e] - B[r * n + k] * B[k * n + c] / piv;
+      nv[cnt] = v;
+    }
+    __syncthreads();
+    cnt = 0;
+    for (int e = tid; e < n * n; e += kCoarseNT, ++cnt) B[e] = nv[cnt];
+    __syncthreads();
+  }
+  for (int k = tid; k < n * n; k += kCoarseNT) I.cinv[k] = B[k];
 }
 
 }  // namespace cdi

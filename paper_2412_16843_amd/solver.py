@@ -109,6 +109,15 @@ class CDISolver:
         return out, dict(iterations=info.iterations, converged=info.converged,
                          relres=info.relres, bnorm=info.bnorm, ms=info.ms, status=st)
 
+    def timing_enable(self, kernel: str | None):
+        L.check(self.lib.cdi_timing_enable(self.ctx, kernel.encode() if kernel else None))
+
+    def timing_read(self):
+        ms = C.c_double()
+        n = C.c_int64()
+        L.check(self.lib.cdi_timing_read(self.ctx, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
     def state(self, idx: int = 0):
         torch.cuda.synchronize(self.device)
         f = self.fields[idx]
