@@ -145,32 +145,39 @@ __device__ __forceinline__ void st_agent(double* p, double v) {
 
 // Last-block-done: every block of an instance publishes its partial (thread 0,
 // st_agent), then counts itself in once that store has completed; the last
-// one to arrive reads all partials with ld_agent.  Arrivals are
-// spread over kSubCounters counters (block `local` uses counter local % k)
-// whose last arrivals count into counter 0, so no single address takes more
-// than ~nblocks/kSubCounters + kSubCounters serialised atomics.
+// one to arrive reads all partials with ld_agent.  Arrivals are spread over
+// g = ceil(sqrt(nblocks)) (at most kSubCounters) counters -- block `local`
+// uses counter local % g -- whose last arrivals count into counter 0, so no
+// single address takes more than ~2 sqrt(nblocks) serialised atomics.
 constexpr int kSubCounters = 64;
 constexpr int kCounterStride = kSubCounters + 1;   // counters per reduction kind
+
+__device__ __forceinline__ int arrival_groups(int nblocks) {
+  int g = 1;
+  while (g * g < nblocks && g < kSubCounters) ++g;
+  return g;
+}
 
 __device__ __forceinline__ bool arrive_last(unsigned* counters, int nblocks, int local) {
   __shared__ int s_last;
   __syncthreads();
   if (threadIdx.x == 0) {
     __builtin_amdgcn_s_waitcnt(0);   // the partial store is complete (acknowledged)
+    const int g = arrival_groups(nblocks);
     bool last;
-    if (nblocks <= 2 * kSubCounters) {
+    if (g == 1) {
       const unsigned prev = atomicAdd(&counters[0], 1u);
       last = prev == (unsigned)(nblocks - 1);
       if (last) atomicExch(&counters[0], 0u);
     } else {
-      const int sub = local % kSubCounters;
-      const int members = (nblocks - sub + kSubCounters - 1) / kSubCounters;
+      const int sub = local % g;
+      const int members = (nblocks - sub + g - 1) / g;
       const unsigned prev = atomicAdd(&counters[1 + sub], 1u);
       last = false;
       if (prev == (unsigned)(members - 1)) {
         atomicExch(&counters[1 + sub], 0u);
         const unsigned top = atomicAdd(&counters[0], 1u);
-        last = top == (unsigned)(kSubCounters - 1);
+        last = top == (unsigned)(g - 1);
         if (last) atomicExch(&counters[0], 0u);
       }
     }
