@@ -197,6 +197,62 @@ cdi_status cdi_timing_enable(cdi_ctx* ctx, const char* kernel);
  * cdi_timing_enable.  Synchronises the stream. */
 cdi_status cdi_timing_read(cdi_ctx* ctx, double* total_ms, int64_t* launches);
 
+/* ------------------------------------------------------------------------
+ * Learned pressure guess.  A small encoder-decoder network (4 levels,
+ * 32/64/128/256 channels, 3x3 convolutions, BF16 matrix cores with FP32
+ * accumulation) maps the features (phi, rho/max(rho1,rho2), b_hat) of a
+ * projection to a normalised pressure; its output is only the initial guess
+ * of the flexible CG, which still iterates to poisson_rtol.
+ *   b_hat = (b - mean b) / rms(b - mean b),
+ *   p     = s * y * rms(b - mean b) * max(rho1, rho2) * h^2,
+ * with s the Galerkin factor (f, p)/(p, K p) fitted on the device, so that
+ * the guess is never worse than zero in the energy norm of the operator.
+ * Parameters are FP32 in a fixed order (per 3x3 layer e0, e1, e2, e3, d2,
+ * d1, d0: weights [co][ci][3][3] then biases [co]; then the 1x1 output layer
+ * weights [32] and bias [1]), owned by the caller. */
+typedef struct cdi_net cdi_net;
+
+/* Number of FP32 parameters. */
+size_t cdi_net_param_count(void);
+
+/* Device workspace bytes of a network for `batch` images of h x w cells
+ * (h, w multiples of 8); train != 0 adds the gradient buffers. */
+size_t cdi_net_workspace_bytes(int32_t batch, int32_t h, int32_t w, int32_t train);
+
+/* Create a network over caller-owned params (and grads when train != 0),
+ * workspace and stream.  Packs the BF16 weights. */
+cdi_status cdi_net_init(const float* params, float* grads, int32_t batch, int32_t h, int32_t w,
+                        int32_t train, void* workspace, size_t workspace_bytes, void* hip_stream,
+                        cdi_net** out);
+
+/* Re-pack the BF16 weights after the caller changed params. */
+cdi_status cdi_net_repack(cdi_net* net);
+
+/* x: FP32 [batch][3][h][w] features; y: FP32 [batch][h][w] output. */
+cdi_status cdi_net_forward(cdi_net* net, const float* x, float* y);
+
+/* Mean-squared-error gradients of the last forward pass against target
+ * (FP32 [batch][h][w]) into grads; loss (device FP32 scalar) may be NULL. */
+cdi_status cdi_net_backward(cdi_net* net, const float* target, float* loss);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8; step counts from 1) on
+ * params with caller-owned FP32 moments m, v (zero-initialised). */
+cdi_status cdi_net_adam(cdi_net* net, float* m, float* v, int32_t step, double lr);
+
+void cdi_net_destroy(cdi_net* net);
+const char* cdi_net_last_error(void);
+
+/* Use `net` (batch 1, h = ny, w = nx of instance 0) for the initial guess of
+ * every pressure solve of a single-instance context created with
+ * guess = CDI_GUESS_LEARNED; NULL detaches (the previous pressure is then
+ * used).  The context borrows the network. */
+cdi_status cdi_guess_attach(cdi_ctx* ctx, cdi_net* net);
+
+/* Features and normalised target of instance idx's last projection (after
+ * cdi_step: the final-stage projection of the last step): features FP32
+ * [3][ny][nx], target FP32 [ny][nx] (may be NULL), both device buffers. */
+cdi_status cdi_guess_features(cdi_ctx* ctx, int32_t idx, float* features, float* target);
+
 /* Release the context (host memory only; caller buffers are untouched). */
 void cdi_destroy(cdi_ctx* ctx);
 

@@ -21,7 +21,10 @@ GUESS = {"zero": 0, "prev": 1, "learned": 2}
 
 EXPORTS = ("cdi_workspace_bytes", "cdi_default_dt", "cdi_init", "cdi_init_batch", "cdi_step",
            "cdi_solve_pressure", "cdi_diagnostics", "cdi_eval_rhs", "cdi_timing_enable",
-           "cdi_timing_read", "cdi_destroy", "cdi_last_error")
+           "cdi_timing_read", "cdi_destroy", "cdi_last_error", "cdi_net_param_count",
+           "cdi_net_workspace_bytes", "cdi_net_init", "cdi_net_repack", "cdi_net_forward",
+           "cdi_net_backward", "cdi_net_adam", "cdi_net_destroy", "cdi_net_last_error",
+           "cdi_guess_attach", "cdi_guess_features")
 
 
 class cdi_params(C.Structure):
@@ -94,6 +97,28 @@ def lib() -> C.CDLL:
     L.cdi_timing_enable.restype = i32
     L.cdi_timing_read.argtypes = [vp, P(f64), P(C.c_int64)]
     L.cdi_timing_read.restype = i32
+    L.cdi_net_param_count.argtypes = []
+    L.cdi_net_param_count.restype = C.c_size_t
+    L.cdi_net_workspace_bytes.argtypes = [i32, i32, i32, i32]
+    L.cdi_net_workspace_bytes.restype = C.c_size_t
+    L.cdi_net_init.argtypes = [vp, vp, i32, i32, i32, i32, vp, C.c_size_t, vp, P(vp)]
+    L.cdi_net_init.restype = i32
+    L.cdi_net_repack.argtypes = [vp]
+    L.cdi_net_repack.restype = i32
+    L.cdi_net_forward.argtypes = [vp, vp, vp]
+    L.cdi_net_forward.restype = i32
+    L.cdi_net_backward.argtypes = [vp, vp, vp]
+    L.cdi_net_backward.restype = i32
+    L.cdi_net_adam.argtypes = [vp, vp, vp, i32, f64]
+    L.cdi_net_adam.restype = i32
+    L.cdi_net_destroy.argtypes = [vp]
+    L.cdi_net_destroy.restype = None
+    L.cdi_net_last_error.argtypes = []
+    L.cdi_net_last_error.restype = C.c_char_p
+    L.cdi_guess_attach.argtypes = [vp, vp]
+    L.cdi_guess_attach.restype = i32
+    L.cdi_guess_features.argtypes = [vp, i32, vp, vp]
+    L.cdi_guess_features.restype = i32
     L.cdi_destroy.argtypes = [vp]
     L.cdi_destroy.restype = None
     L.cdi_last_error.argtypes = []
@@ -105,6 +130,12 @@ def lib() -> C.CDLL:
 def check(status: int, allow=()) -> int:
     if status != 0 and status not in allow:
         raise CDIError(status, lib().cdi_last_error().decode())
+    return status
+
+
+def check_net(status: int) -> int:
+    if status != 0:
+        raise CDIError(status, lib().cdi_net_last_error().decode())
     return status
 
 

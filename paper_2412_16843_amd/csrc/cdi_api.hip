@@ -14,6 +14,7 @@
 
 #include "../../include/cdi.h"
 #include "diag_kernels.h"
+#include "net_internal.h"
 
 using namespace cdi;
 
@@ -84,7 +85,6 @@ cdi_status resolve(const cdi_params* in, Resolved& r) {
   if (p.slip_model < CDI_SLIP_1A || p.slip_model > CDI_SLIP_4B) return fail(CDI_ERR_ARG, "bad slip_model");
   if (p.precision != CDI_FP64 && p.precision != CDI_MIXED) return fail(CDI_ERR_ARG, "bad precision");
   if (p.guess < CDI_GUESS_ZERO || p.guess > CDI_GUESS_LEARNED) return fail(CDI_ERR_ARG, "bad guess");
-  if (p.guess == CDI_GUESS_LEARNED) return fail(CDI_ERR_ARG, "learned guess is not available in this build");
   if (p.poisson_rtol < 0 || p.poisson_maxit < 0 || p.mg_smooth < 0) return fail(CDI_ERR_ARG, "bad solver limits");
   r.p = p;
   r.h = hx;
@@ -292,6 +292,7 @@ struct cdi_ctx {
   double rtol = 1e-10;
   int maxit = 200;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  cdi_net* net = nullptr;        // learned initial guess (borrowed)
   // measurement hook: events around every launch of one kernel family
   std::string timed;
   std::vector<hipEvent_t> tev;
@@ -419,6 +420,27 @@ cdi_status solve_loop(cdi_ctx* c, int guess) {
   return CDI_OK;
 }
 
+// Initial-guess mode of k_pcg_init: 0 zero, 1 previous pressure, 2 fitted
+// network output.
+int guess_mode(const cdi_ctx* c) {
+  if (c->guess == CDI_GUESS_ZERO) return 0;
+  return (c->guess == CDI_GUESS_LEARNED && c->net) ? 2 : 1;
+}
+
+// Network inference for the initial guess of instance 0's next solve (the
+// right-hand side and its statistics come from k_rhs / k_solve_setup).
+void learned_guess(cdi_ctx* c, int src) {
+  const Inst& I = c->B.inst[0];
+  const double* phi = src == 0 ? I.phi : (src == 1 ? I.phi_a : I.phi_b);
+  const unsigned g = (unsigned)std::min(1024, ceil_div(I.nx * I.ny, kNT));
+  timed(c, "net", [&] {
+    k_features<<<g, kNT, 0, c->stream>>>(c->d_inst, 0, phi, nullptr, cdinet::features(c->net), nullptr);
+    cdinet::forward(c->net);
+    k_guess_apply<<<g, kNT, 0, c->stream>>>(c->d_inst, cdinet::output(c->net));
+    k_guess_fit<<<(unsigned)c->B.cell.size(), kNT, 0, c->stream>>>(c->d_cell, c->d_inst);
+  });
+}
+
 template <typename S>
 cdi_status run_step(cdi_ctx* c) {
   Batch& B = c->B;
@@ -436,7 +458,8 @@ cdi_status run_step(cdi_ctx* c) {
     });
     const double tfac = k < 3 ? RK_C[k + 1] : 1.0;
     timed(c, "rhs", [&] { k_rhs<S><<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, dst, tfac, c->rtol, c->maxit); });
-    cdi_status s = solve_loop<S>(c, c->guess == CDI_GUESS_ZERO ? 0 : 1);
+    if (c->guess == CDI_GUESS_LEARNED && c->net) learned_guess(c, dst);
+    cdi_status s = solve_loop<S>(c, guess_mode(c));
     if (s == CDI_ERR_NOCONV) st = s;
     else if (s != CDI_OK) return s;
     timed(c, "project", [&] { k_project<<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, tfac, k == 3, dst); });
@@ -592,7 +615,8 @@ cdi_status cdi_solve_pressure(cdi_ctx* c, const double* b, double* p, cdi_solve_
   else
     k_solve_setup<double><<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, b, c->rtol, c->maxit);
   c->coef_ready = false;
-  const int guess = c->guess == CDI_GUESS_ZERO ? 0 : 1;
+  if (c->guess == CDI_GUESS_LEARNED && c->net) learned_guess(c, 0);
+  const int guess = guess_mode(c);
   cdi_status s = c->mixed ? solve_loop<float>(c, guess) : solve_loop<double>(c, guess);
   c->coef_ready = false;   // coefficients now follow the caller phase field
   k_solve_out<<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, p);
@@ -605,7 +629,9 @@ cdi_status cdi_solve_pressure(cdi_ctx* c, const double* b, double* p, cdi_solve_
     HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
     info->iterations = c->last_iters[0];
     info->converged = c->last_conv[0];
-    info->guess_used = guess ? CDI_GUESS_PREV : CDI_GUESS_ZERO;
+    info->guess_used = guess ? ((c->guess == CDI_GUESS_LEARNED && c->net) ? CDI_GUESS_LEARNED
+                                                                       : CDI_GUESS_PREV)
+                             : CDI_GUESS_ZERO;
     info->relres = c->last_relres[0];
     info->bnorm = c->h_pcg[0].fnorm;
     info->ms = ms;
@@ -686,7 +712,7 @@ cdi_status cdi_timing_enable(cdi_ctx* c, const char* kernel) {
   if (!c) return fail(CDI_ERR_ARG, "ctx is NULL");
   static const char* known[] = {"phase_prep", "stage", "rhs", "pcg_init", "mg_down",
                                 "mg_down_other", "mg_coarse", "mg_up", "mg_up_other", "mg_coef",
-                                "pcg_spmv", "pcg_xmean", "project"};
+                                "pcg_spmv", "pcg_xmean", "project", "net"};
   HIPCHK(hipStreamSynchronize(c->stream));
   c->tev_used = 0;
   c->timed_ms = 0.0;
@@ -708,6 +734,29 @@ cdi_status cdi_timing_read(cdi_ctx* c, double* total_ms, int64_t* launches) {
   HIPCHK(timing_flush(c));
   *total_ms = c->timed_ms;
   *launches = c->timed_launches;
+  return CDI_OK;
+}
+
+cdi_status cdi_guess_attach(cdi_ctx* c, cdi_net* net) {
+  if (!c) return fail(CDI_ERR_ARG, "ctx is NULL");
+  if (!net) { c->net = nullptr; return CDI_OK; }
+  if (c->B.n != 1) return fail(CDI_ERR_STATE, "the learned guess needs a single-instance context");
+  if (c->guess != CDI_GUESS_LEARNED) return fail(CDI_ERR_STATE, "context was not created with CDI_GUESS_LEARNED");
+  const Inst& I = c->B.inst[0];
+  if (cdinet::batch(net) != 1 || cdinet::height(net) != I.ny || cdinet::width(net) != I.nx)
+    return fail(CDI_ERR_SHAPE, "network shape must be batch 1, h = ny, w = nx");
+  if (cdinet::stream_of(net) != c->stream) return fail(CDI_ERR_ARG, "network and context must share the stream");
+  c->net = net;
+  return CDI_OK;
+}
+
+cdi_status cdi_guess_features(cdi_ctx* c, int32_t idx, float* features, float* target) {
+  if (!c || !features) return fail(CDI_ERR_ARG, "NULL argument");
+  if (idx < 0 || idx >= c->B.n) return fail(CDI_ERR_ARG, "instance out of range");
+  const Inst& I = c->B.inst[idx];
+  const unsigned g = (unsigned)std::min(1024, ceil_div(I.nx * I.ny, kNT));
+  k_features<<<g, kNT, 0, c->stream>>>(c->d_inst, idx, I.phi, I.p, features, target);
+  HIPCHK(hipGetLastError());
   return CDI_OK;
 }
 

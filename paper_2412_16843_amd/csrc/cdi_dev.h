@@ -34,7 +34,8 @@ struct PcgScalars {
   double alpha, beta;
   double dr, dq, zq;        // (d, r), (d, q), (z, q)
   double rr, fnorm, relres;
-  double bmean, xmean;
+  double bmean, xmean, brms;
+  double gscale;            // factor applied to the initial guess (1 unless fitted)
   double rtol;
   int done;                 // 1 once converged (or maxit reached): kernels exit early
   int iters;

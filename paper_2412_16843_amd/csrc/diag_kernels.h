@@ -121,13 +121,13 @@ __global__ void __launch_bounds__(kNT) k_solve_setup(const Tile* __restrict__ ti
                                                      const Inst* __restrict__ insts,
                                                      const double* __restrict__ bin, double rtol,
                                                      int maxit) {
-  __shared__ double sh[kNT / 64];
+  __shared__ double sh[2 * kNT / 64];
   const Tile t = tiles[blockIdx.x];
   const Inst& I = insts[t.inst];
   const int nx = I.nx, ny = I.ny;
   const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
   const int i = t.i0 + tx, j = t.j0 + ty;
-  double bs[1] = {0.0};
+  double bs[2] = {0.0, 0.0};
   if (i < nx && j < ny) {
     const size_t o = (size_t)j * nx + i;
     const double r1 = I.rho1, r2 = I.rho2;
@@ -146,14 +146,21 @@ __global__ void __launch_bounds__(kNT) k_solve_setup(const Tile* __restrict__ ti
     const double b = bin ? bin[o] : I.b[o];
     I.b[o] = b;
     bs[0] = b;
+    bs[1] = b * b;
   }
-  block_sum<1>(bs, sh);
-  if (threadIdx.x == 0) st_agent(&I.part[t.local], bs[0]);
+  block_sum<2>(bs, sh);
+  if (threadIdx.x == 0) {
+    st_agent(&I.part[t.local], bs[0]);
+    st_agent(&I.part[I.ntiles + t.local], bs[1]);
+  }
   if (arrive_last(I.counters + 0 * kCounterStride, I.ntiles, t.local)) {
     const double s = sum_partials(I.part, I.ntiles, sh);
+    const double s2 = sum_partials(I.part + I.ntiles, I.ntiles, sh);
     if (threadIdx.x == 0) {
       PcgScalars* P = I.pcg;
-      P->bmean = s / ((double)nx * ny);
+      const double n = (double)nx * ny;
+      P->bmean = s / n;
+      P->brms = sqrt(fmax(s2 / n - P->bmean * P->bmean, 0.0));
       P->done = 0; P->iters = 0; P->first = 1; P->converged = 0; P->pad = 0;
       P->rtol = rtol; P->maxit = maxit;
     }
@@ -172,6 +179,40 @@ __global__ void __launch_bounds__(kNT) k_solve_out(const Tile* __restrict__ tile
   const size_t o = (size_t)j * nx + i;
   const bool zero = I.pcg->pad != 0;
   pout[o] = zero ? 0.0 : I.x[o] - I.pcg->xmean;
+}
+
+// Learned-guess features of one instance's projection: phi, rho/rho_max and
+// (b - mean b)/rms (0 where rms = 0), FP32 [3][ny][nx]; optionally the
+// normalised target p / (rms rho_max h^2) from the pressure p (the right-hand
+// sides of the projections vary on the grid scale, so h^2 sets the scale).
+__global__ void __launch_bounds__(kNT) k_features(const Inst* __restrict__ insts, int idx,
+                                                  const double* __restrict__ phi,
+                                                  const double* __restrict__ p,
+                                                  float* __restrict__ feat,
+                                                  float* __restrict__ target) {
+  const Inst& I = insts[idx];
+  const size_t n = (size_t)I.nx * I.ny;
+  const double rmax = fmax(I.rho1, I.rho2);
+  const double mean = I.pcg->bmean, rms = I.pcg->brms;
+  const double pscale = rms * rmax * I.h * I.h;
+  for (size_t c = blockIdx.x * (size_t)kNT + threadIdx.x; c < n; c += (size_t)gridDim.x * kNT) {
+    const double ph = phi[c];
+    feat[c] = (float)ph;
+    feat[n + c] = (float)(((I.rho1 - I.rho2) * ph + I.rho2) / rmax);
+    feat[2 * n + c] = rms > 0.0 ? (float)((I.b[c] - mean) / rms) : 0.f;
+    if (target) target[c] = pscale > 0.0 ? (float)(p[c] / pscale) : 0.f;
+  }
+}
+
+// Pressure guess from the network output: p = y rms rho_max h^2 (then fitted
+// by k_guess_fit).
+__global__ void __launch_bounds__(kNT) k_guess_apply(const Inst* __restrict__ insts,
+                                                     const float* __restrict__ y) {
+  const Inst& I = insts[0];
+  const size_t n = (size_t)I.nx * I.ny;
+  const double pscale = I.pcg->brms * fmax(I.rho1, I.rho2) * I.h * I.h;
+  for (size_t c = blockIdx.x * (size_t)kNT + threadIdx.x; c < n; c += (size_t)gridDim.x * kNT)
+    I.p[c] = (double)y[c] * pscale;
 }
 
 }  // namespace cdi

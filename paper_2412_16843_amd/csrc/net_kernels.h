@@ -1,0 +1,392 @@
+// Learned pressure guess: encoder-decoder network (4 levels, 32/64/128/256
+// channels, 3x3 convolutions) trained and evaluated with BF16 matrix cores
+// (v_mfma_f32_16x16x32_bf16, FP32 accumulation).  Its output is only the
+// initial guess of the pressure solve.
+//
+// Tensors are [batch][channel][row][column] (column fastest).  Activations
+// and activation gradients are BF16; parameters, their gradients and the
+// Adam moments are FP32 (master copy); the convolution weights are repacked
+// to BF16 [co][tap][ci] for the matrix cores.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cdinet {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int NT = 256;          // 4 waves
+constexpr int TCO = 64;          // output-channel tile (16 per wave)
+constexpr int TPX = 64;          // pixel tile along a row (4 MFMA column blocks)
+constexpr int KC = 32;           // input channels per MFMA step
+
+__device__ __forceinline__ float bf2f(__bf16 v) { return (float)v; }
+__device__ __forceinline__ __bf16 f2bf(float v) { return (__bf16)v; }
+
+// ------------------------------------------------------------------ conv 3x3
+// y[b,o,i,j] = act(bias[o] + sum_{c,ky,kx} w[o,ky*3+kx,c] x[b,c,i+ky-1,j+kx-1])
+// as an implicit GEMM: M = output channels, N = pixels of one row segment,
+// K = 32 input channels per step, 9 taps.  Zero padding outside the image.
+// Wave w owns output channels [16w, 16w+16) of the tile and 4 blocks of 16
+// pixels.  ci must be a multiple of 32.  relu: 0 none, 1 relu.
+// Output either BF16 (yb) or FP32 (yf), whichever is non-null.
+__global__ void __launch_bounds__(NT) k_conv3_fwd(const __bf16* __restrict__ x,
+                                                  const __bf16* __restrict__ wp,
+                                                  const float* __restrict__ bias,
+                                                  __bf16* __restrict__ yb, float* __restrict__ yf,
+                                                  int B, int ci, int co, int H, int W, int relu) {
+  __shared__ __attribute__((aligned(16))) __bf16 s_x[3 * (TPX + 2) * KC];   // [row][px][c]
+  __shared__ __attribute__((aligned(16))) __bf16 s_w[TCO * 9 * KC];         // [o][tap][c]
+  const int nxt = (W + TPX - 1) / TPX;
+  int blk = blockIdx.x;
+  const int xt = blk % nxt; blk /= nxt;
+  const int row = blk % H; blk /= H;
+  const int b = blk;
+  const int co0 = blockIdx.y * TCO;
+  const int x0 = xt * TPX;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  f32x4 acc[4];
+#pragma unroll
+  for (int n = 0; n < 4; ++n) acc[n] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const size_t plane = (size_t)H * W;
+  for (int c0 = 0; c0 < ci; c0 += KC) {
+    // stage the input patch: rows row-1..row+1, columns x0-1..x0+TPX
+    for (int e = tid; e < KC * 3 * (TPX + 2); e += NT) {
+      const int px = e % (TPX + 2);
+      const int r = (e / (TPX + 2)) % 3;
+      const int c = e / (3 * (TPX + 2));
+      const int yy = row + r - 1, xx = x0 + px - 1;
+      __bf16 v = f2bf(0.f);
+      if (yy >= 0 && yy < H && xx >= 0 && xx < W) v = x[((size_t)b * ci + c0 + c) * plane + (size_t)yy * W + xx];
+      s_x[(r * (TPX + 2) + px) * KC + c] = v;
+    }
+    // stage the weights of the tile
+    for (int e = tid; e < TCO * 9 * KC; e += NT) {
+      const int c = e % KC;
+      const int t = (e / KC) % 9;
+      const int o = e / (9 * KC);
+      __bf16 v = f2bf(0.f);
+      if (co0 + o < co) v = wp[((size_t)(co0 + o) * 9 + t) * ci + c0 + c];
+      s_w[e] = v;
+    }
+    __syncthreads();
+    const int kq = 8 * (lane >> 4);
+    const int li = lane & 15;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      const int ky = t / 3, kx = t - 3 * ky;
+      const bf16x8 a = *(const bf16x8*)&s_w[((16 * wv + li) * 9 + t) * KC + kq];
+#pragma unroll
+      for (int n = 0; n < 4; ++n) {
+        const bf16x8 bv = *(const bf16x8*)&s_x[(ky * (TPX + 2) + 16 * n + li + kx) * KC + kq];
+        acc[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bv, acc[n], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+  // epilogue: lane holds rows 4(lane/16)+q (output channels), column lane%16
+#pragma unroll
+  for (int n = 0; n < 4; ++n) {
+    const int px = x0 + 16 * n + (lane & 15);
+    if (px >= W) continue;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int o = co0 + 16 * wv + 4 * (lane >> 4) + q;
+      if (o >= co) continue;
+      float v = acc[n][q] + (bias ? bias[o] : 0.f);
+      if (relu) v = fmaxf(v, 0.f);
+      const size_t idx = ((size_t)b * co + o) * plane + (size_t)row * W + px;
+      if (yb) yb[idx] = f2bf(v);
+      else yf[idx] = v;
+    }
+  }
+}
+
+// ------------------------------------------------------- weight gradient
+// dw[o,c,tap] partial sums over the pixels of one chunk of rows:
+// sum_{i,j} dy[b,o,i,j] x[b,c,i+ky-1,j+kx-1] as GEMM M = o, N = c, K = 32
+// pixels per step.  Grid: (co/64, ci/32, chunks); chunk = (sample, rows
+// [r0, r0+rows)).  Partial results go to part[chunk][o][c][tap] (FP32).
+__global__ void __launch_bounds__(NT) k_conv3_wgrad(const __bf16* __restrict__ x,
+                                                    const __bf16* __restrict__ dy,
+                                                    float* __restrict__ part, int B, int ci,
+                                                    int co, int H, int W, int rows) {
+  __shared__ __attribute__((aligned(16))) __bf16 s_dy[TCO * TPX];             // [o][px]
+  __shared__ __attribute__((aligned(16))) __bf16 s_x[KC * 3 * (TPX + 2 + 6)]; // [c][row][px]
+  constexpr int XP = TPX + 8;   // padded row pitch (16-byte aligned reads at any shift)
+  const int co0 = blockIdx.x * TCO, c0 = blockIdx.y * KC;
+  const int chunks_per_b = (H + rows - 1) / rows;
+  const int b = blockIdx.z / chunks_per_b;
+  const int r0 = (blockIdx.z % chunks_per_b) * rows;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int li = lane & 15, kq = 8 * (lane >> 4);
+  f32x4 acc[2][9];
+#pragma unroll
+  for (int n = 0; n < 2; ++n)
+#pragma unroll
+    for (int t = 0; t < 9; ++t) acc[n][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const size_t plane = (size_t)H * W;
+  for (int row = r0; row < r0 + rows && row < H; ++row) {
+    for (int x0 = 0; x0 < W; x0 += TPX) {
+      for (int e = tid; e < TCO * TPX; e += NT) {
+        const int px = e % TPX, o = e / TPX;
+        __bf16 v = f2bf(0.f);
+        if (co0 + o < co && x0 + px < W) v = dy[((size_t)b * co + co0 + o) * plane + (size_t)row * W + x0 + px];
+        s_dy[e] = v;
+      }
+      // x: columns x0-1 .. x0+TPX stored at px index 0..TPX+1 (pitch XP)
+      for (int e = tid; e < KC * 3 * XP; e += NT) {
+        const int px = e % XP;
+        const int r = (e / XP) % 3;
+        const int c = e / (3 * XP);
+        const int yy = row + r - 1, xx = x0 + px - 1;
+        __bf16 v = f2bf(0.f);
+        if (px < TPX + 2 && yy >= 0 && yy < H && xx >= 0 && xx < W)
+          v = x[((size_t)b * ci + c0 + c) * plane + (size_t)yy * W + xx];
+        s_x[e] = v;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int ks = 0; ks < TPX / 32; ++ks) {
+        // A: dy[o = 16 wv + li][px = 32 ks + kq .. +8]
+        const bf16x8 a = *(const bf16x8*)&s_dy[(16 * wv + li) * TPX + 32 * ks + kq];
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+          const int ky = t / 3, kx = t - 3 * ky;
+#pragma unroll
+          for (int n = 0; n < 2; ++n) {
+            // B: x[c = 16 n + li][shifted px = 32 ks + kq + kx .. +8] (element-wise gather:
+            // the shift by kx breaks 16-byte alignment)
+            bf16x8 bv;
+            const __bf16* src = &s_x[((16 * n + li) * 3 + ky) * XP + 32 * ks + kq + kx];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) bv[q] = src[q];
+            acc[n][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bv, acc[n][t], 0, 0, 0);
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // D: rows (o) 4(lane/16)+q, column (c) lane%16
+  float* out = part + (size_t)blockIdx.z * co * ci * 9;
+#pragma unroll
+  for (int n = 0; n < 2; ++n)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int o = co0 + 16 * wv + 4 * (lane >> 4) + q;
+      const int c = c0 + 16 * n + li;
+      if (o >= co) continue;
+#pragma unroll
+      for (int t = 0; t < 9; ++t) out[((size_t)o * ci + c) * 9 + t] = acc[n][t][q];
+    }
+}
+
+// Sum of the chunk partials (fixed order) into the FP32 gradient of the
+// weights in the master layout [o][c][3][3], and the bias gradient.
+__global__ void k_wgrad_reduce(const float* __restrict__ part, int chunks, int co, int ci,
+                               int ci_used, float* __restrict__ gw) {
+  const int n = co * ci_used * 9;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+    const int t = e % 9, c = (e / 9) % ci_used, o = e / (9 * ci_used);
+    float s = 0.f;
+    for (int k = 0; k < chunks; ++k) s += part[((size_t)k * co * ci + (size_t)o * ci + c) * 9 + t];
+    gw[e] = s;
+  }
+}
+
+// Bias gradient: sum over batch and pixels of dy[b,o,:,:] (one block per o).
+__global__ void __launch_bounds__(NT) k_bias_grad(const __bf16* __restrict__ dy, int B, int co,
+                                                  int HW, float* __restrict__ gb) {
+  __shared__ float sh[NT];
+  const int o = blockIdx.x;
+  float s = 0.f;
+  for (int b = 0; b < B; ++b)
+    for (int p = threadIdx.x; p < HW; p += NT) s += bf2f(dy[((size_t)b * co + o) * HW + p]);
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int st = NT / 2; st > 0; st >>= 1) {
+    if (threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) gb[o] = sh[0];
+}
+
+// --------------------------------------------------------- weight packing
+// Master [o][c][3][3] (c < ci_used) -> BF16 [o][tap][c] with c padded to ci.
+// transpose != 0: the backward-data operator, BF16 [c][tap'][o] with the
+// taps rotated by 180 degrees (so that the forward kernel computes the
+// adjoint convolution).
+__global__ void k_pack_w(const float* __restrict__ w, int co, int ci_used, int ci,
+                         __bf16* __restrict__ wp, int transpose) {
+  const int n = co * 9 * ci;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+    if (!transpose) {
+      const int c = e % ci, t = (e / ci) % 9, o = e / (9 * ci);
+      wp[e] = f2bf(c < ci_used ? w[((size_t)o * ci_used + c) * 9 + t] : 0.f);
+    } else {
+      // wp layout [c][t'][o] with o fastest, size ci * 9 * co
+      const int o = e % co, t = (e / co) % 9, c = e / (9 * co);
+      wp[e] = f2bf(c < ci_used ? w[((size_t)o * ci_used + c) * 9 + (8 - t)] : 0.f);
+    }
+  }
+}
+
+// ------------------------------------------------------------- elementwise
+// 2x2 mean pooling
+__global__ void k_pool(const __bf16* __restrict__ x, __bf16* __restrict__ y, int BC, int H, int W) {
+  const int h = H / 2, w = W / 2;
+  const size_t n = (size_t)BC * h * w;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+    const int j = e % w, i = (e / w) % h;
+    const size_t bc = e / ((size_t)w * h);
+    const __bf16* s = x + bc * H * W + (size_t)(2 * i) * W + 2 * j;
+    y[e] = f2bf(0.25f * (bf2f(s[0]) + bf2f(s[1]) + bf2f(s[W]) + bf2f(s[W + 1])));
+  }
+}
+
+// y[b] = cat(up2(lo[b]) (clo channels), skip[b] (cs channels)) at H x W
+__global__ void k_upcat(const __bf16* __restrict__ lo, const __bf16* __restrict__ skip,
+                        __bf16* __restrict__ y, int B, int clo, int cs, int H, int W) {
+  const int C = clo + cs;
+  const size_t n = (size_t)B * C * H * W;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+    const int j = e % W, i = (e / W) % H;
+    const int c = (e / ((size_t)W * H)) % C;
+    const int b = e / ((size_t)W * H * C);
+    __bf16 v;
+    if (c < clo) v = lo[(((size_t)b * clo + c) * (H / 2) + i / 2) * (W / 2) + j / 2];
+    else v = skip[(((size_t)b * cs + (c - clo)) * H + i) * W + j];
+    y[e] = v;
+  }
+}
+
+// Backward of cat(up2(lo), skip): dlo = sum of the 2x2 block of the first
+// clo channels; dskip_out = dcat[clo:] (+ pool_backward(dpool) when given:
+// the skip tensor also fed the next level's pooling).
+__global__ void k_upcat_bwd_lo(const __bf16* __restrict__ dcat, __bf16* __restrict__ dlo, int B,
+                               int clo, int C, int H, int W) {
+  const int h = H / 2, w = W / 2;
+  const size_t n = (size_t)B * clo * h * w;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+    const int j = e % w, i = (e / w) % h;
+    const int c = (e / ((size_t)w * h)) % clo;
+    const int b = e / ((size_t)w * h * clo);
+    const __bf16* s = dcat + (((size_t)b * C + c) * H + 2 * i) * W + 2 * j;
+    dlo[e] = f2bf(bf2f(s[0]) + bf2f(s[1]) + bf2f(s[W]) + bf2f(s[W + 1]));
+  }
+}
+
+// dskip[b,c,i,j] = dcat[b, clo+c, i, j] + dpool[b,c,i/2,j/2] / 4
+__global__ void k_skip_grad(const __bf16* __restrict__ dcat, const __bf16* __restrict__ dpool,
+                            __bf16* __restrict__ dskip, int B, int clo, int cs, int H, int W) {
+  const int C = clo + cs;
+  const size_t n = (size_t)B * cs * H * W;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+    const int j = e % W, i = (e / W) % H;
+    const int c = (e / ((size_t)W * H)) % cs;
+    const int b = e / ((size_t)W * H * cs);
+    float v = bf2f(dcat[(((size_t)b * C + clo + c) * H + i) * W + j]);
+    if (dpool) v += 0.25f * bf2f(dpool[(((size_t)b * cs + c) * (H / 2) + i / 2) * (W / 2) + j / 2]);
+    dskip[e] = f2bf(v);
+  }
+}
+
+// d(pre-activation) = d(post) * (post > 0), in place on a BF16 gradient
+__global__ void k_relu_bwd(__bf16* __restrict__ g, const __bf16* __restrict__ y, size_t n) {
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x)
+    if (!(bf2f(y[e]) > 0.f)) g[e] = f2bf(0.f);
+}
+
+// 1x1 output layer: y[b,p] = sum_c w[c] d0[b,c,p] + bias (FP32 out)
+__global__ void k_out_fwd(const __bf16* __restrict__ d0, const float* __restrict__ w,
+                          const float* __restrict__ bias, float* __restrict__ y, int B, int C,
+                          int HW) {
+  const size_t n = (size_t)B * HW;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+    const int p = e % HW;
+    const int b = e / HW;
+    float s = bias[0];
+    for (int c = 0; c < C; ++c) s += w[c] * bf2f(d0[((size_t)b * C + c) * HW + p]);
+    y[e] = s;
+  }
+}
+
+// Loss gradient dy = 2 (y - t) / N and the output layer's backward:
+// dd0[b,c,p] = w[c] dy[b,p] (BF16); per-block partials of dw[c], db, loss.
+__global__ void __launch_bounds__(NT) k_out_bwd(const __bf16* __restrict__ d0,
+                                                const float* __restrict__ w,
+                                                const float* __restrict__ y,
+                                                const float* __restrict__ t,
+                                                __bf16* __restrict__ dd0,
+                                                float* __restrict__ part /* [blocks][C+2] */,
+                                                int B, int C, int HW) {
+  __shared__ float sh[NT];
+  const size_t n = (size_t)B * HW;
+  const float inv_n = 1.f / (float)n;
+  float acc[34];
+  for (int c = 0; c < C + 2; ++c) acc[c] = 0.f;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+    const int p = e % HW;
+    const int b = e / HW;
+    const float diff = y[e] - t[e];
+    const float dyv = 2.f * diff * inv_n;
+    for (int c = 0; c < C; ++c) {
+      const size_t idx = ((size_t)b * C + c) * HW + p;
+      acc[c] += dyv * bf2f(d0[idx]);
+      dd0[idx] = f2bf(w[c] * dyv);
+    }
+    acc[C] += dyv;
+    acc[C + 1] += diff * diff * inv_n;
+  }
+  for (int c = 0; c < C + 2; ++c) {
+    sh[threadIdx.x] = acc[c];
+    __syncthreads();
+    for (int st = NT / 2; st > 0; st >>= 1) {
+      if (threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) part[(size_t)blockIdx.x * (C + 2) + c] = sh[0];
+    __syncthreads();
+  }
+}
+
+__global__ void k_out_reduce(const float* __restrict__ part, int blocks, int C,
+                             float* __restrict__ gw, float* __restrict__ gb, float* __restrict__ loss) {
+  const int c = threadIdx.x;
+  if (c >= C + 2) return;
+  float s = 0.f;
+  for (int k = 0; k < blocks; ++k) s += part[(size_t)k * (C + 2) + c];
+  if (c < C) gw[c] = s;
+  else if (c == C) gb[0] = s;
+  else loss[0] = s;
+}
+
+// Adam (bias-corrected) on the FP32 master parameters.
+__global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, size_t n, float lr, float b1, float b2, float eps,
+                       float c1, float c2) {
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+    const float gg = g[e];
+    const float mm = b1 * m[e] + (1.f - b1) * gg;
+    const float vv = b2 * v[e] + (1.f - b2) * gg * gg;
+    m[e] = mm;
+    v[e] = vv;
+    p[e] -= lr * (mm / c1) / (sqrtf(vv / c2) + eps);
+  }
+}
+
+// Input features (FP32 [B][3][H][W]) -> BF16 [B][32][H][W], channels 3..31 zero.
+__global__ void k_pack_input(const float* __restrict__ f, __bf16* __restrict__ x, int B, int HW,
+                             int cpad) {
+  const size_t n = (size_t)B * cpad * HW;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+    const int p = e % HW;
+    const int c = (e / HW) % cpad;
+    const int b = e / ((size_t)HW * cpad);
+    x[e] = f2bf(c < 3 ? f[((size_t)b * 3 + c) * HW + p] : 0.f);
+  }
+}
+
+}  // namespace cdinet

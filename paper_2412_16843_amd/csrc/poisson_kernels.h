@@ -43,14 +43,14 @@ template <typename S>
 __global__ void __launch_bounds__(kNT) k_rhs(const Tile* __restrict__ tiles,
                                               const Inst* __restrict__ insts, int src, double tau,
                                               double rtol, int maxit) {
-  __shared__ double sh[kNT / 64];
+  __shared__ double sh[2 * kNT / 64];
   const Tile t = tiles[blockIdx.x];
   const Inst& I = insts[t.inst];
   const int nx = I.nx, ny = I.ny;
   const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
   const int i = t.i0 + tx, j = t.j0 + ty;
   const double* __restrict__ ph = src == 0 ? I.phi : (src == 1 ? I.phi_a : I.phi_b);
-  double bsum[1] = {0.0};
+  double bsum[2] = {0.0, 0.0};
   if (i < nx && j < ny) {
     const size_t o = (size_t)j * nx + i;
     const int ie = wrap(i + 1, nx), iw = wrap(i - 1, nx);
@@ -76,6 +76,7 @@ __global__ void __launch_bounds__(kNT) k_rhs(const Tile* __restrict__ tiles,
     I.vstar[o] = vs;
     I.b[o] = b;
     bsum[0] = b;
+    bsum[1] = b * b;
     const double ih2 = I.inv_h * I.inv_h;
     const double ax = ih2 / rfw;
     const double ay = j >= 1 ? ih2 / rfs : 0.0;
@@ -86,13 +87,19 @@ __global__ void __launch_bounds__(kNT) k_rhs(const Tile* __restrict__ tiles,
       ((S*)I.lev[0].ay)[o] = (S)ay;
     }
   }
-  block_sum<1>(bsum, sh);
-  if (threadIdx.x == 0) st_agent(&I.part[t.local], bsum[0]);
+  block_sum<2>(bsum, sh);
+  if (threadIdx.x == 0) {
+    st_agent(&I.part[t.local], bsum[0]);
+    st_agent(&I.part[I.ntiles + t.local], bsum[1]);
+  }
   if (arrive_last(I.counters + 0 * kCounterStride, I.ntiles, t.local)) {
     const double s = sum_partials(I.part, I.ntiles, sh);
+    const double s2 = sum_partials(I.part + I.ntiles, I.ntiles, sh);
     if (threadIdx.x == 0) {
       PcgScalars* P = I.pcg;
-      P->bmean = s / ((double)nx * ny);
+      const double n = (double)nx * ny;
+      P->bmean = s / n;
+      P->brms = sqrt(fmax(s2 / n - P->bmean * P->bmean, 0.0));
       P->done = 0; P->iters = 0; P->first = 1; P->converged = 0; P->pad = 0;
       P->rtol = rtol; P->maxit = maxit;
     }
@@ -112,7 +119,8 @@ __device__ __forceinline__ double apply_K(const Inst& I, const double* __restric
   return s;
 }
 
-// f = -(b - mean b); x0 = guess (previous pressure) or 0; r = f - K x0.
+// f = -(b - mean b); x0 = guess (1: the previous pressure, 2: the fitted
+// multiple gscale of the learned pressure held in p) or 0; r = f - K x0.
 __global__ void __launch_bounds__(kNT) k_pcg_init(const Tile* __restrict__ tiles,
                                                   const Inst* __restrict__ insts, int guess) {
   __shared__ double sh[2 * kNT / 64];
@@ -127,8 +135,9 @@ __global__ void __launch_bounds__(kNT) k_pcg_init(const Tile* __restrict__ tiles
     const double f = -(I.b[o] - I.pcg->bmean);
     double r = f;
     if (guess) {
-      r = f - apply_K(I, I.p, j, i);
-      I.x[o] = I.p[o];
+      const double gs = guess == 2 ? I.pcg->gscale : 1.0;
+      r = f - gs * apply_K(I, I.p, j, i);
+      I.x[o] = gs * I.p[o];
     } else {
       I.x[o] = 0.0;
     }
@@ -204,6 +213,37 @@ __global__ void __launch_bounds__(kNT) k_pcg_spmv(const Tile* __restrict__ tiles
       P->alpha = dq != 0.0 ? dr / dq : 0.0;
       P->first = 0;
     }
+  }
+}
+
+// Galerkin fit of the learned guess held in p: gscale = (f, p)/(p, K p)
+// minimises the K-norm error of x0 = gscale p, so the fitted guess is never
+// worse than x0 = 0 in that norm.
+__global__ void __launch_bounds__(kNT) k_guess_fit(const Tile* __restrict__ tiles,
+                                                   const Inst* __restrict__ insts) {
+  __shared__ double sh[2 * kNT / 64];
+  const Tile t = tiles[blockIdx.x];
+  const Inst& I = insts[t.inst];
+  const int nx = I.nx, ny = I.ny;
+  const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+  const int i = t.i0 + tx, j = t.j0 + ty;
+  double s[2] = {0.0, 0.0};
+  if (i < nx && j < ny) {
+    const size_t o = (size_t)j * nx + i;
+    const double f = -(I.b[o] - I.pcg->bmean);
+    const double pv = I.p[o];
+    s[0] = f * pv;
+    s[1] = pv * apply_K(I, I.p, j, i);
+  }
+  block_sum<2>(s, sh);
+  if (threadIdx.x == 0) {
+    st_agent(&I.part[t.local], s[0]);
+    st_agent(&I.part[I.ntiles + t.local], s[1]);
+  }
+  if (arrive_last(I.counters + 7 * kCounterStride, I.ntiles, t.local)) {
+    const double fp = sum_partials(I.part, I.ntiles, sh);
+    const double pkp = sum_partials(I.part + I.ntiles, I.ntiles, sh);
+    if (threadIdx.x == 0) I.pcg->gscale = pkp > 0.0 ? fp / pkp : 0.0;
   }
 }
 

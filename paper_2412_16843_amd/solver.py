@@ -109,6 +109,21 @@ class CDISolver:
         return out, dict(iterations=info.iterations, converged=info.converged,
                          relres=info.relres, bnorm=info.bnorm, ms=info.ms, status=st)
 
+    def attach_guess(self, net) -> None:
+        """Use a GuessNet (batch 1, h = ny, w = nx) for every solve's initial
+        guess (context created with guess="learned"); None detaches."""
+        L.check(self.lib.cdi_guess_attach(self.ctx, net.handle if net is not None else None))
+        self._net = net
+
+    def guess_features(self, idx: int = 0):
+        """Features [3, ny, nx] and normalised target [ny, nx] of the last
+        projection of instance idx (FP32 device tensors)."""
+        p = self.params[idx]
+        f = torch.empty((3, p.ny, p.nx), dtype=torch.float32, device=self.device)
+        t = torch.empty((p.ny, p.nx), dtype=torch.float32, device=self.device)
+        L.check(self.lib.cdi_guess_features(self.ctx, idx, f.data_ptr(), t.data_ptr()))
+        return f, t
+
     def timing_enable(self, kernel: str | None):
         L.check(self.lib.cdi_timing_enable(self.ctx, kernel.encode() if kernel else None))
 

@@ -1,0 +1,85 @@
+"""Pins of the FP64 network reference (oracle/unet.py): convolution against
+SciPy's 2-D correlation, the layer algebra against its definitions, and
+every gradient against central finite differences of the loss."""
+import numpy as np
+import pytest
+from scipy.signal import correlate2d
+
+from oracle import unet
+
+
+def test_conv3_equals_scipy_correlation():
+    rng = np.random.default_rng(0)
+    x = rng.standard_normal((2, 3, 8, 10))
+    w = rng.standard_normal((4, 3, 3, 3))
+    b = rng.standard_normal(4)
+    y = unet.conv3(x, w, b)
+    for bb in range(2):
+        for o in range(4):
+            ref = sum(correlate2d(x[bb, c], w[o, c], mode="same", boundary="fill")
+                      for c in range(3)) + b[o]
+            assert np.allclose(y[bb, o], ref, atol=1e-12)
+
+
+def test_pool_and_up_are_adjoint_up_to_scale():
+    rng = np.random.default_rng(1)
+    a = rng.standard_normal((1, 2, 8, 8))
+    c = rng.standard_normal((1, 2, 4, 4))
+    # <pool(a), c> = <a, pool_backward(c)>, <up(c), a> = <c, up_backward(a)>
+    assert np.isclose(np.sum(unet.pool(a) * c), np.sum(a * unet.pool_backward(c)))
+    assert np.isclose(np.sum(unet.up(c) * a), np.sum(c * unet.up_backward(a)))
+    assert np.allclose(unet.pool(unet.up(c)), c)
+
+
+def test_gradients_match_finite_differences():
+    rng = np.random.default_rng(2)
+    p = unet.init_params(3)
+    for k in p:
+        if k.endswith(".b"):
+            p[k] = 0.1 * rng.standard_normal(p[k].shape)
+    x = rng.standard_normal((2, 3, 16, 16))
+    t = rng.standard_normal((2, 1, 16, 16))
+    y, c = unet.forward(p, x)
+    g = unet.backward(p, c, y, t)
+
+    def L():
+        return unet.loss(unet.forward(p, x)[0], t)
+
+    h = 1e-6
+    for key in ["e0.w", "e1.w", "e2.w", "e3.w", "d2.w", "d1.w", "d0.w", "out.w",
+                "e0.b", "d2.b", "out.b"]:
+        arr = p[key]
+        for _ in range(3):
+            idx = tuple(int(rng.integers(0, s)) for s in arr.shape)
+            old = arr[idx]
+            arr[idx] = old + h
+            lp = L()
+            arr[idx] = old - h
+            lm = L()
+            arr[idx] = old
+            fd = (lp - lm) / (2 * h)
+            assert abs(fd - g[key][idx]) <= 1e-6 * max(1.0, abs(fd)) + 1e-9, (key, idx, fd, g[key][idx])
+    for _ in range(3):
+        idx = tuple(int(rng.integers(0, s)) for s in x.shape)
+        old = x[idx]
+        x[idx] = old + h
+        lp = L()
+        x[idx] = old - h
+        lm = L()
+        x[idx] = old
+        assert abs((lp - lm) / (2 * h) - g["x"][idx]) < 1e-7
+
+
+def test_adam_moves_downhill():
+    rng = np.random.default_rng(4)
+    p = unet.init_params(5)
+    x = rng.standard_normal((1, 3, 16, 16))
+    t = np.zeros((1, 1, 16, 16))
+    m = {k: np.zeros_like(v) for k, v in p.items()}
+    v = {k: np.zeros_like(val) for k, val in p.items()}
+    losses = []
+    for s in range(1, 6):
+        y, c = unet.forward(p, x)
+        losses.append(unet.loss(y, t))
+        unet.adam(p, unet.backward(p, c, y, t), m, v, s, lr=1e-3)
+    assert losses[-1] < losses[0]
