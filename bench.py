@@ -111,6 +111,69 @@ def cpu_baseline(case, budget_s: float = 12.0, max_steps: int = 2000):
                        f"({dt:.1f} s, NumPy/SciPy FP64, one thread)")
 
 
+def poisson_learned_vs_plain(nx: int = 2048, train_iters: int = 300, verbose: bool = False):
+    """Pressure time-to-solution at relative residual 1e-10 on the 2048x1024
+    density-ratio-10 grid: zero guess, previous-step pressure and the learned
+    guess (network inference, Galerkin fit on span{previous pressure, network
+    output}, flexible CG), all on the GPU.
+    The network is trained first, on the GPU, on snapshots of other cases at
+    the same resolution (drops at 45/75 deg, a Couette at Ca 0.05)."""
+    import torch
+    from paper_2412_16843_amd import learned, train_guess
+    from paper_2412_16843_amd.solver import CDISolver
+    ny = nx // 2
+    t0 = time.perf_counter()
+    train_cases = [W.drop_case(nx, ny, th, 10.0, steps=24) for th in (45.0, 75.0)]
+    train_cases.append(W.couette_case(nx, ny, lx=2.0, ly=1.0, ratio=10.0, ca=0.05, steps=24))
+    data = train_guess.collect(train_cases, steps=24, every=3)
+    t_collect = time.perf_counter() - t0
+    net = learned.GuessNet(8, 256, 256)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    losses = train_guess.train(net, data, iters=train_iters, lr=5e-4,
+                               log_every=100 if verbose else 0)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    params = net.params.cpu().numpy()
+    net.close()
+    del data
+    rows = []
+    for case in (W.config5("drop", nx), W.config5("couette", nx)):
+        s = CDISolver(case.params, case.phi0, guess="prev", rtol=1e-10)
+        inf = learned.GuessNet(1, ny, nx, params=params, train=False, stream=s.stream)
+        s.attach_guess(inf)
+        s.step(10)
+        for _ in range(3):
+            p_prev = s.fields[0]["p"].clone()
+            s.step(1)
+            rec = {}
+            for mode in ("zero", "prev", "learned"):
+                s.set_guess(mode)
+                _, info = s.solve_last_rhs(p0=p_prev if mode != "zero" else None)
+                rec[mode] = (info["iterations"], info["ms"])
+            s.set_guess("prev")
+            rows.append(rec)
+        s.timing_enable("net")
+        s.set_guess("learned")
+        s.solve_last_rhs()
+        net_ms, net_n = s.timing_read()
+        s.timing_enable(None)
+        inf.close()
+        s.close()
+    mean = lambda m, k: sum(r[m][k] for r in rows) / len(rows)
+    return {
+        "grid": f"{nx}x{ny}", "rtol": 1e-10, "solves": len(rows),
+        "iters_zero": mean("zero", 0), "iters_prev": mean("prev", 0),
+        "iters_learned": mean("learned", 0),
+        "ms_zero": round(mean("zero", 1), 3), "ms_prev": round(mean("prev", 1), 3),
+        "ms_learned": round(mean("learned", 1), 3),
+        "ms_inference": round(net_ms / max(net_n, 1), 3),
+        "train": {"snapshots": 24, "iters": train_iters, "batch": 8, "crop": 256,
+                  "loss_first": losses[0], "loss_last": losses[-1],
+                  "train_s": round(t_train, 2), "collect_s": round(t_collect, 2)},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,6 +184,8 @@ def main():
     ap.add_argument("--kernel", default="auto",
                     help="kernel family for the roofline entry (auto: largest device time)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--poisson", action="store_true",
+                    help="add the learned-vs-plain pressure time-to-solution at 2048x1024")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -186,6 +251,8 @@ def main():
                      "algo_bytes_per_launch": per_launch_bytes},
     }
     s.close()
+    if args.poisson:
+        out["poisson_learned_vs_plain"] = poisson_learned_vs_plain()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(case)
     print(json.dumps(out), flush=True)

@@ -204,9 +204,11 @@ cdi_status cdi_timing_read(cdi_ctx* ctx, double* total_ms, int64_t* launches);
  * projection to a normalised pressure; its output is only the initial guess
  * of the flexible CG, which still iterates to poisson_rtol.
  *   b_hat = (b - mean b) / rms(b - mean b),
- *   p     = s * y * rms(b - mean b) * max(rho1, rho2) * h^2,
- * with s the Galerkin factor (f, p)/(p, K p) fitted on the device, so that
- * the guess is never worse than zero in the energy norm of the operator.
+ *   g     = y * rms(b - mean b) * max(rho1, rho2) * h^2,
+ * and the initial guess is x0 = a p_prev + c g with (a, c) the Galerkin fit
+ * on span{p_prev, g} (p_prev the previous pressure) computed on the device,
+ * so that x0 is never worse than p_prev or zero in the energy norm of the
+ * operator.
  * Parameters are FP32 in a fixed order (per 3x3 layer e0, e1, e2, e3, d2,
  * d1, d0: weights [co][ci][3][3] then biases [co]; then the 1x1 output layer
  * weights [32] and bias [1]), owned by the caller. */
@@ -242,11 +244,14 @@ cdi_status cdi_net_adam(cdi_net* net, float* m, float* v, int32_t step, double l
 void cdi_net_destroy(cdi_net* net);
 const char* cdi_net_last_error(void);
 
-/* Use `net` (batch 1, h = ny, w = nx of instance 0) for the initial guess of
- * every pressure solve of a single-instance context created with
- * guess = CDI_GUESS_LEARNED; NULL detaches (the previous pressure is then
- * used).  The context borrows the network. */
+/* Use `net` (batch 1, h = ny, w = nx of instance 0, same stream) for the
+ * initial guess of the pressure solves of a single-instance context while
+ * its guess mode is CDI_GUESS_LEARNED; NULL detaches (the previous pressure
+ * is then used).  The context borrows the network. */
 cdi_status cdi_guess_attach(cdi_ctx* ctx, cdi_net* net);
+
+/* Switch the initial-guess mode (CDI_GUESS_*) of later pressure solves. */
+cdi_status cdi_set_guess(cdi_ctx* ctx, int32_t guess);
 
 /* Features and normalised target of instance idx's last projection (after
  * cdi_step: the final-stage projection of the last step): features FP32

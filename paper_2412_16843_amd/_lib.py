@@ -24,7 +24,7 @@ EXPORTS = ("cdi_workspace_bytes", "cdi_default_dt", "cdi_init", "cdi_init_batch"
            "cdi_timing_read", "cdi_destroy", "cdi_last_error", "cdi_net_param_count",
            "cdi_net_workspace_bytes", "cdi_net_init", "cdi_net_repack", "cdi_net_forward",
            "cdi_net_backward", "cdi_net_adam", "cdi_net_destroy", "cdi_net_last_error",
-           "cdi_guess_attach", "cdi_guess_features")
+           "cdi_set_guess", "cdi_guess_attach", "cdi_guess_features")
 
 
 class cdi_params(C.Structure):
@@ -115,6 +115,8 @@ def lib() -> C.CDLL:
     L.cdi_net_destroy.restype = None
     L.cdi_net_last_error.argtypes = []
     L.cdi_net_last_error.restype = C.c_char_p
+    L.cdi_set_guess.argtypes = [vp, i32]
+    L.cdi_set_guess.restype = i32
     L.cdi_guess_attach.argtypes = [vp, vp]
     L.cdi_guess_attach.restype = i32
     L.cdi_guess_features.argtypes = [vp, i32, vp, vp]

@@ -737,11 +737,17 @@ cdi_status cdi_timing_read(cdi_ctx* c, double* total_ms, int64_t* launches) {
   return CDI_OK;
 }
 
+cdi_status cdi_set_guess(cdi_ctx* c, int32_t guess) {
+  if (!c) return fail(CDI_ERR_ARG, "ctx is NULL");
+  if (guess < CDI_GUESS_ZERO || guess > CDI_GUESS_LEARNED) return fail(CDI_ERR_ARG, "bad guess");
+  c->guess = guess;
+  return CDI_OK;
+}
+
 cdi_status cdi_guess_attach(cdi_ctx* c, cdi_net* net) {
   if (!c) return fail(CDI_ERR_ARG, "ctx is NULL");
   if (!net) { c->net = nullptr; return CDI_OK; }
   if (c->B.n != 1) return fail(CDI_ERR_STATE, "the learned guess needs a single-instance context");
-  if (c->guess != CDI_GUESS_LEARNED) return fail(CDI_ERR_STATE, "context was not created with CDI_GUESS_LEARNED");
   const Inst& I = c->B.inst[0];
   if (cdinet::batch(net) != 1 || cdinet::height(net) != I.ny || cdinet::width(net) != I.nx)
     return fail(CDI_ERR_SHAPE, "network shape must be batch 1, h = ny, w = nx");

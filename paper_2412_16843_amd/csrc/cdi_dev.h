@@ -35,7 +35,7 @@ struct PcgScalars {
   double dr, dq, zq;        // (d, r), (d, q), (z, q)
   double rr, fnorm, relres;
   double bmean, xmean, brms;
-  double gscale;            // factor applied to the initial guess (1 unless fitted)
+  double gscale, gscale2;   // x0 = gscale p + gscale2 g for the learned guess g
   double rtol;
   int done;                 // 1 once converged (or maxit reached): kernels exit early
   int iters;

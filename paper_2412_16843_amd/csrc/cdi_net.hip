@@ -132,8 +132,15 @@ void conv(cdi_net* n, const __bf16* x, const __bf16* w, const float* bias, __bf1
           int ci, int co, int level, int relu) {
   const int H = n->H >> level, W = n->W >> level;
   const int nxt = (W + TPX - 1) / TPX;
-  dim3 grid((unsigned)(n->B * H * nxt), (unsigned)((co + TCO - 1) / TCO));
-  k_conv3_fwd<<<grid, NT, 0, n->stream>>>(x, w, bias, yb, yf, n->B, ci, co, H, W, relu);
+  if (co <= 32) {   // 32-channel tile, 4 rows per block
+    const int rows = CROWS * 2;
+    dim3 grid((unsigned)(n->B * ((H + rows - 1) / rows) * nxt), (unsigned)((co + 31) / 32));
+    k_conv3_fwd<2><<<grid, NT, 0, n->stream>>>(x, w, bias, yb, yf, n->B, ci, co, H, W, relu);
+  } else {          // 64-channel tile, 2 rows per block
+    const int rows = CROWS;
+    dim3 grid((unsigned)(n->B * ((H + rows - 1) / rows) * nxt), (unsigned)((co + 63) / 64));
+    k_conv3_fwd<4><<<grid, NT, 0, n->stream>>>(x, w, bias, yb, yf, n->B, ci, co, H, W, relu);
+  }
 }
 
 void pack_weights(cdi_net* n) {

@@ -204,15 +204,15 @@ __global__ void __launch_bounds__(kNT) k_features(const Inst* __restrict__ insts
   }
 }
 
-// Pressure guess from the network output: p = y rms rho_max h^2 (then fitted
-// by k_guess_fit).
+// Pressure guess from the network output: g = y rms rho_max h^2, held in zf
+// until k_guess_fit combines it with the previous pressure.
 __global__ void __launch_bounds__(kNT) k_guess_apply(const Inst* __restrict__ insts,
                                                      const float* __restrict__ y) {
   const Inst& I = insts[0];
   const size_t n = (size_t)I.nx * I.ny;
   const double pscale = I.pcg->brms * fmax(I.rho1, I.rho2) * I.h * I.h;
   for (size_t c = blockIdx.x * (size_t)kNT + threadIdx.x; c < n; c += (size_t)gridDim.x * kNT)
-    I.p[c] = (double)y[c] * pscale;
+    I.zf[c] = (double)y[c] * pscale;
 }
 
 }  // namespace cdi

@@ -26,79 +26,130 @@ __device__ __forceinline__ __bf16 f2bf(float v) { return (__bf16)v; }
 
 // ------------------------------------------------------------------ conv 3x3
 // y[b,o,i,j] = act(bias[o] + sum_{c,ky,kx} w[o,ky*3+kx,c] x[b,c,i+ky-1,j+kx-1])
-// as an implicit GEMM: M = output channels, N = pixels of one row segment,
-// K = 32 input channels per step, 9 taps.  Zero padding outside the image.
-// Wave w owns output channels [16w, 16w+16) of the tile and 4 blocks of 16
-// pixels.  ci must be a multiple of 32.  relu: 0 none, 1 relu.
+// as an implicit GEMM: M = output channels, N = pixels, K = 32 input channels
+// per step, 9 taps.  One block computes 64 output channels x 2 rows x 64
+// columns; wave w owns output channels [16w, 16w+16) for both rows (8 MFMA
+// accumulators), so each staged weight chunk serves 128 pixels.  Weights are
+// staged with 16-byte loads; the 4 input rows of a chunk with 16-byte loads
+// along x plus the two halo columns.  Zero padding outside the image.
+// ci must be a multiple of 32.  relu: 0 none, 1 relu.
 // Output either BF16 (yb) or FP32 (yf), whichever is non-null.
+// WCO waves along the output channels (4: 64-channel tile, 2 rows per wave
+// group; 2: 32-channel tile for 32-channel layers, the other two waves take
+// two more rows), so no wave multiplies padding channels.
+constexpr int CROWS = 2;   // rows per wave
+template <int WCO>
 __global__ void __launch_bounds__(NT) k_conv3_fwd(const __bf16* __restrict__ x,
                                                   const __bf16* __restrict__ wp,
                                                   const float* __restrict__ bias,
                                                   __bf16* __restrict__ yb, float* __restrict__ yf,
                                                   int B, int ci, int co, int H, int W, int relu) {
-  __shared__ __attribute__((aligned(16))) __bf16 s_x[3 * (TPX + 2) * KC];   // [row][px][c]
-  __shared__ __attribute__((aligned(16))) __bf16 s_w[TCO * 9 * KC];         // [o][tap][c]
+  constexpr int TC = 16 * WCO;                       // output channels of the tile
+  constexpr int ROWS = CROWS * (4 / WCO);            // output rows of the tile
+  constexpr int XR = ROWS + 2;                       // staged input rows
+  __shared__ __attribute__((aligned(16))) __bf16 s_x[XR * (TPX + 2) * KC];   // [row][px][c]
+  __shared__ __attribute__((aligned(16))) __bf16 s_w[TC * 9 * KC];           // [o][tap][c]
   const int nxt = (W + TPX - 1) / TPX;
+  const int nyt = (H + ROWS - 1) / ROWS;
   int blk = blockIdx.x;
   const int xt = blk % nxt; blk /= nxt;
-  const int row = blk % H; blk /= H;
+  const int row0 = (blk % nyt) * ROWS; blk /= nyt;
   const int b = blk;
-  const int co0 = blockIdx.y * TCO;
+  const int co0 = blockIdx.y * TC;
   const int x0 = xt * TPX;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  f32x4 acc[4];
+  const int wco = wv % WCO;                          // channel block of this wave
+  const int wr0 = (wv / WCO) * CROWS;                // first tile row of this wave
+  const bool vec = (W % 8) == 0;
+  f32x4 acc[CROWS][4];
 #pragma unroll
-  for (int n = 0; n < 4; ++n) acc[n] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int r = 0; r < CROWS; ++r)
+#pragma unroll
+    for (int n = 0; n < 4; ++n) acc[r][n] = f32x4{0.f, 0.f, 0.f, 0.f};
   const size_t plane = (size_t)H * W;
+  const int kq = 8 * (lane >> 4);
+  const int li = lane & 15;
   for (int c0 = 0; c0 < ci; c0 += KC) {
-    // stage the input patch: rows row-1..row+1, columns x0-1..x0+TPX
-    for (int e = tid; e < KC * 3 * (TPX + 2); e += NT) {
-      const int px = e % (TPX + 2);
-      const int r = (e / (TPX + 2)) % 3;
-      const int c = e / (3 * (TPX + 2));
-      const int yy = row + r - 1, xx = x0 + px - 1;
+    // input rows row0-1 .. row0+ROWS: 8-column vectors of the 64-column core
+    for (int e = tid; e < KC * XR * (TPX / 8); e += NT) {
+      const int v8 = e % (TPX / 8);
+      const int r = (e / (TPX / 8)) % XR;
+      const int c = e / (XR * (TPX / 8));
+      const int yy = row0 + r - 1, xx = x0 + 8 * v8;
+      bf16x8 v;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = f2bf(0.f);
+      if (yy >= 0 && yy < H && xx < W) {
+        const __bf16* src = &x[((size_t)b * ci + c0 + c) * plane + (size_t)yy * W + xx];
+        if (vec && xx + 8 <= W) {
+          v = *(const bf16x8*)src;   // 16-byte aligned: W and the plane are multiples of 8
+        } else {
+#pragma unroll
+          for (int q = 0; q < 8; ++q)
+            if (xx + q < W) v[q] = src[q];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) s_x[(r * (TPX + 2) + 1 + 8 * v8 + q) * KC + c] = v[q];
+    }
+    // the two halo columns x0-1 and x0+TPX
+    for (int e = tid; e < KC * XR * 2; e += NT) {
+      const int side = e & 1;
+      const int r = (e >> 1) % XR;
+      const int c = e / (2 * XR);
+      const int yy = row0 + r - 1, xx = side ? x0 + TPX : x0 - 1;
       __bf16 v = f2bf(0.f);
       if (yy >= 0 && yy < H && xx >= 0 && xx < W) v = x[((size_t)b * ci + c0 + c) * plane + (size_t)yy * W + xx];
-      s_x[(r * (TPX + 2) + px) * KC + c] = v;
+      s_x[(r * (TPX + 2) + (side ? TPX + 1 : 0)) * KC + c] = v;
     }
-    // stage the weights of the tile
-    for (int e = tid; e < TCO * 9 * KC; e += NT) {
-      const int c = e % KC;
-      const int t = (e / KC) % 9;
-      const int o = e / (9 * KC);
-      __bf16 v = f2bf(0.f);
-      if (co0 + o < co) v = wp[((size_t)(co0 + o) * 9 + t) * ci + c0 + c];
-      s_w[e] = v;
+    // weights of the tile: 4 vectors of 8 input channels per (o, tap)
+    for (int e = tid; e < TC * 9 * (KC / 8); e += NT) {
+      const int v8 = e % (KC / 8);
+      const int ot = e / (KC / 8);           // o * 9 + tap
+      const int o = ot / 9;
+      bf16x8 v;
+      if (co0 + o < co) {
+        v = *(const bf16x8*)&wp[((size_t)(co0 * 9) + ot) * ci + c0 + 8 * v8];
+      } else {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = f2bf(0.f);
+      }
+      *(bf16x8*)&s_w[ot * KC + 8 * v8] = v;
     }
     __syncthreads();
-    const int kq = 8 * (lane >> 4);
-    const int li = lane & 15;
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
       const int ky = t / 3, kx = t - 3 * ky;
-      const bf16x8 a = *(const bf16x8*)&s_w[((16 * wv + li) * 9 + t) * KC + kq];
+      const bf16x8 a = *(const bf16x8*)&s_w[((16 * wco + li) * 9 + t) * KC + kq];
 #pragma unroll
-      for (int n = 0; n < 4; ++n) {
-        const bf16x8 bv = *(const bf16x8*)&s_x[(ky * (TPX + 2) + 16 * n + li + kx) * KC + kq];
-        acc[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bv, acc[n], 0, 0, 0);
-      }
+      for (int r = 0; r < CROWS; ++r)
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+          const bf16x8 bv = *(const bf16x8*)&s_x[((wr0 + r + ky) * (TPX + 2) + 16 * n + li + kx) * KC + kq];
+          acc[r][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bv, acc[r][n], 0, 0, 0);
+        }
     }
     __syncthreads();
   }
   // epilogue: lane holds rows 4(lane/16)+q (output channels), column lane%16
 #pragma unroll
-  for (int n = 0; n < 4; ++n) {
-    const int px = x0 + 16 * n + (lane & 15);
-    if (px >= W) continue;
+  for (int r = 0; r < CROWS; ++r) {
+    const int row = row0 + wr0 + r;
+    if (row >= H) continue;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int o = co0 + 16 * wv + 4 * (lane >> 4) + q;
-      if (o >= co) continue;
-      float v = acc[n][q] + (bias ? bias[o] : 0.f);
-      if (relu) v = fmaxf(v, 0.f);
-      const size_t idx = ((size_t)b * co + o) * plane + (size_t)row * W + px;
-      if (yb) yb[idx] = f2bf(v);
-      else yf[idx] = v;
+    for (int n = 0; n < 4; ++n) {
+      const int px = x0 + 16 * n + (lane & 15);
+      if (px >= W) continue;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int o = co0 + 16 * wco + 4 * (lane >> 4) + q;
+        if (o >= co) continue;
+        float v = acc[r][n][q] + (bias ? bias[o] : 0.f);
+        if (relu) v = fmaxf(v, 0.f);
+        const size_t idx = ((size_t)b * co + o) * plane + (size_t)row * W + px;
+        if (yb) yb[idx] = f2bf(v);
+        else yf[idx] = v;
+      }
     }
   }
 }

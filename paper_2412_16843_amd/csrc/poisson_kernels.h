@@ -119,8 +119,8 @@ __device__ __forceinline__ double apply_K(const Inst& I, const double* __restric
   return s;
 }
 
-// f = -(b - mean b); x0 = guess (1: the previous pressure, 2: the fitted
-// multiple gscale of the learned pressure held in p) or 0; r = f - K x0.
+// f = -(b - mean b); x0 = guess (1: the previous pressure p, 2: the fitted
+// combination of p and the learned pressure g held in zf) or 0; r = f - K x0.
 __global__ void __launch_bounds__(kNT) k_pcg_init(const Tile* __restrict__ tiles,
                                                   const Inst* __restrict__ insts, int guess) {
   __shared__ double sh[2 * kNT / 64];
@@ -134,10 +134,13 @@ __global__ void __launch_bounds__(kNT) k_pcg_init(const Tile* __restrict__ tiles
     const size_t o = (size_t)j * nx + i;
     const double f = -(I.b[o] - I.pcg->bmean);
     double r = f;
-    if (guess) {
-      const double gs = guess == 2 ? I.pcg->gscale : 1.0;
-      r = f - gs * apply_K(I, I.p, j, i);
-      I.x[o] = gs * I.p[o];
+    if (guess == 2) {
+      const double a = I.pcg->gscale, c = I.pcg->gscale2;
+      r = f - a * apply_K(I, I.p, j, i) - c * apply_K(I, I.zf, j, i);
+      I.x[o] = a * I.p[o] + c * I.zf[o];
+    } else if (guess) {
+      r = f - apply_K(I, I.p, j, i);
+      I.x[o] = I.p[o];
     } else {
       I.x[o] = 0.0;
     }
@@ -216,34 +219,46 @@ __global__ void __launch_bounds__(kNT) k_pcg_spmv(const Tile* __restrict__ tiles
   }
 }
 
-// Galerkin fit of the learned guess held in p: gscale = (f, p)/(p, K p)
-// minimises the K-norm error of x0 = gscale p, so the fitted guess is never
-// worse than x0 = 0 in that norm.
+// Galerkin fit of the initial guess on span{p, g}: p the previous pressure,
+// g the network's guess (in zf).  The coefficients (a, c) solve the 2x2
+// normal equations of min ||x0 - x*||_K over x0 = a p + c g, so the fitted
+// guess is never worse, in that norm, than the previous pressure or zero.
 __global__ void __launch_bounds__(kNT) k_guess_fit(const Tile* __restrict__ tiles,
                                                    const Inst* __restrict__ insts) {
-  __shared__ double sh[2 * kNT / 64];
+  __shared__ double sh[5 * kNT / 64];
   const Tile t = tiles[blockIdx.x];
   const Inst& I = insts[t.inst];
   const int nx = I.nx, ny = I.ny;
   const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
   const int i = t.i0 + tx, j = t.j0 + ty;
-  double s[2] = {0.0, 0.0};
+  double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};   // pKp, pKg, gKg, p.f, g.f
   if (i < nx && j < ny) {
     const size_t o = (size_t)j * nx + i;
     const double f = -(I.b[o] - I.pcg->bmean);
-    const double pv = I.p[o];
-    s[0] = f * pv;
-    s[1] = pv * apply_K(I, I.p, j, i);
+    const double pv = I.p[o], gv = I.zf[o];
+    const double kp = apply_K(I, I.p, j, i), kg = apply_K(I, I.zf, j, i);
+    s[0] = pv * kp; s[1] = pv * kg; s[2] = gv * kg; s[3] = pv * f; s[4] = gv * f;
   }
-  block_sum<2>(s, sh);
-  if (threadIdx.x == 0) {
-    st_agent(&I.part[t.local], s[0]);
-    st_agent(&I.part[I.ntiles + t.local], s[1]);
-  }
+  block_sum<5>(s, sh);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 5; ++k) st_agent(&I.part[k * I.ntiles + t.local], s[k]);
   if (arrive_last(I.counters + 7 * kCounterStride, I.ntiles, t.local)) {
-    const double fp = sum_partials(I.part, I.ntiles, sh);
-    const double pkp = sum_partials(I.part + I.ntiles, I.ntiles, sh);
-    if (threadIdx.x == 0) I.pcg->gscale = pkp > 0.0 ? fp / pkp : 0.0;
+    double m[5];
+    for (int k = 0; k < 5; ++k) m[k] = sum_partials(I.part + k * I.ntiles, I.ntiles, sh);
+    if (threadIdx.x == 0) {
+      double a = 0.0, c = 0.0;
+      const double det = m[0] * m[2] - m[1] * m[1];
+      if (m[0] > 0.0 && m[2] > 0.0 && det > 1e-12 * m[0] * m[2]) {
+        a = (m[3] * m[2] - m[4] * m[1]) / det;
+        c = (m[4] * m[0] - m[3] * m[1]) / det;
+      } else if (m[2] > 0.0) {
+        c = m[4] / m[2];
+      } else if (m[0] > 0.0) {
+        a = m[3] / m[0];
+      }
+      I.pcg->gscale = a;
+      I.pcg->gscale2 = c;
+    }
   }
 }
 

@@ -109,6 +109,22 @@ class CDISolver:
         return out, dict(iterations=info.iterations, converged=info.converged,
                          relres=info.relres, bnorm=info.bnorm, ms=info.ms, status=st)
 
+    def set_guess(self, mode: str) -> None:
+        """Initial-guess mode of later solves: "zero", "prev" or "learned"."""
+        L.check(self.lib.cdi_set_guess(self.ctx, L.GUESS[mode]))
+
+    def solve_last_rhs(self, p0=None):
+        """Re-solve the last projection's pressure equation (b = NULL)."""
+        p = self.params[0]
+        out = torch.zeros((p.ny, p.nx), dtype=torch.float64, device=self.device)
+        if p0 is not None:
+            out.copy_(p0)
+        info = L.cdi_solve_info()
+        st = self.lib.cdi_solve_pressure(self.ctx, None, out.data_ptr(), C.byref(info))
+        L.check(st, allow=(-4,))
+        return out, dict(iterations=info.iterations, converged=info.converged,
+                         relres=info.relres, ms=info.ms, guess_used=info.guess_used)
+
     def attach_guess(self, net) -> None:
         """Use a GuessNet (batch 1, h = ny, w = nx) for every solve's initial
         guess (context created with guess="learned"); None detaches."""
