@@ -166,6 +166,8 @@ size_t carve(const Resolved& R, int ntiles_cell, int ntiles_mg0, char* base, siz
   D.d1 = (double*)take(nc * 8);
   D.q = (double*)take(nc * 8);
   D.zf = (double*)take(nc * 8);
+  for (int k = 0; k < 4; ++k) D.ph[k] = (double*)take(nc * 8);
+  for (int k = 0; k < 4; ++k) D.ph2[k] = (double*)take(nc * 8);
   D.part = (double*)take((size_t)8 * std::max(ntiles_cell, ntiles_mg0) * 8);
   D.pcg = (PcgScalars*)take(sizeof(PcgScalars));
   D.counters = (unsigned*)take(sizeof(unsigned) * 8 * kCounterStride);
@@ -293,6 +295,7 @@ struct cdi_ctx {
   int maxit = 200;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   cdi_net* net = nullptr;        // learned initial guess (borrowed)
+  int hist_steps = 0;            // steps recorded in the per-stage pressure history
   // measurement hook: events around every launch of one kernel family
   std::string timed;
   std::vector<hipEvent_t> tev;
@@ -370,14 +373,14 @@ void launch_coef(cdi_ctx* c) {
 // Flexible-CG loop after the right-hand side is in place.  Returns NOCONV
 // if an instance stopped at maxit.
 template <typename S>
-cdi_status solve_loop(cdi_ctx* c, int guess) {
+cdi_status solve_loop(cdi_ctx* c, int guess, int stage) {
   Batch& B = c->B;
   const unsigned ncell = (unsigned)B.cell.size();
   if (!c->uniform_rho || !c->coef_ready) {
     launch_coef<S>(c);
     c->coef_ready = true;
   }
-  timed(c, "pcg_init", [&] { k_pcg_init<<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, guess); });
+  timed(c, "pcg_init", [&] { k_pcg_init<<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, guess, stage); });
   // z0 = M r0 (residual in buffer 0)
   launch_vcycle<S>(c, 0, 0, 0);
   int it = 0;
@@ -459,12 +462,17 @@ cdi_status run_step(cdi_ctx* c) {
     const double tfac = k < 3 ? RK_C[k + 1] : 1.0;
     timed(c, "rhs", [&] { k_rhs<S><<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, dst, tfac, c->rtol, c->maxit); });
     if (c->guess == CDI_GUESS_LEARNED && c->net) learned_guess(c, dst);
-    cdi_status s = solve_loop<S>(c, guess_mode(c));
+    // previous-pressure guess: the same stage of the previous step (linear
+    // extrapolation once two steps exist), else the last pressure
+    int gm = guess_mode(c);
+    if (gm == 1 && c->hist_steps >= 1) gm = c->hist_steps >= 2 ? 4 : 3;
+    cdi_status s = solve_loop<S>(c, gm, k);
     if (s == CDI_ERR_NOCONV) st = s;
     else if (s != CDI_OK) return s;
-    timed(c, "project", [&] { k_project<<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, tfac, k == 3, dst); });
+    timed(c, "project", [&] { k_project<<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, tfac, k == 3, dst, k); });
   }
   (void)dt;
+  c->hist_steps += 1;
   HIPCHK(hipGetLastError());
   return st;
 }
@@ -617,7 +625,7 @@ cdi_status cdi_solve_pressure(cdi_ctx* c, const double* b, double* p, cdi_solve_
   c->coef_ready = false;
   if (c->guess == CDI_GUESS_LEARNED && c->net) learned_guess(c, 0);
   const int guess = guess_mode(c);
-  cdi_status s = c->mixed ? solve_loop<float>(c, guess) : solve_loop<double>(c, guess);
+  cdi_status s = c->mixed ? solve_loop<float>(c, guess, 0) : solve_loop<double>(c, guess, 0);
   c->coef_ready = false;   // coefficients now follow the caller phase field
   k_solve_out<<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, p);
   HIPCHK(hipEventRecord(c->ev1, c->stream));

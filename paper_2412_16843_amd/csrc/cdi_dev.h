@@ -71,6 +71,8 @@ struct Inst {
   // pressure (FP64 CG vectors)
   double* b; double* x; double* rr; double* rr2; double* d0; double* d1; double* q;
   double* zf;                          // FP64 copy of level-0 correction (mixed path)
+  double* ph[4];                       // pressure of each RK stage in the previous step
+  double* ph2[4];                      // ... and in the step before
   double* part;                        // reduction partials, [8][ntiles]
   PcgScalars* pcg;
   unsigned* counters;                  // [8 kinds][kCounterStride] arrival counters

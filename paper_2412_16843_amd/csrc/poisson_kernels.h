@@ -119,10 +119,23 @@ __device__ __forceinline__ double apply_K(const Inst& I, const double* __restric
   return s;
 }
 
-// f = -(b - mean b); x0 = guess (1: the previous pressure p, 2: the fitted
-// combination of p and the learned pressure g held in zf) or 0; r = f - K x0.
+// f = -(b - mean b); x0 = guess or 0; r = f - K x0.  guess 1: the previous
+// pressure p; 2: the fitted combination of p and the learned pressure g held
+// in zf; 3: the same RK stage's pressure in the previous step (ph[stage]);
+// 4: its linear extrapolation in time 2 ph[stage] - ph2[stage].
+__device__ __forceinline__ double guess_value(const Inst& I, int guess, int stage, size_t o) {
+  switch (guess) {
+    case 1: return I.p[o];
+    case 2: return I.pcg->gscale * I.p[o] + I.pcg->gscale2 * I.zf[o];
+    case 3: return I.ph[stage][o];
+    case 4: return 2.0 * I.ph[stage][o] - I.ph2[stage][o];
+    default: return 0.0;
+  }
+}
+
 __global__ void __launch_bounds__(kNT) k_pcg_init(const Tile* __restrict__ tiles,
-                                                  const Inst* __restrict__ insts, int guess) {
+                                                  const Inst* __restrict__ insts, int guess,
+                                                  int stage) {
   __shared__ double sh[2 * kNT / 64];
   const Tile t = tiles[blockIdx.x];
   const Inst& I = insts[t.inst];
@@ -134,13 +147,15 @@ __global__ void __launch_bounds__(kNT) k_pcg_init(const Tile* __restrict__ tiles
     const size_t o = (size_t)j * nx + i;
     const double f = -(I.b[o] - I.pcg->bmean);
     double r = f;
-    if (guess == 2) {
-      const double a = I.pcg->gscale, c = I.pcg->gscale2;
-      r = f - a * apply_K(I, I.p, j, i) - c * apply_K(I, I.zf, j, i);
-      I.x[o] = a * I.p[o] + c * I.zf[o];
-    } else if (guess) {
-      r = f - apply_K(I, I.p, j, i);
-      I.x[o] = I.p[o];
+    if (guess) {
+      const int ie = wrap(i + 1, nx), iw = wrap(i - 1, nx);
+      const double xc = guess_value(I, guess, stage, o);
+      double kx = I.ax0[o] * (xc - guess_value(I, guess, stage, (size_t)j * nx + iw)) +
+                  I.ax0[(size_t)j * nx + ie] * (xc - guess_value(I, guess, stage, (size_t)j * nx + ie));
+      if (j >= 1) kx += I.ay0[o] * (xc - guess_value(I, guess, stage, o - nx));
+      if (j + 1 < ny) kx += I.ay0[o + nx] * (xc - guess_value(I, guess, stage, o + nx));
+      r = f - kx;
+      I.x[o] = xc;
     } else {
       I.x[o] = 0.0;
     }
@@ -299,7 +314,7 @@ __global__ void __launch_bounds__(kNT) k_pcg_xmean(const Tile* __restrict__ tile
 // from phi_next.
 __global__ void __launch_bounds__(kNT) k_project(const Tile* __restrict__ tiles,
                                                  const Inst* __restrict__ insts, double tau,
-                                                 int final_stage, int src) {
+                                                 int final_stage, int src, int stage) {
   const Tile t = tiles[blockIdx.x];
   const Inst& I = insts[t.inst];
   const int nx = I.nx, ny = I.ny;
@@ -321,7 +336,12 @@ __global__ void __launch_bounds__(kNT) k_project(const Tile* __restrict__ tiles,
   } else {
     vo[o] = 0.0;
   }
-  I.p[o] = xc - (zero ? 0.0 : I.pcg->xmean);
+  const double pn = xc - (zero ? 0.0 : I.pcg->xmean);
+  I.p[o] = pn;
+  if (stage >= 0) {   // pressure history of this RK stage (for the next step's guess)
+    I.ph2[stage][o] = I.ph[stage][o];
+    I.ph[stage][o] = pn;
+  }
   if (final_stage) {
     const double* __restrict__ ph = src == 1 ? I.phi_a : I.phi_b;
     I.phi[o] = ph[o];
@@ -722,12 +742,16 @@ __global__ void __launch_bounds__(kCoarseNT) k_mg_coarse(const Inst* __restrict_
     const S* r = s_r + oc[nl - 1];
     S* z = s_z + oc[nl - 1];
     if (I.cdense) {
-      for (int row = tid; row < n; row += kCoarseNT) {
+      // z = M r with 16 lanes per row (n <= 64 rows x 16 = 1024 threads)
+      const int row = tid >> 4, part = tid & 15;
+      double acc = 0.0;
+      if (row < n) {
         const double* M = I.cinv + (size_t)row * n;
-        double acc = 0.0;
-        for (int k = 0; k < n; ++k) acc += M[k] * (double)r[k];
-        z[row] = (S)acc;
+        for (int k = part; k < n; k += 16) acc += M[k] * (double)r[k];
       }
+#pragma unroll
+      for (int off = 8; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 16);
+      if (row < n && part == 0) z[row] = (S)acc;
       __syncthreads();
     } else {
       // CG in LDS scratch (FP64 values kept in the S arrays' spare room is not
