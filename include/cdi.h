@@ -66,6 +66,7 @@ enum { CDI_SLIP_1A = 0, CDI_SLIP_1B, CDI_SLIP_2A, CDI_SLIP_2B,
        CDI_SLIP_3A, CDI_SLIP_3B, CDI_SLIP_4A, CDI_SLIP_4B };
 enum { CDI_FP64 = 0, CDI_MIXED = 1 };
 enum { CDI_GUESS_ZERO = 0, CDI_GUESS_PREV = 1, CDI_GUESS_LEARNED = 2 };
+enum { CDI_LAUNCH_TILED = 0, CDI_LAUNCH_PERSISTENT = 1 };
 
 /* Problem statement (Sec. 2 and Sec. 4 of the paper).  Any field left 0 where
  * a default is stated takes that default. */
@@ -93,7 +94,8 @@ typedef struct {
   double poisson_rtol;   /* stop when ||f - K x||_2 <= rtol ||f||_2; 0 -> 1e-10       */
   int32_t poisson_maxit; /* 0 -> 200                                                  */
   int32_t mg_smooth;     /* red-black Gauss-Seidel sweeps before and after the coarse
-                            correction on every level; 0 -> 1                         */
+                            correction on every level; 0 -> 1; only 1 is supported
+                            (larger values return CDI_ERR_ARG)                        */
 } cdi_params;
 
 /* Device pointers of one instance's state, layouts as above (caller-owned,
@@ -189,7 +191,8 @@ cdi_status cdi_eval_rhs(cdi_ctx* ctx, double* l_phi, double* l_mx, double* l_my,
 /* Measurement hook.  While enabled, every launch of the named kernel family
  * ("phase_prep", "stage", "rhs", "pcg_init", "mg_down" (finest level, with the
  * fused CG update), "mg_down_other", "mg_coarse", "mg_up" (finest level),
- * "mg_up_other", "mg_coef", "pcg_spmv", "pcg_xmean", "project") is bracketed
+ * "mg_up_other", "mg_coef", "pcg_spmv", "pcg_xmean", "project", "net",
+ * "persistent") is bracketed
  * by HIP events on the context stream; NULL disables.  Resets the totals. */
 cdi_status cdi_timing_enable(cdi_ctx* ctx, const char* kernel);
 
@@ -249,6 +252,20 @@ const char* cdi_net_last_error(void);
  * its guess mode is CDI_GUESS_LEARNED; NULL detaches (the previous pressure
  * is then used).  The context borrows the network. */
 cdi_status cdi_guess_attach(cdi_ctx* ctx, cdi_net* net);
+
+/* How cdi_step enqueues the work of a step (same discretisation and solver
+ * either way; results agree to the solver tolerance, not bitwise, because
+ * the CG reductions are summed in a different order):
+ *   CDI_LAUNCH_TILED (default): every phase of the step is a launch over
+ *     tiles of every instance (many workgroups per instance); the host
+ *     checks the CG stopping test every few iterations.
+ *   CDI_LAUNCH_PERSISTENT: one launch per 32 steps with one workgroup of
+ *     1024 threads per instance running whole steps, CG loop and stopping
+ *     test included, with no host round trip (pays off for small grids and
+ *     ensembles of them).  Not available with CDI_GUESS_LEARNED and an
+ *     attached network (cdi_step then returns CDI_ERR_STATE). */
+cdi_status cdi_set_launch(cdi_ctx* ctx, int32_t mode);
+cdi_status cdi_get_launch(cdi_ctx* ctx, int32_t* mode);
 
 /* Switch the initial-guess mode (CDI_GUESS_*) of later pressure solves. */
 cdi_status cdi_set_guess(cdi_ctx* ctx, int32_t guess);

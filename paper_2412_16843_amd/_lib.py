@@ -18,13 +18,15 @@ STATUS = {0: "CDI_OK", -1: "CDI_ERR_ARG", -2: "CDI_ERR_SHAPE", -3: "CDI_ERR_DEVI
 SLIP = {"1A": 0, "1B": 1, "2A": 2, "2B": 3, "3A": 4, "3B": 5, "4A": 6, "4B": 7}
 CDI_FP64, CDI_MIXED = 0, 1
 GUESS = {"zero": 0, "prev": 1, "learned": 2}
+LAUNCH = {"tiled": 0, "persistent": 1}
 
 EXPORTS = ("cdi_workspace_bytes", "cdi_default_dt", "cdi_init", "cdi_init_batch", "cdi_step",
            "cdi_solve_pressure", "cdi_diagnostics", "cdi_eval_rhs", "cdi_timing_enable",
            "cdi_timing_read", "cdi_destroy", "cdi_last_error", "cdi_net_param_count",
            "cdi_net_workspace_bytes", "cdi_net_init", "cdi_net_repack", "cdi_net_forward",
            "cdi_net_backward", "cdi_net_adam", "cdi_net_destroy", "cdi_net_last_error",
-           "cdi_set_guess", "cdi_guess_attach", "cdi_guess_features")
+           "cdi_set_guess", "cdi_guess_attach", "cdi_guess_features", "cdi_set_launch",
+           "cdi_get_launch")
 
 
 class cdi_params(C.Structure):
@@ -121,6 +123,10 @@ def lib() -> C.CDLL:
     L.cdi_guess_attach.restype = i32
     L.cdi_guess_features.argtypes = [vp, i32, vp, vp]
     L.cdi_guess_features.restype = i32
+    L.cdi_set_launch.argtypes = [vp, i32]
+    L.cdi_set_launch.restype = i32
+    L.cdi_get_launch.argtypes = [vp, P(i32)]
+    L.cdi_get_launch.restype = i32
     L.cdi_destroy.argtypes = [vp]
     L.cdi_destroy.restype = None
     L.cdi_last_error.argtypes = []

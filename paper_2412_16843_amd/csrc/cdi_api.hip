@@ -13,7 +13,7 @@
 #include <vector>
 
 #include "../../include/cdi.h"
-#include "diag_kernels.h"
+#include "persistent_kernels.h"
 #include "net_internal.h"
 
 using namespace cdi;
@@ -86,6 +86,7 @@ cdi_status resolve(const cdi_params* in, Resolved& r) {
   if (p.precision != CDI_FP64 && p.precision != CDI_MIXED) return fail(CDI_ERR_ARG, "bad precision");
   if (p.guess < CDI_GUESS_ZERO || p.guess > CDI_GUESS_LEARNED) return fail(CDI_ERR_ARG, "bad guess");
   if (p.poisson_rtol < 0 || p.poisson_maxit < 0 || p.mg_smooth < 0) return fail(CDI_ERR_ARG, "bad solver limits");
+  if (p.mg_smooth > 1) return fail(CDI_ERR_ARG, "mg_smooth: one sweep before and after is supported");
   r.p = p;
   r.h = hx;
   r.dt = p.dt > 0 ? p.dt : cfl_dt(p, hx);
@@ -166,6 +167,8 @@ size_t carve(const Resolved& R, int ntiles_cell, int ntiles_mg0, char* base, siz
   D.d1 = (double*)take(nc * 8);
   D.q = (double*)take(nc * 8);
   D.zf = (double*)take(nc * 8);
+  D.mg_t = take(nc * S);
+  D.mg_r0 = take(nc * S);
   for (int k = 0; k < 4; ++k) D.ph[k] = (double*)take(nc * 8);
   for (int k = 0; k < 4; ++k) D.ph2[k] = (double*)take(nc * 8);
   D.part = (double*)take((size_t)8 * std::max(ntiles_cell, ntiles_mg0) * 8);
@@ -296,6 +299,7 @@ struct cdi_ctx {
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   cdi_net* net = nullptr;        // learned initial guess (borrowed)
   int hist_steps = 0;            // steps recorded in the per-stage pressure history
+  int launch = CDI_LAUNCH_TILED; // how cdi_step enqueues a step
   // measurement hook: events around every launch of one kernel family
   std::string timed;
   std::vector<hipEvent_t> tev;
@@ -477,6 +481,41 @@ cdi_status run_step(cdi_ctx* c) {
   return st;
 }
 
+// Steps of the persistent launch per kernel: bounds the duration of one
+// launch; the per-stage history carries over between launches.
+constexpr int kPersistChunk = 32;
+
+template <typename S>
+cdi_status run_persistent(cdi_ctx* c, int nsteps) {
+  Batch& B = c->B;
+  const int gm = c->guess == CDI_GUESS_ZERO ? 0 : 1;
+  for (int done = 0; done < nsteps; done += kPersistChunk) {
+    const int m = std::min(kPersistChunk, nsteps - done);
+    timed(c, "persistent", [&] {
+      k_step_persistent<S><<<(unsigned)B.n, PNT, 0, c->stream>>>(c->d_cell, c->d_inst, m,
+                                                                 c->hist_steps, gm, c->rtol,
+                                                                 c->maxit, done > 0);
+    });
+    HIPCHK(hipGetLastError());
+    c->hist_steps += m;
+  }
+  for (int k = 0; k < B.n; ++k)
+    HIPCHK(hipMemcpyAsync(c->h_pcg + k, B.inst[k].pcg, sizeof(PcgScalars), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  bool noconv = false;
+  int maxi = 0;
+  for (int k = 0; k < B.n; ++k) {
+    c->last_iters[k] = c->h_pcg[k].iters;
+    c->last_relres[k] = c->h_pcg[k].relres;
+    c->last_conv[k] = c->h_pcg[k].converged;
+    maxi = std::max(maxi, c->h_pcg[k].max_iters);
+    if (c->h_pcg[k].nfail) noconv = true;
+  }
+  c->pred_iters = std::max(1, maxi);
+  if (noconv) return fail(CDI_ERR_NOCONV, "pressure solve did not reach rtol within maxit");
+  return CDI_OK;
+}
+
 }  // namespace
 
 // ================================================================ C ABI
@@ -595,6 +634,15 @@ cdi_status cdi_step(cdi_ctx* c, int32_t nsteps) {
   if (!c) return fail(CDI_ERR_ARG, "ctx is NULL");
   if (nsteps < 0) return fail(CDI_ERR_ARG, "nsteps < 0");
   cdi_status st = CDI_OK;
+  if (c->launch == CDI_LAUNCH_PERSISTENT && nsteps > 0) {
+    if (c->guess == CDI_GUESS_LEARNED && c->net)
+      return fail(CDI_ERR_STATE, "the learned guess needs the tiled launch");
+    st = c->mixed ? run_persistent<float>(c, nsteps) : run_persistent<double>(c, nsteps);
+    if (st != CDI_OK && st != CDI_ERR_NOCONV) return st;
+    c->t += nsteps * c->B.R[0].dt;
+    c->step += nsteps;
+    return st;
+  }
   for (int s = 0; s < nsteps; ++s) {
     cdi_status r = c->mixed ? run_step<float>(c) : run_step<double>(c);
     if (r == CDI_ERR_NOCONV) st = r;
@@ -720,7 +768,7 @@ cdi_status cdi_timing_enable(cdi_ctx* c, const char* kernel) {
   if (!c) return fail(CDI_ERR_ARG, "ctx is NULL");
   static const char* known[] = {"phase_prep", "stage", "rhs", "pcg_init", "mg_down",
                                 "mg_down_other", "mg_coarse", "mg_up", "mg_up_other", "mg_coef",
-                                "pcg_spmv", "pcg_xmean", "project", "net"};
+                                "pcg_spmv", "pcg_xmean", "project", "net", "persistent"};
   HIPCHK(hipStreamSynchronize(c->stream));
   c->tev_used = 0;
   c->timed_ms = 0.0;
@@ -742,6 +790,20 @@ cdi_status cdi_timing_read(cdi_ctx* c, double* total_ms, int64_t* launches) {
   HIPCHK(timing_flush(c));
   *total_ms = c->timed_ms;
   *launches = c->timed_launches;
+  return CDI_OK;
+}
+
+cdi_status cdi_set_launch(cdi_ctx* c, int32_t mode) {
+  if (!c) return fail(CDI_ERR_ARG, "ctx is NULL");
+  if (mode != CDI_LAUNCH_TILED && mode != CDI_LAUNCH_PERSISTENT)
+    return fail(CDI_ERR_ARG, "bad launch mode %d", mode);
+  c->launch = mode;
+  return CDI_OK;
+}
+
+cdi_status cdi_get_launch(cdi_ctx* c, int32_t* mode) {
+  if (!c || !mode) return fail(CDI_ERR_ARG, "NULL argument");
+  *mode = c->launch;
   return CDI_OK;
 }
 

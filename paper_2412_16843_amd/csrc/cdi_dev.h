@@ -42,8 +42,11 @@ struct PcgScalars {
   int maxit;
   int first;                // 1 before the first direction is formed
   int converged;
+  int zero_rhs;             // 1 when the right-hand side vanished (p = 0)
+  int coef_ok;              // persistent path: coarse coefficients current
+  int nfail;                // persistent path: solves that stopped at maxit
+  int max_iters;            // persistent path: largest iteration count
   int pad;
-  int pad2;
 };
 
 struct Inst {
@@ -77,6 +80,8 @@ struct Inst {
   PcgScalars* pcg;
   unsigned* counters;                  // [8 kinds][kCounterStride] arrival counters
   Level lev[kMaxLevels];
+  void* mg_t;                          // S [ny*nx] residual scratch of the one-block V-cycle
+  void* mg_r0;                         // S [ny*nx] level-0 residual copy (mixed, one-block V-cycle)
   double* cinv;                        // dense inverse of the coarsest operator (n <= 64)
   int cdense;                          // 1 if cinv is used for the coarsest solve
   int pad_;

@@ -161,7 +161,7 @@ __global__ void __launch_bounds__(kNT) k_solve_setup(const Tile* __restrict__ ti
       const double n = (double)nx * ny;
       P->bmean = s / n;
       P->brms = sqrt(fmax(s2 / n - P->bmean * P->bmean, 0.0));
-      P->done = 0; P->iters = 0; P->first = 1; P->converged = 0; P->pad = 0;
+      P->done = 0; P->iters = 0; P->first = 1; P->converged = 0; P->zero_rhs = 0;
       P->rtol = rtol; P->maxit = maxit;
     }
   }
@@ -177,7 +177,7 @@ __global__ void __launch_bounds__(kNT) k_solve_out(const Tile* __restrict__ tile
   const int i = t.i0 + tx, j = t.j0 + ty;
   if (i >= nx || j >= ny) return;
   const size_t o = (size_t)j * nx + i;
-  const bool zero = I.pcg->pad != 0;
+  const bool zero = I.pcg->zero_rhs != 0;
   pout[o] = zero ? 0.0 : I.x[o] - I.pcg->xmean;
 }
 

@@ -39,6 +39,46 @@ static_assert(FX * FY == 2 * kNT, "MG tile = 2 cells per thread");
 // (tau given as a multiple of the instance time step), the FP64 face
 // coefficients of the pressure operator (and their S copy for the V-cycle),
 // and the instance's mean of b.  Resets the CG state.
+// Right-hand side and operator coefficients at cell (j, i); returns b.
+template <typename S>
+__device__ __forceinline__ double rhs_cell(const Inst& I, const double* __restrict__ ph, int j,
+                                           int i, double tau) {
+  const int nx = I.nx, ny = I.ny;
+  const size_t o = (size_t)j * nx + i;
+  const int ie = wrap(i + 1, nx), iw = wrap(i - 1, nx);
+  const double r1 = I.rho1, r2 = I.rho2;
+  const double rc = (r1 - r2) * ph[o] + r2;
+  const double rw = (r1 - r2) * ph[(size_t)j * nx + iw] + r2;
+  const double re = (r1 - r2) * ph[(size_t)j * nx + ie] + r2;
+  const double rfw = 0.5 * (rw + rc), rfe = 0.5 * (rc + re);
+  const double uw = I.mx[o] / rfw;
+  const double ue = I.mx[(size_t)j * nx + ie] / rfe;
+  double vs = 0.0, vn = 0.0, rfs = 0.0;
+  if (j >= 1) {
+    const double rs = (r1 - r2) * ph[o - nx] + r2;
+    rfs = 0.5 * (rs + rc);
+    vs = I.my[o] / rfs;
+  }
+  if (j + 1 <= ny - 1) {
+    const double rn = (r1 - r2) * ph[o + nx] + r2;
+    vn = I.my[o + nx] / (0.5 * (rc + rn));
+  }
+  const double b = ((ue - uw) + (vn - vs)) * I.inv_h / (tau * I.dt);
+  I.ustar[o] = uw;
+  I.vstar[o] = vs;
+  I.b[o] = b;
+  const double ih2 = I.inv_h * I.inv_h;
+  const double ax = ih2 / rfw;
+  const double ay = j >= 1 ? ih2 / rfs : 0.0;
+  I.ax0[o] = ax;
+  I.ay0[o] = ay;
+  if (I.mixed) {
+    ((S*)I.lev[0].ax)[o] = (S)ax;
+    ((S*)I.lev[0].ay)[o] = (S)ay;
+  }
+  return b;
+}
+
 template <typename S>
 __global__ void __launch_bounds__(kNT) k_rhs(const Tile* __restrict__ tiles,
                                               const Inst* __restrict__ insts, int src, double tau,
@@ -52,40 +92,9 @@ __global__ void __launch_bounds__(kNT) k_rhs(const Tile* __restrict__ tiles,
   const double* __restrict__ ph = src == 0 ? I.phi : (src == 1 ? I.phi_a : I.phi_b);
   double bsum[2] = {0.0, 0.0};
   if (i < nx && j < ny) {
-    const size_t o = (size_t)j * nx + i;
-    const int ie = wrap(i + 1, nx), iw = wrap(i - 1, nx);
-    const double r1 = I.rho1, r2 = I.rho2;
-    const double rc = (r1 - r2) * ph[o] + r2;
-    const double rw = (r1 - r2) * ph[(size_t)j * nx + iw] + r2;
-    const double re = (r1 - r2) * ph[(size_t)j * nx + ie] + r2;
-    const double rfw = 0.5 * (rw + rc), rfe = 0.5 * (rc + re);
-    const double uw = I.mx[o] / rfw;
-    const double ue = I.mx[(size_t)j * nx + ie] / rfe;
-    double vs = 0.0, vn = 0.0, rfs = 0.0;
-    if (j >= 1) {
-      const double rs = (r1 - r2) * ph[o - nx] + r2;
-      rfs = 0.5 * (rs + rc);
-      vs = I.my[o] / rfs;
-    }
-    if (j + 1 <= ny - 1) {
-      const double rn = (r1 - r2) * ph[o + nx] + r2;
-      vn = I.my[o + nx] / (0.5 * (rc + rn));
-    }
-    const double b = ((ue - uw) + (vn - vs)) * I.inv_h / (tau * I.dt);
-    I.ustar[o] = uw;
-    I.vstar[o] = vs;
-    I.b[o] = b;
+    const double b = rhs_cell<S>(I, ph, j, i, tau);
     bsum[0] = b;
     bsum[1] = b * b;
-    const double ih2 = I.inv_h * I.inv_h;
-    const double ax = ih2 / rfw;
-    const double ay = j >= 1 ? ih2 / rfs : 0.0;
-    I.ax0[o] = ax;
-    I.ay0[o] = ay;
-    if (I.mixed) {
-      ((S*)I.lev[0].ax)[o] = (S)ax;
-      ((S*)I.lev[0].ay)[o] = (S)ay;
-    }
   }
   block_sum<2>(bsum, sh);
   if (threadIdx.x == 0) {
@@ -100,7 +109,7 @@ __global__ void __launch_bounds__(kNT) k_rhs(const Tile* __restrict__ tiles,
       const double n = (double)nx * ny;
       P->bmean = s / n;
       P->brms = sqrt(fmax(s2 / n - P->bmean * P->bmean, 0.0));
-      P->done = 0; P->iters = 0; P->first = 1; P->converged = 0; P->pad = 0;
+      P->done = 0; P->iters = 0; P->first = 1; P->converged = 0; P->zero_rhs = 0;
       P->rtol = rtol; P->maxit = maxit;
     }
   }
@@ -133,6 +142,28 @@ __device__ __forceinline__ double guess_value(const Inst& I, int guess, int stag
   }
 }
 
+// f = -(b - mean b), x0 and r0 = f - K x0 at cell (j, i).
+__device__ __forceinline__ void pcg_init_cell(const Inst& I, int guess, int stage, int j, int i,
+                                              double bmean, double& f, double& r) {
+  const int nx = I.nx, ny = I.ny;
+  const size_t o = (size_t)j * nx + i;
+  f = -(I.b[o] - bmean);
+  r = f;
+  if (guess) {
+    const int ie = wrap(i + 1, nx), iw = wrap(i - 1, nx);
+    const double xc = guess_value(I, guess, stage, o);
+    double kx = I.ax0[o] * (xc - guess_value(I, guess, stage, (size_t)j * nx + iw)) +
+                I.ax0[(size_t)j * nx + ie] * (xc - guess_value(I, guess, stage, (size_t)j * nx + ie));
+    if (j >= 1) kx += I.ay0[o] * (xc - guess_value(I, guess, stage, o - nx));
+    if (j + 1 < ny) kx += I.ay0[o + nx] * (xc - guess_value(I, guess, stage, o + nx));
+    r = f - kx;
+    I.x[o] = xc;
+  } else {
+    I.x[o] = 0.0;
+  }
+  I.rr[o] = r;
+}
+
 __global__ void __launch_bounds__(kNT) k_pcg_init(const Tile* __restrict__ tiles,
                                                   const Inst* __restrict__ insts, int guess,
                                                   int stage) {
@@ -144,22 +175,8 @@ __global__ void __launch_bounds__(kNT) k_pcg_init(const Tile* __restrict__ tiles
   const int i = t.i0 + tx, j = t.j0 + ty;
   double s[2] = {0.0, 0.0};
   if (i < nx && j < ny) {
-    const size_t o = (size_t)j * nx + i;
-    const double f = -(I.b[o] - I.pcg->bmean);
-    double r = f;
-    if (guess) {
-      const int ie = wrap(i + 1, nx), iw = wrap(i - 1, nx);
-      const double xc = guess_value(I, guess, stage, o);
-      double kx = I.ax0[o] * (xc - guess_value(I, guess, stage, (size_t)j * nx + iw)) +
-                  I.ax0[(size_t)j * nx + ie] * (xc - guess_value(I, guess, stage, (size_t)j * nx + ie));
-      if (j >= 1) kx += I.ay0[o] * (xc - guess_value(I, guess, stage, o - nx));
-      if (j + 1 < ny) kx += I.ay0[o + nx] * (xc - guess_value(I, guess, stage, o + nx));
-      r = f - kx;
-      I.x[o] = xc;
-    } else {
-      I.x[o] = 0.0;
-    }
-    I.rr[o] = r;
+    double f, r;
+    pcg_init_cell(I, guess, stage, j, i, I.pcg->bmean, f, r);
     s[0] = f * f;
     s[1] = r * r;
   }
@@ -176,7 +193,7 @@ __global__ void __launch_bounds__(kNT) k_pcg_init(const Tile* __restrict__ tiles
       P->fnorm = sqrt(ff);
       P->rr = rr;
       if (ff == 0.0) {          // b = 0: the mean-free solution is p = 0
-        P->relres = 0.0; P->done = 1; P->converged = 1; P->pad = 1;
+        P->relres = 0.0; P->done = 1; P->converged = 1; P->zero_rhs = 1;
       } else {
         P->relres = sqrt(rr) / P->fnorm;
         if (P->relres <= P->rtol) { P->done = 1; P->converged = 1; }
@@ -312,17 +329,11 @@ __global__ void __launch_bounds__(kNT) k_pcg_xmean(const Tile* __restrict__ tile
 // instance time step); the pressure is stored mean-free.  final_stage: the
 // result is the new state (caller fields) and the new phase field is copied
 // from phi_next.
-__global__ void __launch_bounds__(kNT) k_project(const Tile* __restrict__ tiles,
-                                                 const Inst* __restrict__ insts, double tau,
-                                                 int final_stage, int src, int stage) {
-  const Tile t = tiles[blockIdx.x];
-  const Inst& I = insts[t.inst];
-  const int nx = I.nx, ny = I.ny;
-  const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
-  const int i = t.i0 + tx, j = t.j0 + ty;
-  if (i >= nx || j >= ny) return;
+__device__ __forceinline__ void project_cell(const Inst& I, double tau, int final_stage,
+                                             const double* __restrict__ ph, int stage, bool zero,
+                                             double xmean, int j, int i) {
+  const int nx = I.nx;
   const size_t o = (size_t)j * nx + i;
-  const bool zero = I.pcg->pad != 0;
   const double* __restrict__ x = I.x;
   const double xc = zero ? 0.0 : x[o];
   const double xw = zero ? 0.0 : x[(size_t)j * nx + wrap(i - 1, nx)];
@@ -336,16 +347,26 @@ __global__ void __launch_bounds__(kNT) k_project(const Tile* __restrict__ tiles,
   } else {
     vo[o] = 0.0;
   }
-  const double pn = xc - (zero ? 0.0 : I.pcg->xmean);
+  const double pn = xc - (zero ? 0.0 : xmean);
   I.p[o] = pn;
   if (stage >= 0) {   // pressure history of this RK stage (for the next step's guess)
     I.ph2[stage][o] = I.ph[stage][o];
     I.ph[stage][o] = pn;
   }
-  if (final_stage) {
-    const double* __restrict__ ph = src == 1 ? I.phi_a : I.phi_b;
-    I.phi[o] = ph[o];
-  }
+  if (final_stage) I.phi[o] = ph[o];
+}
+
+__global__ void __launch_bounds__(kNT) k_project(const Tile* __restrict__ tiles,
+                                                 const Inst* __restrict__ insts, double tau,
+                                                 int final_stage, int src, int stage) {
+  const Tile t = tiles[blockIdx.x];
+  const Inst& I = insts[t.inst];
+  const int nx = I.nx, ny = I.ny;
+  const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+  const int i = t.i0 + tx, j = t.j0 + ty;
+  if (i >= nx || j >= ny) return;
+  const double* __restrict__ ph = src == 1 ? I.phi_a : I.phi_b;
+  project_cell(I, tau, final_stage, ph, stage, I.pcg->zero_rhs != 0, I.pcg->xmean, j, i);
 }
 
 // ================================================================ multigrid
@@ -608,75 +629,38 @@ __global__ void __launch_bounds__(kNT) k_mg_up(const Tile* __restrict__ tiles,
   }
 }
 
-// ------------------------------------------------ single-block coarse cycle
-// Every level from lc down lives in LDS (coefficients, right-hand side,
-// correction, scratch).  With lc == 0 the block holds the whole problem and
-// also applies the CG update, the stopping test and beta.
+// ------------------------------------------------------------ V-cycle core
+// One level as the cycle code sees it: coefficients, right-hand side,
+// correction and a residual scratch of the level's size, each in global
+// memory or in LDS.
 template <typename S>
-__global__ void __launch_bounds__(kCoarseNT) k_mg_coarse(const Inst* __restrict__ insts,
-                                                          int update, int parity, int rsel) {
-  __shared__ S s_ax[kCLX], s_ay[kCLY], s_r[kCLX], s_z[kCLX], s_t[kCLX];
-  __shared__ double s_red[2 * kCoarseNT / 64];
-  __shared__ double s_sc[4];
-  const Inst& I = insts[blockIdx.x];
-  if (I.pcg->done) return;
-  const int lc = I.lc, nl = I.nlev;
-  int oc[kMaxLevels], oy[kMaxLevels];
-  {
-    int a = 0, b = 0;
-    for (int l = lc; l < nl; ++l) {
-      oc[l] = a; oy[l] = b;
-      a += I.lev[l].nx * I.lev[l].ny;
-      b += (I.lev[l].ny + 1) * I.lev[l].nx;
-    }
-  }
+struct MgView {
+  const S* ax;
+  const S* ay;
+  S* r;
+  S* z;
+  S* t;
+  int nx, ny;
+};
+
+// V-cycle on levels lo..nl-1 of instance I by one block of kCoarseNT threads:
+// pre-smoothing from zero (red z = r/D, black Gauss-Seidel), residual,
+// restriction R = P^T/4 down to the coarsest level, its exact (mean-free)
+// solve, then prolongation and post-smoothing (black, red) back up.  On
+// return V(lo).z holds the correction; V(lo).r is not modified.  V(l)
+// returns the view of level l (a functor, so that views into LDS keep their
+// address space after inlining).
+template <typename S, typename ViewF>
+__device__ __forceinline__ void mg_cycle(const Inst& I, const ViewF& V, int lo, int nl,
+                                         double* s_red, double* s_sc) {
   const int tid = threadIdx.x;
-  // ---- CG update when the whole grid is coarse
-  if (lc == 0 && update) {
-    const Level& L0 = I.lev[0];
-    const int n = L0.nx * L0.ny;
-    const double alpha = I.pcg->alpha;
-    const double* __restrict__ d = parity ? I.d1 : I.d0;
-    const double* __restrict__ rin = rsel ? I.rr : I.rr2;
-    double* __restrict__ rout = rsel ? I.rr2 : I.rr;
-    double red[2] = {0.0, 0.0};
-    for (int c = tid; c < n; c += kCoarseNT) {
-      const double x = I.x[c] + alpha * d[c];
-      const double r = rin[c] - alpha * I.q[c];
-      I.x[c] = x;
-      rout[c] = r;
-      red[0] += r * r;
-      red[1] += x;
-    }
-    block_sum<2, kCoarseNT>(red, s_red);
-    if (tid == 0) {
-      pcg_stop_test(I.pcg, red[0], red[1], (double)n);
-      s_sc[0] = I.pcg->done;
-    }
-    __syncthreads();
-    if (s_sc[0] != 0.0) return;
-  }
-  // ---- load the coarse hierarchy
-  for (int l = lc; l < nl; ++l) {
-    const Level& L = I.lev[l];
-    const int n = L.nx * L.ny, nf = (L.ny + 1) * L.nx;
-    for (int c = tid; c < n; c += kCoarseNT) s_ax[oc[l] + c] = ((const S*)L.ax)[c];
-    for (int c = tid; c < nf; c += kCoarseNT) s_ay[oy[l] + c] = ((const S*)L.ay)[c];
-  }
-  {
-    const Level& L = I.lev[lc];
-    const int n = L.nx * L.ny;
-    for (int c = tid; c < n; c += kCoarseNT)
-      s_r[oc[lc] + c] = lc == 0 ? (S)(rsel ? I.rr2 : I.rr)[c] : ((const S*)L.r)[c];
-  }
-  __syncthreads();
-  // level helpers (LDS)
   auto sweep = [&](int l, int color, bool from_zero) {
-    const int nx = I.lev[l].nx, ny = I.lev[l].ny;
-    const S* ax = s_ax + oc[l];
-    const S* ay = s_ay + oy[l];
-    const S* r = s_r + oc[l];
-    S* z = s_z + oc[l];
+    const MgView<S> Lv = V(l);
+    const int nx = Lv.nx, ny = Lv.ny;
+    const S* ax = Lv.ax;
+    const S* ay = Lv.ay;
+    const S* r = Lv.r;
+    S* z = Lv.z;
     for (int c = tid; c < nx * ny; c += kCoarseNT) {
       const int j = c / nx, i = c - j * nx;
       if (((i + j) & 1) != color) continue;
@@ -691,17 +675,19 @@ __global__ void __launch_bounds__(kCoarseNT) k_mg_coarse(const Inst* __restrict_
     }
   };
   // ---- down
-  for (int l = lc; l < nl - 1; ++l) {
-    const int nx = I.lev[l].nx, ny = I.lev[l].ny;
+  for (int l = lo; l < nl - 1; ++l) {
+    const MgView<S> Lv = V(l), Cv = V(l + 1);
+    const int nx = Lv.nx, ny = Lv.ny;
     sweep(l, 0, true);
     __syncthreads();
     sweep(l, 1, false);
     __syncthreads();
     {
-      const S* ax = s_ax + oc[l];
-      const S* ay = s_ay + oy[l];
-      const S* r = s_r + oc[l];
-      const S* z = s_z + oc[l];
+      const S* ax = Lv.ax;
+      const S* ay = Lv.ay;
+      const S* r = Lv.r;
+      const S* z = Lv.z;
+      S* t = Lv.t;
       for (int c = tid; c < nx * ny; c += kCoarseNT) {
         const int j = c / nx, i = c - j * nx;
         const int ie = wrap(i + 1, nx), iw = wrap(i - 1, nx);
@@ -709,13 +695,14 @@ __global__ void __launch_bounds__(kCoarseNT) k_mg_coarse(const Inst* __restrict_
         S kz = ax[c] * (zc - z[j * nx + iw]) + ax[j * nx + ie] * (zc - z[j * nx + ie]);
         if (j >= 1) kz += ay[c] * (zc - z[c - nx]);
         if (j + 1 < ny) kz += ay[c + nx] * (zc - z[c + nx]);
-        s_t[c] = r[c] - kz;
+        t[c] = r[c] - kz;
       }
     }
     __syncthreads();
     {
-      const int cnx = I.lev[l + 1].nx, cny = I.lev[l + 1].ny;
-      S* rc = s_r + oc[l + 1];
+      const int cnx = Cv.nx, cny = Cv.ny;
+      const S* t = Lv.t;
+      S* rc = Cv.r;
       for (int c = tid; c < cnx * cny; c += kCoarseNT) {
         const int J = c / cnx, Ic = c - J * cnx;
         S wy[4] = {S(0.25), S(0.75), S(0.75), S(0.25)};
@@ -727,7 +714,7 @@ __global__ void __launch_bounds__(kCoarseNT) k_mg_coarse(const Inst* __restrict_
           if (wy[dy] == S(0)) continue;
           const int j = 2 * J - 1 + dy;
           S row = 0;
-          for (int dx = 0; dx < 4; ++dx) row += wx[dx] * s_t[j * nx + wrap(2 * Ic - 1 + dx, nx)];
+          for (int dx = 0; dx < 4; ++dx) row += wx[dx] * t[j * nx + wrap(2 * Ic - 1 + dx, nx)];
           acc += wy[dy] * row;
         }
         rc[c] = S(0.25) * acc;
@@ -737,10 +724,10 @@ __global__ void __launch_bounds__(kCoarseNT) k_mg_coarse(const Inst* __restrict_
   }
   // ---- coarsest level: exact solve (mean-free part)
   {
-    const Level& L = I.lev[nl - 1];
+    const MgView<S> L = V(nl - 1);
     const int nx = L.nx, ny = L.ny, n = nx * ny;
-    const S* r = s_r + oc[nl - 1];
-    S* z = s_z + oc[nl - 1];
+    const S* r = L.r;
+    S* z = L.z;
     if (I.cdense) {
       // z = M r with 16 lanes per row (n <= 64 rows x 16 = 1024 threads)
       const int row = tid >> 4, part = tid & 15;
@@ -754,23 +741,21 @@ __global__ void __launch_bounds__(kCoarseNT) k_mg_coarse(const Inst* __restrict_
       if (row < n && part == 0) z[row] = (S)acc;
       __syncthreads();
     } else {
-      // CG in LDS scratch (FP64 values kept in the S arrays' spare room is not
-      // possible for float, so the CG runs on s_t / s_z with an FP64 recurrence)
-      const S* ax = s_ax + oc[nl - 1];
-      const S* ay = s_ay + oy[nl - 1];
+      // CG with one cell per thread (n <= kCoarseNT) and an FP64 recurrence;
+      // the direction is shared through the level's scratch
+      const S* ax = L.ax;
+      const S* ay = L.ay;
       double m[1] = {0.0};
       for (int c = tid; c < n; c += kCoarseNT) m[0] += (double)r[c];
       block_sum<1, kCoarseNT>(m, s_red);
       if (tid == 0) s_sc[0] = m[0] / n;
       __syncthreads();
       const double mean = s_sc[0];
-      // x in z, residual in s_t (first n), direction in s_t + n, K p in s_ax spare: use
-      // per-thread registers for up to kCoarseNT cells (n <= 1024 = kCoarseNT)
       const int c = tid;
       const bool own = c < n;
       const int j = own ? c / nx : 0, i = own ? c - j * nx : 0;
       double xr = 0.0, rr = own ? (double)r[c] - mean : 0.0, pr = rr;
-      S* pbuf = s_t;   // direction shared through LDS
+      S* pbuf = L.t;
       double rho[1] = {rr * rr};
       block_sum<1, kCoarseNT>(rho, s_red);
       if (tid == 0) s_sc[1] = rho[0];
@@ -809,11 +794,12 @@ __global__ void __launch_bounds__(kCoarseNT) k_mg_coarse(const Inst* __restrict_
     }
   }
   // ---- up: prolong, post-smooth (black, red)
-  for (int l = nl - 2; l >= lc; --l) {
-    const int nx = I.lev[l].nx, ny = I.lev[l].ny;
-    const int cnx = I.lev[l + 1].nx, cny = I.lev[l + 1].ny;
-    S* z = s_z + oc[l];
-    const S* e = s_z + oc[l + 1];
+  for (int l = nl - 2; l >= lo; --l) {
+    const MgView<S> Lv = V(l), Cv = V(l + 1);
+    const int nx = Lv.nx, ny = Lv.ny;
+    const int cnx = Cv.nx, cny = Cv.ny;
+    S* z = Lv.z;
+    const S* e = Cv.z;
     for (int c = tid; c < nx * ny; c += kCoarseNT) {
       const int j = c / nx, i = c - j * nx;
       z[c] += prolong<S>(e, cnx, cny, j, i);
@@ -824,11 +810,96 @@ __global__ void __launch_bounds__(kCoarseNT) k_mg_coarse(const Inst* __restrict_
     sweep(l, 0, false);
     __syncthreads();
   }
+}
+
+// LDS of the single-block cycle over the coarse levels lc..nl-1.
+template <typename S>
+struct CoarseLds {
+  S ax[kCLX], ay[kCLY], r[kCLX], z[kCLX], t[kCLX];
+  double red[2 * kCoarseNT / 64];
+  double sc[4];
+};
+
+// View of coarse level l (lc <= l < nl) inside the CoarseLds arrays; the
+// levels are stored one after the other from lc.
+template <typename S>
+__device__ __forceinline__ MgView<S> coarse_view(const Inst& I, CoarseLds<S>& C, int l) {
+  int a = 0, b = 0;
+  for (int m = I.lc; m < l; ++m) {
+    a += I.lev[m].nx * I.lev[m].ny;
+    b += (I.lev[m].ny + 1) * I.lev[m].nx;
+  }
+  MgView<S> v;
+  v.nx = I.lev[l].nx; v.ny = I.lev[l].ny;
+  v.ax = C.ax + a; v.ay = C.ay + b;
+  v.r = C.r + a; v.z = C.z + a; v.t = C.t;
+  return v;
+}
+
+// Load the coefficients of levels lc..nl-1 into LDS.
+template <typename S>
+__device__ __forceinline__ void coarse_load_coef(const Inst& I, CoarseLds<S>& C) {
+  for (int l = I.lc; l < I.nlev; ++l) {
+    const Level& L = I.lev[l];
+    const int n = L.nx * L.ny, nf = (L.ny + 1) * L.nx;
+    const MgView<S> v = coarse_view<S>(I, C, l);
+    for (int c = threadIdx.x; c < n; c += kCoarseNT) ((S*)v.ax)[c] = ((const S*)L.ax)[c];
+    for (int c = threadIdx.x; c < nf; c += kCoarseNT) ((S*)v.ay)[c] = ((const S*)L.ay)[c];
+  }
+}
+
+// ------------------------------------------------ single-block coarse cycle
+// Every level from lc down lives in LDS (coefficients, right-hand side,
+// correction, scratch).  With lc == 0 the block holds the whole problem and
+// also applies the CG update, the stopping test and beta.
+template <typename S>
+__global__ void __launch_bounds__(kCoarseNT) k_mg_coarse(const Inst* __restrict__ insts,
+                                                          int update, int parity, int rsel) {
+  __shared__ CoarseLds<S> C;
+  const Inst& I = insts[blockIdx.x];
+  if (I.pcg->done) return;
+  const int lc = I.lc, nl = I.nlev;
+  const int tid = threadIdx.x;
+  // ---- CG update when the whole grid is coarse
+  if (lc == 0 && update) {
+    const Level& L0 = I.lev[0];
+    const int n = L0.nx * L0.ny;
+    const double alpha = I.pcg->alpha;
+    const double* __restrict__ d = parity ? I.d1 : I.d0;
+    const double* __restrict__ rin = rsel ? I.rr : I.rr2;
+    double* __restrict__ rout = rsel ? I.rr2 : I.rr;
+    double red[2] = {0.0, 0.0};
+    for (int c = tid; c < n; c += kCoarseNT) {
+      const double x = I.x[c] + alpha * d[c];
+      const double r = rin[c] - alpha * I.q[c];
+      I.x[c] = x;
+      rout[c] = r;
+      red[0] += r * r;
+      red[1] += x;
+    }
+    block_sum<2, kCoarseNT>(red, C.red);
+    if (tid == 0) {
+      pcg_stop_test(I.pcg, red[0], red[1], (double)n);
+      C.sc[0] = I.pcg->done;
+    }
+    __syncthreads();
+    if (C.sc[0] != 0.0) return;
+  }
+  coarse_load_coef<S>(I, C);
+  {
+    const Level& L = I.lev[lc];
+    const int n = L.nx * L.ny;
+    S* r = coarse_view<S>(I, C, lc).r;
+    for (int c = tid; c < n; c += kCoarseNT)
+      r[c] = lc == 0 ? (S)(rsel ? I.rr2 : I.rr)[c] : ((const S*)L.r)[c];
+  }
+  __syncthreads();
+  mg_cycle<S>(I, [&](int l) { return coarse_view<S>(I, C, l); }, lc, nl, C.red, C.sc);
   // ---- publish the level-lc correction (and beta when it is level 0)
   {
     const Level& L = I.lev[lc];
     const int n = L.nx * L.ny;
-    const S* z = s_z + oc[lc];
+    const S* z = coarse_view<S>(I, C, lc).z;
     if (lc > 0) {
       for (int c = tid; c < n; c += kCoarseNT) ((S*)L.z)[c] = z[c];
     } else {
@@ -838,7 +909,7 @@ __global__ void __launch_bounds__(kCoarseNT) k_mg_coarse(const Inst* __restrict_
         I.zf[c] = zz;
         zq[0] += zz * I.q[c];
       }
-      block_sum<1, kCoarseNT>(zq, s_red);
+      block_sum<1, kCoarseNT>(zq, C.red);
       if (tid == 0) {
         PcgScalars* P = I.pcg;
         P->zq = zq[0];
@@ -852,8 +923,7 @@ __global__ void __launch_bounds__(kCoarseNT) k_mg_coarse(const Inst* __restrict_
 // the mean of the 2^l fine faces covering a coarse face, times 4^-l (each
 // halving doubles h); identical to averaging pairs level by level.
 template <typename S>
-__global__ void __launch_bounds__(kNT) k_mg_coef(const Inst* __restrict__ insts) {
-  const Inst& I = insts[blockIdx.y];
+__device__ __forceinline__ void mg_coef_levels(const Inst& I, int start, int stride) {
   const Level& F = I.lev[0];
   const S* fax = (const S*)F.ax;
   const S* fay = (const S*)F.ay;
@@ -862,7 +932,7 @@ __global__ void __launch_bounds__(kNT) k_mg_coef(const Inst* __restrict__ insts)
     const int m = 1 << l;
     const S scale = S(1.0 / ((double)m * m * m));   // mean over m faces times 4^-l
     const int n = C.nx * (C.ny + 1);
-    for (int c = blockIdx.x * kNT + threadIdx.x; c < n; c += gridDim.x * kNT) {
+    for (int c = start; c < n; c += stride) {
       const int J = c / C.nx, Ic = c - J * C.nx;
       if (J < C.ny) {
         S a = 0;
@@ -877,15 +947,18 @@ __global__ void __launch_bounds__(kNT) k_mg_coef(const Inst* __restrict__ insts)
   }
 }
 
+template <typename S>
+__global__ void __launch_bounds__(kNT) k_mg_coef(const Inst* __restrict__ insts) {
+  mg_coef_levels<S>(insts[blockIdx.y], blockIdx.x * kNT + threadIdx.x, gridDim.x * kNT);
+}
+
 // Dense inverse of the coarsest operator K_c + s 11^T / n (s its mean
 // diagonal): symmetric positive definite, inverted in LDS by Gauss-Jordan
 // without pivoting.  For a mean-free right-hand side the product is the
 // mean-free solution of K_c z = r.
 template <typename S>
-__global__ void __launch_bounds__(kCoarseNT) k_coarse_inv(const Inst* __restrict__ insts) {
-  __shared__ double B[kDenseMax * kDenseMax];
-  __shared__ double s_red[kCoarseNT / 64];
-  const Inst& I = insts[blockIdx.x];
+__device__ __forceinline__ void coarse_inverse(const Inst& I, double* B, double* s_red,
+                                               double* s_shift_slot) {
   if (!I.cdense) return;
   const Level& L = I.lev[I.nlev - 1];
   const int nx = L.nx, ny = L.ny, n = nx * ny;
@@ -908,10 +981,10 @@ __global__ void __launch_bounds__(kCoarseNT) k_coarse_inv(const Inst* __restrict
     dsum[0] += d;
   }
   block_sum<1, kCoarseNT>(dsum, s_red);
-  __shared__ double s_shift;
-  if (tid == 0) s_shift = dsum[0] / n / n;
+  if (tid == 0) *s_shift_slot = dsum[0] / n / n;
   __syncthreads();
-  for (int k = tid; k < n * n; k += kCoarseNT) B[k] += s_shift;
+  const double shift = *s_shift_slot;
+  for (int k = tid; k < n * n; k += kCoarseNT) B[k] += shift;
   __syncthreads();
   constexpr int PER = (kDenseMax * kDenseMax + kCoarseNT - 1) / kCoarseNT;
   for (int k = 0; k < n; ++k) {
@@ -933,6 +1006,13 @@ __global__ void __launch_bounds__(kCoarseNT) k_coarse_inv(const Inst* __restrict
     __syncthreads();
   }
   for (int k = tid; k < n * n; k += kCoarseNT) I.cinv[k] = B[k];
+}
+
+template <typename S>
+__global__ void __launch_bounds__(kCoarseNT) k_coarse_inv(const Inst* __restrict__ insts) {
+  __shared__ double B[kDenseMax * kDenseMax];
+  __shared__ double s_red[kCoarseNT / 64 + 1];
+  coarse_inverse<S>(insts[blockIdx.x], B, s_red, s_red + kCoarseNT / 64);
 }
 
 }  // namespace cdi

@@ -88,17 +88,25 @@ __device__ __forceinline__ T d2dy2_cell(const T* q, int stride, int j, int ny, T
 // chemical potential) with one-sided rows at the walls (Sec. 4); the wall
 // rows also publish the extrapolated wall quantities of the slip models.
 // src: 0 caller phi, 1 phi_a, 2 phi_b.
+constexpr int PRY = TY + 6, PRX = TX + 2;   // rows j0-3 .. j0+TY+2, cols i0-1 .. i0+TX
 template <typename S>
-__global__ void __launch_bounds__(kNT) k_phase_prep(const Tile* __restrict__ tiles,
-                                                     const Inst* __restrict__ insts, int src) {
-  constexpr int RY = TY + 6, RX = TX + 2;   // rows j0-3 .. j0+TY+2, cols i0-1 .. i0+TX
-  __shared__ double s_phi[RY * RX];
-  __shared__ S s_psi[RY * RX];
-  const Tile t = tiles[blockIdx.x];
-  const Inst& I = insts[t.inst];
+struct PrepLds {
+  double phi[PRY * PRX];
+  S psi[PRY * PRX];
+};
+
+// One tile of the phase preparation, run by kNT threads (tid in [0, kNT)).
+// Contains one block barrier: every thread of the block calls it, with
+// active = false for threads that have no tile in this round.
+template <typename S>
+__device__ __forceinline__ void phase_prep_tile(const Tile& t, const Inst& I, int src,
+                                                PrepLds<S>& L, int tid, bool active) {
+  constexpr int RY = PRY, RX = PRX;
+  double* s_phi = L.phi;
+  S* s_psi = L.psi;
   const int nx = I.nx, ny = I.ny;
   const double* __restrict__ phi = src == 0 ? I.phi : (src == 1 ? I.phi_a : I.phi_b);
-  for (int k = threadIdx.x; k < RY * RX; k += kNT) {
+  for (int k = tid; active && k < RY * RX; k += kNT) {
     const int rj = k / RX, ri = k - rj * RX;
     const int j = t.j0 - 3 + rj, i = wrap(t.i0 - 1 + ri, nx);
     double f = 0.0, ps = 0.0;
@@ -111,7 +119,8 @@ __global__ void __launch_bounds__(kNT) k_phase_prep(const Tile* __restrict__ til
     s_psi[k] = (S)ps;
   }
   __syncthreads();
-  const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+  if (!active) return;
+  const int tx = tid % TX, ty = tid / TX;
   const int i = t.i0 + tx, j = t.j0 + ty;
   if (i >= nx || j >= ny) return;
   const int c = (ty + 3) * RX + (tx + 1);
@@ -178,6 +187,14 @@ __global__ void __launch_bounds__(kNT) k_phase_prep(const Tile* __restrict__ til
   }
 }
 
+template <typename S>
+__global__ void __launch_bounds__(kNT) k_phase_prep(const Tile* __restrict__ tiles,
+                                                     const Inst* __restrict__ insts, int src) {
+  __shared__ PrepLds<S> L;
+  const Tile t = tiles[blockIdx.x];
+  phase_prep_tile<S>(t, insts[t.inst], src, L, threadIdx.x, true);
+}
+
 // ------------------------------------------------------------ stage operator
 // One RK4 stage: CDI face fluxes F = u phi_f - gamma[eps dphi/h - phi_f(1-phi_f) n_f]
 // (eq. CDI; wall y-faces F = 0 by the no-flux and no-penetration BCs), the
@@ -190,23 +207,36 @@ __global__ void __launch_bounds__(kNT) k_phase_prep(const Tile* __restrict__ til
 // k: stage index 0..3 (k < 0: evaluate the operator only); src/dst:
 // phase-field buffers (0 caller, 1 phi_a, 2 phi_b); c_next = RK c_{k+1}
 // (multiplied by each instance's dt), b_k the RK4 weight of stage k.
-template <typename S>
-__global__ void __launch_bounds__(kNT) k_stage(const Tile* __restrict__ tiles,
-                                                const Inst* __restrict__ insts, int k, int src,
-                                                int dst, double c_next, double b_k, int write_wall) {
-  constexpr int CY = TY + 3, CX = TX + 3;   // cells: rows j0-2..j0+TY, cols i0-2..i0+TX
-  constexpr int UY = TY + 2, UX = TX + 2;   // u/v: rows j0-1..j0+TY, cols i0-1..i0+TX
-  constexpr int XY = TY + 1, XX = TX + 2;   // x-faces: rows j0-1..j0+TY-1, cols i0-1..i0+TX
-  constexpr int YY = TY + 2, YX = TX + 1;   // y-faces: rows j0-1..j0+TY, cols i0-1..i0+TX-1
-  constexpr int CRY = TY + 1, CRX = TX + 1; // corners: rows j0..j0+TY, cols i0..i0+TX
-  __shared__ S s_phi[CY * CX], s_nx[CY * CX], s_ny[CY * CX], s_mc[CY * CX];
-  __shared__ S s_u[UY * UX], s_v[UY * UX];
-  __shared__ S s_fx[XY * XX], s_mx[XY * XX];
-  __shared__ S s_fy[YY * YX], s_my[YY * YX];
-  __shared__ S s_txy[CRY * CRX];
+namespace st {
+constexpr int CY = TY + 3, CX = TX + 3;   // cells: rows j0-2..j0+TY, cols i0-2..i0+TX
+constexpr int UY = TY + 2, UX = TX + 2;   // u/v: rows j0-1..j0+TY, cols i0-1..i0+TX
+constexpr int XY = TY + 1, XX = TX + 2;   // x-faces: rows j0-1..j0+TY-1, cols i0-1..i0+TX
+constexpr int YY = TY + 2, YX = TX + 1;   // y-faces: rows j0-1..j0+TY, cols i0-1..i0+TX-1
+constexpr int CRY = TY + 1, CRX = TX + 1; // corners: rows j0..j0+TY, cols i0..i0+TX
+}  // namespace st
 
-  const Tile t = tiles[blockIdx.x];
-  const Inst& I = insts[t.inst];
+template <typename S>
+struct StageLds {
+  S phi[st::CY * st::CX], nx[st::CY * st::CX], ny[st::CY * st::CX], mc[st::CY * st::CX];
+  S u[st::UY * st::UX], v[st::UY * st::UX];
+  S fx[st::XY * st::XX], mx[st::XY * st::XX];
+  S fy[st::YY * st::YX], my[st::YY * st::YX];
+  S txy[st::CRY * st::CRX];
+};
+
+// One tile of the stage operator, run by kNT threads (tid in [0, kNT)).
+// Contains two block barriers: every thread of the block calls it, with
+// active = false for threads that have no tile in this round.
+template <typename S>
+__device__ __forceinline__ void stage_tile(const Tile& t, const Inst& I, int k, int src, int dst,
+                                           double c_next, double b_k, int write_wall,
+                                           StageLds<S>& L, int tid, bool active) {
+  using namespace st;
+  S* s_phi = L.phi; S* s_nx = L.nx; S* s_ny = L.ny; S* s_mc = L.mc;
+  S* s_u = L.u; S* s_v = L.v;
+  S* s_fx = L.fx; S* s_mx = L.mx;
+  S* s_fy = L.fy; S* s_my = L.my;
+  S* s_txy = L.txy;
   const int nx = I.nx, ny = I.ny;
   const int i0 = t.i0, j0 = t.j0;
   const double* __restrict__ phs = src == 0 ? I.phi : (src == 1 ? I.phi_a : I.phi_b);
@@ -216,7 +246,7 @@ __global__ void __launch_bounds__(kNT) k_stage(const Tile* __restrict__ tiles,
   const S* __restrict__ gny = (const S*)I.nhy;
   const S* __restrict__ gmc = (const S*)I.muc;
 
-  for (int q = threadIdx.x; q < CY * CX; q += kNT) {
+  for (int q = tid; active && q < CY * CX; q += kNT) {
     const int rj = q / CX, ri = q - rj * CX;
     const int j = j0 - 2 + rj, i = wrap(i0 - 2 + ri, nx);
     S a = 0, b = 0, c = 0, d = 0;
@@ -226,7 +256,7 @@ __global__ void __launch_bounds__(kNT) k_stage(const Tile* __restrict__ tiles,
     }
     s_phi[q] = a; s_nx[q] = b; s_ny[q] = c; s_mc[q] = d;
   }
-  for (int q = threadIdx.x; q < UY * UX; q += kNT) {
+  for (int q = tid; active && q < UY * UX; q += kNT) {
     const int rj = q / UX, ri = q - rj * UX;
     const int j = j0 - 1 + rj, i = wrap(i0 - 1 + ri, nx);
     s_u[q] = (j >= 0 && j < ny) ? (S)us[(size_t)j * nx + i] : S(0);
@@ -236,7 +266,7 @@ __global__ void __launch_bounds__(kNT) k_stage(const Tile* __restrict__ tiles,
   const S gam = (S)I.gamma, eps = (S)I.eps, inv_h = (S)I.inv_h;
   const S drho = (S)(I.rho1 - I.rho2), rho2 = (S)I.rho2;
   // x-face fluxes (each face computed once per block by this one code path)
-  for (int q = threadIdx.x; q < XY * XX; q += kNT) {
+  for (int q = tid; active && q < XY * XX; q += kNT) {
     const int rj = q / XX, ri = q - rj * XX;
     const int j = j0 - 1 + rj;
     S F = 0, m = 0;
@@ -254,7 +284,7 @@ __global__ void __launch_bounds__(kNT) k_stage(const Tile* __restrict__ tiles,
     s_fx[q] = F; s_mx[q] = m;
   }
   // y-face fluxes; wall faces carry no flux
-  for (int q = threadIdx.x; q < YY * YX; q += kNT) {
+  for (int q = tid; active && q < YY * YX; q += kNT) {
     const int rj = q / YX, ri = q - rj * YX;
     const int f = j0 - 1 + rj;   // y-face index
     S F = 0, m = 0;
@@ -274,7 +304,7 @@ __global__ void __launch_bounds__(kNT) k_stage(const Tile* __restrict__ tiles,
   // corner shear stress: interior corners mu4 (du/dy + dv/dx); wall corners GNBC
   {
     const S mud = (S)(I.mu1 - I.mu2), mu2 = (S)I.mu2;
-    for (int q = threadIdx.x; q < CRY * CRX; q += kNT) {
+    for (int q = tid; active && q < CRY * CRX; q += kNT) {
       const int rj = q / CRX, ri = q - rj * CRX;
       const int jc = j0 + rj, ic = i0 + ri;
       S tau = 0;
@@ -304,7 +334,8 @@ __global__ void __launch_bounds__(kNT) k_stage(const Tile* __restrict__ tiles,
   }
   __syncthreads();
 
-  const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+  if (!active) return;
+  const int tx = tid % TX, ty = tid / TX;
   const int i = i0 + tx, j = j0 + ty;
   if (i >= nx || j >= ny) return;
   const size_t o = (size_t)j * nx + i;
@@ -397,6 +428,15 @@ __global__ void __launch_bounds__(kNT) k_stage(const Tile* __restrict__ tiles,
       I.my[o] = my0 + I.dt * an;
     }
   }
+}
+
+template <typename S>
+__global__ void __launch_bounds__(kNT) k_stage(const Tile* __restrict__ tiles,
+                                                const Inst* __restrict__ insts, int k, int src,
+                                                int dst, double c_next, double b_k, int write_wall) {
+  __shared__ StageLds<S> L;
+  const Tile t = tiles[blockIdx.x];
+  stage_tile<S>(t, insts[t.inst], k, src, dst, c_next, b_k, write_wall, L, threadIdx.x, true);
 }
 
 }  // namespace cdi

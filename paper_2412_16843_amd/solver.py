@@ -24,7 +24,8 @@ class CDISolver:
     """
 
     def __init__(self, params, phi0, precision: str = "fp64", guess: str = "prev",
-                 rtol: float = 0.0, maxit: int = 0, device: str = "cuda:0", u0=None, v0=None):
+                 rtol: float = 0.0, maxit: int = 0, device: str = "cuda:0", u0=None, v0=None,
+                 launch: str = "tiled"):
         if not torch.cuda.is_available():
             raise RuntimeError("CDISolver needs a GPU (the HIP library has no CPU path)")
         single = not isinstance(params, (list, tuple))
@@ -69,6 +70,8 @@ class CDISolver:
         L.check(self.lib.cdi_init_batch(self.cparams, self.n, self.cfields, self.ws_ptr, nbytes,
                                         self.stream.cuda_stream, C.byref(ctx)))
         self.ctx = ctx
+        if launch != "tiled":
+            self.set_launch(launch)
 
     # ------------------------------------------------------------------ run
     def step(self, nsteps: int = 1, allow_noconv: bool = False) -> int:
@@ -108,6 +111,15 @@ class CDISolver:
         L.check(st, allow=(-4,))
         return out, dict(iterations=info.iterations, converged=info.converged,
                          relres=info.relres, bnorm=info.bnorm, ms=info.ms, status=st)
+
+    def set_launch(self, mode: str) -> None:
+        """How cdi_step enqueues a step: "tiled" or "persistent"."""
+        L.check(self.lib.cdi_set_launch(self.ctx, L.LAUNCH[mode]))
+
+    def get_launch(self) -> str:
+        m = C.c_int32()
+        L.check(self.lib.cdi_get_launch(self.ctx, C.byref(m)))
+        return {v: k for k, v in L.LAUNCH.items()}[m.value]
 
     def set_guess(self, mode: str) -> None:
         """Initial-guess mode of later solves: "zero", "prev" or "learned"."""
