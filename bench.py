@@ -183,6 +183,8 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--kernel", default="auto",
                     help="kernel family for the roofline entry (auto: largest device time)")
+    ap.add_argument("--launch", default="auto", choices=["auto", "tiled", "persistent"],
+                    help="auto: the library's autotuner picks the launch form and tile shape")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--poisson", action="store_true",
                     help="add the learned-vs-plain pressure time-to-solution at 2048x1024")
@@ -201,6 +203,11 @@ def main():
     s = CDISolver(p, case.phi0, precision=args.precision, guess="prev", rtol=1e-10)
     s.step(args.warmup)
     torch.cuda.synchronize()
+    tuned = None
+    if args.launch == "auto":
+        tuned = s.tune(trial_steps=10)
+    else:
+        s.set_launch(args.launch)
 
     # dominant kernel: device time per family over a short probe run
     fam = args.kernel
@@ -243,7 +250,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": case.name, "nx": p.nx, "ny": p.ny,
                    "precision": args.precision, "poisson_rtol": 1e-10,
-                   "last_pcg_iters": d["last_iters"], "parallelism": "single-gpu"},
+                   "last_pcg_iters": d["last_iters"], "launch": s.get_launch(),
+                   "tile_rows": s.get_tile_rows(), "autotune": tuned,
+                   "parallelism": "single-gpu"},
         "roofline": {"bound": "hbm", "kernel": fam, "achieved": round(achieved, 2),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,

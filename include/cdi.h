@@ -66,7 +66,7 @@ enum { CDI_SLIP_1A = 0, CDI_SLIP_1B, CDI_SLIP_2A, CDI_SLIP_2B,
        CDI_SLIP_3A, CDI_SLIP_3B, CDI_SLIP_4A, CDI_SLIP_4B };
 enum { CDI_FP64 = 0, CDI_MIXED = 1 };
 enum { CDI_GUESS_ZERO = 0, CDI_GUESS_PREV = 1, CDI_GUESS_LEARNED = 2 };
-enum { CDI_LAUNCH_TILED = 0, CDI_LAUNCH_PERSISTENT = 1 };
+enum { CDI_LAUNCH_TILED = 0, CDI_LAUNCH_PERSISTENT = 1, CDI_LAUNCH_GRAPH = 2 };
 
 /* Problem statement (Sec. 2 and Sec. 4 of the paper).  Any field left 0 where
  * a default is stated takes that default. */
@@ -262,10 +262,53 @@ cdi_status cdi_guess_attach(cdi_ctx* ctx, cdi_net* net);
  *   CDI_LAUNCH_PERSISTENT: one launch per 32 steps with one workgroup of
  *     1024 threads per instance running whole steps, CG loop and stopping
  *     test included, with no host round trip (pays off for small grids and
- *     ensembles of them).  Not available with CDI_GUESS_LEARNED and an
- *     attached network (cdi_step then returns CDI_ERR_STATE). */
+ *     ensembles of them).
+ *   CDI_LAUNCH_GRAPH: the tiled kernels of a whole step captured once in a
+ *     HIP graph with a fixed CG iteration budget per solve (the largest
+ *     recent count + 1; iterations after convergence return at once, so the
+ *     results are bitwise those of CDI_LAUNCH_TILED) and replayed every step
+ *     on a stream of the library's own, ordered after and before the
+ *     caller's stream by events; one host synchronisation per step.  A step
+ *     that needs more iterations than the budget is redone from a snapshot
+ *     on the stream path and the budget grows.  The first two steps of a run
+ *     take the stream path.
+ * PERSISTENT and GRAPH are not available with CDI_GUESS_LEARNED and an
+ * attached network (cdi_step then returns CDI_ERR_STATE). */
 cdi_status cdi_set_launch(cdi_ctx* ctx, int32_t mode);
 cdi_status cdi_get_launch(cdi_ctx* ctx, int32_t* mode);
+
+/* Graph launch counters: steps replayed from the captured graph, steps
+ * redone on the stream path after exceeding the budget, and the current
+ * CG iteration budget per solve (0 = no graph captured). */
+cdi_status cdi_graph_stats(cdi_ctx* ctx, int64_t* replays, int64_t* redone, int32_t* budget);
+
+/* Rows per thread of the wide-tile CG kernels (right-hand side, CG start,
+ * CG direction and operator product, projection): 1 (64 x 4 cell tiles,
+ * more and shorter workgroups, suits small grids) or 4 (64 x 16 cell tiles,
+ * fewer workgroups, shorter halos and fewer partial sums on large grids).
+ * cdi_init picks 4 from 2^18 cells per batch on, else 1. */
+cdi_status cdi_set_tile_rows(cdi_ctx* ctx, int32_t rows);
+cdi_status cdi_get_tile_rows(cdi_ctx* ctx, int32_t* rows);
+
+/* Autotuner: times `trial_steps` steps (after warm-up steps) of every launch
+ * candidate -- tiled with 1 and with 4 rows per thread, persistent, graph
+ * (with the faster tiled shape) -- each from the same saved state, restores
+ * that state (fields, pressure history, time and step counters), and keeps
+ * the fastest candidate for later cdi_step calls.  `scratch` is caller-owned
+ * device memory of at least cdi_tune_bytes(ctx) bytes for the saved state.
+ * Synchronises the stream. */
+typedef struct {
+  int32_t launch;          /* chosen CDI_LAUNCH_*                                  */
+  int32_t tile_rows;       /* chosen rows per thread (1 or 4)                      */
+  int32_t ncand;           /* candidates timed                                     */
+  int32_t pad;
+  double ms_per_step[4];   /* tiled/1 row, tiled/4 rows, persistent, graph;
+                              -1 = skipped                                         */
+} cdi_tune_info;
+
+size_t cdi_tune_bytes(const cdi_ctx* ctx);
+cdi_status cdi_tune(cdi_ctx* ctx, int32_t trial_steps, void* scratch, size_t scratch_bytes,
+                    cdi_tune_info* out);
 
 /* Switch the initial-guess mode (CDI_GUESS_*) of later pressure solves. */
 cdi_status cdi_set_guess(cdi_ctx* ctx, int32_t guess);

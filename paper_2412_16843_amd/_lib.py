@@ -18,7 +18,7 @@ STATUS = {0: "CDI_OK", -1: "CDI_ERR_ARG", -2: "CDI_ERR_SHAPE", -3: "CDI_ERR_DEVI
 SLIP = {"1A": 0, "1B": 1, "2A": 2, "2B": 3, "3A": 4, "3B": 5, "4A": 6, "4B": 7}
 CDI_FP64, CDI_MIXED = 0, 1
 GUESS = {"zero": 0, "prev": 1, "learned": 2}
-LAUNCH = {"tiled": 0, "persistent": 1}
+LAUNCH = {"tiled": 0, "persistent": 1, "graph": 2}
 
 EXPORTS = ("cdi_workspace_bytes", "cdi_default_dt", "cdi_init", "cdi_init_batch", "cdi_step",
            "cdi_solve_pressure", "cdi_diagnostics", "cdi_eval_rhs", "cdi_timing_enable",
@@ -26,7 +26,8 @@ EXPORTS = ("cdi_workspace_bytes", "cdi_default_dt", "cdi_init", "cdi_init_batch"
            "cdi_net_workspace_bytes", "cdi_net_init", "cdi_net_repack", "cdi_net_forward",
            "cdi_net_backward", "cdi_net_adam", "cdi_net_destroy", "cdi_net_last_error",
            "cdi_set_guess", "cdi_guess_attach", "cdi_guess_features", "cdi_set_launch",
-           "cdi_get_launch")
+           "cdi_get_launch", "cdi_set_tile_rows", "cdi_get_tile_rows", "cdi_tune_bytes",
+           "cdi_tune", "cdi_graph_stats")
 
 
 class cdi_params(C.Structure):
@@ -57,6 +58,11 @@ class cdi_diag(C.Structure):
                 ("max_div", C.c_double), ("max_uslip", C.c_double * 2),
                 ("max_uY", C.c_double * 2), ("ke", C.c_double), ("last_iters", C.c_int32),
                 ("nonfinite", C.c_int32), ("last_relres", C.c_double)]
+
+
+class cdi_tune_info(C.Structure):
+    _fields_ = [("launch", C.c_int32), ("tile_rows", C.c_int32), ("ncand", C.c_int32),
+                ("pad", C.c_int32), ("ms_per_step", C.c_double * 4)]
 
 
 class CDIError(RuntimeError):
@@ -127,6 +133,16 @@ def lib() -> C.CDLL:
     L.cdi_set_launch.restype = i32
     L.cdi_get_launch.argtypes = [vp, P(i32)]
     L.cdi_get_launch.restype = i32
+    L.cdi_set_tile_rows.argtypes = [vp, i32]
+    L.cdi_set_tile_rows.restype = i32
+    L.cdi_get_tile_rows.argtypes = [vp, P(i32)]
+    L.cdi_get_tile_rows.restype = i32
+    L.cdi_graph_stats.argtypes = [vp, P(C.c_int64), P(C.c_int64), P(i32)]
+    L.cdi_graph_stats.restype = i32
+    L.cdi_tune_bytes.argtypes = [vp]
+    L.cdi_tune_bytes.restype = C.c_size_t
+    L.cdi_tune.argtypes = [vp, i32, vp, C.c_size_t, P(cdi_tune_info)]
+    L.cdi_tune.restype = i32
     L.cdi_destroy.argtypes = [vp]
     L.cdi_destroy.restype = None
     L.cdi_last_error.argtypes = []

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/cdi.h"
@@ -167,6 +168,7 @@ size_t carve(const Resolved& R, int ntiles_cell, int ntiles_mg0, char* base, siz
   D.d1 = (double*)take(nc * 8);
   D.q = (double*)take(nc * 8);
   D.zf = (double*)take(nc * 8);
+  D.snap = (double*)take((11 * nc + nx) * 8);
   D.mg_t = take(nc * S);
   D.mg_r0 = take(nc * S);
   for (int k = 0; k < 4; ++k) D.ph[k] = (double*)take(nc * 8);
@@ -201,13 +203,29 @@ struct Batch {
   std::vector<Inst> inst;               // host copies
   // tile lists (host), concatenated into one device array
   std::vector<Tile> cell;               // level-0 cell tiles of every instance
+  std::vector<Tile> wide;               // level-0 wide tiles of every instance
   std::vector<std::vector<Tile>> mg;    // per level: multigrid tiles of instances with level < lc
   int max_lc = 0, max_nlev = 0;
   size_t shared_bytes = 0;
 };
 
-void build_tiles(Batch& B) {
+void build_wide(Batch& B, int rows) {
+  B.wide.clear();
+  const int wy = rows * TY;
+  for (int k = 0; k < B.n; ++k) {
+    const Resolved& R = B.R[k];
+    Inst& I = B.inst[k];
+    I.first_wide = (int)B.wide.size();
+    int lw = 0;
+    for (int j0 = 0; j0 < R.p.ny; j0 += wy)
+      for (int i0 = 0; i0 < R.p.nx; i0 += TX) B.wide.push_back(Tile{k, i0, j0, 0, lw++, {0, 0, 0}});
+    I.nwide = lw;
+  }
+}
+
+void build_tiles(Batch& B, int wide_rows) {
   B.cell.clear();
+  B.wide.clear();
   B.max_lc = 0;
   B.max_nlev = 0;
   for (int k = 0; k < B.n; ++k) {
@@ -233,6 +251,25 @@ void build_tiles(Batch& B) {
     }
     for (int l = R.lc; l < R.nlev; ++l) { I.lev[l].first_tile = 0; I.lev[l].ntiles = 0; }
   }
+  build_wide(B, wide_rows);
+}
+
+// Workgroups of a launch are dispatched to the XCDs round robin (block b on
+// XCD b % kXcds), each XCD with its own L2.  Reorder a tile list so that every
+// XCD receives one contiguous band of tiles: neighbouring tiles, whose halos
+// overlap, then share an L2 instead of fetching the same rows from HBM twice.
+constexpr size_t kXcds = 8;
+
+std::vector<Tile> xcd_order(const std::vector<Tile>& t) {
+  const size_t n = t.size();
+  std::vector<Tile> out(n);
+  size_t src = 0;
+  for (size_t x = 0; x < kXcds && x < n; ++x) {
+    const size_t cnt = (n - x + kXcds - 1) / kXcds;   // blocks x, x + 8, x + 16, ...
+    for (size_t k = 0; k < cnt; ++k) out[x + k * kXcds] = t[src + k];
+    src += cnt;
+  }
+  return out;
 }
 
 int mg0_tiles(const Resolved& R) { return ceil_div(R.p.nx, FX) * ceil_div(R.p.ny, FY); }
@@ -241,16 +278,17 @@ int cell_tiles(const Resolved& R) { return ceil_div(R.p.nx, TX) * ceil_div(R.p.n
 size_t batch_bytes(const std::vector<Resolved>& Rs, Batch* B, char* base) {
   const int n = (int)Rs.size();
   // shared header: instances, diag outputs, tile lists
-  size_t ntile_cell = 0, ntile_mg = 0;
+  size_t ntile_cell = 0, ntile_mg = 0, ntile_wide = 0;
   for (auto& R : Rs) {
     ntile_cell += cell_tiles(R);
+    ntile_wide += (size_t)cell_tiles(R);   // room for the shortest wide tile (1 row)
     int nx = R.p.nx, ny = R.p.ny;
     for (int l = 0; l < R.lc; ++l) { ntile_mg += (size_t)ceil_div(nx, FX) * ceil_div(ny, FY); nx /= 2; ny /= 2; }
   }
   size_t off = 0;
   off = align256(off + sizeof(Inst) * n);
   off = align256(off + sizeof(DiagOut) * n);
-  off = align256(off + sizeof(Tile) * (ntile_cell + ntile_mg + 1));
+  off = align256(off + sizeof(Tile) * (2 * ntile_cell + ntile_wide + ntile_mg + 1));
   for (int k = 0; k < n; ++k)
     off = carve(Rs[k], cell_tiles(Rs[k]), mg0_tiles(Rs[k]), base, off, B ? &B->inst[k] : nullptr);
   (void)B;
@@ -280,7 +318,9 @@ struct cdi_ctx {
   char* ws = nullptr;
   Inst* d_inst = nullptr;
   DiagOut* d_diag = nullptr;
-  Tile* d_cell = nullptr;
+  Tile* d_cell = nullptr;          // level-0 tiles, XCD-banded order (tiled launches)
+  Tile* d_cell_inst = nullptr;     // level-0 tiles, instance by instance (persistent launch)
+  Tile* d_wide = nullptr;          // level-0 wide tiles, XCD-banded order
   std::vector<Tile*> d_mg;
   bool mixed = false;
   bool uniform_rho = true;
@@ -290,6 +330,8 @@ struct cdi_ctx {
   std::vector<double> mass0;
   PcgScalars* h_pcg = nullptr;   // pinned
   int pred_iters = 4;
+  int wide_rows = 4;             // rows per thread of the wide-tile kernels (1 or 4)
+  int wide_rows_pick = 4;        // autotuner: faster tiled shape so far
   std::vector<int> last_iters;
   std::vector<double> last_relres;
   std::vector<int> last_conv;
@@ -300,6 +342,14 @@ struct cdi_ctx {
   cdi_net* net = nullptr;        // learned initial guess (borrowed)
   int hist_steps = 0;            // steps recorded in the per-stage pressure history
   int launch = CDI_LAUNCH_TILED; // how cdi_step enqueues a step
+  // graph launch: captured step with a fixed CG budget per solve
+  hipStream_t gstream = nullptr;   // capture / replay stream (the caller's may be the null stream)
+  hipEvent_t gev0 = nullptr, gev1 = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  int graph_budget = 0;            // CG iterations per solve in the captured step
+  int graph_slack = 0;             // consecutive steps that needed at most budget - 2
+  long graph_replays = 0, graph_misses = 0;
   // measurement hook: events around every launch of one kernel family
   std::string timed;
   std::vector<hipEvent_t> tev;
@@ -312,6 +362,13 @@ struct cdi_ctx {
 namespace {
 
 constexpr int kTimedPairs = 512;
+
+// Call f with the rows-per-thread of the wide-tile kernels as a constant.
+template <typename F>
+void with_rows(int rows, F&& f) {
+  if (rows == kWideRows[1]) f(std::integral_constant<int, kWideRows[1]>{});
+  else f(std::integral_constant<int, kWideRows[0]>{});
+}
 
 hipError_t timing_flush(cdi_ctx* c) {
   if (c->tev_used == 0) return hipSuccess;
@@ -379,12 +436,16 @@ void launch_coef(cdi_ctx* c) {
 template <typename S>
 cdi_status solve_loop(cdi_ctx* c, int guess, int stage) {
   Batch& B = c->B;
-  const unsigned ncell = (unsigned)B.cell.size();
+  const unsigned nwide = (unsigned)B.wide.size();
   if (!c->uniform_rho || !c->coef_ready) {
     launch_coef<S>(c);
     c->coef_ready = true;
   }
-  timed(c, "pcg_init", [&] { k_pcg_init<<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, guess, stage); });
+  timed(c, "pcg_init", [&] {
+    with_rows(c->wide_rows, [&](auto R) {
+      k_pcg_init<decltype(R)::value><<<nwide, kNT, 0, c->stream>>>(c->d_wide, c->d_inst, guess, stage);
+    });
+  });
   // z0 = M r0 (residual in buffer 0)
   launch_vcycle<S>(c, 0, 0, 0);
   int it = 0;
@@ -392,7 +453,11 @@ cdi_status solve_loop(cdi_ctx* c, int guess, int stage) {
   bool all_done = false;
   while (it < c->maxit) {
     const int par = it & 1;
-    timed(c, "pcg_spmv", [&] { k_pcg_spmv<<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, par, par); });
+    timed(c, "pcg_spmv", [&] {
+      with_rows(c->wide_rows, [&](auto R) {
+        k_pcg_spmv<decltype(R)::value><<<nwide, kNT, 0, c->stream>>>(c->d_wide, c->d_inst, par, par);
+      });
+    });
     launch_vcycle<S>(c, 1, par, par ^ 1);
     ++it;
     if (it >= next_check || it >= c->maxit) {
@@ -411,7 +476,11 @@ cdi_status solve_loop(cdi_ctx* c, int guess, int stage) {
       HIPCHK(hipMemcpyAsync(c->h_pcg + k, B.inst[k].pcg, sizeof(PcgScalars), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
   }
-  timed(c, "pcg_xmean", [&] { k_pcg_xmean<<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst); });
+  timed(c, "pcg_xmean", [&] {
+    with_rows(c->wide_rows, [&](auto R) {
+      k_pcg_xmean<decltype(R)::value><<<nwide, kNT, 0, c->stream>>>(c->d_wide, c->d_inst);
+    });
+  });
   int maxi = 0;
   bool noconv = false;
   for (int k = 0; k < B.n; ++k) {
@@ -444,7 +513,9 @@ void learned_guess(cdi_ctx* c, int src) {
     k_features<<<g, kNT, 0, c->stream>>>(c->d_inst, 0, phi, nullptr, cdinet::features(c->net), nullptr);
     cdinet::forward(c->net);
     k_guess_apply<<<g, kNT, 0, c->stream>>>(c->d_inst, cdinet::output(c->net));
-    k_guess_fit<<<(unsigned)c->B.cell.size(), kNT, 0, c->stream>>>(c->d_cell, c->d_inst);
+    with_rows(c->wide_rows, [&](auto R) {
+      k_guess_fit<decltype(R)::value><<<(unsigned)c->B.wide.size(), kNT, 0, c->stream>>>(c->d_wide, c->d_inst);
+    });
   });
 }
 
@@ -452,6 +523,7 @@ template <typename S>
 cdi_status run_step(cdi_ctx* c) {
   Batch& B = c->B;
   const unsigned ncell = (unsigned)B.cell.size();
+  const unsigned nwide = (unsigned)B.wide.size();
   const double dt = B.R[0].dt;   // every instance carries its own dt in Inst
   cdi_status st = CDI_OK;
   for (int k = 0; k < 4; ++k) {
@@ -464,7 +536,12 @@ cdi_status run_step(cdi_ctx* c) {
                                                 k < 3 ? RK_C[k + 1] : 1.0, RK_B[k], k == 3);
     });
     const double tfac = k < 3 ? RK_C[k + 1] : 1.0;
-    timed(c, "rhs", [&] { k_rhs<S><<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, dst, tfac, c->rtol, c->maxit); });
+    timed(c, "rhs", [&] {
+      with_rows(c->wide_rows, [&](auto R) {
+        k_rhs<S, decltype(R)::value><<<nwide, kNT, 0, c->stream>>>(c->d_wide, c->d_inst, dst, tfac,
+                                                                   c->rtol, c->maxit);
+      });
+    });
     if (c->guess == CDI_GUESS_LEARNED && c->net) learned_guess(c, dst);
     // previous-pressure guess: the same stage of the previous step (linear
     // extrapolation once two steps exist), else the last pressure
@@ -473,12 +550,191 @@ cdi_status run_step(cdi_ctx* c) {
     cdi_status s = solve_loop<S>(c, gm, k);
     if (s == CDI_ERR_NOCONV) st = s;
     else if (s != CDI_OK) return s;
-    timed(c, "project", [&] { k_project<<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, tfac, k == 3, dst, k); });
+    timed(c, "project", [&] {
+      with_rows(c->wide_rows, [&](auto R) {
+        k_project<decltype(R)::value><<<nwide, kNT, 0, c->stream>>>(c->d_wide, c->d_inst, tfac, k == 3, dst, k);
+      });
+    });
   }
   (void)dt;
   c->hist_steps += 1;
   HIPCHK(hipGetLastError());
   return st;
+}
+
+// ------------------------------------------------------------ graph launch
+// The same launches as solve_loop with exactly `budget` CG iterations and no
+// host polling: once an instance's solve has converged, its remaining
+// iteration kernels return at once, so the result is bitwise that of the
+// stream path.  k_graph_mark records an instance whose solve needed more.
+template <typename S>
+void enqueue_solve_fixed(cdi_ctx* c, int guess, int stage, int budget) {
+  Batch& B = c->B;
+  const unsigned nwide = (unsigned)B.wide.size();
+  if (!c->uniform_rho) launch_coef<S>(c);
+  with_rows(c->wide_rows, [&](auto R) {
+    k_pcg_init<decltype(R)::value><<<nwide, kNT, 0, c->stream>>>(c->d_wide, c->d_inst, guess, stage);
+  });
+  launch_vcycle<S>(c, 0, 0, 0);
+  for (int it = 0; it < budget; ++it) {
+    const int par = it & 1;
+    with_rows(c->wide_rows, [&](auto R) {
+      k_pcg_spmv<decltype(R)::value><<<nwide, kNT, 0, c->stream>>>(c->d_wide, c->d_inst, par, par);
+    });
+    launch_vcycle<S>(c, 1, par, par ^ 1);
+  }
+  with_rows(c->wide_rows, [&](auto R) {
+    k_pcg_xmean<decltype(R)::value><<<nwide, kNT, 0, c->stream>>>(c->d_wide, c->d_inst);
+  });
+  k_graph_mark<<<(unsigned)ceil_div(B.n, 64), 64, 0, c->stream>>>(c->d_inst, B.n, 0);
+}
+
+// Copy every instance's step state (fields and per-stage pressure history)
+// to (save) or from its snapshot area.
+cdi_status snapshot(cdi_ctx* c, bool save) {
+  for (int k = 0; k < c->B.n; ++k) {
+    const Inst& I = c->B.inst[k];
+    const size_t n = (size_t)I.nx * I.ny;
+    double* bufs[11] = {I.phi, I.u, I.p, I.ph[0], I.ph[1], I.ph[2], I.ph[3],
+                        I.ph2[0], I.ph2[1], I.ph2[2], I.ph2[3]};
+    size_t pos = 0;
+    for (double* b : bufs) {
+      HIPCHK(hipMemcpyAsync(save ? I.snap + pos : b, save ? b : I.snap + pos, n * sizeof(double),
+                            hipMemcpyDeviceToDevice, c->stream));
+      pos += n;
+    }
+    HIPCHK(hipMemcpyAsync(save ? I.snap + pos : I.v, save ? I.v : I.snap + pos,
+                          (n + I.nx) * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  }
+  return CDI_OK;
+}
+
+void graph_drop(cdi_ctx* c) {
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  c->gexec = nullptr;
+  c->graph = nullptr;
+  c->graph_budget = 0;
+}
+
+// Capture one RK4 step (snapshot, 4 stages with fixed-budget solves, copy of
+// the CG scalars to pinned memory) on the context's capture stream.
+template <typename S>
+cdi_status graph_capture(cdi_ctx* c, int budget) {
+  graph_drop(c);
+  Batch& B = c->B;
+  const unsigned ncell = (unsigned)B.cell.size();
+  const unsigned nwide = (unsigned)B.wide.size();
+  hipStream_t user = c->stream;
+  const std::string timed0 = c->timed;
+  c->timed.clear();
+  c->stream = c->gstream;
+  auto body = [&]() -> cdi_status {
+    cdi_status st = snapshot(c, true);
+    if (st != CDI_OK) return st;
+    k_graph_mark<<<(unsigned)ceil_div(B.n, 64), 64, 0, c->stream>>>(c->d_inst, B.n, 1);
+    const int gm = c->guess == CDI_GUESS_ZERO ? 0 : 4;   // history of >= 2 steps exists
+    for (int k = 0; k < 4; ++k) {
+      const int src = k == 0 ? 0 : (k == 2 ? 2 : 1);
+      const int dst = (k == 0 || k == 2) ? 1 : 2;
+      const double tfac = k < 3 ? RK_C[k + 1] : 1.0;
+      k_phase_prep<S><<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, src);
+      k_stage<S><<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, k, src, dst, tfac, RK_B[k], k == 3);
+      with_rows(c->wide_rows, [&](auto R) {
+        k_rhs<S, decltype(R)::value><<<nwide, kNT, 0, c->stream>>>(c->d_wide, c->d_inst, dst, tfac,
+                                                                   c->rtol, c->maxit);
+      });
+      enqueue_solve_fixed<S>(c, gm, k, budget);
+      with_rows(c->wide_rows, [&](auto R) {
+        k_project<decltype(R)::value><<<nwide, kNT, 0, c->stream>>>(c->d_wide, c->d_inst, tfac, k == 3, dst, k);
+      });
+    }
+    for (int k = 0; k < B.n; ++k)
+      HIPCHK(hipMemcpyAsync(c->h_pcg + k, B.inst[k].pcg, sizeof(PcgScalars), hipMemcpyDeviceToHost,
+                            c->stream));
+    return CDI_OK;
+  };
+  hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+  cdi_status st = e == hipSuccess ? body() : fail(CDI_ERR_DEVICE, "hipStreamBeginCapture: %s", hipGetErrorString(e));
+  hipGraph_t g = nullptr;
+  if (e == hipSuccess) {
+    hipError_t e2 = hipStreamEndCapture(c->stream, &g);
+    if (st == CDI_OK && e2 != hipSuccess) st = fail(CDI_ERR_DEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e2));
+    if (st == CDI_OK && (e2 = hipGetLastError()) != hipSuccess)
+      st = fail(CDI_ERR_DEVICE, "capture: %s", hipGetErrorString(e2));
+  }
+  c->stream = user;
+  c->timed = timed0;
+  if (st != CDI_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  c->graph = g;
+  e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    graph_drop(c);
+    return fail(CDI_ERR_DEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+  }
+  c->graph_budget = budget;
+  c->graph_slack = 0;
+  return CDI_OK;
+}
+
+// One step through the captured graph.  The first two steps (before the
+// pressure history exists) and any step whose budget turned out too small run
+// on the stream path; the latter from the restored snapshot.
+template <typename S>
+cdi_status run_graph_step(cdi_ctx* c) {
+  if (c->hist_steps < 2) return run_step<S>(c);
+  Batch& B = c->B;
+  if (!c->gstream) {
+    HIPCHK(hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&c->gev0, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&c->gev1, hipEventDisableTiming));
+  }
+  if (!c->uniform_rho || !c->coef_ready) {
+    // coefficients of a uniform density are set up once, outside the graph
+    if (c->uniform_rho) { launch_coef<S>(c); c->coef_ready = true; }
+  }
+  const int want = std::min(c->maxit, c->pred_iters + 1);
+  if (!c->gexec || want > c->graph_budget || (c->graph_slack >= 50 && want < c->graph_budget)) {
+    cdi_status st = graph_capture<S>(c, want);
+    if (st != CDI_OK) return st;
+  }
+  // order the replay after the caller's work and the caller's later work after it
+  HIPCHK(hipEventRecord(c->gev0, c->stream));
+  HIPCHK(hipStreamWaitEvent(c->gstream, c->gev0, 0));
+  HIPCHK(hipGraphLaunch(c->gexec, c->gstream));
+  HIPCHK(hipEventRecord(c->gev1, c->gstream));
+  HIPCHK(hipStreamWaitEvent(c->stream, c->gev1, 0));
+  HIPCHK(hipEventSynchronize(c->gev1));
+  c->graph_replays += 1;
+  bool miss = false;
+  int maxi = 0;
+  for (int k = 0; k < B.n; ++k) {
+    miss = miss || c->h_pcg[k].miss;
+    maxi = std::max(maxi, c->h_pcg[k].step_iters);
+  }
+  if (miss) {
+    // budget too small: back to the step's start, redo it on the stream path
+    c->graph_misses += 1;
+    cdi_status st = snapshot(c, false);
+    if (st != CDI_OK) return st;
+    c->pred_iters = std::max(c->pred_iters, c->graph_budget + 2);
+    return run_step<S>(c);
+  }
+  bool noconv = false;
+  for (int k = 0; k < B.n; ++k) {
+    c->last_iters[k] = c->h_pcg[k].iters;
+    c->last_relres[k] = c->h_pcg[k].relres;
+    c->last_conv[k] = c->h_pcg[k].converged;
+    if (!c->h_pcg[k].converged) noconv = true;
+  }
+  c->pred_iters = std::max(1, maxi);
+  c->graph_slack = maxi + 2 <= c->graph_budget ? c->graph_slack + 1 : 0;
+  c->hist_steps += 1;
+  if (noconv) return fail(CDI_ERR_NOCONV, "pressure solve did not reach rtol within maxit");
+  return CDI_OK;
 }
 
 // Steps of the persistent launch per kernel: bounds the duration of one
@@ -492,7 +748,7 @@ cdi_status run_persistent(cdi_ctx* c, int nsteps) {
   for (int done = 0; done < nsteps; done += kPersistChunk) {
     const int m = std::min(kPersistChunk, nsteps - done);
     timed(c, "persistent", [&] {
-      k_step_persistent<S><<<(unsigned)B.n, PNT, 0, c->stream>>>(c->d_cell, c->d_inst, m,
+      k_step_persistent<S><<<(unsigned)B.n, PNT, 0, c->stream>>>(c->d_cell_inst, c->d_inst, m,
                                                                  c->hist_steps, gm, c->rtol,
                                                                  c->maxit, done > 0);
     });
@@ -573,7 +829,12 @@ cdi_status cdi_init_batch(const cdi_params* params, int32_t n, const cdi_fields*
     if (Rs[k].p.rho1 != Rs[k].p.rho2) c->uniform_rho = false;
   }
   batch_bytes(Rs, &B, c->ws);
-  build_tiles(B);
+  // wide tiles: 4 rows per thread once the batch has enough cells to fill
+  // the GPU with the taller tiles (cdi_tune measures instead of guessing)
+  long cells = 0;
+  for (int k = 0; k < n; ++k) cells += (long)Rs[k].p.nx * Rs[k].p.ny;
+  c->wide_rows = cells >= (1L << 18) ? 4 : 1;
+  build_tiles(B, c->wide_rows);
   // shared header
   size_t off = 0;
   c->d_inst = (Inst*)(c->ws + off);
@@ -581,14 +842,24 @@ cdi_status cdi_init_batch(const cdi_params* params, int32_t n, const cdi_fields*
   c->d_diag = (DiagOut*)(c->ws + off);
   off = align256(off + sizeof(DiagOut) * n);
   Tile* tl = (Tile*)(c->ws + off);
-  std::vector<Tile> all = B.cell;
+  // tiled launches: XCD-banded order; persistent launch: instance order
+  std::vector<Tile> all = xcd_order(B.cell);
   c->d_cell = tl;
   c->d_mg.assign(B.mg.size(), nullptr);
   size_t pos = all.size();
   for (size_t l = 0; l < B.mg.size(); ++l) {
     c->d_mg[l] = tl + pos;
-    all.insert(all.end(), B.mg[l].begin(), B.mg[l].end());
-    pos += B.mg[l].size();
+    const std::vector<Tile> lv = xcd_order(B.mg[l]);
+    all.insert(all.end(), lv.begin(), lv.end());
+    pos += lv.size();
+  }
+  c->d_cell_inst = tl + pos;
+  all.insert(all.end(), B.cell.begin(), B.cell.end());
+  pos += B.cell.size();
+  c->d_wide = tl + pos;
+  {
+    const std::vector<Tile> w = xcd_order(B.wide);
+    all.insert(all.end(), w.begin(), w.end());
   }
   c->h_pcg = nullptr;
   hipError_t e = hipHostMalloc((void**)&c->h_pcg, sizeof(PcgScalars) * n, hipHostMallocDefault);
@@ -643,8 +914,12 @@ cdi_status cdi_step(cdi_ctx* c, int32_t nsteps) {
     c->step += nsteps;
     return st;
   }
+  const bool graph = c->launch == CDI_LAUNCH_GRAPH;
+  if (graph && c->guess == CDI_GUESS_LEARNED && c->net)
+    return fail(CDI_ERR_STATE, "the learned guess needs the tiled launch");
   for (int s = 0; s < nsteps; ++s) {
-    cdi_status r = c->mixed ? run_step<float>(c) : run_step<double>(c);
+    cdi_status r = graph ? (c->mixed ? run_graph_step<float>(c) : run_graph_step<double>(c))
+                         : (c->mixed ? run_step<float>(c) : run_step<double>(c));
     if (r == CDI_ERR_NOCONV) st = r;
     else if (r != CDI_OK) return r;
     c->t += c->B.R[0].dt;
@@ -793,11 +1068,156 @@ cdi_status cdi_timing_read(cdi_ctx* c, double* total_ms, int64_t* launches) {
   return CDI_OK;
 }
 
+// Rebuild the wide tile list for `rows` rows per thread and upload it.
+static cdi_status apply_wide_rows(cdi_ctx* c, int rows) {
+  if (rows == c->wide_rows) return CDI_OK;
+  graph_drop(c);   // the captured step holds the old launch grids
+  Batch& B = c->B;
+  build_wide(B, rows);
+  const std::vector<Tile> w = xcd_order(B.wide);
+  HIPCHK(hipMemcpyAsync(c->d_wide, w.data(), sizeof(Tile) * w.size(), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(c->d_inst, B.inst.data(), sizeof(Inst) * B.n, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  c->wide_rows = rows;
+  return CDI_OK;
+}
+
+cdi_status cdi_set_tile_rows(cdi_ctx* c, int32_t rows) {
+  if (!c) return fail(CDI_ERR_ARG, "ctx is NULL");
+  if (rows != kWideRows[0] && rows != kWideRows[1])
+    return fail(CDI_ERR_ARG, "rows must be %d or %d", kWideRows[0], kWideRows[1]);
+  return apply_wide_rows(c, rows);
+}
+
+cdi_status cdi_get_tile_rows(cdi_ctx* c, int32_t* rows) {
+  if (!c || !rows) return fail(CDI_ERR_ARG, "NULL argument");
+  *rows = c->wide_rows;
+  return CDI_OK;
+}
+
+// Device state a step reads besides its scratch: the caller fields and the
+// per-stage pressure history (FP64), per instance.
+static size_t tune_bytes(const cdi_ctx* c) {
+  size_t b = 0;
+  for (int k = 0; k < c->B.n; ++k) {
+    const size_t n = (size_t)c->B.R[k].p.nx * c->B.R[k].p.ny, nx = c->B.R[k].p.nx;
+    b += align256((11 * n + nx) * sizeof(double));
+  }
+  return b;
+}
+
+size_t cdi_tune_bytes(const cdi_ctx* c) { return c ? tune_bytes(c) : 0; }
+
+static cdi_status tune_copy(cdi_ctx* c, char* scratch, bool save) {
+  size_t off = 0;
+  for (int k = 0; k < c->B.n; ++k) {
+    const Inst& I = c->B.inst[k];
+    const size_t n = (size_t)I.nx * I.ny, nf = n + I.nx;
+    double* bufs[11] = {I.phi, I.u, I.p, I.ph[0], I.ph[1], I.ph[2], I.ph[3],
+                        I.ph2[0], I.ph2[1], I.ph2[2], I.ph2[3]};
+    double* base = (double*)(scratch + off);
+    size_t pos = 0;
+    for (double* b : bufs) {
+      void* dst = save ? (void*)(base + pos) : (void*)b;
+      const void* src = save ? (const void*)b : (const void*)(base + pos);
+      HIPCHK(hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+      pos += n;
+    }
+    void* dst = save ? (void*)(base + pos) : (void*)I.v;
+    const void* src = save ? (const void*)I.v : (const void*)(base + pos);
+    HIPCHK(hipMemcpyAsync(dst, src, nf * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    off += align256((11 * n + I.nx) * sizeof(double));
+  }
+  return CDI_OK;
+}
+
+cdi_status cdi_tune(cdi_ctx* c, int32_t trial_steps, void* scratch, size_t scratch_bytes,
+                    cdi_tune_info* out) {
+  if (!c || !scratch) return fail(CDI_ERR_ARG, "NULL argument");
+  if (trial_steps < 1) return fail(CDI_ERR_ARG, "trial_steps must be >= 1");
+  if (scratch_bytes < tune_bytes(c))
+    return fail(CDI_ERR_ARG, "scratch too small: %zu < %zu bytes", scratch_bytes, tune_bytes(c));
+  char* sc = (char*)scratch;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  cdi_status st = tune_copy(c, sc, true);
+  if (st != CDI_OK) return st;
+  // host-side state a step advances
+  const double t0 = c->t;
+  const long step0 = c->step;
+  const int hist0 = c->hist_steps, pred0 = c->pred_iters;
+  const std::vector<int> it0 = c->last_iters, conv0 = c->last_conv;
+  const std::vector<double> rel0 = c->last_relres;
+  const std::string timed0 = c->timed;
+  c->timed.clear();
+  c->wide_rows_pick = c->wide_rows;
+  struct Cand { int launch, rows; };
+  Cand cands[4] = {{CDI_LAUNCH_TILED, kWideRows[0]}, {CDI_LAUNCH_TILED, kWideRows[1]},
+                   {CDI_LAUNCH_PERSISTENT, c->wide_rows}, {CDI_LAUNCH_GRAPH, c->wide_rows}};
+  double best = INFINITY, best_tiled = INFINITY;
+  Cand pick{c->launch, c->wide_rows};
+  cdi_tune_info info{};
+  for (int q = 0; q < 4; ++q) {
+    info.ms_per_step[q] = -1.0;
+    Cand& cd = cands[q];
+    const bool learned = c->guess == CDI_GUESS_LEARNED && c->net;
+    if (cd.launch != CDI_LAUNCH_TILED && learned) continue;
+    if (cd.launch != CDI_LAUNCH_TILED) cd.rows = c->wide_rows_pick;   // the faster tiled shape
+    if ((st = apply_wide_rows(c, cd.rows)) != CDI_OK) break;
+    c->launch = cd.launch;
+    // warm-up: code load, iteration predictor; the graph form captures its
+    // step once the pressure history exists
+    cdi_status r = cdi_step(c, cd.launch == CDI_LAUNCH_GRAPH ? 3 : 1);
+    if (r == CDI_OK || r == CDI_ERR_NOCONV) {
+      HIPCHK(hipEventRecord(c->ev0, c->stream));
+      r = cdi_step(c, trial_steps);
+      HIPCHK(hipEventRecord(c->ev1, c->stream));
+      HIPCHK(hipEventSynchronize(c->ev1));
+    }
+    if (r != CDI_OK && r != CDI_ERR_NOCONV) { st = r; break; }
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    info.ms_per_step[q] = ms / trial_steps;
+    info.ncand += 1;
+    if (info.ms_per_step[q] < best) { best = info.ms_per_step[q]; pick = cd; }
+    if (cd.launch == CDI_LAUNCH_TILED && info.ms_per_step[q] < best_tiled) {
+      best_tiled = info.ms_per_step[q];
+      c->wide_rows_pick = cd.rows;
+    }
+    // back to the saved state for the next candidate
+    cdi_status rs = tune_copy(c, sc, false);
+    if (rs != CDI_OK) return rs;
+    c->t = t0; c->step = step0; c->hist_steps = hist0; c->pred_iters = pred0;
+  }
+  HIPCHK(hipStreamSynchronize(c->stream));
+  c->t = t0; c->step = step0; c->hist_steps = hist0; c->pred_iters = pred0;
+  c->last_iters = it0; c->last_conv = conv0; c->last_relres = rel0;
+  c->timed = timed0;
+  if (st != CDI_OK) {
+    (void)tune_copy(c, sc, false);
+    (void)hipStreamSynchronize(c->stream);
+    return st;
+  }
+  if ((st = apply_wide_rows(c, pick.rows)) != CDI_OK) return st;
+  c->launch = pick.launch;
+  info.launch = pick.launch;
+  info.tile_rows = pick.rows;
+  if (out) *out = info;
+  return CDI_OK;
+}
+
 cdi_status cdi_set_launch(cdi_ctx* c, int32_t mode) {
   if (!c) return fail(CDI_ERR_ARG, "ctx is NULL");
-  if (mode != CDI_LAUNCH_TILED && mode != CDI_LAUNCH_PERSISTENT)
+  if (mode != CDI_LAUNCH_TILED && mode != CDI_LAUNCH_PERSISTENT && mode != CDI_LAUNCH_GRAPH)
     return fail(CDI_ERR_ARG, "bad launch mode %d", mode);
   c->launch = mode;
+  return CDI_OK;
+}
+
+cdi_status cdi_graph_stats(cdi_ctx* c, int64_t* replays, int64_t* redone, int32_t* budget) {
+  if (!c || !replays || !redone || !budget) return fail(CDI_ERR_ARG, "NULL argument");
+  *replays = c->graph_replays;
+  *redone = c->graph_misses;
+  *budget = c->graph_budget;
   return CDI_OK;
 }
 
@@ -810,6 +1230,7 @@ cdi_status cdi_get_launch(cdi_ctx* c, int32_t* mode) {
 cdi_status cdi_set_guess(cdi_ctx* c, int32_t guess) {
   if (!c) return fail(CDI_ERR_ARG, "ctx is NULL");
   if (guess < CDI_GUESS_ZERO || guess > CDI_GUESS_LEARNED) return fail(CDI_ERR_ARG, "bad guess");
+  if (guess != c->guess) graph_drop(c);   // the captured step holds the guess mode
   c->guess = guess;
   return CDI_OK;
 }
@@ -840,6 +1261,13 @@ void cdi_destroy(cdi_ctx* c) {
   if (!c) return;
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   else (void)hipDeviceSynchronize();
+  graph_drop(c);
+  if (c->gstream) {
+    (void)hipStreamSynchronize(c->gstream);
+    (void)hipStreamDestroy(c->gstream);
+  }
+  if (c->gev0) (void)hipEventDestroy(c->gev0);
+  if (c->gev1) (void)hipEventDestroy(c->gev1);
   if (c->h_pcg) (void)hipHostFree(c->h_pcg);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);

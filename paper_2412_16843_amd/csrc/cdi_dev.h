@@ -46,6 +46,8 @@ struct PcgScalars {
   int coef_ok;              // persistent path: coarse coefficients current
   int nfail;                // persistent path: solves that stopped at maxit
   int max_iters;            // persistent path: largest iteration count
+  int miss;                 // graph path: a solve of the step ended unconverged
+  int step_iters;           // graph path: largest iteration count of the step
   int pad;
 };
 
@@ -55,6 +57,7 @@ struct Inst {
   int nlev, lc;             // multigrid levels; first level done by the coarse kernel
   int slip_model, mixed;
   int first_tile, ntiles;   // tiles of level 0 in the cell tile list
+  int first_wide, nwide;    // tiles of level 0 in the wide tile list
   double h, inv_h, eps, gamma, sigma, cos_eq;
   double rho1, rho2, mu1, mu2, beta1, beta2, uw_bot, uw_top, dt;
   // caller state (FP64)
@@ -80,6 +83,7 @@ struct Inst {
   PcgScalars* pcg;
   unsigned* counters;                  // [8 kinds][kCounterStride] arrival counters
   Level lev[kMaxLevels];
+  double* snap;                        // graph path: state at the start of the step
   void* mg_t;                          // S [ny*nx] residual scratch of the one-block V-cycle
   void* mg_r0;                         // S [ny*nx] level-0 residual copy (mixed, one-block V-cycle)
   double* cinv;                        // dense inverse of the coarsest operator (n <= 64)
@@ -97,6 +101,14 @@ struct Tile {
 
 // ---------------------------------------------------------------- helpers
 __device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+// Periodic index for any offset: halo columns of a tile wider than the grid
+// can lie more than one period away.
+__device__ __forceinline__ int wrap_any(int i, int n) {
+  while (i < 0) i += n;
+  while (i >= n) i -= n;
+  return i;
+}
 
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {

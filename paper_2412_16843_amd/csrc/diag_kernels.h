@@ -167,6 +167,22 @@ __global__ void __launch_bounds__(kNT) k_solve_setup(const Tile* __restrict__ ti
   }
 }
 
+// Graph path bookkeeping, one thread per instance: clear the step's miss flag
+// and iteration maximum (begin), or record whether the solve just enqueued
+// converged within its fixed iteration budget (end).
+__global__ void k_graph_mark(const Inst* __restrict__ insts, int n, int begin) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  PcgScalars* P = insts[k].pcg;
+  if (begin) {
+    P->miss = 0;
+    P->step_iters = 0;
+  } else {
+    if (!P->done) P->miss = 1;
+    if (P->iters > P->step_iters) P->step_iters = P->iters;
+  }
+}
+
 // Mean-free solution of a standalone solve into the caller's buffer.
 __global__ void __launch_bounds__(kNT) k_solve_out(const Tile* __restrict__ tiles,
                                                    const Inst* __restrict__ insts, double* pout) {

@@ -79,7 +79,7 @@ __device__ __forceinline__ double rhs_cell(const Inst& I, const double* __restri
   return b;
 }
 
-template <typename S>
+template <typename S, int WR>
 __global__ void __launch_bounds__(kNT) k_rhs(const Tile* __restrict__ tiles,
                                               const Inst* __restrict__ insts, int src, double tau,
                                               double rtol, int maxit) {
@@ -87,23 +87,24 @@ __global__ void __launch_bounds__(kNT) k_rhs(const Tile* __restrict__ tiles,
   const Tile t = tiles[blockIdx.x];
   const Inst& I = insts[t.inst];
   const int nx = I.nx, ny = I.ny;
-  const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
-  const int i = t.i0 + tx, j = t.j0 + ty;
   const double* __restrict__ ph = src == 0 ? I.phi : (src == 1 ? I.phi_a : I.phi_b);
   double bsum[2] = {0.0, 0.0};
-  if (i < nx && j < ny) {
-    const double b = rhs_cell<S>(I, ph, j, i, tau);
-    bsum[0] = b;
-    bsum[1] = b * b;
+  for (int r = 0; r < WR; ++r) {
+    const int i = t.i0 + wide_tx(), j = t.j0 + wide_ty(r);
+    if (i < nx && j < ny) {
+      const double b = rhs_cell<S>(I, ph, j, i, tau);
+      bsum[0] += b;
+      bsum[1] += b * b;
+    }
   }
   block_sum<2>(bsum, sh);
   if (threadIdx.x == 0) {
     st_agent(&I.part[t.local], bsum[0]);
-    st_agent(&I.part[I.ntiles + t.local], bsum[1]);
+    st_agent(&I.part[I.nwide + t.local], bsum[1]);
   }
-  if (arrive_last(I.counters + 0 * kCounterStride, I.ntiles, t.local)) {
-    const double s = sum_partials(I.part, I.ntiles, sh);
-    const double s2 = sum_partials(I.part + I.ntiles, I.ntiles, sh);
+  if (arrive_last(I.counters + 0 * kCounterStride, I.nwide, t.local)) {
+    const double s = sum_partials(I.part, I.nwide, sh);
+    const double s2 = sum_partials(I.part + I.nwide, I.nwide, sh);
     if (threadIdx.x == 0) {
       PcgScalars* P = I.pcg;
       const double n = (double)nx * ny;
@@ -164,30 +165,58 @@ __device__ __forceinline__ void pcg_init_cell(const Inst& I, int guess, int stag
   I.rr[o] = r;
 }
 
+// Wide-tile form: the guess over the tile and a one-cell halo is formed once
+// into LDS, then r0 = f - K x0 on the tile (same arithmetic as pcg_init_cell).
+template <int WR>
 __global__ void __launch_bounds__(kNT) k_pcg_init(const Tile* __restrict__ tiles,
                                                   const Inst* __restrict__ insts, int guess,
                                                   int stage) {
+  constexpr int RY = WR * TY + 2, RX = TX + 2;
+  __shared__ double s_x[RY * RX];
   __shared__ double sh[2 * kNT / 64];
   const Tile t = tiles[blockIdx.x];
   const Inst& I = insts[t.inst];
   const int nx = I.nx, ny = I.ny;
-  const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
-  const int i = t.i0 + tx, j = t.j0 + ty;
+  const double bmean = I.pcg->bmean;
+  if (guess) {
+    for (int k = threadIdx.x; k < RY * RX; k += kNT) {
+      const int rj = k / RX, ri = k - rj * RX;
+      const int j = t.j0 - 1 + rj, i = wrap_any(t.i0 - 1 + ri, nx);
+      s_x[k] = (j >= 0 && j < ny) ? guess_value(I, guess, stage, (size_t)j * nx + i) : 0.0;
+    }
+    __syncthreads();
+  }
   double s[2] = {0.0, 0.0};
-  if (i < nx && j < ny) {
-    double f, r;
-    pcg_init_cell(I, guess, stage, j, i, I.pcg->bmean, f, r);
-    s[0] = f * f;
-    s[1] = r * r;
+  for (int r = 0; r < WR; ++r) {
+    const int tx = wide_tx(), ty = wide_ty(r);
+    const int i = t.i0 + tx, j = t.j0 + ty;
+    if (i < nx && j < ny) {
+      const size_t o = (size_t)j * nx + i;
+      const double f = -(I.b[o] - bmean);
+      double rv = f, xc = 0.0;
+      if (guess) {
+        const int c = (ty + 1) * RX + tx + 1;
+        const int ie = wrap(i + 1, nx);
+        xc = s_x[c];
+        double kx = I.ax0[o] * (xc - s_x[c - 1]) + I.ax0[(size_t)j * nx + ie] * (xc - s_x[c + 1]);
+        if (j >= 1) kx += I.ay0[o] * (xc - s_x[c - RX]);
+        if (j + 1 < ny) kx += I.ay0[o + nx] * (xc - s_x[c + RX]);
+        rv = f - kx;
+      }
+      I.x[o] = xc;
+      I.rr[o] = rv;
+      s[0] += f * f;
+      s[1] += rv * rv;
+    }
   }
   block_sum<2>(s, sh);
   if (threadIdx.x == 0) {
     st_agent(&I.part[t.local], s[0]);
-    st_agent(&I.part[I.ntiles + t.local], s[1]);
+    st_agent(&I.part[I.nwide + t.local], s[1]);
   }
-  if (arrive_last(I.counters + 1 * kCounterStride, I.ntiles, t.local)) {
-    const double ff = sum_partials(I.part, I.ntiles, sh);
-    const double rr = sum_partials(I.part + I.ntiles, I.ntiles, sh);
+  if (arrive_last(I.counters + 1 * kCounterStride, I.nwide, t.local)) {
+    const double ff = sum_partials(I.part, I.nwide, sh);
+    const double rr = sum_partials(I.part + I.nwide, I.nwide, sh);
     if (threadIdx.x == 0) {
       PcgScalars* P = I.pcg;
       P->fnorm = sqrt(ff);
@@ -204,44 +233,62 @@ __global__ void __launch_bounds__(kNT) k_pcg_init(const Tile* __restrict__ tiles
 
 // d = z + beta d_old (d = z on the first iteration), q = K d, (d, r), (d, q);
 // last block: alpha = (d, r)/(d, q).
+// Wide-tile form: d over the tile and a one-cell halo is formed once into
+// LDS; q = K d on the tile from it.
+template <int WR>
 __global__ void __launch_bounds__(kNT) k_pcg_spmv(const Tile* __restrict__ tiles,
                                                   const Inst* __restrict__ insts, int parity,
                                                   int rsel) {
+  constexpr int RY = WR * TY + 2, RX = TX + 2;
+  __shared__ double s_d[RY * RX];
   __shared__ double sh[2 * kNT / 64];
   const Tile t = tiles[blockIdx.x];
   const Inst& I = insts[t.inst];
   if (I.pcg->done) return;
   const int nx = I.nx, ny = I.ny;
-  const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
-  const int i = t.i0 + tx, j = t.j0 + ty;
   const double* __restrict__ dold = parity ? I.d0 : I.d1;
   double* __restrict__ dnew = parity ? I.d1 : I.d0;
   const double* __restrict__ z = I.zf;
+  const double* __restrict__ rv = rsel ? I.rr2 : I.rr;
   const bool first = I.pcg->first != 0;
   const double beta = first ? 0.0 : I.pcg->beta;
+  for (int k = threadIdx.x; k < RY * RX; k += kNT) {
+    const int rj = k / RX, ri = k - rj * RX;
+    const int j = t.j0 - 1 + rj, i = wrap_any(t.i0 - 1 + ri, nx);
+    double dv = 0.0;
+    if (j >= 0 && j < ny) {
+      const size_t o = (size_t)j * nx + i;
+      dv = first ? z[o] : z[o] + beta * dold[o];
+    }
+    s_d[k] = dv;
+  }
+  __syncthreads();
   double s[2] = {0.0, 0.0};
-  if (i < nx && j < ny) {
-    const size_t o = (size_t)j * nx + i;
-    auto dval = [&](size_t idx) { return first ? z[idx] : z[idx] + beta * dold[idx]; };
-    const int ie = wrap(i + 1, nx), iw = wrap(i - 1, nx);
-    const double dc = dval(o);
-    double q = I.ax0[o] * (dc - dval((size_t)j * nx + iw)) +
-               I.ax0[(size_t)j * nx + ie] * (dc - dval((size_t)j * nx + ie));
-    if (j >= 1) q += I.ay0[o] * (dc - dval(o - nx));
-    if (j + 1 < ny) q += I.ay0[o + nx] * (dc - dval(o + nx));
-    dnew[o] = dc;
-    I.q[o] = q;
-    s[0] = dc * (rsel ? I.rr2 : I.rr)[o];
-    s[1] = dc * q;
+  for (int r = 0; r < WR; ++r) {
+    const int tx = wide_tx(), ty = wide_ty(r);
+    const int i = t.i0 + tx, j = t.j0 + ty;
+    if (i < nx && j < ny) {
+      const size_t o = (size_t)j * nx + i;
+      const int c = (ty + 1) * RX + tx + 1;
+      const int ie = wrap(i + 1, nx);
+      const double dc = s_d[c];
+      double q = I.ax0[o] * (dc - s_d[c - 1]) + I.ax0[(size_t)j * nx + ie] * (dc - s_d[c + 1]);
+      if (j >= 1) q += I.ay0[o] * (dc - s_d[c - RX]);
+      if (j + 1 < ny) q += I.ay0[o + nx] * (dc - s_d[c + RX]);
+      dnew[o] = dc;
+      I.q[o] = q;
+      s[0] += dc * rv[o];
+      s[1] += dc * q;
+    }
   }
   block_sum<2>(s, sh);
   if (threadIdx.x == 0) {
     st_agent(&I.part[t.local], s[0]);
-    st_agent(&I.part[I.ntiles + t.local], s[1]);
+    st_agent(&I.part[I.nwide + t.local], s[1]);
   }
-  if (arrive_last(I.counters + 2 * kCounterStride, I.ntiles, t.local)) {
-    const double dr = sum_partials(I.part, I.ntiles, sh);
-    const double dq = sum_partials(I.part + I.ntiles, I.ntiles, sh);
+  if (arrive_last(I.counters + 2 * kCounterStride, I.nwide, t.local)) {
+    const double dr = sum_partials(I.part, I.nwide, sh);
+    const double dq = sum_partials(I.part + I.nwide, I.nwide, sh);
     if (threadIdx.x == 0) {
       PcgScalars* P = I.pcg;
       P->dr = dr; P->dq = dq;
@@ -255,28 +302,30 @@ __global__ void __launch_bounds__(kNT) k_pcg_spmv(const Tile* __restrict__ tiles
 // g the network's guess (in zf).  The coefficients (a, c) solve the 2x2
 // normal equations of min ||x0 - x*||_K over x0 = a p + c g, so the fitted
 // guess is never worse, in that norm, than the previous pressure or zero.
+template <int WR>
 __global__ void __launch_bounds__(kNT) k_guess_fit(const Tile* __restrict__ tiles,
                                                    const Inst* __restrict__ insts) {
   __shared__ double sh[5 * kNT / 64];
   const Tile t = tiles[blockIdx.x];
   const Inst& I = insts[t.inst];
   const int nx = I.nx, ny = I.ny;
-  const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
-  const int i = t.i0 + tx, j = t.j0 + ty;
   double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};   // pKp, pKg, gKg, p.f, g.f
-  if (i < nx && j < ny) {
-    const size_t o = (size_t)j * nx + i;
-    const double f = -(I.b[o] - I.pcg->bmean);
-    const double pv = I.p[o], gv = I.zf[o];
-    const double kp = apply_K(I, I.p, j, i), kg = apply_K(I, I.zf, j, i);
-    s[0] = pv * kp; s[1] = pv * kg; s[2] = gv * kg; s[3] = pv * f; s[4] = gv * f;
+  for (int r = 0; r < WR; ++r) {
+    const int i = t.i0 + wide_tx(), j = t.j0 + wide_ty(r);
+    if (i < nx && j < ny) {
+      const size_t o = (size_t)j * nx + i;
+      const double f = -(I.b[o] - I.pcg->bmean);
+      const double pv = I.p[o], gv = I.zf[o];
+      const double kp = apply_K(I, I.p, j, i), kg = apply_K(I, I.zf, j, i);
+      s[0] += pv * kp; s[1] += pv * kg; s[2] += gv * kg; s[3] += pv * f; s[4] += gv * f;
+    }
   }
   block_sum<5>(s, sh);
   if (threadIdx.x == 0)
-    for (int k = 0; k < 5; ++k) st_agent(&I.part[k * I.ntiles + t.local], s[k]);
-  if (arrive_last(I.counters + 7 * kCounterStride, I.ntiles, t.local)) {
+    for (int k = 0; k < 5; ++k) st_agent(&I.part[k * I.nwide + t.local], s[k]);
+  if (arrive_last(I.counters + 7 * kCounterStride, I.nwide, t.local)) {
     double m[5];
-    for (int k = 0; k < 5; ++k) m[k] = sum_partials(I.part + k * I.ntiles, I.ntiles, sh);
+    for (int k = 0; k < 5; ++k) m[k] = sum_partials(I.part + k * I.nwide, I.nwide, sh);
     if (threadIdx.x == 0) {
       double a = 0.0, c = 0.0;
       const double det = m[0] * m[2] - m[1] * m[1];
@@ -306,6 +355,7 @@ __device__ __forceinline__ void pcg_stop_test(PcgScalars* P, double rr, double s
 }
 
 // Mean of the solution when the solve ended before any CG update.
+template <int WR>
 __global__ void __launch_bounds__(kNT) k_pcg_xmean(const Tile* __restrict__ tiles,
                                                    const Inst* __restrict__ insts) {
   __shared__ double sh[kNT / 64];
@@ -313,14 +363,15 @@ __global__ void __launch_bounds__(kNT) k_pcg_xmean(const Tile* __restrict__ tile
   const Inst& I = insts[t.inst];
   const int nx = I.nx, ny = I.ny;
   if (I.pcg->iters > 0) return;
-  const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
-  const int i = t.i0 + tx, j = t.j0 + ty;
   double s[1] = {0.0};
-  if (i < nx && j < ny) s[0] = I.x[(size_t)j * nx + i];
+  for (int r = 0; r < WR; ++r) {
+    const int i = t.i0 + wide_tx(), j = t.j0 + wide_ty(r);
+    if (i < nx && j < ny) s[0] += I.x[(size_t)j * nx + i];
+  }
   block_sum<1>(s, sh);
   if (threadIdx.x == 0) st_agent(&I.part[t.local], s[0]);
-  if (arrive_last(I.counters + 6 * kCounterStride, I.ntiles, t.local)) {
-    const double sx = sum_partials(I.part, I.ntiles, sh);
+  if (arrive_last(I.counters + 6 * kCounterStride, I.nwide, t.local)) {
+    const double sx = sum_partials(I.part, I.nwide, sh);
     if (threadIdx.x == 0) I.pcg->xmean = sx / ((double)nx * ny);
   }
 }
@@ -356,17 +407,20 @@ __device__ __forceinline__ void project_cell(const Inst& I, double tau, int fina
   if (final_stage) I.phi[o] = ph[o];
 }
 
+template <int WR>
 __global__ void __launch_bounds__(kNT) k_project(const Tile* __restrict__ tiles,
                                                  const Inst* __restrict__ insts, double tau,
                                                  int final_stage, int src, int stage) {
   const Tile t = tiles[blockIdx.x];
   const Inst& I = insts[t.inst];
   const int nx = I.nx, ny = I.ny;
-  const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
-  const int i = t.i0 + tx, j = t.j0 + ty;
-  if (i >= nx || j >= ny) return;
   const double* __restrict__ ph = src == 1 ? I.phi_a : I.phi_b;
-  project_cell(I, tau, final_stage, ph, stage, I.pcg->zero_rhs != 0, I.pcg->xmean, j, i);
+  const bool zero = I.pcg->zero_rhs != 0;
+  const double xmean = I.pcg->xmean;
+  for (int r = 0; r < WR; ++r) {
+    const int i = t.i0 + wide_tx(), j = t.j0 + wide_ty(r);
+    if (i < nx && j < ny) project_cell(I, tau, final_stage, ph, stage, zero, xmean, j, i);
+  }
 }
 
 // ================================================================ multigrid
@@ -400,49 +454,74 @@ __global__ void __launch_bounds__(kNT) k_mg_down(const Tile* __restrict__ tiles,
   // level-0 residual: read the previous buffer when updating, write the current one
   const double* __restrict__ rin = (upd ? (rsel ? I.rr : I.rr2) : (rsel ? I.rr2 : I.rr));
   double* __restrict__ rout = rsel ? I.rr2 : I.rr;
-  // CG update on the tile (FP64), partial ||r||^2 and sum(x)
+  // loads (rows outside the grid hold zeros and are never used as cells)
+  for (int k = threadIdx.x; k < RY * (RX + 1); k += kNT) {
+    const int rj = k / (RX + 1), ri = k - rj * (RX + 1);
+    const int j = j0 - H + rj, i = wrap_any(i0 - H + ri, nx);
+    s_ax[k] = (j >= 0 && j < ny) ? ldS<S>(L.ax, (size_t)j * nx + i) : S(0);
+  }
+  for (int k = threadIdx.x; k < (RY + 1) * RX; k += kNT) {
+    const int rj = k / RX, ri = k - rj * RX;
+    const int j = j0 - H + rj, i = wrap_any(i0 - H + ri, nx);
+    s_ay[k] = (j >= 0 && j <= ny) ? ldS<S>(L.ay, (size_t)j * nx + i) : S(0);
+  }
+  // residual over the region; with the CG update (level 0) the new residual
+  // r - alpha q is formed once per cell from a single read of r and q, and
+  // on the tile itself x += alpha d, r is stored, ||r||^2 and sum(x) summed
   double red[2] = {0.0, 0.0};
-  if (upd) {
-    const double* __restrict__ d = parity ? I.d1 : I.d0;
-    for (int k = threadIdx.x; k < FX * FY; k += kNT) {
-      const int ty = k / FX, tx = k - ty * FX;
-      const int j = j0 + ty, i = i0 + tx;
-      if (j < ny && i < nx) {
+  if (!upd) {
+    for (int k = threadIdx.x; k < RY * RX; k += kNT) {
+      const int rj = k / RX, ri = k - rj * RX;
+      const int j = j0 - H + rj, i = wrap_any(i0 - H + ri, nx);
+      S r = 0;
+      if (j >= 0 && j < ny) {
         const size_t o = (size_t)j * nx + i;
-        const double x = I.x[o] + alpha * d[o];
-        const double r = rin[o] - alpha * I.q[o];
-        I.x[o] = x;
-        rout[o] = r;
-        red[0] += r * r;
+        r = level == 0 ? (S)rin[o] : ldS<S>(L.r, o);
+      }
+      s_r[k] = r;
+    }
+  } else {
+    // all loads of the thread's region cells first, then the stores
+    constexpr int NPT = (RY * RX + kNT - 1) / kNT;
+    const double* __restrict__ dvec = parity ? I.d1 : I.d0;
+    const double* __restrict__ qv = I.q;
+    double* __restrict__ xv = I.x;
+    double rl[NPT], ql[NPT], xl[NPT], dl[NPT];
+    size_t ol[NPT];
+    bool inl[NPT], own[NPT];
+#pragma unroll
+    for (int e = 0; e < NPT; ++e) {
+      const int k = threadIdx.x + e * kNT;
+      const int rj = k / RX, ri = k - rj * RX;
+      const int j = j0 - H + rj, iu = i0 - H + ri;
+      inl[e] = k < RY * RX && j >= 0 && j < ny;
+      own[e] = inl[e] && rj >= H && rj < H + FY && ri >= H && ri < H + FX && iu < nx;
+      ol[e] = inl[e] ? (size_t)j * nx + wrap_any(iu, nx) : 0;
+      rl[e] = inl[e] ? rin[ol[e]] : 0.0;
+      ql[e] = inl[e] ? qv[ol[e]] : 0.0;
+      xl[e] = own[e] ? xv[ol[e]] : 0.0;
+      dl[e] = own[e] ? dvec[ol[e]] : 0.0;
+    }
+#pragma unroll
+    for (int e = 0; e < NPT; ++e) {
+      const int k = threadIdx.x + e * kNT;
+      const double rv = rl[e] - alpha * ql[e];
+      if (k < RY * RX) s_r[k] = inl[e] ? (S)rv : S(0);
+      if (own[e]) {
+        const double x = xl[e] + alpha * dl[e];
+        xv[ol[e]] = x;
+        rout[ol[e]] = rv;
+        red[0] += rv * rv;
         red[1] += x;
       }
     }
+  }
+  if (upd) {
     block_sum<2>(red, sh);
     if (threadIdx.x == 0) {
       st_agent(&I.part[t.local], red[0]);
       st_agent(&I.part[L.ntiles + t.local], red[1]);
     }
-  }
-  // loads (rows outside the grid hold zeros and are never used as cells)
-  for (int k = threadIdx.x; k < RY * (RX + 1); k += kNT) {
-    const int rj = k / (RX + 1), ri = k - rj * (RX + 1);
-    const int j = j0 - H + rj, i = wrap(i0 - H + ri, nx);
-    s_ax[k] = (j >= 0 && j < ny) ? ldS<S>(L.ax, (size_t)j * nx + i) : S(0);
-  }
-  for (int k = threadIdx.x; k < (RY + 1) * RX; k += kNT) {
-    const int rj = k / RX, ri = k - rj * RX;
-    const int j = j0 - H + rj, i = wrap(i0 - H + ri, nx);
-    s_ay[k] = (j >= 0 && j <= ny) ? ldS<S>(L.ay, (size_t)j * nx + i) : S(0);
-  }
-  for (int k = threadIdx.x; k < RY * RX; k += kNT) {
-    const int rj = k / RX, ri = k - rj * RX;
-    const int j = j0 - H + rj, i = wrap(i0 - H + ri, nx);
-    S r = 0;
-    if (j >= 0 && j < ny) {
-      const size_t o = (size_t)j * nx + i;
-      r = level == 0 ? (S)(upd ? rin[o] - alpha * I.q[o] : rin[o]) : ldS<S>(L.r, o);
-    }
-    s_r[k] = r;
   }
   __syncthreads();
   auto diag = [&](int rj, int ri) {
@@ -553,18 +632,18 @@ __global__ void __launch_bounds__(kNT) k_mg_up(const Tile* __restrict__ tiles,
   const int i0 = t.i0, j0 = t.j0;
   for (int k = threadIdx.x; k < RY * (RX + 1); k += kNT) {
     const int rj = k / (RX + 1), ri = k - rj * (RX + 1);
-    const int j = j0 - H + rj, i = wrap(i0 - H + ri, nx);
+    const int j = j0 - H + rj, i = wrap_any(i0 - H + ri, nx);
     s_ax[k] = (j >= 0 && j < ny) ? ldS<S>(L.ax, (size_t)j * nx + i) : S(0);
   }
   for (int k = threadIdx.x; k < (RY + 1) * RX; k += kNT) {
     const int rj = k / RX, ri = k - rj * RX;
-    const int j = j0 - H + rj, i = wrap(i0 - H + ri, nx);
+    const int j = j0 - H + rj, i = wrap_any(i0 - H + ri, nx);
     s_ay[k] = (j >= 0 && j <= ny) ? ldS<S>(L.ay, (size_t)j * nx + i) : S(0);
   }
   const S* e = (const S*)C.z;
   for (int k = threadIdx.x; k < RY * RX; k += kNT) {
     const int rj = k / RX, ri = k - rj * RX;
-    const int j = j0 - H + rj, i = wrap(i0 - H + ri, nx);
+    const int j = j0 - H + rj, i = wrap_any(i0 - H + ri, nx);
     S r = 0, z = 0;
     if (j >= 0 && j < ny) {
       const size_t o = (size_t)j * nx + i;

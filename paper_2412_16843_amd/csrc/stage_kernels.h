@@ -13,6 +13,12 @@ namespace cdi {
 // tile of the cell kernels: TX x TY cells, one cell per thread
 constexpr int TX = 64, TY = 4;
 static_assert(TX * TY == kNT, "cell tile must match the block size");
+// wide tile of the pointwise / 5-point CG kernels: TX x (WR * TY) cells, WR
+// rows per thread (fewer blocks, fewer per-block reductions and shorter
+// halos on large grids; WR = 1 keeps more, shorter blocks for small ones)
+constexpr int kWideRows[2] = {1, 4};
+__device__ __forceinline__ int wide_tx() { return threadIdx.x % TX; }
+__device__ __forceinline__ int wide_ty(int r) { return threadIdx.x / TX + r * TY; }
 
 // ---------------------------------------------------------------- wall GNBC
 // Contact-line slip u^Y at wall corner i (Sec. 2 eq. u_slip_Y; Sec. 3 Models
@@ -108,7 +114,7 @@ __device__ __forceinline__ void phase_prep_tile(const Tile& t, const Inst& I, in
   const double* __restrict__ phi = src == 0 ? I.phi : (src == 1 ? I.phi_a : I.phi_b);
   for (int k = tid; active && k < RY * RX; k += kNT) {
     const int rj = k / RX, ri = k - rj * RX;
-    const int j = t.j0 - 3 + rj, i = wrap(t.i0 - 1 + ri, nx);
+    const int j = t.j0 - 3 + rj, i = wrap_any(t.i0 - 1 + ri, nx);
     double f = 0.0, ps = 0.0;
     if (j >= 0 && j < ny) {
       f = phi[(size_t)j * nx + i];
@@ -248,7 +254,7 @@ __device__ __forceinline__ void stage_tile(const Tile& t, const Inst& I, int k, 
 
   for (int q = tid; active && q < CY * CX; q += kNT) {
     const int rj = q / CX, ri = q - rj * CX;
-    const int j = j0 - 2 + rj, i = wrap(i0 - 2 + ri, nx);
+    const int j = j0 - 2 + rj, i = wrap_any(i0 - 2 + ri, nx);
     S a = 0, b = 0, c = 0, d = 0;
     if (j >= 0 && j < ny) {
       const size_t o = (size_t)j * nx + i;
@@ -258,7 +264,7 @@ __device__ __forceinline__ void stage_tile(const Tile& t, const Inst& I, int k, 
   }
   for (int q = tid; active && q < UY * UX; q += kNT) {
     const int rj = q / UX, ri = q - rj * UX;
-    const int j = j0 - 1 + rj, i = wrap(i0 - 1 + ri, nx);
+    const int j = j0 - 1 + rj, i = wrap_any(i0 - 1 + ri, nx);
     s_u[q] = (j >= 0 && j < ny) ? (S)us[(size_t)j * nx + i] : S(0);
     s_v[q] = (j >= 0 && j <= ny) ? (S)vs[(size_t)j * nx + i] : S(0);
   }

@@ -113,13 +113,44 @@ class CDISolver:
                          relres=info.relres, bnorm=info.bnorm, ms=info.ms, status=st)
 
     def set_launch(self, mode: str) -> None:
-        """How cdi_step enqueues a step: "tiled" or "persistent"."""
+        """How cdi_step enqueues a step: "tiled", "persistent" or "graph"."""
         L.check(self.lib.cdi_set_launch(self.ctx, L.LAUNCH[mode]))
 
     def get_launch(self) -> str:
         m = C.c_int32()
         L.check(self.lib.cdi_get_launch(self.ctx, C.byref(m)))
         return {v: k for k, v in L.LAUNCH.items()}[m.value]
+
+    def graph_stats(self) -> Dict[str, int]:
+        r, m, b = C.c_int64(), C.c_int64(), C.c_int32()
+        L.check(self.lib.cdi_graph_stats(self.ctx, C.byref(r), C.byref(m), C.byref(b)))
+        return dict(replays=r.value, redone=m.value, budget=b.value)
+
+    def set_tile_rows(self, rows: int) -> None:
+        """Rows per thread of the wide-tile CG kernels (1 or 4)."""
+        L.check(self.lib.cdi_set_tile_rows(self.ctx, int(rows)))
+
+    def get_tile_rows(self) -> int:
+        m = C.c_int32()
+        L.check(self.lib.cdi_get_tile_rows(self.ctx, C.byref(m)))
+        return m.value
+
+    def tune(self, trial_steps: int = 10) -> Dict:
+        """Time every launch candidate from the current state (restored
+        afterwards) and keep the fastest; returns the choice and timings."""
+        nb = self.lib.cdi_tune_bytes(self.ctx)
+        scratch = torch.empty(nb + 256, dtype=torch.uint8, device=self.device)
+        ptr = scratch.data_ptr() + (-scratch.data_ptr()) % 256
+        info = L.cdi_tune_info()
+        L.check(self.lib.cdi_tune(self.ctx, int(trial_steps), ptr, nb, C.byref(info)))
+        torch.cuda.synchronize(self.device)
+        del scratch
+        names = {v: k for k, v in L.LAUNCH.items()}
+        return dict(launch=names[info.launch], tile_rows=info.tile_rows,
+                    ms_per_step={"tiled_rows1": info.ms_per_step[0],
+                                 "tiled_rows4": info.ms_per_step[1],
+                                 "persistent": info.ms_per_step[2],
+                                 "graph": info.ms_per_step[3]})
 
     def set_guess(self, mode: str) -> None:
         """Initial-guess mode of later solves: "zero", "prev" or "learned"."""

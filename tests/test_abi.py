@@ -39,7 +39,8 @@ def test_struct_layouts_match_header():
     structs = {m.group(2): m.group(1)
                for m in re.finditer(r"typedef struct \{([^}]*)\}\s*(\w+);", text)}
     for cname, py in (("cdi_params", L.cdi_params), ("cdi_fields", L.cdi_fields),
-                      ("cdi_solve_info", L.cdi_solve_info), ("cdi_diag", L.cdi_diag)):
+                      ("cdi_solve_info", L.cdi_solve_info), ("cdi_diag", L.cdi_diag),
+                      ("cdi_tune_info", L.cdi_tune_info)):
         body = structs[cname]
         body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
         names = []

@@ -163,3 +163,40 @@ def test_switching_launch_mid_run_keeps_the_trajectory():
     ref, _ = _oracle(case, 9)
     errs = {k: relerr(g[k], ref[k]) for k in FIELDS}
     assert max(errs.values()) < 1e-10, errs
+
+
+@pytest.mark.parametrize("rows", [1, 4])
+def test_wide_tile_rows_match_oracle(rows):
+    """Both wide-tile shapes of the CG kernels (1 and 4 rows per thread)."""
+    case = W.drop_case(128, 64, 60.0, 10.0)
+    s = _solver(case.params, case.phi0, rtol=1e-13, maxit=400)
+    s.set_tile_rows(rows)
+    assert s.get_tile_rows() == rows
+    s.step(4)
+    g = s.state()
+    s.close()
+    ref, _ = _oracle(case, 4)
+    errs = {k: relerr(g[k], ref[k]) for k in FIELDS}
+    assert max(errs.values()) < 1e-10, errs
+
+
+def test_autotune_restores_state_and_keeps_the_trajectory():
+    """cdi_tune times every candidate from a saved state and restores it:
+    the run continues as if the tuner had not run."""
+    case = W.drop_case(64, 32, 60.0, 10.0)
+    s = _solver(case.params, case.phi0, rtol=1e-13, maxit=400)
+    s.step(3)
+    d0 = s.diagnostics()
+    info = s.tune(trial_steps=3)
+    print("tune:", info)
+    assert info["launch"] in ("tiled", "persistent")
+    assert all(v > 0 for v in info["ms_per_step"].values())
+    d1 = s.diagnostics()
+    assert d1["step"] == d0["step"] and d1["t"] == d0["t"]
+    assert d1["mass"] == d0["mass"]
+    s.step(3)
+    g = s.state()
+    s.close()
+    ref, _ = _oracle(case, 6)
+    errs = {k: relerr(g[k], ref[k]) for k in FIELDS}
+    assert max(errs.values()) < 1e-10, errs
