@@ -421,12 +421,12 @@ void launch_vcycle(cdi_ctx* c, int update, int dpar, int rsel) {
 
 template <typename S>
 void launch_coef(cdi_ctx* c) {
-  int maxc = 0;
-  for (int k = 0; k < c->B.n; ++k)
-    if (c->B.R[k].nlev > 1) maxc = std::max(maxc, c->B.R[k].lnx[1] * (c->B.R[k].lny[1] + 1));
-  if (maxc > 0) {
-    const dim3 grid((unsigned)std::max(1, std::min(256, ceil_div(maxc, kNT))), (unsigned)c->B.n);
-    timed(c, "mg_coef", [&] { k_mg_coef<S><<<grid, kNT, 0, c->stream>>>(c->d_inst); });
+  for (int l = 1; l < c->B.max_nlev; ++l) {
+    int maxc = 0;
+    for (int k = 0; k < c->B.n; ++k)
+      if (c->B.R[k].nlev > l) maxc = std::max(maxc, c->B.R[k].lnx[l] * (c->B.R[k].lny[l] + 1));
+    const dim3 grid((unsigned)std::max(1, std::min(1024, ceil_div(maxc, kNT))), (unsigned)c->B.n);
+    timed(c, "mg_coef", [&] { k_mg_coef<S><<<grid, kNT, 0, c->stream>>>(c->d_inst, l); });
   }
   timed(c, "mg_coef", [&] { k_coarse_inv<S><<<(unsigned)c->B.n, kCoarseNT, 0, c->stream>>>(c->d_inst); });
 }

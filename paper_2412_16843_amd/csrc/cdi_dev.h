@@ -102,6 +102,21 @@ struct Tile {
 // ---------------------------------------------------------------- helpers
 __device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
+// Quotient by a runtime divisor d >= 1 for 0 <= n < 2^24: a float reciprocal
+// estimate corrected by one exact integer step (the GPU has no integer
+// divide instruction; the generic one costs tens of operations).
+struct FastDiv {
+  int d;
+  float inv;
+  __device__ __forceinline__ explicit FastDiv(int d_) : d(d_), inv(1.0f / (float)d_) {}
+  __device__ __forceinline__ int div(int n) const {
+    int q = (int)((float)n * inv);
+    const int r = n - q * d;
+    q += (r >= d) - (r < 0);
+    return q;
+  }
+};
+
 // Periodic index for any offset: halo columns of a tile wider than the grid
 // can lie more than one period away.
 __device__ __forceinline__ int wrap_any(int i, int n) {

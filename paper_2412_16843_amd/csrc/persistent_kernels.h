@@ -64,13 +64,14 @@ __device__ int persist_solve(const Inst& I, PersistLds<S>& L, int guess,
                              double& xmean, double& relres, bool& converged) {
   const int nx = I.nx, ny = I.ny, n = nx * ny;
   const int tid = threadIdx.x;
+  const FastDiv dn(nx);
   double* x = I.x;
   double* r = I.rr;
   double* d = I.d0;
   double* q = I.q;
   double s2[2] = {0.0, 0.0};
   for (int c = tid; c < n; c += PNT) {
-    const int j = c / nx, i = c - j * nx;
+    const int j = dn.div(c), i = c - j * nx;
     double f, rv;
     pcg_init_cell(I, guess, stage, j, i, bmean, f, rv);
     s2[0] += f * f;
@@ -107,7 +108,7 @@ __device__ int persist_solve(const Inst& I, PersistLds<S>& L, int guess,
     __syncthreads();
     double dd[2] = {0.0, 0.0};
     for (int c = tid; c < n; c += PNT) {
-      const int j = c / nx, i = c - j * nx;
+      const int j = dn.div(c), i = c - j * nx;
       const double qv = apply_K(I, d, j, i);
       q[c] = qv;
       dd[0] += d[c] * r[c];
@@ -150,6 +151,7 @@ __global__ void __launch_bounds__(PNT) k_step_persistent(const Tile* __restrict_
   PcgScalars* P = I.pcg;
   const int tid = threadIdx.x, q4 = tid / kNT, lt = tid - q4 * kNT;
   const int nx = I.nx, ny = I.ny, n = nx * ny;
+  const FastDiv dn(nx);
   const bool variable_rho = I.rho1 != I.rho2;
   const double RKc[4] = {0.5, 0.5, 1.0, 1.0};
   const double RKb[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
@@ -179,14 +181,16 @@ __global__ void __launch_bounds__(PNT) k_step_persistent(const Tile* __restrict_
       const double tfac = RKc[k];
       double bs[1] = {0.0};
       for (int c = tid; c < n; c += PNT) {
-        const int j = c / nx, i = c - j * nx;
+        const int j = dn.div(c), i = c - j * nx;
         bs[0] += rhs_cell<S>(I, phd, j, i, tfac);
       }
       pall_sum<1>(bs, L.red, L.sc);
       const double bmean = bs[0] / n;
       if (variable_rho || !coef_done) {
-        mg_coef_levels<S>(I, tid, PNT);
-        __syncthreads();
+        for (int l = 1; l < I.nlev; ++l) {
+          mg_coef_level<S>(I, l, tid, PNT);
+          __syncthreads();
+        }
         coarse_inverse<S>(I, L.u.B, L.red, L.sc);
         __syncthreads();
         coef_done = true;
@@ -211,7 +215,7 @@ __global__ void __launch_bounds__(PNT) k_step_persistent(const Tile* __restrict_
         P->done = 1;
       }
       for (int c = tid; c < n; c += PNT) {
-        const int j = c / nx, i = c - j * nx;
+        const int j = dn.div(c), i = c - j * nx;
         project_cell(I, tfac, k == 3, phd, k, zero, xmean, j, i);
       }
       __syncthreads();

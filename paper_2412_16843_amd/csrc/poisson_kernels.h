@@ -733,16 +733,19 @@ template <typename S, typename ViewF>
 __device__ __forceinline__ void mg_cycle(const Inst& I, const ViewF& V, int lo, int nl,
                                          double* s_red, double* s_sc) {
   const int tid = threadIdx.x;
+  // cells of one colour only: h-th cell of colour `color` is row j = h / (nx/2),
+  // column i = 2 (h mod nx/2) + ((j + color) & 1)  (swept levels have even nx)
   auto sweep = [&](int l, int color, bool from_zero) {
     const MgView<S> Lv = V(l);
-    const int nx = Lv.nx, ny = Lv.ny;
+    const int nx = Lv.nx, ny = Lv.ny, hx = nx >> 1;
+    const FastDiv dh(hx);
     const S* ax = Lv.ax;
     const S* ay = Lv.ay;
     const S* r = Lv.r;
     S* z = Lv.z;
-    for (int c = tid; c < nx * ny; c += kCoarseNT) {
-      const int j = c / nx, i = c - j * nx;
-      if (((i + j) & 1) != color) continue;
+    for (int h = tid; h < hx * ny; h += kCoarseNT) {
+      const int j = dh.div(h), i = 2 * (h - j * hx) + ((j + color) & 1);
+      const int c = j * nx + i;
       const int ie = wrap(i + 1, nx), iw = wrap(i - 1, nx);
       const S aw = ax[c], ae = ax[j * nx + ie], as = ay[c], an = ay[c + nx];
       const S D = aw + ae + as + an;
@@ -767,8 +770,9 @@ __device__ __forceinline__ void mg_cycle(const Inst& I, const ViewF& V, int lo, 
       const S* r = Lv.r;
       const S* z = Lv.z;
       S* t = Lv.t;
+      const FastDiv dn(nx);
       for (int c = tid; c < nx * ny; c += kCoarseNT) {
-        const int j = c / nx, i = c - j * nx;
+        const int j = dn.div(c), i = c - j * nx;
         const int ie = wrap(i + 1, nx), iw = wrap(i - 1, nx);
         const S zc = z[c];
         S kz = ax[c] * (zc - z[j * nx + iw]) + ax[j * nx + ie] * (zc - z[j * nx + ie]);
@@ -782,8 +786,9 @@ __device__ __forceinline__ void mg_cycle(const Inst& I, const ViewF& V, int lo, 
       const int cnx = Cv.nx, cny = Cv.ny;
       const S* t = Lv.t;
       S* rc = Cv.r;
+      const FastDiv dc(cnx);
       for (int c = tid; c < cnx * cny; c += kCoarseNT) {
-        const int J = c / cnx, Ic = c - J * cnx;
+        const int J = dc.div(c), Ic = c - J * cnx;
         S wy[4] = {S(0.25), S(0.75), S(0.75), S(0.25)};
         if (J == 0) { wy[0] = S(0); wy[1] = S(1); }
         if (J == cny - 1) { wy[3] = S(0); wy[2] = S(1); }
@@ -879,8 +884,9 @@ __device__ __forceinline__ void mg_cycle(const Inst& I, const ViewF& V, int lo, 
     const int cnx = Cv.nx, cny = Cv.ny;
     S* z = Lv.z;
     const S* e = Cv.z;
+    const FastDiv dn(nx);
     for (int c = tid; c < nx * ny; c += kCoarseNT) {
-      const int j = c / nx, i = c - j * nx;
+      const int j = dn.div(c), i = c - j * nx;
       z[c] += prolong<S>(e, cnx, cny, j, i);
     }
     __syncthreads();
@@ -998,37 +1004,35 @@ __global__ void __launch_bounds__(kCoarseNT) k_mg_coarse(const Inst* __restrict_
   }
 }
 
-// Coarse-level coefficients of every level l >= 1, straight from level 0:
-// the mean of the 2^l fine faces covering a coarse face, times 4^-l (each
-// halving doubles h); identical to averaging pairs level by level.
+// Coarse-level coefficients of level l from level l-1: a coarse face covers
+// two fine faces; its coefficient is their mean times 1/4 (h doubles).
+// Level by level this is the mean of the 2^l level-0 faces times 4^-l, with
+// coalesced (stride-2) reads instead of stride-2^l ones.
 template <typename S>
-__device__ __forceinline__ void mg_coef_levels(const Inst& I, int start, int stride) {
-  const Level& F = I.lev[0];
+__device__ __forceinline__ void mg_coef_level(const Inst& I, int l, int start, int stride) {
+  const Level& F = I.lev[l - 1];
+  const Level& C = I.lev[l];
   const S* fax = (const S*)F.ax;
   const S* fay = (const S*)F.ay;
-  for (int l = 1; l < I.nlev; ++l) {
-    const Level& C = I.lev[l];
-    const int m = 1 << l;
-    const S scale = S(1.0 / ((double)m * m * m));   // mean over m faces times 4^-l
-    const int n = C.nx * (C.ny + 1);
-    for (int c = start; c < n; c += stride) {
-      const int J = c / C.nx, Ic = c - J * C.nx;
-      if (J < C.ny) {
-        S a = 0;
-        for (int k = 0; k < m; ++k) a += fax[(size_t)(J * m + k) * F.nx + Ic * m];
-        ((S*)C.ax)[(size_t)J * C.nx + Ic] = a * scale;
-      }
-      S b = 0;
-      if (J >= 1 && J < C.ny)
-        for (int k = 0; k < m; ++k) b += fay[(size_t)(J * m) * F.nx + Ic * m + k];
-      ((S*)C.ay)[(size_t)J * C.nx + Ic] = b * scale;
-    }
+  const int n = C.nx * (C.ny + 1);
+  for (int c = start; c < n; c += stride) {
+    const int J = c / C.nx, Ic = c - J * C.nx;
+    if (J < C.ny)
+      ((S*)C.ax)[c] = (fax[(size_t)(2 * J) * F.nx + 2 * Ic] + fax[(size_t)(2 * J + 1) * F.nx + 2 * Ic]) *
+                      S(0.125);
+    S b = 0;
+    if (J >= 1 && J < C.ny)
+      b = (fay[(size_t)(2 * J) * F.nx + 2 * Ic] + fay[(size_t)(2 * J) * F.nx + 2 * Ic + 1]) * S(0.125);
+    ((S*)C.ay)[c] = b;
   }
 }
 
+// Level l of every instance that has it (grid.y = instance).
 template <typename S>
-__global__ void __launch_bounds__(kNT) k_mg_coef(const Inst* __restrict__ insts) {
-  mg_coef_levels<S>(insts[blockIdx.y], blockIdx.x * kNT + threadIdx.x, gridDim.x * kNT);
+__global__ void __launch_bounds__(kNT) k_mg_coef(const Inst* __restrict__ insts, int l) {
+  const Inst& I = insts[blockIdx.y];
+  if (l >= I.nlev) return;
+  mg_coef_level<S>(I, l, blockIdx.x * kNT + threadIdx.x, gridDim.x * kNT);
 }
 
 // Dense inverse of the coarsest operator K_c + s 11^T / n (s its mean
@@ -1067,16 +1071,16 @@ __device__ __forceinline__ void coarse_inverse(const Inst& I, double* B, double*
   __syncthreads();
   constexpr int PER = (kDenseMax * kDenseMax + kCoarseNT - 1) / kCoarseNT;
   for (int k = 0; k < n; ++k) {
-    const double piv = B[k * n + k];
+    const double ipiv = 1.0 / B[k * n + k];
     double nv[PER];
     int cnt = 0;
     for (int e = tid; e < n * n; e += kCoarseNT, ++cnt) {
       const int r = e / n, c = e - r * n;
       double v;
-      if (r == k && c == k) v = 1.0 / piv;
-      else if (r == k) v = B[k * n + c] / piv;
-      else if (c == k) v = -B[r * n + k] / piv;
-      else v = B[e] - B[r * n + k] * B[k * n + c] / piv;
+      if (r == k && c == k) v = ipiv;
+      else if (r == k) v = B[k * n + c] * ipiv;
+      else if (c == k) v = -B[r * n + k] * ipiv;
+      else v = B[e] - B[r * n + k] * (B[k * n + c] * ipiv);
       nv[cnt] = v;
     }
     __syncthreads();
