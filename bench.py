@@ -49,8 +49,11 @@ ALGO_BYTES_PER_CELL = {
     "mg_up": 5 * 8 + 2 + 8,
     # z, d_old, a_x, a_y, r read; d, q written
     "pcg_spmv": 5 * 8 + 2 * 8,
-    # u*, v*, x, a_x, a_y read; u, v, p written
-    "project": 5 * 8 + 3 * 8,
+    # u*, v*, x, a_x, a_y read; u, v, p written; per-stage pressure history
+    # (read ph, write ph2 and ph); final stage only: next phi copied (1/4)
+    "project": 5 * 8 + 3 * 8 + 3 * 8 + 16 / 4,
+    # b, guess (two history fields), a_x, a_y read; x, r written
+    "pcg_init": 5 * 8 + 2 * 8,
 }
 
 
@@ -79,6 +82,71 @@ def algo_bytes_per_launch(fam: str, p) -> float:
         n = sum(a * b for a, b in levels[lc:])
         return 8 * (2 * levels[lc][0] * levels[lc][1] + 2 * n)
     raise KeyError(fam)
+
+
+def traffic_record(fam: str, workload_name: str):
+    """HBM bytes per launch of kernel family `fam` from the committed
+    rocprofv3 --pmc summary, if it was taken on the current sources."""
+    from paper_2412_16843_amd import rocprof_summary as R
+    path = os.path.join(ROOT, "profiles", f"k_{fam}_{workload_name}_traffic.md")
+    rec = R.read_record(path)
+    if not rec or rec.get("src_sha256") != R.source_hash() or rec.get("kernel") != f"k_{fam}":
+        return None
+    return rec["read_bytes_per_launch"] + rec["write_bytes_per_launch"]
+
+
+# algorithmic bytes per fine cell of the multigrid levels below the finest,
+# per CG iteration (each level moves r, a_x, a_y in, z out and the coarse r on
+# the way down, r, a_x, a_y, z in and z out on the way up: ~74 B per level
+# cell, a quarter of the cells per level)
+MG_COARSE_BYTES_PER_FINE_CELL = 74.0 / 3.0
+
+
+def step_bytes_per_cell(iters_per_step: float) -> float:
+    """Algorithmic bytes per cell of one RK4 step with `iters_per_step` CG
+    iterations summed over its 4 solves."""
+    b = ALGO_BYTES_PER_CELL
+    per_stage = b["phase_prep"] + b["stage"] + b["rhs"] + b["pcg_init"] + b["project"]
+    per_iter = b["pcg_spmv"] + b["mg_down"] + b["mg_up"] + MG_COARSE_BYTES_PER_FINE_CELL
+    return 4 * per_stage + iters_per_step * per_iter
+
+
+def hbm_case(CDISolver, nx: int = 2048, steps: int = 10):
+    """Per-kernel algorithmic bandwidth on an nx x nx/2 density-ratio-10 drop
+    (FP64), where the stencil and multigrid kernels are bandwidth bound, and
+    the whole step's algorithmic bytes over its time."""
+    import torch
+    case = W.drop_case(nx, nx // 2, 60.0, 10.0, name=f"drop{nx}x{nx // 2}_r10")
+    s = CDISolver(case.params, case.phi0, guess="prev", rtol=1e-10)
+    s.step(3)
+    out = {"workload": case.name, "peak": HBM_PEAK_GBS, "unit": "GB/s", "kernels": {}}
+    probe = 2
+    iters_per_step = None
+    for fam in ("stage", "phase_prep", "rhs", "pcg_init", "mg_down", "mg_up", "pcg_spmv",
+                "project"):
+        s.timing_enable(fam)
+        s.step(probe)
+        ms, n = s.timing_read()
+        avg = ms / max(n, 1) * 1e-3
+        gbs = algo_bytes_per_launch(fam, case.params) / avg / 1e9 if avg > 0 else 0.0
+        out["kernels"][fam] = {"achieved": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+                               "avg_launch_us": round(avg * 1e6, 2)}
+        if fam == "pcg_spmv":
+            iters_per_step = n / probe
+    s.timing_enable(None)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    cells = case.params.nx * case.params.ny
+    out["mcell_steps_per_s"] = round(cells * steps / dt / 1e6, 2)
+    bpc = step_bytes_per_cell(iters_per_step)
+    out["step"] = {"cg_iters_per_step": iters_per_step, "algo_bytes_per_cell": round(bpc, 1),
+                   "achieved": round(bpc * cells * steps / dt / 1e9, 1),
+                   "frac": round(bpc * cells * steps / dt / 1e9 / HBM_PEAK_GBS, 4)}
+    s.close()
+    return out
 
 
 def workload(name: str):
@@ -186,6 +254,10 @@ def main():
     ap.add_argument("--launch", default="auto", choices=["auto", "tiled", "persistent"],
                     help="auto: the library's autotuner picks the launch form and tile shape")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-hbm-case", action="store_true",
+                    help="skip the per-kernel HBM fractions on the 2048x1024 grid")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="end with a 256 MiB device copy (calibrates rocprofv3 --pmc byte counters)")
     ap.add_argument("--poisson", action="store_true",
                     help="add the learned-vs-plain pressure time-to-solution at 2048x1024")
     args = ap.parse_args()
@@ -255,11 +327,23 @@ def main():
                    "parallelism": "single-gpu"},
         "roofline": {"bound": "hbm", "kernel": fam, "achieved": round(achieved, 2),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 5),
+                     "traffic": traffic_record(fam, case.name),
                      "launches": k_n, "avg_launch_us": round(avg_s * 1e6, 3),
                      "algo_bytes_per_launch": per_launch_bytes},
     }
     s.close()
+    if args.copy_calibration:
+        n = 256 * 2**20 // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    if not args.no_hbm_case:
+        # 2048x1024: ~0.5 GB of state, mostly served by the 256 MB MALL;
+        # 8192x4096: ~8 GB, DRAM bound
+        out["roofline_hbm_case"] = [hbm_case(CDISolver, 2048), hbm_case(CDISolver, 8192, steps=3)]
     if args.poisson:
         out["poisson_learned_vs_plain"] = poisson_learned_vs_plain()
     if not args.no_cpu:

@@ -2,6 +2,7 @@
 // workspace layout, tile lists spanning every instance of a batch, and the
 // stream-ordered launch sequence of one RK4 step (4 stage evaluations, 4
 // variable-density projections by multigrid-preconditioned flexible CG).
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -354,6 +355,7 @@ struct cdi_ctx {
   std::string timed;
   std::vector<hipEvent_t> tev;
   int tev_used = 0;
+  hipEvent_t kev0 = nullptr, kev1 = nullptr;   // events of the launch being measured
   double timed_ms = 0.0;
   long timed_launches = 0;
 };
@@ -388,14 +390,29 @@ hipError_t timing_flush(cdi_ctx* c) {
 // Launch `body` and, when `name` is the kernel family being measured,
 // bracket it with events on the context stream.
 template <typename F>
-void timed(cdi_ctx* c, const char* name, F&& body) {
+void timed(cdi_ctx* c, const char* name, F&& body, bool single = true) {
   if (c->timed.empty() || c->timed != name) { body(); return; }
   if (c->tev_used == kTimedPairs) (void)timing_flush(c);
-  (void)hipEventRecord(c->tev[2 * c->tev_used], c->stream);
-  body();
-  (void)hipEventRecord(c->tev[2 * c->tev_used + 1], c->stream);
+  hipEvent_t e0 = c->tev[2 * c->tev_used], e1 = c->tev[2 * c->tev_used + 1];
+  if (single) {
+    // one kernel: its own begin / end timestamps (the launch carries the events)
+    c->kev0 = e0;
+    c->kev1 = e1;
+    body();
+    c->kev0 = c->kev1 = nullptr;
+  } else {
+    (void)hipEventRecord(e0, c->stream);
+    body();
+    (void)hipEventRecord(e1, c->stream);
+  }
   c->tev_used += 1;
 }
+
+// Launch on the context stream; while a kernel family is being measured the
+// launch records the kernel's start and end in the family's event pair.
+#define CDI_LAUNCH(c, kern, grid, block, ...)                                          \
+  hipExtLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, (c)->stream, (c)->kev0,     \
+                        (c)->kev1, 0, __VA_ARGS__)
 
 // V-cycle z = M r over every instance.  update: the first kernel applies the
 // CG step (d from buffer dpar) and the stopping test; rsel: residual buffer
@@ -406,16 +423,16 @@ void launch_vcycle(cdi_ctx* c, int update, int dpar, int rsel) {
   for (int l = 0; l < B.max_lc; ++l)
     if (!B.mg[l].empty())
       timed(c, (l == 0 && update) ? "mg_down" : "mg_down_other", [&] {
-        k_mg_down<S><<<(unsigned)B.mg[l].size(), kNT, 0, c->stream>>>(c->d_mg[l], c->d_inst, l,
+        CDI_LAUNCH(c, k_mg_down<S>, (unsigned)B.mg[l].size(), kNT, c->d_mg[l], c->d_inst, l,
                                                                       update, dpar, rsel);
       });
   timed(c, "mg_coarse", [&] {
-    k_mg_coarse<S><<<(unsigned)B.n, kCoarseNT, 0, c->stream>>>(c->d_inst, update, dpar, rsel);
+    CDI_LAUNCH(c, k_mg_coarse<S>, (unsigned)B.n, kCoarseNT, c->d_inst, update, dpar, rsel);
   });
   for (int l = B.max_lc - 1; l >= 0; --l)
     if (!B.mg[l].empty())
       timed(c, l == 0 ? "mg_up" : "mg_up_other", [&] {
-        k_mg_up<S><<<(unsigned)B.mg[l].size(), kNT, 0, c->stream>>>(c->d_mg[l], c->d_inst, l, rsel);
+        CDI_LAUNCH(c, k_mg_up<S>, (unsigned)B.mg[l].size(), kNT, c->d_mg[l], c->d_inst, l, rsel);
       });
 }
 
@@ -426,9 +443,9 @@ void launch_coef(cdi_ctx* c) {
     for (int k = 0; k < c->B.n; ++k)
       if (c->B.R[k].nlev > l) maxc = std::max(maxc, c->B.R[k].lnx[l] * (c->B.R[k].lny[l] + 1));
     const dim3 grid((unsigned)std::max(1, std::min(1024, ceil_div(maxc, kNT))), (unsigned)c->B.n);
-    timed(c, "mg_coef", [&] { k_mg_coef<S><<<grid, kNT, 0, c->stream>>>(c->d_inst, l); });
+    timed(c, "mg_coef", [&] { CDI_LAUNCH(c, k_mg_coef<S>, grid, kNT, c->d_inst, l); });
   }
-  timed(c, "mg_coef", [&] { k_coarse_inv<S><<<(unsigned)c->B.n, kCoarseNT, 0, c->stream>>>(c->d_inst); });
+  timed(c, "mg_coef", [&] { CDI_LAUNCH(c, k_coarse_inv<S>, (unsigned)c->B.n, kCoarseNT, c->d_inst); });
 }
 
 // Flexible-CG loop after the right-hand side is in place.  Returns NOCONV
@@ -443,7 +460,7 @@ cdi_status solve_loop(cdi_ctx* c, int guess, int stage) {
   }
   timed(c, "pcg_init", [&] {
     with_rows(c->wide_rows, [&](auto R) {
-      k_pcg_init<decltype(R)::value><<<nwide, kNT, 0, c->stream>>>(c->d_wide, c->d_inst, guess, stage);
+      CDI_LAUNCH(c, k_pcg_init<decltype(R)::value>, nwide, kNT, c->d_wide, c->d_inst, guess, stage);
     });
   });
   // z0 = M r0 (residual in buffer 0)
@@ -455,7 +472,7 @@ cdi_status solve_loop(cdi_ctx* c, int guess, int stage) {
     const int par = it & 1;
     timed(c, "pcg_spmv", [&] {
       with_rows(c->wide_rows, [&](auto R) {
-        k_pcg_spmv<decltype(R)::value><<<nwide, kNT, 0, c->stream>>>(c->d_wide, c->d_inst, par, par);
+        CDI_LAUNCH(c, k_pcg_spmv<decltype(R)::value>, nwide, kNT, c->d_wide, c->d_inst, par, par);
       });
     });
     launch_vcycle<S>(c, 1, par, par ^ 1);
@@ -478,7 +495,7 @@ cdi_status solve_loop(cdi_ctx* c, int guess, int stage) {
   }
   timed(c, "pcg_xmean", [&] {
     with_rows(c->wide_rows, [&](auto R) {
-      k_pcg_xmean<decltype(R)::value><<<nwide, kNT, 0, c->stream>>>(c->d_wide, c->d_inst);
+      CDI_LAUNCH(c, k_pcg_xmean<decltype(R)::value>, nwide, kNT, c->d_wide, c->d_inst);
     });
   });
   int maxi = 0;
@@ -510,13 +527,13 @@ void learned_guess(cdi_ctx* c, int src) {
   const double* phi = src == 0 ? I.phi : (src == 1 ? I.phi_a : I.phi_b);
   const unsigned g = (unsigned)std::min(1024, ceil_div(I.nx * I.ny, kNT));
   timed(c, "net", [&] {
-    k_features<<<g, kNT, 0, c->stream>>>(c->d_inst, 0, phi, nullptr, cdinet::features(c->net), nullptr);
+    CDI_LAUNCH(c, k_features, g, kNT, c->d_inst, 0, phi, nullptr, cdinet::features(c->net), nullptr);
     cdinet::forward(c->net);
-    k_guess_apply<<<g, kNT, 0, c->stream>>>(c->d_inst, cdinet::output(c->net));
+    CDI_LAUNCH(c, k_guess_apply, g, kNT, c->d_inst, cdinet::output(c->net));
     with_rows(c->wide_rows, [&](auto R) {
       k_guess_fit<decltype(R)::value><<<(unsigned)c->B.wide.size(), kNT, 0, c->stream>>>(c->d_wide, c->d_inst);
     });
-  });
+  }, false);
 }
 
 template <typename S>
@@ -529,16 +546,16 @@ cdi_status run_step(cdi_ctx* c) {
   for (int k = 0; k < 4; ++k) {
     const int src = k == 0 ? 0 : (k == 2 ? 2 : 1);
     const int dst = (k == 0 || k == 2) ? 1 : 2;
-    timed(c, "phase_prep", [&] { k_phase_prep<S><<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, src); });
+    timed(c, "phase_prep", [&] { CDI_LAUNCH(c, k_phase_prep<S>, ncell, kNT, c->d_cell, c->d_inst, src); });
     // per-instance dt: c_next and tau are passed as multiples of the instance dt
     timed(c, "stage", [&] {
-      k_stage<S><<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, k, src, dst,
+      CDI_LAUNCH(c, k_stage<S>, ncell, kNT, c->d_cell, c->d_inst, k, src, dst,
                                                 k < 3 ? RK_C[k + 1] : 1.0, RK_B[k], k == 3);
     });
     const double tfac = k < 3 ? RK_C[k + 1] : 1.0;
     timed(c, "rhs", [&] {
       with_rows(c->wide_rows, [&](auto R) {
-        k_rhs<S, decltype(R)::value><<<nwide, kNT, 0, c->stream>>>(c->d_wide, c->d_inst, dst, tfac,
+        CDI_LAUNCH(c, (k_rhs<S, decltype(R)::value>), nwide, kNT, c->d_wide, c->d_inst, dst, tfac,
                                                                    c->rtol, c->maxit);
       });
     });
@@ -552,7 +569,7 @@ cdi_status run_step(cdi_ctx* c) {
     else if (s != CDI_OK) return s;
     timed(c, "project", [&] {
       with_rows(c->wide_rows, [&](auto R) {
-        k_project<decltype(R)::value><<<nwide, kNT, 0, c->stream>>>(c->d_wide, c->d_inst, tfac, k == 3, dst, k);
+        CDI_LAUNCH(c, k_project<decltype(R)::value>, nwide, kNT, c->d_wide, c->d_inst, tfac, k == 3, dst, k);
       });
     });
   }
@@ -748,9 +765,8 @@ cdi_status run_persistent(cdi_ctx* c, int nsteps) {
   for (int done = 0; done < nsteps; done += kPersistChunk) {
     const int m = std::min(kPersistChunk, nsteps - done);
     timed(c, "persistent", [&] {
-      k_step_persistent<S><<<(unsigned)B.n, PNT, 0, c->stream>>>(c->d_cell_inst, c->d_inst, m,
-                                                                 c->hist_steps, gm, c->rtol,
-                                                                 c->maxit, done > 0);
+      CDI_LAUNCH(c, k_step_persistent<S>, (unsigned)B.n, PNT, c->d_cell_inst, c->d_inst, m,
+                 c->hist_steps, gm, c->rtol, c->maxit, (int)(done > 0));
     });
     HIPCHK(hipGetLastError());
     c->hist_steps += m;

@@ -102,15 +102,16 @@ struct Tile {
 // ---------------------------------------------------------------- helpers
 __device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
-// Quotient by a runtime divisor d >= 1 for 0 <= n < 2^24: a float reciprocal
-// estimate corrected by one exact integer step (the GPU has no integer
-// divide instruction; the generic one costs tens of operations).
+// Quotient by a runtime divisor d >= 1 for any non-negative int n: a
+// double-precision reciprocal estimate (off by at most one) corrected by one
+// exact integer step (the GPU has no integer divide instruction; the generic
+// sequence costs tens of operations).
 struct FastDiv {
   int d;
-  float inv;
-  __device__ __forceinline__ explicit FastDiv(int d_) : d(d_), inv(1.0f / (float)d_) {}
+  double inv;
+  __device__ __forceinline__ explicit FastDiv(int d_) : d(d_), inv(1.0 / (double)d_) {}
   __device__ __forceinline__ int div(int n) const {
-    int q = (int)((float)n * inv);
+    int q = (int)((double)n * inv);
     const int r = n - q * d;
     q += (r >= d) - (r < 0);
     return q;
