@@ -323,7 +323,9 @@ def main():
         "config": {"workload": case.name, "nx": p.nx, "ny": p.ny,
                    "precision": args.precision, "poisson_rtol": 1e-10,
                    "last_pcg_iters": d["last_iters"], "launch": s.get_launch(),
-                   "tile_rows": s.get_tile_rows(), "autotune": tuned,
+                   "tile_rows": s.get_tile_rows(), "coarse_cells": s.get_coarse_cells(),
+                   "mg_smooth": s.get_mg_smooth(),
+                   "autotune": tuned,
                    "parallelism": "single-gpu"},
         "roofline": {"bound": "hbm", "kernel": fam, "achieved": round(achieved, 2),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -93,9 +93,9 @@ typedef struct {
   int32_t guess;         /* initial guess of each pressure solve                      */
   double poisson_rtol;   /* stop when ||f - K x||_2 <= rtol ||f||_2; 0 -> 1e-10       */
   int32_t poisson_maxit; /* 0 -> 200                                                  */
-  int32_t mg_smooth;     /* red-black Gauss-Seidel sweeps before and after the coarse
-                            correction on every level; 0 -> 1; only 1 is supported
-                            (larger values return CDI_ERR_ARG)                        */
+  int32_t mg_smooth;     /* red-black Gauss-Seidel sweep pairs before and after the
+                            coarse correction on every level: 1 or 2; 0 -> 1; larger
+                            values return CDI_ERR_ARG; equal across a batch           */
 } cdi_params;
 
 /* Device pointers of one instance's state, layouts as above (caller-owned,
@@ -290,19 +290,37 @@ cdi_status cdi_graph_stats(cdi_ctx* ctx, int64_t* replays, int64_t* redone, int3
 cdi_status cdi_set_tile_rows(cdi_ctx* ctx, int32_t rows);
 cdi_status cdi_get_tile_rows(cdi_ctx* ctx, int32_t* rows);
 
+/* Start of the one-block coarse kernel of the V-cycle: it runs every level
+ * with at most `cells` cells (levels up to 1024 cells in its LDS, larger
+ * ones from global memory); the finer levels run as tiled kernels.  Larger
+ * values mean fewer launches per CG iteration but more work on one compute
+ * unit.  cells in [1024, 2^20]; cdi_init sets 4096. */
+cdi_status cdi_set_coarse_cells(cdi_ctx* ctx, int32_t cells);
+cdi_status cdi_get_coarse_cells(cdi_ctx* ctx, int32_t* cells);
+
+/* Red-black sweep pairs of the V-cycle (1 or 2; the value of mg_smooth at
+ * init).  Changes the iteration count, not the converged solution. */
+cdi_status cdi_set_mg_smooth(cdi_ctx* ctx, int32_t nu);
+cdi_status cdi_get_mg_smooth(cdi_ctx* ctx, int32_t* nu);
+
 /* Autotuner: times `trial_steps` steps (after warm-up steps) of every launch
- * candidate -- tiled with 1 and with 4 rows per thread, persistent, graph
- * (with the faster tiled shape) -- each from the same saved state, restores
- * that state (fields, pressure history, time and step counters), and keeps
- * the fastest candidate for later cdi_step calls.  `scratch` is caller-owned
- * device memory of at least cdi_tune_bytes(ctx) bytes for the saved state.
- * Synchronises the stream. */
+ * candidate -- tiled with 1 and 2 sweep pairs, 1 and 4 rows per thread, the
+ * coarse kernel starting at 1024, 4096 and 16384 cells; persistent (with the
+ * fastest tiled sweep count); graph (with the fastest tiled shape) -- each
+ * from the same saved state, restores that state (fields, pressure history,
+ * time and step counters), and keeps the fastest candidate for later
+ * cdi_step calls.  The pressure still meets poisson_rtol in every candidate.
+ * `scratch` is caller-owned device memory of at least cdi_tune_bytes(ctx)
+ * bytes for the saved state.  Synchronises the stream. */
 typedef struct {
   int32_t launch;          /* chosen CDI_LAUNCH_*                                  */
   int32_t tile_rows;       /* chosen rows per thread (1 or 4)                      */
+  int32_t coarse_cells;    /* chosen coarse-kernel threshold                       */
+  int32_t mg_smooth;       /* chosen sweep pairs                                   */
   int32_t ncand;           /* candidates timed                                     */
   int32_t pad;
-  double ms_per_step[4];   /* tiled/1 row, tiled/4 rows, persistent, graph;
+  double ms_per_step[14];  /* tiled [sweeps 1, 2] x [rows 1, 4] x [coarse 1024,
+                              4096, 16384] (row-major), persistent, graph;
                               -1 = skipped                                         */
 } cdi_tune_info;
 

@@ -27,7 +27,8 @@ EXPORTS = ("cdi_workspace_bytes", "cdi_default_dt", "cdi_init", "cdi_init_batch"
            "cdi_net_backward", "cdi_net_adam", "cdi_net_destroy", "cdi_net_last_error",
            "cdi_set_guess", "cdi_guess_attach", "cdi_guess_features", "cdi_set_launch",
            "cdi_get_launch", "cdi_set_tile_rows", "cdi_get_tile_rows", "cdi_tune_bytes",
-           "cdi_tune", "cdi_graph_stats")
+           "cdi_tune", "cdi_graph_stats", "cdi_set_coarse_cells", "cdi_get_coarse_cells",
+           "cdi_set_mg_smooth", "cdi_get_mg_smooth")
 
 
 class cdi_params(C.Structure):
@@ -61,8 +62,9 @@ class cdi_diag(C.Structure):
 
 
 class cdi_tune_info(C.Structure):
-    _fields_ = [("launch", C.c_int32), ("tile_rows", C.c_int32), ("ncand", C.c_int32),
-                ("pad", C.c_int32), ("ms_per_step", C.c_double * 4)]
+    _fields_ = [("launch", C.c_int32), ("tile_rows", C.c_int32), ("coarse_cells", C.c_int32),
+                ("mg_smooth", C.c_int32), ("ncand", C.c_int32), ("pad", C.c_int32),
+                ("ms_per_step", C.c_double * 14)]
 
 
 class CDIError(RuntimeError):
@@ -137,6 +139,14 @@ def lib() -> C.CDLL:
     L.cdi_set_tile_rows.restype = i32
     L.cdi_get_tile_rows.argtypes = [vp, P(i32)]
     L.cdi_get_tile_rows.restype = i32
+    L.cdi_set_coarse_cells.argtypes = [vp, i32]
+    L.cdi_set_coarse_cells.restype = i32
+    L.cdi_get_coarse_cells.argtypes = [vp, P(i32)]
+    L.cdi_get_coarse_cells.restype = i32
+    L.cdi_set_mg_smooth.argtypes = [vp, i32]
+    L.cdi_set_mg_smooth.restype = i32
+    L.cdi_get_mg_smooth.argtypes = [vp, P(i32)]
+    L.cdi_get_mg_smooth.restype = i32
     L.cdi_graph_stats.argtypes = [vp, P(C.c_int64), P(C.c_int64), P(i32)]
     L.cdi_graph_stats.restype = i32
     L.cdi_tune_bytes.argtypes = [vp]

@@ -48,6 +48,7 @@ struct Resolved {
   cdi_params p;
   double h, dt, rtol;
   int maxit, nlev, lc;
+  int lg;                   // first level done by the one-block coarse kernel (<= lc)
   int lnx[kMaxLevels], lny[kMaxLevels];
 };
 
@@ -88,7 +89,7 @@ cdi_status resolve(const cdi_params* in, Resolved& r) {
   if (p.precision != CDI_FP64 && p.precision != CDI_MIXED) return fail(CDI_ERR_ARG, "bad precision");
   if (p.guess < CDI_GUESS_ZERO || p.guess > CDI_GUESS_LEARNED) return fail(CDI_ERR_ARG, "bad guess");
   if (p.poisson_rtol < 0 || p.poisson_maxit < 0 || p.mg_smooth < 0) return fail(CDI_ERR_ARG, "bad solver limits");
-  if (p.mg_smooth > 1) return fail(CDI_ERR_ARG, "mg_smooth: one sweep before and after is supported");
+  if (p.mg_smooth > 2) return fail(CDI_ERR_ARG, "mg_smooth: 1 or 2 sweep pairs are supported");
   r.p = p;
   r.h = hx;
   r.dt = p.dt > 0 ? p.dt : cfl_dt(p, hx);
@@ -110,6 +111,7 @@ cdi_status resolve(const cdi_params* in, Resolved& r) {
   r.lc = r.nlev - 1;
   for (int k = 0; k < r.nlev; ++k)
     if ((long)r.lnx[k] * r.lny[k] <= kCoarseCells) { r.lc = k; break; }
+  r.lg = r.lc;
   long cells = 0, yfaces = 0;   // LDS footprint of the single-block coarse cycle
   for (int k = r.lc; k < r.nlev; ++k) {
     cells += (long)r.lnx[k] * r.lny[k];
@@ -127,6 +129,10 @@ int ceil_div(int a, int b) { return (a + b - 1) / b; }
 struct Layout {
   size_t inst_bytes;        // per instance (sum over instances in `offs`)
 };
+
+// Doubles of one instance's step state: phi, u, p and the 8 pressure-history
+// fields (ny * nx each) and v ((ny + 1) * nx).
+size_t snap_doubles(int nx, int ny) { return 12 * (size_t)nx * ny + (size_t)nx; }
 
 // Carve one instance's arrays out of `base` (device) starting at offset `off`;
 // with base == nullptr only the size is computed.
@@ -169,7 +175,7 @@ size_t carve(const Resolved& R, int ntiles_cell, int ntiles_mg0, char* base, siz
   D.d1 = (double*)take(nc * 8);
   D.q = (double*)take(nc * 8);
   D.zf = (double*)take(nc * 8);
-  D.snap = (double*)take((11 * nc + nx) * 8);
+  D.snap = (double*)take(snap_doubles(nx, ny) * 8);
   D.mg_t = take(nc * S);
   D.mg_r0 = take(nc * S);
   for (int k = 0; k < 4; ++k) D.ph[k] = (double*)take(nc * 8);
@@ -206,7 +212,7 @@ struct Batch {
   std::vector<Tile> cell;               // level-0 cell tiles of every instance
   std::vector<Tile> wide;               // level-0 wide tiles of every instance
   std::vector<std::vector<Tile>> mg;    // per level: multigrid tiles of instances with level < lc
-  int max_lc = 0, max_nlev = 0;
+  int max_lc = 0, max_nlev = 0, max_lg = 0;
   size_t shared_bytes = 0;
 };
 
@@ -224,16 +230,35 @@ void build_wide(Batch& B, int rows) {
   }
 }
 
+// Multigrid tiles of the tiled kernels: levels below each instance's lg.
+void build_mg(Batch& B) {
+  B.max_lg = 0;
+  for (int k = 0; k < B.n; ++k) B.max_lg = std::max(B.max_lg, B.R[k].lg);
+  B.mg.assign(std::max(B.max_lc, 1), {});
+  for (int k = 0; k < B.n; ++k) {
+    const Resolved& R = B.R[k];
+    Inst& I = B.inst[k];
+    I.lg = R.lg;
+    for (int l = 0; l < R.lg; ++l) {
+      Level& L = I.lev[l];
+      L.first_tile = (int)B.mg[l].size();
+      int loc = 0;
+      for (int j0 = 0; j0 < L.ny; j0 += FY)
+        for (int i0 = 0; i0 < L.nx; i0 += FX) B.mg[l].push_back(Tile{k, i0, j0, l, loc++, {0, 0, 0}});
+      L.ntiles = loc;
+    }
+    for (int l = R.lg; l < R.nlev; ++l) { I.lev[l].first_tile = 0; I.lev[l].ntiles = 0; }
+  }
+}
+
 void build_tiles(Batch& B, int wide_rows) {
   B.cell.clear();
-  B.wide.clear();
   B.max_lc = 0;
   B.max_nlev = 0;
   for (int k = 0; k < B.n; ++k) {
     B.max_lc = std::max(B.max_lc, B.R[k].lc);
     B.max_nlev = std::max(B.max_nlev, B.R[k].nlev);
   }
-  B.mg.assign(std::max(B.max_lc, 1), {});
   for (int k = 0; k < B.n; ++k) {
     const Resolved& R = B.R[k];
     Inst& I = B.inst[k];
@@ -242,17 +267,17 @@ void build_tiles(Batch& B, int wide_rows) {
     for (int j0 = 0; j0 < R.p.ny; j0 += TY)
       for (int i0 = 0; i0 < R.p.nx; i0 += TX) B.cell.push_back(Tile{k, i0, j0, 0, local++, {0, 0, 0}});
     I.ntiles = local;
-    for (int l = 0; l < R.lc; ++l) {
-      Level& L = I.lev[l];
-      L.first_tile = (int)B.mg[l].size();
-      int loc = 0;
-      for (int j0 = 0; j0 < L.ny; j0 += FY)
-        for (int i0 = 0; i0 < L.nx; i0 += FX) B.mg[l].push_back(Tile{k, i0, j0, l, loc++, {0, 0, 0}});
-      L.ntiles = loc;
-    }
-    for (int l = R.lc; l < R.nlev; ++l) { I.lev[l].first_tile = 0; I.lev[l].ntiles = 0; }
   }
+  build_mg(B);
   build_wide(B, wide_rows);
+}
+
+// Coarse-kernel start level for a threshold: the first level with at most
+// `cells` cells (never below lc: those levels live in the kernel's LDS).
+void set_lg(Resolved& R, long cells) {
+  R.lg = R.lc;
+  for (int k = 0; k < R.lc; ++k)
+    if ((long)R.lnx[k] * R.lny[k] <= cells) { R.lg = k; break; }
 }
 
 // Workgroups of a launch are dispatched to the XCDs round robin (block b on
@@ -260,6 +285,8 @@ void build_tiles(Batch& B, int wide_rows) {
 // XCD receives one contiguous band of tiles: neighbouring tiles, whose halos
 // overlap, then share an L2 instead of fetching the same rows from HBM twice.
 constexpr size_t kXcds = 8;
+constexpr long kDefaultCoarseCells = 4096;
+constexpr long kTuneCoarse[3] = {1024, 4096, 16384};   // coarse-kernel thresholds tried by cdi_tune
 
 std::vector<Tile> xcd_order(const std::vector<Tile>& t) {
   const size_t n = t.size();
@@ -299,7 +326,8 @@ size_t batch_bytes(const std::vector<Resolved>& Rs, Batch* B, char* base) {
 void fill_inst(const Resolved& R, const cdi_fields& f, Inst& I) {
   const cdi_params& p = R.p;
   I.nx = p.nx; I.ny = p.ny;
-  I.nlev = R.nlev; I.lc = R.lc;
+  I.nlev = R.nlev; I.lc = R.lc; I.lg = R.lg;
+  I.nu = p.mg_smooth > 0 ? p.mg_smooth : 1;
   I.slip_model = p.slip_model;
   I.mixed = p.precision == CDI_MIXED;
   I.h = R.h; I.inv_h = 1.0 / R.h;
@@ -332,7 +360,11 @@ struct cdi_ctx {
   PcgScalars* h_pcg = nullptr;   // pinned
   int pred_iters = 4;
   int wide_rows = 4;             // rows per thread of the wide-tile kernels (1 or 4)
+  int nu = 1;                    // red-black sweep pairs of the V-cycle
   int wide_rows_pick = 4;        // autotuner: faster tiled shape so far
+  long coarse_cells = 4096;      // coarse kernel takes every level with at most this many cells
+  long coarse_cells_pick = 4096;
+  int nu_pick = 1;
   std::vector<int> last_iters;
   std::vector<double> last_relres;
   std::vector<int> last_conv;
@@ -420,19 +452,26 @@ void timed(cdi_ctx* c, const char* name, F&& body, bool single = true) {
 template <typename S>
 void launch_vcycle(cdi_ctx* c, int update, int dpar, int rsel) {
   Batch& B = c->B;
-  for (int l = 0; l < B.max_lc; ++l)
+  for (int l = 0; l < B.max_lg; ++l)
     if (!B.mg[l].empty())
       timed(c, (l == 0 && update) ? "mg_down" : "mg_down_other", [&] {
-        CDI_LAUNCH(c, k_mg_down<S>, (unsigned)B.mg[l].size(), kNT, c->d_mg[l], c->d_inst, l,
+        if (c->nu == 2)
+          CDI_LAUNCH(c, (k_mg_down<S, 2>), (unsigned)B.mg[l].size(), kNT, c->d_mg[l], c->d_inst, l,
+                     update, dpar, rsel);
+        else
+          CDI_LAUNCH(c, (k_mg_down<S, 1>), (unsigned)B.mg[l].size(), kNT, c->d_mg[l], c->d_inst, l,
                                                                       update, dpar, rsel);
       });
   timed(c, "mg_coarse", [&] {
     CDI_LAUNCH(c, k_mg_coarse<S>, (unsigned)B.n, kCoarseNT, c->d_inst, update, dpar, rsel);
   });
-  for (int l = B.max_lc - 1; l >= 0; --l)
+  for (int l = B.max_lg - 1; l >= 0; --l)
     if (!B.mg[l].empty())
       timed(c, l == 0 ? "mg_up" : "mg_up_other", [&] {
-        CDI_LAUNCH(c, k_mg_up<S>, (unsigned)B.mg[l].size(), kNT, c->d_mg[l], c->d_inst, l, rsel);
+        if (c->nu == 2)
+          CDI_LAUNCH(c, (k_mg_up<S, 2>), (unsigned)B.mg[l].size(), kNT, c->d_mg[l], c->d_inst, l, rsel);
+        else
+          CDI_LAUNCH(c, (k_mg_up<S, 1>), (unsigned)B.mg[l].size(), kNT, c->d_mg[l], c->d_inst, l, rsel);
       });
 }
 
@@ -620,9 +659,29 @@ cdi_status snapshot(cdi_ctx* c, bool save) {
                             hipMemcpyDeviceToDevice, c->stream));
       pos += n;
     }
+    if (pos + n + I.nx > snap_doubles(I.nx, I.ny))
+      return fail(CDI_ERR_STATE, "snapshot layout exceeds its area");
     HIPCHK(hipMemcpyAsync(save ? I.snap + pos : I.v, save ? I.v : I.snap + pos,
                           (n + I.nx) * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
   }
+  return CDI_OK;
+}
+
+// Upload the run-time tile lists (wide tiles, multigrid tiles below lg) and
+// the instance descriptors into their fixed slots.
+cdi_status upload_shape(cdi_ctx* c) {
+  Batch& B = c->B;
+  const std::vector<Tile> w = xcd_order(B.wide);
+  HIPCHK(hipMemcpyAsync(c->d_wide, w.data(), sizeof(Tile) * w.size(), hipMemcpyHostToDevice, c->stream));
+  std::vector<std::vector<Tile>> lv(B.max_lg);
+  for (int l = 0; l < B.max_lg; ++l) {
+    lv[l] = xcd_order(B.mg[l]);
+    if (!lv[l].empty())
+      HIPCHK(hipMemcpyAsync(c->d_mg[l], lv[l].data(), sizeof(Tile) * lv[l].size(),
+                            hipMemcpyHostToDevice, c->stream));
+  }
+  HIPCHK(hipMemcpyAsync(c->d_inst, B.inst.data(), sizeof(Inst) * B.n, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));   // the host lists go out of scope
   return CDI_OK;
 }
 
@@ -824,6 +883,8 @@ cdi_status cdi_init_batch(const cdi_params* params, int32_t n, const cdi_fields*
       return fail(CDI_ERR_ARG, "instance %d: a field pointer is NULL", k);
     if (Rs[k].p.precision != Rs[0].p.precision)
       return fail(CDI_ERR_ARG, "all instances of a batch must use the same precision");
+    if (std::max(1, Rs[k].p.mg_smooth) != std::max(1, Rs[0].p.mg_smooth))
+      return fail(CDI_ERR_ARG, "all instances of a batch must use the same mg_smooth");
   }
   const size_t need = batch_bytes(Rs, nullptr, nullptr);
   if (workspace_bytes < need)
@@ -837,6 +898,7 @@ cdi_status cdi_init_batch(const cdi_params* params, int32_t n, const cdi_fields*
   B.R = Rs;
   B.inst.assign(n, Inst{});
   c->mixed = Rs[0].p.precision == CDI_MIXED;
+  c->nu = std::max(1, Rs[0].p.mg_smooth);
   c->guess = Rs[0].p.guess;
   c->rtol = Rs[0].rtol;
   c->maxit = Rs[0].maxit;
@@ -850,6 +912,8 @@ cdi_status cdi_init_batch(const cdi_params* params, int32_t n, const cdi_fields*
   long cells = 0;
   for (int k = 0; k < n; ++k) cells += (long)Rs[k].p.nx * Rs[k].p.ny;
   c->wide_rows = cells >= (1L << 18) ? 4 : 1;
+  c->coarse_cells = kDefaultCoarseCells;
+  for (int k = 0; k < n; ++k) set_lg(B.R[k], c->coarse_cells);
   build_tiles(B, c->wide_rows);
   // shared header
   size_t off = 0;
@@ -858,24 +922,24 @@ cdi_status cdi_init_batch(const cdi_params* params, int32_t n, const cdi_fields*
   c->d_diag = (DiagOut*)(c->ws + off);
   off = align256(off + sizeof(DiagOut) * n);
   Tile* tl = (Tile*)(c->ws + off);
-  // tiled launches: XCD-banded order; persistent launch: instance order
+  // fixed slots: level-0 cell tiles (XCD-banded order, tiled launches; then
+  // instance order, persistent launch), the wide tiles (room for 1 row per
+  // thread), the multigrid tiles of every level below lc (the coarse-kernel
+  // start level lg <= lc and the wide shape change at run time)
   std::vector<Tile> all = xcd_order(B.cell);
   c->d_cell = tl;
-  c->d_mg.assign(B.mg.size(), nullptr);
   size_t pos = all.size();
-  for (size_t l = 0; l < B.mg.size(); ++l) {
-    c->d_mg[l] = tl + pos;
-    const std::vector<Tile> lv = xcd_order(B.mg[l]);
-    all.insert(all.end(), lv.begin(), lv.end());
-    pos += lv.size();
-  }
   c->d_cell_inst = tl + pos;
   all.insert(all.end(), B.cell.begin(), B.cell.end());
   pos += B.cell.size();
   c->d_wide = tl + pos;
-  {
-    const std::vector<Tile> w = xcd_order(B.wide);
-    all.insert(all.end(), w.begin(), w.end());
+  pos += B.cell.size();
+  c->d_mg.assign(std::max(B.max_lc, 1), nullptr);
+  for (int l = 0; l < B.max_lc; ++l) {
+    c->d_mg[l] = tl + pos;
+    for (int k = 0; k < n; ++k)
+      if (l < Rs[k].lc)
+        pos += (size_t)ceil_div(Rs[k].lnx[l], FX) * ceil_div(Rs[k].lny[l], FY);
   }
   c->h_pcg = nullptr;
   hipError_t e = hipHostMalloc((void**)&c->h_pcg, sizeof(PcgScalars) * n, hipHostMallocDefault);
@@ -893,6 +957,14 @@ cdi_status cdi_init_batch(const cdi_params* params, int32_t n, const cdi_fields*
     return cleanup_fail(e, "copy instances");
   if ((e = hipMemcpyAsync(tl, all.data(), sizeof(Tile) * all.size(), hipMemcpyHostToDevice, c->stream)) != hipSuccess)
     return cleanup_fail(e, "copy tiles");
+  {
+    cdi_status us = upload_shape(c);
+    if (us != CDI_OK) {
+      (void)hipHostFree(c->h_pcg);
+      delete c;
+      return us;
+    }
+  }
   // zero the whole per-instance workspace once (walls of v-type arrays,
   // counters, flags); every later write stays inside the domain
   const size_t hdr = (size_t)((char*)B.inst[0].phi_a - c->ws);
@@ -1084,17 +1156,50 @@ cdi_status cdi_timing_read(cdi_ctx* c, double* total_ms, int64_t* launches) {
   return CDI_OK;
 }
 
-// Rebuild the wide tile list for `rows` rows per thread and upload it.
-static cdi_status apply_wide_rows(cdi_ctx* c, int rows) {
-  if (rows == c->wide_rows) return CDI_OK;
+// Switch the run-time launch shape: rows per thread of the wide-tile kernels
+// and the coarse kernel's start level (first level with at most
+// `coarse_cells` cells); rebuilds and uploads the affected tile lists.
+static cdi_status apply_shape(cdi_ctx* c, int rows, long coarse_cells, int nu) {
+  if (rows == c->wide_rows && coarse_cells == c->coarse_cells && nu == c->nu) return CDI_OK;
   graph_drop(c);   // the captured step holds the old launch grids
   Batch& B = c->B;
-  build_wide(B, rows);
-  const std::vector<Tile> w = xcd_order(B.wide);
-  HIPCHK(hipMemcpyAsync(c->d_wide, w.data(), sizeof(Tile) * w.size(), hipMemcpyHostToDevice, c->stream));
-  HIPCHK(hipMemcpyAsync(c->d_inst, B.inst.data(), sizeof(Inst) * B.n, hipMemcpyHostToDevice, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
+  build_wide(B, rows);
+  for (int k = 0; k < B.n; ++k) set_lg(B.R[k], coarse_cells);
+  build_mg(B);
+  for (int k = 0; k < B.n; ++k) B.inst[k].nu = nu;
   c->wide_rows = rows;
+  c->coarse_cells = coarse_cells;
+  c->nu = nu;
+  return upload_shape(c);
+}
+
+static cdi_status apply_wide_rows(cdi_ctx* c, int rows) {
+  return apply_shape(c, rows, c->coarse_cells, c->nu);
+}
+
+cdi_status cdi_set_mg_smooth(cdi_ctx* c, int32_t nu) {
+  if (!c) return fail(CDI_ERR_ARG, "ctx is NULL");
+  if (nu < 1 || nu > 2) return fail(CDI_ERR_ARG, "mg_smooth must be 1 or 2");
+  return apply_shape(c, c->wide_rows, c->coarse_cells, nu);
+}
+
+cdi_status cdi_get_mg_smooth(cdi_ctx* c, int32_t* nu) {
+  if (!c || !nu) return fail(CDI_ERR_ARG, "NULL argument");
+  *nu = c->nu;
+  return CDI_OK;
+}
+
+cdi_status cdi_set_coarse_cells(cdi_ctx* c, int32_t cells) {
+  if (!c) return fail(CDI_ERR_ARG, "ctx is NULL");
+  if (cells < kCoarseCells || cells > (1 << 20))
+    return fail(CDI_ERR_ARG, "coarse_cells must be in [%d, %d]", kCoarseCells, 1 << 20);
+  return apply_shape(c, c->wide_rows, cells, c->nu);
+}
+
+cdi_status cdi_get_coarse_cells(cdi_ctx* c, int32_t* cells) {
+  if (!c || !cells) return fail(CDI_ERR_ARG, "NULL argument");
+  *cells = (int32_t)c->coarse_cells;
   return CDI_OK;
 }
 
@@ -1115,10 +1220,8 @@ cdi_status cdi_get_tile_rows(cdi_ctx* c, int32_t* rows) {
 // per-stage pressure history (FP64), per instance.
 static size_t tune_bytes(const cdi_ctx* c) {
   size_t b = 0;
-  for (int k = 0; k < c->B.n; ++k) {
-    const size_t n = (size_t)c->B.R[k].p.nx * c->B.R[k].p.ny, nx = c->B.R[k].p.nx;
-    b += align256((11 * n + nx) * sizeof(double));
-  }
+  for (int k = 0; k < c->B.n; ++k)
+    b += align256(snap_doubles(c->B.R[k].p.nx, c->B.R[k].p.ny) * sizeof(double));
   return b;
 }
 
@@ -1139,10 +1242,11 @@ static cdi_status tune_copy(cdi_ctx* c, char* scratch, bool save) {
       HIPCHK(hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
       pos += n;
     }
+    if (pos + nf > snap_doubles(I.nx, I.ny)) return fail(CDI_ERR_STATE, "saved state exceeds its area");
     void* dst = save ? (void*)(base + pos) : (void*)I.v;
     const void* src = save ? (const void*)I.v : (const void*)(base + pos);
     HIPCHK(hipMemcpyAsync(dst, src, nf * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-    off += align256((11 * n + I.nx) * sizeof(double));
+    off += align256(snap_doubles(I.nx, I.ny) * sizeof(double));
   }
   return CDI_OK;
 }
@@ -1166,19 +1270,32 @@ cdi_status cdi_tune(cdi_ctx* c, int32_t trial_steps, void* scratch, size_t scrat
   const std::string timed0 = c->timed;
   c->timed.clear();
   c->wide_rows_pick = c->wide_rows;
-  struct Cand { int launch, rows; };
-  Cand cands[4] = {{CDI_LAUNCH_TILED, kWideRows[0]}, {CDI_LAUNCH_TILED, kWideRows[1]},
-                   {CDI_LAUNCH_PERSISTENT, c->wide_rows}, {CDI_LAUNCH_GRAPH, c->wide_rows}};
+  c->coarse_cells_pick = c->coarse_cells;
+  c->nu_pick = c->nu;
+  // candidates: tiled for every (sweep pairs, rows, coarse cells), then
+  // persistent (with the fastest tiled sweep count) and graph (with the
+  // fastest tiled shape)
+  struct Cand { int launch, rows; long coarse; int nu; int slot; };
+  std::vector<Cand> cands;
+  for (int v = 0; v < 2; ++v)
+    for (int r = 0; r < 2; ++r)
+      for (int q = 0; q < 3; ++q)
+        cands.push_back({CDI_LAUNCH_TILED, kWideRows[r], kTuneCoarse[q], v + 1, v * 6 + r * 3 + q});
+  cands.push_back({CDI_LAUNCH_PERSISTENT, 0, 0, 0, 12});
+  cands.push_back({CDI_LAUNCH_GRAPH, 0, 0, 0, 13});
   double best = INFINITY, best_tiled = INFINITY;
-  Cand pick{c->launch, c->wide_rows};
+  Cand pick{c->launch, c->wide_rows, c->coarse_cells, c->nu, -1};
   cdi_tune_info info{};
-  for (int q = 0; q < 4; ++q) {
-    info.ms_per_step[q] = -1.0;
-    Cand& cd = cands[q];
+  for (int q = 0; q < 14; ++q) info.ms_per_step[q] = -1.0;
+  for (Cand& cd : cands) {
     const bool learned = c->guess == CDI_GUESS_LEARNED && c->net;
     if (cd.launch != CDI_LAUNCH_TILED && learned) continue;
-    if (cd.launch != CDI_LAUNCH_TILED) cd.rows = c->wide_rows_pick;   // the faster tiled shape
-    if ((st = apply_wide_rows(c, cd.rows)) != CDI_OK) break;
+    if (cd.launch != CDI_LAUNCH_TILED) {   // the fastest tiled shape
+      cd.rows = c->wide_rows_pick;
+      cd.coarse = c->coarse_cells_pick;
+      cd.nu = c->nu_pick;
+    }
+    if ((st = apply_shape(c, cd.rows, cd.coarse, cd.nu)) != CDI_OK) break;
     c->launch = cd.launch;
     // warm-up: code load, iteration predictor; the graph form captures its
     // step once the pressure history exists
@@ -1192,12 +1309,15 @@ cdi_status cdi_tune(cdi_ctx* c, int32_t trial_steps, void* scratch, size_t scrat
     if (r != CDI_OK && r != CDI_ERR_NOCONV) { st = r; break; }
     float ms = 0.f;
     HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
-    info.ms_per_step[q] = ms / trial_steps;
+    const double per = ms / trial_steps;
+    info.ms_per_step[cd.slot] = per;
     info.ncand += 1;
-    if (info.ms_per_step[q] < best) { best = info.ms_per_step[q]; pick = cd; }
-    if (cd.launch == CDI_LAUNCH_TILED && info.ms_per_step[q] < best_tiled) {
-      best_tiled = info.ms_per_step[q];
+    if (per < best) { best = per; pick = cd; }
+    if (cd.launch == CDI_LAUNCH_TILED && per < best_tiled) {
+      best_tiled = per;
       c->wide_rows_pick = cd.rows;
+      c->coarse_cells_pick = cd.coarse;
+      c->nu_pick = cd.nu;
     }
     // back to the saved state for the next candidate
     cdi_status rs = tune_copy(c, sc, false);
@@ -1213,10 +1333,12 @@ cdi_status cdi_tune(cdi_ctx* c, int32_t trial_steps, void* scratch, size_t scrat
     (void)hipStreamSynchronize(c->stream);
     return st;
   }
-  if ((st = apply_wide_rows(c, pick.rows)) != CDI_OK) return st;
+  if ((st = apply_shape(c, pick.rows, pick.coarse, pick.nu)) != CDI_OK) return st;
   c->launch = pick.launch;
   info.launch = pick.launch;
   info.tile_rows = pick.rows;
+  info.coarse_cells = (int32_t)pick.coarse;
+  info.mg_smooth = pick.nu;
   if (out) *out = info;
   return CDI_OK;
 }

@@ -54,7 +54,9 @@ struct PcgScalars {
 struct Inst {
   // grid and physics (Sec. 2, Sec. 4)
   int nx, ny;
-  int nlev, lc;             // multigrid levels; first level done by the coarse kernel
+  int nlev, lc;             // multigrid levels; first level held in the coarse kernel's LDS
+  int lg;                   // first level done by the one-block coarse kernel (lg <= lc)
+  int nu;                   // red-black sweep pairs before and after the coarse correction
   int slip_model, mixed;
   int first_tile, ntiles;   // tiles of level 0 in the cell tile list
   int first_wide, nwide;    // tiles of level 0 in the wide tile list

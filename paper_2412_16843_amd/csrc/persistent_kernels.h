@@ -39,22 +39,6 @@ __device__ __forceinline__ void pall_sum(double (&v)[NV], double* red, double* s
   __syncthreads();
 }
 
-// Level view of the persistent V-cycle: levels below lc in global memory
-// (level 0 reads `r0`), levels from lc in LDS.
-template <typename S>
-__device__ __forceinline__ MgView<S> persist_view(const Inst& I, CoarseLds<S>& C, S* r0,
-                                                  int l) {
-  if (l >= I.lc) return coarse_view<S>(I, C, l);
-  const Level& L = I.lev[l];
-  MgView<S> v;
-  v.nx = L.nx; v.ny = L.ny;
-  v.ax = (const S*)L.ax; v.ay = (const S*)L.ay;
-  v.r = l == 0 ? r0 : (S*)L.r;
-  v.z = (S*)L.z;
-  v.t = (S*)I.mg_t;
-  return v;
-}
-
 // One projection solve K x = -(b - mean b) by flexible CG with the V-cycle
 // preconditioner, to relative residual rtol; guess as in k_pcg_init.  Leaves
 // x in I.x and returns the iteration count.
@@ -83,7 +67,7 @@ __device__ int persist_solve(const Inst& I, PersistLds<S>& L, int guess,
   relres = zero ? 0.0 : sqrt(s2[1]) / fnorm;
   S* r0 = I.mixed ? (S*)I.mg_r0 : (S*)(void*)r;
   const bool lds0 = I.lc == 0;
-  auto view = [&](int l) { return persist_view<S>(I, L.u.coarse, r0, l); };
+  auto view = [&](int l) { return mixed_view<S>(I, L.u.coarse, r0, l); };
   int it = 0;
   double dq_old = 0.0;
   (void)ny;

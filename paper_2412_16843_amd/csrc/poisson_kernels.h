@@ -432,12 +432,14 @@ __device__ __forceinline__ S ldS(const void* p, size_t o) { return ((const S*)p)
 // Level 0 reads the FP64 CG residual; with `update` it first applies the CG
 // step x += alpha d, r -= alpha q (d from buffer `parity`) and takes the
 // stopping test.
-template <typename S>
+template <typename S, int NU>
 __global__ void __launch_bounds__(kNT) k_mg_down(const Tile* __restrict__ tiles,
                                                   const Inst* __restrict__ insts, int level,
                                                   int update, int parity, int rsel) {
-  constexpr int H = 3;
-  constexpr int RY = FY + 2 * H, RX = FX + 2 * H;       // 22 x 38 (r, z)
+  // NU red-black pairs; every half-sweep after the first (pointwise) one
+  // shrinks the valid region by one cell, the residual needs a 2-cell halo
+  constexpr int H = 2 * NU + 1;
+  constexpr int RY = FY + 2 * H, RX = FX + 2 * H;       // 22 x 38 (r, z) for NU = 1
   constexpr int PY = FY + 2, PX = FX + 2;                // residual, halo 1
   __shared__ S s_r[RY * RX], s_z[RY * RX];
   __shared__ S s_ax[RY * (RX + 1)], s_ay[(RY + 1) * RX];
@@ -538,18 +540,23 @@ __global__ void __launch_bounds__(kNT) k_mg_down(const Tile* __restrict__ tiles,
     s_z[k] = z;
   }
   __syncthreads();
-  // black cells: Gauss-Seidel with the red neighbours (halo 2)
-  for (int k = threadIdx.x; k < RY * RX; k += kNT) {
-    const int rj = k / RX, ri = k - rj * RX;
-    if (rj < 1 || rj >= RY - 1 || ri < 1 || ri >= RX - 1) continue;
-    const int j = j0 - H + rj, i = i0 - H + ri;
-    if (!valid(rj) || ((i + j) & 1) == 0) continue;
-    const S aw = s_ax[rj * (RX + 1) + ri], ae = s_ax[rj * (RX + 1) + ri + 1];
-    const S as = s_ay[rj * RX + ri], an = s_ay[(rj + 1) * RX + ri];
-    const S nb = aw * s_z[k - 1] + ae * s_z[k + 1] + as * s_z[k - RX] + an * s_z[k + RX];
-    s_z[k] = (s_r[k] + nb) / (aw + ae + as + an);
+  // then Gauss-Seidel half-sweeps black, red, black, ... (half-sweep sw on
+  // the region shrunk by sw cells)
+#pragma unroll
+  for (int sw = 1; sw < 2 * NU; ++sw) {
+    const int color = sw & 1;   // 1 black, 0 red
+    for (int k = threadIdx.x; k < RY * RX; k += kNT) {
+      const int rj = k / RX, ri = k - rj * RX;
+      if (rj < sw || rj >= RY - sw || ri < sw || ri >= RX - sw) continue;
+      const int j = j0 - H + rj, i = i0 - H + ri;
+      if (!valid(rj) || ((i + j) & 1) != color) continue;
+      const S aw = s_ax[rj * (RX + 1) + ri], ae = s_ax[rj * (RX + 1) + ri + 1];
+      const S as = s_ay[rj * RX + ri], an = s_ay[(rj + 1) * RX + ri];
+      const S nb = aw * s_z[k - 1] + ae * s_z[k + 1] + as * s_z[k - RX] + an * s_z[k + RX];
+      s_z[k] = (s_r[k] + nb) / (aw + ae + as + an);
+    }
+    __syncthreads();
   }
-  __syncthreads();
   // store the smoothed z on the tile
   for (int k = threadIdx.x; k < FX * FY; k += kNT) {
     const int ty = k / FX, tx = k - ty * FX;
@@ -614,12 +621,12 @@ __device__ __forceinline__ S prolong(const S* e, int cnx, int cny, int j, int i)
 
 // z += P e, then post-smoothing (black, then red).  Level 0 writes the FP64
 // preconditioned residual and forms the flexible-CG beta.
-template <typename S>
+template <typename S, int NU>
 __global__ void __launch_bounds__(kNT) k_mg_up(const Tile* __restrict__ tiles,
                                                 const Inst* __restrict__ insts, int level,
                                                 int rsel) {
-  constexpr int H = 2;
-  constexpr int RY = FY + 2 * H, RX = FX + 2 * H;       // 20 x 36
+  constexpr int H = 2 * NU;
+  constexpr int RY = FY + 2 * H, RX = FX + 2 * H;       // 20 x 36 for NU = 1
   __shared__ S s_r[RY * RX], s_z[RY * RX];
   __shared__ S s_ax[RY * (RX + 1)], s_ay[(RY + 1) * RX];
   __shared__ double sh[kNT / 64];
@@ -661,24 +668,21 @@ __global__ void __launch_bounds__(kNT) k_mg_up(const Tile* __restrict__ tiles,
     const S nb = aw * s_z[k - 1] + ae * s_z[k + 1] + as * s_z[k - RX] + an * s_z[k + RX];
     return (s_r[k] + nb) / (aw + ae + as + an);
   };
-  // black sweep on the tile + halo 1
-  for (int k = threadIdx.x; k < RY * RX; k += kNT) {
-    const int rj = k / RX, ri = k - rj * RX;
-    if (rj < 1 || rj >= RY - 1 || ri < 1 || ri >= RX - 1) continue;
-    const int j = j0 - H + rj, i = i0 - H + ri;
-    if (!valid(rj) || ((i + j) & 1) == 0) continue;
-    s_z[k] = gs(k, rj, ri);
+  // half-sweeps black, red, ... (the reverse of the pre-smoothing), the
+  // last one (red) on the tile itself
+#pragma unroll
+  for (int sw = 0; sw < 2 * NU; ++sw) {
+    const int color = (sw & 1) ? 0 : 1;   // black first
+    const int m = sw + 1;
+    for (int k = threadIdx.x; k < RY * RX; k += kNT) {
+      const int rj = k / RX, ri = k - rj * RX;
+      if (rj < m || rj >= RY - m || ri < m || ri >= RX - m) continue;
+      const int j = j0 - H + rj, i = i0 - H + ri;
+      if (!valid(rj) || ((i + j) & 1) != color) continue;
+      s_z[k] = gs(k, rj, ri);
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  // red sweep on the tile
-  for (int k = threadIdx.x; k < RY * RX; k += kNT) {
-    const int rj = k / RX, ri = k - rj * RX;
-    if (rj < H || rj >= RY - H || ri < H || ri >= RX - H) continue;
-    const int j = j0 - H + rj, i = i0 - H + ri;
-    if (!valid(rj) || ((i + j) & 1) != 0) continue;
-    s_z[k] = gs(k, rj, ri);
-  }
-  __syncthreads();
   double zq[1] = {0.0};
   for (int k = threadIdx.x; k < FX * FY; k += kNT) {
     const int ty = k / FX, tx = k - ty * FX;
@@ -764,6 +768,12 @@ __device__ __forceinline__ void mg_cycle(const Inst& I, const ViewF& V, int lo, 
     __syncthreads();
     sweep(l, 1, false);
     __syncthreads();
+    for (int k = 1; k < I.nu; ++k) {
+      sweep(l, 0, false);
+      __syncthreads();
+      sweep(l, 1, false);
+      __syncthreads();
+    }
     {
       const S* ax = Lv.ax;
       const S* ay = Lv.ay;
@@ -890,10 +900,12 @@ __device__ __forceinline__ void mg_cycle(const Inst& I, const ViewF& V, int lo, 
       z[c] += prolong<S>(e, cnx, cny, j, i);
     }
     __syncthreads();
-    sweep(l, 1, false);
-    __syncthreads();
-    sweep(l, 0, false);
-    __syncthreads();
+    for (int k = 0; k < I.nu; ++k) {
+      sweep(l, 1, false);
+      __syncthreads();
+      sweep(l, 0, false);
+      __syncthreads();
+    }
   }
 }
 
@@ -933,32 +945,51 @@ __device__ __forceinline__ void coarse_load_coef(const Inst& I, CoarseLds<S>& C)
   }
 }
 
+// Level view of a one-block V-cycle: levels from lc in LDS, finer levels in
+// global memory (level 0 reads `r0`, the others their own r; the residual
+// scratch of the global levels is I.mg_t).
+template <typename S>
+__device__ __forceinline__ MgView<S> mixed_view(const Inst& I, CoarseLds<S>& C, S* r0, int l) {
+  if (l >= I.lc) return coarse_view<S>(I, C, l);
+  const Level& L = I.lev[l];
+  MgView<S> v;
+  v.nx = L.nx; v.ny = L.ny;
+  v.ax = (const S*)L.ax; v.ay = (const S*)L.ay;
+  v.r = l == 0 ? r0 : (S*)L.r;
+  v.z = (S*)L.z;
+  v.t = (S*)I.mg_t;
+  return v;
+}
+
 // ------------------------------------------------ single-block coarse cycle
-// Every level from lc down lives in LDS (coefficients, right-hand side,
-// correction, scratch).  With lc == 0 the block holds the whole problem and
-// also applies the CG update, the stopping test and beta.
+// Every level from lg down runs in one block: levels lg..lc-1 from global
+// memory (L2-resident at these sizes), levels from lc in LDS (coefficients,
+// right-hand side, correction, scratch).  lg trades launches of the tiled
+// kernels against one CU's throughput and is chosen per context.  With
+// lg == 0 the block holds the whole problem and also applies the CG update,
+// the stopping test and beta.
 template <typename S>
 __global__ void __launch_bounds__(kCoarseNT) k_mg_coarse(const Inst* __restrict__ insts,
                                                           int update, int parity, int rsel) {
   __shared__ CoarseLds<S> C;
   const Inst& I = insts[blockIdx.x];
   if (I.pcg->done) return;
-  const int lc = I.lc, nl = I.nlev;
+  const int lg = I.lg, lc = I.lc, nl = I.nlev;
   const int tid = threadIdx.x;
-  // ---- CG update when the whole grid is coarse
-  if (lc == 0 && update) {
+  double* __restrict__ rcur = rsel ? I.rr2 : I.rr;   // level-0 residual the cycle reads
+  // ---- CG update when the whole grid is handled here
+  if (lg == 0 && update) {
     const Level& L0 = I.lev[0];
     const int n = L0.nx * L0.ny;
     const double alpha = I.pcg->alpha;
     const double* __restrict__ d = parity ? I.d1 : I.d0;
     const double* __restrict__ rin = rsel ? I.rr : I.rr2;
-    double* __restrict__ rout = rsel ? I.rr2 : I.rr;
     double red[2] = {0.0, 0.0};
     for (int c = tid; c < n; c += kCoarseNT) {
       const double x = I.x[c] + alpha * d[c];
       const double r = rin[c] - alpha * I.q[c];
       I.x[c] = x;
-      rout[c] = r;
+      rcur[c] = r;
       red[0] += r * r;
       red[1] += x;
     }
@@ -971,22 +1002,34 @@ __global__ void __launch_bounds__(kCoarseNT) k_mg_coarse(const Inst* __restrict_
     if (C.sc[0] != 0.0) return;
   }
   coarse_load_coef<S>(I, C);
+  S* r0 = I.mixed ? (S*)I.mg_r0 : (S*)(void*)rcur;
+  auto view = [&](int l) { return mixed_view<S>(I, C, r0, l); };
   {
-    const Level& L = I.lev[lc];
+    // right-hand side of level lg: into LDS when lg is an LDS level, into the
+    // S copy of the level-0 residual on the mixed path
+    const Level& L = I.lev[lg];
     const int n = L.nx * L.ny;
-    S* r = coarse_view<S>(I, C, lc).r;
-    for (int c = tid; c < n; c += kCoarseNT)
-      r[c] = lc == 0 ? (S)(rsel ? I.rr2 : I.rr)[c] : ((const S*)L.r)[c];
+    if (lg >= lc) {
+      S* r = coarse_view<S>(I, C, lg).r;
+      for (int c = tid; c < n; c += kCoarseNT)
+        r[c] = lg == 0 ? (S)rcur[c] : ((const S*)L.r)[c];
+    } else if (lg == 0 && I.mixed) {
+      for (int c = tid; c < n; c += kCoarseNT) r0[c] = (S)rcur[c];
+    }
   }
   __syncthreads();
-  mg_cycle<S>(I, [&](int l) { return coarse_view<S>(I, C, l); }, lc, nl, C.red, C.sc);
-  // ---- publish the level-lc correction (and beta when it is level 0)
+  if (lg >= lc)   // LDS levels only: views the compiler knows to be LDS (ds_ instructions)
+    mg_cycle<S>(I, [&](int l) { return coarse_view<S>(I, C, l); }, lg, nl, C.red, C.sc);
+  else
+    mg_cycle<S>(I, view, lg, nl, C.red, C.sc);
+  // ---- publish the level-lg correction (and beta when it is level 0)
   {
-    const Level& L = I.lev[lc];
+    const Level& L = I.lev[lg];
     const int n = L.nx * L.ny;
-    const S* z = coarse_view<S>(I, C, lc).z;
-    if (lc > 0) {
-      for (int c = tid; c < n; c += kCoarseNT) ((S*)L.z)[c] = z[c];
+    const S* z = view(lg).z;
+    if (lg > 0) {
+      if (lg >= lc)
+        for (int c = tid; c < n; c += kCoarseNT) ((S*)L.z)[c] = z[c];
     } else {
       double zq[1] = {0.0};
       for (int c = tid; c < n; c += kCoarseNT) {

@@ -25,7 +25,7 @@ class CDISolver:
 
     def __init__(self, params, phi0, precision: str = "fp64", guess: str = "prev",
                  rtol: float = 0.0, maxit: int = 0, device: str = "cuda:0", u0=None, v0=None,
-                 launch: str = "tiled"):
+                 launch: str = "tiled", mg_smooth: int = 0):
         if not torch.cuda.is_available():
             raise RuntimeError("CDISolver needs a GPU (the HIP library has no CPU path)")
         single = not isinstance(params, (list, tuple))
@@ -39,7 +39,7 @@ class CDISolver:
         self.device = torch.device(device)
         self.lib = L.lib()
         self.cparams = (L.cdi_params * self.n)(*[
-            L.make_params(p, precision, guess, rtol, maxit) for p in self.params])
+            L.make_params(p, precision, guess, rtol, maxit, mg_smooth) for p in self.params])
         self.fields: List[Dict[str, torch.Tensor]] = []
         cf = (L.cdi_fields * self.n)()
         for k, p in enumerate(self.params):
@@ -130,6 +130,24 @@ class CDISolver:
         """Rows per thread of the wide-tile CG kernels (1 or 4)."""
         L.check(self.lib.cdi_set_tile_rows(self.ctx, int(rows)))
 
+    def set_mg_smooth(self, nu: int) -> None:
+        """Red-black sweep pairs of the V-cycle (1 or 2)."""
+        L.check(self.lib.cdi_set_mg_smooth(self.ctx, int(nu)))
+
+    def get_mg_smooth(self) -> int:
+        m = C.c_int32()
+        L.check(self.lib.cdi_get_mg_smooth(self.ctx, C.byref(m)))
+        return m.value
+
+    def set_coarse_cells(self, cells: int) -> None:
+        """Levels with at most `cells` cells run in the one-block coarse kernel."""
+        L.check(self.lib.cdi_set_coarse_cells(self.ctx, int(cells)))
+
+    def get_coarse_cells(self) -> int:
+        m = C.c_int32()
+        L.check(self.lib.cdi_get_coarse_cells(self.ctx, C.byref(m)))
+        return m.value
+
     def get_tile_rows(self) -> int:
         m = C.c_int32()
         L.check(self.lib.cdi_get_tile_rows(self.ctx, C.byref(m)))
@@ -146,11 +164,15 @@ class CDISolver:
         torch.cuda.synchronize(self.device)
         del scratch
         names = {v: k for k, v in L.LAUNCH.items()}
+        ms = {}
+        for v, nu in enumerate((1, 2)):
+            for r, rows in enumerate((1, 4)):
+                for q, cc in enumerate((1024, 4096, 16384)):
+                    ms[f"tiled_nu{nu}_rows{rows}_coarse{cc}"] = info.ms_per_step[v * 6 + r * 3 + q]
+        ms["persistent"] = info.ms_per_step[12]
+        ms["graph"] = info.ms_per_step[13]
         return dict(launch=names[info.launch], tile_rows=info.tile_rows,
-                    ms_per_step={"tiled_rows1": info.ms_per_step[0],
-                                 "tiled_rows4": info.ms_per_step[1],
-                                 "persistent": info.ms_per_step[2],
-                                 "graph": info.ms_per_step[3]})
+                    coarse_cells=info.coarse_cells, mg_smooth=info.mg_smooth, ms_per_step=ms)
 
     def set_guess(self, mode: str) -> None:
         """Initial-guess mode of later solves: "zero", "prev" or "learned"."""

@@ -103,3 +103,18 @@ def test_null_and_small_workspace_rejected():
     nf = L.cdi_fields(None, 1, 1, 1)
     assert lib.cdi_init(C.byref(cp), C.byref(nf), 256, 1 << 30, None, C.byref(ctx)) == -1
     assert lib.cdi_step(None, 1) == -1
+
+
+def test_smoothing_sweeps_validated_on_host():
+    """mg_smooth: 0 -> 1, 1 and 2 accepted, larger rejected before device work."""
+    L = _lib()
+    lib = L.lib()
+    f = L.cdi_fields(1, 1, 1, 1)
+    ctx = C.c_void_p()
+    for nu in (0, 1, 2):
+        cp = L.make_params(_params(), mg_smooth=nu)
+        assert lib.cdi_workspace_bytes(C.byref(cp), 1) > 0, nu
+    cp = L.make_params(_params(), mg_smooth=3)
+    assert lib.cdi_workspace_bytes(C.byref(cp), 1) == 0
+    assert lib.cdi_init(C.byref(cp), C.byref(f), 256, 1 << 30, None, C.byref(ctx)) == -1
+    assert b"mg_smooth" in lib.cdi_last_error()

@@ -59,14 +59,20 @@ def test_graph_bitwise_equals_stream_launch(make):
     assert da["step"] == db["step"] and da["t"] == db["t"]
 
 
-def test_graph_budget_miss_redoes_the_step_bitwise():
+@pytest.mark.parametrize("cells", [1024, 4096])
+def test_graph_budget_miss_redoes_the_step_bitwise(cells):
     """Switching to the zero initial guess makes the solves need more
     iterations than the captured budget: the step is redone from its
-    snapshot and the trajectory stays bitwise that of the stream launch."""
+    snapshot and the trajectory stays bitwise that of the stream launch.
+    At 4096 cells the one-block coarse kernel owns every level of the 64x32
+    grid and uses the scratch array next to the snapshot (a snapshot that
+    overran its area was caught here)."""
     case = W.drop_case(64, 32, 60.0, 10.0)
     a = _solver(case.params, case.phi0, rtol=1e-12, maxit=400, launch="tiled")
     b = _solver(case.params, case.phi0, rtol=1e-12, maxit=400, launch="graph")
     b.set_tile_rows(a.get_tile_rows())
+    for s in (a, b):
+        s.set_coarse_cells(cells)
     for s in (a, b):
         s.step(6)
         s.set_guess("zero")

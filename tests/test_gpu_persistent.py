@@ -200,3 +200,78 @@ def test_autotune_restores_state_and_keeps_the_trajectory():
     ref, _ = _oracle(case, 6)
     errs = {k: relerr(g[k], ref[k]) for k in FIELDS}
     assert max(errs.values()) < 1e-10, errs
+
+
+@pytest.mark.parametrize("cells", [1024, 4096, 16384])
+@pytest.mark.parametrize("make,precision", [
+    (lambda: W.couette_case(256, 64, lx=4.0, ly=1.0), "fp64"),   # levels 16384 / 4096 / 1024
+    (lambda: W.drop_case(128, 64, 60.0, 10.0), "fp64"),          # 8192 / 2048 / 512
+    (lambda: W.drop_case(128, 64, 60.0, 10.0), "mixed"),
+])
+def test_coarse_kernel_start_level_matches_oracle(cells, make, precision):
+    """The one-block coarse kernel taking over the levels with at most
+    `cells` cells (global memory above 1024 cells, the whole grid at 16384
+    for 256x64): same solution as the oracle."""
+    case = make()
+    rtol = 1e-13 if precision == "fp64" else 1e-10
+    s = _solver(case.params, case.phi0, rtol=rtol, maxit=400, precision=precision)
+    s.set_coarse_cells(cells)
+    assert s.get_coarse_cells() == cells
+    s.step(5)
+    d = s.diagnostics()
+    g = s.state()
+    s.close()
+    ref, _ = _oracle(case, 5)
+    errs = {k: relerr(g[k], ref[k]) for k in FIELDS}
+    print(case.name, precision, cells, errs, "iters", d["last_iters"])
+    assert d["last_relres"] <= rtol
+    if precision == "fp64":
+        assert max(errs.values()) < 1e-10, errs
+    else:
+        assert errs["phi"] < 1e-5 and max(errs.values()) < 1e-3, errs
+
+
+def test_autotune_stays_inside_its_scratch():
+    """The tuner's saved state fills exactly cdi_tune_bytes: guard bytes
+    right after the scratch are untouched (regression: a state copy once
+    overran it by one field)."""
+    torch = pytest.importorskip("torch")
+    import ctypes as C
+    from paper_2412_16843_amd import _lib as L
+    case = W.drop_case(64, 32, 60.0, 10.0)
+    s = _solver(case.params, case.phi0, rtol=1e-12)
+    s.step(2)
+    nb = s.lib.cdi_tune_bytes(s.ctx)
+    guard = 1 << 16
+    buf = torch.full((nb + guard + 256,), 0x5A, dtype=torch.uint8, device="cuda")
+    off = (-buf.data_ptr()) % 256
+    info = L.cdi_tune_info()
+    L.check(s.lib.cdi_tune(s.ctx, 2, buf.data_ptr() + off, nb, C.byref(info)))
+    torch.cuda.synchronize()
+    tail = buf[off + nb:off + nb + guard].cpu().numpy()
+    s.close()
+    assert (tail == 0x5A).all()
+
+
+@pytest.mark.parametrize("launch", ["tiled", "persistent"])
+@pytest.mark.parametrize("make", [
+    lambda: W.couette_case(256, 64, lx=4.0, ly=1.0),
+    lambda: W.drop_case(128, 64, 60.0, 10.0),
+])
+def test_two_sweep_pairs_match_oracle_in_fewer_iterations(launch, make):
+    """V(2,2) smoothing (mg_smooth = 2): same solution as the oracle, and
+    fewer CG iterations per solve than V(1,1)."""
+    case = make()
+    its = {}
+    for nu in (1, 2):
+        s = _solver(case.params, case.phi0, rtol=1e-13, maxit=400, launch=launch, mg_smooth=nu)
+        s.step(4)
+        its[nu] = s.diagnostics()["last_iters"]
+        g = s.state()
+        s.close()
+        if nu == 2:
+            ref, _ = _oracle(case, 4)
+            errs = {k: relerr(g[k], ref[k]) for k in FIELDS}
+            assert max(errs.values()) < 1e-10, errs
+    print(case.name, launch, "iterations V(1,1) / V(2,2):", its)
+    assert its[2] < its[1]
