@@ -585,7 +585,11 @@ cdi_status run_step(cdi_ctx* c) {
   for (int k = 0; k < 4; ++k) {
     const int src = k == 0 ? 0 : (k == 2 ? 2 : 1);
     const int dst = (k == 0 || k == 2) ? 1 : 2;
-    timed(c, "phase_prep", [&] { CDI_LAUNCH(c, k_phase_prep<S>, ncell, kNT, c->d_cell, c->d_inst, src); });
+    timed(c, "phase_prep", [&] {
+      with_rows(c->wide_rows, [&](auto R) {
+        CDI_LAUNCH(c, (k_phase_prep<S, decltype(R)::value>), nwide, kNT, c->d_wide, c->d_inst, src);
+      });
+    });
     // per-instance dt: c_next and tau are passed as multiples of the instance dt
     timed(c, "stage", [&] {
       CDI_LAUNCH(c, k_stage<S>, ncell, kNT, c->d_cell, c->d_inst, k, src, dst,
@@ -714,7 +718,9 @@ cdi_status graph_capture(cdi_ctx* c, int budget) {
       const int src = k == 0 ? 0 : (k == 2 ? 2 : 1);
       const int dst = (k == 0 || k == 2) ? 1 : 2;
       const double tfac = k < 3 ? RK_C[k + 1] : 1.0;
-      k_phase_prep<S><<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, src);
+      with_rows(c->wide_rows, [&](auto R) {
+        k_phase_prep<S, decltype(R)::value><<<nwide, kNT, 0, c->stream>>>(c->d_wide, c->d_inst, src);
+      });
       k_stage<S><<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, k, src, dst, tfac, RK_B[k], k == 3);
       with_rows(c->wide_rows, [&](auto R) {
         k_rhs<S, decltype(R)::value><<<nwide, kNT, 0, c->stream>>>(c->d_wide, c->d_inst, dst, tfac,
@@ -1067,10 +1073,10 @@ cdi_status cdi_eval_rhs(cdi_ctx* c, double* l_phi, double* l_mx, double* l_my, d
   const Inst& I = B.inst[0];
   const size_t nc = (size_t)I.nx * I.ny;
   if (c->mixed) {
-    k_phase_prep<float><<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, 0);
+    k_phase_prep<float, 1><<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, 0);
     k_stage<float><<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, -1, 0, 0, 0.0, 0.0, 1);
   } else {
-    k_phase_prep<double><<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, 0);
+    k_phase_prep<double, 1><<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, 0);
     k_stage<double><<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, -1, 0, 0, 0.0, 0.0, 1);
   }
   HIPCHK(hipGetLastError());
@@ -1090,8 +1096,8 @@ cdi_status cdi_diagnostics(cdi_ctx* c, int32_t idx, cdi_diag* out) {
   Batch& B = c->B;
   if (idx < 0 || idx >= B.n) return fail(CDI_ERR_ARG, "instance %d out of range", idx);
   const unsigned ncell = (unsigned)B.cell.size();
-  if (c->mixed) k_phase_prep<float><<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, 0);
-  else k_phase_prep<double><<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, 0);
+  if (c->mixed) k_phase_prep<float, 1><<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, 0);
+  else k_phase_prep<double, 1><<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, 0);
   k_wall<<<(unsigned)B.n, kNT, 0, c->stream>>>(c->d_inst);
   k_diag<<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, c->d_diag);
   HIPCHK(hipGetLastError());

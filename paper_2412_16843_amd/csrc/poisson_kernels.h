@@ -39,29 +39,52 @@ static_assert(FX * FY == 2 * kNT, "MG tile = 2 cells per thread");
 // (tau given as a multiple of the instance time step), the FP64 face
 // coefficients of the pressure operator (and their S copy for the V-cycle),
 // and the instance's mean of b.  Resets the CG state.
-// Right-hand side and operator coefficients at cell (j, i); returns b.
-template <typename S>
-__device__ __forceinline__ double rhs_cell(const Inst& I, const double* __restrict__ ph, int j,
-                                           int i, double tau) {
+// Right-hand side and operator coefficients at cell (j, i): the values it
+// reads (load) and the arithmetic and stores (store), split so that a thread
+// can issue the loads of all its cells first; rhs_cell does both; returns b.
+struct RhsIn {
+  double pc, pw, pe, ps, pn;   // phase field: cell, west, east, south, north
+  double mxo, mxe, myo, myn;   // (rho u)* on the west/east x-faces, south/north y-faces
+};
+
+__device__ __forceinline__ RhsIn rhs_load(const Inst& I, const double* __restrict__ ph, int j,
+                                          int i) {
   const int nx = I.nx, ny = I.ny;
   const size_t o = (size_t)j * nx + i;
   const int ie = wrap(i + 1, nx), iw = wrap(i - 1, nx);
+  RhsIn v;
+  v.pc = ph[o];
+  v.pw = ph[(size_t)j * nx + iw];
+  v.pe = ph[(size_t)j * nx + ie];
+  v.mxo = I.mx[o];
+  v.mxe = I.mx[(size_t)j * nx + ie];
+  v.ps = v.myo = v.pn = v.myn = 0.0;
+  if (j >= 1) { v.ps = ph[o - nx]; v.myo = I.my[o]; }
+  if (j + 1 <= ny - 1) { v.pn = ph[o + nx]; v.myn = I.my[o + nx]; }
+  return v;
+}
+
+template <typename S>
+__device__ __forceinline__ double rhs_store(const Inst& I, const RhsIn& v, int j, int i,
+                                            double tau) {
+  const int nx = I.nx, ny = I.ny;
+  const size_t o = (size_t)j * nx + i;
   const double r1 = I.rho1, r2 = I.rho2;
-  const double rc = (r1 - r2) * ph[o] + r2;
-  const double rw = (r1 - r2) * ph[(size_t)j * nx + iw] + r2;
-  const double re = (r1 - r2) * ph[(size_t)j * nx + ie] + r2;
+  const double rc = (r1 - r2) * v.pc + r2;
+  const double rw = (r1 - r2) * v.pw + r2;
+  const double re = (r1 - r2) * v.pe + r2;
   const double rfw = 0.5 * (rw + rc), rfe = 0.5 * (rc + re);
-  const double uw = I.mx[o] / rfw;
-  const double ue = I.mx[(size_t)j * nx + ie] / rfe;
+  const double uw = v.mxo / rfw;
+  const double ue = v.mxe / rfe;
   double vs = 0.0, vn = 0.0, rfs = 0.0;
   if (j >= 1) {
-    const double rs = (r1 - r2) * ph[o - nx] + r2;
+    const double rs = (r1 - r2) * v.ps + r2;
     rfs = 0.5 * (rs + rc);
-    vs = I.my[o] / rfs;
+    vs = v.myo / rfs;
   }
   if (j + 1 <= ny - 1) {
-    const double rn = (r1 - r2) * ph[o + nx] + r2;
-    vn = I.my[o + nx] / (0.5 * (rc + rn));
+    const double rn = (r1 - r2) * v.pn + r2;
+    vn = v.myn / (0.5 * (rc + rn));
   }
   const double b = ((ue - uw) + (vn - vs)) * I.inv_h / (tau * I.dt);
   I.ustar[o] = uw;
@@ -79,6 +102,12 @@ __device__ __forceinline__ double rhs_cell(const Inst& I, const double* __restri
   return b;
 }
 
+template <typename S>
+__device__ __forceinline__ double rhs_cell(const Inst& I, const double* __restrict__ ph, int j,
+                                           int i, double tau) {
+  return rhs_store<S>(I, rhs_load(I, ph, j, i), j, i, tau);
+}
+
 template <typename S, int WR>
 __global__ void __launch_bounds__(kNT) k_rhs(const Tile* __restrict__ tiles,
                                               const Inst* __restrict__ insts, int src, double tau,
@@ -89,10 +118,17 @@ __global__ void __launch_bounds__(kNT) k_rhs(const Tile* __restrict__ tiles,
   const int nx = I.nx, ny = I.ny;
   const double* __restrict__ ph = src == 0 ? I.phi : (src == 1 ? I.phi_a : I.phi_b);
   double bsum[2] = {0.0, 0.0};
+  RhsIn v[WR];
+#pragma unroll
+  for (int r = 0; r < WR; ++r) {
+    const int i = t.i0 + wide_tx(), j = t.j0 + wide_ty(r);
+    if (i < nx && j < ny) v[r] = rhs_load(I, ph, j, i);
+  }
+#pragma unroll
   for (int r = 0; r < WR; ++r) {
     const int i = t.i0 + wide_tx(), j = t.j0 + wide_ty(r);
     if (i < nx && j < ny) {
-      const double b = rhs_cell<S>(I, ph, j, i, tau);
+      const double b = rhs_store<S>(I, v[r], j, i, tau);
       bsum[0] += b;
       bsum[1] += b * b;
     }
@@ -187,20 +223,37 @@ __global__ void __launch_bounds__(kNT) k_pcg_init(const Tile* __restrict__ tiles
     __syncthreads();
   }
   double s[2] = {0.0, 0.0};
+  // every global read of the thread's rows first, then arithmetic and stores
+  double bv[WR], aw[WR], ae[WR], as[WR], an[WR];
+#pragma unroll
+  for (int r = 0; r < WR; ++r) {
+    const int i = t.i0 + wide_tx(), j = t.j0 + wide_ty(r);
+    bv[r] = aw[r] = ae[r] = as[r] = an[r] = 0.0;
+    if (i < nx && j < ny) {
+      const size_t o = (size_t)j * nx + i;
+      bv[r] = I.b[o];
+      if (guess) {
+        aw[r] = I.ax0[o];
+        ae[r] = I.ax0[(size_t)j * nx + wrap(i + 1, nx)];
+        if (j >= 1) as[r] = I.ay0[o];
+        if (j + 1 < ny) an[r] = I.ay0[o + nx];
+      }
+    }
+  }
+#pragma unroll
   for (int r = 0; r < WR; ++r) {
     const int tx = wide_tx(), ty = wide_ty(r);
     const int i = t.i0 + tx, j = t.j0 + ty;
     if (i < nx && j < ny) {
       const size_t o = (size_t)j * nx + i;
-      const double f = -(I.b[o] - bmean);
+      const double f = -(bv[r] - bmean);
       double rv = f, xc = 0.0;
       if (guess) {
         const int c = (ty + 1) * RX + tx + 1;
-        const int ie = wrap(i + 1, nx);
         xc = s_x[c];
-        double kx = I.ax0[o] * (xc - s_x[c - 1]) + I.ax0[(size_t)j * nx + ie] * (xc - s_x[c + 1]);
-        if (j >= 1) kx += I.ay0[o] * (xc - s_x[c - RX]);
-        if (j + 1 < ny) kx += I.ay0[o + nx] * (xc - s_x[c + RX]);
+        double kx = aw[r] * (xc - s_x[c - 1]) + ae[r] * (xc - s_x[c + 1]);
+        if (j >= 1) kx += as[r] * (xc - s_x[c - RX]);
+        if (j + 1 < ny) kx += an[r] * (xc - s_x[c + RX]);
         rv = f - kx;
       }
       I.x[o] = xc;
@@ -264,20 +317,35 @@ __global__ void __launch_bounds__(kNT) k_pcg_spmv(const Tile* __restrict__ tiles
   }
   __syncthreads();
   double s[2] = {0.0, 0.0};
+  // every global read of the thread's rows first, then arithmetic and stores
+  double aw[WR], ae[WR], as[WR], an[WR], rr[WR];
+#pragma unroll
+  for (int r = 0; r < WR; ++r) {
+    const int i = t.i0 + wide_tx(), j = t.j0 + wide_ty(r);
+    aw[r] = ae[r] = as[r] = an[r] = rr[r] = 0.0;
+    if (i < nx && j < ny) {
+      const size_t o = (size_t)j * nx + i;
+      aw[r] = I.ax0[o];
+      ae[r] = I.ax0[(size_t)j * nx + wrap(i + 1, nx)];
+      if (j >= 1) as[r] = I.ay0[o];
+      if (j + 1 < ny) an[r] = I.ay0[o + nx];
+      rr[r] = rv[o];
+    }
+  }
+#pragma unroll
   for (int r = 0; r < WR; ++r) {
     const int tx = wide_tx(), ty = wide_ty(r);
     const int i = t.i0 + tx, j = t.j0 + ty;
     if (i < nx && j < ny) {
       const size_t o = (size_t)j * nx + i;
       const int c = (ty + 1) * RX + tx + 1;
-      const int ie = wrap(i + 1, nx);
       const double dc = s_d[c];
-      double q = I.ax0[o] * (dc - s_d[c - 1]) + I.ax0[(size_t)j * nx + ie] * (dc - s_d[c + 1]);
-      if (j >= 1) q += I.ay0[o] * (dc - s_d[c - RX]);
-      if (j + 1 < ny) q += I.ay0[o + nx] * (dc - s_d[c + RX]);
+      double q = aw[r] * (dc - s_d[c - 1]) + ae[r] * (dc - s_d[c + 1]);
+      if (j >= 1) q += as[r] * (dc - s_d[c - RX]);
+      if (j + 1 < ny) q += an[r] * (dc - s_d[c + RX]);
       dnew[o] = dc;
       I.q[o] = q;
-      s[0] += dc * rv[o];
+      s[0] += dc * rr[r];
       s[1] += dc * q;
     }
   }
@@ -380,31 +448,56 @@ __global__ void __launch_bounds__(kNT) k_pcg_xmean(const Tile* __restrict__ tile
 // instance time step); the pressure is stored mean-free.  final_stage: the
 // result is the new state (caller fields) and the new phase field is copied
 // from phi_next.
-__device__ __forceinline__ void project_cell(const Inst& I, double tau, int final_stage,
-                                             const double* __restrict__ ph, int stage, bool zero,
-                                             double xmean, int j, int i) {
+// Projection at cell (j, i), split into the reads (project_load) and the
+// arithmetic and stores (project_store) like the right-hand side.
+struct ProjIn {
+  double xc, xw, xs;       // pressure iterate: cell, west, south
+  double us, vs, ax, ay;   // u*, v*, face coefficients
+  double hist, ph;         // stage pressure history; next phase field (final stage)
+};
+
+__device__ __forceinline__ ProjIn project_load(const Inst& I, int final_stage,
+                                               const double* __restrict__ ph, int stage,
+                                               bool zero, int j, int i) {
   const int nx = I.nx;
   const size_t o = (size_t)j * nx + i;
-  const double* __restrict__ x = I.x;
-  const double xc = zero ? 0.0 : x[o];
-  const double xw = zero ? 0.0 : x[(size_t)j * nx + wrap(i - 1, nx)];
+  ProjIn v;
+  v.xc = zero ? 0.0 : I.x[o];
+  v.xw = zero ? 0.0 : I.x[(size_t)j * nx + wrap(i - 1, nx)];
+  v.xs = (zero || j < 1) ? 0.0 : I.x[o - nx];
+  v.us = I.ustar[o];
+  v.ax = I.ax0[o];
+  v.vs = j >= 1 ? I.vstar[o] : 0.0;
+  v.ay = j >= 1 ? I.ay0[o] : 0.0;
+  v.hist = stage >= 0 ? I.ph[stage][o] : 0.0;
+  v.ph = final_stage ? ph[o] : 0.0;
+  return v;
+}
+
+__device__ __forceinline__ void project_store(const Inst& I, const ProjIn& v, double tau,
+                                              int final_stage, int stage, bool zero,
+                                              double xmean, int j, int i) {
+  const int nx = I.nx;
+  const size_t o = (size_t)j * nx + i;
   const double scale = tau * I.dt * I.h;   // tau grad(p)/rho_f = tau (p_c - p_w) h a_f
   double* __restrict__ uo = final_stage ? I.u : I.us;
   double* __restrict__ vo = final_stage ? I.v : I.vs;
-  uo[o] = I.ustar[o] - scale * (xc - xw) * I.ax0[o];
-  if (j >= 1) {
-    const double xs = zero ? 0.0 : x[o - nx];
-    vo[o] = I.vstar[o] - scale * (xc - xs) * I.ay0[o];
-  } else {
-    vo[o] = 0.0;
-  }
-  const double pn = xc - (zero ? 0.0 : xmean);
+  uo[o] = v.us - scale * (v.xc - v.xw) * v.ax;
+  vo[o] = j >= 1 ? v.vs - scale * (v.xc - v.xs) * v.ay : 0.0;
+  const double pn = v.xc - (zero ? 0.0 : xmean);
   I.p[o] = pn;
   if (stage >= 0) {   // pressure history of this RK stage (for the next step's guess)
-    I.ph2[stage][o] = I.ph[stage][o];
+    I.ph2[stage][o] = v.hist;
     I.ph[stage][o] = pn;
   }
-  if (final_stage) I.phi[o] = ph[o];
+  if (final_stage) I.phi[o] = v.ph;
+}
+
+__device__ __forceinline__ void project_cell(const Inst& I, double tau, int final_stage,
+                                             const double* __restrict__ ph, int stage, bool zero,
+                                             double xmean, int j, int i) {
+  project_store(I, project_load(I, final_stage, ph, stage, zero, j, i), tau, final_stage, stage,
+                zero, xmean, j, i);
 }
 
 template <int WR>
@@ -417,9 +510,16 @@ __global__ void __launch_bounds__(kNT) k_project(const Tile* __restrict__ tiles,
   const double* __restrict__ ph = src == 1 ? I.phi_a : I.phi_b;
   const bool zero = I.pcg->zero_rhs != 0;
   const double xmean = I.pcg->xmean;
+  ProjIn v[WR];
+#pragma unroll
   for (int r = 0; r < WR; ++r) {
     const int i = t.i0 + wide_tx(), j = t.j0 + wide_ty(r);
-    if (i < nx && j < ny) project_cell(I, tau, final_stage, ph, stage, zero, xmean, j, i);
+    if (i < nx && j < ny) v[r] = project_load(I, final_stage, ph, stage, zero, j, i);
+  }
+#pragma unroll
+  for (int r = 0; r < WR; ++r) {
+    const int i = t.i0 + wide_tx(), j = t.j0 + wide_ty(r);
+    if (i < nx && j < ny) project_store(I, v[r], tau, final_stage, stage, zero, xmean, j, i);
   }
 }
 

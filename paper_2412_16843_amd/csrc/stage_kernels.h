@@ -95,38 +95,20 @@ __device__ __forceinline__ T d2dy2_cell(const T* q, int stride, int j, int ny, T
 // rows also publish the extrapolated wall quantities of the slip models.
 // src: 0 caller phi, 1 phi_a, 2 phi_b.
 constexpr int PRY = TY + 6, PRX = TX + 2;   // rows j0-3 .. j0+TY+2, cols i0-1 .. i0+TX
-template <typename S>
+// LDS of one phase-preparation tile of TX x (WR * TY) cells
+template <typename S, int WR = 1>
 struct PrepLds {
-  double phi[PRY * PRX];
-  S psi[PRY * PRX];
+  double phi[(WR * TY + 6) * PRX];
+  S psi[(WR * TY + 6) * PRX];
 };
 
-// One tile of the phase preparation, run by kNT threads (tid in [0, kNT)).
-// Contains one block barrier: every thread of the block calls it, with
-// active = false for threads that have no tile in this round.
-template <typename S>
-__device__ __forceinline__ void phase_prep_tile(const Tile& t, const Inst& I, int src,
-                                                PrepLds<S>& L, int tid, bool active) {
-  constexpr int RY = PRY, RX = PRX;
-  double* s_phi = L.phi;
-  S* s_psi = L.psi;
+// Cell (ty, tx) of a phase-preparation tile whose LDS region has RY rows.
+template <typename S, int RY>
+__device__ __forceinline__ void phase_prep_cell(const Tile& t, const Inst& I,
+                                                const double* s_phi, const S* s_psi, int tx,
+                                                int ty) {
+  constexpr int RX = PRX;
   const int nx = I.nx, ny = I.ny;
-  const double* __restrict__ phi = src == 0 ? I.phi : (src == 1 ? I.phi_a : I.phi_b);
-  for (int k = tid; active && k < RY * RX; k += kNT) {
-    const int rj = k / RX, ri = k - rj * RX;
-    const int j = t.j0 - 3 + rj, i = wrap_any(t.i0 - 1 + ri, nx);
-    double f = 0.0, ps = 0.0;
-    if (j >= 0 && j < ny) {
-      f = phi[(size_t)j * nx + i];
-      const double c = fmin(fmax(f, 0.0), 1.0);
-      ps = I.eps * log((c + kDeltaPsi) / (1.0 - c + kDeltaPsi));   // psi from FP64 phi
-    }
-    s_phi[k] = f;
-    s_psi[k] = (S)ps;
-  }
-  __syncthreads();
-  if (!active) return;
-  const int tx = tid % TX, ty = tid / TX;
   const int i = t.i0 + tx, j = t.j0 + ty;
   if (i >= nx || j >= ny) return;
   const int c = (ty + 3) * RX + (tx + 1);
@@ -193,13 +175,59 @@ __device__ __forceinline__ void phase_prep_tile(const Tile& t, const Inst& I, in
   }
 }
 
-template <typename S>
+// One tile of the phase preparation (TX x WR*TY cells, WR rows per thread),
+// run by kNT threads (tid in [0, kNT)).  Contains one block barrier: every
+// thread of the block calls it, with active = false for threads that have no
+// tile in this round.
+template <typename S, int WR = 1>
+__device__ __forceinline__ void phase_prep_tile(const Tile& t, const Inst& I, int src,
+                                                PrepLds<S, WR>& L, int tid, bool active) {
+  constexpr int RY = WR * TY + 6, RX = PRX;
+  constexpr int NPT = (RY * RX + kNT - 1) / kNT;
+  double* s_phi = L.phi;
+  S* s_psi = L.psi;
+  const int nx = I.nx, ny = I.ny;
+  const double* __restrict__ phi = src == 0 ? I.phi : (src == 1 ? I.phi_a : I.phi_b);
+  // every load of the thread's region cells first, then psi from FP64 phi
+  double fv[NPT];
+#pragma unroll
+  for (int e = 0; e < NPT; ++e) {
+    const int k = tid + e * kNT;
+    const int rj = k / RX, ri = k - rj * RX;
+    const int j = t.j0 - 3 + rj;
+    fv[e] = 0.0;
+    if (active && k < RY * RX && j >= 0 && j < ny)
+      fv[e] = phi[(size_t)j * nx + wrap_any(t.i0 - 1 + ri, nx)];
+  }
+#pragma unroll
+  for (int e = 0; e < NPT; ++e) {
+    const int k = tid + e * kNT;
+    if (!active || k >= RY * RX) continue;
+    const int j = t.j0 - 3 + k / RX;
+    double ps = 0.0;
+    if (j >= 0 && j < ny) {
+      const double c = fmin(fmax(fv[e], 0.0), 1.0);
+      ps = I.eps * log((c + kDeltaPsi) / (1.0 - c + kDeltaPsi));
+    }
+    s_phi[k] = fv[e];
+    s_psi[k] = (S)ps;
+  }
+  __syncthreads();
+  if (!active) return;
+#pragma unroll
+  for (int row = 0; row < WR; ++row)
+    phase_prep_cell<S, RY>(t, I, s_phi, s_psi, tid % TX, tid / TX + row * TY);
+}
+
+template <typename S, int WR>
 __global__ void __launch_bounds__(kNT) k_phase_prep(const Tile* __restrict__ tiles,
                                                      const Inst* __restrict__ insts, int src) {
-  __shared__ PrepLds<S> L;
+  __shared__ PrepLds<S, WR> L;
   const Tile t = tiles[blockIdx.x];
-  phase_prep_tile<S>(t, insts[t.inst], src, L, threadIdx.x, true);
+  phase_prep_tile<S, WR>(t, insts[t.inst], src, L, threadIdx.x, true);
 }
+
+
 
 // ------------------------------------------------------------ stage operator
 // One RK4 stage: CDI face fluxes F = u phi_f - gamma[eps dphi/h - phi_f(1-phi_f) n_f]
@@ -252,21 +280,63 @@ __device__ __forceinline__ void stage_tile(const Tile& t, const Inst& I, int k, 
   const S* __restrict__ gny = (const S*)I.nhy;
   const S* __restrict__ gmc = (const S*)I.muc;
 
-  for (int q = tid; active && q < CY * CX; q += kNT) {
-    const int rj = q / CX, ri = q - rj * CX;
-    const int j = j0 - 2 + rj, i = wrap_any(i0 - 2 + ri, nx);
-    S a = 0, b = 0, c = 0, d = 0;
-    if (j >= 0 && j < ny) {
-      const size_t o = (size_t)j * nx + i;
-      a = (S)phs[o]; b = gnx[o]; c = gny[o]; d = gmc[o];
-    }
-    s_phi[q] = a; s_nx[q] = b; s_ny[q] = c; s_mc[q] = d;
+  // operands of this thread's RK update, fetched now so that their latency
+  // hides behind the LDS phases (own cell; west and south base densities)
+  const int ctx = tid % TX, cty = tid / TX;
+  const int ci = i0 + ctx, cj = j0 + cty;
+  const bool own = active && ci < nx && cj < ny;
+  const size_t co_ = own ? (size_t)cj * nx + ci : 0;
+  double pre_acc[3] = {0.0, 0.0, 0.0}, pre_phn = 0.0, pre_phw = 0.0, pre_phs = 0.0;
+  double pre_u = 0.0, pre_v = 0.0;
+  if (own && k >= 0) {
+    const double* __restrict__ phn0 = I.phi;
+    if (k > 0) { pre_acc[0] = I.acc_phi[co_]; pre_acc[1] = I.acc_mx[co_]; pre_acc[2] = I.acc_my[co_]; }
+    pre_phn = phn0[co_];
+    pre_phw = phn0[(size_t)cj * nx + wrap(ci - 1, nx)];
+    if (cj >= 1) pre_phs = phn0[co_ - nx];
+    pre_u = I.u[co_];
+    pre_v = I.v[co_];
   }
-  for (int q = tid; active && q < UY * UX; q += kNT) {
-    const int rj = q / UX, ri = q - rj * UX;
-    const int j = j0 - 1 + rj, i = wrap_any(i0 - 1 + ri, nx);
-    s_u[q] = (j >= 0 && j < ny) ? (S)us[(size_t)j * nx + i] : S(0);
-    s_v[q] = (j >= 0 && j <= ny) ? (S)vs[(size_t)j * nx + i] : S(0);
+  // halo regions: every load of the thread first, then the LDS stores
+  {
+    constexpr int NC = (CY * CX + kNT - 1) / kNT, NU = (UY * UX + kNT - 1) / kNT;
+    S va[NC][4];
+    S vu[NU][2];
+#pragma unroll
+    for (int e = 0; e < NC; ++e) {
+      const int q = tid + e * kNT;
+      const int rj = q / CX, ri = q - rj * CX;
+      const int j = j0 - 2 + rj;
+      va[e][0] = va[e][1] = va[e][2] = va[e][3] = S(0);
+      if (active && q < CY * CX && j >= 0 && j < ny) {
+        const size_t o = (size_t)j * nx + wrap_any(i0 - 2 + ri, nx);
+        va[e][0] = (S)phs[o]; va[e][1] = gnx[o]; va[e][2] = gny[o]; va[e][3] = gmc[o];
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < NU; ++e) {
+      const int q = tid + e * kNT;
+      const int rj = q / UX, ri = q - rj * UX;
+      const int j = j0 - 1 + rj;
+      vu[e][0] = vu[e][1] = S(0);
+      if (active && q < UY * UX) {
+        const size_t o = (size_t)j * nx + wrap_any(i0 - 1 + ri, nx);
+        if (j >= 0 && j < ny) vu[e][0] = (S)us[o];
+        if (j >= 0 && j <= ny) vu[e][1] = (S)vs[o];
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < NC; ++e) {
+      const int q = tid + e * kNT;
+      if (active && q < CY * CX) {
+        s_phi[q] = va[e][0]; s_nx[q] = va[e][1]; s_ny[q] = va[e][2]; s_mc[q] = va[e][3];
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < NU; ++e) {
+      const int q = tid + e * kNT;
+      if (active && q < UY * UX) { s_u[q] = vu[e][0]; s_v[q] = vu[e][1]; }
+    }
   }
   __syncthreads();
   const S gam = (S)I.gamma, eps = (S)I.eps, inv_h = (S)I.inv_h;
@@ -400,33 +470,34 @@ __device__ __forceinline__ void stage_tile(const Tile& t, const Inst& I, int k, 
     I.acc_my[o] = (double)Lmy;
     return;
   }
-  // ---- RK4 accumulation and next stage
+  // ---- RK4 accumulation and next stage (operands prefetched above)
+  (void)phn;
   double ap, am, an;
   if (k == 0) {
     ap = b_k * Lphi; am = b_k * (double)Lmx; an = b_k * (double)Lmy;
   } else {
-    ap = I.acc_phi[o] + b_k * Lphi;
-    am = I.acc_mx[o] + b_k * (double)Lmx;
-    an = I.acc_my[o] + b_k * (double)Lmy;
+    ap = pre_acc[0] + b_k * Lphi;
+    am = pre_acc[1] + b_k * (double)Lmx;
+    an = pre_acc[2] + b_k * (double)Lmy;
   }
   const double cn = c_next * I.dt;   // RK c_{k+1} dt of this instance
   const double r1 = I.rho1, r2 = I.rho2;
-  const double rl = (r1 - r2) * phn[(size_t)j * nx + wrap(i - 1, nx)] + r2;
-  const double rc = (r1 - r2) * phn[o] + r2;
+  const double rl = (r1 - r2) * pre_phw + r2;
+  const double rc = (r1 - r2) * pre_phn + r2;
   const double rfx0 = 0.5 * (rl + rc);
-  const double mx0 = rfx0 * I.u[o];
+  const double mx0 = rfx0 * pre_u;
   if (k < 3) {
     I.acc_phi[o] = ap; I.acc_mx[o] = am;
-    pdst[o] = phn[o] + cn * Lphi;
+    pdst[o] = pre_phn + cn * Lphi;
     I.mx[o] = mx0 + cn * (double)Lmx;
   } else {
-    pdst[o] = phn[o] + I.dt * ap;
+    pdst[o] = pre_phn + I.dt * ap;
     I.mx[o] = mx0 + I.dt * am;
   }
   if (j >= 1) {
-    const double rb = (r1 - r2) * phn[o - nx] + r2;
+    const double rb = (r1 - r2) * pre_phs + r2;
     const double rfy0 = 0.5 * (rb + rc);
-    const double my0 = rfy0 * I.v[o];
+    const double my0 = rfy0 * pre_v;
     if (k < 3) {
       I.acc_my[o] = an;
       I.my[o] = my0 + cn * (double)Lmy;
