@@ -631,13 +631,17 @@ __global__ void __launch_bounds__(kNT) k_mg_down(const Tile* __restrict__ tiles,
            s_ay[(rj + 1) * RX + ri];
   };
   auto valid = [&](int rj) { const int j = j0 - H + rj; return j >= 0 && j < ny; };
-  // red cells: z = r / D over the whole region
-  for (int k = threadIdx.x; k < RY * RX; k += kNT) {
-    const int rj = k / RX, ri = k - rj * RX;
-    const int j = j0 - H + rj, i = i0 - H + ri;
-    S z = 0;
-    if (valid(rj) && ((i + j) & 1) == 0) z = s_r[k] / diag(rj, ri);
-    s_z[k] = z;
+  // The region's colour is (rj + ri) & 1 (i0, j0 even): the sweeps visit
+  // only cells of their colour, RX/2 per row, so no lane idles on the other
+  // colour.
+  static_assert(RX % 2 == 0, "colour-compact sweeps need an even region width");
+  constexpr int HX = RX / 2;
+  // red cells: z = r / D over the whole region; black cells start at 0
+  for (int k = threadIdx.x; k < RY * RX; k += kNT) s_z[k] = S(0);
+  __syncthreads();
+  for (int h = threadIdx.x; h < RY * HX; h += kNT) {
+    const int rj = h / HX, ri = 2 * (h - rj * HX) + (rj & 1);
+    if (valid(rj)) s_z[rj * RX + ri] = s_r[rj * RX + ri] / diag(rj, ri);
   }
   __syncthreads();
   // then Gauss-Seidel half-sweeps black, red, black, ... (half-sweep sw on
@@ -645,11 +649,10 @@ __global__ void __launch_bounds__(kNT) k_mg_down(const Tile* __restrict__ tiles,
 #pragma unroll
   for (int sw = 1; sw < 2 * NU; ++sw) {
     const int color = sw & 1;   // 1 black, 0 red
-    for (int k = threadIdx.x; k < RY * RX; k += kNT) {
-      const int rj = k / RX, ri = k - rj * RX;
-      if (rj < sw || rj >= RY - sw || ri < sw || ri >= RX - sw) continue;
-      const int j = j0 - H + rj, i = i0 - H + ri;
-      if (!valid(rj) || ((i + j) & 1) != color) continue;
+    for (int h = threadIdx.x; h < (RY - 2 * sw) * HX; h += kNT) {
+      const int rj = sw + h / HX, ri = 2 * (h % HX) + ((rj + color) & 1);
+      if (ri < sw || ri >= RX - sw || !valid(rj)) continue;
+      const int k = rj * RX + ri;
       const S aw = s_ax[rj * (RX + 1) + ri], ae = s_ax[rj * (RX + 1) + ri + 1];
       const S as = s_ay[rj * RX + ri], an = s_ay[(rj + 1) * RX + ri];
       const S nb = aw * s_z[k - 1] + ae * s_z[k + 1] + as * s_z[k - RX] + an * s_z[k + RX];
@@ -770,16 +773,18 @@ __global__ void __launch_bounds__(kNT) k_mg_up(const Tile* __restrict__ tiles,
   };
   // half-sweeps black, red, ... (the reverse of the pre-smoothing), the
   // last one (red) on the tile itself
+  // colour of region cell (rj, ri) is (rj + ri) & 1 (i0, j0, H even): the
+  // sweeps visit only cells of their colour
+  static_assert(RX % 2 == 0, "colour-compact sweeps need an even region width");
+  constexpr int HX = RX / 2;
 #pragma unroll
   for (int sw = 0; sw < 2 * NU; ++sw) {
     const int color = (sw & 1) ? 0 : 1;   // black first
     const int m = sw + 1;
-    for (int k = threadIdx.x; k < RY * RX; k += kNT) {
-      const int rj = k / RX, ri = k - rj * RX;
-      if (rj < m || rj >= RY - m || ri < m || ri >= RX - m) continue;
-      const int j = j0 - H + rj, i = i0 - H + ri;
-      if (!valid(rj) || ((i + j) & 1) != color) continue;
-      s_z[k] = gs(k, rj, ri);
+    for (int h = threadIdx.x; h < (RY - 2 * m) * HX; h += kNT) {
+      const int rj = m + h / HX, ri = 2 * (h % HX) + ((rj + color) & 1);
+      if (ri < m || ri >= RX - m || !valid(rj)) continue;
+      s_z[rj * RX + ri] = gs(rj * RX + ri, rj, ri);
     }
     __syncthreads();
   }
