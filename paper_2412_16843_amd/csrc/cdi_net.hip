@@ -97,16 +97,17 @@ size_t carve(cdi_net* n, char* base, bool train) {
   n->e[2] = act(128, 2);
   n->p[2] = act(128, 3);
   n->e[3] = act(256, 3);
-  n->c2 = act(384, 2);
   n->d2 = act(128, 2);
-  n->c1 = act(192, 1);
   n->d1 = act(64, 1);
-  n->c0 = act(96, 0);
   n->d0 = act(32, 0);
   n->y = (float*)take(B * H * W * sizeof(float));
   n->loss = (float*)take(256);
   n->train = train;
   if (train) {
+    // the decoder's concatenated inputs, read by the weight gradient
+    n->c2 = act(384, 2);
+    n->c1 = act(192, 1);
+    n->c0 = act(96, 0);
     n->dd0 = act(32, 0); n->dc0 = act(96, 0);
     n->dd1 = act(64, 1); n->dc1 = act(192, 1);
     n->dd2 = act(128, 2); n->dc2 = act(384, 2);
@@ -127,19 +128,22 @@ size_t carve(cdi_net* n, char* base, bool train) {
 }
 
 unsigned grid1d(size_t n) { return (unsigned)std::min<size_t>(4096, (n + 255) / 256); }
+unsigned rows_grid(size_t rows) { return (unsigned)std::min<size_t>(65535, std::max<size_t>(1, rows)); }
 
+// 3x3 convolution at `level`; with xlo the input is cat(up2(xlo), x) read
+// in place (clo channels from xlo).
 void conv(cdi_net* n, const __bf16* x, const __bf16* w, const float* bias, __bf16* yb, float* yf,
-          int ci, int co, int level, int relu) {
+          int ci, int co, int level, int relu, const __bf16* xlo = nullptr, int clo = 0) {
   const int H = n->H >> level, W = n->W >> level;
   const int nxt = (W + TPX - 1) / TPX;
   if (co <= 32) {   // 32-channel tile, 4 rows per block
     const int rows = CROWS * 2;
     dim3 grid((unsigned)(n->B * ((H + rows - 1) / rows) * nxt), (unsigned)((co + 31) / 32));
-    k_conv3_fwd<2><<<grid, NT, 0, n->stream>>>(x, w, bias, yb, yf, n->B, ci, co, H, W, relu);
+    k_conv3_fwd<2><<<grid, NT, 0, n->stream>>>(x, w, bias, yb, yf, n->B, ci, co, H, W, relu, xlo, clo);
   } else {          // 64-channel tile, 2 rows per block
     const int rows = CROWS;
     dim3 grid((unsigned)(n->B * ((H + rows - 1) / rows) * nxt), (unsigned)((co + 63) / 64));
-    k_conv3_fwd<4><<<grid, NT, 0, n->stream>>>(x, w, bias, yb, yf, n->B, ci, co, H, W, relu);
+    k_conv3_fwd<4><<<grid, NT, 0, n->stream>>>(x, w, bias, yb, yf, n->B, ci, co, H, W, relu, xlo, clo);
   }
 }
 
@@ -167,12 +171,17 @@ void forward(cdi_net* n) {
   conv(n, n->p[1], n->wp[2], P + n->boff[2], n->e[2], nullptr, 64, 128, 2, 1);
   k_pool<<<grid1d((size_t)B * 128 * HW / 64), 256, 0, n->stream>>>(n->e[2], n->p[2], B * 128, H / 4, W / 4);
   conv(n, n->p[2], n->wp[3], P + n->boff[3], n->e[3], nullptr, 128, 256, 3, 1);
-  k_upcat<<<grid1d((size_t)B * 384 * HW / 16), 256, 0, n->stream>>>(n->e[3], n->e[2], n->c2, B, 256, 128, H / 4, W / 4);
-  conv(n, n->c2, n->wp[4], P + n->boff[4], n->d2, nullptr, 384, 128, 2, 1);
-  k_upcat<<<grid1d((size_t)B * 192 * HW / 4), 256, 0, n->stream>>>(n->d2, n->e[1], n->c1, B, 128, 64, H / 2, W / 2);
-  conv(n, n->c1, n->wp[5], P + n->boff[5], n->d1, nullptr, 192, 64, 1, 1);
-  k_upcat<<<grid1d((size_t)B * 96 * HW), 256, 0, n->stream>>>(n->d1, n->e[0], n->c0, B, 64, 32, H, W);
-  conv(n, n->c0, n->wp[6], P + n->boff[6], n->d0, nullptr, 96, 32, 0, 1);
+  // decoder: the convolutions read cat(up2(lo), skip) in place; training
+  // also stores the concatenation, which the weight gradient reads
+  if (n->train)
+    k_upcat<<<rows_grid((size_t)B * 384 * (H / 4)), 256, 0, n->stream>>>(n->e[3], n->e[2], n->c2, B, 256, 128, H / 4, W / 4);
+  conv(n, n->e[2], n->wp[4], P + n->boff[4], n->d2, nullptr, 384, 128, 2, 1, n->e[3], 256);
+  if (n->train)
+    k_upcat<<<rows_grid((size_t)B * 192 * (H / 2)), 256, 0, n->stream>>>(n->d2, n->e[1], n->c1, B, 128, 64, H / 2, W / 2);
+  conv(n, n->e[1], n->wp[5], P + n->boff[5], n->d1, nullptr, 192, 64, 1, 1, n->d2, 128);
+  if (n->train)
+    k_upcat<<<rows_grid((size_t)B * 96 * H), 256, 0, n->stream>>>(n->d1, n->e[0], n->c0, B, 64, 32, H, W);
+  conv(n, n->e[0], n->wp[6], P + n->boff[6], n->d0, nullptr, 96, 32, 0, 1, n->d1, 64);
   k_out_fwd<<<grid1d((size_t)B * HW), 256, 0, n->stream>>>(n->d0, P + n->out_w, P + n->out_b, n->y, B, 32, (int)HW);
 }
 

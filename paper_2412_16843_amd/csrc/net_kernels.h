@@ -38,12 +38,20 @@ __device__ __forceinline__ __bf16 f2bf(float v) { return (__bf16)v; }
 // group; 2: 32-channel tile for 32-channel layers, the other two waves take
 // two more rows), so no wave multiplies padding channels.
 constexpr int CROWS = 2;   // rows per wave
+//
+// Decoder form (xlo != nullptr): the input is cat(up2(xlo), x) without being
+// stored -- channels [0, clo) are read from xlo (B x clo x H/2 x W/2) at
+// (row/2, col/2), channels [clo, ci) from x (B x (ci-clo) x H x W); clo is a
+// multiple of 32, so each 32-channel step reads one of the two.
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 template <int WCO>
 __global__ void __launch_bounds__(NT) k_conv3_fwd(const __bf16* __restrict__ x,
                                                   const __bf16* __restrict__ wp,
                                                   const float* __restrict__ bias,
                                                   __bf16* __restrict__ yb, float* __restrict__ yf,
-                                                  int B, int ci, int co, int H, int W, int relu) {
+                                                  int B, int ci, int co, int H, int W, int relu,
+                                                  const __bf16* __restrict__ xlo = nullptr,
+                                                  int clo = 0) {
   constexpr int TC = 16 * WCO;                       // output channels of the tile
   constexpr int ROWS = CROWS * (4 / WCO);            // output rows of the tile
   constexpr int XR = ROWS + 2;                       // staged input rows
@@ -69,7 +77,11 @@ __global__ void __launch_bounds__(NT) k_conv3_fwd(const __bf16* __restrict__ x,
   const size_t plane = (size_t)H * W;
   const int kq = 8 * (lane >> 4);
   const int li = lane & 15;
+  const int hh = H / 2, wh = W / 2;
+  const size_t plane_lo = (size_t)hh * wh;
+  const int cskip = ci - clo;
   for (int c0 = 0; c0 < ci; c0 += KC) {
+    const bool lo = xlo != nullptr && c0 < clo;   // this step reads the upsampled tensor
     // input rows row0-1 .. row0+ROWS: 8-column vectors of the 64-column core
     for (int e = tid; e < KC * XR * (TPX / 8); e += NT) {
       const int v8 = e % (TPX / 8);
@@ -80,13 +92,29 @@ __global__ void __launch_bounds__(NT) k_conv3_fwd(const __bf16* __restrict__ x,
 #pragma unroll
       for (int q = 0; q < 8; ++q) v[q] = f2bf(0.f);
       if (yy >= 0 && yy < H && xx < W) {
-        const __bf16* src = &x[((size_t)b * ci + c0 + c) * plane + (size_t)yy * W + xx];
-        if (vec && xx + 8 <= W) {
-          v = *(const bf16x8*)src;   // 16-byte aligned: W and the plane are multiples of 8
-        } else {
+        if (lo) {
+          // 8 columns xx..xx+7 of up2(xlo) = 4 columns xx/2.. of xlo, each twice
+          const __bf16* src = &xlo[((size_t)b * clo + c0 + c) * plane_lo + (size_t)(yy >> 1) * wh + (xx >> 1)];
+          if (vec && xx + 8 <= W) {
+            const bf16x4 h4 = *(const bf16x4*)src;   // 8-byte aligned: W/2 and the plane are multiples of 4
 #pragma unroll
-          for (int q = 0; q < 8; ++q)
-            if (xx + q < W) v[q] = src[q];
+            for (int q = 0; q < 8; ++q) v[q] = h4[q >> 1];
+          } else {
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+              if (xx + q < W) v[q] = src[q >> 1];
+          }
+        } else {
+          const __bf16* src = xlo != nullptr
+              ? &x[((size_t)b * cskip + (c0 - clo) + c) * plane + (size_t)yy * W + xx]
+              : &x[((size_t)b * ci + c0 + c) * plane + (size_t)yy * W + xx];
+          if (vec && xx + 8 <= W) {
+            v = *(const bf16x8*)src;   // 16-byte aligned: W and the plane are multiples of 8
+          } else {
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+              if (xx + q < W) v[q] = src[q];
+          }
         }
       }
 #pragma unroll
@@ -99,7 +127,11 @@ __global__ void __launch_bounds__(NT) k_conv3_fwd(const __bf16* __restrict__ x,
       const int c = e / (2 * XR);
       const int yy = row0 + r - 1, xx = side ? x0 + TPX : x0 - 1;
       __bf16 v = f2bf(0.f);
-      if (yy >= 0 && yy < H && xx >= 0 && xx < W) v = x[((size_t)b * ci + c0 + c) * plane + (size_t)yy * W + xx];
+      if (yy >= 0 && yy < H && xx >= 0 && xx < W) {
+        if (lo) v = xlo[((size_t)b * clo + c0 + c) * plane_lo + (size_t)(yy >> 1) * wh + (xx >> 1)];
+        else if (xlo != nullptr) v = x[((size_t)b * cskip + (c0 - clo) + c) * plane + (size_t)yy * W + xx];
+        else v = x[((size_t)b * ci + c0 + c) * plane + (size_t)yy * W + xx];
+      }
       s_x[(r * (TPX + 2) + (side ? TPX + 1 : 0)) * KC + c] = v;
     }
     // weights of the tile: 4 vectors of 8 input channels per (o, tap)
@@ -300,16 +332,20 @@ __global__ void k_pool(const __bf16* __restrict__ x, __bf16* __restrict__ y, int
 // y[b] = cat(up2(lo[b]) (clo channels), skip[b] (cs channels)) at H x W
 __global__ void k_upcat(const __bf16* __restrict__ lo, const __bf16* __restrict__ skip,
                         __bf16* __restrict__ y, int B, int clo, int cs, int H, int W) {
+  // one output row (b, c, i) per loop step of a block; columns across threads
   const int C = clo + cs;
-  const size_t n = (size_t)B * C * H * W;
-  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
-    const int j = e % W, i = (e / W) % H;
-    const int c = (e / ((size_t)W * H)) % C;
-    const int b = e / ((size_t)W * H * C);
-    __bf16 v;
-    if (c < clo) v = lo[(((size_t)b * clo + c) * (H / 2) + i / 2) * (W / 2) + j / 2];
-    else v = skip[(((size_t)b * cs + (c - clo)) * H + i) * W + j];
-    y[e] = v;
+  const int nrows = B * C * H;
+  for (int row = blockIdx.x; row < nrows; row += gridDim.x) {
+    const int i = row % H, bc = row / H;
+    const int c = bc % C, b = bc / C;
+    __bf16* out = y + (size_t)row * W;
+    if (c < clo) {
+      const __bf16* src = lo + (((size_t)b * clo + c) * (H / 2) + i / 2) * (W / 2);
+      for (int j = threadIdx.x; j < W; j += blockDim.x) out[j] = src[j >> 1];
+    } else {
+      const __bf16* src = skip + (((size_t)b * cs + (c - clo)) * H + i) * W;
+      for (int j = threadIdx.x; j < W; j += blockDim.x) out[j] = src[j];
+    }
   }
 }
 

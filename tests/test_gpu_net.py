@@ -58,6 +58,29 @@ def test_network_forward_and_gradients_match_fp64_oracle(B, H, Wd):
     net.close()
 
 
+@pytest.mark.parametrize("B,H,Wd", [(2, 16, 16), (1, 24, 40), (1, 32, 96)])
+def test_inference_forward_equals_training_forward(B, H, Wd):
+    """The inference net reads cat(up2(lo), skip) in place inside the decoder
+    convolutions; the training net additionally stores the concatenation.
+    Both must give the same output bit for bit, and match the oracle (widths
+    24 and 40 take the unvectorised column path at some level)."""
+    torch = _torch()
+    from paper_2412_16843_amd import learned
+    rng = np.random.default_rng(11)
+    p = _rand_params(3)
+    x = rng.standard_normal((B, 3, H, Wd))
+    tr = learned.GuessNet(B, H, Wd, params=learned.flatten(p))
+    inf = learned.GuessNet(B, H, Wd, params=learned.flatten(p), train=False)
+    xt = torch.as_tensor(x, dtype=torch.float32)
+    y_tr = tr.forward(xt).cpu().numpy()
+    y_inf = inf.forward(xt).cpu().numpy()
+    tr.close()
+    inf.close()
+    assert np.array_equal(y_tr, y_inf)
+    y_ref, _ = unet.forward(p, x)
+    assert np.linalg.norm(y_inf - y_ref[:, 0]) / np.linalg.norm(y_ref) < 3e-2
+
+
 def test_training_reduces_loss_and_guess_beats_zero():
     torch = _torch()
     from paper_2412_16843_amd import learned, train_guess
