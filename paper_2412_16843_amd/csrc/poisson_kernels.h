@@ -28,6 +28,7 @@ namespace cdi {
 
 constexpr int kCoarseCells = 1024;   // levels at or below this size run in one block
 constexpr int kCoarseNT = 1024;
+static_assert(kCoarseCells <= kCoarseNT, "a coarse right-hand side is loaded one value per thread");
 constexpr int kDenseMax = 64;        // coarsest grids up to this size use a dense inverse
 constexpr int kCLX = 1376;           // LDS cells of all coarse levels (<= 1024 * 4/3)
 constexpr int kCLY = 2432;           // LDS y-faces of all coarse levels
@@ -64,11 +65,9 @@ __device__ __forceinline__ RhsIn rhs_load(const Inst& I, const double* __restric
   return v;
 }
 
-template <typename S>
-__device__ __forceinline__ double rhs_store(const Inst& I, const RhsIn& v, int j, int i,
-                                            double tau) {
-  const int nx = I.nx, ny = I.ny;
-  const size_t o = (size_t)j * nx + i;
+// b at cell row j from the gathered values (the arithmetic of rhs_store).
+__device__ __forceinline__ double rhs_value(const Inst& I, const RhsIn& v, int j, double tau) {
+  const int ny = I.ny;
   const double r1 = I.rho1, r2 = I.rho2;
   const double rc = (r1 - r2) * v.pc + r2;
   const double rw = (r1 - r2) * v.pw + r2;
@@ -76,17 +75,35 @@ __device__ __forceinline__ double rhs_store(const Inst& I, const RhsIn& v, int j
   const double rfw = 0.5 * (rw + rc), rfe = 0.5 * (rc + re);
   const double uw = v.mxo / rfw;
   const double ue = v.mxe / rfe;
-  double vs = 0.0, vn = 0.0, rfs = 0.0;
+  double vs = 0.0, vn = 0.0;
   if (j >= 1) {
     const double rs = (r1 - r2) * v.ps + r2;
-    rfs = 0.5 * (rs + rc);
-    vs = v.myo / rfs;
+    vs = v.myo / (0.5 * (rs + rc));
   }
   if (j + 1 <= ny - 1) {
     const double rn = (r1 - r2) * v.pn + r2;
     vn = v.myn / (0.5 * (rc + rn));
   }
-  const double b = ((ue - uw) + (vn - vs)) * I.inv_h / (tau * I.dt);
+  return ((ue - uw) + (vn - vs)) * I.inv_h / (tau * I.dt);
+}
+
+template <typename S>
+__device__ __forceinline__ double rhs_store(const Inst& I, const RhsIn& v, int j, int i,
+                                            double tau) {
+  const int nx = I.nx;
+  const size_t o = (size_t)j * nx + i;
+  const double r1 = I.rho1, r2 = I.rho2;
+  const double rc = (r1 - r2) * v.pc + r2;
+  const double rw = (r1 - r2) * v.pw + r2;
+  const double rfw = 0.5 * (rw + rc);
+  const double uw = v.mxo / rfw;
+  double vs = 0.0, rfs = 0.0;
+  if (j >= 1) {
+    const double rs = (r1 - r2) * v.ps + r2;
+    rfs = 0.5 * (rs + rc);
+    vs = v.myo / rfs;
+  }
+  const double b = rhs_value(I, v, j, tau);
   I.ustar[o] = uw;
   I.vstar[o] = vs;
   I.b[o] = b;
@@ -139,8 +156,9 @@ __global__ void __launch_bounds__(kNT) k_rhs(const Tile* __restrict__ tiles,
     st_agent(&I.part[I.nwide + t.local], bsum[1]);
   }
   if (arrive_last(I.counters + 0 * kCounterStride, I.nwide, t.local)) {
-    const double s = sum_partials(I.part, I.nwide, sh);
-    const double s2 = sum_partials(I.part + I.nwide, I.nwide, sh);
+    double ss[2];
+    sum_partials_n<2>(I.part, I.nwide, I.nwide, ss, sh);
+    const double s = ss[0], s2 = ss[1];
     if (threadIdx.x == 0) {
       PcgScalars* P = I.pcg;
       const double n = (double)nx * ny;
@@ -215,10 +233,21 @@ __global__ void __launch_bounds__(kNT) k_pcg_init(const Tile* __restrict__ tiles
   const int nx = I.nx, ny = I.ny;
   const double bmean = I.pcg->bmean;
   if (guess) {
-    for (int k = threadIdx.x; k < RY * RX; k += kNT) {
+    // the guess over the tile and its halo: all reads of the thread first
+    constexpr int NG = (RY * RX + kNT - 1) / kNT;
+    double gv[NG];
+#pragma unroll
+    for (int e = 0; e < NG; ++e) {
+      const int k = threadIdx.x + e * kNT;
       const int rj = k / RX, ri = k - rj * RX;
-      const int j = t.j0 - 1 + rj, i = wrap_any(t.i0 - 1 + ri, nx);
-      s_x[k] = (j >= 0 && j < ny) ? guess_value(I, guess, stage, (size_t)j * nx + i) : 0.0;
+      const int j = t.j0 - 1 + rj;
+      gv[e] = (k < RY * RX && j >= 0 && j < ny)
+                  ? guess_value(I, guess, stage, (size_t)j * nx + wrap_any(t.i0 - 1 + ri, nx)) : 0.0;
+    }
+#pragma unroll
+    for (int e = 0; e < NG; ++e) {
+      const int k = threadIdx.x + e * kNT;
+      if (k < RY * RX) s_x[k] = gv[e];
     }
     __syncthreads();
   }
@@ -240,12 +269,13 @@ __global__ void __launch_bounds__(kNT) k_pcg_init(const Tile* __restrict__ tiles
       }
     }
   }
+  double xo[WR], ro[WR];
 #pragma unroll
   for (int r = 0; r < WR; ++r) {
     const int tx = wide_tx(), ty = wide_ty(r);
     const int i = t.i0 + tx, j = t.j0 + ty;
+    xo[r] = ro[r] = 0.0;
     if (i < nx && j < ny) {
-      const size_t o = (size_t)j * nx + i;
       const double f = -(bv[r] - bmean);
       double rv = f, xc = 0.0;
       if (guess) {
@@ -256,10 +286,19 @@ __global__ void __launch_bounds__(kNT) k_pcg_init(const Tile* __restrict__ tiles
         if (j + 1 < ny) kx += an[r] * (xc - s_x[c + RX]);
         rv = f - kx;
       }
-      I.x[o] = xc;
-      I.rr[o] = rv;
+      xo[r] = xc;
+      ro[r] = rv;
       s[0] += f * f;
       s[1] += rv * rv;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < WR; ++r) {
+    const int i = t.i0 + wide_tx(), j = t.j0 + wide_ty(r);
+    if (i < nx && j < ny) {
+      const size_t o = (size_t)j * nx + i;
+      I.x[o] = xo[r];
+      I.rr[o] = ro[r];
     }
   }
   block_sum<2>(s, sh);
@@ -268,8 +307,9 @@ __global__ void __launch_bounds__(kNT) k_pcg_init(const Tile* __restrict__ tiles
     st_agent(&I.part[I.nwide + t.local], s[1]);
   }
   if (arrive_last(I.counters + 1 * kCounterStride, I.nwide, t.local)) {
-    const double ff = sum_partials(I.part, I.nwide, sh);
-    const double rr = sum_partials(I.part + I.nwide, I.nwide, sh);
+    double ss[2];
+    sum_partials_n<2>(I.part, I.nwide, I.nwide, ss, sh);
+    const double ff = ss[0], rr = ss[1];
     if (threadIdx.x == 0) {
       PcgScalars* P = I.pcg;
       P->fnorm = sqrt(ff);
@@ -305,19 +345,23 @@ __global__ void __launch_bounds__(kNT) k_pcg_spmv(const Tile* __restrict__ tiles
   const double* __restrict__ rv = rsel ? I.rr2 : I.rr;
   const bool first = I.pcg->first != 0;
   const double beta = first ? 0.0 : I.pcg->beta;
-  for (int k = threadIdx.x; k < RY * RX; k += kNT) {
+  // every global read of the thread first: d over the tile and its halo,
+  // then the coefficients and r of its own rows
+  constexpr int ND = (RY * RX + kNT - 1) / kNT;
+  double zl[ND], dl[ND];
+#pragma unroll
+  for (int e = 0; e < ND; ++e) {
+    const int k = threadIdx.x + e * kNT;
     const int rj = k / RX, ri = k - rj * RX;
-    const int j = t.j0 - 1 + rj, i = wrap_any(t.i0 - 1 + ri, nx);
-    double dv = 0.0;
-    if (j >= 0 && j < ny) {
-      const size_t o = (size_t)j * nx + i;
-      dv = first ? z[o] : z[o] + beta * dold[o];
+    const int j = t.j0 - 1 + rj;
+    zl[e] = dl[e] = 0.0;
+    if (k < RY * RX && j >= 0 && j < ny) {
+      const size_t o = (size_t)j * nx + wrap_any(t.i0 - 1 + ri, nx);
+      zl[e] = z[o];
+      if (!first) dl[e] = dold[o];
     }
-    s_d[k] = dv;
   }
-  __syncthreads();
   double s[2] = {0.0, 0.0};
-  // every global read of the thread's rows first, then arithmetic and stores
   double aw[WR], ae[WR], as[WR], an[WR], rr[WR];
 #pragma unroll
   for (int r = 0; r < WR; ++r) {
@@ -333,20 +377,36 @@ __global__ void __launch_bounds__(kNT) k_pcg_spmv(const Tile* __restrict__ tiles
     }
   }
 #pragma unroll
+  for (int e = 0; e < ND; ++e) {
+    const int k = threadIdx.x + e * kNT;
+    if (k < RY * RX) s_d[k] = first ? zl[e] : zl[e] + beta * dl[e];
+  }
+  __syncthreads();
+  double dco[WR], qo[WR];
+#pragma unroll
   for (int r = 0; r < WR; ++r) {
     const int tx = wide_tx(), ty = wide_ty(r);
     const int i = t.i0 + tx, j = t.j0 + ty;
+    dco[r] = qo[r] = 0.0;
     if (i < nx && j < ny) {
-      const size_t o = (size_t)j * nx + i;
       const int c = (ty + 1) * RX + tx + 1;
       const double dc = s_d[c];
       double q = aw[r] * (dc - s_d[c - 1]) + ae[r] * (dc - s_d[c + 1]);
       if (j >= 1) q += as[r] * (dc - s_d[c - RX]);
       if (j + 1 < ny) q += an[r] * (dc - s_d[c + RX]);
-      dnew[o] = dc;
-      I.q[o] = q;
+      dco[r] = dc;
+      qo[r] = q;
       s[0] += dc * rr[r];
       s[1] += dc * q;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < WR; ++r) {
+    const int i = t.i0 + wide_tx(), j = t.j0 + wide_ty(r);
+    if (i < nx && j < ny) {
+      const size_t o = (size_t)j * nx + i;
+      dnew[o] = dco[r];
+      I.q[o] = qo[r];
     }
   }
   block_sum<2>(s, sh);
@@ -355,8 +415,9 @@ __global__ void __launch_bounds__(kNT) k_pcg_spmv(const Tile* __restrict__ tiles
     st_agent(&I.part[I.nwide + t.local], s[1]);
   }
   if (arrive_last(I.counters + 2 * kCounterStride, I.nwide, t.local)) {
-    const double dr = sum_partials(I.part, I.nwide, sh);
-    const double dq = sum_partials(I.part + I.nwide, I.nwide, sh);
+    double ss[2];
+    sum_partials_n<2>(I.part, I.nwide, I.nwide, ss, sh);
+    const double dr = ss[0], dq = ss[1];
     if (threadIdx.x == 0) {
       PcgScalars* P = I.pcg;
       P->dr = dr; P->dq = dq;
@@ -393,7 +454,7 @@ __global__ void __launch_bounds__(kNT) k_guess_fit(const Tile* __restrict__ tile
     for (int k = 0; k < 5; ++k) st_agent(&I.part[k * I.nwide + t.local], s[k]);
   if (arrive_last(I.counters + 7 * kCounterStride, I.nwide, t.local)) {
     double m[5];
-    for (int k = 0; k < 5; ++k) m[k] = sum_partials(I.part + k * I.nwide, I.nwide, sh);
+    sum_partials_n<5>(I.part, I.nwide, I.nwide, m, sh);
     if (threadIdx.x == 0) {
       double a = 0.0, c = 0.0;
       const double det = m[0] * m[2] - m[1] * m[1];
@@ -556,69 +617,89 @@ __global__ void __launch_bounds__(kNT) k_mg_down(const Tile* __restrict__ tiles,
   // level-0 residual: read the previous buffer when updating, write the current one
   const double* __restrict__ rin = (upd ? (rsel ? I.rr : I.rr2) : (rsel ? I.rr2 : I.rr));
   double* __restrict__ rout = rsel ? I.rr2 : I.rr;
-  // loads (rows outside the grid hold zeros and are never used as cells)
-  for (int k = threadIdx.x; k < RY * (RX + 1); k += kNT) {
+  // Every global read of the thread (coefficients, right-hand side and, with
+  // the CG update, q, x, d) is issued before the first LDS store, so a block
+  // waits for one memory latency, not one per loop trip.  Rows outside the
+  // grid hold zeros and are never used as cells.
+  constexpr int NAX = (RY * (RX + 1) + kNT - 1) / kNT;
+  constexpr int NAY = ((RY + 1) * RX + kNT - 1) / kNT;
+  constexpr int NPT = (RY * RX + kNT - 1) / kNT;
+  S axl[NAX], ayl[NAY];
+#pragma unroll
+  for (int e = 0; e < NAX; ++e) {
+    const int k = threadIdx.x + e * kNT;
     const int rj = k / (RX + 1), ri = k - rj * (RX + 1);
-    const int j = j0 - H + rj, i = wrap_any(i0 - H + ri, nx);
-    s_ax[k] = (j >= 0 && j < ny) ? ldS<S>(L.ax, (size_t)j * nx + i) : S(0);
+    const int j = j0 - H + rj;
+    axl[e] = (k < RY * (RX + 1) && j >= 0 && j < ny)
+                 ? ldS<S>(L.ax, (size_t)j * nx + wrap_any(i0 - H + ri, nx)) : S(0);
   }
-  for (int k = threadIdx.x; k < (RY + 1) * RX; k += kNT) {
+#pragma unroll
+  for (int e = 0; e < NAY; ++e) {
+    const int k = threadIdx.x + e * kNT;
     const int rj = k / RX, ri = k - rj * RX;
-    const int j = j0 - H + rj, i = wrap_any(i0 - H + ri, nx);
-    s_ay[k] = (j >= 0 && j <= ny) ? ldS<S>(L.ay, (size_t)j * nx + i) : S(0);
+    const int j = j0 - H + rj;
+    ayl[e] = (k < (RY + 1) * RX && j >= 0 && j <= ny)
+                 ? ldS<S>(L.ay, (size_t)j * nx + wrap_any(i0 - H + ri, nx)) : S(0);
+  }
+  const double* __restrict__ dvec = parity ? I.d1 : I.d0;
+  const double* __restrict__ qv = I.q;
+  double* __restrict__ xv = I.x;
+  double rl[NPT], ql[NPT], xl[NPT], dl[NPT];
+  size_t ol[NPT];
+  bool inl[NPT], own[NPT];
+#pragma unroll
+  for (int e = 0; e < NPT; ++e) {
+    const int k = threadIdx.x + e * kNT;
+    const int rj = k / RX, ri = k - rj * RX;
+    const int j = j0 - H + rj, iu = i0 - H + ri;
+    inl[e] = k < RY * RX && j >= 0 && j < ny;
+    own[e] = upd && inl[e] && rj >= H && rj < H + FY && ri >= H && ri < H + FX && iu < nx;
+    ol[e] = inl[e] ? (size_t)j * nx + wrap_any(iu, nx) : 0;
+    if (level == 0) rl[e] = inl[e] ? rin[ol[e]] : 0.0;
+    else rl[e] = inl[e] ? (double)ldS<S>(L.r, ol[e]) : 0.0;
+    ql[e] = (upd && inl[e]) ? qv[ol[e]] : 0.0;
+    xl[e] = own[e] ? xv[ol[e]] : 0.0;
+    dl[e] = own[e] ? dvec[ol[e]] : 0.0;
+  }
+#pragma unroll
+  for (int e = 0; e < NAX; ++e) {
+    const int k = threadIdx.x + e * kNT;
+    if (k < RY * (RX + 1)) s_ax[k] = axl[e];
+  }
+#pragma unroll
+  for (int e = 0; e < NAY; ++e) {
+    const int k = threadIdx.x + e * kNT;
+    if (k < (RY + 1) * RX) s_ay[k] = ayl[e];
   }
   // residual over the region; with the CG update (level 0) the new residual
   // r - alpha q is formed once per cell from a single read of r and q, and
   // on the tile itself x += alpha d, r is stored, ||r||^2 and sum(x) summed
   double red[2] = {0.0, 0.0};
-  if (!upd) {
-    for (int k = threadIdx.x; k < RY * RX; k += kNT) {
-      const int rj = k / RX, ri = k - rj * RX;
-      const int j = j0 - H + rj, i = wrap_any(i0 - H + ri, nx);
-      S r = 0;
-      if (j >= 0 && j < ny) {
-        const size_t o = (size_t)j * nx + i;
-        r = level == 0 ? (S)rin[o] : ldS<S>(L.r, o);
-      }
-      s_r[k] = r;
-    }
-  } else {
-    // all loads of the thread's region cells first, then the stores
-    constexpr int NPT = (RY * RX + kNT - 1) / kNT;
-    const double* __restrict__ dvec = parity ? I.d1 : I.d0;
-    const double* __restrict__ qv = I.q;
-    double* __restrict__ xv = I.x;
-    double rl[NPT], ql[NPT], xl[NPT], dl[NPT];
-    size_t ol[NPT];
-    bool inl[NPT], own[NPT];
 #pragma unroll
-    for (int e = 0; e < NPT; ++e) {
-      const int k = threadIdx.x + e * kNT;
-      const int rj = k / RX, ri = k - rj * RX;
-      const int j = j0 - H + rj, iu = i0 - H + ri;
-      inl[e] = k < RY * RX && j >= 0 && j < ny;
-      own[e] = inl[e] && rj >= H && rj < H + FY && ri >= H && ri < H + FX && iu < nx;
-      ol[e] = inl[e] ? (size_t)j * nx + wrap_any(iu, nx) : 0;
-      rl[e] = inl[e] ? rin[ol[e]] : 0.0;
-      ql[e] = inl[e] ? qv[ol[e]] : 0.0;
-      xl[e] = own[e] ? xv[ol[e]] : 0.0;
-      dl[e] = own[e] ? dvec[ol[e]] : 0.0;
+  for (int e = 0; e < NPT; ++e) {
+    const int k = threadIdx.x + e * kNT;
+    if (k >= RY * RX) continue;
+    if (!upd) {
+      s_r[k] = (S)rl[e];
+      continue;
     }
-#pragma unroll
-    for (int e = 0; e < NPT; ++e) {
-      const int k = threadIdx.x + e * kNT;
-      const double rv = rl[e] - alpha * ql[e];
-      if (k < RY * RX) s_r[k] = inl[e] ? (S)rv : S(0);
-      if (own[e]) {
-        const double x = xl[e] + alpha * dl[e];
-        xv[ol[e]] = x;
-        rout[ol[e]] = rv;
-        red[0] += rv * rv;
-        red[1] += x;
-      }
+    const double rv = rl[e] - alpha * ql[e];
+    s_r[k] = inl[e] ? (S)rv : S(0);
+    if (own[e]) {
+      const double x = xl[e] + alpha * dl[e];
+      xl[e] = x;
+      rl[e] = rv;
+      red[0] += rv * rv;
+      red[1] += x;
     }
   }
   if (upd) {
+#pragma unroll
+    for (int e = 0; e < NPT; ++e)
+      if (own[e]) {
+        xv[ol[e]] = xl[e];
+        rout[ol[e]] = rl[e];
+      }
     block_sum<2>(red, sh);
     if (threadIdx.x == 0) {
       st_agent(&I.part[t.local], red[0]);
@@ -636,22 +717,24 @@ __global__ void __launch_bounds__(kNT) k_mg_down(const Tile* __restrict__ tiles,
   // colour.
   static_assert(RX % 2 == 0, "colour-compact sweeps need an even region width");
   constexpr int HX = RX / 2;
-  // red cells: z = r / D over the whole region; black cells start at 0
-  for (int k = threadIdx.x; k < RY * RX; k += kNT) s_z[k] = S(0);
-  __syncthreads();
+  // red cells: z = r / D over the whole region (0 on rows outside the grid).
+  // Black cells need no start value: the first black half-sweep reads only
+  // red neighbours, and every later read stays inside the part of the region
+  // that an earlier half-sweep has written.
   for (int h = threadIdx.x; h < RY * HX; h += kNT) {
     const int rj = h / HX, ri = 2 * (h - rj * HX) + (rj & 1);
-    if (valid(rj)) s_z[rj * RX + ri] = s_r[rj * RX + ri] / diag(rj, ri);
+    s_z[rj * RX + ri] = valid(rj) ? s_r[rj * RX + ri] / diag(rj, ri) : S(0);
   }
   __syncthreads();
   // then Gauss-Seidel half-sweeps black, red, black, ... (half-sweep sw on
-  // the region shrunk by sw cells)
+  // the region shrunk by sw cells; 0 on rows outside the grid)
 #pragma unroll
   for (int sw = 1; sw < 2 * NU; ++sw) {
     const int color = sw & 1;   // 1 black, 0 red
     for (int h = threadIdx.x; h < (RY - 2 * sw) * HX; h += kNT) {
       const int rj = sw + h / HX, ri = 2 * (h % HX) + ((rj + color) & 1);
-      if (ri < sw || ri >= RX - sw || !valid(rj)) continue;
+      if (ri < sw || ri >= RX - sw) continue;
+      if (!valid(rj)) { s_z[rj * RX + ri] = S(0); continue; }
       const int k = rj * RX + ri;
       const S aw = s_ax[rj * (RX + 1) + ri], ae = s_ax[rj * (RX + 1) + ri + 1];
       const S as = s_ay[rj * RX + ri], an = s_ay[(rj + 1) * RX + ri];
@@ -704,8 +787,9 @@ __global__ void __launch_bounds__(kNT) k_mg_down(const Tile* __restrict__ tiles,
     ((S*)C.r)[(size_t)J * C.nx + Ic] = S(0.25) * acc;
   }
   if (upd && arrive_last(I.counters + 3 * kCounterStride, L.ntiles, t.local)) {
-    const double rr = sum_partials(I.part, L.ntiles, sh);
-    const double sx = sum_partials(I.part + L.ntiles, L.ntiles, sh);
+    double ss[2];
+    sum_partials_n<2>(I.part, L.ntiles, L.ntiles, ss, sh);
+    const double rr = ss[0], sx = ss[1];
     if (threadIdx.x == 0) pcg_stop_test(I.pcg, rr, sx, (double)nx * ny);
   }
 }
@@ -730,8 +814,12 @@ __global__ void __launch_bounds__(kNT) k_mg_up(const Tile* __restrict__ tiles,
                                                 int rsel) {
   constexpr int H = 2 * NU;
   constexpr int RY = FY + 2 * H, RX = FX + 2 * H;       // 20 x 36 for NU = 1
+  // coarse correction around the region: rows and columns (j0-H)/2-1 ..
+  // (j0-H)/2+RY/2 (i0, j0 and H are even), columns wrapped on load
+  constexpr int EY = RY / 2 + 2, EX = RX / 2 + 2;
   __shared__ S s_r[RY * RX], s_z[RY * RX];
   __shared__ S s_ax[RY * (RX + 1)], s_ay[(RY + 1) * RX];
+  __shared__ S s_e[EY * EX];
   __shared__ double sh[kNT / 64];
   const Tile t = tiles[blockIdx.x];
   const Inst& I = insts[t.inst];
@@ -740,27 +828,92 @@ __global__ void __launch_bounds__(kNT) k_mg_up(const Tile* __restrict__ tiles,
   const Level& C = I.lev[level + 1];
   const int nx = L.nx, ny = L.ny;
   const int i0 = t.i0, j0 = t.j0;
-  for (int k = threadIdx.x; k < RY * (RX + 1); k += kNT) {
+  const int Jb = ((j0 - H) >> 1) - 1, Ib = ((i0 - H) >> 1) - 1;
+  // every global read of the thread is issued before the first LDS store
+  constexpr int NAX = (RY * (RX + 1) + kNT - 1) / kNT;
+  constexpr int NAY = ((RY + 1) * RX + kNT - 1) / kNT;
+  constexpr int NPT = (RY * RX + kNT - 1) / kNT;
+  constexpr int NE = (EY * EX + kNT - 1) / kNT;
+  constexpr int NQ = FX * FY / kNT;
+  S axl[NAX], ayl[NAY], el[NE], zl[NPT];
+  double rl[NPT], qt[NQ];
+#pragma unroll
+  for (int e = 0; e < NAX; ++e) {
+    const int k = threadIdx.x + e * kNT;
     const int rj = k / (RX + 1), ri = k - rj * (RX + 1);
-    const int j = j0 - H + rj, i = wrap_any(i0 - H + ri, nx);
-    s_ax[k] = (j >= 0 && j < ny) ? ldS<S>(L.ax, (size_t)j * nx + i) : S(0);
+    const int j = j0 - H + rj;
+    axl[e] = (k < RY * (RX + 1) && j >= 0 && j < ny)
+                 ? ldS<S>(L.ax, (size_t)j * nx + wrap_any(i0 - H + ri, nx)) : S(0);
   }
-  for (int k = threadIdx.x; k < (RY + 1) * RX; k += kNT) {
+#pragma unroll
+  for (int e = 0; e < NAY; ++e) {
+    const int k = threadIdx.x + e * kNT;
     const int rj = k / RX, ri = k - rj * RX;
-    const int j = j0 - H + rj, i = wrap_any(i0 - H + ri, nx);
-    s_ay[k] = (j >= 0 && j <= ny) ? ldS<S>(L.ay, (size_t)j * nx + i) : S(0);
+    const int j = j0 - H + rj;
+    ayl[e] = (k < (RY + 1) * RX && j >= 0 && j <= ny)
+                 ? ldS<S>(L.ay, (size_t)j * nx + wrap_any(i0 - H + ri, nx)) : S(0);
   }
-  const S* e = (const S*)C.z;
-  for (int k = threadIdx.x; k < RY * RX; k += kNT) {
+  const S* __restrict__ ec = (const S*)C.z;
+#pragma unroll
+  for (int e = 0; e < NE; ++e) {
+    const int k = threadIdx.x + e * kNT;
+    const int cj = k / EX, ci = k - cj * EX;
+    const int J = Jb + cj;
+    el[e] = (k < EY * EX && J >= 0 && J < C.ny)
+                ? ec[(size_t)J * C.nx + wrap_any(Ib + ci, C.nx)] : S(0);
+  }
+  const double* __restrict__ rin = rsel ? I.rr2 : I.rr;
+#pragma unroll
+  for (int e = 0; e < NPT; ++e) {
+    const int k = threadIdx.x + e * kNT;
     const int rj = k / RX, ri = k - rj * RX;
-    const int j = j0 - H + rj, i = wrap_any(i0 - H + ri, nx);
-    S r = 0, z = 0;
+    const int j = j0 - H + rj;
+    const bool in = k < RY * RX && j >= 0 && j < ny;
+    const size_t o = in ? (size_t)j * nx + wrap_any(i0 - H + ri, nx) : 0;
+    rl[e] = !in ? 0.0 : level == 0 ? rin[o] : (double)ldS<S>(L.r, o);
+    zl[e] = in ? ldS<S>(L.z, o) : S(0);
+  }
+#pragma unroll
+  for (int e = 0; e < NQ; ++e) {   // level 0: q on the tile, for z.q
+    const int k = threadIdx.x + e * kNT;
+    const int ty = k / FX, tx = k - ty * FX;
+    const int j = j0 + ty, i = i0 + tx;
+    qt[e] = (level == 0 && j < ny && i < nx) ? I.q[(size_t)j * nx + i] : 0.0;
+  }
+#pragma unroll
+  for (int e = 0; e < NAX; ++e) {
+    const int k = threadIdx.x + e * kNT;
+    if (k < RY * (RX + 1)) s_ax[k] = axl[e];
+  }
+#pragma unroll
+  for (int e = 0; e < NAY; ++e) {
+    const int k = threadIdx.x + e * kNT;
+    if (k < (RY + 1) * RX) s_ay[k] = ayl[e];
+  }
+#pragma unroll
+  for (int e = 0; e < NE; ++e) {
+    const int k = threadIdx.x + e * kNT;
+    if (k < EY * EX) s_e[k] = el[e];
+  }
+  __syncthreads();
+  // z += P e (bilinear prolongation from the staged coarse correction)
+#pragma unroll
+  for (int e = 0; e < NPT; ++e) {
+    const int k = threadIdx.x + e * kNT;
+    if (k >= RY * RX) continue;
+    const int rj = k / RX, ri = k - rj * RX;
+    const int j = j0 - H + rj, iu = i0 - H + ri;
+    S z = 0;
     if (j >= 0 && j < ny) {
-      const size_t o = (size_t)j * nx + i;
-      r = level == 0 ? (S)(rsel ? I.rr2 : I.rr)[o] : ldS<S>(L.r, o);
-      z = ldS<S>(L.z, o) + prolong<S>(e, C.nx, C.ny, j, i);
+      const int J = j >> 1, Icu = iu >> 1;   // unwrapped coarse column (floor)
+      const int cI = Icu - Ib, cI2 = cI + ((iu & 1) ? 1 : -1);
+      int J2 = (j & 1) ? J + 1 : J - 1;
+      if (J2 < 0 || J2 >= C.ny) J2 = J;
+      const S a = s_e[(J - Jb) * EX + cI], b = s_e[(J - Jb) * EX + cI2];
+      const S c = s_e[(J2 - Jb) * EX + cI], d = s_e[(J2 - Jb) * EX + cI2];
+      z = zl[e] + (S(0.5625) * a + S(0.1875) * b + S(0.1875) * c + S(0.0625) * d);
     }
-    s_r[k] = r;
+    s_r[k] = (S)rl[e];
     s_z[k] = z;
   }
   __syncthreads();
@@ -788,22 +941,29 @@ __global__ void __launch_bounds__(kNT) k_mg_up(const Tile* __restrict__ tiles,
     }
     __syncthreads();
   }
+  if (level != 0) {   // uniform per launch
+#pragma unroll
+    for (int e = 0; e < NQ; ++e) {
+      const int k = threadIdx.x + e * kNT;
+      const int ty = k / FX, tx = k - ty * FX;
+      const int j = j0 + ty, i = i0 + tx;
+      if (j < ny && i < nx) ((S*)L.z)[(size_t)j * nx + i] = s_z[(ty + H) * RX + (tx + H)];
+    }
+    return;
+  }
+  // level 0: the FP64 preconditioned residual and its partial z.q
   double zq[1] = {0.0};
-  for (int k = threadIdx.x; k < FX * FY; k += kNT) {
+#pragma unroll
+  for (int e = 0; e < NQ; ++e) {
+    const int k = threadIdx.x + e * kNT;
     const int ty = k / FX, tx = k - ty * FX;
     const int j = j0 + ty, i = i0 + tx;
     if (j < ny && i < nx) {
-      const size_t o = (size_t)j * nx + i;
       const S z = s_z[(ty + H) * RX + (tx + H)];
-      if (level == 0) {
-        I.zf[o] = (double)z;
-        zq[0] += (double)z * I.q[o];
-      } else {
-        ((S*)L.z)[o] = z;
-      }
+      I.zf[(size_t)j * nx + i] = (double)z;
+      zq[0] += (double)z * qt[e];
     }
   }
-  if (level != 0) return;   // uniform per launch: every thread of the block returns here
   block_sum<1>(zq, sh);
   if (threadIdx.x == 0) st_agent(&I.part[t.local], zq[0]);
   if (arrive_last(I.counters + 4 * kCounterStride, L.ntiles, t.local)) {
@@ -1038,16 +1198,51 @@ __device__ __forceinline__ MgView<S> coarse_view(const Inst& I, CoarseLds<S>& C,
   return v;
 }
 
-// Load the coefficients of levels lc..nl-1 into LDS.
+// Load the coefficients of levels lc..nl-1 into LDS, where they are stored
+// level after level (the layout of coarse_view), and, with rdst, the rn
+// values of a right-hand side (S values from rs, or FP64 from rd).  Every
+// global read of a thread is issued before its first LDS store: the block
+// waits for one memory latency instead of one per level and array.
 template <typename S>
-__device__ __forceinline__ void coarse_load_coef(const Inst& I, CoarseLds<S>& C) {
-  for (int l = I.lc; l < I.nlev; ++l) {
-    const Level& L = I.lev[l];
-    const int n = L.nx * L.ny, nf = (L.ny + 1) * L.nx;
-    const MgView<S> v = coarse_view<S>(I, C, l);
-    for (int c = threadIdx.x; c < n; c += kCoarseNT) ((S*)v.ax)[c] = ((const S*)L.ax)[c];
-    for (int c = threadIdx.x; c < nf; c += kCoarseNT) ((S*)v.ay)[c] = ((const S*)L.ay)[c];
+__device__ __forceinline__ void coarse_load_coef(const Inst& I, CoarseLds<S>& C,
+                                                 S* rdst = nullptr, const S* rs = nullptr,
+                                                 const double* rd = nullptr, int rn = 0) {
+  constexpr int NX = (kCLX + kCoarseNT - 1) / kCoarseNT;
+  constexpr int NY = (kCLY + kCoarseNT - 1) / kCoarseNT;
+  // flat index f of the concatenated x (y) arrays -> level and offset
+  auto locate = [&](int f, bool yf, const S*& src) {
+    for (int l = I.lc; l < I.nlev; ++l) {
+      const Level& L = I.lev[l];
+      const int n = yf ? (L.ny + 1) * L.nx : L.nx * L.ny;
+      if (f < n) { src = (const S*)(yf ? L.ay : L.ax) + f; return true; }
+      f -= n;
+    }
+    return false;
+  };
+  S gx[NX], gy[NY];
+  bool hx[NX], hy[NY];
+#pragma unroll
+  for (int e = 0; e < NX; ++e) {
+    const S* src = nullptr;
+    hx[e] = locate(threadIdx.x + e * kCoarseNT, false, src);
+    gx[e] = hx[e] ? *src : S(0);
   }
+#pragma unroll
+  for (int e = 0; e < NY; ++e) {
+    const S* src = nullptr;
+    hy[e] = locate(threadIdx.x + e * kCoarseNT, true, src);
+    gy[e] = hy[e] ? *src : S(0);
+  }
+  S gr = S(0);
+  const bool hr = rdst != nullptr && (int)threadIdx.x < rn;
+  if (hr) gr = rd != nullptr ? (S)rd[threadIdx.x] : rs[threadIdx.x];
+#pragma unroll
+  for (int e = 0; e < NX; ++e)
+    if (hx[e]) C.ax[threadIdx.x + e * kCoarseNT] = gx[e];
+#pragma unroll
+  for (int e = 0; e < NY; ++e)
+    if (hy[e]) C.ay[threadIdx.x + e * kCoarseNT] = gy[e];
+  if (hr) rdst[threadIdx.x] = gr;
 }
 
 // Level view of a one-block V-cycle: levels from lc in LDS, finer levels in
@@ -1106,20 +1301,21 @@ __global__ void __launch_bounds__(kCoarseNT) k_mg_coarse(const Inst* __restrict_
     __syncthreads();
     if (C.sc[0] != 0.0) return;
   }
-  coarse_load_coef<S>(I, C);
   S* r0 = I.mixed ? (S*)I.mg_r0 : (S*)(void*)rcur;
   auto view = [&](int l) { return mixed_view<S>(I, C, r0, l); };
   {
-    // right-hand side of level lg: into LDS when lg is an LDS level, into the
-    // S copy of the level-0 residual on the mixed path
+    // right-hand side of level lg: into LDS with the coefficients when lg is
+    // an LDS level (at most kCoarseCells = kCoarseNT cells), into the S copy
+    // of the level-0 residual on the mixed path
     const Level& L = I.lev[lg];
     const int n = L.nx * L.ny;
     if (lg >= lc) {
-      S* r = coarse_view<S>(I, C, lg).r;
-      for (int c = tid; c < n; c += kCoarseNT)
-        r[c] = lg == 0 ? (S)rcur[c] : ((const S*)L.r)[c];
-    } else if (lg == 0 && I.mixed) {
-      for (int c = tid; c < n; c += kCoarseNT) r0[c] = (S)rcur[c];
+      coarse_load_coef<S>(I, C, coarse_view<S>(I, C, lg).r, (const S*)L.r,
+                          lg == 0 ? rcur : nullptr, n);
+    } else {
+      coarse_load_coef<S>(I, C);
+      if (lg == 0 && I.mixed)
+        for (int c = tid; c < n; c += kCoarseNT) r0[c] = (S)rcur[c];
     }
   }
   __syncthreads();
