@@ -504,8 +504,11 @@ cdi_status solve_loop(cdi_ctx* c, int guess, int stage) {
   });
   // z0 = M r0 (residual in buffer 0)
   launch_vcycle<S>(c, 0, 0, 0);
+  // the host first checks after the predicted count (the last solve's):
+  // with a steady count that is the one wait per solve; an over-estimate
+  // costs only early-exit launches
   int it = 0;
-  int next_check = std::max(1, c->pred_iters - 1);
+  int next_check = std::max(1, c->pred_iters);
   bool all_done = false;
   while (it < c->maxit) {
     const int par = it & 1;
@@ -651,23 +654,18 @@ void enqueue_solve_fixed(cdi_ctx* c, int guess, int stage, int budget) {
 
 // Copy every instance's step state (fields and per-stage pressure history)
 // to (save) or from its snapshot area.
+// (k_snapshot: phi, u, p, ph[0..3], ph2[0..3] and v one after another.)
 cdi_status snapshot(cdi_ctx* c, bool save) {
+  size_t most = 0;
   for (int k = 0; k < c->B.n; ++k) {
     const Inst& I = c->B.inst[k];
-    const size_t n = (size_t)I.nx * I.ny;
-    double* bufs[11] = {I.phi, I.u, I.p, I.ph[0], I.ph[1], I.ph[2], I.ph[3],
-                        I.ph2[0], I.ph2[1], I.ph2[2], I.ph2[3]};
-    size_t pos = 0;
-    for (double* b : bufs) {
-      HIPCHK(hipMemcpyAsync(save ? I.snap + pos : b, save ? b : I.snap + pos, n * sizeof(double),
-                            hipMemcpyDeviceToDevice, c->stream));
-      pos += n;
-    }
-    if (pos + n + I.nx > snap_doubles(I.nx, I.ny))
-      return fail(CDI_ERR_STATE, "snapshot layout exceeds its area");
-    HIPCHK(hipMemcpyAsync(save ? I.snap + pos : I.v, save ? I.v : I.snap + pos,
-                          (n + I.nx) * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    const size_t need = 12 * (size_t)I.nx * I.ny + I.nx;
+    if (need > snap_doubles(I.nx, I.ny)) return fail(CDI_ERR_STATE, "snapshot layout exceeds its area");
+    most = std::max(most, need);
   }
+  const dim3 grid((unsigned)std::min<size_t>(1024, (most + kNT - 1) / kNT), (unsigned)c->B.n);
+  k_snapshot<<<grid, kNT, 0, c->stream>>>(c->d_inst, save ? 1 : 0);
+  HIPCHK(hipGetLastError());
   return CDI_OK;
 }
 

@@ -588,6 +588,40 @@ __global__ void __launch_bounds__(kNT) k_project(const Tile* __restrict__ tiles,
 template <typename S>
 __device__ __forceinline__ S ldS(const void* p, size_t o) { return ((const S*)p)[o]; }
 
+// One red-black Gauss-Seidel half-sweep on an LDS region of RY x RX cells
+// (coefficients s_ax with RX + 1 per row, s_ay with RX per row and RY + 1
+// rows): the cells of colour `color` ((rj + ri) & 1) in rows and columns
+// [m, RY - m) x [m, RX - m), 0 on rows outside the grid.  A cell of one colour
+// reads only cells of the other, so each thread issues the LDS reads of all
+// its cells before the first of its writes.
+template <typename S, int RY, int RX, typename ValidF>
+__device__ __forceinline__ void lds_half_sweep(S* s_z, const S* s_r, const S* s_ax, const S* s_ay,
+                                               int m, int color, const ValidF& valid) {
+  constexpr int HX = RX / 2;
+  constexpr int NC = (RY * HX + kNT - 1) / kNT;
+  S val[NC];
+  int kk[NC];
+  bool act[NC];
+#pragma unroll
+  for (int e = 0; e < NC; ++e) {
+    const int h = threadIdx.x + e * kNT;
+    const int rj = m + h / HX, ri = 2 * (h % HX) + ((rj + color) & 1);
+    act[e] = h < (RY - 2 * m) * HX && ri >= m && ri < RX - m;
+    kk[e] = rj * RX + ri;
+    val[e] = S(0);
+    if (act[e] && valid(rj)) {
+      const int k = kk[e];
+      const S aw = s_ax[rj * (RX + 1) + ri], ae = s_ax[rj * (RX + 1) + ri + 1];
+      const S as = s_ay[rj * RX + ri], an = s_ay[(rj + 1) * RX + ri];
+      const S nb = aw * s_z[k - 1] + ae * s_z[k + 1] + as * s_z[k - RX] + an * s_z[k + RX];
+      val[e] = (s_r[k] + nb) / (aw + ae + as + an);
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < NC; ++e)
+    if (act[e]) s_z[kk[e]] = val[e];
+}
+
 // Pre-smoothing from z = 0 (red z = r/D, black Gauss-Seidel), residual
 // r - K z and restriction R = P^T/4 to the next level, on one fine tile.
 // Level 0 reads the FP64 CG residual; with `update` it first applies the CG
@@ -721,26 +755,18 @@ __global__ void __launch_bounds__(kNT) k_mg_down(const Tile* __restrict__ tiles,
   // Black cells need no start value: the first black half-sweep reads only
   // red neighbours, and every later read stays inside the part of the region
   // that an earlier half-sweep has written.
-  for (int h = threadIdx.x; h < RY * HX; h += kNT) {
+#pragma unroll
+  for (int e = 0; e < (RY * HX + kNT - 1) / kNT; ++e) {
+    const int h = threadIdx.x + e * kNT;
     const int rj = h / HX, ri = 2 * (h - rj * HX) + (rj & 1);
-    s_z[rj * RX + ri] = valid(rj) ? s_r[rj * RX + ri] / diag(rj, ri) : S(0);
+    if (h < RY * HX) s_z[rj * RX + ri] = valid(rj) ? s_r[rj * RX + ri] / diag(rj, ri) : S(0);
   }
   __syncthreads();
   // then Gauss-Seidel half-sweeps black, red, black, ... (half-sweep sw on
   // the region shrunk by sw cells; 0 on rows outside the grid)
 #pragma unroll
   for (int sw = 1; sw < 2 * NU; ++sw) {
-    const int color = sw & 1;   // 1 black, 0 red
-    for (int h = threadIdx.x; h < (RY - 2 * sw) * HX; h += kNT) {
-      const int rj = sw + h / HX, ri = 2 * (h % HX) + ((rj + color) & 1);
-      if (ri < sw || ri >= RX - sw) continue;
-      if (!valid(rj)) { s_z[rj * RX + ri] = S(0); continue; }
-      const int k = rj * RX + ri;
-      const S aw = s_ax[rj * (RX + 1) + ri], ae = s_ax[rj * (RX + 1) + ri + 1];
-      const S as = s_ay[rj * RX + ri], an = s_ay[(rj + 1) * RX + ri];
-      const S nb = aw * s_z[k - 1] + ae * s_z[k + 1] + as * s_z[k - RX] + an * s_z[k + RX];
-      s_z[k] = (s_r[k] + nb) / (aw + ae + as + an);
-    }
+    lds_half_sweep<S, RY, RX>(s_z, s_r, s_ax, s_ay, sw, sw & 1 /* 1 black, 0 red */, valid);
     __syncthreads();
   }
   // store the smoothed z on the tile
@@ -750,7 +776,10 @@ __global__ void __launch_bounds__(kNT) k_mg_down(const Tile* __restrict__ tiles,
     if (j < ny && i < nx) ((S*)L.z)[(size_t)j * nx + i] = s_z[(ty + H) * RX + (tx + H)];
   }
   // residual r - K z on the tile + halo 1
-  for (int k = threadIdx.x; k < PY * PX; k += kNT) {
+#pragma unroll
+  for (int e = 0; e < (PY * PX + kNT - 1) / kNT; ++e) {
+    const int k = threadIdx.x + e * kNT;
+    if (k >= PY * PX) break;
     const int pj = k / PX, pi = k - pj * PX;
     const int rj = pj + H - 1, ri = pi + H - 1;
     const int c = rj * RX + ri;
@@ -918,27 +947,14 @@ __global__ void __launch_bounds__(kNT) k_mg_up(const Tile* __restrict__ tiles,
   }
   __syncthreads();
   auto valid = [&](int rj) { const int j = j0 - H + rj; return j >= 0 && j < ny; };
-  auto gs = [&](int k, int rj, int ri) {
-    const S aw = s_ax[rj * (RX + 1) + ri], ae = s_ax[rj * (RX + 1) + ri + 1];
-    const S as = s_ay[rj * RX + ri], an = s_ay[(rj + 1) * RX + ri];
-    const S nb = aw * s_z[k - 1] + ae * s_z[k + 1] + as * s_z[k - RX] + an * s_z[k + RX];
-    return (s_r[k] + nb) / (aw + ae + as + an);
-  };
   // half-sweeps black, red, ... (the reverse of the pre-smoothing), the
-  // last one (red) on the tile itself
-  // colour of region cell (rj, ri) is (rj + ri) & 1 (i0, j0, H even): the
-  // sweeps visit only cells of their colour
+  // last one (red) on the tile itself; the colour of region cell (rj, ri) is
+  // (rj + ri) & 1 (i0, j0, H even) and the sweeps visit only cells of their
+  // colour (rows outside the grid hold 0 and keep it)
   static_assert(RX % 2 == 0, "colour-compact sweeps need an even region width");
-  constexpr int HX = RX / 2;
 #pragma unroll
   for (int sw = 0; sw < 2 * NU; ++sw) {
-    const int color = (sw & 1) ? 0 : 1;   // black first
-    const int m = sw + 1;
-    for (int h = threadIdx.x; h < (RY - 2 * m) * HX; h += kNT) {
-      const int rj = m + h / HX, ri = 2 * (h % HX) + ((rj + color) & 1);
-      if (ri < m || ri >= RX - m || !valid(rj)) continue;
-      s_z[rj * RX + ri] = gs(rj * RX + ri, rj, ri);
-    }
+    lds_half_sweep<S, RY, RX>(s_z, s_r, s_ax, s_ay, sw + 1, (sw & 1) ? 0 : 1 /* black first */, valid);
     __syncthreads();
   }
   if (level != 0) {   // uniform per launch
@@ -998,9 +1014,26 @@ struct MgView {
 // return V(lo).z holds the correction; V(lo).r is not modified.  V(l)
 // returns the view of level l (a functor, so that views into LDS keep their
 // address space after inlining).
+// Row part of the dense coarsest inverse a thread multiplies: entries
+// (tid / 16, tid % 16 + 16 u), u < 4, loaded ahead of the cycle by the caller.
+struct DensePart {
+  double m[kDenseMax / 16];
+};
+
+__device__ __forceinline__ void dense_part_load(const Inst& I, DensePart& dp) {
+  const int n = I.lev[I.nlev - 1].nx * I.lev[I.nlev - 1].ny;
+  const int row = threadIdx.x >> 4, part = threadIdx.x & 15;
+#pragma unroll
+  for (int u = 0; u < kDenseMax / 16; ++u) {
+    const int k = part + 16 * u;
+    dp.m[u] = (I.cdense && row < n && k < n) ? I.cinv[(size_t)row * n + k] : 0.0;
+  }
+}
+
 template <typename S, typename ViewF>
 __device__ __forceinline__ void mg_cycle(const Inst& I, const ViewF& V, int lo, int nl,
-                                         double* s_red, double* s_sc) {
+                                         double* s_red, double* s_sc,
+                                         const DensePart* dp = nullptr) {
   const int tid = threadIdx.x;
   // cells of one colour only: h-th cell of colour `color` is row j = h / (nx/2),
   // column i = 2 (h mod nx/2) + ((j + color) & 1)  (swept levels have even nx)
@@ -1092,8 +1125,14 @@ __device__ __forceinline__ void mg_cycle(const Inst& I, const ViewF& V, int lo, 
       const int row = tid >> 4, part = tid & 15;
       double acc = 0.0;
       if (row < n) {
-        const double* M = I.cinv + (size_t)row * n;
-        for (int k = part; k < n; k += 16) acc += M[k] * (double)r[k];
+        if (dp) {   // the row part was loaded ahead (same order of terms)
+#pragma unroll
+          for (int u = 0; u < kDenseMax / 16; ++u)
+            if (part + 16 * u < n) acc += dp->m[u] * (double)r[part + 16 * u];
+        } else {
+          const double* M = I.cinv + (size_t)row * n;
+          for (int k = part; k < n; k += 16) acc += M[k] * (double)r[k];
+        }
       }
 #pragma unroll
       for (int off = 8; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 16);
@@ -1301,6 +1340,11 @@ __global__ void __launch_bounds__(kCoarseNT) k_mg_coarse(const Inst* __restrict_
     __syncthreads();
     if (C.sc[0] != 0.0) return;
   }
+  // the dense coarsest inverse's row parts are loaded with the coefficients,
+  // long before the cycle reaches the coarsest level
+  static_assert(kDenseMax * 16 <= kCoarseNT, "16 threads per dense row");
+  DensePart dp;
+  dense_part_load(I, dp);
   S* r0 = I.mixed ? (S*)I.mg_r0 : (S*)(void*)rcur;
   auto view = [&](int l) { return mixed_view<S>(I, C, r0, l); };
   {
@@ -1320,9 +1364,9 @@ __global__ void __launch_bounds__(kCoarseNT) k_mg_coarse(const Inst* __restrict_
   }
   __syncthreads();
   if (lg >= lc)   // LDS levels only: views the compiler knows to be LDS (ds_ instructions)
-    mg_cycle<S>(I, [&](int l) { return coarse_view<S>(I, C, l); }, lg, nl, C.red, C.sc);
+    mg_cycle<S>(I, [&](int l) { return coarse_view<S>(I, C, l); }, lg, nl, C.red, C.sc, &dp);
   else
-    mg_cycle<S>(I, view, lg, nl, C.red, C.sc);
+    mg_cycle<S>(I, view, lg, nl, C.red, C.sc, &dp);
   // ---- publish the level-lg correction (and beta when it is level 0)
   {
     const Level& L = I.lev[lg];
