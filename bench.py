@@ -253,6 +253,12 @@ def main():
                     help="kernel family for the roofline entry (auto: largest device time)")
     ap.add_argument("--launch", default="auto", choices=["auto", "tiled", "persistent"],
                     help="auto: the library's autotuner picks the launch form and tile shape")
+    ap.add_argument("--tile-rows", type=int, default=0,
+                    help="with --launch tiled: rows per thread of the wide-tile kernels (1 or 4)")
+    ap.add_argument("--coarse-cells", type=int, default=0,
+                    help="with --launch tiled: level size from which one block runs the V-cycle")
+    ap.add_argument("--mg-smooth", type=int, default=0,
+                    help="with --launch tiled: red-black sweep pairs per smoothing (1 or 2)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-hbm-case", action="store_true",
                     help="skip the per-kernel HBM fractions on the 2048x1024 grid")
@@ -279,7 +285,15 @@ def main():
     if args.launch == "auto":
         tuned = s.tune(trial_steps=10)
     else:
+        # a fixed launch form and shape, e.g. the autotuner's pick, for
+        # profiler runs (which would otherwise tune under the profiler)
         s.set_launch(args.launch)
+        if args.tile_rows:
+            s.set_tile_rows(args.tile_rows)
+        if args.coarse_cells:
+            s.set_coarse_cells(args.coarse_cells)
+        if args.mg_smooth:
+            s.set_mg_smooth(args.mg_smooth)
 
     # dominant kernel: device time per family over a short probe run
     fam = args.kernel

@@ -306,7 +306,9 @@ cdi_status cdi_get_mg_smooth(cdi_ctx* ctx, int32_t* nu);
 /* Autotuner: times `trial_steps` steps (after warm-up steps) of every launch
  * candidate -- tiled with 1 and 2 sweep pairs, 1 and 4 rows per thread, the
  * coarse kernel starting at 1024, 4096 and 16384 cells; persistent (with the
- * fastest tiled sweep count); graph (with the fastest tiled shape) -- each
+ * fastest tiled sweep count; skipped when an instance has more than 16384
+ * cells, where one block per instance cannot compete); graph (with the
+ * fastest tiled shape) -- each
  * from the same saved state, restores that state (fields, pressure history,
  * time and step counters), and keeps the fastest candidate for later
  * cdi_step calls.  The pressure still meets poisson_rtol in every candidate.

@@ -535,11 +535,17 @@ cdi_status solve_loop(cdi_ctx* c, int guess, int stage) {
       HIPCHK(hipMemcpyAsync(c->h_pcg + k, B.inst[k].pcg, sizeof(PcgScalars), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
   }
-  timed(c, "pcg_xmean", [&] {
-    with_rows(c->wide_rows, [&](auto R) {
-      CDI_LAUNCH(c, k_pcg_xmean<decltype(R)::value>, nwide, kNT, c->d_wide, c->d_inst);
+  // the solution mean needs its own pass only for a solve that ended before
+  // any CG update (the update kernels sum x as they go); the host copies of
+  // the CG scalars say whether any instance did
+  bool need_xmean = false;
+  for (int k = 0; k < B.n; ++k) need_xmean = need_xmean || c->h_pcg[k].iters == 0;
+  if (need_xmean)
+    timed(c, "pcg_xmean", [&] {
+      with_rows(c->wide_rows, [&](auto R) {
+        CDI_LAUNCH(c, k_pcg_xmean<decltype(R)::value>, nwide, kNT, c->d_wide, c->d_inst);
+      });
     });
-  });
   int maxi = 0;
   bool noconv = false;
   for (int k = 0; k < B.n; ++k) {
@@ -1255,6 +1261,8 @@ static cdi_status tune_copy(cdi_ctx* c, char* scratch, bool save) {
   return CDI_OK;
 }
 
+constexpr long kPersistTuneCells = 16384;
+
 cdi_status cdi_tune(cdi_ctx* c, int32_t trial_steps, void* scratch, size_t scratch_bytes,
                     cdi_tune_info* out) {
   if (!c || !scratch) return fail(CDI_ERR_ARG, "NULL argument");
@@ -1291,9 +1299,15 @@ cdi_status cdi_tune(cdi_ctx* c, int32_t trial_steps, void* scratch, size_t scrat
   Cand pick{c->launch, c->wide_rows, c->coarse_cells, c->nu, -1};
   cdi_tune_info info{};
   for (int q = 0; q < 14; ++q) info.ms_per_step[q] = -1.0;
+  // one block per instance: timed only where an instance fits a CU's reach
+  // (beyond 16384 cells a step takes several times the tiled one, up to
+  // seconds on the largest grids)
+  long max_cells = 0;
+  for (int k = 0; k < c->B.n; ++k) max_cells = std::max(max_cells, (long)c->B.R[k].p.nx * c->B.R[k].p.ny);
   for (Cand& cd : cands) {
     const bool learned = c->guess == CDI_GUESS_LEARNED && c->net;
     if (cd.launch != CDI_LAUNCH_TILED && learned) continue;
+    if (cd.launch == CDI_LAUNCH_PERSISTENT && max_cells > kPersistTuneCells) continue;
     if (cd.launch != CDI_LAUNCH_TILED) {   // the fastest tiled shape
       cd.rows = c->wide_rows_pick;
       cd.coarse = c->coarse_cells_pick;
