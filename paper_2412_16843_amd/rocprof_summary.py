@@ -2,8 +2,10 @@
 
 Two uses:
 
-  kernel statistics (``--kernel-trace --stats`` run):
+  kernel statistics (``--kernel-trace --stats`` run), per kernel and per
+  (kernel, grid size):
       python -m paper_2412_16843_amd.rocprof_summary stats <run>_kernel_stats.csv
+      python -m paper_2412_16843_amd.rocprof_summary grid <run>_kernel_trace.csv
 
   HBM traffic per launch (two ``--pmc`` runs of the same command, one with
   FETCH_SIZE, one with WRITE_SIZE; each must also run a plain device copy of
@@ -30,12 +32,13 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 
 
 def source_hash() -> str:
-    """sha256 over the library's device code: every kernel lives in the
-    csrc/*.h headers (the .hip files hold host code only)."""
+    """sha256 over the solver's device code: every solver kernel lives in the
+    csrc/*.h headers (the .hip files hold host code only); the network's
+    headers (net_*.h) are left out, their kernels are not in these records."""
     h = hashlib.sha256()
     csrc = os.path.join(HERE, "csrc")
     for name in sorted(os.listdir(csrc)):
-        if name.endswith(".h"):
+        if name.endswith(".h") and not name.startswith("net_"):
             with open(os.path.join(csrc, name), "rb") as f:
                 h.update(name.encode())
                 h.update(f.read())
@@ -56,6 +59,23 @@ def stats(path: str, top: int = 20) -> str:
             _short(r["Name"]), r["Calls"], float(r["TotalDurationNs"]) / 1e6,
             float(r["AverageNs"]) / 1e3, float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3,
             float(r["Percentage"])))
+    return "\n".join(out)
+
+
+def by_grid(trace_csv: str, top: int = 24) -> str:
+    """Per (kernel, grid size) launch durations from a --kernel-trace CSV: the
+    multigrid kernels run once per level, so the level-0 launches (largest
+    grid) are the ones a kernel family of bench.py times."""
+    agg = collections.defaultdict(list)
+    for r in csv.DictReader(open(trace_csv)):
+        grid = r.get("Grid_Size") or r.get("Grid_Size_X")
+        agg[(_short(r["Kernel_Name"]), int(grid))].append(
+            (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    out = ["| kernel | grid | calls | total (ms) | average (us) | min (us) | max (us) |",
+           "|---|---:|---:|---:|---:|---:|---:|"]
+    for (name, grid), d in sorted(agg.items(), key=lambda kv: -sum(kv[1]))[:top]:
+        out.append("| `{}` | {} | {} | {:.2f} | {:.2f} | {:.2f} | {:.2f} |".format(
+            name, grid, len(d), sum(d) / 1e3, sum(d) / len(d), min(d), max(d)))
     return "\n".join(out)
 
 
@@ -126,6 +146,9 @@ def main(argv=None):
     s = sub.add_parser("stats")
     s.add_argument("csv")
     s.add_argument("--top", type=int, default=20)
+    gsub = sub.add_parser("grid")
+    gsub.add_argument("trace_csv")
+    gsub.add_argument("--top", type=int, default=24)
     t = sub.add_parser("traffic")
     t.add_argument("fetch_csv")
     t.add_argument("write_csv")
@@ -135,6 +158,8 @@ def main(argv=None):
     a = ap.parse_args(argv)
     if a.cmd == "stats":
         print(stats(a.csv, a.top))
+    elif a.cmd == "grid":
+        print(by_grid(a.trace_csv, a.top))
     else:
         print(traffic(a.fetch_csv, a.write_csv, a.kernel, a.copy_bytes, a.workload))
 
