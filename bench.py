@@ -237,7 +237,8 @@ def poisson_learned_vs_plain(nx: int = 2048, train_iters: int = 300, verbose: bo
         "ms_learned": round(mean("learned", 1), 3),
         "ms_inference": round(net_ms / max(net_n, 1), 3),
         "train": {"snapshots": 24, "iters": train_iters, "batch": 8, "crop": 256,
-                  "loss_first": losses[0], "loss_last": losses[-1],
+                  "loss_first10pct": round(train_guess.loss_summary(losses)[0], 4),
+                  "loss_last10pct": round(train_guess.loss_summary(losses)[1], 4),
                   "train_s": round(t_train, 2), "collect_s": round(t_collect, 2)},
     }
 

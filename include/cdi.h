@@ -335,7 +335,10 @@ cdi_status cdi_set_guess(cdi_ctx* ctx, int32_t guess);
 
 /* Features and normalised target of instance idx's last projection (after
  * cdi_step: the final-stage projection of the last step): features FP32
- * [3][ny][nx], target FP32 [ny][nx] (may be NULL), both device buffers. */
+ * [3][ny][nx] = (phi, rho / max(rho1, rho2), asinh((b - mean b) / rms b)),
+ * target FP32 [ny][nx] (may be NULL) = the pressure scaled to unit rms (the
+ * learned guess enters the solve through a scale-invariant fit), both device
+ * buffers. */
 cdi_status cdi_guess_features(cdi_ctx* ctx, int32_t idx, float* features, float* target);
 
 /* Release the context (host memory only; caller buffers are untouched). */

@@ -1409,6 +1409,7 @@ cdi_status cdi_guess_features(cdi_ctx* c, int32_t idx, float* features, float* t
   const Inst& I = c->B.inst[idx];
   const unsigned g = (unsigned)std::min(1024, ceil_div(I.nx * I.ny, kNT));
   k_features<<<g, kNT, 0, c->stream>>>(c->d_inst, idx, I.phi, I.p, features, target);
+  if (target) k_target_unit_rms<<<1, kNT, 0, c->stream>>>(target, (size_t)I.nx * I.ny);
   HIPCHK(hipGetLastError());
   return CDI_OK;
 }

@@ -194,7 +194,7 @@ void wgrad(cdi_net* n, int l, const __bf16* x, const __bf16* dy) {
   const int per_b = chunks / n->B;
   const int rows = (Hl + per_b - 1) / per_b;
   dim3 grid((unsigned)((L.co + TCO - 1) / TCO), (unsigned)(L.ci / KC), (unsigned)chunks);
-  k_conv3_wgrad<<<grid, NT, 0, n->stream>>>(x, dy, n->wpart, n->B, L.ci, L.co, Hl, Wl, rows);
+  k_conv3_wgrad<<<grid, NT, 0, n->stream>>>(x, dy, n->wpart, n->B, L.ci, L.co, Hl, Wl, rows, per_b);
   const size_t cnt = (size_t)L.co * L.ci_used * 9;
   k_wgrad_reduce<<<grid1d(cnt), 256, 0, n->stream>>>(n->wpart, chunks, L.co, L.ci, L.ci_used,
                                                     n->grads + n->woff[l]);

@@ -240,9 +240,28 @@ __global__ void __launch_bounds__(kNT) k_features(const Inst* __restrict__ insts
     const double ph = phi[c];
     feat[c] = (float)ph;
     feat[n + c] = (float)(((I.rho1 - I.rho2) * ph + I.rho2) / rmax);
-    feat[2 * n + c] = rms > 0.0 ? (float)((I.b[c] - mean) / rms) : 0.f;
+    // the right-hand side peaks at hundreds of its rms near the interface:
+    // asinh keeps its sign and small values and compresses the peaks
+    feat[2 * n + c] = rms > 0.0 ? (float)asinh((I.b[c] - mean) / rms) : 0.f;
     if (target) target[c] = pscale > 0.0 ? (float)(p[c] / pscale) : 0.f;
   }
+}
+
+// Training target scaled to unit rms (one block; FP64 sum of squares in a
+// fixed order).  The guess enters the solve only through the energy-norm fit
+// of k_guess_fit, which is invariant to its scale, so the network is trained
+// on the shape of the pressure: snapshots whose pressure levels differ by
+// orders of magnitude then weigh alike in the loss.
+__global__ void __launch_bounds__(kNT) k_target_unit_rms(float* __restrict__ target, size_t n) {
+  __shared__ double sh[kNT / 64];
+  __shared__ double s_scale;
+  double s[1] = {0.0};
+  for (size_t c = threadIdx.x; c < n; c += kNT) s[0] += (double)target[c] * target[c];
+  block_sum<1>(s, sh);
+  if (threadIdx.x == 0) s_scale = s[0] > 0.0 ? 1.0 / sqrt(s[0] / (double)n) : 0.0;
+  __syncthreads();
+  const double f = s_scale;
+  for (size_t c = threadIdx.x; c < n; c += kNT) target[c] = (float)(target[c] * f);
 }
 
 // Pressure guess from the network output: g = y rms rho_max h^2, held in zf

@@ -194,12 +194,14 @@ __global__ void __launch_bounds__(NT) k_conv3_fwd(const __bf16* __restrict__ x,
 __global__ void __launch_bounds__(NT) k_conv3_wgrad(const __bf16* __restrict__ x,
                                                     const __bf16* __restrict__ dy,
                                                     float* __restrict__ part, int B, int ci,
-                                                    int co, int H, int W, int rows) {
+                                                    int co, int H, int W, int rows,
+                                                    int chunks_per_b) {
   __shared__ __attribute__((aligned(16))) __bf16 s_dy[TCO * TPX];             // [o][px]
   __shared__ __attribute__((aligned(16))) __bf16 s_x[KC * 3 * (TPX + 2 + 6)]; // [c][row][px]
   constexpr int XP = TPX + 8;   // padded row pitch (16-byte aligned reads at any shift)
   const int co0 = blockIdx.x * TCO, c0 = blockIdx.y * KC;
-  const int chunks_per_b = (H + rows - 1) / rows;
+  // blockIdx.z = b * chunks_per_b + chunk; chunk k covers rows k*rows .. ; the
+  // chunks past the last row (chunks_per_b * rows may exceed H) add nothing
   const int b = blockIdx.z / chunks_per_b;
   const int r0 = (blockIdx.z % chunks_per_b) * rows;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;

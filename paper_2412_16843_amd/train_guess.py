@@ -36,13 +36,16 @@ def collect(cases: Sequence, steps: int, every: int = 1, precision: str = "fp64"
 
 def train(net: GuessNet, data, iters: int, lr: float = 1e-3, seed: int = 0,
           log_every: int = 0) -> List[float]:
-    """Adam on random mini-batches (and random crops of net.h x net.w)."""
+    """Adam on random mini-batches (and random crops of net.h x net.w).
+    Returns the loss of every iteration (each of a different random batch:
+    compare means over many iterations, see loss_summary)."""
     rng = np.random.default_rng(seed)
     B, h, w = net.batch, net.h, net.w
     losses = []
     x = torch.empty((B, 3, h, w), dtype=torch.float32, device=net.device)
     t = torch.empty((B, h, w), dtype=torch.float32, device=net.device)
     t0 = time.time()
+    dev_losses = []
     for it in range(iters):
         for b in range(B):
             f, tt = data[int(rng.integers(len(data)))]
@@ -54,9 +57,14 @@ def train(net: GuessNet, data, iters: int, lr: float = 1e-3, seed: int = 0,
         net.forward(x)
         loss = net.backward(t)
         net.adam(lr)
+        dev_losses.append(loss.detach().clone().reshape(()))
         if log_every and (it % log_every == 0 or it == iters - 1):
-            losses.append(float(loss.item()))
-            print(f"iter {it} loss {losses[-1]:.4e} ({time.time() - t0:.1f} s)", flush=True)
-        elif not log_every:
-            losses.append(float(loss.item()) if it % 10 == 0 or it == iters - 1 else losses[-1] if losses else float(loss.item()))
+            print(f"iter {it} loss {float(loss.item()):.4e} ({time.time() - t0:.1f} s)", flush=True)
+    losses = [float(v) for v in torch.stack(dev_losses).cpu()] if dev_losses else []
     return losses
+
+
+def loss_summary(losses: Sequence[float], frac: float = 0.1):
+    """Mean loss over the first and the last `frac` of the iterations."""
+    k = max(1, int(len(losses) * frac))
+    return float(np.mean(losses[:k])), float(np.mean(losses[-k:]))

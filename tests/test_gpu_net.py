@@ -34,8 +34,11 @@ def _rand_params(seed):
     return p
 
 
-@pytest.mark.parametrize("B,H,Wd", [(2, 16, 16), (1, 32, 96)])
+@pytest.mark.parametrize("B,H,Wd", [(2, 16, 16), (1, 32, 96), (1, 40, 48)])
 def test_network_forward_and_gradients_match_fp64_oracle(B, H, Wd):
+    """(1, 40, 48): 32 weight-gradient row chunks of 2 rows cover the 40 rows
+    of level 0 (the last chunks hold no rows), a split the kernel once
+    recomputed inconsistently from the row count."""
     torch = _torch()
     from paper_2412_16843_amd import learned
     rng = np.random.default_rng(7)
@@ -91,7 +94,9 @@ def test_training_reduces_loss_and_guess_beats_zero():
     print("target rms: min %.3e max %.3e" % (min(trms), max(trms)))
     net = learned.GuessNet(8, 64, 128)
     losses = train_guess.train(net, data, iters=300, lr=2e-3, log_every=50)
-    assert losses[-1] < 0.5 * losses[0], losses
+    first, last = train_guess.loss_summary(losses)   # means over 30 iterations each
+    print("loss: first 10 %% %.4f, last 10 %% %.4f" % (first, last))
+    assert last < 0.5 * first, (first, last)
     # held-out case: compare the pressure solve from zero and from the network
     case = W.drop_case(128, 64, 60.0, 10.0, steps=10)
     plain = CDISolver(case.params, case.phi0, guess="zero", rtol=1e-10)
