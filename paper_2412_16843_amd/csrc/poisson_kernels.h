@@ -1030,6 +1030,52 @@ __device__ __forceinline__ void dense_part_load(const Inst& I, DensePart& dp) {
   }
 }
 
+// One cell of a level with at most kCoarseNT cells, owned by thread c for a
+// whole pre- or post-smoothing: its coefficients, diagonal and right-hand
+// side are read from the level's arrays once and kept in registers, so a
+// half-sweep reads only the four neighbouring corrections.  The arithmetic is
+// that of the sweep, residual and operator of mg_cycle, term for term.
+template <typename S>
+struct OwnedCell {
+  S aw, ae, as, an, D, r;
+  int c, w, e;
+  bool own, hs, hn;
+  int color;   // (i + j) & 1
+};
+
+template <typename S>
+__device__ __forceinline__ OwnedCell<S> owned_cell(const MgView<S>& L, int c) {
+  OwnedCell<S> o;
+  const int nx = L.nx, ny = L.ny;
+  o.own = c < nx * ny;
+  const int j = o.own ? FastDiv(nx).div(c) : 0, i = c - j * nx;
+  o.c = o.own ? c : 0;
+  o.w = j * nx + wrap(i - 1, nx);
+  o.e = j * nx + wrap(i + 1, nx);
+  o.hs = j >= 1;
+  o.hn = j + 1 < ny;
+  o.color = (i + j) & 1;
+  o.aw = o.own ? L.ax[o.c] : S(0);
+  o.ae = o.own ? L.ax[o.e] : S(0);
+  o.as = o.own ? L.ay[o.c] : S(0);
+  o.an = o.own ? L.ay[o.c + nx] : S(0);
+  o.D = o.aw + o.ae + o.as + o.an;
+  o.r = o.own ? L.r[o.c] : S(0);
+  return o;
+}
+
+// Gauss-Seidel update of an owned cell (colour `color` only).
+template <typename S>
+__device__ __forceinline__ void owned_gs(const OwnedCell<S>& o, S* z, int nx, int color,
+                                         bool from_zero) {
+  if (!o.own || o.color != color) return;
+  if (from_zero) { z[o.c] = o.r / o.D; return; }
+  S nb = o.aw * z[o.w] + o.ae * z[o.e];
+  if (o.hs) nb += o.as * z[o.c - nx];
+  if (o.hn) nb += o.an * z[o.c + nx];
+  z[o.c] = (o.r + nb) / o.D;
+}
+
 template <typename S, typename ViewF>
 __device__ __forceinline__ void mg_cycle(const Inst& I, const ViewF& V, int lo, int nl,
                                          double* s_red, double* s_sc,
@@ -1062,6 +1108,27 @@ __device__ __forceinline__ void mg_cycle(const Inst& I, const ViewF& V, int lo, 
   for (int l = lo; l < nl - 1; ++l) {
     const MgView<S> Lv = V(l), Cv = V(l + 1);
     const int nx = Lv.nx, ny = Lv.ny;
+    if (nx * ny <= kCoarseNT) {   // one cell per thread: coefficients in registers
+      const OwnedCell<S> oc = owned_cell<S>(Lv, tid);
+      owned_gs<S>(oc, Lv.z, nx, 0, true);
+      __syncthreads();
+      owned_gs<S>(oc, Lv.z, nx, 1, false);
+      __syncthreads();
+      for (int k = 1; k < I.nu; ++k) {
+        owned_gs<S>(oc, Lv.z, nx, 0, false);
+        __syncthreads();
+        owned_gs<S>(oc, Lv.z, nx, 1, false);
+        __syncthreads();
+      }
+      if (oc.own) {
+        const S* z = Lv.z;
+        const S zc = z[oc.c];
+        S kz = oc.aw * (zc - z[oc.w]) + oc.ae * (zc - z[oc.e]);
+        if (oc.hs) kz += oc.as * (zc - z[oc.c - nx]);
+        if (oc.hn) kz += oc.an * (zc - z[oc.c + nx]);
+        Lv.t[oc.c] = oc.r - kz;
+      }
+    } else {
     sweep(l, 0, true);
     __syncthreads();
     sweep(l, 1, false);
@@ -1088,6 +1155,7 @@ __device__ __forceinline__ void mg_cycle(const Inst& I, const ViewF& V, int lo, 
         if (j + 1 < ny) kz += ay[c + nx] * (zc - z[c + nx]);
         t[c] = r[c] - kz;
       }
+    }
     }
     __syncthreads();
     {
@@ -1204,11 +1272,21 @@ __device__ __forceinline__ void mg_cycle(const Inst& I, const ViewF& V, int lo, 
       z[c] += prolong<S>(e, cnx, cny, j, i);
     }
     __syncthreads();
-    for (int k = 0; k < I.nu; ++k) {
-      sweep(l, 1, false);
-      __syncthreads();
-      sweep(l, 0, false);
-      __syncthreads();
+    if (nx * ny <= kCoarseNT) {   // one cell per thread: coefficients in registers
+      const OwnedCell<S> oc = owned_cell<S>(Lv, tid);
+      for (int k = 0; k < I.nu; ++k) {
+        owned_gs<S>(oc, z, nx, 1, false);
+        __syncthreads();
+        owned_gs<S>(oc, z, nx, 0, false);
+        __syncthreads();
+      }
+    } else {
+      for (int k = 0; k < I.nu; ++k) {
+        sweep(l, 1, false);
+        __syncthreads();
+        sweep(l, 0, false);
+        __syncthreads();
+      }
     }
   }
 }
