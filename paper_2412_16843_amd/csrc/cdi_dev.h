@@ -170,6 +170,34 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* sh /* >= NV*N
   __syncthreads();   // sh may be reused right after
 }
 
+// Fixed-order block sum of NV values per thread, result in every thread
+// (each thread adds the per-wave sums in the same order).  One barrier; the
+// caller places a barrier between the last read of `sh` and its next use.
+template <int NV, int NT = kNT>
+__device__ __forceinline__ void block_allsum(double (&v)[NV], double* sh /* >= NV*NT/64 */) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = wave_sum(v[k]);
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) sh[k * (NT / 64) + w] = v[k];
+  }
+  __syncthreads();
+  // lane ww < NW of every wave reads wave ww's sum; an xor butterfly over
+  // those NW lanes leaves the same total in each of them (every pairwise
+  // addition is commutative, so all lanes hold identical bits), and lane 0's
+  // copy goes to the whole wave
+  constexpr int NW = NT / 64;
+  static_assert((NW & (NW - 1)) == 0, "a power-of-two number of waves");
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double t = lane < NW ? sh[k * NW + lane] : 0.0;
+#pragma unroll
+    for (int off = NW / 2; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+    v[k] = __shfl(t, 0, 64);
+  }
+}
+
 // Coherent load / store of a value exchanged between blocks of one launch.
 // Both bypass the per-XCD L2 (device-coherent access), so publishing a
 // partial needs no L2 write-back or invalidation (an agent-scope fence would

@@ -78,7 +78,7 @@ __device__ int persist_solve(const Inst& I, PersistLds<S>& L, int guess,
       for (int c = tid; c < n; c += PNT) rl[c] = (S)r[c];
       __syncthreads();
     }
-    mg_cycle<S>(I, view, 0, I.nlev, L.red, L.sc);
+    mg_cycle<S>(I, view, 0, I.nlev, L.red, L.sc, L.u.coarse.cg);
     const S* z = view(0).z;
     // flexible CG: the new direction is K-orthogonalised against the last one
     double beta = 0.0;

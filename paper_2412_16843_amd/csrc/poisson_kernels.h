@@ -30,6 +30,7 @@ constexpr int kCoarseCells = 1024;   // levels at or below this size run in one 
 constexpr int kCoarseNT = 1024;
 static_assert(kCoarseCells <= kCoarseNT, "a coarse right-hand side is loaded one value per thread");
 constexpr int kDenseMax = 64;        // coarsest grids up to this size use a dense inverse
+constexpr double kCoarseCgRtol = 1e-8;   // relative residual of the coarsest CG otherwise
 constexpr int kCLX = 1376;           // LDS cells of all coarse levels (<= 1024 * 4/3)
 constexpr int kCLY = 2432;           // LDS y-faces of all coarse levels
 constexpr int FX = 32, FY = 16;            // fine tile of the multigrid kernels
@@ -1078,7 +1079,7 @@ __device__ __forceinline__ void owned_gs(const OwnedCell<S>& o, S* z, int nx, in
 
 template <typename S, typename ViewF>
 __device__ __forceinline__ void mg_cycle(const Inst& I, const ViewF& V, int lo, int nl,
-                                         double* s_red, double* s_sc,
+                                         double* s_red, double* s_sc, double* s_vec,
                                          const DensePart* dp = nullptr) {
   const int tid = threadIdx.x;
   // cells of one colour only: h-th cell of colour `color` is row j = h / (nx/2),
@@ -1207,53 +1208,72 @@ __device__ __forceinline__ void mg_cycle(const Inst& I, const ViewF& V, int lo, 
       if (row < n && part == 0) z[row] = (S)acc;
       __syncthreads();
     } else {
-      // CG with one cell per thread (n <= kCoarseNT) and an FP64 recurrence;
-      // the direction is shared through the level's scratch
-      const S* ax = L.ax;
-      const S* ay = L.ay;
+      // Coarsest grids beyond the dense inverse (dimensions that stop halving,
+      // e.g. 30 x 15): CG with one cell per thread (n <= kCoarseNT) in FP64,
+      // in the single-reduction form of Chronopoulos and Gear (both inner
+      // products of an iteration in one block reduction: two barriers per
+      // iteration).  The residual is shared through an FP64 LDS vector, so
+      // the recurrence stays consistent on the mixed path.  As the coarsest
+      // solve inside the preconditioner it stops at a relative residual of
+      // kCoarseCgRtol; the flexible outer CG tolerates the inexact solve and
+      // still meets its own tolerance.
       double m[1] = {0.0};
       for (int c = tid; c < n; c += kCoarseNT) m[0] += (double)r[c];
-      block_sum<1, kCoarseNT>(m, s_red);
-      if (tid == 0) s_sc[0] = m[0] / n;
-      __syncthreads();
-      const double mean = s_sc[0];
+      block_allsum<1, kCoarseNT>(m, s_red);
+      const double mean = m[0] / n;
       const int c = tid;
       const bool own = c < n;
       const int j = own ? c / nx : 0, i = own ? c - j * nx : 0;
-      double xr = 0.0, rr = own ? (double)r[c] - mean : 0.0, pr = rr;
-      S* pbuf = L.t;
-      double rho[1] = {rr * rr};
-      block_sum<1, kCoarseNT>(rho, s_red);
-      if (tid == 0) s_sc[1] = rho[0];
-      __syncthreads();
-      double rh = s_sc[1];
-      const double rh0 = rh;
-      for (int it = 0; it < 2 * n && rh > 1e-24 * rh0 && rh > 0.0; ++it) {
-        if (own) pbuf[c] = (S)pr;
+      const int cw = j * nx + wrap(i - 1, nx), ce = j * nx + wrap(i + 1, nx);
+      const double aw = own ? (double)L.ax[c] : 0.0, ae = own ? (double)L.ax[ce] : 0.0;
+      const double as = (own && j >= 1) ? (double)L.ay[c] : 0.0;
+      const double an = (own && j + 1 < ny) ? (double)L.ay[c + nx] : 0.0;
+      double xr = 0.0, rr = own ? (double)r[c] - mean : 0.0, pr = 0.0, sr = 0.0;
+      double gam_old = 0.0, alpha = 0.0, gam0 = 0.0;
+      // only the waves that own cells work; the others pass the barriers
+      // and read the same sums, so every thread takes the same branches
+      constexpr int NW = kCoarseNT / 64;
+      const int nwa = (n + 63) >> 6;
+      const bool act = (tid >> 6) < nwa;
+      for (int it = 0; it <= 2 * n; ++it) {
+        // the previous iteration's reads of s_vec (operator) and s_red
+        // (sums) happened before its second barrier and before the barrier
+        // below respectively
+        if (own) s_vec[c] = rr;
         __syncthreads();
-        double q = 0.0;
-        if (own) {
-          const int ie = wrap(i + 1, nx), iw = wrap(i - 1, nx);
-          q = (double)ax[c] * (pr - (double)pbuf[j * nx + iw]) +
-              (double)ax[j * nx + ie] * (pr - (double)pbuf[j * nx + ie]);
-          if (j >= 1) q += (double)ay[c] * (pr - (double)pbuf[c - nx]);
-          if (j + 1 < ny) q += (double)ay[c + nx] * (pr - (double)pbuf[c + nx]);
+        double wv = 0.0;
+        if (act) {
+          if (own) {
+            wv = aw * (rr - s_vec[cw]) + ae * (rr - s_vec[ce]);
+            if (j >= 1) wv += as * (rr - s_vec[c - nx]);
+            if (j + 1 < ny) wv += an * (rr - s_vec[c + nx]);
+          }
+          const double g0 = wave_sum(rr * rr), g1 = wave_sum(wv * rr);   // (r, r), (A r, r)
+          if ((tid & 63) == 0) {
+            s_red[tid >> 6] = g0;
+            s_red[NW + (tid >> 6)] = g1;
+          }
         }
-        double pq[1] = {pr * q};
-        block_sum<1, kCoarseNT>(pq, s_red);
-        if (tid == 0) s_sc[2] = pq[0];
         __syncthreads();
-        const double alpha = s_sc[2] > 0.0 ? rh / s_sc[2] : 0.0;
+        double gam = 0.0, del = 0.0;
+        for (int ww = 0; ww < nwa; ++ww) {   // the same order in every thread
+          gam += s_red[ww];
+          del += s_red[NW + ww];
+        }
+        if (it == 0) gam0 = gam;
+        if (!(gam > kCoarseCgRtol * kCoarseCgRtol * gam0)) break;
+        double beta = 0.0, den = del;
+        if (it > 0) {
+          beta = gam / gam_old;
+          den = del - beta * gam / alpha;
+        }
+        if (!(den > 0.0)) break;
+        alpha = gam / den;
+        pr = rr + beta * pr;   // p = r + beta p
+        sr = wv + beta * sr;   // s = A p
         xr += alpha * pr;
-        rr -= alpha * q;
-        double rn[1] = {rr * rr};
-        block_sum<1, kCoarseNT>(rn, s_red);
-        if (tid == 0) s_sc[3] = rn[0];
-        __syncthreads();
-        const double rh_new = s_sc[3];
-        pr = rr + (rh > 0.0 ? rh_new / rh : 0.0) * pr;
-        rh = rh_new;
-        if (alpha == 0.0) break;
+        rr -= alpha * sr;
+        gam_old = gam;
       }
       if (own) z[c] = (S)xr;
       __syncthreads();
@@ -1295,6 +1315,7 @@ __device__ __forceinline__ void mg_cycle(const Inst& I, const ViewF& V, int lo, 
 template <typename S>
 struct CoarseLds {
   S ax[kCLX], ay[kCLY], r[kCLX], z[kCLX], t[kCLX];
+  double cg[kCoarseNT];   // shared FP64 vector of the coarsest CG
   double red[2 * kCoarseNT / 64];
   double sc[4];
 };
@@ -1442,9 +1463,9 @@ __global__ void __launch_bounds__(kCoarseNT) k_mg_coarse(const Inst* __restrict_
   }
   __syncthreads();
   if (lg >= lc)   // LDS levels only: views the compiler knows to be LDS (ds_ instructions)
-    mg_cycle<S>(I, [&](int l) { return coarse_view<S>(I, C, l); }, lg, nl, C.red, C.sc, &dp);
+    mg_cycle<S>(I, [&](int l) { return coarse_view<S>(I, C, l); }, lg, nl, C.red, C.sc, C.cg, &dp);
   else
-    mg_cycle<S>(I, view, lg, nl, C.red, C.sc, &dp);
+    mg_cycle<S>(I, view, lg, nl, C.red, C.sc, C.cg, &dp);
   // ---- publish the level-lg correction (and beta when it is level 0)
   {
     const Level& L = I.lev[lg];
