@@ -275,3 +275,29 @@ def test_two_sweep_pairs_match_oracle_in_fewer_iterations(launch, make):
             assert max(errs.values()) < 1e-10, errs
     print(case.name, launch, "iterations V(1,1) / V(2,2):", its)
     assert its[2] < its[1]
+
+
+@pytest.mark.parametrize("launch", ["tiled", "persistent"])
+def test_coarsest_cg_grid_matches_oracle(launch):
+    """240 x 120 halves to a 30 x 15 coarsest grid (450 cells, beyond the
+    dense inverse): the V-cycle ends in the single-reduction CG of the coarse
+    kernel.  FP64 against the oracle at 1e-10 (CG to 1e-13); the mixed path
+    reaches the residual with the mass conserved."""
+    case = W.drop_case(240, 120, 60.0, 10.0)
+    steps = 3
+    ref, _ = _oracle(case, steps)
+    s = _solver(case.params, case.phi0, rtol=1e-13, maxit=400, launch=launch)
+    s.step(steps)
+    d = s.diagnostics()
+    g = s.state()
+    s.close()
+    errs = {k: relerr(g[k], ref[k]) for k in FIELDS}
+    print(launch, "240x120 FP64 vs oracle:", errs, "iterations", d["last_iters"])
+    assert max(errs.values()) < 1e-10, errs
+    assert d["last_iters"] <= 40
+    m = _solver(case.params, case.phi0, precision="mixed", rtol=1e-10, launch=launch)
+    m.step(steps)
+    dm = m.diagnostics()
+    m.close()
+    assert dm["last_relres"] <= 1e-10
+    assert abs(dm["mass"] - dm["mass0"]) <= 1e-12 * dm["mass0"]
