@@ -136,14 +136,14 @@ void conv(cdi_net* n, const __bf16* x, const __bf16* w, const float* bias, __bf1
           int ci, int co, int level, int relu, const __bf16* xlo = nullptr, int clo = 0) {
   const int H = n->H >> level, W = n->W >> level;
   const int nxt = (W + TPX - 1) / TPX;
-  if (co <= 32) {   // 32-channel tile, 4 rows per block
-    const int rows = CROWS * 2;
+  if (co <= 32) {   // 32-channel x 8-row tile: one wave per 2 rows, all 32 channels
+    const int rows = CROWS * 4;
     dim3 grid((unsigned)(n->B * ((H + rows - 1) / rows) * nxt), (unsigned)((co + 31) / 32));
-    k_conv3_fwd<2><<<grid, NT, 0, n->stream>>>(x, w, bias, yb, yf, n->B, ci, co, H, W, relu, xlo, clo);
-  } else {          // 64-channel tile, 2 rows per block
-    const int rows = CROWS;
+    k_conv3_fwd<2, 1><<<grid, NT, 0, n->stream>>>(x, w, bias, yb, yf, n->B, ci, co, H, W, relu, xlo, clo);
+  } else {          // 64-channel x 4-row tile: 2 waves along the channels, 2 along the rows
+    const int rows = CROWS * 2;
     dim3 grid((unsigned)(n->B * ((H + rows - 1) / rows) * nxt), (unsigned)((co + 63) / 64));
-    k_conv3_fwd<4><<<grid, NT, 0, n->stream>>>(x, w, bias, yb, yf, n->B, ci, co, H, W, relu, xlo, clo);
+    k_conv3_fwd<2, 2><<<grid, NT, 0, n->stream>>>(x, w, bias, yb, yf, n->B, ci, co, H, W, relu, xlo, clo);
   }
 }
 

@@ -34,9 +34,11 @@ __device__ __forceinline__ __bf16 f2bf(float v) { return (__bf16)v; }
 // along x plus the two halo columns.  Zero padding outside the image.
 // ci must be a multiple of 32.  relu: 0 none, 1 relu.
 // Output either BF16 (yb) or FP32 (yf), whichever is non-null.
-// WCO waves along the output channels (4: 64-channel tile, 2 rows per wave
-// group; 2: 32-channel tile for 32-channel layers, the other two waves take
-// two more rows), so no wave multiplies padding channels.
+// A wave computes CF 16-channel fragments x CROWS rows x 64 columns, so each
+// input fragment read from LDS feeds CF matrix-core products; WCH waves lie
+// along the output channels and 4 / WCH along the rows (CF = 2: WCH = 1 for
+// the 32-channel layers, a 32-channel x 8-row tile; WCH = 2 for the others,
+// 64 channels x 4 rows).
 constexpr int CROWS = 2;   // rows per wave
 //
 // Decoder form (xlo != nullptr): the input is cat(up2(xlo), x) without being
@@ -44,7 +46,7 @@ constexpr int CROWS = 2;   // rows per wave
 // (row/2, col/2), channels [clo, ci) from x (B x (ci-clo) x H x W); clo is a
 // multiple of 32, so each 32-channel step reads one of the two.
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
-template <int WCO>
+template <int CF, int WCH>
 __global__ void __launch_bounds__(NT) k_conv3_fwd(const __bf16* __restrict__ x,
                                                   const __bf16* __restrict__ wp,
                                                   const float* __restrict__ bias,
@@ -52,11 +54,15 @@ __global__ void __launch_bounds__(NT) k_conv3_fwd(const __bf16* __restrict__ x,
                                                   int B, int ci, int co, int H, int W, int relu,
                                                   const __bf16* __restrict__ xlo = nullptr,
                                                   int clo = 0) {
-  constexpr int TC = 16 * WCO;                       // output channels of the tile
-  constexpr int ROWS = CROWS * (4 / WCO);            // output rows of the tile
+  constexpr int TC = 16 * CF * WCH;                  // output channels of the tile
+  constexpr int ROWS = CROWS * (4 / WCH);            // output rows of the tile
   constexpr int XR = ROWS + 2;                       // staged input rows
-  __shared__ __attribute__((aligned(16))) __bf16 s_x[XR * (TPX + 2) * KC];   // [row][px][c]
-  __shared__ __attribute__((aligned(16))) __bf16 s_w[TC * 9 * KC];           // [o][tap][c]
+  // LDS pitch of one pixel's (or one (o, tap)'s) 32 channels: 40 BF16 = 80
+  // bytes keeps every 8-channel vector 16-byte aligned and spreads 16
+  // consecutive pixels over 16 banks (a 64-byte pitch hits 4)
+  constexpr int KP = KC + 8;
+  __shared__ __attribute__((aligned(16))) __bf16 s_x[XR * (TPX + 2) * KP];   // [row][px][c]
+  __shared__ __attribute__((aligned(16))) __bf16 s_w[TC * 9 * KP];           // [o][tap][c]
   const int nxt = (W + TPX - 1) / TPX;
   const int nyt = (H + ROWS - 1) / ROWS;
   int blk = blockIdx.x;
@@ -66,14 +72,15 @@ __global__ void __launch_bounds__(NT) k_conv3_fwd(const __bf16* __restrict__ x,
   const int co0 = blockIdx.y * TC;
   const int x0 = xt * TPX;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int wco = wv % WCO;                          // channel block of this wave
-  const int wr0 = (wv / WCO) * CROWS;                // first tile row of this wave
-  const bool vec = (W % 8) == 0;
-  f32x4 acc[CROWS][4];
+  const int wco = wv % WCH;                          // channel group of this wave
+  const int wr0 = (wv / WCH) * CROWS;                // first tile row of this wave
+  f32x4 acc[CF][CROWS][4];
 #pragma unroll
-  for (int r = 0; r < CROWS; ++r)
+  for (int f = 0; f < CF; ++f)
 #pragma unroll
-    for (int n = 0; n < 4; ++n) acc[r][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int r = 0; r < CROWS; ++r)
+#pragma unroll
+      for (int n = 0; n < 4; ++n) acc[f][r][n] = f32x4{0.f, 0.f, 0.f, 0.f};
   const size_t plane = (size_t)H * W;
   const int kq = 8 * (lane >> 4);
   const int li = lane & 15;
@@ -82,43 +89,31 @@ __global__ void __launch_bounds__(NT) k_conv3_fwd(const __bf16* __restrict__ x,
   const int cskip = ci - clo;
   for (int c0 = 0; c0 < ci; c0 += KC) {
     const bool lo = xlo != nullptr && c0 < clo;   // this step reads the upsampled tensor
-    // input rows row0-1 .. row0+ROWS: 8-column vectors of the 64-column core
-    for (int e = tid; e < KC * XR * (TPX / 8); e += NT) {
-      const int v8 = e % (TPX / 8);
-      const int r = (e / (TPX / 8)) % XR;
-      const int c = e / (XR * (TPX / 8));
-      const int yy = row0 + r - 1, xx = x0 + 8 * v8;
+    // input rows row0-1 .. row0+ROWS, the 64-column core: a thread gathers
+    // 8 channels of one pixel (each load coalesced along the pixels of the
+    // wave) and stores them as one 16-byte vector
+    for (int e = tid; e < (KC / 8) * XR * TPX; e += NT) {
+      const int px = e % TPX;
+      const int r = (e / TPX) % XR;
+      const int c8 = e / (TPX * XR);
+      const int yy = row0 + r - 1, xx = x0 + px;
       bf16x8 v;
 #pragma unroll
       for (int q = 0; q < 8; ++q) v[q] = f2bf(0.f);
       if (yy >= 0 && yy < H && xx < W) {
         if (lo) {
-          // 8 columns xx..xx+7 of up2(xlo) = 4 columns xx/2.. of xlo, each twice
-          const __bf16* src = &xlo[((size_t)b * clo + c0 + c) * plane_lo + (size_t)(yy >> 1) * wh + (xx >> 1)];
-          if (vec && xx + 8 <= W) {
-            const bf16x4 h4 = *(const bf16x4*)src;   // 8-byte aligned: W/2 and the plane are multiples of 4
+          const __bf16* src = &xlo[((size_t)b * clo + c0 + 8 * c8) * plane_lo + (size_t)(yy >> 1) * wh + (xx >> 1)];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) v[q] = h4[q >> 1];
-          } else {
-#pragma unroll
-            for (int q = 0; q < 8; ++q)
-              if (xx + q < W) v[q] = src[q >> 1];
-          }
+          for (int q = 0; q < 8; ++q) v[q] = src[(size_t)q * plane_lo];
         } else {
           const __bf16* src = xlo != nullptr
-              ? &x[((size_t)b * cskip + (c0 - clo) + c) * plane + (size_t)yy * W + xx]
-              : &x[((size_t)b * ci + c0 + c) * plane + (size_t)yy * W + xx];
-          if (vec && xx + 8 <= W) {
-            v = *(const bf16x8*)src;   // 16-byte aligned: W and the plane are multiples of 8
-          } else {
+              ? &x[((size_t)b * cskip + (c0 - clo) + 8 * c8) * plane + (size_t)yy * W + xx]
+              : &x[((size_t)b * ci + c0 + 8 * c8) * plane + (size_t)yy * W + xx];
 #pragma unroll
-            for (int q = 0; q < 8; ++q)
-              if (xx + q < W) v[q] = src[q];
-          }
+          for (int q = 0; q < 8; ++q) v[q] = src[(size_t)q * plane];
         }
       }
-#pragma unroll
-      for (int q = 0; q < 8; ++q) s_x[(r * (TPX + 2) + 1 + 8 * v8 + q) * KC + c] = v[q];
+      *(bf16x8*)&s_x[(r * (TPX + 2) + 1 + px) * KP + 8 * c8] = v;
     }
     // the two halo columns x0-1 and x0+TPX
     for (int e = tid; e < KC * XR * 2; e += NT) {
@@ -132,7 +127,7 @@ __global__ void __launch_bounds__(NT) k_conv3_fwd(const __bf16* __restrict__ x,
         else if (xlo != nullptr) v = x[((size_t)b * cskip + (c0 - clo) + c) * plane + (size_t)yy * W + xx];
         else v = x[((size_t)b * ci + c0 + c) * plane + (size_t)yy * W + xx];
       }
-      s_x[(r * (TPX + 2) + (side ? TPX + 1 : 0)) * KC + c] = v;
+      s_x[(r * (TPX + 2) + (side ? TPX + 1 : 0)) * KP + c] = v;
     }
     // weights of the tile: 4 vectors of 8 input channels per (o, tap)
     for (int e = tid; e < TC * 9 * (KC / 8); e += NT) {
@@ -146,24 +141,31 @@ __global__ void __launch_bounds__(NT) k_conv3_fwd(const __bf16* __restrict__ x,
 #pragma unroll
         for (int q = 0; q < 8; ++q) v[q] = f2bf(0.f);
       }
-      *(bf16x8*)&s_w[ot * KC + 8 * v8] = v;
+      *(bf16x8*)&s_w[ot * KP + 8 * v8] = v;
     }
     __syncthreads();
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
       const int ky = t / 3, kx = t - 3 * ky;
-      const bf16x8 a = *(const bf16x8*)&s_w[((16 * wco + li) * 9 + t) * KC + kq];
+      bf16x8 a[CF];
+#pragma unroll
+      for (int f = 0; f < CF; ++f)
+        a[f] = *(const bf16x8*)&s_w[((16 * (wco * CF + f) + li) * 9 + t) * KP + kq];
 #pragma unroll
       for (int r = 0; r < CROWS; ++r)
 #pragma unroll
         for (int n = 0; n < 4; ++n) {
-          const bf16x8 bv = *(const bf16x8*)&s_x[((wr0 + r + ky) * (TPX + 2) + 16 * n + li + kx) * KC + kq];
-          acc[r][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bv, acc[r][n], 0, 0, 0);
+          const bf16x8 bv = *(const bf16x8*)&s_x[((wr0 + r + ky) * (TPX + 2) + 16 * n + li + kx) * KP + kq];
+#pragma unroll
+          for (int f = 0; f < CF; ++f)
+            acc[f][r][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[f], bv, acc[f][r][n], 0, 0, 0);
         }
     }
     __syncthreads();
   }
   // epilogue: lane holds rows 4(lane/16)+q (output channels), column lane%16
+#pragma unroll
+  for (int f = 0; f < CF; ++f)
 #pragma unroll
   for (int r = 0; r < CROWS; ++r) {
     const int row = row0 + wr0 + r;
@@ -174,9 +176,9 @@ __global__ void __launch_bounds__(NT) k_conv3_fwd(const __bf16* __restrict__ x,
       if (px >= W) continue;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int o = co0 + 16 * wco + 4 * (lane >> 4) + q;
+        const int o = co0 + 16 * (wco * CF + f) + 4 * (lane >> 4) + q;
         if (o >= co) continue;
-        float v = acc[r][n][q] + (bias ? bias[o] : 0.f);
+        float v = acc[f][r][n][q] + (bias ? bias[o] : 0.f);
         if (relu) v = fmaxf(v, 0.f);
         const size_t idx = ((size_t)b * co + o) * plane + (size_t)row * W + px;
         if (yb) yb[idx] = f2bf(v);
