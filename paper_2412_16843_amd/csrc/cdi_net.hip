@@ -26,7 +26,7 @@ struct LayerDesc {
 };
 
 constexpr int kLayers = 7;
-const LayerDesc kNet[kLayers] = {
+constexpr LayerDesc kNet[kLayers] = {
     {"e0", 32, 32, 3, 0},    {"e1", 32, 64, 32, 1},   {"e2", 64, 128, 64, 2},
     {"e3", 128, 256, 128, 3}, {"d2", 384, 128, 384, 2}, {"d1", 192, 64, 192, 1},
     {"d0", 96, 32, 96, 0}};
@@ -89,7 +89,6 @@ size_t carve(cdi_net* n, char* base, bool train) {
     n->wt[l] = (__bf16*)take((size_t)kNet[l].co * 9 * kNet[l].ci * sizeof(__bf16));
   }
   n->feat = (float*)take(B * 3 * H * W * sizeof(float));
-  n->x0 = act(32, 0);
   n->e[0] = act(32, 0);
   n->p[0] = act(32, 1);
   n->e[1] = act(64, 1);
@@ -99,12 +98,14 @@ size_t carve(cdi_net* n, char* base, bool train) {
   n->e[3] = act(256, 3);
   n->d2 = act(128, 2);
   n->d1 = act(64, 1);
-  n->d0 = act(32, 0);
   n->y = (float*)take(B * H * W * sizeof(float));
   n->loss = (float*)take(256);
   n->train = train;
   if (train) {
-    // the decoder's concatenated inputs, read by the weight gradient
+    // the padded input and the decoder's concatenated inputs, read by the
+    // weight gradients
+    n->x0 = act(32, 0);
+    n->d0 = act(32, 0);
     n->c2 = act(384, 2);
     n->c1 = act(192, 1);
     n->c0 = act(96, 0);
@@ -133,17 +134,21 @@ unsigned rows_grid(size_t rows) { return (unsigned)std::min<size_t>(65535, std::
 // 3x3 convolution at `level`; with xlo the input is cat(up2(xlo), x) read
 // in place (clo channels from xlo).
 void conv(cdi_net* n, const __bf16* x, const __bf16* w, const float* bias, __bf16* yb, float* yf,
-          int ci, int co, int level, int relu, const __bf16* xlo = nullptr, int clo = 0) {
+          int ci, int co, int level, int relu, const __bf16* xlo = nullptr, int clo = 0,
+          const float* xf = nullptr, const float* ow = nullptr, const float* ob = nullptr,
+          float* yo = nullptr) {
   const int H = n->H >> level, W = n->W >> level;
   const int nxt = (W + TPX - 1) / TPX;
   if (co <= 32) {   // 32-channel x 8-row tile: one wave per 2 rows, all 32 channels
     const int rows = CROWS * 4;
     dim3 grid((unsigned)(n->B * ((H + rows - 1) / rows) * nxt), (unsigned)((co + 31) / 32));
-    k_conv3_fwd<2, 1><<<grid, NT, 0, n->stream>>>(x, w, bias, yb, yf, n->B, ci, co, H, W, relu, xlo, clo);
+    k_conv3_fwd<2, 1><<<grid, NT, 0, n->stream>>>(x, w, bias, yb, yf, n->B, ci, co, H, W, relu, xlo, clo, xf,
+                                                   ow, ob, yo);
   } else {          // 64-channel x 4-row tile: 2 waves along the channels, 2 along the rows
+    // (the fused output layer is only used on the 32-channel last layer)
     const int rows = CROWS * 2;
     dim3 grid((unsigned)(n->B * ((H + rows - 1) / rows) * nxt), (unsigned)((co + 63) / 64));
-    k_conv3_fwd<2, 2><<<grid, NT, 0, n->stream>>>(x, w, bias, yb, yf, n->B, ci, co, H, W, relu, xlo, clo);
+    k_conv3_fwd<2, 2><<<grid, NT, 0, n->stream>>>(x, w, bias, yb, yf, n->B, ci, co, H, W, relu, xlo, clo, xf);
   }
 }
 
@@ -163,8 +168,11 @@ void forward(cdi_net* n) {
   const int B = n->B, H = n->H, W = n->W;
   const size_t HW = (size_t)H * W;
   float* P = n->params;
-  k_pack_input<<<grid1d((size_t)B * 32 * HW), 256, 0, n->stream>>>(n->feat, n->x0, B, (int)HW, 32);
-  conv(n, n->x0, n->wp[0], P + n->boff[0], n->e[0], nullptr, 32, 32, 0, 1);
+  // the first layer reads the FP32 features; training also stores the
+  // padded BF16 input, which its weight gradient reads
+  if (n->train)
+    k_pack_input<<<grid1d((size_t)B * 32 * HW), 256, 0, n->stream>>>(n->feat, n->x0, B, (int)HW, 32);
+  conv(n, nullptr, n->wp[0], P + n->boff[0], n->e[0], nullptr, 32, 32, 0, 1, nullptr, 0, n->feat);
   k_pool<<<grid1d((size_t)B * 32 * HW / 4), 256, 0, n->stream>>>(n->e[0], n->p[0], B * 32, H, W);
   conv(n, n->p[0], n->wp[1], P + n->boff[1], n->e[1], nullptr, 32, 64, 1, 1);
   k_pool<<<grid1d((size_t)B * 64 * HW / 16), 256, 0, n->stream>>>(n->e[1], n->p[1], B * 64, H / 2, W / 2);
@@ -181,8 +189,12 @@ void forward(cdi_net* n) {
   conv(n, n->e[1], n->wp[5], P + n->boff[5], n->d1, nullptr, 192, 64, 1, 1, n->d2, 128);
   if (n->train)
     k_upcat<<<rows_grid((size_t)B * 96 * H), 256, 0, n->stream>>>(n->d1, n->e[0], n->c0, B, 64, 32, H, W);
-  conv(n, n->e[0], n->wp[6], P + n->boff[6], n->d0, nullptr, 96, 32, 0, 1, n->d1, 64);
-  k_out_fwd<<<grid1d((size_t)B * HW), 256, 0, n->stream>>>(n->d0, P + n->out_w, P + n->out_b, n->y, B, 32, (int)HW);
+  // last 3x3 layer (32 channels: one tile holds them all) with the 1x1
+  // output layer fused into its epilogue; its activation is stored only for
+  // training (the backward pass reads it)
+  static_assert(kNet[6].co == 32, "the fused output layer needs a 32-channel last layer");
+  conv(n, n->e[0], n->wp[6], P + n->boff[6], n->train ? n->d0 : nullptr, nullptr, 96, 32, 0, 1,
+       n->d1, 64, nullptr, P + n->out_w, P + n->out_b, n->y);
 }
 
 namespace {

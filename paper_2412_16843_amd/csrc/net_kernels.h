@@ -41,6 +41,8 @@ __device__ __forceinline__ __bf16 f2bf(float v) { return (__bf16)v; }
 // 64 channels x 4 rows).
 constexpr int CROWS = 2;   // rows per wave
 //
+// First-layer form (xf != nullptr): the input is the 3 FP32 feature planes
+// (ci = 32, channels 3..31 zero), rounded to BF16 on staging.
 // Decoder form (xlo != nullptr): the input is cat(up2(xlo), x) without being
 // stored -- channels [0, clo) are read from xlo (B x clo x H/2 x W/2) at
 // (row/2, col/2), channels [clo, ci) from x (B x (ci-clo) x H x W); clo is a
@@ -53,7 +55,11 @@ __global__ void __launch_bounds__(NT) k_conv3_fwd(const __bf16* __restrict__ x,
                                                   __bf16* __restrict__ yb, float* __restrict__ yf,
                                                   int B, int ci, int co, int H, int W, int relu,
                                                   const __bf16* __restrict__ xlo = nullptr,
-                                                  int clo = 0) {
+                                                  int clo = 0,
+                                                  const float* __restrict__ xf = nullptr,
+                                                  const float* __restrict__ ow = nullptr,
+                                                  const float* __restrict__ ob = nullptr,
+                                                  float* __restrict__ yo = nullptr) {
   constexpr int TC = 16 * CF * WCH;                  // output channels of the tile
   constexpr int ROWS = CROWS * (4 / WCH);            // output rows of the tile
   constexpr int XR = ROWS + 2;                       // staged input rows
@@ -101,7 +107,11 @@ __global__ void __launch_bounds__(NT) k_conv3_fwd(const __bf16* __restrict__ x,
 #pragma unroll
       for (int q = 0; q < 8; ++q) v[q] = f2bf(0.f);
       if (yy >= 0 && yy < H && xx < W) {
-        if (lo) {
+        if (xf) {   // first layer: 3 FP32 feature planes, the other channels 0
+#pragma unroll
+          for (int q = 0; q < 3; ++q)
+            if (8 * c8 + q < 3) v[q] = f2bf(xf[((size_t)b * 3 + 8 * c8 + q) * plane + (size_t)yy * W + xx]);
+        } else if (lo) {
           const __bf16* src = &xlo[((size_t)b * clo + c0 + 8 * c8) * plane_lo + (size_t)(yy >> 1) * wh + (xx >> 1)];
 #pragma unroll
           for (int q = 0; q < 8; ++q) v[q] = src[(size_t)q * plane_lo];
@@ -123,7 +133,8 @@ __global__ void __launch_bounds__(NT) k_conv3_fwd(const __bf16* __restrict__ x,
       const int yy = row0 + r - 1, xx = side ? x0 + TPX : x0 - 1;
       __bf16 v = f2bf(0.f);
       if (yy >= 0 && yy < H && xx >= 0 && xx < W) {
-        if (lo) v = xlo[((size_t)b * clo + c0 + c) * plane_lo + (size_t)(yy >> 1) * wh + (xx >> 1)];
+        if (xf) v = c < 3 ? f2bf(xf[((size_t)b * 3 + c) * plane + (size_t)yy * W + xx]) : f2bf(0.f);
+        else if (lo) v = xlo[((size_t)b * clo + c0 + c) * plane_lo + (size_t)(yy >> 1) * wh + (xx >> 1)];
         else if (xlo != nullptr) v = x[((size_t)b * cskip + (c0 - clo) + c) * plane + (size_t)yy * W + xx];
         else v = x[((size_t)b * ci + c0 + c) * plane + (size_t)yy * W + xx];
       }
@@ -182,9 +193,35 @@ __global__ void __launch_bounds__(NT) k_conv3_fwd(const __bf16* __restrict__ x,
         if (relu) v = fmaxf(v, 0.f);
         const size_t idx = ((size_t)b * co + o) * plane + (size_t)row * W + px;
         if (yb) yb[idx] = f2bf(v);
-        else yf[idx] = v;
+        else if (yf) yf[idx] = v;
       }
     }
+  }
+  // Fused 1x1 output layer (yo != nullptr; a 32-channel tile, WCH = 1, so a
+  // wave holds all 32 channels of its pixels): y = ob + sum_o ow[o] v_o with
+  // v_o the BF16-rounded activation.  Each lane adds its 2 x 4 channels, then
+  // the four lane groups (lane / 16) are added by two xor exchanges (every
+  // lane ends with the same bits: each exchange adds the same two values).
+  if (yo) {
+#pragma unroll
+    for (int r = 0; r < CROWS; ++r)
+#pragma unroll
+      for (int n = 0; n < 4; ++n) {
+        float sum = 0.f;
+#pragma unroll
+        for (int f = 0; f < CF; ++f)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int o = 16 * (wco * CF + f) + 4 * (lane >> 4) + q;
+            float v = acc[f][r][n][q] + (bias ? bias[co0 + o] : 0.f);
+            if (relu) v = fmaxf(v, 0.f);
+            sum += ow[o] * bf2f(f2bf(v));
+          }
+        sum += __shfl_xor(sum, 16, 64);
+        sum += __shfl_xor(sum, 32, 64);
+        const int row = row0 + wr0 + r, px = x0 + 16 * n + (lane & 15);
+        if (lane < 16 && row < H && px < W) yo[(size_t)b * plane + (size_t)row * W + px] = ob[0] + sum;
+      }
   }
 }
 
@@ -388,20 +425,6 @@ __global__ void k_skip_grad(const __bf16* __restrict__ dcat, const __bf16* __res
 __global__ void k_relu_bwd(__bf16* __restrict__ g, const __bf16* __restrict__ y, size_t n) {
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x)
     if (!(bf2f(y[e]) > 0.f)) g[e] = f2bf(0.f);
-}
-
-// 1x1 output layer: y[b,p] = sum_c w[c] d0[b,c,p] + bias (FP32 out)
-__global__ void k_out_fwd(const __bf16* __restrict__ d0, const float* __restrict__ w,
-                          const float* __restrict__ bias, float* __restrict__ y, int B, int C,
-                          int HW) {
-  const size_t n = (size_t)B * HW;
-  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
-    const int p = e % HW;
-    const int b = e / HW;
-    float s = bias[0];
-    for (int c = 0; c < C; ++c) s += w[c] * bf2f(d0[((size_t)b * C + c) * HW + p]);
-    y[e] = s;
-  }
 }
 
 // Loss gradient dy = 2 (y - t) / N and the output layer's backward:
