@@ -70,17 +70,23 @@ def mg_levels(nx: int, ny: int, coarse_cells: int = 1024):
     return levels, lc
 
 
-def algo_bytes_per_launch(fam: str, p) -> float:
-    """Algorithmic bytes of one launch of kernel family `fam` on workload p."""
+def algo_bytes_per_launch(fam: str, p, coarse_cells: int = 1024) -> float:
+    """Algorithmic bytes of one launch of kernel family `fam` on workload p
+    (`coarse_cells`: the level size from which the single-block coarse kernel
+    runs the V-cycle)."""
     cells = p.nx * p.ny
     if fam in ALGO_BYTES_PER_CELL:
         return ALGO_BYTES_PER_CELL[fam] * cells
-    levels, lc = mg_levels(p.nx, p.ny)
+    levels, lg = mg_levels(p.nx, p.ny, coarse_cells)
     if fam == "mg_coarse":
-        # level-lc right-hand side read and correction written, coefficients of
-        # every coarse level read (x- and y-faces)
-        n = sum(a * b for a, b in levels[lc:])
-        return 8 * (2 * levels[lc][0] * levels[lc][1] + 2 * n)
+        # right-hand side of the first level it runs read and its correction
+        # written, the x- and y-face coefficients of every level from there
+        # read, and the dense inverse of the coarsest grid (up to 64 cells)
+        coef = sum(a * b + a * (b + 1) for a, b in levels[lg:])
+        n0 = levels[lg][0] * levels[lg][1]
+        nc = levels[-1][0] * levels[-1][1]
+        dense = nc * nc if nc <= 64 else 0
+        return 8 * (2 * n0 + coef + dense)
     raise KeyError(fam)
 
 
@@ -319,7 +325,7 @@ def main():
     elapsed = t1 - t0
     cells = p.nx * p.ny
     value = cells * args.steps / elapsed / 1e6
-    per_launch_bytes = algo_bytes_per_launch(fam, p)
+    per_launch_bytes = algo_bytes_per_launch(fam, p, s.get_coarse_cells())
     avg_s = (k_ms / max(k_n, 1)) * 1e-3
     achieved = per_launch_bytes / avg_s / 1e9 if avg_s > 0 else 0.0
     out = {
