@@ -275,8 +275,8 @@ def main():
                     help="add the learned-vs-plain pressure time-to-solution at 2048x1024")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
-              "decomposition is a design described in DESIGN.md, not part of this build.",
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the library "
+              "advances its instances on a single GPU and has no multi-GPU decomposition.",
               file=sys.stderr)
         sys.exit(2)
 

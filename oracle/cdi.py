@@ -13,7 +13,7 @@ and y = Ly.  Arrays are row-major, x fastest:
 Corner (i, j) sits at (i h, j h); corner rows 0 and ny lie on the walls.
 
 Readings of points the paper leaves open (each used identically by the GPU
-path, documented in DESIGN.md):
+path):
   * n = G / (|G| + DELTA_N), G the cell-centred gradient of phi;
   * psi = eps ln((clip(phi) + DELTA_PSI) / (1 - clip(phi) + DELTA_PSI));
   * face values are arithmetic means of the two adjacent cells, corner
