@@ -851,8 +851,11 @@ __global__ void __launch_bounds__(kNT) k_mg_up(const Tile* __restrict__ tiles,
   constexpr int EY = RY / 2 + 2, EX = RX / 2 + 2;
   __shared__ S s_r[RY * RX], s_z[RY * RX];
   __shared__ S s_ax[RY * (RX + 1)], s_ay[(RY + 1) * RX];
-  __shared__ S s_e[EY * EX];
   __shared__ double sh[kNT / 64];
+  // the staged coarse correction lives in s_r until the prolongation has
+  // read it (one LDS array less: 5 blocks per CU instead of 4 at V(2,2) FP64)
+  static_assert(EY * EX <= RY * RX, "coarse correction fits the right-hand-side array");
+  S* const s_e = s_r;
   const Tile t = tiles[blockIdx.x];
   const Inst& I = insts[t.inst];
   if (I.pcg->done) return;
@@ -945,8 +948,15 @@ __global__ void __launch_bounds__(kNT) k_mg_up(const Tile* __restrict__ tiles,
       const S c = s_e[(J2 - Jb) * EX + cI], d = s_e[(J2 - Jb) * EX + cI2];
       z = zl[e] + (S(0.5625) * a + S(0.1875) * b + S(0.1875) * c + S(0.0625) * d);
     }
+    zl[e] = z;
+  }
+  __syncthreads();   // every read of s_e (= s_r) is done
+#pragma unroll
+  for (int e = 0; e < NPT; ++e) {
+    const int k = threadIdx.x + e * kNT;
+    if (k >= RY * RX) continue;
     s_r[k] = (S)rl[e];
-    s_z[k] = z;
+    s_z[k] = zl[e];
   }
   __syncthreads();
   auto valid = [&](int rj) { const int j = j0 - H + rj; return j >= 0 && j < ny; };
