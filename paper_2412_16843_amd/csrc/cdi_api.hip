@@ -197,6 +197,7 @@ size_t carve(const Resolved& R, int ntiles_cell, int ntiles_mg0, char* base, siz
     }
     L.r = (l == 0) ? nullptr : take(lc * S);
     L.z = take(lc * S);
+    L.zo = (l == 0) ? nullptr : take(lc * S);
   }
   const size_t ncs = (size_t)R.lnx[R.nlev - 1] * R.lny[R.nlev - 1];
   D.cdense = ncs <= (size_t)kDenseMax ? 1 : 0;

@@ -25,7 +25,9 @@ struct Level {
   void* ax;                 // S[ny*nx]
   void* ay;                 // S[(ny+1)*nx]
   void* r;                  // S[ny*nx]  residual / right-hand side of the level
-  void* z;                  // S[ny*nx]  correction of the level
+  void* z;                  // S[ny*nx]  correction of the level (pre-smoothed on tiled levels)
+  void* zo;                 // S[ny*nx]  post-smoothed correction written by the tiled up-sweep
+                            //           (levels 1..lg-1; a launch never reads what it writes)
 };
 
 // Per-instance scalars of the flexible CG, written by the last block of the

@@ -839,7 +839,10 @@ __device__ __forceinline__ S prolong(const S* e, int cnx, int cny, int j, int i)
 }
 
 // z += P e, then post-smoothing (black, then red).  Level 0 writes the FP64
-// preconditioned residual and forms the flexible-CG beta.
+// preconditioned residual and forms the flexible-CG beta; a coarser level
+// writes its result to zo, never to z: the blocks of one launch read the
+// pre-smoothed z of their neighbours' cells in their halos, and a block may
+// start after its neighbour has finished.
 template <typename S, int NU>
 __global__ void __launch_bounds__(kNT) k_mg_up(const Tile* __restrict__ tiles,
                                                 const Inst* __restrict__ insts, int level,
@@ -888,7 +891,9 @@ __global__ void __launch_bounds__(kNT) k_mg_up(const Tile* __restrict__ tiles,
     ayl[e] = (k < (RY + 1) * RX && j >= 0 && j <= ny)
                  ? ldS<S>(L.ay, (size_t)j * nx + wrap_any(i0 - H + ri, nx)) : S(0);
   }
-  const S* __restrict__ ec = (const S*)C.z;
+  // the finished correction of the coarser level: zo where this kernel
+  // produced it, z where the one-block coarse kernel did (level lg)
+  const S* __restrict__ ec = (const S*)(level + 1 < I.lg ? C.zo : C.z);
 #pragma unroll
   for (int e = 0; e < NE; ++e) {
     const int k = threadIdx.x + e * kNT;
@@ -976,7 +981,7 @@ __global__ void __launch_bounds__(kNT) k_mg_up(const Tile* __restrict__ tiles,
       const int k = threadIdx.x + e * kNT;
       const int ty = k / FX, tx = k - ty * FX;
       const int j = j0 + ty, i = i0 + tx;
-      if (j < ny && i < nx) ((S*)L.z)[(size_t)j * nx + i] = s_z[(ty + H) * RX + (tx + H)];
+      if (j < ny && i < nx) ((S*)L.zo)[(size_t)j * nx + i] = s_z[(ty + H) * RX + (tx + H)];
     }
     return;
   }

@@ -69,7 +69,25 @@ def test_stage_operator_at_full_size(name, make):
     assert max(errs.values()) < 1e-12, errs
 
 
-@pytest.mark.parametrize("name,make", FULL[:2])
+def residual_floor(pg, rfx, rfy, h, bm):
+    """eps |||A| |p||| / ||b||: the relative residual that FP64 rounding of
+    p, or of the evaluation of b - A p, can produce by itself.  On the
+    8192 x 4096 grid (h = 2/8192, rho = 0.01: face coefficients ~1e9) it is
+    ~1e-10, so a fixed 2e-10 bound cannot be met there by any FP64 solver."""
+    a = np.abs(pg)
+    fx = (a + np.roll(a, 1, axis=1)) / rfx
+    out = fx + np.roll(fx, -1, axis=1)
+    fy = (a[1:] + a[:-1]) / rfy[1:-1]
+    out[:-1] += fy
+    out[1:] += fy
+    return float(np.finfo(float).eps * np.linalg.norm(out / (h * h)) / np.linalg.norm(bm))
+
+
+# the largest grid the bench measures (33.5 M cells, DRAM bound)
+LARGEST = ("drop8192x4096_r10", lambda: W.drop_case(8192, 4096, 60.0, 10.0))
+
+
+@pytest.mark.parametrize("name,make", FULL[:2] + [LARGEST])
 def test_pressure_solve_at_full_size_meets_residual(name, make):
     case = make()
     p = case.params
@@ -87,10 +105,15 @@ def test_pressure_solve_at_full_size_meets_residual(name, make):
     bm = b - b.mean()
     res = poisson.apply_A(pg, rfx, rfy, p.h) - bm
     rel = np.linalg.norm(res) / np.linalg.norm(bm)
+    floor = residual_floor(pg, rfx, rfy, p.h, bm)
     print(name, "iterations", info["iterations"], "relres (GPU)", info["relres"],
-          "true relres (oracle operator)", rel)
+          "true relres (oracle operator)", rel, "FP64 floor", floor)
     assert info["converged"] == 1
-    assert rel <= 2e-10, rel
+    # twice the requested tolerance (the recurrence residual drifts from the
+    # true one by rounding), plus what FP64 can resolve at all: rounding the
+    # solution to FP64 and evaluating b - A p each move the residual by up to
+    # about one floor
+    assert rel <= 2e-10 + 4 * floor, (rel, floor)
     assert abs(pg.mean()) <= 1e-12 * np.abs(pg).max()
 
 
@@ -139,3 +162,53 @@ def test_config4_full_ensemble_sampled_against_oracle():
         print(c.name, c.params.nx, "x", c.params.ny, "vs oracle:", errs)
         assert max(errs.values()) < 1e-10, (c.name, errs)
     s.close()
+
+
+def test_largest_grid_step_conserves_mass_and_bounds():
+    """One FP64 step of the 8192 x 4096 ratio-10 drop (4 projections to
+    1e-10): total phi conserved to round-off, phi within [0, 1] up to the
+    CDI flux's round-off, every solve at its residual."""
+    case = LARGEST[1]()
+    s = _solver(case.params, case.phi0, rtol=1e-10)
+    s.step(1)
+    d = s.diagnostics()
+    s.close()
+    print("8192x4096 step:", {k: d[k] for k in ("mass", "mass0", "phi_min", "phi_max",
+                                                 "last_iters", "last_relres")})
+    assert abs(d["mass"] - d["mass0"]) <= 1e-12 * d["mass0"]
+    assert d["phi_min"] >= -1e-12 and d["phi_max"] <= 1.0 + 1e-12
+    assert d["last_relres"] <= 1e-10
+
+
+def test_up_sweep_has_no_cross_block_race_at_4m_cells():
+    """Regression: the tiled up-sweep of a coarse level once wrote its result
+    over the correction its neighbours read in their halos.  Below ~2^21
+    cells every block of a level-1 launch is resident at once and read before
+    any wrote; from 2^22 cells blocks started late and read smoothed values,
+    so the preconditioner changed from run to run and the smoothest modes
+    diverged.  A smooth right-hand side on a 2048 x 2048 grid must converge
+    in a multigrid-like count, to the same bits in three solves."""
+    case = W.drop_case(2048, 2048, 60.0, 10.0, lx=2.0, ly=2.0, r0=0.4)
+    p = case.params
+    y, x = np.mgrid[0:p.ny, 0:p.nx]
+    b = np.sin(2 * np.pi * x / p.nx) * np.cos(np.pi * (y + 0.5) / p.ny)
+    import torch
+    outs, iters = [], []
+    for fresh in (True, False, True):
+        if fresh:
+            if outs:
+                s.close()
+            s = _solver(p, case.phi0, rtol=1e-10, guess="zero")
+        pg, info = s.solve_pressure(torch.as_tensor(b))
+        assert info["converged"] == 1, info
+        outs.append(pg.cpu().numpy())
+        iters.append(info["iterations"])
+    s.close()
+    print("2048x2048 smooth rhs: iterations", iters)
+    assert max(iters) <= 20, iters
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+    rfx, rfy = cdi.face_rho(case.phi0, p)
+    bm = b - b.mean()
+    rel = np.linalg.norm(poisson.apply_A(outs[0], rfx, rfy, p.h) - bm) / np.linalg.norm(bm)
+    floor = residual_floor(outs[0], rfx, rfy, p.h, bm)
+    assert rel <= 2e-10 + 4 * floor, (rel, floor)
