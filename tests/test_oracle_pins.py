@@ -372,6 +372,34 @@ def test_navier_slip_couette_profile_is_exact_steady_state():
     assert np.allclose(w["top"]["u_wall"], 1.0 - a * ls, atol=1e-13)
 
 
+@pytest.mark.parametrize("phi_value", [0.0, 0.5, 1.0])
+def test_navier_slip_uses_the_phase_weighted_wall_friction(phi_value):
+    """Wall friction beta_c = beta2 + (beta1 - beta2) phi at the corner (slip
+    BC of Sec. 2) with the asymmetric Couette's values (Sec. 5.2: beta1 = 1.2,
+    beta2 = 0.591, mu = 1.95).  A uniform phase field has no CDI flux, no
+    surface tension and no uncompensated Young stress (u^Y carries d psi/d tau
+    = 0), so the linear profile u = a (y - H/2), a = 2U/(H + 2 mu/beta_c) is an
+    exact discrete steady state: phi = 1 takes beta1, phi = 0 beta2, phi = 1/2
+    their mean."""
+    c = W.couette_case(16, 16, lx=1.0, ly=1.0, steps=3)
+    p = c.params.replace(rho1=0.81, rho2=0.81, mu1=1.95, mu2=1.95, beta1=1.2, beta2=0.591,
+                         sigma=5.5, theta_eq=math.acos(0.38))
+    beta_c = 0.591 + (1.2 - 0.591) * phi_value
+    ls = 1.95 / beta_c
+    a = 2 * 1.0 / (p.ly + 2 * ls)
+    y = (np.arange(p.ny) + 0.5) * p.h
+    s = cdi.initial_state(np.full((p.ny, p.nx), phi_value))
+    s.u = np.repeat((a * (y - 0.5))[:, None], p.nx, axis=1)
+    u0 = s.u.copy()
+    for _ in range(3):
+        s = cdi.step(s, p)
+    assert np.allclose(s.u, u0, atol=1e-13)
+    assert np.abs(s.v).max() < 1e-13
+    w = cdi.wall_stress(s.phi, s.u, p, cdi.phase_fields(s.phi, p))
+    assert np.allclose(w["top"]["u_wall"], 1.0 - a * ls, atol=1e-13)
+    assert np.allclose(w["bot"]["u_wall"], -1.0 + a * ls, atol=1e-13)
+
+
 def test_uniform_flow_is_transported_consistently():
     """sigma = 0, density ratio 10, u = U_wall = U everywhere: the consistent
     mass flux keeps u = U exactly while the drop is advected."""

@@ -174,6 +174,33 @@ def couette_case(nx: int, ny: int, lx: float = 4.0, ly: float = 1.0, ratio: floa
     return _finish(name or f"couette{nx}x{ny}", p, phi0, steps, "couette")
 
 
+def paper_couette_case(variant: str = "asymmetric", nx: int = 512, steps: int = 2000,
+                       name: str | None = None) -> Case:
+    """The two-phase Couette flow of Sec. 5.2 in the molecular-dynamics units
+    it is stated in: domain 108.8 x 13.6 (Ny = Nx / 8), rho = 0.81, mu = 1.95
+    for both fluids, sigma = 5.5, eps = 0.33 sqrt(2)/2, gamma = 2.5 U, top wall
+    at +U and bottom wall at -U, the slab of fluid 1 in [Lx/4, 3Lx/4].
+
+    symmetric: theta_eq = 90 deg, beta1 = beta2 = 1.2, U = 0.25;
+    asymmetric: theta_eq = acos(0.38), beta1 = 1.2, beta2 = 0.591, U = 0.20.
+    """
+    if nx % 8:
+        raise ValueError("Nx must be a multiple of 8 (Lx / Ly = 8)")
+    if variant == "symmetric":
+        theta, b1, b2, U = math.pi / 2, 1.2, 1.2, 0.25
+    elif variant == "asymmetric":
+        theta, b1, b2, U = math.acos(0.38), 1.2, 0.591, 0.20
+    else:
+        raise ValueError(variant)
+    lx, ly = 108.8, 13.6
+    eps = 0.33 * math.sqrt(2.0) / 2.0
+    p = Params(nx=nx, ny=nx // 8, lx=lx, ly=ly, eps=eps, gamma=2.5 * U, sigma=5.5,
+               theta_eq=theta, rho1=0.81, rho2=0.81, mu1=1.95, mu2=1.95, beta1=b1, beta2=b2,
+               u_wall_bot=-U, u_wall_top=U)
+    phi0 = couette_phi(nx, nx // 8, lx, ly, eps)
+    return _finish(name or f"couette_{variant}{nx}x{nx // 8}", p, phi0, steps, "couette")
+
+
 def config1() -> Case:
     """2D equilibrium drop, 64x32 on 2x1, theta 90 -> 60 deg, 500 steps (FP64)."""
     return drop_case(64, 32, 60.0, 1.0, steps=500, name="drop64x32")
