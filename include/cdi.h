@@ -298,6 +298,17 @@ cdi_status cdi_get_tile_rows(cdi_ctx* ctx, int32_t* rows);
 cdi_status cdi_set_coarse_cells(cdi_ctx* ctx, int32_t cells);
 cdi_status cdi_get_coarse_cells(cdi_ctx* ctx, int32_t* cells);
 
+/* Order of the time extrapolation that forms each solve's initial guess
+ * (previous-pressure guess): the same RK stage's pressure of the last q + 1
+ * steps, combined with the weights of the polynomial through them (q = 0:
+ * the last step's pressure; 1: linear, 2 p1 - p2; 2: quadratic, 3 p1 - 3 p2
+ * + p3; 3: cubic, 4 p1 - 6 p2 + 4 p3 - p4), lowered while fewer steps
+ * exist.  order in [0, 3]; cdi_init sets 3.  The guess is an implementation
+ * choice of the solver (the paper does not specify one): it changes the
+ * iteration count, not the converged solution. */
+cdi_status cdi_set_extrapolation(cdi_ctx* ctx, int32_t order);
+cdi_status cdi_get_extrapolation(cdi_ctx* ctx, int32_t* order);
+
 /* Red-black sweep pairs of the V-cycle (1 or 2; the value of mg_smooth at
  * init).  Changes the iteration count, not the converged solution. */
 cdi_status cdi_set_mg_smooth(cdi_ctx* ctx, int32_t nu);

@@ -28,7 +28,8 @@ EXPORTS = ("cdi_workspace_bytes", "cdi_default_dt", "cdi_init", "cdi_init_batch"
            "cdi_set_guess", "cdi_guess_attach", "cdi_guess_features", "cdi_set_launch",
            "cdi_get_launch", "cdi_set_tile_rows", "cdi_get_tile_rows", "cdi_tune_bytes",
            "cdi_tune", "cdi_graph_stats", "cdi_set_coarse_cells", "cdi_get_coarse_cells",
-           "cdi_set_mg_smooth", "cdi_get_mg_smooth")
+           "cdi_set_mg_smooth", "cdi_get_mg_smooth", "cdi_set_extrapolation",
+           "cdi_get_extrapolation")
 
 
 class cdi_params(C.Structure):
@@ -147,6 +148,10 @@ def lib() -> C.CDLL:
     L.cdi_set_mg_smooth.restype = i32
     L.cdi_get_mg_smooth.argtypes = [vp, P(i32)]
     L.cdi_get_mg_smooth.restype = i32
+    L.cdi_set_extrapolation.argtypes = [vp, i32]
+    L.cdi_set_extrapolation.restype = i32
+    L.cdi_get_extrapolation.argtypes = [vp, P(i32)]
+    L.cdi_get_extrapolation.restype = i32
     L.cdi_graph_stats.argtypes = [vp, P(C.c_int64), P(C.c_int64), P(i32)]
     L.cdi_graph_stats.restype = i32
     L.cdi_tune_bytes.argtypes = [vp]

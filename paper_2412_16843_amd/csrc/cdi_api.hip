@@ -132,7 +132,7 @@ struct Layout {
 
 // Doubles of one instance's step state: phi, u, p and the 8 pressure-history
 // fields (ny * nx each) and v ((ny + 1) * nx).
-size_t snap_doubles(int nx, int ny) { return 12 * (size_t)nx * ny + (size_t)nx; }
+size_t snap_doubles(int nx, int ny) { return (4 + 4 * kHistDepth) * (size_t)nx * ny + (size_t)nx; }
 
 // Carve one instance's arrays out of `base` (device) starting at offset `off`;
 // with base == nullptr only the size is computed.
@@ -178,8 +178,8 @@ size_t carve(const Resolved& R, int ntiles_cell, int ntiles_mg0, char* base, siz
   D.snap = (double*)take(snap_doubles(nx, ny) * 8);
   D.mg_t = take(nc * S);
   D.mg_r0 = take(nc * S);
-  for (int k = 0; k < 4; ++k) D.ph[k] = (double*)take(nc * 8);
-  for (int k = 0; k < 4; ++k) D.ph2[k] = (double*)take(nc * 8);
+  for (int d = 0; d < kHistDepth; ++d)
+    for (int k = 0; k < 4; ++k) D.hp[d][k] = (double*)take(nc * 8);
   D.part = (double*)take((size_t)8 * std::max(ntiles_cell, ntiles_mg0) * 8);
   D.pcg = (PcgScalars*)take(sizeof(PcgScalars));
   D.counters = (unsigned*)take(sizeof(unsigned) * 8 * kCounterStride);
@@ -375,6 +375,7 @@ struct cdi_ctx {
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   cdi_net* net = nullptr;        // learned initial guess (borrowed)
   int hist_steps = 0;            // steps recorded in the per-stage pressure history
+  int extrap_order = kHistDepth - 1;   // highest time-extrapolation order of the guess
   int launch = CDI_LAUNCH_TILED; // how cdi_step enqueues a step
   // graph launch: captured step with a fixed CG budget per solve
   hipStream_t gstream = nullptr;   // capture / replay stream (the caller's may be the null stream)
@@ -616,7 +617,7 @@ cdi_status run_step(cdi_ctx* c) {
     // previous-pressure guess: the same stage of the previous step (linear
     // extrapolation once two steps exist), else the last pressure
     int gm = guess_mode(c);
-    if (gm == 1 && c->hist_steps >= 1) gm = c->hist_steps >= 2 ? 4 : 3;
+    if (gm == 1 && c->hist_steps >= 1) gm = history_mode(c->hist_steps, c->extrap_order);
     cdi_status s = solve_loop<S>(c, gm, k);
     if (s == CDI_ERR_NOCONV) st = s;
     else if (s != CDI_OK) return s;
@@ -661,12 +662,12 @@ void enqueue_solve_fixed(cdi_ctx* c, int guess, int stage, int budget) {
 
 // Copy every instance's step state (fields and per-stage pressure history)
 // to (save) or from its snapshot area.
-// (k_snapshot: phi, u, p, ph[0..3], ph2[0..3] and v one after another.)
+// (k_snapshot: phi, u, p, the history hp[d][stage] and v one after another.)
 cdi_status snapshot(cdi_ctx* c, bool save) {
   size_t most = 0;
   for (int k = 0; k < c->B.n; ++k) {
     const Inst& I = c->B.inst[k];
-    const size_t need = 12 * (size_t)I.nx * I.ny + I.nx;
+    const size_t need = (4 + 4 * kHistDepth) * (size_t)I.nx * I.ny + I.nx;
     if (need > snap_doubles(I.nx, I.ny)) return fail(CDI_ERR_STATE, "snapshot layout exceeds its area");
     most = std::max(most, need);
   }
@@ -718,7 +719,8 @@ cdi_status graph_capture(cdi_ctx* c, int budget) {
     cdi_status st = snapshot(c, true);
     if (st != CDI_OK) return st;
     k_graph_mark<<<(unsigned)ceil_div(B.n, 64), 64, 0, c->stream>>>(c->d_inst, B.n, 1);
-    const int gm = c->guess == CDI_GUESS_ZERO ? 0 : 4;   // history of >= 2 steps exists
+    // the full history of the extrapolation order exists (run_graph_step)
+    const int gm = c->guess == CDI_GUESS_ZERO ? 0 : history_mode(c->extrap_order + 1, c->extrap_order);
     for (int k = 0; k < 4; ++k) {
       const int src = k == 0 ? 0 : (k == 2 ? 2 : 1);
       const int dst = (k == 0 || k == 2) ? 1 : 2;
@@ -772,7 +774,7 @@ cdi_status graph_capture(cdi_ctx* c, int budget) {
 // on the stream path; the latter from the restored snapshot.
 template <typename S>
 cdi_status run_graph_step(cdi_ctx* c) {
-  if (c->hist_steps < 2) return run_step<S>(c);
+  if (c->hist_steps < c->extrap_order + 1) return run_step<S>(c);
   Batch& B = c->B;
   if (!c->gstream) {
     HIPCHK(hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking));
@@ -836,7 +838,7 @@ cdi_status run_persistent(cdi_ctx* c, int nsteps) {
     const int m = std::min(kPersistChunk, nsteps - done);
     timed(c, "persistent", [&] {
       CDI_LAUNCH(c, k_step_persistent<S>, (unsigned)B.n, PNT, c->d_cell_inst, c->d_inst, m,
-                 c->hist_steps, gm, c->rtol, c->maxit, (int)(done > 0));
+                 c->hist_steps, gm, c->extrap_order, c->rtol, c->maxit, (int)(done > 0));
     });
     HIPCHK(hipGetLastError());
     c->hist_steps += m;
@@ -1201,6 +1203,21 @@ cdi_status cdi_get_mg_smooth(cdi_ctx* c, int32_t* nu) {
   return CDI_OK;
 }
 
+cdi_status cdi_set_extrapolation(cdi_ctx* c, int32_t order) {
+  if (!c) return fail(CDI_ERR_ARG, "ctx is NULL");
+  if (order < 0 || order > kHistDepth - 1)
+    return fail(CDI_ERR_ARG, "extrapolation order must be in [0, %d]", kHistDepth - 1);
+  if (order != c->extrap_order) graph_drop(c);   // a captured step holds its guess mode
+  c->extrap_order = order;
+  return CDI_OK;
+}
+
+cdi_status cdi_get_extrapolation(cdi_ctx* c, int32_t* order) {
+  if (!c || !order) return fail(CDI_ERR_ARG, "NULL argument");
+  *order = c->extrap_order;
+  return CDI_OK;
+}
+
 cdi_status cdi_set_coarse_cells(cdi_ctx* c, int32_t cells) {
   if (!c) return fail(CDI_ERR_ARG, "ctx is NULL");
   if (cells < kCoarseCells || cells > (1 << 20))
@@ -1243,8 +1260,9 @@ static cdi_status tune_copy(cdi_ctx* c, char* scratch, bool save) {
   for (int k = 0; k < c->B.n; ++k) {
     const Inst& I = c->B.inst[k];
     const size_t n = (size_t)I.nx * I.ny, nf = n + I.nx;
-    double* bufs[11] = {I.phi, I.u, I.p, I.ph[0], I.ph[1], I.ph[2], I.ph[3],
-                        I.ph2[0], I.ph2[1], I.ph2[2], I.ph2[3]};
+    double* bufs[3 + 4 * kHistDepth] = {I.phi, I.u, I.p};
+    for (int d = 0; d < kHistDepth; ++d)
+      for (int s = 0; s < 4; ++s) bufs[3 + 4 * d + s] = I.hp[d][s];
     double* base = (double*)(scratch + off);
     size_t pos = 0;
     for (double* b : bufs) {

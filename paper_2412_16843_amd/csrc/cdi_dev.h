@@ -11,6 +11,7 @@
 namespace cdi {
 
 constexpr int kMaxLevels = 14;
+constexpr int kHistDepth = 4;    // steps of per-stage pressure kept for the initial guess
 constexpr int kNT = 256;          // threads per block of every tiled kernel
 constexpr double kDeltaN = 1e-12; // normal-vector regularisation: n = G/(|G| + dN)
 constexpr double kDeltaPsi = 1e-12;
@@ -81,8 +82,7 @@ struct Inst {
   // pressure (FP64 CG vectors)
   double* b; double* x; double* rr; double* rr2; double* d0; double* d1; double* q;
   double* zf;                          // FP64 copy of level-0 correction (mixed path)
-  double* ph[4];                       // pressure of each RK stage in the previous step
-  double* ph2[4];                      // ... and in the step before
+  double* hp[kHistDepth][4];           // pressure of each RK stage d + 1 steps back (d = 0: the last step)
   double* part;                        // reduction partials, [8][ntiles]
   PcgScalars* pcg;
   unsigned* counters;                  // [8 kinds][kCounterStride] arrival counters
@@ -110,6 +110,15 @@ __device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >=
 // double-precision reciprocal estimate (off by at most one) corrected by one
 // exact integer step (the GPU has no integer divide instruction; the generic
 // sequence costs tens of operations).
+// Initial-guess mode of a solve whose RK stage has hs >= 1 steps of pressure
+// history: 3 + q, where q is the order of the polynomial extrapolation in
+// time through the last q + 1 steps (0 the last step's pressure, 1 linear,
+// 2 quadratic, 3 cubic), the highest that hs supports, at most max_order.
+__host__ __device__ inline int history_mode(int hs, int max_order) {
+  const int q = hs - 1 < max_order ? hs - 1 : max_order;
+  return 3 + q;
+}
+
 struct FastDiv {
   int d;
   double inv;

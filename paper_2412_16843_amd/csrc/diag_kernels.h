@@ -184,24 +184,23 @@ __global__ void k_graph_mark(const Inst* __restrict__ insts, int n, int begin) {
 }
 
 // Step snapshot of instance blockIdx.y: the fields phi, u, p, the stage
-// pressure histories ph[0..3], ph2[0..3] (n values each) and v (n + nx) stored
+// pressure history hp[d][stage] (d-major; n values each) and v (n + nx) stored
 // one after another in I.snap (save), or copied back from it.  One launch
 // instead of a copy per field.
 __global__ void __launch_bounds__(kNT) k_snapshot(const Inst* __restrict__ insts, int save) {
   const Inst& I = insts[blockIdx.y];
   const size_t n = (size_t)I.nx * I.ny;
-  const size_t total = 12 * n + I.nx;
+  constexpr size_t kF = 3 + 4 * kHistDepth;   // fields of n values before v
+  const size_t total = (kF + 1) * n + I.nx;
   for (size_t e = (size_t)blockIdx.x * kNT + threadIdx.x; e < total; e += (size_t)gridDim.x * kNT) {
-    const size_t f = e / n < 11 ? e / n : 11;
+    const size_t f = e / n < kF ? e / n : kF;
     const size_t o = e - f * n;
     double* fld;
     switch (f) {
       case 0: fld = I.phi; break;
       case 1: fld = I.u; break;
       case 2: fld = I.p; break;
-      case 3: case 4: case 5: case 6: fld = I.ph[f - 3]; break;
-      case 7: case 8: case 9: case 10: fld = I.ph2[f - 7]; break;
-      default: fld = I.v; break;
+      default: fld = f < kF ? I.hp[(f - 3) / 4][(f - 3) % 4] : I.v; break;
     }
     if (save) I.snap[e] = fld[o];
     else fld[o] = I.snap[e];

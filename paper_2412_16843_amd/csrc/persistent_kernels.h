@@ -128,7 +128,7 @@ __device__ int persist_solve(const Inst& I, PersistLds<S>& L, int guess,
 template <typename S>
 __global__ void __launch_bounds__(PNT) k_step_persistent(const Tile* __restrict__ tiles,
                                                          const Inst* __restrict__ insts,
-                                                         int nsteps, int hist, int guess,
+                                                         int nsteps, int hist, int guess, int order,
                                                          double rtol, int maxit, int accumulate) {
   __shared__ PersistLds<S> L;
   const Inst& I = insts[blockIdx.x];
@@ -183,7 +183,7 @@ __global__ void __launch_bounds__(PNT) k_step_persistent(const Tile* __restrict_
       __syncthreads();
       int gm = guess;
       const int hs = hist + s;
-      if (gm == 1 && hs >= 1) gm = hs >= 2 ? 4 : 3;
+      if (gm == 1 && hs >= 1) gm = history_mode(hs, order);
       bool zero, conv;
       double xmean, relres;
       const int it = persist_solve<S>(I, L, gm, k, bmean, rtol, maxit, zero, xmean, relres, conv);

@@ -188,14 +188,18 @@ __device__ __forceinline__ double apply_K(const Inst& I, const double* __restric
 
 // f = -(b - mean b); x0 = guess or 0; r = f - K x0.  guess 1: the previous
 // pressure p; 2: the fitted combination of p and the learned pressure g held
-// in zf; 3: the same RK stage's pressure in the previous step (ph[stage]);
-// 4: its linear extrapolation in time 2 ph[stage] - ph2[stage].
+// in zf; 3..6: the same RK stage's pressure extrapolated in time from the
+// last 1..4 steps (constant, linear, quadratic, cubic polynomial through
+// equally spaced values: weights 1; 2, -1; 3, -3, 1; 4, -6, 4, -1).
 __device__ __forceinline__ double guess_value(const Inst& I, int guess, int stage, size_t o) {
   switch (guess) {
     case 1: return I.p[o];
     case 2: return I.pcg->gscale * I.p[o] + I.pcg->gscale2 * I.zf[o];
-    case 3: return I.ph[stage][o];
-    case 4: return 2.0 * I.ph[stage][o] - I.ph2[stage][o];
+    case 3: return I.hp[0][stage][o];
+    case 4: return 2.0 * I.hp[0][stage][o] - I.hp[1][stage][o];
+    case 5: return 3.0 * (I.hp[0][stage][o] - I.hp[1][stage][o]) + I.hp[2][stage][o];
+    case 6: return 4.0 * (I.hp[0][stage][o] + I.hp[2][stage][o]) - 6.0 * I.hp[1][stage][o] -
+                   I.hp[3][stage][o];
     default: return 0.0;
   }
 }
@@ -517,7 +521,8 @@ __global__ void __launch_bounds__(kNT) k_pcg_xmean(const Tile* __restrict__ tile
 struct ProjIn {
   double xc, xw, xs;       // pressure iterate: cell, west, south
   double us, vs, ax, ay;   // u*, v*, face coefficients
-  double hist, ph;         // stage pressure history; next phase field (final stage)
+  double hist[kHistDepth - 1];   // stage pressure history, newest first
+  double ph;                     // next phase field (final stage)
 };
 
 __device__ __forceinline__ ProjIn project_load(const Inst& I, int final_stage,
@@ -533,7 +538,8 @@ __device__ __forceinline__ ProjIn project_load(const Inst& I, int final_stage,
   v.ax = I.ax0[o];
   v.vs = j >= 1 ? I.vstar[o] : 0.0;
   v.ay = j >= 1 ? I.ay0[o] : 0.0;
-  v.hist = stage >= 0 ? I.ph[stage][o] : 0.0;
+#pragma unroll
+  for (int d = 0; d + 1 < kHistDepth; ++d) v.hist[d] = stage >= 0 ? I.hp[d][stage][o] : 0.0;
   v.ph = final_stage ? ph[o] : 0.0;
   return v;
 }
@@ -551,8 +557,9 @@ __device__ __forceinline__ void project_store(const Inst& I, const ProjIn& v, do
   const double pn = v.xc - (zero ? 0.0 : xmean);
   I.p[o] = pn;
   if (stage >= 0) {   // pressure history of this RK stage (for the next step's guess)
-    I.ph2[stage][o] = v.hist;
-    I.ph[stage][o] = pn;
+#pragma unroll
+    for (int d = 1; d < kHistDepth; ++d) I.hp[d][stage][o] = v.hist[d - 1];
+    I.hp[0][stage][o] = pn;
   }
   if (final_stage) I.phi[o] = v.ph;
 }

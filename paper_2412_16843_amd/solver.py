@@ -139,6 +139,16 @@ class CDISolver:
         L.check(self.lib.cdi_get_mg_smooth(self.ctx, C.byref(m)))
         return m.value
 
+    def set_extrapolation(self, order: int) -> None:
+        """Order (0..3) of the time extrapolation of the previous steps'
+        pressure that starts each solve."""
+        L.check(self.lib.cdi_set_extrapolation(self.ctx, int(order)))
+
+    def get_extrapolation(self) -> int:
+        m = C.c_int32()
+        L.check(self.lib.cdi_get_extrapolation(self.ctx, C.byref(m)))
+        return m.value
+
     def set_coarse_cells(self, cells: int) -> None:
         """Levels with at most `cells` cells run in the one-block coarse kernel."""
         L.check(self.lib.cdi_set_coarse_cells(self.ctx, int(cells)))
