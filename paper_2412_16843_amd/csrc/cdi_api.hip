@@ -360,6 +360,7 @@ struct cdi_ctx {
   std::vector<double> mass0;
   PcgScalars* h_pcg = nullptr;   // pinned
   int pred_iters = 4;
+  int pred_stage[4] = {0, 0, 0, 0};   // per RK stage: CG iterations of its last solve
   int wide_rows = 4;             // rows per thread of the wide-tile kernels (1 or 4)
   int nu = 1;                    // red-black sweep pairs of the V-cycle
   int wide_rows_pick = 4;        // autotuner: faster tiled shape so far
@@ -510,7 +511,10 @@ cdi_status solve_loop(cdi_ctx* c, int guess, int stage) {
   // with a steady count that is the one wait per solve; an over-estimate
   // costs only early-exit launches
   int it = 0;
-  int next_check = std::max(1, c->pred_iters);
+  // (each RK stage keeps its own count: the four stages' solves differ,
+  // while one stage's count changes slowly from step to step)
+  int& pred = c->pred_stage[stage & 3];
+  int next_check = std::max(1, pred > 0 ? pred : c->pred_iters);
   bool all_done = false;
   while (it < c->maxit) {
     const int par = it & 1;
@@ -558,6 +562,7 @@ cdi_status solve_loop(cdi_ctx* c, int guess, int stage) {
     if (!c->h_pcg[k].converged) noconv = true;
   }
   c->pred_iters = std::max(1, maxi);
+  pred = std::max(1, maxi);
   HIPCHK(hipGetLastError());
   if (noconv) return fail(CDI_ERR_NOCONV, "pressure solve did not reach rtol within maxit");
   return CDI_OK;
@@ -629,6 +634,8 @@ cdi_status run_step(cdi_ctx* c) {
   }
   (void)dt;
   c->hist_steps += 1;
+  // the graph launch sizes its fixed budget from the step's largest count
+  c->pred_iters = *std::max_element(c->pred_stage, c->pred_stage + 4);
   HIPCHK(hipGetLastError());
   return st;
 }
@@ -1296,6 +1303,8 @@ cdi_status cdi_tune(cdi_ctx* c, int32_t trial_steps, void* scratch, size_t scrat
   const double t0 = c->t;
   const long step0 = c->step;
   const int hist0 = c->hist_steps, pred0 = c->pred_iters;
+  int pred_stage0[4];
+  std::copy(c->pred_stage, c->pred_stage + 4, pred_stage0);
   const std::vector<int> it0 = c->last_iters, conv0 = c->last_conv;
   const std::vector<double> rel0 = c->last_relres;
   const std::string timed0 = c->timed;
@@ -1360,9 +1369,11 @@ cdi_status cdi_tune(cdi_ctx* c, int32_t trial_steps, void* scratch, size_t scrat
     cdi_status rs = tune_copy(c, sc, false);
     if (rs != CDI_OK) return rs;
     c->t = t0; c->step = step0; c->hist_steps = hist0; c->pred_iters = pred0;
+    std::copy(pred_stage0, pred_stage0 + 4, c->pred_stage);
   }
   HIPCHK(hipStreamSynchronize(c->stream));
   c->t = t0; c->step = step0; c->hist_steps = hist0; c->pred_iters = pred0;
+  std::copy(pred_stage0, pred_stage0 + 4, c->pred_stage);
   c->last_iters = it0; c->last_conv = conv0; c->last_relres = rel0;
   c->timed = timed0;
   if (st != CDI_OK) {
