@@ -648,8 +648,12 @@ __global__ void __launch_bounds__(kNT) k_mg_down(const Tile* __restrict__ tiles,
   constexpr int PY = FY + 2, PX = FX + 2;                // residual, halo 1
   __shared__ S s_r[RY * RX], s_z[RY * RX];
   __shared__ S s_ax[RY * (RX + 1)], s_ay[(RY + 1) * RX];
-  __shared__ S s_rp[PY * PX];
   __shared__ double sh[2 * kNT / 64];
+  // the residual for the restriction replaces the right-hand side once every
+  // read of it is done (one LDS array less: 4 blocks per CU instead of 3 at
+  // V(2,2) FP64)
+  static_assert(PY * PX <= RY * RX, "residual fits the right-hand-side array");
+  S* const s_rp = s_r;
   const Tile t = tiles[blockIdx.x];
   const Inst& I = insts[t.inst];
   if (I.pcg->done) return;
@@ -785,23 +789,33 @@ __global__ void __launch_bounds__(kNT) k_mg_down(const Tile* __restrict__ tiles,
     const int j = j0 + ty, i = i0 + tx;
     if (j < ny && i < nx) ((S*)L.z)[(size_t)j * nx + i] = s_z[(ty + H) * RX + (tx + H)];
   }
-  // residual r - K z on the tile + halo 1
+  // residual r - K z on the tile + halo 1: into registers, then (after every
+  // thread's reads of s_r) into s_rp = s_r
+  constexpr int NR = (PY * PX + kNT - 1) / kNT;
+  S rpl[NR];
 #pragma unroll
-  for (int e = 0; e < (PY * PX + kNT - 1) / kNT; ++e) {
+  for (int e = 0; e < NR; ++e) {
     const int k = threadIdx.x + e * kNT;
-    if (k >= PY * PX) break;
-    const int pj = k / PX, pi = k - pj * PX;
-    const int rj = pj + H - 1, ri = pi + H - 1;
-    const int c = rj * RX + ri;
     S rp = 0;
-    if (valid(rj)) {
-      const S aw = s_ax[rj * (RX + 1) + ri], ae = s_ax[rj * (RX + 1) + ri + 1];
-      const S as = s_ay[rj * RX + ri], an = s_ay[(rj + 1) * RX + ri];
-      const S zc = s_z[c];
-      rp = s_r[c] - (aw * (zc - s_z[c - 1]) + ae * (zc - s_z[c + 1]) + as * (zc - s_z[c - RX]) +
-                     an * (zc - s_z[c + RX]));
+    if (k < PY * PX) {
+      const int pj = k / PX, pi = k - pj * PX;
+      const int rj = pj + H - 1, ri = pi + H - 1;
+      const int c = rj * RX + ri;
+      if (valid(rj)) {
+        const S aw = s_ax[rj * (RX + 1) + ri], ae = s_ax[rj * (RX + 1) + ri + 1];
+        const S as = s_ay[rj * RX + ri], an = s_ay[(rj + 1) * RX + ri];
+        const S zc = s_z[c];
+        rp = s_r[c] - (aw * (zc - s_z[c - 1]) + ae * (zc - s_z[c + 1]) +
+                       as * (zc - s_z[c - RX]) + an * (zc - s_z[c + RX]));
+      }
     }
-    s_rp[k] = rp;
+    rpl[e] = rp;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < NR; ++e) {
+    const int k = threadIdx.x + e * kNT;
+    if (k < PY * PX) s_rp[k] = rpl[e];
   }
   __syncthreads();
   // restriction to the coarse tile
