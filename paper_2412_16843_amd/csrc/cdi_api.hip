@@ -490,6 +490,14 @@ void launch_coef(cdi_ctx* c) {
   timed(c, "mg_coef", [&] { CDI_LAUNCH(c, k_coarse_inv<S>, (unsigned)c->B.n, kCoarseNT, c->d_inst); });
 }
 
+// True if a solve of the batch met a NaN or Inf (host copies of the CG
+// scalars must be current).
+bool any_nonfinite(const cdi_ctx* c) {
+  for (int k = 0; k < c->B.n; ++k)
+    if (c->h_pcg[k].nonfinite) return true;
+  return false;
+}
+
 // Flexible-CG loop after the right-hand side is in place.  Returns NOCONV
 // if an instance stopped at maxit.
 template <typename S>
@@ -564,6 +572,7 @@ cdi_status solve_loop(cdi_ctx* c, int guess, int stage) {
   c->pred_iters = std::max(1, maxi);
   pred = std::max(1, maxi);
   HIPCHK(hipGetLastError());
+  if (any_nonfinite(c)) return fail(CDI_ERR_NONFINITE, "non-finite value in the pressure solve");
   if (noconv) return fail(CDI_ERR_NOCONV, "pressure solve did not reach rtol within maxit");
   return CDI_OK;
 }
@@ -829,6 +838,7 @@ cdi_status run_graph_step(cdi_ctx* c) {
   c->pred_iters = std::max(1, maxi);
   c->graph_slack = maxi + 2 <= c->graph_budget ? c->graph_slack + 1 : 0;
   c->hist_steps += 1;
+  if (any_nonfinite(c)) return fail(CDI_ERR_NONFINITE, "non-finite value in the pressure solve");
   if (noconv) return fail(CDI_ERR_NOCONV, "pressure solve did not reach rtol within maxit");
   return CDI_OK;
 }
@@ -863,6 +873,7 @@ cdi_status run_persistent(cdi_ctx* c, int nsteps) {
     if (c->h_pcg[k].nfail) noconv = true;
   }
   c->pred_iters = std::max(1, maxi);
+  if (any_nonfinite(c)) return fail(CDI_ERR_NONFINITE, "non-finite value in the pressure solve");
   if (noconv) return fail(CDI_ERR_NOCONV, "pressure solve did not reach rtol within maxit");
   return CDI_OK;
 }

@@ -51,7 +51,7 @@ struct PcgScalars {
   int max_iters;            // persistent path: largest iteration count
   int miss;                 // graph path: a solve of the step ended unconverged
   int step_iters;           // graph path: largest iteration count of the step
-  int pad;
+  int nonfinite;            // 1 once a norm of the solve was NaN or Inf (the solve stops)
 };
 
 struct Inst {

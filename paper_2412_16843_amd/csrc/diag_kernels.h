@@ -162,6 +162,7 @@ __global__ void __launch_bounds__(kNT) k_solve_setup(const Tile* __restrict__ ti
       P->bmean = s / n;
       P->brms = sqrt(fmax(s2 / n - P->bmean * P->bmean, 0.0));
       P->done = 0; P->iters = 0; P->first = 1; P->converged = 0; P->zero_rhs = 0;
+      P->nonfinite = 0;
       P->rtol = rtol; P->maxit = maxit;
     }
   }

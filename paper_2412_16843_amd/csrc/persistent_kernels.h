@@ -193,6 +193,7 @@ __global__ void __launch_bounds__(PNT) k_step_persistent(const Tile* __restrict_
         P->bmean = bmean;
         P->iters = it;
         P->relres = relres;
+        P->nonfinite = isfinite(relres) ? 0 : 1;
         P->converged = conv ? 1 : 0;
         P->zero_rhs = zero ? 1 : 0;
         P->xmean = xmean;

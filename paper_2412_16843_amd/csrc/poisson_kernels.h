@@ -168,6 +168,7 @@ __global__ void __launch_bounds__(kNT) k_rhs(const Tile* __restrict__ tiles,
       P->bmean = s / n;
       P->brms = sqrt(fmax(s2 / n - P->bmean * P->bmean, 0.0));
       P->done = 0; P->iters = 0; P->first = 1; P->converged = 0; P->zero_rhs = 0;
+      P->nonfinite = 0;
       P->rtol = rtol; P->maxit = maxit;
     }
   }
@@ -321,7 +322,9 @@ __global__ void __launch_bounds__(kNT) k_pcg_init(const Tile* __restrict__ tiles
       PcgScalars* P = I.pcg;
       P->fnorm = sqrt(ff);
       P->rr = rr;
-      if (ff == 0.0) {          // b = 0: the mean-free solution is p = 0
+      if (!isfinite(ff) || !isfinite(rr)) {   // NaN / Inf in b or the guess: stop
+        P->relres = NAN; P->done = 1; P->converged = 0; P->nonfinite = 1;
+      } else if (ff == 0.0) {   // b = 0: the mean-free solution is p = 0
         P->relres = 0.0; P->done = 1; P->converged = 1; P->zero_rhs = 1;
       } else {
         P->relres = sqrt(rr) / P->fnorm;
@@ -486,7 +489,8 @@ __device__ __forceinline__ void pcg_stop_test(PcgScalars* P, double rr, double s
   P->xmean = sx / n;
   P->iters += 1;
   P->relres = sqrt(rr) / P->fnorm;
-  if (P->relres <= P->rtol) { P->done = 1; P->converged = 1; }
+  if (!isfinite(rr)) { P->done = 1; P->nonfinite = 1; }
+  else if (P->relres <= P->rtol) { P->done = 1; P->converged = 1; }
   else if (P->iters >= P->maxit) { P->done = 1; }
 }
 

@@ -78,7 +78,9 @@ def test_workspace_and_default_dt_host_only():
 @pytest.mark.parametrize("kw,status", [
     (dict(nx=63), -2), (dict(ny=6), -2), (dict(eps=0.0), -1), (dict(theta_eq=0.0), -1),
     (dict(theta_eq=math.pi), -1), (dict(beta1=0.0), -1), (dict(gamma=-1.0), -1),
-    (dict(rho2=0.0), -1), (dict(lx=3.0), -2), (dict(dt=-1.0), -1)])
+    (dict(rho2=0.0), -1), (dict(lx=3.0), -2), (dict(dt=-1.0), -1),
+    # empty, negative and below-minimum grids
+    (dict(nx=0), -2), (dict(ny=0), -2), (dict(nx=-8), -2), (dict(nx=2, ny=2), -2)])
 def test_invalid_parameters_rejected_before_device_work(kw, status):
     L = _lib()
     lib = L.lib()
