@@ -165,14 +165,20 @@ cdi_status cdi_init_batch(const cdi_params* params, int32_t n, const cdi_fields*
 /* Advance every instance by nsteps RK4 steps (4 stage evaluations and 4
  * projections each).  Returns CDI_ERR_NOCONV if a pressure solve did not reach
  * poisson_rtol within poisson_maxit (the fields then hold the best iterate);
- * CDI_ERR_NONFINITE if a non-finite value was detected. */
+ * CDI_ERR_NONFINITE if a non-finite value was detected: a solve whose
+ * right-hand side or residual norm is NaN or Inf stops at once and the step
+ * returns after that stage (the fields are then not a valid state). */
 cdi_status cdi_step(cdi_ctx* ctx, int32_t nsteps);
 
 /* Standalone pressure solve of instance 0 with the density of its current
  * phase field: sum_faces (p_nb - p)/(rho_f h^2) = b - mean(b).  b: device,
  * ny*nx (NULL = the right-hand side of the last projection); p: device,
  * ny*nx, in: initial guess when params.guess == CDI_GUESS_PREV, out: the
- * mean-free solution.  info may be NULL. */
+ * mean-free solution.  info may be NULL.  Returns CDI_ERR_NOCONV when
+ * poisson_maxit iterations did not reach poisson_rtol (p holds the last
+ * iterate, info the iterations and residual), CDI_ERR_NONFINITE when b (or
+ * the residual) is not finite; a right-hand side whose mean-free part is
+ * zero gives p = 0 without an iteration. */
 cdi_status cdi_solve_pressure(cdi_ctx* ctx, const double* b, double* p, cdi_solve_info* info);
 
 /* Diagnostics of instance `idx` for its current state (FP64 reductions on the
