@@ -50,7 +50,7 @@
 extern "C" {
 #endif
 
-#define CDI_ABI_VERSION 1
+#define CDI_ABI_VERSION 2
 
 typedef enum {
   CDI_OK = 0,
@@ -96,6 +96,13 @@ typedef struct {
   int32_t mg_smooth;     /* red-black Gauss-Seidel sweep pairs before and after the
                             coarse correction on every level: 1 or 2; 0 -> 1; larger
                             values return CDI_ERR_ARG; equal across a batch           */
+  double gamma_factor;   /* > 0: the regularisation velocity of each step is
+                            min(gamma, gamma_factor * max |u|, |v| over the faces of
+                            the state the step starts from), the paper's rule
+                            gamma = 2.5 |u|_max (Sec. 5); gamma is then its upper
+                            bound, the value the time step of dt == 0 is sized for.
+                            0: gamma fixed.  < 0 returns CDI_ERR_ARG.  Not available
+                            with the persistent launch (CDI_ERR_ARG there).          */
 } cdi_params;
 
 /* Device pointers of one instance's state, layouts as above (caller-owned,

@@ -367,9 +367,25 @@ def initial_state(phi0: np.ndarray) -> State:
                  np.zeros((ny, nx)))
 
 
+def step_gamma(u: np.ndarray, v: np.ndarray, p) -> float:
+    """Regularisation velocity of a step that starts from velocities (u, v).
+    The paper sets gamma = 2.5 |u|_max (Sec. 5, drop and Couette cases); with
+    gamma_factor > 0 it is read here as gamma_factor times the largest face
+    velocity magnitude |u| or |v| of the starting state, bounded above by the
+    fixed gamma (the value the time step is sized for).  gamma_factor = 0
+    keeps gamma fixed."""
+    f = getattr(p, "gamma_factor", 0.0)
+    if f <= 0.0:
+        return p.gamma
+    return min(p.gamma, f * max(float(np.abs(u).max()), float(np.abs(v).max())))
+
+
 def step(s: State, p, solver=None) -> State:
     """One RK4 step (Sec. 4) of the coupled CDI / momentum system with a
-    projection after every stage and after the final combination."""
+    projection after every stage and after the final combination; gamma is
+    held for the whole step (step_gamma)."""
+    if getattr(p, "gamma_factor", 0.0) > 0.0:
+        p = p.replace(gamma=step_gamma(s.u, s.v, p), gamma_factor=0.0)
     dt = p.dt
     phi0, u0, v0 = s.phi, s.u, s.v
     rfx0, rfy0 = face_rho(phi0, p)

@@ -12,7 +12,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libcdi.so")
 
-CDI_ABI_VERSION = 1
+CDI_ABI_VERSION = 2
 STATUS = {0: "CDI_OK", -1: "CDI_ERR_ARG", -2: "CDI_ERR_SHAPE", -3: "CDI_ERR_DEVICE",
           -4: "CDI_ERR_NOCONV", -5: "CDI_ERR_NONFINITE", -6: "CDI_ERR_STATE"}
 SLIP = {"1A": 0, "1B": 1, "2A": 2, "2B": 3, "3A": 4, "3B": 5, "4A": 6, "4B": 7}
@@ -41,7 +41,8 @@ class cdi_params(C.Structure):
                 ("u_wall_bot", C.c_double), ("u_wall_top", C.c_double), ("dt", C.c_double),
                 ("cfl", C.c_double), ("slip_model", C.c_int32), ("precision", C.c_int32),
                 ("guess", C.c_int32), ("poisson_rtol", C.c_double),
-                ("poisson_maxit", C.c_int32), ("mg_smooth", C.c_int32)]
+                ("poisson_maxit", C.c_int32), ("mg_smooth", C.c_int32),
+                ("gamma_factor", C.c_double)]
 
 
 class cdi_fields(C.Structure):
@@ -187,4 +188,5 @@ def make_params(p, precision: str = "fp64", guess: str = "prev", rtol: float = 0
         mu1=p.mu1, mu2=p.mu2, beta1=p.beta1, beta2=p.beta2, u_wall_bot=p.u_wall_bot,
         u_wall_top=p.u_wall_top, dt=p.dt, cfl=0.0, slip_model=SLIP[p.slip_model],
         precision=CDI_MIXED if precision == "mixed" else CDI_FP64, guess=GUESS[guess],
-        poisson_rtol=rtol, poisson_maxit=maxit, mg_smooth=mg_smooth)
+        poisson_rtol=rtol, poisson_maxit=maxit, mg_smooth=mg_smooth,
+        gamma_factor=getattr(p, "gamma_factor", 0.0))

@@ -76,6 +76,7 @@ cdi_status resolve(const cdi_params* in, Resolved& r) {
   if (std::fabs(hx - hy) > 1e-12 * hx) return fail(CDI_ERR_SHAPE, "lx/nx=%g != ly/ny=%g", hx, hy);
   if (!(p.eps > 0)) return fail(CDI_ERR_ARG, "eps must be > 0");
   if (!(p.gamma > 0)) return fail(CDI_ERR_ARG, "gamma must be > 0");
+  if (!(p.gamma_factor >= 0)) return fail(CDI_ERR_ARG, "gamma_factor must be >= 0");
   if (!(p.sigma >= 0)) return fail(CDI_ERR_ARG, "sigma must be >= 0");
   if (!(p.theta_eq > 0 && p.theta_eq < M_PI)) return fail(CDI_ERR_ARG, "theta_eq must be in (0, pi)");
   if (!(p.rho1 > 0 && p.rho2 > 0)) return fail(CDI_ERR_ARG, "densities must be > 0");
@@ -333,6 +334,7 @@ void fill_inst(const Resolved& R, const cdi_fields& f, Inst& I) {
   I.mixed = p.precision == CDI_MIXED;
   I.h = R.h; I.inv_h = 1.0 / R.h;
   I.eps = p.eps; I.gamma = p.gamma; I.sigma = p.sigma; I.cos_eq = std::cos(p.theta_eq);
+  I.gamma_factor = p.gamma_factor;
   I.rho1 = p.rho1; I.rho2 = p.rho2; I.mu1 = p.mu1; I.mu2 = p.mu2;
   I.beta1 = p.beta1; I.beta2 = p.beta2;
   I.uw_bot = p.u_wall_bot; I.uw_top = p.u_wall_top;
@@ -354,6 +356,7 @@ struct cdi_ctx {
   std::vector<Tile*> d_mg;
   bool mixed = false;
   bool uniform_rho = true;
+  bool dyn_gamma = false;         // an instance recomputes gamma every step
   bool coef_ready = false;
   double t = 0.0;
   long step = 0;
@@ -607,6 +610,7 @@ cdi_status run_step(cdi_ctx* c) {
   const unsigned nwide = (unsigned)B.wide.size();
   const double dt = B.R[0].dt;   // every instance carries its own dt in Inst
   cdi_status st = CDI_OK;
+  if (c->dyn_gamma) k_gamma_step<<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst);
   for (int k = 0; k < 4; ++k) {
     const int src = k == 0 ? 0 : (k == 2 ? 2 : 1);
     const int dst = (k == 0 || k == 2) ? 1 : 2;
@@ -735,6 +739,7 @@ cdi_status graph_capture(cdi_ctx* c, int budget) {
     cdi_status st = snapshot(c, true);
     if (st != CDI_OK) return st;
     k_graph_mark<<<(unsigned)ceil_div(B.n, 64), 64, 0, c->stream>>>(c->d_inst, B.n, 1);
+    if (c->dyn_gamma) k_gamma_step<<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst);
     // the full history of the extrapolation order exists (run_graph_step)
     const int gm = c->guess == CDI_GUESS_ZERO ? 0 : history_mode(c->extrap_order + 1, c->extrap_order);
     for (int k = 0; k < 4; ++k) {
@@ -936,6 +941,7 @@ cdi_status cdi_init_batch(const cdi_params* params, int32_t n, const cdi_fields*
   for (int k = 0; k < n; ++k) {
     fill_inst(Rs[k], fields[k], B.inst[k]);
     if (Rs[k].p.rho1 != Rs[k].p.rho2) c->uniform_rho = false;
+    if (Rs[k].p.gamma_factor > 0) c->dyn_gamma = true;
   }
   batch_bytes(Rs, &B, c->ws);
   // wide tiles: 4 rows per thread once the batch has enough cells to fill
@@ -1001,6 +1007,8 @@ cdi_status cdi_init_batch(const cdi_params* params, int32_t n, const cdi_fields*
   const size_t hdr = (size_t)((char*)B.inst[0].phi_a - c->ws);
   if ((e = hipMemsetAsync(c->ws + hdr, 0, need - hdr, c->stream)) != hipSuccess)
     return cleanup_fail(e, "clear workspace");
+  k_gamma_init<<<(unsigned)ceil_div(n, 64), 64, 0, c->stream>>>(c->d_inst, n);
+  if ((e = hipGetLastError()) != hipSuccess) return cleanup_fail(e, "gamma init");
   if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return cleanup_fail(e, "init sync");
   if ((e = hipEventCreate(&c->ev0)) != hipSuccess) return cleanup_fail(e, "event");
   if ((e = hipEventCreate(&c->ev1)) != hipSuccess) return cleanup_fail(e, "event");
@@ -1097,6 +1105,8 @@ cdi_status cdi_eval_rhs(cdi_ctx* c, double* l_phi, double* l_mx, double* l_my, d
   const unsigned ncell = (unsigned)B.cell.size();
   const Inst& I = B.inst[0];
   const size_t nc = (size_t)I.nx * I.ny;
+  // the regularisation velocity of a step that would start from this state
+  if (c->dyn_gamma) k_gamma_step<<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst);
   if (c->mixed) {
     k_phase_prep<float, 1><<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, 0);
     k_stage<float><<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, -1, 0, 0, 0.0, 0.0, 1);
@@ -1346,7 +1356,8 @@ cdi_status cdi_tune(cdi_ctx* c, int32_t trial_steps, void* scratch, size_t scrat
   for (Cand& cd : cands) {
     const bool learned = c->guess == CDI_GUESS_LEARNED && c->net;
     if (cd.launch != CDI_LAUNCH_TILED && learned) continue;
-    if (cd.launch == CDI_LAUNCH_PERSISTENT && max_cells > kPersistTuneCells) continue;
+    if (cd.launch == CDI_LAUNCH_PERSISTENT && (max_cells > kPersistTuneCells || c->dyn_gamma))
+      continue;
     if (cd.launch != CDI_LAUNCH_TILED) {   // the fastest tiled shape
       cd.rows = c->wide_rows_pick;
       cd.coarse = c->coarse_cells_pick;
@@ -1406,6 +1417,8 @@ cdi_status cdi_set_launch(cdi_ctx* c, int32_t mode) {
   if (!c) return fail(CDI_ERR_ARG, "ctx is NULL");
   if (mode != CDI_LAUNCH_TILED && mode != CDI_LAUNCH_PERSISTENT && mode != CDI_LAUNCH_GRAPH)
     return fail(CDI_ERR_ARG, "bad launch mode %d", mode);
+  if (mode == CDI_LAUNCH_PERSISTENT && c->dyn_gamma)
+    return fail(CDI_ERR_ARG, "the persistent launch keeps gamma fixed (gamma_factor > 0)");
   c->launch = mode;
   return CDI_OK;
 }

@@ -39,6 +39,7 @@ struct PcgScalars {
   double rr, fnorm, relres;
   double bmean, xmean, brms;
   double gscale, gscale2;   // x0 = gscale p + gscale2 g for the learned guess g
+  double gamma_step;        // regularisation velocity of the current step
   double rtol;
   int done;                 // 1 once converged (or maxit reached): kernels exit early
   int iters;
@@ -64,6 +65,7 @@ struct Inst {
   int first_tile, ntiles;   // tiles of level 0 in the cell tile list
   int first_wide, nwide;    // tiles of level 0 in the wide tile list
   double h, inv_h, eps, gamma, sigma, cos_eq;
+  double gamma_factor;      // > 0: gamma of a step = min(gamma, gamma_factor max|u|)
   double rho1, rho2, mu1, mu2, beta1, beta2, uw_bot, uw_top, dt;
   // caller state (FP64)
   double* phi; double* u; double* v; double* p;
@@ -214,6 +216,21 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* sh /* >= NV*N
 // Fixed-order block sum of NV values per thread, result in every thread
 // (each thread adds the per-wave sums in the same order).  One barrier; the
 // caller places a barrier between the last read of `sh` and its next use.
+// Maximum of v over the block, in every thread (max is exact in any order).
+// sh holds >= NT / 64 doubles; every thread must call it.
+template <int NT = kNT>
+__device__ __forceinline__ double block_max(double v, double* sh) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double m = sh[0];
+#pragma unroll
+  for (int w = 1; w < NT / 64; ++w) m = fmax(m, sh[w]);
+  __syncthreads();
+  return m;
+}
+
 template <int NV, int NT = kNT>
 __device__ __forceinline__ void block_allsum(double (&v)[NV], double* sh /* >= NV*NT/64 */) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;

@@ -168,6 +168,41 @@ __global__ void __launch_bounds__(kNT) k_solve_setup(const Tile* __restrict__ ti
   }
 }
 
+// Regularisation velocity of each instance's next step.  Fixed gamma:
+// gamma itself (k_gamma_init, once).  gamma_factor > 0 (the paper's gamma =
+// 2.5 |u|_max, Sec. 5): min(gamma, gamma_factor * max |u|, |v|) over the
+// faces of the state the step starts from -- the largest value per cell tile,
+// then over the tiles' partials by the last block (k_gamma_step, at the
+// start of every step).
+__global__ void k_gamma_init(const Inst* __restrict__ insts, int n) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) insts[k].pcg->gamma_step = insts[k].gamma;
+}
+
+__global__ void __launch_bounds__(kNT) k_gamma_step(const Tile* __restrict__ tiles,
+                                                    const Inst* __restrict__ insts) {
+  __shared__ double sh[kNT / 64];
+  const Tile t = tiles[blockIdx.x];
+  const Inst& I = insts[t.inst];
+  if (!(I.gamma_factor > 0.0)) return;   // the same for every block of the instance
+  const int nx = I.nx, ny = I.ny;
+  const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+  const int i = t.i0 + tx, j = t.j0 + ty;
+  double m = 0.0;
+  if (i < nx && j < ny) {   // v rows 0..ny-1; row ny is a wall and holds 0
+    const size_t o = (size_t)j * nx + i;
+    m = fmax(fabs(I.u[o]), fabs(I.v[o]));
+  }
+  m = block_max(m, sh);
+  if (threadIdx.x == 0) st_agent(&I.part[t.local], m);
+  if (arrive_last(I.counters + 0 * kCounterStride, I.ntiles, t.local)) {
+    double mm = 0.0;
+    for (int k = threadIdx.x; k < I.ntiles; k += kNT) mm = fmax(mm, ld_agent(&I.part[k]));
+    mm = block_max(mm, sh);
+    if (threadIdx.x == 0) I.pcg->gamma_step = fmin(I.gamma, I.gamma_factor * mm);
+  }
+}
+
 // Graph path bookkeeping, one thread per instance: clear the step's miss flag
 // and iteration maximum (begin), or record whether the solve just enqueued
 // converged within its fixed iteration budget (end).

@@ -339,7 +339,7 @@ __device__ __forceinline__ void stage_tile(const Tile& t, const Inst& I, int k, 
     }
   }
   __syncthreads();
-  const S gam = (S)I.gamma, eps = (S)I.eps, inv_h = (S)I.inv_h;
+  const S gam = (S)I.pcg->gamma_step, eps = (S)I.eps, inv_h = (S)I.inv_h;
   const S drho = (S)(I.rho1 - I.rho2), rho2 = (S)I.rho2;
   // x-face fluxes (each face computed once per block by this one code path)
   for (int q = tid; active && q < XY * XX; q += kNT) {

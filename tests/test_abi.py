@@ -80,7 +80,8 @@ def test_workspace_and_default_dt_host_only():
     (dict(theta_eq=math.pi), -1), (dict(beta1=0.0), -1), (dict(gamma=-1.0), -1),
     (dict(rho2=0.0), -1), (dict(lx=3.0), -2), (dict(dt=-1.0), -1),
     # empty, negative and below-minimum grids
-    (dict(nx=0), -2), (dict(ny=0), -2), (dict(nx=-8), -2), (dict(nx=2, ny=2), -2)])
+    (dict(nx=0), -2), (dict(ny=0), -2), (dict(nx=-8), -2), (dict(nx=2, ny=2), -2),
+    (dict(gamma_factor=-1.0), -1), (dict(gamma_factor=float("nan")), -1)])
 def test_invalid_parameters_rejected_before_device_work(kw, status):
     L = _lib()
     lib = L.lib()

@@ -400,6 +400,35 @@ def test_navier_slip_uses_the_phase_weighted_wall_friction(phi_value):
     assert np.allclose(w["bot"]["u_wall"], -1.0 + a * ls, atol=1e-13)
 
 
+def test_step_gamma_follows_the_largest_face_velocity():
+    """gamma = 2.5 |u|_max (Sec. 5): on a constructed state whose largest
+    magnitude is a negative v face (-0.7, against 0.3 in u) the step's gamma
+    is 2.5 x 0.7 = 1.75, capped by the fixed gamma; a state at rest gets 0."""
+    c = W.drop_case(32, 16, 60.0, 10.0)
+    ny, nx = 16, 32
+    u = np.zeros((ny, nx)); v = np.zeros((ny + 1, nx))
+    u[4, 7] = 0.3; v[9, 3] = -0.7
+    p = c.params.replace(gamma=10.0, gamma_factor=2.5)
+    assert cdi.step_gamma(u, v, p) == 1.75
+    assert cdi.step_gamma(u, v, p.replace(gamma=1.0)) == 1.0
+    assert cdi.step_gamma(np.zeros_like(u), np.zeros_like(v), p) == 0.0
+    assert cdi.step_gamma(u, v, p.replace(gamma_factor=0.0)) == 10.0
+
+
+def test_dynamic_gamma_step_is_the_fixed_gamma_step_at_its_value():
+    """A step with gamma_factor > 0 holds gamma = 2.5 max|u| (here 2.5 x 0.7)
+    for all four stages: bit for bit the fixed-gamma step at that value."""
+    c = W.drop_case(32, 16, 60.0, 10.0)
+    ny, nx = 16, 32
+    s = cdi.initial_state(c.phi0)
+    s.u = np.zeros((ny, nx)); s.v = np.zeros((ny + 1, nx))
+    s.u[4, 7] = 0.3; s.v[9, 3] = -0.7
+    a = cdi.step(s, c.params.replace(gamma=10.0, gamma_factor=2.5))
+    b = cdi.step(s, c.params.replace(gamma=1.75, gamma_factor=0.0))
+    for k in ("phi", "u", "v", "p"):
+        assert np.array_equal(getattr(a, k), getattr(b, k)), k
+
+
 def test_uniform_flow_is_transported_consistently():
     """sigma = 0, density ratio 10, u = U_wall = U everywhere: the consistent
     mass flux keeps u = U exactly while the drop is advected."""

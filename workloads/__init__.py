@@ -35,7 +35,9 @@ class Params:
     thickness, gamma the regularisation velocity scale, sigma the surface
     tension, theta_eq the equilibrium contact angle measured inside fluid 1
     (radians), beta1/beta2 the wall friction of each fluid (Sec. 2, slip BC),
-    u_wall_bot/u_wall_top the tangential wall speeds (+x).
+    u_wall_bot/u_wall_top the tangential wall speeds (+x).  gamma_factor > 0
+    selects the paper's velocity-dependent regularisation (Sec. 5: gamma =
+    2.5 |u|_max): each step takes min(gamma, gamma_factor * max |u|, |v|).
     """
     nx: int
     ny: int
@@ -55,6 +57,7 @@ class Params:
     u_wall_top: float = 0.0
     dt: float = 0.0
     slip_model: str = "4A"
+    gamma_factor: float = 0.0   # > 0: gamma of a step = min(gamma, factor * max|u|)
 
     @property
     def h(self) -> float:
