@@ -31,6 +31,7 @@ from __future__ import annotations
 import argparse
 import json
 import math
+import os
 import time
 
 import numpy as np
@@ -77,21 +78,42 @@ def case(nx: int, gamma: float = 1.0, gamma_factor: float = 2.5):
 
 
 def run(nx: int, t_end: float, outputs: int = 10, gamma: float = 1.0,
-        gamma_factor: float = 2.5, verbose: bool = True) -> dict:
+        gamma_factor: float = 2.5, verbose: bool = True, checkpoint: str | None = None,
+        max_seconds: float = 0.0) -> dict | None:
+    """Run to t_end; with `checkpoint`, resume from that file if it exists
+    and, when `max_seconds` of wall time pass before t_end, save the state
+    there and return None (the run continues on the next call)."""
     from paper_2412_16843_amd.solver import CDISolver
     p, phi0 = case(nx, gamma, gamma_factor)
     h = p.h
     mass = float(phi0.sum()) * h * h
-    s = CDISolver(p, phi0, rtol=1e-10)
-    s.tune()
     per = max(1, int(round(t_end / outputs / p.dt)))
+    start, history, umax_max, u0, v0, p0 = 0, [], 0.0, None, None, None
+    if checkpoint and os.path.exists(checkpoint):
+        ck = np.load(checkpoint)
+        assert int(ck["nx"]) == nx and int(ck["per"]) == per, "checkpoint of another run"
+        phi0, u0, v0, p0 = ck["phi"], ck["u"], ck["v"], ck["p"]
+        start, umax_max = int(ck["done"]), float(ck["umax_max"])
+        history = [tuple(r) for r in ck["history"]]
+    s = CDISolver(p, phi0, rtol=1e-10, u0=u0, v0=v0)
+    if p0 is not None:
+        s.set_state(0, p=p0)
+    s.tune()
     t0 = time.perf_counter()
-    history = []
-    umax_max = 0.0
-    for k in range(outputs):
+    for k in range(start, outputs):
+        if checkpoint and max_seconds > 0 and k > start and time.perf_counter() - t0 > max_seconds:
+            g = s.state()
+            np.savez(checkpoint, nx=nx, per=per, done=k, umax_max=umax_max,
+                     history=np.array(history), phi=g["phi"], u=g["u"], v=g["v"], p=g["p"])
+            s.close()
+            if verbose:
+                print(f"nx {nx}: state after {k} of {outputs} intervals saved to {checkpoint}",
+                      flush=True)
+            return None
         s.step(per)
         g = s.state()
         d = s.diagnostics()
+        d["t"] = (k + 1) * per * p.dt      # also across resumed segments
         L = wetted_length(g["phi"], h)
         umax = float(max(np.abs(g["u"]).max(), np.abs(g["v"]).max()))
         if k > 0:
@@ -101,20 +123,19 @@ def run(nx: int, t_end: float, outputs: int = 10, gamma: float = 1.0,
             print(f"nx {nx} t {d['t']:.4f} L {L:.6f} max slip {d['max_uslip_bot']:.4e} "
                   f"|u|max {umax:.3e} {time.perf_counter() - t0:.0f} s", flush=True)
     d = s.diagnostics()
-    g = s.state()
     s.close()
     L = history[-1][1]
     L_ex = exact_wetted_length()
     L_mass = exact_wetted_length(math.sqrt(2.0 * mass / math.pi))
     return dict(nx=nx, ny=nx // 2, eps_over_h=round(p.eps / h, 4), gamma=gamma,
                 gamma_factor=gamma_factor, dt=p.dt,
-                steps=per * outputs, t=d["t"], L=L, L_exact=L_ex,
+                steps=per * outputs, t=per * outputs * p.dt, L=L, L_exact=L_ex,
                 L_err=abs(L - L_ex) / L_ex,
                 L_err_own_mass=abs(L - L_mass) / L_mass,
                 L_change_last_tenth=abs(L - history[-2][1]) / L_ex,
                 max_uslip=max(d["max_uslip_bot"], d["max_uslip_top"]),
                 max_u_after_first_tenth=umax_max,
-                mass_drift=abs(d["mass"] - d["mass0"]) / d["mass0"],
+                mass_drift=abs(d["mass"] / mass - 1.0),   # against the initial drop
                 phi_min=d["phi_min"], phi_max=d["phi_max"],
                 seconds=round(time.perf_counter() - t0, 1))
 
@@ -126,9 +147,16 @@ def main(argv=None):
     ap.add_argument("--outputs", type=int, default=10)
     ap.add_argument("--gamma", type=float, default=1.0)
     ap.add_argument("--gamma-factor", type=float, default=2.5)
+    ap.add_argument("--checkpoint", default=None,
+                    help="resume from / save to this .npz (one resolution per file)")
+    ap.add_argument("--max-seconds", type=float, default=0.0,
+                    help="with --checkpoint: save and stop after this much wall time")
     a = ap.parse_args(argv)
     for nx in a.nx:
-        print(json.dumps(run(nx, a.t_end, a.outputs, a.gamma, a.gamma_factor)), flush=True)
+        r = run(nx, a.t_end, a.outputs, a.gamma, a.gamma_factor, checkpoint=a.checkpoint,
+                max_seconds=a.max_seconds)
+        if r is not None:
+            print(json.dumps(r), flush=True)
 
 
 if __name__ == "__main__":
