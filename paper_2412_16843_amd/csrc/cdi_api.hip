@@ -608,7 +608,6 @@ cdi_status run_step(cdi_ctx* c) {
   Batch& B = c->B;
   const unsigned ncell = (unsigned)B.cell.size();
   const unsigned nwide = (unsigned)B.wide.size();
-  const double dt = B.R[0].dt;   // every instance carries its own dt in Inst
   cdi_status st = CDI_OK;
   if (c->dyn_gamma) k_gamma_step<<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst);
   for (int k = 0; k < 4; ++k) {
@@ -645,7 +644,6 @@ cdi_status run_step(cdi_ctx* c) {
       });
     });
   }
-  (void)dt;
   c->hist_steps += 1;
   // the graph launch sizes its fixed budget from the step's largest count
   c->pred_iters = *std::max_element(c->pred_stage, c->pred_stage + 4);
