@@ -589,7 +589,7 @@ int guess_mode(const cdi_ctx* c) {
 
 // Network inference for the initial guess of instance 0's next solve (the
 // right-hand side and its statistics come from k_rhs / k_solve_setup).
-void learned_guess(cdi_ctx* c, int src) {
+void learned_guess(cdi_ctx* c, int src, int base, int stage) {
   const Inst& I = c->B.inst[0];
   const double* phi = src == 0 ? I.phi : (src == 1 ? I.phi_a : I.phi_b);
   const unsigned g = (unsigned)std::min(1024, ceil_div(I.nx * I.ny, kNT));
@@ -598,7 +598,8 @@ void learned_guess(cdi_ctx* c, int src) {
     cdinet::forward(c->net);
     CDI_LAUNCH(c, k_guess_apply, g, kNT, c->d_inst, cdinet::output(c->net));
     with_rows(c->wide_rows, [&](auto R) {
-      k_guess_fit<decltype(R)::value><<<(unsigned)c->B.wide.size(), kNT, 0, c->stream>>>(c->d_wide, c->d_inst);
+      k_guess_fit<decltype(R)::value><<<(unsigned)c->B.wide.size(), kNT, 0, c->stream>>>(c->d_wide, c->d_inst,
+                                                                                          base, stage);
     });
   }, false);
 }
@@ -630,7 +631,9 @@ cdi_status run_step(cdi_ctx* c) {
                                                                    c->rtol, c->maxit);
       });
     });
-    if (c->guess == CDI_GUESS_LEARNED && c->net) learned_guess(c, dst);
+    // the learned guess is fitted on top of the plain guess of this solve
+    if (c->guess == CDI_GUESS_LEARNED && c->net)
+      learned_guess(c, dst, c->hist_steps >= 1 ? history_mode(c->hist_steps, c->extrap_order) : 1, k);
     // previous-pressure guess: the same stage of the previous step (linear
     // extrapolation once two steps exist), else the last pressure
     int gm = guess_mode(c);
@@ -1071,7 +1074,7 @@ cdi_status cdi_solve_pressure(cdi_ctx* c, const double* b, double* p, cdi_solve_
   else
     k_solve_setup<double><<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, b, c->rtol, c->maxit);
   c->coef_ready = false;
-  if (c->guess == CDI_GUESS_LEARNED && c->net) learned_guess(c, 0);
+  if (c->guess == CDI_GUESS_LEARNED && c->net) learned_guess(c, 0, 1, 0);
   const int guess = guess_mode(c);
   cdi_status s = c->mixed ? solve_loop<float>(c, guess, 0) : solve_loop<double>(c, guess, 0);
   c->coef_ready = false;   // coefficients now follow the caller phase field

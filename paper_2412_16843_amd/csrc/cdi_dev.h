@@ -53,6 +53,8 @@ struct PcgScalars {
   int miss;                 // graph path: a solve of the step ended unconverged
   int step_iters;           // graph path: largest iteration count of the step
   int nonfinite;            // 1 once a norm of the solve was NaN or Inf (the solve stops)
+  int gbase;                // guess mode of the fitted base of the learned guess (1, 3..6)
+  int pad;
 };
 
 struct Inst {

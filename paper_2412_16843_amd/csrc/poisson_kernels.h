@@ -187,15 +187,16 @@ __device__ __forceinline__ double apply_K(const Inst& I, const double* __restric
   return s;
 }
 
-// f = -(b - mean b); x0 = guess or 0; r = f - K x0.  guess 1: the previous
-// pressure p; 2: the fitted combination of p and the learned pressure g held
-// in zf; 3..6: the same RK stage's pressure extrapolated in time from the
-// last 1..4 steps (constant, linear, quadratic, cubic polynomial through
-// equally spaced values: weights 1; 2, -1; 3, -3, 1; 4, -6, 4, -1).
-__device__ __forceinline__ double guess_value(const Inst& I, int guess, int stage, size_t o) {
+// Initial guess of a solve, value at cell o (r0 = f - K x0 with f = -(b -
+// mean b)).  guess 1: the caller's / last pressure p; 3..6: the same RK
+// stage's pressure extrapolated in time from the last 1..4 steps (constant,
+// linear, quadratic, cubic polynomial through equally spaced values: weights
+// 1; 2, -1; 3, -3, 1; 4, -6, 4, -1); 2: the learned guess, the fitted
+// combination gscale * base + gscale2 * g of a base of mode gbase (one of the
+// above) and the network output g held in zf.
+__device__ __forceinline__ double base_guess(const Inst& I, int guess, int stage, size_t o) {
   switch (guess) {
     case 1: return I.p[o];
-    case 2: return I.pcg->gscale * I.p[o] + I.pcg->gscale2 * I.zf[o];
     case 3: return I.hp[0][stage][o];
     case 4: return 2.0 * I.hp[0][stage][o] - I.hp[1][stage][o];
     case 5: return 3.0 * (I.hp[0][stage][o] - I.hp[1][stage][o]) + I.hp[2][stage][o];
@@ -203,6 +204,12 @@ __device__ __forceinline__ double guess_value(const Inst& I, int guess, int stag
                    I.hp[3][stage][o];
     default: return 0.0;
   }
+}
+
+__device__ __forceinline__ double guess_value(const Inst& I, int guess, int stage, size_t o) {
+  if (guess == 2)
+    return I.pcg->gscale * base_guess(I, I.pcg->gbase, stage, o) + I.pcg->gscale2 * I.zf[o];
+  return base_guess(I, guess, stage, o);
 }
 
 // f = -(b - mean b), x0 and r0 = f - K x0 at cell (j, i).
@@ -443,7 +450,8 @@ __global__ void __launch_bounds__(kNT) k_pcg_spmv(const Tile* __restrict__ tiles
 // guess is never worse, in that norm, than the previous pressure or zero.
 template <int WR>
 __global__ void __launch_bounds__(kNT) k_guess_fit(const Tile* __restrict__ tiles,
-                                                   const Inst* __restrict__ insts) {
+                                                   const Inst* __restrict__ insts, int base,
+                                                   int stage) {
   __shared__ double sh[5 * kNT / 64];
   const Tile t = tiles[blockIdx.x];
   const Inst& I = insts[t.inst];
@@ -454,8 +462,14 @@ __global__ void __launch_bounds__(kNT) k_guess_fit(const Tile* __restrict__ tile
     if (i < nx && j < ny) {
       const size_t o = (size_t)j * nx + i;
       const double f = -(I.b[o] - I.pcg->bmean);
-      const double pv = I.p[o], gv = I.zf[o];
-      const double kp = apply_K(I, I.p, j, i), kg = apply_K(I, I.zf, j, i);
+      const int ie = wrap(i + 1, nx), iw = wrap(i - 1, nx);
+      const double pv = base_guess(I, base, stage, o), gv = I.zf[o];
+      // K applied to the base (apply_K's terms, with base values)
+      double kp = I.ax0[o] * (pv - base_guess(I, base, stage, (size_t)j * nx + iw)) +
+                  I.ax0[(size_t)j * nx + ie] * (pv - base_guess(I, base, stage, (size_t)j * nx + ie));
+      if (j >= 1) kp += I.ay0[o] * (pv - base_guess(I, base, stage, o - nx));
+      if (j + 1 < ny) kp += I.ay0[o + nx] * (pv - base_guess(I, base, stage, o + nx));
+      const double kg = apply_K(I, I.zf, j, i);
       s[0] += pv * kp; s[1] += pv * kg; s[2] += gv * kg; s[3] += pv * f; s[4] += gv * f;
     }
   }
@@ -478,6 +492,7 @@ __global__ void __launch_bounds__(kNT) k_guess_fit(const Tile* __restrict__ tile
       }
       I.pcg->gscale = a;
       I.pcg->gscale2 = c;
+      I.pcg->gbase = base;
     }
   }
 }

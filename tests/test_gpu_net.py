@@ -100,19 +100,26 @@ def test_training_reduces_loss_and_guess_beats_zero():
     # held-out case: compare the pressure solve from zero and from the network
     case = W.drop_case(128, 64, 60.0, 10.0, steps=10)
     plain = CDISolver(case.params, case.phi0, guess="zero", rtol=1e-10)
+    prev = CDISolver(case.params, case.phi0, guess="prev", rtol=1e-10)
     lrn = CDISolver(case.params, case.phi0, guess="learned", rtol=1e-10)
     inf = learned.GuessNet(1, 64, 128, params=net.params.cpu().numpy(), train=False,
                            stream=lrn.stream)
     lrn.attach_guess(inf)
-    it_zero, it_learn = [], []
+    it_zero, it_prev, it_learn = [], [], []
     for _ in range(case.steps):
         plain.step(1)
+        prev.step(1)
         lrn.step(1)
         it_zero.append(plain.diagnostics()["last_iters"])
+        it_prev.append(prev.diagnostics()["last_iters"])
         it_learn.append(lrn.diagnostics()["last_iters"])
-    print("iterations from zero:", it_zero, "from the network:", it_learn)
+    print("iterations from zero:", it_zero, "from the extrapolated history:", it_prev,
+          "from the network fitted on that history:", it_learn)
     assert np.mean(it_learn) < np.mean(it_zero)
+    # the fit spans the plain guess, so it starts no farther (energy norm)
+    # from the solution: no more iterations on average
+    assert np.mean(it_learn) <= np.mean(it_prev) + 0.5
     a, b = plain.state(), lrn.state()
     # both converge to the same 1e-10 residual: fields agree closely
     assert np.abs(a["phi"] - b["phi"]).max() < 1e-8
-    inf.close(); net.close(); plain.close(); lrn.close()
+    inf.close(); net.close(); plain.close(); prev.close(); lrn.close()
