@@ -318,6 +318,7 @@ size_t batch_bytes(const std::vector<Resolved>& Rs, Batch* B, char* base) {
   size_t off = 0;
   off = align256(off + sizeof(Inst) * n);
   off = align256(off + sizeof(DiagOut) * n);
+  off = align256(off + sizeof(PcgScalars) * n);
   off = align256(off + sizeof(Tile) * (2 * ntile_cell + ntile_wide + ntile_mg + 1));
   for (int k = 0; k < n; ++k)
     off = carve(Rs[k], cell_tiles(Rs[k]), mg0_tiles(Rs[k]), base, off, B ? &B->inst[k] : nullptr);
@@ -350,6 +351,7 @@ struct cdi_ctx {
   char* ws = nullptr;
   Inst* d_inst = nullptr;
   DiagOut* d_diag = nullptr;
+  PcgScalars* d_pcg_all = nullptr;   // gather area of the batch's CG scalars
   Tile* d_cell = nullptr;          // level-0 tiles, XCD-banded order (tiled launches)
   Tile* d_cell_inst = nullptr;     // level-0 tiles, instance by instance (persistent launch)
   Tile* d_wide = nullptr;          // level-0 wide tiles, XCD-banded order
@@ -493,6 +495,22 @@ void launch_coef(cdi_ctx* c) {
   timed(c, "mg_coef", [&] { CDI_LAUNCH(c, k_coarse_inv<S>, (unsigned)c->B.n, kCoarseNT, c->d_inst); });
 }
 
+// Enqueue the copy of every instance's CG scalars into the pinned host array
+// (one copy for a single instance, else a gather kernel and one copy).
+cdi_status pcg_to_host(cdi_ctx* c) {
+  const int n = c->B.n;
+  if (n == 1) {
+    HIPCHK(hipMemcpyAsync(c->h_pcg, c->B.inst[0].pcg, sizeof(PcgScalars), hipMemcpyDeviceToHost,
+                          c->stream));
+    return CDI_OK;
+  }
+  k_gather_pcg<<<(unsigned)ceil_div(n, 64), 64, 0, c->stream>>>(c->d_inst, n, c->d_pcg_all);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(c->h_pcg, c->d_pcg_all, sizeof(PcgScalars) * n, hipMemcpyDeviceToHost,
+                        c->stream));
+  return CDI_OK;
+}
+
 // True if a solve of the batch met a NaN or Inf (host copies of the CG
 // scalars must be current).
 bool any_nonfinite(const cdi_ctx* c) {
@@ -537,9 +555,8 @@ cdi_status solve_loop(cdi_ctx* c, int guess, int stage) {
     launch_vcycle<S>(c, 1, par, par ^ 1);
     ++it;
     if (it >= next_check || it >= c->maxit) {
-      HIPCHK(hipMemcpyAsync(c->h_pcg, B.inst[0].pcg, sizeof(PcgScalars), hipMemcpyDeviceToHost, c->stream));
-      for (int k = 1; k < B.n; ++k)
-        HIPCHK(hipMemcpyAsync(c->h_pcg + k, B.inst[k].pcg, sizeof(PcgScalars), hipMemcpyDeviceToHost, c->stream));
+      cdi_status cs = pcg_to_host(c);
+      if (cs != CDI_OK) return cs;
       HIPCHK(hipStreamSynchronize(c->stream));
       all_done = true;
       for (int k = 0; k < B.n; ++k) all_done = all_done && c->h_pcg[k].done;
@@ -548,8 +565,8 @@ cdi_status solve_loop(cdi_ctx* c, int guess, int stage) {
     }
   }
   if (!all_done) {
-    for (int k = 0; k < B.n; ++k)
-      HIPCHK(hipMemcpyAsync(c->h_pcg + k, B.inst[k].pcg, sizeof(PcgScalars), hipMemcpyDeviceToHost, c->stream));
+    cdi_status cs = pcg_to_host(c);
+    if (cs != CDI_OK) return cs;
     HIPCHK(hipStreamSynchronize(c->stream));
   }
   // the solution mean needs its own pass only for a solve that ended before
@@ -760,10 +777,7 @@ cdi_status graph_capture(cdi_ctx* c, int budget) {
         k_project<decltype(R)::value><<<nwide, kNT, 0, c->stream>>>(c->d_wide, c->d_inst, tfac, k == 3, dst, k);
       });
     }
-    for (int k = 0; k < B.n; ++k)
-      HIPCHK(hipMemcpyAsync(c->h_pcg + k, B.inst[k].pcg, sizeof(PcgScalars), hipMemcpyDeviceToHost,
-                            c->stream));
-    return CDI_OK;
+    return pcg_to_host(c);
   };
   hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
   cdi_status st = e == hipSuccess ? body() : fail(CDI_ERR_DEVICE, "hipStreamBeginCapture: %s", hipGetErrorString(e));
@@ -866,8 +880,10 @@ cdi_status run_persistent(cdi_ctx* c, int nsteps) {
     HIPCHK(hipGetLastError());
     c->hist_steps += m;
   }
-  for (int k = 0; k < B.n; ++k)
-    HIPCHK(hipMemcpyAsync(c->h_pcg + k, B.inst[k].pcg, sizeof(PcgScalars), hipMemcpyDeviceToHost, c->stream));
+  {
+    cdi_status cs = pcg_to_host(c);
+    if (cs != CDI_OK) return cs;
+  }
   HIPCHK(hipStreamSynchronize(c->stream));
   bool noconv = false;
   int maxi = 0;
@@ -959,6 +975,8 @@ cdi_status cdi_init_batch(const cdi_params* params, int32_t n, const cdi_fields*
   off = align256(off + sizeof(Inst) * n);
   c->d_diag = (DiagOut*)(c->ws + off);
   off = align256(off + sizeof(DiagOut) * n);
+  c->d_pcg_all = (PcgScalars*)(c->ws + off);
+  off = align256(off + sizeof(PcgScalars) * n);
   Tile* tl = (Tile*)(c->ws + off);
   // fixed slots: level-0 cell tiles (XCD-banded order, tiled launches; then
   // instance order, persistent launch), the wide tiles (room for 1 row per

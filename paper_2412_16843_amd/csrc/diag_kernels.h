@@ -203,6 +203,13 @@ __global__ void __launch_bounds__(kNT) k_gamma_step(const Tile* __restrict__ til
   }
 }
 
+// Every instance's CG scalars side by side (one thread per instance), so that
+// the host reads a batch's scalars with one copy instead of one per instance.
+__global__ void k_gather_pcg(const Inst* __restrict__ insts, int n, PcgScalars* __restrict__ out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) out[k] = *insts[k].pcg;
+}
+
 // Graph path bookkeeping, one thread per instance: clear the step's miss flag
 // and iteration maximum (begin), or record whether the solve just enqueued
 // converged within its fixed iteration budget (end).
