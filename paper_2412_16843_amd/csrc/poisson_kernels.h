@@ -207,8 +207,11 @@ __device__ __forceinline__ double base_guess(const Inst& I, int guess, int stage
 }
 
 __device__ __forceinline__ double guess_value(const Inst& I, int guess, int stage, size_t o) {
-  if (guess == 2)
-    return I.pcg->gscale * base_guess(I, I.pcg->gbase, stage, o) + I.pcg->gscale2 * I.zf[o];
+  if (guess == 2) {
+    const double b = I.pcg->gscale * base_guess(I, I.pcg->gbase, stage, o);
+    const double c = I.pcg->gscale2;   // 0 when the network output was dropped
+    return c != 0.0 ? b + c * I.zf[o] : b;
+  }
   return base_guess(I, guess, stage, o);
 }
 
@@ -482,7 +485,11 @@ __global__ void __launch_bounds__(kNT) k_guess_fit(const Tile* __restrict__ tile
     if (threadIdx.x == 0) {
       double a = 0.0, c = 0.0;
       const double det = m[0] * m[2] - m[1] * m[1];
-      if (m[0] > 0.0 && m[2] > 0.0 && det > 1e-12 * m[0] * m[2]) {
+      bool finite = true;
+      for (int k = 0; k < 5; ++k) finite = finite && isfinite(m[k]);
+      if (!finite) {   // a non-finite network output (e.g. garbage weights): the base alone
+        a = 1.0;
+      } else if (m[0] > 0.0 && m[2] > 0.0 && det > 1e-12 * m[0] * m[2]) {
         a = (m[3] * m[2] - m[4] * m[1]) / det;
         c = (m[4] * m[0] - m[3] * m[1]) / det;
       } else if (m[2] > 0.0) {

@@ -123,3 +123,34 @@ def test_training_reduces_loss_and_guess_beats_zero():
     # both converge to the same 1e-10 residual: fields agree closely
     assert np.abs(a["phi"] - b["phi"]).max() < 1e-8
     inf.close(); net.close(); plain.close(); prev.close(); lrn.close()
+
+
+@pytest.mark.parametrize("garbage", ["nan", "huge"])
+def test_garbage_network_falls_back_to_the_plain_guess(garbage):
+    """Network weights that produce a non-finite output (NaN weights, or
+    weights so large that the fit's sums overflow) must not break a solve:
+    the fit keeps the plain guess alone, so the run is bit for bit the run
+    without the network."""
+    torch = _torch()
+    from paper_2412_16843_amd import learned
+    from paper_2412_16843_amd._lib import lib
+    from paper_2412_16843_amd.solver import CDISolver
+    case = W.drop_case(128, 64, 60.0, 10.0)
+    prev = CDISolver(case.params, case.phi0, guess="prev", rtol=1e-10)
+    lrn = CDISolver(case.params, case.phi0, guess="learned", rtol=1e-10)
+    n = lib().cdi_net_param_count()
+    bad = np.full(n, np.nan if garbage == "nan" else 1e30, dtype=np.float32)
+    inf = learned.GuessNet(1, 64, 128, params=bad, train=False, stream=lrn.stream)
+    lrn.attach_guess(inf)
+    it_prev, it_learn = [], []
+    for _ in range(6):
+        prev.step(1)
+        lrn.step(1)
+        it_prev.append(prev.diagnostics()["last_iters"])
+        it_learn.append(lrn.diagnostics()["last_iters"])
+    a, b = prev.state(), lrn.state()
+    print(garbage, "iterations without / with the network:", it_prev, it_learn)
+    assert it_learn == it_prev
+    for k in ("phi", "u", "v", "p"):
+        assert np.array_equal(a[k], b[k]), k
+    inf.close(); prev.close(); lrn.close()

@@ -121,10 +121,11 @@ def test_config1_full_run_parity():
     assert abs(d["max_uslip_bot"] - od["max_uslip_bot"]) < 1e-9 * od["max_uslip_bot"]
 
 
-def test_config2_parity_200_steps():
-    """Two-phase Couette 256x64, first 200 of its 4000 steps (FP64)."""
+def test_config2_full_run_parity():
+    """Two-phase Couette 256x64, its full 4000 steps (FP64; ~25 s of oracle)."""
     case = W.config2()
-    g, o, d = _run_pair(case, 200)
+    g, o, d = _run_pair(case, case.steps)
+    assert case.steps == 4000
     errs = {k: relerr(g[k], ref) for k, ref in (("phi", o.phi), ("u", o.u), ("v", o.v),
                                                   ("p", o.p))}
     print("config2 per-field relative error:", errs)
