@@ -164,17 +164,19 @@ def test_config4_full_ensemble_sampled_against_oracle():
     s.close()
 
 
-def test_largest_grid_step_conserves_mass_and_bounds():
-    """One FP64 step of the 8192 x 4096 ratio-10 drop (4 projections to
-    1e-10): total phi conserved to round-off, phi within [0, 1] up to the
-    CDI flux's round-off, every solve at its residual."""
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_largest_grid_step_conserves_mass_and_bounds(precision):
+    """One step of the 8192 x 4096 ratio-10 drop (4 projections to 1e-10),
+    FP64 and mixed: total phi conserved to round-off (phi and its flux
+    differences stay FP64 on the mixed path), phi within [0, 1] up to the CDI
+    flux's round-off, every solve at its residual."""
     case = LARGEST[1]()
-    s = _solver(case.params, case.phi0, rtol=1e-10)
+    s = _solver(case.params, case.phi0, rtol=1e-10, precision=precision)
     s.step(1)
     d = s.diagnostics()
     s.close()
-    print("8192x4096 step:", {k: d[k] for k in ("mass", "mass0", "phi_min", "phi_max",
-                                                 "last_iters", "last_relres")})
+    print("8192x4096 step", precision, {k: d[k] for k in ("mass", "mass0", "phi_min", "phi_max",
+                                                           "last_iters", "last_relres")})
     assert abs(d["mass"] - d["mass0"]) <= 1e-12 * d["mass0"]
     assert d["phi_min"] >= -1e-12 and d["phi_max"] <= 1.0 + 1e-12
     assert d["last_relres"] <= 1e-10
