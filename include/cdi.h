@@ -283,10 +283,12 @@ cdi_status cdi_guess_attach(cdi_ctx* ctx, cdi_net* net);
  *     on a stream of the library's own, ordered after and before the
  *     caller's stream by events; one host synchronisation per step.  A step
  *     that needs more iterations than the budget is redone from a snapshot
- *     on the stream path and the budget grows.  The first two steps of a run
- *     take the stream path.
+ *     on the stream path and the budget grows.  The first steps of a run,
+ *     until the pressure history of the extrapolated guess is complete
+ *     (order + 1 steps, cdi_set_extrapolation), take the stream path.
  * PERSISTENT and GRAPH are not available with CDI_GUESS_LEARNED and an
- * attached network (cdi_step then returns CDI_ERR_STATE). */
+ * attached network (cdi_step then returns CDI_ERR_STATE); PERSISTENT is not
+ * available with gamma_factor > 0 (CDI_ERR_ARG). */
 cdi_status cdi_set_launch(cdi_ctx* ctx, int32_t mode);
 cdi_status cdi_get_launch(cdi_ctx* ctx, int32_t* mode);
 
@@ -331,7 +333,8 @@ cdi_status cdi_get_mg_smooth(cdi_ctx* ctx, int32_t* nu);
  * candidate -- tiled with 1 and 2 sweep pairs, 1 and 4 rows per thread, the
  * coarse kernel starting at 1024, 4096 and 16384 cells; persistent (with the
  * fastest tiled sweep count; skipped when an instance has more than 16384
- * cells, where one block per instance cannot compete); graph (with the
+ * cells, where one block per instance cannot compete, and with gamma_factor
+ * > 0); graph (with the
  * fastest tiled shape) -- each
  * from the same saved state, restores that state (fields, pressure history,
  * time and step counters), and keeps the fastest candidate for later
