@@ -178,7 +178,7 @@ __device__ __forceinline__ void phase_prep_cell(const Tile& t, const Inst& I,
 // One tile of the phase preparation (TX x WR*TY cells, WR rows per thread),
 // run by kNT threads (tid in [0, kNT)).  Contains one block barrier: every
 // thread of the block calls it, with active = false for threads that have no
-// tile in this round.
+// tile in this pass over the tiles.
 template <typename S, int WR = 1>
 __device__ __forceinline__ void phase_prep_tile(const Tile& t, const Inst& I, int src,
                                                 PrepLds<S, WR>& L, int tid, bool active) {
@@ -260,7 +260,7 @@ struct StageLds {
 
 // One tile of the stage operator, run by kNT threads (tid in [0, kNT)).
 // Contains two block barriers: every thread of the block calls it, with
-// active = false for threads that have no tile in this round.
+// active = false for threads that have no tile in this pass over the tiles.
 template <typename S>
 __device__ __forceinline__ void stage_tile(const Tile& t, const Inst& I, int k, int src, int dst,
                                            double c_next, double b_k, int write_wall,
