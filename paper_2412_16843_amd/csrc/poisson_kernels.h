@@ -35,6 +35,8 @@ constexpr int kDenseMax = 64;        // coarsest grids up to this size use a den
 constexpr double kCoarseCgRtol = 1e-4;
 constexpr int kCLX = 1376;           // LDS cells of all coarse levels (<= 1024 * 4/3)
 constexpr int kCLY = 2432;           // LDS y-faces of all coarse levels
+constexpr int kWideOwn = 4;          // cells per thread of the wide coarse level (2 per colour)
+constexpr int kWideCells = kWideOwn * kCoarseNT;   // its maximum size
 constexpr int FX = 32, FY = 16;            // fine tile of the multigrid kernels
 static_assert(FX * FY == 2 * kNT, "MG tile = 2 cells per thread");
 
@@ -1095,21 +1097,25 @@ __device__ __forceinline__ void dense_part_load(const Inst& I, DensePart& dp) {
   }
 }
 
-// One cell of a level with at most kCoarseNT cells, owned by thread c for a
-// whole pre- or post-smoothing: its coefficients, diagonal and right-hand
-// side are read from the level's arrays once and kept in registers, so a
-// half-sweep reads only the four neighbouring corrections.  The arithmetic is
-// that of the sweep, residual and operator of mg_cycle, term for term.
+// One cell of a coarse level, owned by one thread for a whole pre- or
+// post-smoothing: its coefficients, the reciprocal of its diagonal and its
+// right-hand side are read from the level's arrays once and kept in
+// registers, so a half-sweep reads only the four neighbouring corrections.
+// The residual and operator are those of mg_cycle term for term; the
+// Gauss-Seidel update multiplies by the reciprocal diagonal where the swept
+// global levels divide (at most an ulp apart per update: the smoother stays
+// a fixed linear map, which is all the flexible CG needs of it).
 template <typename S>
 struct OwnedCell {
-  S aw, ae, as, an, D, r;
+  S aw, ae, as, an, iD, r;
   int c, w, e;
   bool own, hs, hn;
   int color;   // (i + j) & 1
 };
 
 template <typename S>
-__device__ __forceinline__ OwnedCell<S> owned_cell(const MgView<S>& L, int c) {
+__device__ __forceinline__ OwnedCell<S> owned_cell(const MgView<S>& L, int c,
+                                                   const double* rd = nullptr) {
   OwnedCell<S> o;
   const int nx = L.nx, ny = L.ny;
   o.own = c < nx * ny;
@@ -1124,8 +1130,8 @@ __device__ __forceinline__ OwnedCell<S> owned_cell(const MgView<S>& L, int c) {
   o.ae = o.own ? L.ax[o.e] : S(0);
   o.as = o.own ? L.ay[o.c] : S(0);
   o.an = o.own ? L.ay[o.c + nx] : S(0);
-  o.D = o.aw + o.ae + o.as + o.an;
-  o.r = o.own ? L.r[o.c] : S(0);
+  o.iD = o.own ? S(1) / (o.aw + o.ae + o.as + o.an) : S(0);
+  o.r = o.own ? (rd != nullptr ? (S)rd[o.c] : L.r[o.c]) : S(0);
   return o;
 }
 
@@ -1134,11 +1140,45 @@ template <typename S>
 __device__ __forceinline__ void owned_gs(const OwnedCell<S>& o, S* z, int nx, int color,
                                          bool from_zero) {
   if (!o.own || o.color != color) return;
-  if (from_zero) { z[o.c] = o.r / o.D; return; }
+  if (from_zero) { z[o.c] = o.r * o.iD; return; }
   S nb = o.aw * z[o.w] + o.ae * z[o.e];
   if (o.hs) nb += o.as * z[o.c - nx];
   if (o.hn) nb += o.an * z[o.c + nx];
-  z[o.c] = (o.r + nb) / o.D;
+  z[o.c] = (o.r + nb) * o.iD;
+}
+
+// Residual t = r - K z of an owned cell.
+template <typename S>
+__device__ __forceinline__ void owned_residual(const OwnedCell<S>& o, const S* z, S* t, int nx) {
+  if (!o.own) return;
+  const S zc = z[o.c];
+  S kz = o.aw * (zc - z[o.w]) + o.ae * (zc - z[o.e]);
+  if (o.hs) kz += o.as * (zc - z[o.c - nx]);
+  if (o.hn) kz += o.an * (zc - z[o.c + nx]);
+  t[o.c] = o.r - kz;
+}
+
+// Restriction R = P^T / 4 of a level's residual t (nx wide) to the right-hand
+// side rc of the next coarser level, by one block of kCoarseNT threads.
+template <typename S>
+__device__ __forceinline__ void restrict_block(const S* t, int nx, S* rc, int cnx, int cny) {
+  const FastDiv dc(cnx);
+  for (int c = threadIdx.x; c < cnx * cny; c += kCoarseNT) {
+    const int J = dc.div(c), Ic = c - J * cnx;
+    S wy[4] = {S(0.25), S(0.75), S(0.75), S(0.25)};
+    if (J == 0) { wy[0] = S(0); wy[1] = S(1); }
+    if (J == cny - 1) { wy[3] = S(0); wy[2] = S(1); }
+    const S wx[4] = {S(0.25), S(0.75), S(0.75), S(0.25)};
+    S acc = 0;
+    for (int dy = 0; dy < 4; ++dy) {
+      if (wy[dy] == S(0)) continue;
+      const int j = 2 * J - 1 + dy;
+      S row = 0;
+      for (int dx = 0; dx < 4; ++dx) row += wx[dx] * t[j * nx + wrap(2 * Ic - 1 + dx, nx)];
+      acc += wy[dy] * row;
+    }
+    rc[c] = S(0.25) * acc;
+  }
 }
 
 template <typename S, typename ViewF>
@@ -1185,14 +1225,7 @@ __device__ __forceinline__ void mg_cycle(const Inst& I, const ViewF& V, int lo, 
         owned_gs<S>(oc, Lv.z, nx, 1, false);
         __syncthreads();
       }
-      if (oc.own) {
-        const S* z = Lv.z;
-        const S zc = z[oc.c];
-        S kz = oc.aw * (zc - z[oc.w]) + oc.ae * (zc - z[oc.e]);
-        if (oc.hs) kz += oc.as * (zc - z[oc.c - nx]);
-        if (oc.hn) kz += oc.an * (zc - z[oc.c + nx]);
-        Lv.t[oc.c] = oc.r - kz;
-      }
+      owned_residual<S>(oc, Lv.z, Lv.t, nx);
     } else {
     sweep(l, 0, true);
     __syncthreads();
@@ -1223,28 +1256,7 @@ __device__ __forceinline__ void mg_cycle(const Inst& I, const ViewF& V, int lo, 
     }
     }
     __syncthreads();
-    {
-      const int cnx = Cv.nx, cny = Cv.ny;
-      const S* t = Lv.t;
-      S* rc = Cv.r;
-      const FastDiv dc(cnx);
-      for (int c = tid; c < cnx * cny; c += kCoarseNT) {
-        const int J = dc.div(c), Ic = c - J * cnx;
-        S wy[4] = {S(0.25), S(0.75), S(0.75), S(0.25)};
-        if (J == 0) { wy[0] = S(0); wy[1] = S(1); }
-        if (J == cny - 1) { wy[3] = S(0); wy[2] = S(1); }
-        const S wx[4] = {S(0.25), S(0.75), S(0.75), S(0.25)};
-        S acc = 0;
-        for (int dy = 0; dy < 4; ++dy) {
-          if (wy[dy] == S(0)) continue;
-          const int j = 2 * J - 1 + dy;
-          S row = 0;
-          for (int dx = 0; dx < 4; ++dx) row += wx[dx] * t[j * nx + wrap(2 * Ic - 1 + dx, nx)];
-          acc += wy[dy] * row;
-        }
-        rc[c] = S(0.25) * acc;
-      }
-    }
+    restrict_block<S>(Lv.t, nx, Cv.r, Cv.nx, Cv.ny);
     __syncthreads();
   }
   // ---- coarsest level: exact solve (mean-free part)
@@ -1447,6 +1459,81 @@ __device__ __forceinline__ void coarse_load_coef(const Inst& I, CoarseLds<S>& C,
   if (hr) rdst[threadIdx.x] = gr;
 }
 
+// LDS of the wide level of the one-block cycle: level lc - 1 when the cycle
+// starts there (more than kCoarseCells cells, at most kWideCells).
+template <typename S>
+struct WideLds {
+  S z[kWideCells], t[kWideCells];
+};
+
+// Cell of colour `col` with colour-compact index h on an nx x ny level (nx
+// even): row h / (nx/2), column 2 (h mod nx/2) + ((row + col) & 1); nx ny
+// (no cell) past the last one.
+__device__ __forceinline__ int wide_cell_index(int h, int col, int nx, int ny) {
+  const int hx = nx >> 1;
+  if (h >= hx * ny) return nx * ny;
+  const int j = h / hx;
+  return j * nx + 2 * (h - j * hx) + ((j + col) & 1);
+}
+
+// V-cycle from the wide level (level lc - 1, nx x ny): every thread owns up
+// to kWideOwn of its cells, whose coefficients, diagonal and right-hand side
+// the caller has read into registers together with the other levels'
+// coefficients: oc[2 m + col] is the cell of colour col with colour-compact
+// index tid + m kCoarseNT, so a half-sweep runs the update only on cells of
+// its colour, in every lane.  The level's correction and residual are in
+// LDS, and the levels from lc run in mg_cycle.  The arithmetic is that of
+// mg_cycle on the level; only the storage differs, so a barrier phase costs
+// LDS latency instead of a pass over global memory.
+template <typename S>
+__device__ __forceinline__ void wide_cycle(const Inst& I, int nx, int ny,
+                                           const OwnedCell<S> (&oc)[kWideOwn], WideLds<S>& W,
+                                           CoarseLds<S>& C, const DensePart* dp) {
+  const int tid = threadIdx.x;
+  {
+#pragma unroll
+    for (int m = 0; m < kWideOwn / 2; ++m) owned_gs<S>(oc[2 * m + 0], W.z, nx, 0, true);
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < kWideOwn / 2; ++m) owned_gs<S>(oc[2 * m + 1], W.z, nx, 1, false);
+    __syncthreads();
+    for (int s = 1; s < I.nu; ++s) {
+#pragma unroll
+      for (int m = 0; m < kWideOwn / 2; ++m) owned_gs<S>(oc[2 * m + 0], W.z, nx, 0, false);
+      __syncthreads();
+#pragma unroll
+      for (int m = 0; m < kWideOwn / 2; ++m) owned_gs<S>(oc[2 * m + 1], W.z, nx, 1, false);
+      __syncthreads();
+    }
+#pragma unroll
+    for (int k = 0; k < kWideOwn; ++k) owned_residual<S>(oc[k], W.z, W.t, nx);
+  }
+  __syncthreads();
+  const MgView<S> Cv = coarse_view<S>(I, C, I.lc);
+  restrict_block<S>(W.t, nx, Cv.r, Cv.nx, Cv.ny);
+  __syncthreads();
+  mg_cycle<S>(I, [&](int l) { return coarse_view<S>(I, C, l); }, I.lc, I.nlev, C.red, C.sc,
+              C.cg, dp);
+  // prolongation over all cells (the barrier below orders it before the
+  // smoothing, whose cells are spread over the threads by colour)
+  const FastDiv dn(nx);
+  for (int c = tid; c < nx * ny; c += kCoarseNT) {
+    const int j = dn.div(c), i = c - j * nx;
+    W.z[c] += prolong<S>(Cv.z, Cv.nx, Cv.ny, j, i);
+  }
+  __syncthreads();
+  {
+    for (int s = 0; s < I.nu; ++s) {
+#pragma unroll
+      for (int m = 0; m < kWideOwn / 2; ++m) owned_gs<S>(oc[2 * m + 1], W.z, nx, 1, false);
+      __syncthreads();
+#pragma unroll
+      for (int m = 0; m < kWideOwn / 2; ++m) owned_gs<S>(oc[2 * m + 0], W.z, nx, 0, false);
+      __syncthreads();
+    }
+  }
+}
+
 // Level view of a one-block V-cycle: levels from lc in LDS, finer levels in
 // global memory (level 0 reads `r0`, the others their own r; the residual
 // scratch of the global levels is I.mg_t).
@@ -1466,7 +1553,8 @@ __device__ __forceinline__ MgView<S> mixed_view(const Inst& I, CoarseLds<S>& C, 
 // ------------------------------------------------ single-block coarse cycle
 // Every level from lg down runs in one block: levels lg..lc-1 from global
 // memory (L2-resident at these sizes), levels from lc in LDS (coefficients,
-// right-hand side, correction, scratch).  lg trades launches of the tiled
+// right-hand side, correction, scratch); a start level lg = lc - 1 keeps its
+// correction and residual in LDS too (wide_cycle).  lg trades launches of the tiled
 // kernels against one CU's throughput and is chosen per context.  With
 // lg == 0 the block holds the whole problem and also applies the CG update,
 // the stopping test and beta.
@@ -1474,9 +1562,12 @@ template <typename S>
 __global__ void __launch_bounds__(kCoarseNT) k_mg_coarse(const Inst* __restrict__ insts,
                                                           int update, int parity, int rsel) {
   __shared__ CoarseLds<S> C;
+  __shared__ WideLds<S> W;
   const Inst& I = insts[blockIdx.x];
   if (I.pcg->done) return;
   const int lg = I.lg, lc = I.lc, nl = I.nlev;
+  const bool wide = lg + 1 == lc && I.lev[lg].nx * I.lev[lg].ny <= kWideCells &&
+                    (I.lev[lg].nx & 1) == 0;
   const int tid = threadIdx.x;
   double* __restrict__ rcur = rsel ? I.rr2 : I.rr;   // level-0 residual the cycle reads
   // ---- CG update when the whole grid is handled here
@@ -1510,6 +1601,17 @@ __global__ void __launch_bounds__(kCoarseNT) k_mg_coarse(const Inst* __restrict_
   dense_part_load(I, dp);
   S* r0 = I.mixed ? (S*)I.mg_r0 : (S*)(void*)rcur;
   auto view = [&](int l) { return mixed_view<S>(I, C, r0, l); };
+  // the wide level's cells, read before the LDS levels' coefficients so
+  // that the block waits for one memory latency; on level 0 the right-hand
+  // side is the FP64 residual itself (its S copy r0 is written below)
+  OwnedCell<S> woc[kWideOwn];
+  if (wide) {
+    const int nx = I.lev[lg].nx, ny = I.lev[lg].ny;
+#pragma unroll
+    for (int k = 0; k < kWideOwn; ++k)
+      woc[k] = owned_cell<S>(view(lg), wide_cell_index(tid + (k >> 1) * kCoarseNT, k & 1, nx, ny),
+                             lg == 0 ? rcur : nullptr);
+  }
   {
     // right-hand side of level lg: into LDS with the coefficients when lg is
     // an LDS level (at most kCoarseCells = kCoarseNT cells), into the S copy
@@ -1528,15 +1630,17 @@ __global__ void __launch_bounds__(kCoarseNT) k_mg_coarse(const Inst* __restrict_
   __syncthreads();
   if (lg >= lc)   // LDS levels only: views the compiler knows to be LDS (ds_ instructions)
     mg_cycle<S>(I, [&](int l) { return coarse_view<S>(I, C, l); }, lg, nl, C.red, C.sc, C.cg, &dp);
+  else if (wide)
+    wide_cycle<S>(I, I.lev[lg].nx, I.lev[lg].ny, woc, W, C, &dp);
   else
     mg_cycle<S>(I, view, lg, nl, C.red, C.sc, C.cg, &dp);
   // ---- publish the level-lg correction (and beta when it is level 0)
   {
     const Level& L = I.lev[lg];
     const int n = L.nx * L.ny;
-    const S* z = view(lg).z;
+    const S* z = wide ? W.z : view(lg).z;
     if (lg > 0) {
-      if (lg >= lc)
+      if (lg >= lc || wide)
         for (int c = tid; c < n; c += kCoarseNT) ((S*)L.z)[c] = z[c];
     } else {
       double zq[1] = {0.0};
