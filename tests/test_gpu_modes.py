@@ -57,18 +57,25 @@ def test_mixed_precision_against_fp64_oracle(make, steps):
     assert max(errs.values()) < 1e-3, errs
 
 
-def test_batched_ensemble_matches_solo_and_oracle():
+@pytest.mark.parametrize("coarse_cells", [1024, 4096])
+def test_batched_ensemble_matches_solo_and_oracle(coarse_cells):
+    """Four instances of different sizes in one context: bitwise the solo
+    runs, and the oracle to 1e-10.  With coarse_cells 4096 the one-block
+    coarse kernel of each instance starts at its wide level (64x32 level 0,
+    48x24, 64x32 and 80x40 level 1), each block deciding for itself."""
     cases = [W.drop_case(64, 32, 60.0, 10.0, name="a"),
              W.couette_case(96, 48, lx=2.0, ly=1.0, ratio=1.0, theta_eq_deg=70.0, name="b"),
              W.drop_case(128, 64, 120.0, 1.0, name="c"),
              W.couette_case(160, 80, lx=2.0, ly=1.0, ratio=10.0, ca=0.05, name="d")]
     steps = 4
     s = _solver([c.params for c in cases], [c.phi0 for c in cases], rtol=1e-13, maxit=400)
+    s.set_coarse_cells(coarse_cells)
     s.step(steps)
     batched = [s.state(k) for k in range(len(cases))]
     s.close()
     for k, c in enumerate(cases):
         solo = _solver(c.params, c.phi0, rtol=1e-13, maxit=400)
+        solo.set_coarse_cells(coarse_cells)
         solo.step(steps)
         g = solo.state()
         solo.close()

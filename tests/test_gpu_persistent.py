@@ -207,11 +207,14 @@ def test_autotune_restores_state_and_keeps_the_trajectory():
     (lambda: W.couette_case(256, 64, lx=4.0, ly=1.0), "fp64"),   # levels 16384 / 4096 / 1024
     (lambda: W.drop_case(128, 64, 60.0, 10.0), "fp64"),          # 8192 / 2048 / 512
     (lambda: W.drop_case(128, 64, 60.0, 10.0), "mixed"),
+    (lambda: W.couette_case(96, 48, lx=2.0, ly=1.0, ratio=10.0), "fp64"),  # 4608 / 1152 / 288
 ])
 def test_coarse_kernel_start_level_matches_oracle(cells, make, precision):
     """The one-block coarse kernel taking over the levels with at most
     `cells` cells (global memory above 1024 cells, the whole grid at 16384
-    for 256x64): same solution as the oracle."""
+    for 256x64): same solution as the oracle.  At 4096 it starts at the
+    wide level just above the LDS levels (4096, 2048 and 1152 cells: two,
+    one and a partial set of cells of each colour per thread)."""
     case = make()
     rtol = 1e-13 if precision == "fp64" else 1e-10
     s = _solver(case.params, case.phi0, rtol=rtol, maxit=400, precision=precision)
