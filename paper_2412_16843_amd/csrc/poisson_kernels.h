@@ -1477,14 +1477,14 @@ __device__ __forceinline__ int wide_cell_index(int h, int col, int nx, int ny) {
 }
 
 // V-cycle from the wide level (level lc - 1, nx x ny): every thread owns up
-// to kWideOwn of its cells, whose coefficients, diagonal and right-hand side
-// the caller has read into registers together with the other levels'
-// coefficients: oc[2 m + col] is the cell of colour col with colour-compact
-// index tid + m kCoarseNT, so a half-sweep runs the update only on cells of
-// its colour, in every lane.  The level's correction and residual are in
-// LDS, and the levels from lc run in mg_cycle.  The arithmetic is that of
-// mg_cycle on the level; only the storage differs, so a barrier phase costs
-// LDS latency instead of a pass over global memory.
+// to kWideOwn of its cells, whose coefficients, reciprocal diagonal and
+// right-hand side the caller has read into registers together with the
+// other levels' coefficients: oc[2 m + col] is the cell of colour col with
+// colour-compact index tid + m kCoarseNT, so a half-sweep runs the update
+// only on cells of its colour, in every lane.  The level's correction and
+// residual are in LDS, and the levels from lc run in mg_cycle.  The
+// arithmetic is that of mg_cycle's owned cells; only the storage differs, so
+// a barrier phase costs LDS latency instead of a pass over global memory.
 template <typename S>
 __device__ __forceinline__ void wide_cycle(const Inst& I, int nx, int ny,
                                            const OwnedCell<S> (&oc)[kWideOwn], WideLds<S>& W,
