@@ -306,8 +306,10 @@ cdi_status cdi_set_tile_rows(cdi_ctx* ctx, int32_t rows);
 cdi_status cdi_get_tile_rows(cdi_ctx* ctx, int32_t* rows);
 
 /* Start of the one-block coarse kernel of the V-cycle: it runs every level
- * with at most `cells` cells (levels up to 1024 cells in its LDS, larger
- * ones from global memory); the finer levels run as tiled kernels.  Larger
+ * with at most `cells` cells (levels up to 1024 cells in its LDS; a start
+ * level just above those, at most 4096 cells, with its correction and
+ * residual in LDS and its cells in registers; larger ones from global
+ * memory); the finer levels run as tiled kernels.  Larger
  * values mean fewer launches per CG iteration but more work on one compute
  * unit.  cells in [1024, 2^20]; cdi_init sets 4096. */
 cdi_status cdi_set_coarse_cells(cdi_ctx* ctx, int32_t cells);
