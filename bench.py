@@ -1,20 +1,31 @@
 #!/usr/bin/env python3
 """Throughput of the CDI + GNBC time step on one MI355X.
 
-One "step" is one full RK4 time step of the workload: 4 stage evaluations
-(phase-field preparation, fused CDI-flux / momentum / GNBC stage kernel,
-projection right-hand side) and 4 variable-density pressure projections by
-multigrid-preconditioned flexible CG to a relative residual of 1e-10.
+One "step" is one full RK4 time step of every instance of the workload: 4
+stage evaluations (phase-field preparation, fused CDI-flux / momentum / GNBC
+stage kernel, projection right-hand side) and 4 variable-density pressure
+projections by multigrid-preconditioned flexible CG to a relative residual of
+1e-10.  The default workload is the seeded 64-instance ensemble of uneven
+drop and Couette grids (128x64 .. 512x256, 3.9 M cells), FP64, all instances
+in one batched context: the largest single-GPU configuration of the
+benchmark set.
 
 Prints one JSON line:
-  metric/value/unit       Mcell-steps/s = nx * ny * steps / wall time / 1e6,
-                          inputs resident in HBM, timed between two device
-                          synchronisations
-  roofline                the dominant kernel's algorithmic bytes per launch
-                          over its average launch time (HIP events on the
-                          library stream), against the 8 TB/s HBM peak
+  metric/value/unit       Mcell-steps/s = sum over instances of nx * ny *
+                          steps / wall time / 1e6, inputs resident in HBM,
+                          timed between two device synchronisations with no
+                          per-kernel instrumentation
+  roofline                the dominant kernel family's algorithmic bytes per
+                          launch over its average launch time (start / end
+                          timestamps of its own launches, taken in a
+                          separate pass on the library stream), against the
+                          8 TB/s HBM peak
+  kernel_time_ms_per_step device time per step of every kernel family
+  poisson_learned_vs_plain  pressure time to solution at 1e-10 on the
+                          2048x1024 ratio-10 grid: zero guess, previous
+                          pressure and the learned guess
   cpu_baseline            the FP64 CPU oracle on a bounded sample of the same
-                          workload on this host
+                          workload on this host (all cores, and one thread)
 """
 from __future__ import annotations
 
@@ -22,6 +33,7 @@ import argparse
 import json
 import math
 import os
+import subprocess
 import sys
 import time
 
@@ -58,6 +70,10 @@ ALGO_BYTES_PER_CELL = {
     "pcg_init": 7 * 8 + 2 * 8,
 }
 
+# every family the library can time (cdi_timing_enable)
+FAMILIES = ("phase_prep", "stage", "rhs", "pcg_init", "pcg_spmv", "mg_down", "mg_down_other",
+            "mg_coarse", "mg_up", "mg_up_other", "mg_coef", "pcg_xmean", "project")
+
 
 def mg_levels(nx: int, ny: int, coarse_cells: int = 1024):
     """Multigrid hierarchy of the library: halve while both sizes are even and
@@ -72,23 +88,27 @@ def mg_levels(nx: int, ny: int, coarse_cells: int = 1024):
     return levels, lc
 
 
-def algo_bytes_per_launch(fam: str, p, coarse_cells: int = 1024) -> float:
-    """Algorithmic bytes of one launch of kernel family `fam` on workload p
-    (`coarse_cells`: the level size from which the single-block coarse kernel
-    runs the V-cycle)."""
-    cells = p.nx * p.ny
+def _coarse_bytes(nx: int, ny: int, coarse_cells: int) -> float:
+    """Right-hand side of the first level the coarse kernel runs read and its
+    correction written, the x- and y-face coefficients of every level from
+    there read, and the dense inverse of the coarsest grid (up to 64 cells)."""
+    levels, lg = mg_levels(nx, ny, coarse_cells)
+    coef = sum(a * b + a * (b + 1) for a, b in levels[lg:])
+    n0 = levels[lg][0] * levels[lg][1]
+    nc = levels[-1][0] * levels[-1][1]
+    dense = nc * nc if nc <= 64 else 0
+    return 8.0 * (2 * n0 + coef + dense)
+
+
+def algo_bytes_per_launch(fam: str, params, coarse_cells: int = 1024) -> float:
+    """Algorithmic bytes of one launch of kernel family `fam` over every
+    instance in `params` (one launch covers all instances of a batch)."""
+    if not isinstance(params, (list, tuple)):
+        params = [params]
     if fam in ALGO_BYTES_PER_CELL:
-        return ALGO_BYTES_PER_CELL[fam] * cells
-    levels, lg = mg_levels(p.nx, p.ny, coarse_cells)
+        return ALGO_BYTES_PER_CELL[fam] * sum(p.nx * p.ny for p in params)
     if fam == "mg_coarse":
-        # right-hand side of the first level it runs read and its correction
-        # written, the x- and y-face coefficients of every level from there
-        # read, and the dense inverse of the coarsest grid (up to 64 cells)
-        coef = sum(a * b + a * (b + 1) for a, b in levels[lg:])
-        n0 = levels[lg][0] * levels[lg][1]
-        nc = levels[-1][0] * levels[-1][1]
-        dense = nc * nc if nc <= 64 else 0
-        return 8 * (2 * n0 + coef + dense)
+        return sum(_coarse_bytes(p.nx, p.ny, coarse_cells) for p in params)
     raise KeyError(fam)
 
 
@@ -117,6 +137,23 @@ def step_bytes_per_cell(iters_per_step: float) -> float:
     per_stage = b["phase_prep"] + b["stage"] + b["rhs"] + b["pcg_init"] + b["project"]
     per_iter = b["pcg_spmv"] + b["mg_down"] + b["mg_up"] + MG_COARSE_BYTES_PER_FINE_CELL
     return 4 * per_stage + iters_per_step * per_iter
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def family_times(s, steps: int, families=FAMILIES):
+    """Device time (ms) and launch count of every kernel family over `steps`
+    steps each, one family timed at a time."""
+    out = {}
+    for k in families:
+        s.timing_enable(k)
+        s.step(steps)
+        ms, n = s.timing_read()
+        out[k] = (ms, n)
+    s.timing_enable(None)
+    return out
 
 
 def hbm_case(CDISolver, nx: int = 2048, steps: int = 10):
@@ -149,6 +186,7 @@ def hbm_case(CDISolver, nx: int = 2048, steps: int = 10):
     dt = time.perf_counter() - t0
     cells = case.params.nx * case.params.ny
     out["mcell_steps_per_s"] = round(cells * steps / dt / 1e6, 2)
+    out["steps"] = steps
     bpc = step_bytes_per_cell(iters_per_step)
     out["step"] = {"cg_iters_per_step": iters_per_step, "algo_bytes_per_cell": round(bpc, 1),
                    "achieved": round(bpc * cells * steps / dt / 1e9, 1),
@@ -157,36 +195,130 @@ def hbm_case(CDISolver, nx: int = 2048, steps: int = 10):
     return out
 
 
+ENSEMBLE = "ensemble64"
+
+
 def workload(name: str):
+    """List of cases of a named workload (one entry for a single grid)."""
+    if name in (ENSEMBLE, "config4"):
+        return W.config4()
     if name in ("couette256x64", "config2"):
-        return W.config2()
+        return [W.config2()]
     if name in ("drop64x32", "config1"):
-        return W.config1()
+        return [W.config1()]
     if name.startswith("drop") and "x" in name:
         nx = int(name[4:].split("x")[0])
-        return W.drop_case(nx, nx // 2, 60.0, 10.0, steps=200, name=f"drop{nx}x{nx // 2}_r10")
+        return [W.drop_case(nx, nx // 2, 60.0, 10.0, steps=200, name=f"drop{nx}x{nx // 2}_r10")]
     raise SystemExit(f"unknown workload {name}")
 
 
-def cpu_baseline(case, budget_s: float = 12.0, max_steps: int = 2000):
-    """The oracle as it stands, single-threaded NumPy/SciPy, on the first
-    steps of the same workload until `budget_s` of CPU time is used."""
-    from oracle import cdi
-    s = cdi.initial_state(case.phi0)
+def _cells(cases) -> int:
+    return sum(c.params.nx * c.params.ny for c in cases)
+
+
+def timed_rate(s, cases, steps: int):
+    """Mcell-steps/s of `steps` steps, between two device synchronisations,
+    with no instrumentation enabled."""
+    import torch
+    s.timing_enable(None)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    n = 0
-    while n < max_steps:
-        s = cdi.step(s, case.params)
-        n += 1
-        if time.perf_counter() - t0 > budget_s:
-            break
+    s.step(steps)
+    torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    cells = case.params.nx * case.params.ny
-    return dict(value=cells * n / dt / 1e6, unit="Mcell-steps/s", cores=1, kind="oracle",
-                sample=f"first {n} steps of {case.name} from its initial state "
-                       f"({dt:.1f} s, NumPy/SciPy FP64, one thread)")
+    return _cells(cases) * steps / dt / 1e6, dt
 
 
+def secondary_rate(CDISolver, name: str, precision: str, steps: int, warmup: int = 10,
+                   tune: bool = True):
+    """Throughput of another workload / precision (reported beside the headline)."""
+    cases = workload(name)
+    s = CDISolver([c.params for c in cases], [c.phi0 for c in cases], precision=precision,
+                  guess="prev", rtol=1e-10)
+    s.step(warmup)
+    tuned = s.tune(trial_steps=5) if tune else None
+    rate, dt = timed_rate(s, cases, steps)
+    d = s.diagnostics()
+    out = {"workload": name, "precision": precision, "value": round(rate, 3),
+           "unit": "Mcell-steps/s", "steps": steps, "ms_per_step": round(dt / steps * 1e3, 4),
+           "launch": s.get_launch(), "last_pcg_iters": d["last_iters"]}
+    if tuned:
+        out["tile_rows"], out["coarse_cells"] = tuned["tile_rows"], tuned["coarse_cells"]
+        out["mg_smooth"] = tuned["mg_smooth"]
+    s.close()
+    return out
+
+
+# ----------------------------------------------------------- CPU baseline
+def _oracle_instance_step(args):
+    """One oracle step of ensemble instance k from its initial state (CPU
+    child process, one thread).  Returns (cells, seconds)."""
+    k, name = args
+    from oracle import cdi
+    c = workload(name)[k]
+    s = cdi.initial_state(c.phi0)
+    t0 = time.perf_counter()
+    cdi.step(s, c.params)
+    return c.params.nx * c.params.ny, time.perf_counter() - t0
+
+
+def _cpu_leg(name: str, workers: int, budget_s: float):
+    """Child-process body of the CPU baseline: the oracle's first step of the
+    workload's instances, over `workers` processes of one thread each (all
+    instances), or in one thread in order until `budget_s` seconds."""
+    t0 = time.perf_counter()
+    n_inst = len(workload(name))
+    if workers > 1:
+        import multiprocessing as mp
+        with mp.get_context("fork").Pool(workers) as pool:
+            res = pool.map(_oracle_instance_step, [(k, name) for k in range(n_inst)],
+                           chunksize=1)
+        wall = time.perf_counter() - t0
+        cells = sum(r[0] for r in res)
+        done = n_inst
+    else:
+        cells, done = 0, 0
+        for k in range(n_inst):
+            c, _ = _oracle_instance_step((k, name))
+            cells += c
+            done += 1
+            if time.perf_counter() - t0 > budget_s:
+                break
+        wall = time.perf_counter() - t0
+    print(json.dumps({"cells": cells, "instances": done, "wall_s": wall}), flush=True)
+
+
+def cpu_baseline(name: str, budget_s: float = 15.0):
+    """The oracle as it stands (NumPy/SciPy FP64, never tuned for this),
+    timed in child processes that never touch the GPU: once with one process
+    per core over all of the workload's instances, once in a single thread
+    on the first instances within `budget_s`.  Each instance takes one step
+    from its initial state."""
+    cores = min(os.cpu_count() or 1, 16)
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    legs = {}
+    for workers in (cores, 1):
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-leg", name,
+                            "--cpu-workers", str(workers), "--cpu-budget", str(budget_s)],
+                           env=env, capture_output=True, text=True, timeout=600)
+        if r.returncode != 0:
+            raise RuntimeError("CPU baseline leg failed:\n" + r.stderr[-2000:])
+        legs[workers] = json.loads(r.stdout.strip().splitlines()[-1])
+    multi, single = legs[cores], legs[1]
+    n_inst = len(workload(name))
+    return dict(
+        value=multi["cells"] / multi["wall_s"] / 1e6, unit="Mcell-steps/s", cores=cores,
+        kind="oracle",
+        sample=(f"first step of each of the {multi['instances']} instances of {name} from its "
+                f"initial state, {cores} single-threaded processes ({multi['wall_s']:.1f} s wall, "
+                f"NumPy/SciPy FP64)"),
+        single_thread=dict(
+            value=single["cells"] / single["wall_s"] / 1e6, unit="Mcell-steps/s", cores=1,
+            sample=(f"first step of the first {single['instances']} of {n_inst} instances of "
+                    f"{name} from their initial state, one thread ({single['wall_s']:.1f} s)")))
+
+
+# ------------------------------------------------- learned vs plain Poisson
 def poisson_learned_vs_plain(nx: int = 2048, train_iters: int = 300, verbose: bool = False):
     """Pressure time-to-solution at relative residual 1e-10 on the 2048x1024
     density-ratio-10 grid: zero guess, previous-step pressure and the learned
@@ -212,6 +344,7 @@ def poisson_learned_vs_plain(nx: int = 2048, train_iters: int = 300, verbose: bo
     t_train = time.perf_counter() - t1
     params = net.params.cpu().numpy()
     net.close()
+    n_snap = len(data)
     del data
     rows = []
     for case in (W.config5("drop", nx), W.config5("couette", nx)):
@@ -244,7 +377,7 @@ def poisson_learned_vs_plain(nx: int = 2048, train_iters: int = 300, verbose: bo
         "ms_zero": round(mean("zero", 1), 3), "ms_prev": round(mean("prev", 1), 3),
         "ms_learned": round(mean("learned", 1), 3),
         "ms_inference": round(net_ms / max(net_n, 1), 3),
-        "train": {"snapshots": 24, "iters": train_iters, "batch": 8, "crop": 256,
+        "train": {"snapshots": n_snap, "iters": train_iters, "batch": 8, "crop": 256,
                   "loss_first10pct": round(train_guess.loss_summary(losses)[0], 4),
                   "loss_last10pct": round(train_guess.loss_summary(losses)[1], 4),
                   "train_s": round(t_train, 2), "collect_s": round(t_collect, 2)},
@@ -254,9 +387,9 @@ def poisson_learned_vs_plain(nx: int = 2048, train_iters: int = 300, verbose: bo
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="couette256x64")
+    ap.add_argument("--workload", default=ENSEMBLE)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--kernel", default="auto",
                     help="kernel family for the roofline entry (auto: largest device time)")
@@ -270,12 +403,20 @@ def main():
                     help="with --launch tiled: red-black sweep pairs per smoothing (1 or 2)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-hbm-case", action="store_true",
-                    help="skip the per-kernel HBM fractions on the 2048x1024 grid")
+                    help="skip the per-kernel HBM fractions on the 2048x1024 and 8192x4096 grids")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="skip the mixed-precision ensemble and the Couette 256x64 lines")
+    ap.add_argument("--no-poisson", action="store_true",
+                    help="skip the learned-vs-plain pressure time-to-solution at 2048x1024")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with a 256 MiB device copy (calibrates rocprofv3 --pmc byte counters)")
-    ap.add_argument("--poisson", action="store_true",
-                    help="add the learned-vs-plain pressure time-to-solution at 2048x1024")
+    ap.add_argument("--cpu-leg", default=None, help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-workers", type=int, default=1, help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-budget", type=float, default=15.0, help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.cpu_leg:
+        _cpu_leg(args.cpu_leg, args.cpu_workers, args.cpu_budget)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the library "
               "advances its instances on a single GPU and has no multi-GPU decomposition.",
@@ -285,9 +426,11 @@ def main():
     import torch
     from paper_2412_16843_amd.solver import CDISolver
 
-    case = workload(args.workload)
-    p = case.params
-    s = CDISolver(p, case.phi0, precision=args.precision, guess="prev", rtol=1e-10)
+    cases = workload(args.workload)
+    params = [c.params for c in cases]
+    log(f"workload {args.workload}: {len(cases)} instance(s), {_cells(cases)} cells")
+    s = CDISolver(params, [c.phi0 for c in cases], precision=args.precision, guess="prev",
+                  rtol=1e-10)
     if args.launch != "auto":
         # a fixed launch form and shape, e.g. the autotuner's pick, for
         # profiler runs (which would otherwise tune under the profiler)
@@ -303,33 +446,33 @@ def main():
     tuned = None
     if args.launch == "auto":   # the tuner times candidates from the warmed-up state
         tuned = s.tune(trial_steps=10)
+        log(f"tuned: {tuned['launch']} rows {tuned['tile_rows']} coarse {tuned['coarse_cells']} "
+            f"nu {tuned['mg_smooth']}")
 
-    # dominant kernel: device time per family over a short probe run
+    # the headline: K steps with no instrumentation
+    value, elapsed = timed_rate(s, cases, args.steps)
+    d = s.diagnostics(0)
+    log(f"timed {args.steps} steps: {elapsed * 1e3 / args.steps:.3f} ms/step, {value:.2f} "
+        "Mcell-steps/s")
+
+    # separate pass: device time of every kernel family (its own launches'
+    # start / end timestamps), the dominant one is the roofline entry
+    probe = 5
+    fam_t = family_times(s, probe)
+    kernel_ms = {k: round(ms / probe, 4) for k, (ms, n) in fam_t.items() if n}
     fam = args.kernel
     if fam == "auto":
-        best = (-1.0, None)
-        for k in list(ALGO_BYTES_PER_CELL) + ["mg_coarse"]:
-            s.timing_enable(k)
-            s.step(5)
-            ms, n = s.timing_read()
-            if ms > best[0]:
-                best = (ms, k)
-        fam = best[1]
-    s.timing_enable(fam)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    s.step(args.steps)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    k_ms, k_n = s.timing_read()
-    s.timing_enable(None)
-    d = s.diagnostics()
-    elapsed = t1 - t0
-    cells = p.nx * p.ny
-    value = cells * args.steps / elapsed / 1e6
-    per_launch_bytes = algo_bytes_per_launch(fam, p, s.get_coarse_cells())
+        fam = max(fam_t, key=lambda k: fam_t[k][0])
+    k_ms, k_n = fam_t[fam] if fam in fam_t else (0.0, 0)
+    coarse_cells = s.get_coarse_cells()
+    try:
+        per_launch_bytes = algo_bytes_per_launch(fam, params, coarse_cells)
+    except KeyError:
+        per_launch_bytes = None
     avg_s = (k_ms / max(k_n, 1)) * 1e-3
-    achieved = per_launch_bytes / avg_s / 1e9 if avg_s > 0 else 0.0
+    achieved = per_launch_bytes / avg_s / 1e9 if (avg_s > 0 and per_launch_bytes) else 0.0
+    name = args.workload if len(cases) > 1 else cases[0].name
+    iters_per_step = fam_t["pcg_spmv"][1] / probe if fam_t.get("pcg_spmv") else None
     out = {
         "metric": "Mcell-steps/s per CDI-GNBC step",
         "value": round(value, 4),
@@ -343,21 +486,27 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": case.name, "nx": p.nx, "ny": p.ny,
+        "config": {"workload": name, "instances": len(cases), "cells": _cells(cases),
+                   "grids": (f"{min(p.nx for p in params)}x{min(p.ny for p in params)} .. "
+                             f"{max(p.nx for p in params)}x{max(p.ny for p in params)}"),
                    "precision": args.precision, "poisson_rtol": 1e-10,
-                   "last_pcg_iters": d["last_iters"], "launch": s.get_launch(),
-                   "tile_rows": s.get_tile_rows(), "coarse_cells": s.get_coarse_cells(),
-                   "mg_smooth": s.get_mg_smooth(),
-                   "autotune": tuned,
-                   "parallelism": "single-gpu"},
+                   "cg_iters_per_step": iters_per_step,
+                   "launch": s.get_launch(), "tile_rows": s.get_tile_rows(),
+                   "coarse_cells": coarse_cells, "mg_smooth": s.get_mg_smooth(),
+                   "autotune": tuned, "parallelism": "single-gpu"},
         "roofline": {"bound": "hbm", "kernel": fam, "achieved": round(achieved, 2),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 5),
-                     "traffic": traffic_record(fam, case.name),
+                     "traffic": traffic_record(fam, name),
                      "launches": k_n, "avg_launch_us": round(avg_s * 1e6, 3),
-                     "algo_bytes_per_launch": per_launch_bytes},
+                     "algo_bytes_per_launch": per_launch_bytes,
+                     "share_of_device_time": round(k_ms / max(1e-9, sum(
+                         ms for ms, _ in fam_t.values())), 4)},
+        "kernel_time_ms_per_step": kernel_ms,
     }
     s.close()
+    del s
+    torch.cuda.empty_cache()
     if args.copy_calibration:
         n = 256 * 2**20 // 8
         a = torch.ones(n, dtype=torch.float64, device="cuda")
@@ -365,14 +514,27 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+    if not args.no_secondary:
+        out["secondary"] = []
+        if args.workload == ENSEMBLE:
+            log("secondary: mixed-precision ensemble")
+            out["secondary"].append(secondary_rate(CDISolver, ENSEMBLE, "mixed", 100))
+        log("secondary: Couette 256x64")
+        out["secondary"].append(secondary_rate(CDISolver, "couette256x64", "fp64", 400,
+                                               warmup=20))
     if not args.no_hbm_case:
         # 2048x1024: ~0.5 GB of state, mostly served by the 256 MB MALL;
         # 8192x4096: ~8 GB, DRAM bound
-        out["roofline_hbm_case"] = [hbm_case(CDISolver, 2048), hbm_case(CDISolver, 8192, steps=3)]
-    if args.poisson:
+        log("HBM cases: 2048x1024 and 8192x4096 drops")
+        out["roofline_hbm_case"] = [hbm_case(CDISolver, 2048), hbm_case(CDISolver, 8192, steps=5)]
+        torch.cuda.empty_cache()
+    if not args.no_poisson:
+        log("learned vs plain pressure guess at 2048x1024")
         out["poisson_learned_vs_plain"] = poisson_learned_vs_plain()
+        torch.cuda.empty_cache()
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(case)
+        log("CPU baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(args.workload)
     print(json.dumps(out), flush=True)
 
 

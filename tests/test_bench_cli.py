@@ -25,3 +25,17 @@ def test_coarse_kernel_algorithmic_bytes():
     assert levels[lg] == (64, 16) and levels[-1] == (16, 4)
     coef = sum(a * b + a * (b + 1) for a, b in levels[lg:])   # x- and y-faces
     assert bench.algo_bytes_per_launch("mg_coarse", p) == 8 * (2 * 1024 + coef + 64 * 64)
+
+
+def test_batch_bytes_sum_over_instances():
+    """A batched launch covers every instance: its algorithmic bytes are the
+    sum of the per-instance figures."""
+    sys.path.insert(0, ROOT)
+    import bench
+    cases = W.config4()
+    ps = [c.params for c in cases]
+    assert bench.algo_bytes_per_launch("stage", ps) == sum(
+        bench.algo_bytes_per_launch("stage", p) for p in ps)
+    assert bench.algo_bytes_per_launch("mg_coarse", ps, 4096) == sum(
+        bench.algo_bytes_per_launch("mg_coarse", p, 4096) for p in ps)
+    assert sum(p.nx * p.ny for p in ps) == 3899904

@@ -83,3 +83,27 @@ def test_adam_moves_downhill():
         losses.append(unet.loss(y, t))
         unet.adam(p, unet.backward(p, c, y, t), m, v, s, lr=1e-3)
     assert losses[-1] < losses[0]
+
+
+def test_adam_two_steps_match_hand_computed_values():
+    """Adam (Kingma & Ba, bias-corrected moments; beta1 0.9, beta2 0.999,
+    eps 1e-8 added to the square root) on one scalar parameter p0 = 1 with
+    lr 0.1 and gradients 2, then -1, worked by hand in exact fractions:
+      step 1: m = 1/5, v = 1/250, m_hat = 2, v_hat = 4,
+              p1 = 1 - 0.1 * 2 / (2 + 1e-8)                = 0.9000000005
+      step 2: m = 9/10 * 1/5 - 1/10 = 2/25,
+              v = 999/1000 * 1/250 + 1/1000 = 1249/250000,
+              m_hat = (2/25) / (1 - 0.81)    = 8/19,
+              v_hat = (1249/250000) / (1 - 0.998001) = 4996/1999,
+              p2 = p1 - 0.1 * (8/19) / (sqrt(4996/1999) + 1e-8)
+                 = 0.8733662967024313
+    and the moments carried between the steps are the fractions above."""
+    p = {"w": np.array([1.0])}
+    m = {"w": np.zeros(1)}
+    v = {"w": np.zeros(1)}
+    unet.adam(p, {"w": np.array([2.0])}, m, v, 1, lr=0.1)
+    assert abs(m["w"][0] / 0.2 - 1) < 1e-14 and abs(v["w"][0] / 0.004 - 1) < 1e-14
+    assert abs(p["w"][0] - 0.9000000005) < 2e-15
+    unet.adam(p, {"w": np.array([-1.0])}, m, v, 2, lr=0.1)
+    assert abs(m["w"][0] / 0.08 - 1) < 1e-14 and abs(v["w"][0] / 0.004996 - 1) < 1e-14
+    assert abs(p["w"][0] - 0.8733662967024313) < 2e-15
