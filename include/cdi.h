@@ -201,6 +201,31 @@ cdi_status cdi_diagnostics(cdi_ctx* ctx, int32_t idx, cdi_diag* out);
 cdi_status cdi_eval_rhs(cdi_ctx* ctx, double* l_phi, double* l_mx, double* l_my,
                         double* u_y, double* u_slip);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the stage
+ * operator of cdi_eval_rhs for one instance without a context or workspace.
+ * params: the problem as for cdi_init (validated the same way; the solver
+ * fields poisson_* and guess are ignored); fields: device pointers phi, u, v
+ * (p is not read), layouts as above; outputs as for cdi_eval_rhs: L_phi and
+ * L_mx (ny*nx), L_my ((ny+1)*nx, wall rows written as 0), and, when non-NULL,
+ * u^Y and u_wall - U_wall per wall corner (2*nx each, bottom then top).  All
+ * work is enqueued on hip_stream (NULL = default stream) and the call
+ * returns without synchronising.
+ * Its scratch (instance descriptor, tile list, the phase-field quantities n
+ * and mu_c, wall extrapolations, reduction partials and counters) lives in a
+ * file-scope device array of CDI_NOALLOC_SCRATCH_BYTES bytes that every GPU
+ * the library runs on holds until the process ends; the call performs no
+ * device or pinned-host allocation and no memset (a kernel clears the
+ * counters).  A grid whose scratch does not fit (about 2.6 M cells in FP64,
+ * more on the mixed path) returns CDI_ERR_SHAPE.  Every call on one GPU
+ * shares that GPU's array and keeps the last call's contents: calls that
+ * overlap on one GPU (different streams or host threads without ordering)
+ * race. */
+#define CDI_NOALLOC_SCRATCH_BYTES (64u * 1024u * 1024u)
+cdi_status cdi_eval_rhs_noalloc(const cdi_params* params, const cdi_fields* fields,
+                                double* l_phi, double* l_mx, double* l_my, double* u_y,
+                                double* u_slip, void* hip_stream);
+
 /* Measurement hook.  While enabled, every launch of the named kernel family
  * ("phase_prep", "stage", "rhs", "pcg_init", "mg_down" (finest level, with the
  * fused CG update), "mg_down_other", "mg_coarse", "mg_up" (finest level),

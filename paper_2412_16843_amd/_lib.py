@@ -29,7 +29,7 @@ EXPORTS = ("cdi_workspace_bytes", "cdi_default_dt", "cdi_init", "cdi_init_batch"
            "cdi_get_launch", "cdi_set_tile_rows", "cdi_get_tile_rows", "cdi_tune_bytes",
            "cdi_tune", "cdi_graph_stats", "cdi_set_coarse_cells", "cdi_get_coarse_cells",
            "cdi_set_mg_smooth", "cdi_get_mg_smooth", "cdi_set_extrapolation",
-           "cdi_get_extrapolation")
+           "cdi_get_extrapolation", "cdi_eval_rhs_noalloc")
 
 
 class cdi_params(C.Structure):
@@ -105,6 +105,8 @@ def lib() -> C.CDLL:
     L.cdi_diagnostics.restype = i32
     L.cdi_eval_rhs.argtypes = [vp, vp, vp, vp, vp, vp]
     L.cdi_eval_rhs.restype = i32
+    L.cdi_eval_rhs_noalloc.argtypes = [P(cdi_params), P(cdi_fields), vp, vp, vp, vp, vp, vp]
+    L.cdi_eval_rhs_noalloc.restype = i32
     L.cdi_timing_enable.argtypes = [vp, C.c_char_p]
     L.cdi_timing_enable.restype = i32
     L.cdi_timing_read.argtypes = [vp, P(f64), P(C.c_int64)]

@@ -10,6 +10,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -1503,6 +1504,155 @@ void cdi_destroy(cdi_ctx* c) {
   if (c->ev1) (void)hipEventDestroy(c->ev1);
   for (auto e : c->tev) if (e) (void)hipEventDestroy(e);
   delete c;
+}
+
+}  // extern "C"
+
+// ============================================== allocation-free stage operator
+// cdi_eval_rhs_noalloc: the stage operator of cdi_eval_rhs with its scratch
+// (instance descriptor, tile list, CG scalars, reduction partials and
+// counters, n, mu_c, wall extrapolations) in a file-scope device array
+// instead of a caller workspace, and no context.
+namespace {
+
+constexpr int kMaxDevices = 64;
+
+// Scratch layout of one call (offsets in bytes from the array's device
+// address); with base == nullptr only the size is computed.
+struct NoAllocLayout {
+  size_t inst, pcg, counters, part, tiles, nhx, nhy, muc, wall, uY, uslip, total;
+};
+
+NoAllocLayout noalloc_layout(const Resolved& R) {
+  const size_t nc = (size_t)R.p.nx * R.p.ny;
+  const size_t S = R.p.precision == CDI_MIXED ? sizeof(float) : sizeof(double);
+  const size_t nt = (size_t)cell_tiles(R);
+  NoAllocLayout L;
+  size_t off = 0;
+  auto take = [&](size_t bytes) { const size_t o = off; off = align256(off + bytes); return o; };
+  L.inst = take(sizeof(Inst));
+  L.pcg = take(sizeof(PcgScalars));
+  L.counters = take(sizeof(unsigned) * 8 * kCounterStride);
+  L.part = take(sizeof(double) * 8 * nt);
+  L.tiles = take(sizeof(Tile) * nt);
+  L.nhx = take(nc * S);
+  L.nhy = take(nc * S);
+  L.muc = take(nc * S);
+  L.wall = take(sizeof(double) * 10 * (size_t)R.p.nx);
+  L.uY = take(sizeof(double) * 2 * (size_t)R.p.nx);
+  L.uslip = take(sizeof(double) * 2 * (size_t)R.p.nx);
+  L.total = off;
+  return L;
+}
+
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+}  // namespace
+
+// The scratch array.  Host code never passes this name to a kernel or a copy:
+// it uses the device address that hipGetSymbolAddress returns for the
+// current device (each GPU holds its own copy of the array).
+static __device__ __align__(256) char scratch[CDI_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+// Device address of `scratch` on the current device, looked up once per device.
+cdi_status scratch_address(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(CDI_ERR_DEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices) return fail(CDI_ERR_DEVICE, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(CDI_ERR_DEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return CDI_OK;
+}
+
+// One launch that prepares a call in the scratch: the instance descriptor
+// (passed by value), its CG scalars' regularisation velocity, the level-0
+// cell tile list, cleared arrival counters (their reductions start from
+// zero), and the two wall rows of L_my, which the stage kernel leaves alone.
+__global__ void k_noalloc_setup(Inst I, Inst* __restrict__ dst, Tile* __restrict__ tiles,
+                                int ntx, int ntiles, unsigned* __restrict__ counters,
+                                int ncounters, double* __restrict__ l_my) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g == 0) {
+    *dst = I;
+    I.pcg->gamma_step = I.gamma;
+  }
+  if (g < ntiles) tiles[g] = Tile{0, (g % ntx) * TX, (g / ntx) * TY, 0, g, {0, 0, 0}};
+  if (g < ncounters) counters[g] = 0u;
+  if (g < I.nx) {
+    l_my[g] = 0.0;
+    l_my[(size_t)I.ny * I.nx + g] = 0.0;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+cdi_status cdi_eval_rhs_noalloc(const cdi_params* params, const cdi_fields* fields,
+                                double* l_phi, double* l_mx, double* l_my, double* u_y,
+                                double* u_slip, void* hip_stream) {
+  Resolved R;
+  cdi_status s = resolve(params, R);
+  if (s != CDI_OK) return s;
+  if (!fields || !fields->phi || !fields->u || !fields->v)
+    return fail(CDI_ERR_ARG, "fields (phi, u, v) must be non-NULL");
+  if (!l_phi || !l_mx || !l_my) return fail(CDI_ERR_ARG, "output pointer is NULL");
+  const NoAllocLayout Lo = noalloc_layout(R);
+  if (Lo.total > (size_t)CDI_NOALLOC_SCRATCH_BYTES)
+    return fail(CDI_ERR_SHAPE,
+                "grid %dx%d needs %zu bytes of scratch, more than the %zu bytes of the "
+                "allocation-free entry point", R.p.nx, R.p.ny, Lo.total,
+                (size_t)CDI_NOALLOC_SCRATCH_BYTES);
+  void* base_v = nullptr;
+  s = scratch_address(&base_v);
+  if (s != CDI_OK) return s;
+  char* base = (char*)base_v;
+  hipStream_t st = (hipStream_t)hip_stream;
+  Inst I{};
+  fill_inst(R, *fields, I);
+  const int ntx = ceil_div(R.p.nx, TX), ntiles = cell_tiles(R);
+  I.first_tile = 0;
+  I.ntiles = ntiles;
+  I.pcg = (PcgScalars*)(base + Lo.pcg);
+  I.counters = (unsigned*)(base + Lo.counters);
+  I.part = (double*)(base + Lo.part);
+  I.nhx = base + Lo.nhx;
+  I.nhy = base + Lo.nhy;
+  I.muc = base + Lo.muc;
+  I.wall = (double*)(base + Lo.wall);
+  I.uY = u_y ? u_y : (double*)(base + Lo.uY);
+  I.uslip = u_slip ? u_slip : (double*)(base + Lo.uslip);
+  I.acc_phi = l_phi;
+  I.acc_mx = l_mx;
+  I.acc_my = l_my;
+  Inst* d_inst = (Inst*)(base + Lo.inst);
+  Tile* d_tiles = (Tile*)(base + Lo.tiles);
+  const int ncount = 8 * kCounterStride;
+  const int nset = std::max(std::max(ntiles, ncount), R.p.nx);
+  k_noalloc_setup<<<(unsigned)ceil_div(nset, kNT), kNT, 0, st>>>(
+      I, d_inst, d_tiles, ntx, ntiles, I.counters, ncount, l_my);
+  if (R.p.gamma_factor > 0)
+    k_gamma_step<<<(unsigned)ntiles, kNT, 0, st>>>(d_tiles, d_inst);
+  if (R.p.precision == CDI_MIXED) {
+    k_phase_prep<float, 1><<<(unsigned)ntiles, kNT, 0, st>>>(d_tiles, d_inst, 0);
+    k_stage<float><<<(unsigned)ntiles, kNT, 0, st>>>(d_tiles, d_inst, -1, 0, 0, 0.0, 0.0, 1);
+  } else {
+    k_phase_prep<double, 1><<<(unsigned)ntiles, kNT, 0, st>>>(d_tiles, d_inst, 0);
+    k_stage<double><<<(unsigned)ntiles, kNT, 0, st>>>(d_tiles, d_inst, -1, 0, 0, 0.0, 0.0, 1);
+  }
+  HIPCHK(hipGetLastError());
+  return CDI_OK;
 }
 
 }  // extern "C"

@@ -121,3 +121,24 @@ def test_smoothing_sweeps_validated_on_host():
     assert lib.cdi_workspace_bytes(C.byref(cp), 1) == 0
     assert lib.cdi_init(C.byref(cp), C.byref(f), 256, 1 << 30, None, C.byref(ctx)) == -1
     assert b"mg_smooth" in lib.cdi_last_error()
+
+
+def test_noalloc_entry_point_rejects_a_grid_beyond_its_scratch():
+    """cdi_eval_rhs_noalloc checks the scratch its grid needs against the
+    fixed array before any device work: a 4096 x 2048 grid (8.4 M cells)
+    does not fit the 64 MiB and returns CDI_ERR_SHAPE with a message."""
+    L = _lib()
+    lib = L.lib()
+    case = W.drop_case(4096, 2048, 60.0, 10.0)
+    cp = L.make_params(case.params)
+    dummy = 256   # never dereferenced: the size check comes first
+    cf = L.cdi_fields(dummy, dummy, dummy, None)
+    st = lib.cdi_eval_rhs_noalloc(C.byref(cp), C.byref(cf), dummy, dummy, dummy, None, None,
+                                  None)
+    assert st == -2
+    assert b"scratch" in lib.cdi_last_error()
+    # a null field pointer is an argument error, also before any device work
+    cf0 = L.cdi_fields(None, dummy, dummy, None)
+    small = L.make_params(W.config1().params)
+    assert lib.cdi_eval_rhs_noalloc(C.byref(small), C.byref(cf0), dummy, dummy, dummy, None,
+                                    None, None) == -1
