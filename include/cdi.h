@@ -50,7 +50,7 @@
 extern "C" {
 #endif
 
-#define CDI_ABI_VERSION 2
+#define CDI_ABI_VERSION 3
 
 typedef enum {
   CDI_OK = 0,
@@ -140,6 +140,17 @@ typedef struct {
   int32_t last_iters;  /* iterations of the last pressure solve                  */
   int32_t nonfinite;   /* 1 if a NaN / Inf was found                             */
   double last_relres;
+  /* Contact lines (Sec. 5.1 measures): where the wall phase field,
+   * extrapolated per column from the first two cell rows (Sec. 4), crosses
+   * 1/2, by linear interpolation between column centres (x periodic). */
+  int32_t n_contact[2];  /* crossings per wall (0 bottom, 1 top)                 */
+  double contact_x[4];   /* the first two crossings of each wall in column order:
+                            bottom x0, x1, then top x0, x1; 0 where absent      */
+  double wetted_len[2];  /* |x1 - x0| of a wall with exactly two crossings, else 0 */
+  double theta_est[2];   /* contact angle (radians) of the circular cap with chord
+                            wetted_len and area `mass` (root of
+                            (L / (2 sin t))^2 (t - sin t cos t) = mass), meaningful
+                            for a single drop on that wall; 0 when wetted_len is 0 */
 } cdi_diag;
 
 /* Bytes of caller-provided device workspace for `n` instances described by
@@ -188,8 +199,12 @@ cdi_status cdi_step(cdi_ctx* ctx, int32_t nsteps);
  * zero gives p = 0 without an iteration. */
 cdi_status cdi_solve_pressure(cdi_ctx* ctx, const double* b, double* p, cdi_solve_info* info);
 
-/* Diagnostics of instance `idx` for its current state (FP64 reductions on the
- * device).  Synchronises the stream. */
+/* Diagnostics of instance `idx` for its current state, computed on the device
+ * (FP64 reductions; contact-line positions, wetted length and cap angle of
+ * Sec. 5.1): mass and phase-field bounds (Sec. 2, conservation and
+ * boundedness), slip maxima (Sec. 2 slip BC), contact lines (Sec. 5.1).
+ * Synchronises the stream.  Returns CDI_ERR_NONFINITE (after filling `out`)
+ * when the state holds a NaN or Inf. */
 cdi_status cdi_diagnostics(cdi_ctx* ctx, int32_t idx, cdi_diag* out);
 
 /* Stage operator of instance 0 on its current fields (no time update, no

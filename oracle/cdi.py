@@ -478,9 +478,12 @@ def diagnostics(s: State, p) -> Dict[str, float]:
                max_uY_bot=float(np.max(np.abs(walls["bot"]["uY"]))),
                max_uY_top=float(np.max(np.abs(walls["top"]["uY"]))),
                ke=float(ke))
-    cps = contact_points(walls["bot"]["phi_w"], h)
-    if len(cps) == 2:
-        L = abs(cps[1] - cps[0])
-        out["wetted_len_bot"] = L
-        out["theta_est_bot"] = cap_angle(L, out["mass"])
+    for wall in ("bot", "top"):
+        cps = contact_points(walls[wall]["phi_w"], h)
+        out[f"n_contact_{wall}"] = len(cps)
+        out[f"contact_x_{wall}"] = cps[:2]
+        if len(cps) == 2:
+            L = abs(cps[1] - cps[0])
+            out[f"wetted_len_{wall}"] = L
+            out[f"theta_est_{wall}"] = cap_angle(L, out["mass"])
     return out

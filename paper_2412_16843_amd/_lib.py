@@ -12,7 +12,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libcdi.so")
 
-CDI_ABI_VERSION = 2
+CDI_ABI_VERSION = 3
 STATUS = {0: "CDI_OK", -1: "CDI_ERR_ARG", -2: "CDI_ERR_SHAPE", -3: "CDI_ERR_DEVICE",
           -4: "CDI_ERR_NOCONV", -5: "CDI_ERR_NONFINITE", -6: "CDI_ERR_STATE"}
 SLIP = {"1A": 0, "1B": 1, "2A": 2, "2B": 3, "3A": 4, "3B": 5, "4A": 6, "4B": 7}
@@ -60,7 +60,9 @@ class cdi_diag(C.Structure):
                 ("mass0", C.c_double), ("phi_min", C.c_double), ("phi_max", C.c_double),
                 ("max_div", C.c_double), ("max_uslip", C.c_double * 2),
                 ("max_uY", C.c_double * 2), ("ke", C.c_double), ("last_iters", C.c_int32),
-                ("nonfinite", C.c_int32), ("last_relres", C.c_double)]
+                ("nonfinite", C.c_int32), ("last_relres", C.c_double),
+                ("n_contact", C.c_int32 * 2), ("contact_x", C.c_double * 4),
+                ("wetted_len", C.c_double * 2), ("theta_est", C.c_double * 2)]
 
 
 class cdi_tune_info(C.Structure):

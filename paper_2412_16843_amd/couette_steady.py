@@ -6,8 +6,11 @@ generalized Navier boundary condition balances the wall motion.  At steady
 state each contact line is at rest, so the wall velocity there vanishes:
 u_wall = U_wall + u_slip = 0, i.e. the slip at the contact line equals
 -U_wall.  The run reports the four contact-line positions (phi = 1/2
-crossings of the wall value extrapolated from the first two rows), their
-drift over the last output interval and the wall velocity at each of them.
+crossings of the wall value extrapolated from the first two rows, from the
+library's device diagnostics), their drift over the last output interval and
+the wall velocity at each of them.  On each wall the slab of fluid 1 gives
+two crossings; in column order the first is where phi rises through 1/2
+(the slab's left edge) and the second where it falls.
 
     python -m paper_2412_16843_amd.couette_steady --variant asymmetric --t-end 600
 """
@@ -20,23 +23,6 @@ import time
 import numpy as np
 
 import workloads as W
-
-
-def crossings(w: np.ndarray, h: float):
-    """Positions (x) of the phi = 1/2 crossings of a periodic wall profile,
-    linear between cell centres: (rising, falling) in x."""
-    n = w.size
-    up, down = [], []
-    for i in range(n):
-        a, b = w[i] - 0.5, w[(i + 1) % n] - 0.5
-        if a * b < 0 or (a == 0.0 and b != 0.0):
-            x = (i + 0.5 + a / (a - b)) * h
-            (up if b > a else down).append(x % (n * h))
-    return up, down
-
-
-def wall_profiles(phi: np.ndarray):
-    return 1.5 * phi[0] - 0.5 * phi[1], 1.5 * phi[-1] - 0.5 * phi[-2]
 
 
 def sample(x: float, f: np.ndarray, h: float) -> float:
@@ -64,10 +50,8 @@ def run(variant: str, nx: int, t_end: float, outputs: int, gamma_factor: float) 
     prev = None
     for k in range(outputs):
         s.step(per)
-        g = s.state()
-        bot, top = wall_profiles(g["phi"])
-        cl = {"bot": crossings(bot, h), "top": crossings(top, h)}
-        pos = np.array(sorted(cl["bot"][0] + cl["bot"][1]) + sorted(cl["top"][0] + cl["top"][1]))
+        d = s.diagnostics()
+        pos = np.array(d["contact_x_bot"] + d["contact_x_top"])
         drift = float(np.abs(pos - prev).max()) if prev is not None and pos.shape == prev.shape else None
         prev = pos
         print(f"{variant} t {(k + 1) * per * p.dt:8.2f} contact lines {np.round(pos, 3).tolist()} "
@@ -77,20 +61,18 @@ def run(variant: str, nx: int, t_end: float, outputs: int, gamma_factor: float) 
     slip = s.eval_rhs()[4].cpu().numpy()        # [2][nx]: bottom, top corner slip
     d = s.diagnostics()
     s.close()
-    bot, top = wall_profiles(g["phi"])
     res = {"variant": variant, "nx": nx, "ny": nx // 8, "t": outputs * per * p.dt,
            "steps": outputs * per, "gamma_factor": gamma_factor,
            "contact_lines": {}, "last_drift": drift,
            "mass_drift": abs(d["mass"] - d["mass0"]) / d["mass0"],
            "phi_min": d["phi_min"], "phi_max": d["phi_max"]}
-    for wall, prof, U, row in (("bot", bot, p.u_wall_bot, 0), ("top", top, p.u_wall_top, 1)):
-        up, down = crossings(prof, h)
-        for name, xs in (("rising", up), ("falling", down)):
-            for x in xs:
-                # the slip array is indexed by wall corner, corner i at x = i h
-                us = sample(x, slip[row], h)
-                res["contact_lines"][f"{wall}_{name}_{x:.3f}"] = {
-                    "x": x, "u_slip": us, "u_wall": U + us}
+    for wall, U, row in (("bot", p.u_wall_bot, 0), ("top", p.u_wall_top, 1)):
+        xs = d[f"contact_x_{wall}"]
+        for name, x in zip(("rising", "falling"), xs):
+            # the slip array is indexed by wall corner, corner i at x = i h
+            us = sample(x, slip[row], h)
+            res["contact_lines"][f"{wall}_{name}_{x:.3f}"] = {
+                "x": x, "u_slip": us, "u_wall": U + us}
     return res
 
 

@@ -1155,6 +1155,7 @@ cdi_status cdi_diagnostics(cdi_ctx* c, int32_t idx, cdi_diag* out) {
   else k_phase_prep<double, 1><<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, 0);
   k_wall<<<(unsigned)B.n, kNT, 0, c->stream>>>(c->d_inst);
   k_diag<<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, c->d_diag);
+  k_contact<<<dim3((unsigned)B.n, 2), kNT, 0, c->stream>>>(c->d_inst, c->d_diag);
   HIPCHK(hipGetLastError());
   const Inst& I = B.inst[idx];
   DiagOut d;
@@ -1185,6 +1186,12 @@ cdi_status cdi_diagnostics(cdi_ctx* c, int32_t idx, cdi_diag* out) {
   }
   out->last_iters = c->last_iters[idx];
   out->last_relres = c->last_relres[idx];
+  for (int wl = 0; wl < 2; ++wl) {
+    out->n_contact[wl] = d.n_contact[wl];
+    for (int m = 0; m < kMaxContacts; ++m) out->contact_x[2 * wl + m] = d.contact_x[wl][m];
+    out->wetted_len[wl] = d.wetted_len[wl];
+    out->theta_est[wl] = d.theta_est[wl];
+  }
   return out->nonfinite ? fail(CDI_ERR_NONFINITE, "non-finite value in the state") : CDI_OK;
 }
 

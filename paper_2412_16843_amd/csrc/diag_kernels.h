@@ -2,13 +2,20 @@
 // (mass, phase-field bounds, divergence, kinetic energy, finiteness) and the
 // GNBC wall values of the current state (Sec. 5.1 metrics).
 #pragma once
+#include <climits>
+
 #include "poisson_kernels.h"
 
 namespace cdi {
 
+constexpr int kMaxContacts = 2;   // phi = 1/2 wall crossings stored per wall
+
 struct DiagOut {
   double mass, phi_min, phi_max, max_div, ke, nonfinite;
-  double pad[2];
+  double contact_x[2][kMaxContacts];   // [wall][first crossings in column order]
+  double wetted_len[2], theta_est[2];
+  int n_contact[2];
+  double pad[3];
 };
 
 template <int NV, int NT = kNT>
@@ -111,6 +118,106 @@ __global__ void __launch_bounds__(kNT) k_wall(const Inst* __restrict__ insts) {
     (void)gnbc_corner(I, wall, i, ur, uY, usl);
     I.uY[c] = uY;
     I.uslip[c] = usl;
+  }
+}
+
+// Contact angle of a circular cap whose base chord is L and whose area is
+// `area`: the root on (0, pi) of (L / (2 sin t))^2 (t - sin t cos t) = area
+// (the cap of radius R = L / (2 sin t) has area R^2 (t - sin t cos t)),
+// found by bisection.
+__device__ inline double cap_angle(double L, double area) {
+  auto f = [&](double t) {
+    const double s = sin(t);
+    const double r = L / (2.0 * s);
+    return r * r * (t - s * cos(t)) - area;
+  };
+  double lo = 1e-6, hi = M_PI - 1e-6;
+  double flo = f(lo);
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    const double fm = f(mid);
+    if ((fm > 0.0) == (flo > 0.0)) {
+      lo = mid;
+      flo = fm;
+    } else {
+      hi = mid;
+    }
+  }
+  return 0.5 * (lo + hi);
+}
+
+// Contact-line measures of Sec. 5.1 at each wall: the positions where the
+// wall phase field (extrapolated per column from the first two cell rows,
+// Sec. 4) crosses 1/2, by linear interpolation between column centres
+// (x periodic, a column that holds exactly 1/2 counts as a crossing at its
+// centre), numbered in column order; the wetted length |x1 - x0| of a wall
+// with exactly two crossings; and the contact angle of the circular cap
+// with that chord and the instance's phase-field area sum(phi) h^2.  One
+// block per (instance, wall); needs k_phase_prep's wall arrays on the caller
+// phase field and k_diag's mass.
+__global__ void __launch_bounds__(kNT) k_contact(const Inst* __restrict__ insts,
+                                                 DiagOut* __restrict__ out) {
+  __shared__ int sh[kNT / 64];
+  const int wall = blockIdx.y;
+  const Inst& I = insts[blockIdx.x];
+  const int nx = I.nx;
+  const double* __restrict__ W = I.wall + (size_t)wall * 5 * nx;   // phi_w per column
+  auto crosses = [&](int i) {
+    const double a = W[i] - 0.5, b = W[wrap(i + 1, nx)] - 0.5;
+    return a == 0.0 || a * b < 0.0;
+  };
+  auto block_int = [&](int v, bool is_min) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const int o = __shfl_xor(v, off, 64);
+      v = is_min ? min(v, o) : v + o;
+    }
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    int r = sh[0];
+    for (int w = 1; w < kNT / 64; ++w) r = is_min ? min(r, sh[w]) : r + sh[w];
+    return r;
+  };
+  int cnt = 0;
+  for (int i = threadIdx.x; i < nx; i += kNT) cnt += crosses(i) ? 1 : 0;
+  const int total = block_int(cnt, false);
+  int cols[kMaxContacts];
+  int last = -1;
+#pragma unroll
+  for (int m = 0; m < kMaxContacts; ++m) {
+    int best = INT_MAX;
+    // this thread's columns ascend: its first crossing past `last` is its smallest
+    for (int i = threadIdx.x; i < nx; i += kNT)
+      if (i > last && crosses(i)) {
+        best = i;
+        break;
+      }
+    best = block_int(best, true);
+    cols[m] = best;
+    if (best != INT_MAX) last = best;
+  }
+  if (threadIdx.x == 0) {
+    DiagOut& D = out[blockIdx.x];
+    const double h = I.h;
+    for (int m = 0; m < kMaxContacts; ++m) {
+      double x = 0.0;
+      if (cols[m] != INT_MAX) {
+        const int i = cols[m];
+        const double a = W[i] - 0.5, b = W[wrap(i + 1, nx)] - 0.5;
+        x = (i + 0.5) * h;
+        if (a != 0.0) x += h * a / (a - b);
+      }
+      D.contact_x[wall][m] = x;
+    }
+    D.n_contact[wall] = total;
+    double L = 0.0, th = 0.0;
+    if (total == 2) {
+      L = fabs(D.contact_x[wall][1] - D.contact_x[wall][0]);
+      th = cap_angle(L, D.mass);
+    }
+    D.wetted_len[wall] = L;
+    D.theta_est[wall] = th;
   }
 }
 

@@ -85,7 +85,12 @@ class CDISolver:
                     phi_max=d.phi_max, max_div=d.max_div, max_uslip_bot=d.max_uslip[0],
                     max_uslip_top=d.max_uslip[1], max_uY_bot=d.max_uY[0],
                     max_uY_top=d.max_uY[1], ke=d.ke, last_iters=d.last_iters,
-                    last_relres=d.last_relres, nonfinite=d.nonfinite)
+                    last_relres=d.last_relres, nonfinite=d.nonfinite,
+                    n_contact_bot=d.n_contact[0], n_contact_top=d.n_contact[1],
+                    contact_x_bot=[d.contact_x[k] for k in range(min(2, d.n_contact[0]))],
+                    contact_x_top=[d.contact_x[2 + k] for k in range(min(2, d.n_contact[1]))],
+                    wetted_len_bot=d.wetted_len[0], wetted_len_top=d.wetted_len[1],
+                    theta_est_bot=d.theta_est[0], theta_est_top=d.theta_est[1])
 
     def eval_rhs(self):
         """Stage operator on the current fields of instance 0."""

@@ -1,6 +1,7 @@
-"""CPU checks of the host-side measures of the drop convergence campaign
+"""CPU checks of the drop convergence campaign set-up
 (paper_2412_16843_amd.drop_convergence): the exact wetted length and the
-wall-crossing measure applied to a phase field whose answer is known."""
+interface thickness rule; the measured wetted length comes from the device
+diagnostics (tests/test_gpu_diagnostics.py)."""
 import math
 
 import numpy as np
@@ -18,19 +19,11 @@ def test_exact_wetted_length_closed_forms():
     assert abs(D.exact_wetted_length() - R * math.sqrt(3)) < 1e-15
 
 
-def test_wetted_length_of_a_step_profile_is_exact():
-    """phi linear across the crossing: the interpolated crossings are exact."""
-    nx, h = 64, 1.0 / 64
-    x = (np.arange(nx) + 0.5) * h
-    prof = np.clip(0.5 + (0.2 - np.abs(x - 0.5)) / (4 * h), 0.0, 1.0)
-    phi = np.vstack([prof, prof])          # equal rows: the wall value is prof
-    assert abs(D.wetted_length(phi, h) - 0.4) < 1e-12
-
-
-def test_wetted_length_of_the_initial_drop_is_its_diameter():
-    """The prescribed 90-degree drop at eps/h = 0.7: its phi = 1/2 base
-    chord is the diameter 0.3 up to the profile's discretisation."""
+def test_case_eps_follows_h_to_the_two_thirds():
+    """eps = 0.175 h^(2/3): eps / h = 0.7 at Nx = 64 and 1.4 at Nx = 512, the
+    range of Sec. 5.1; the initial field is the 90-degree prescribed drop."""
     p, phi0 = D.case(256)
-    L = D.wetted_length(phi0, p.h)
-    assert abs(L - 0.3) < 2 * p.h, L
     assert abs(p.eps / p.h - 0.175 * 256 ** (1 / 3)) < 1e-12
+    assert abs(D.case(64)[0].eps / (1 / 64) - 0.7) < 1e-12
+    assert abs(D.case(512)[0].eps / (1 / 512) - 1.4) < 1e-12
+    assert phi0.shape == (128, 256)

@@ -8,9 +8,7 @@ times (tiled launch, the wide-tile shape chosen for the grid size).
   oracle's own discrete operator to the requested 1e-10 relative residual
   (a property that holds at any size; an exact solve at 2 M unknowns would
   take minutes on the CPU), and is mean-free.
-* One full RK4 step of the 1024x512 ratio-10 drop (4 variable-density
-  projections): FP64 GPU vs oracle 1e-10 per field; the mixed-precision path
-  against the same oracle step with its error reported.
+* (The 1024x512 ratio-10 drop at all four angles: tests/test_gpu_config3.py.)
 * The full 64-instance seeded ensemble (128x64 .. 512x256) in one batched
   FP64 context for two steps, sampled instances (smallest, largest, a drop
   and a Couette at each density ratio) against the oracle at 1e-10.
@@ -117,34 +115,23 @@ def test_pressure_solve_at_full_size_meets_residual(name, make):
     assert abs(pg.mean()) <= 1e-12 * np.abs(pg).max()
 
 
-def test_config3_one_step_fp64_and_mixed_against_oracle():
-    case = W.config3(60.0)
-    o = cdi.run(case.phi0, case.params, 1)
-    ref = {"phi": o.phi, "u": o.u, "v": o.v, "p": o.p}
-    s = _solver(case.params, case.phi0, rtol=1e-13, maxit=400)
-    s.step(1)
-    g = s.state()
-    s.close()
-    errs = {k: relerr(g[k], ref[k]) for k in FIELDS}
-    print("config3 one step FP64 vs oracle:", errs)
-    assert max(errs.values()) < 1e-10, errs
-    m = _solver(case.params, case.phi0, precision="mixed", rtol=1e-10)
-    m.step(1)
-    d = m.diagnostics()
-    gm = m.state()
-    m.close()
-    errs = {k: relerr(gm[k], ref[k]) for k in FIELDS}
-    print("config3 one step mixed vs FP64 oracle:", errs)
-    assert d["last_relres"] <= 1e-10
-    assert abs(d["mass"] - d["mass0"]) <= 1e-12 * d["mass0"]
-    assert errs["phi"] < 1e-6 and max(errs.values()) < 1e-3, errs
+# one-step-scale FP32 round-off bounds of the mixed path against the FP64
+# oracle (per field, max |mixed - oracle| / max |oracle|)
+MIXED_BOUND = {"phi": 1e-6, "u": 1e-3, "v": 1e-3, "p": 1e-3}
 
 
 def test_config4_full_ensemble_sampled_against_oracle():
+    """The full seeded 64-instance ensemble in one batched context for two
+    steps, FP64 and mixed: sampled instances (smallest, largest, a drop and
+    a Couette at each density ratio) against the oracle, FP64 at 1e-10 and
+    mixed within MIXED_BOUND per field."""
     cases = W.config4()
     steps = 2
     s = _solver([c.params for c in cases], [c.phi0 for c in cases], rtol=1e-13, maxit=400)
     s.step(steps)
+    m = _solver([c.params for c in cases], [c.phi0 for c in cases], precision="mixed",
+                rtol=1e-10)
+    m.step(steps)
     size = [c.params.nx * c.params.ny for c in cases]
     pick = {int(np.argmin(size)), int(np.argmax(size))}
     for kind in ("drop", "couette"):
@@ -156,12 +143,21 @@ def test_config4_full_ensemble_sampled_against_oracle():
     for k in sorted(pick):
         c = cases[k]
         g = s.state(k)
+        gm = m.state(k)
+        dm = m.diagnostics(k)
         o = cdi.run(c.phi0, c.params, steps)
-        errs = {f: relerr(g[f], ref) for f, ref in (("phi", o.phi), ("u", o.u), ("v", o.v),
-                                                     ("p", o.p))}
-        print(c.name, c.params.nx, "x", c.params.ny, "vs oracle:", errs)
+        ref = {"phi": o.phi, "u": o.u, "v": o.v, "p": o.p}
+        errs = {f: relerr(g[f], ref[f]) for f in FIELDS}
+        errm = {f: relerr(gm[f], ref[f]) for f in FIELDS}
+        print(c.name, c.params.nx, "x", c.params.ny, "FP64 vs oracle:", errs,
+              "mixed vs oracle:", errm)
         assert max(errs.values()) < 1e-10, (c.name, errs)
+        assert dm["last_relres"] <= 1e-10
+        assert abs(dm["mass"] - dm["mass0"]) <= 1e-12 * dm["mass0"]
+        for f in FIELDS:
+            assert errm[f] < MIXED_BOUND[f], (c.name, f, errm)
     s.close()
+    m.close()
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])

@@ -256,6 +256,26 @@ def test_model_4A_spurious_slip_converges_on_prescribed_equilibrium():
     assert errs[0] / errs[1] > 3.3 and errs[1] / errs[2] > 3.3, errs
 
 
+def test_prescribed_field_spurious_slip_under_mesh_refinement():
+    """The paper's mesh study of the prescribed equilibrium field (Sec. 3.1,
+    fig. of the prescribed phase field convergence): with eps = 0.175
+    h^(2/3) (eps / h from 0.7 at Nx = 64 to 1.4 at 512) the spurious slip of
+    Models 4A and 4B converges slightly faster than first order, while
+    Models 2A and 2B do not converge (their model error stays)."""
+    from paper_2412_16843_amd import slip_mesh_study as S
+    for th in (60.0, 120.0):
+        for model in ("4A", "4B", "2A", "2B"):
+            vals = []
+            for nx in (64, 128, 256, 512):
+                p, phi = S.prescribed(nx, th, model)
+                vals.append(np.abs(cdi.slip_velocity_Y(phi, p, "bot", model)["uY"]).max())
+            rates = [math.log2(vals[i] / vals[i + 1]) for i in range(3)]
+            if model[0] == "4":
+                assert min(rates) > 1.0 and np.mean(rates) < 2.0, (th, model, vals, rates)
+            else:
+                assert min(vals) > 0.03 and max(rates) < 0.4, (th, model, vals, rates)
+
+
 def test_slip_integral_constraint_and_direction():
     """Integral of u^Y over a contact line equals (sigma/beta)|cos t - cos t_eq|
     (Sec. 3, integral constraint) and drives spreading when t > t_eq."""
@@ -680,6 +700,28 @@ def _golden():
             k, v = line.split()[:2]
             out[k] = float(v)
     return out
+
+
+def test_contact_points_are_exact_on_piecewise_linear_wall_profiles():
+    """The phi = 1/2 crossings (Sec. 5.1 wetted length) by linear
+    interpolation between column centres (i + 1/2) h are exact for a wall
+    profile that is linear across each crossing, including a crossing across
+    the periodic seam, and a column holding exactly 1/2 counts once, at its
+    centre."""
+    h, n = 0.1, 100
+    x = (np.arange(n) + 0.5) * h
+    w = np.clip(0.5 + np.minimum(x - 2.3, 7.1 - x) / (4 * h), 0.0, 1.0)
+    cps = cdi.contact_points(w, h)
+    assert len(cps) == 2
+    assert abs(cps[0] - 2.3) < 1e-12 and abs(cps[1] - 7.1) < 1e-12
+    w2 = np.array([0.9, 0.9, 0.9, 0.1, 0.1, 0.1, 0.1, 0.3])   # rises between 7 and 0
+    cps = cdi.contact_points(w2, 0.5)
+    assert len(cps) == 2
+    assert abs(cps[0] - (2.5 + 0.4 / 0.8) * 0.5) < 1e-12
+    assert abs(cps[1] - (7.5 + (0.3 - 0.5) / (0.3 - 0.9)) * 0.5) < 1e-12
+    w3 = np.array([0.2, 0.5, 0.8, 0.8, 0.2])
+    cps = cdi.contact_points(w3, 1.0)
+    assert cps[0] == 1.5 and len(cps) == 2     # the exact 1/2 at column 1, then the fall
 
 
 def test_equal_area_cap_golden_values():
