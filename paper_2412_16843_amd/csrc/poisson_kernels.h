@@ -30,9 +30,12 @@ constexpr int kCoarseCells = 1024;   // levels at or below this size run in one 
 constexpr int kCoarseNT = 1024;
 static_assert(kCoarseCells <= kCoarseNT, "a coarse right-hand side is loaded one value per thread");
 constexpr int kDenseMax = 64;        // coarsest grids up to this size use a dense inverse
-// relative residual of the coarsest CG otherwise (1e-8 or 1e-6 took as many
-// outer iterations on the 64-instance ensemble as 1e-4, and more time)
-constexpr double kCoarseCgRtol = 1e-4;
+// relative residual of the coarsest CG otherwise: as the coarsest solve of a
+// preconditioner it need not be exact (the flexible outer CG keeps its own
+// tolerance).  On the 64-instance ensemble 1e-8, 1e-6, 1e-4, 1e-2 and 1e-1
+// took the same outer iterations (21.0 per step over the first 50 steps from
+// rest, 8.0 per step after), and 1e-1 the least time.
+constexpr double kCoarseCgRtol = 1e-1;
 constexpr int kCLX = 1376;           // LDS cells of all coarse levels (<= 1024 * 4/3)
 constexpr int kCLY = 2432;           // LDS y-faces of all coarse levels
 constexpr int kWideOwn = 4;          // cells per thread of the wide coarse level (2 per colour)
