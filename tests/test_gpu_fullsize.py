@@ -115,9 +115,11 @@ def test_pressure_solve_at_full_size_meets_residual(name, make):
     assert abs(pg.mean()) <= 1e-12 * np.abs(pg).max()
 
 
-# one-step-scale FP32 round-off bounds of the mixed path against the FP64
-# oracle (per field, max |mixed - oracle| / max |oracle|)
-MIXED_BOUND = {"phi": 1e-6, "u": 1e-3, "v": 1e-3, "p": 1e-3}
+# FP32 round-off bounds of the mixed path against the FP64 oracle after two
+# steps (per field, max |mixed - oracle| / max |oracle|), a few times above
+# the largest measured over the sampled instances on the MI355X (6.5e-10,
+# 2.3e-7, 8.6e-7, 8.7e-7 for phi, u, v, p)
+MIXED_BOUND = {"phi": 5e-9, "u": 2e-6, "v": 5e-6, "p": 5e-6}
 
 
 def test_config4_full_ensemble_sampled_against_oracle():
