@@ -15,11 +15,14 @@ Prints one JSON line:
                           steps / wall time / 1e6, inputs resident in HBM,
                           timed between two device synchronisations with no
                           per-kernel instrumentation
-  roofline                the dominant kernel family's algorithmic bytes per
-                          launch over its average launch time (start / end
-                          timestamps of its own launches, taken in a
-                          separate pass on the library stream), against the
-                          8 TB/s HBM peak
+  roofline                the bandwidth-bound kernel family with the most
+                          device time: its algorithmic bytes per launch over
+                          its average launch time (start / end timestamps of
+                          its own launches, taken in a separate pass on the
+                          library stream), against the 8 TB/s HBM peak
+  dominant_kernel         the family with the most device time overall and its
+                          share (the one-block coarse cycle, when it leads,
+                          is bound by barrier latency, not bandwidth)
   kernel_time_ms_per_step device time per step of every kernel family
   poisson_learned_vs_plain  pressure time to solution at 1e-10 on the
                           2048x1024 ratio-10 grid: zero guess, previous
@@ -88,15 +91,17 @@ def mg_levels(nx: int, ny: int, coarse_cells: int = 1024):
     return levels, lc
 
 
-def _coarse_bytes(nx: int, ny: int, coarse_cells: int) -> float:
+def _coarse_bytes(p, coarse_cells: int) -> float:
     """Right-hand side of the first level the coarse kernel runs read and its
     correction written, the x- and y-face coefficients of every level from
-    there read, and the dense inverse of the coarsest grid (up to 64 cells)."""
-    levels, lg = mg_levels(nx, ny, coarse_cells)
+    there read, and the dense inverse of the coarsest grid (up to 64 cells,
+    uniform density only: with a variable density the coarsest grid is
+    solved by CG in LDS)."""
+    levels, lg = mg_levels(p.nx, p.ny, coarse_cells)
     coef = sum(a * b + a * (b + 1) for a, b in levels[lg:])
     n0 = levels[lg][0] * levels[lg][1]
     nc = levels[-1][0] * levels[-1][1]
-    dense = nc * nc if nc <= 64 else 0
+    dense = nc * nc if (nc <= 64 and p.rho1 == p.rho2) else 0
     return 8.0 * (2 * n0 + coef + dense)
 
 
@@ -108,7 +113,7 @@ def algo_bytes_per_launch(fam: str, params, coarse_cells: int = 1024) -> float:
     if fam in ALGO_BYTES_PER_CELL:
         return ALGO_BYTES_PER_CELL[fam] * sum(p.nx * p.ny for p in params)
     if fam == "mg_coarse":
-        return sum(_coarse_bytes(p.nx, p.ny, coarse_cells) for p in params)
+        return sum(_coarse_bytes(p, coarse_cells) for p in params)
     raise KeyError(fam)
 
 
@@ -460,9 +465,14 @@ def main():
     probe = 5
     fam_t = family_times(s, probe)
     kernel_ms = {k: round(ms / probe, 4) for k, (ms, n) in fam_t.items() if n}
+    total_dev_ms = sum(ms for ms, _ in fam_t.values())
+    dominant = max(fam_t, key=lambda k: fam_t[k][0])
     fam = args.kernel
     if fam == "auto":
-        fam = max(fam_t, key=lambda k: fam_t[k][0])
+        # the roofline entry is the bandwidth-bound family with the most
+        # device time; the one-block-per-instance coarse cycle is bound by
+        # barrier latency on one CU per instance and is reported beside it
+        fam = max((k for k in fam_t if k in ALGO_BYTES_PER_CELL), key=lambda k: fam_t[k][0])
     k_ms, k_n = fam_t[fam] if fam in fam_t else (0.0, 0)
     coarse_cells = s.get_coarse_cells()
     try:
@@ -500,8 +510,11 @@ def main():
                      "traffic": traffic_record(fam, name),
                      "launches": k_n, "avg_launch_us": round(avg_s * 1e6, 3),
                      "algo_bytes_per_launch": per_launch_bytes,
-                     "share_of_device_time": round(k_ms / max(1e-9, sum(
-                         ms for ms, _ in fam_t.values())), 4)},
+                     "share_of_device_time": round(k_ms / max(1e-9, total_dev_ms), 4)},
+        "dominant_kernel": {"kernel": dominant,
+                            "bound": "latency" if dominant not in ALGO_BYTES_PER_CELL else "hbm",
+                            "share_of_device_time": round(fam_t[dominant][0] / max(1e-9, total_dev_ms), 4),
+                            "avg_launch_us": round(fam_t[dominant][0] / max(1, fam_t[dominant][1]) * 1e3, 3)},
         "kernel_time_ms_per_step": kernel_ms,
     }
     s.close()

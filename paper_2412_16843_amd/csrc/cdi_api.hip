@@ -202,7 +202,12 @@ size_t carve(const Resolved& R, int ntiles_cell, int ntiles_mg0, char* base, siz
     L.zo = (l == 0) ? nullptr : take(lc * S);
   }
   const size_t ncs = (size_t)R.lnx[R.nlev - 1] * R.lny[R.nlev - 1];
-  D.cdense = ncs <= (size_t)kDenseMax ? 1 : 0;
+  // constant operator coefficients (uniform density): computed once; the dense
+  // coarsest inverse is then worth its set-up.  With a variable density the
+  // coarsest grid is solved by the coarsest CG instead of re-inverting it
+  // at every projection.
+  D.coef_const = R.p.rho1 == R.p.rho2 ? 1 : 0;
+  D.cdense = (ncs <= (size_t)kDenseMax && D.coef_const) ? 1 : 0;
   D.cinv = D.cdense ? (double*)take(ncs * ncs * 8) : nullptr;
   return off;
 }
@@ -484,16 +489,23 @@ void launch_vcycle(cdi_ctx* c, int update, int dpar, int rsel) {
       });
 }
 
+// Coarse-level operator coefficients of every instance from the level-0 ones.
+// Instances of uniform density keep constant coefficients: once they have
+// been formed (c->coef_ready) only the variable-density instances recompute
+// theirs, and the dense coarsest inverse (uniform density only) is formed
+// once.
 template <typename S>
 void launch_coef(cdi_ctx* c) {
+  const int only_variable = c->coef_ready ? 1 : 0;
   for (int l = 1; l < c->B.max_nlev; ++l) {
     int maxc = 0;
     for (int k = 0; k < c->B.n; ++k)
       if (c->B.R[k].nlev > l) maxc = std::max(maxc, c->B.R[k].lnx[l] * (c->B.R[k].lny[l] + 1));
     const dim3 grid((unsigned)std::max(1, std::min(1024, ceil_div(maxc, kNT))), (unsigned)c->B.n);
-    timed(c, "mg_coef", [&] { CDI_LAUNCH(c, k_mg_coef<S>, grid, kNT, c->d_inst, l); });
+    timed(c, "mg_coef", [&] { CDI_LAUNCH(c, k_mg_coef<S>, grid, kNT, c->d_inst, l, only_variable); });
   }
-  timed(c, "mg_coef", [&] { CDI_LAUNCH(c, k_coarse_inv<S>, (unsigned)c->B.n, kCoarseNT, c->d_inst); });
+  if (!only_variable)
+    timed(c, "mg_coef", [&] { CDI_LAUNCH(c, k_coarse_inv<S>, (unsigned)c->B.n, kCoarseNT, c->d_inst); });
 }
 
 // Enqueue the copy of every instance's CG scalars into the pinned host array

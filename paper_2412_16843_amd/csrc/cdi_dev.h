@@ -96,7 +96,7 @@ struct Inst {
   void* mg_r0;                         // S [ny*nx] level-0 residual copy (mixed, one-block V-cycle)
   double* cinv;                        // dense inverse of the coarsest operator (n <= 64)
   int cdense;                          // 1 if cinv is used for the coarsest solve
-  int pad_;
+  int coef_const;                      // 1: uniform density, operator coefficients constant
 };
 
 struct Tile {

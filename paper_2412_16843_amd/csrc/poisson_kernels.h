@@ -1687,9 +1687,10 @@ __device__ __forceinline__ void mg_coef_level(const Inst& I, int l, int start, i
 
 // Level l of every instance that has it (grid.y = instance).
 template <typename S>
-__global__ void __launch_bounds__(kNT) k_mg_coef(const Inst* __restrict__ insts, int l) {
+__global__ void __launch_bounds__(kNT) k_mg_coef(const Inst* __restrict__ insts, int l,
+                                                 int only_variable) {
   const Inst& I = insts[blockIdx.y];
-  if (l >= I.nlev) return;
+  if (l >= I.nlev || (only_variable && I.coef_const)) return;
   mg_coef_level<S>(I, l, blockIdx.x * kNT + threadIdx.x, gridDim.x * kNT);
 }
 
