@@ -324,33 +324,29 @@ def cpu_baseline(name: str, budget_s: float = 15.0):
 
 
 # ------------------------------------------------- learned vs plain Poisson
-def poisson_learned_vs_plain(nx: int = 2048, train_iters: int = 300, verbose: bool = False):
+def poisson_learned_vs_plain(nx: int = 2048, train_seconds: float = 60.0, verbose: bool = False):
     """Pressure time-to-solution at relative residual 1e-10 on the 2048x1024
-    density-ratio-10 grid: zero guess, previous-step pressure and the learned
-    guess (network inference, Galerkin fit on span{previous pressure, network
-    output}, flexible CG), all on the GPU.
-    The network is trained first, on the GPU, on snapshots of other cases at
-    the same resolution (drops at 45/75 deg, a Couette at Ca 0.05)."""
+    density-ratio-10 grid (drop and Couette): zero guess, previous-step
+    pressure and the learned guess (network inference, Galerkin fit on
+    span{previous pressure, network output}, flexible CG), all on the GPU.
+    The network is trained first, on the GPU, on ~10^4 snapshots the solver
+    generates on the first three workloads (every step of the 64x32 drop,
+    every 4th of the 256x64 Couette, one 256x256 crop of every step of the
+    four 1024x512 ratio-10 drops over 2000 steps), for `train_seconds`."""
     import torch
     from paper_2412_16843_amd import learned, train_guess
     from paper_2412_16843_amd.solver import CDISolver
     ny = nx // 2
     t0 = time.perf_counter()
-    train_cases = [W.drop_case(nx, ny, th, 10.0, steps=24) for th in (45.0, 75.0)]
-    train_cases.append(W.couette_case(nx, ny, lx=2.0, ly=1.0, ratio=10.0, ca=0.05, steps=24))
-    data = train_guess.collect(train_cases, steps=24, every=3)
+    data = train_guess.collect_configs(verbose=verbose)
     t_collect = time.perf_counter() - t0
-    net = learned.GuessNet(8, 256, 256)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    losses = train_guess.train(net, data, iters=train_iters, lr=5e-4,
-                               log_every=100 if verbose else 0)
-    torch.cuda.synchronize()
-    t_train = time.perf_counter() - t1
-    params = net.params.cpu().numpy()
-    net.close()
-    n_snap = len(data)
+    counts = {k: int(v[0].shape[0]) for k, v in data.items()}
+    log(f"collected {sum(counts.values())} snapshots in {t_collect:.0f} s: {counts}")
+    params, losses, iters = train_guess.train_multi(data, seconds=train_seconds, verbose=verbose)
+    t_train = time.perf_counter() - t0 - t_collect
+    log(f"trained {iters} iterations in {t_train:.0f} s")
     del data
+    torch.cuda.empty_cache()
     rows = []
     for case in (W.config5("drop", nx), W.config5("couette", nx)):
         s = CDISolver(case.params, case.phi0, guess="prev", rtol=1e-10)
@@ -375,6 +371,7 @@ def poisson_learned_vs_plain(nx: int = 2048, train_iters: int = 300, verbose: bo
         inf.close()
         s.close()
     mean = lambda m, k: sum(r[m][k] for r in rows) / len(rows)
+    first, last = train_guess.loss_summary(losses)
     return {
         "grid": f"{nx}x{ny}", "rtol": 1e-10, "solves": len(rows),
         "iters_zero": mean("zero", 0), "iters_prev": mean("prev", 0),
@@ -382,10 +379,10 @@ def poisson_learned_vs_plain(nx: int = 2048, train_iters: int = 300, verbose: bo
         "ms_zero": round(mean("zero", 1), 3), "ms_prev": round(mean("prev", 1), 3),
         "ms_learned": round(mean("learned", 1), 3),
         "ms_inference": round(net_ms / max(net_n, 1), 3),
-        "train": {"snapshots": n_snap, "iters": train_iters, "batch": 8, "crop": 256,
-                  "loss_first10pct": round(train_guess.loss_summary(losses)[0], 4),
-                  "loss_last10pct": round(train_guess.loss_summary(losses)[1], 4),
-                  "train_s": round(t_train, 2), "collect_s": round(t_collect, 2)},
+        "train": {"snapshots": counts, "snapshots_total": sum(counts.values()),
+                  "iters": iters, "batch": 8, "seconds": round(t_train, 1),
+                  "loss_first10pct": round(first, 4), "loss_last10pct": round(last, 4),
+                  "collect_s": round(t_collect, 1)},
     }
 
 

@@ -88,24 +88,41 @@ def up_backward(dy):
     return dy.reshape(B, C, H // 2, 2, W // 2, 2).sum(axis=(3, 5))
 
 
-def forward(p: Dict[str, np.ndarray], x: np.ndarray) -> Tuple[np.ndarray, Dict]:
-    """Network output (B, 1, H, W) and the cache needed by backward."""
+def bf16_round(a: np.ndarray) -> np.ndarray:
+    """Round to the nearest bfloat16 (8 significand bits, ties to even), via
+    the float32 bit pattern: keep the high 16 bits after adding half of the
+    dropped part (0x7FFF) plus the lowest kept bit.  Returned as float64."""
+    b = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    r = (b + 0x7FFF + ((b >> 16) & 1)) & 0xFFFF0000
+    return r.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def forward(p: Dict[str, np.ndarray], x: np.ndarray, bf16: bool = False
+            ) -> Tuple[np.ndarray, Dict]:
+    """Network output (B, 1, H, W) and the cache needed by backward.
+
+    bf16=True evaluates the network as specified for the matrix cores: the
+    input planes, the 3x3 weights, every convolution's activation (after
+    bias and ReLU) and every pooled tensor rounded to bfloat16, everything
+    else (sums, biases, the 1x1 output layer's weights) in float64."""
+    r = bf16_round if bf16 else (lambda a: a)
+    w = {k: (r(v) if k.endswith(".w") and k != "out.w" else v) for k, v in p.items()}
     c = {"x": x}
-    c["e0i"] = x
-    c["e0"] = np.maximum(conv3(x, p["e0.w"], p["e0.b"]), 0.0)
-    c["e1i"] = pool(c["e0"])
-    c["e1"] = np.maximum(conv3(c["e1i"], p["e1.w"], p["e1.b"]), 0.0)
-    c["e2i"] = pool(c["e1"])
-    c["e2"] = np.maximum(conv3(c["e2i"], p["e2.w"], p["e2.b"]), 0.0)
-    c["e3i"] = pool(c["e2"])
-    c["e3"] = np.maximum(conv3(c["e3i"], p["e3.w"], p["e3.b"]), 0.0)
+    c["e0i"] = r(x)
+    c["e0"] = r(np.maximum(conv3(c["e0i"], w["e0.w"], w["e0.b"]), 0.0))
+    c["e1i"] = r(pool(c["e0"]))
+    c["e1"] = r(np.maximum(conv3(c["e1i"], w["e1.w"], w["e1.b"]), 0.0))
+    c["e2i"] = r(pool(c["e1"]))
+    c["e2"] = r(np.maximum(conv3(c["e2i"], w["e2.w"], w["e2.b"]), 0.0))
+    c["e3i"] = r(pool(c["e2"]))
+    c["e3"] = r(np.maximum(conv3(c["e3i"], w["e3.w"], w["e3.b"]), 0.0))
     c["d2i"] = np.concatenate([up(c["e3"]), c["e2"]], axis=1)
-    c["d2"] = np.maximum(conv3(c["d2i"], p["d2.w"], p["d2.b"]), 0.0)
+    c["d2"] = r(np.maximum(conv3(c["d2i"], w["d2.w"], w["d2.b"]), 0.0))
     c["d1i"] = np.concatenate([up(c["d2"]), c["e1"]], axis=1)
-    c["d1"] = np.maximum(conv3(c["d1i"], p["d1.w"], p["d1.b"]), 0.0)
+    c["d1"] = r(np.maximum(conv3(c["d1i"], w["d1.w"], w["d1.b"]), 0.0))
     c["d0i"] = np.concatenate([up(c["d1"]), c["e0"]], axis=1)
-    c["d0"] = np.maximum(conv3(c["d0i"], p["d0.w"], p["d0.b"]), 0.0)
-    y = np.einsum("oc,bchw->bohw", p["out.w"], c["d0"]) + p["out.b"][None, :, None, None]
+    c["d0"] = r(np.maximum(conv3(c["d0i"], w["d0.w"], w["d0.b"]), 0.0))
+    y = np.einsum("oc,bchw->bohw", w["out.w"], c["d0"]) + w["out.b"][None, :, None, None]
     return y, c
 
 

@@ -367,7 +367,11 @@ cdi_status cdi_net_adam(cdi_net* n, float* m, float* v, int32_t step, double lr)
   if (!n->train) return net_fail(CDI_ERR_STATE, "net was created for inference only");
   const size_t cnt = cdinet::param_count();
   const float b1 = 0.9f, b2 = 0.999f;
-  const float c1 = 1.f - std::pow(b1, (float)step), c2 = 1.f - std::pow(b2, (float)step);
+  // bias corrections 1 - beta^step of the FP32 betas the kernel uses, formed
+  // in double: beta2^step lies within ~1e-3 of 1, so in FP32 the difference
+  // would keep only ~4 significant digits
+  const float c1 = (float)(1.0 - std::pow((double)b1, (double)step));
+  const float c2 = (float)(1.0 - std::pow((double)b2, (double)step));
   cdinet::k_adam<<<std::min<unsigned>(2048, (unsigned)((cnt + 255) / 256)), 256, 0, n->stream>>>(
       n->params, n->grads, m, v, cnt, (float)lr, b1, b2, 1e-8f, c1, c2);
   cdinet::pack_weights_public(n);

@@ -59,17 +59,23 @@ class GuessNet:
     """One network instance of fixed batch and image size on one GPU."""
 
     def __init__(self, batch: int, h: int, w: int, params=None, train: bool = True,
-                 device: str = "cuda:0", stream=None):
+                 device: str = "cuda:0", stream=None, share: "GuessNet | None" = None):
+        """share: another network whose parameter, gradient and Adam-moment
+        buffers this one uses (the same weights on another image shape);
+        after the other network's Adam step, call repack() here."""
         self.lib = L.lib()
         self.device = torch.device(device)
         n = self.lib.cdi_net_param_count()
-        p = init_params(0) if params is None else np.asarray(params, dtype=np.float32)
-        if p.size != n:
-            raise ValueError(f"expected {n} parameters, got {p.size}")
-        self.params = torch.as_tensor(p, device=self.device).clone()
-        self.grads = torch.zeros(n, dtype=torch.float32, device=self.device)
-        self.m = torch.zeros_like(self.grads)
-        self.v = torch.zeros_like(self.grads)
+        if share is not None:
+            self.params, self.grads, self.m, self.v = share.params, share.grads, share.m, share.v
+        else:
+            p = init_params(0) if params is None else np.asarray(params, dtype=np.float32)
+            if p.size != n:
+                raise ValueError(f"expected {n} parameters, got {p.size}")
+            self.params = torch.as_tensor(p, device=self.device).clone()
+            self.grads = torch.zeros(n, dtype=torch.float32, device=self.device)
+            self.m = torch.zeros_like(self.grads)
+            self.v = torch.zeros_like(self.grads)
         self.batch, self.h, self.w, self.train = batch, h, w, train
         nbytes = self.lib.cdi_net_workspace_bytes(batch, h, w, int(train))
         if nbytes == 0:
@@ -102,6 +108,10 @@ class GuessNet:
         self.step += 1
         L.check_net(self.lib.cdi_net_adam(self.handle, self.m.data_ptr(), self.v.data_ptr(),
                                           self.step, lr))
+
+    def repack(self):
+        """Re-pack the BF16 weights from the (shared) FP32 parameters."""
+        L.check_net(self.lib.cdi_net_repack(self.handle))
 
     def set_params(self, vec):
         self.params.copy_(torch.as_tensor(np.asarray(vec, dtype=np.float32)))

@@ -154,3 +154,68 @@ def test_garbage_network_falls_back_to_the_plain_guess(garbage):
     for k in ("phi", "u", "v", "p"):
         assert np.array_equal(a[k], b[k]), k
     inf.close(); prev.close(); lrn.close()
+
+
+# elementwise bound of the GPU forward pass against the oracle evaluated with
+# the same bfloat16 rounding points (input planes, 3x3 weights, activations,
+# pooled tensors): what remains is the FP32 accumulation order of the
+# matrix cores, which moves a pre-rounding value by ~1e-6 relative and so
+# flips an occasional activation by one bfloat16 ulp (2^-8) that the next
+# layers carry on; relative to |y| + rms(y)
+BF16_ELEMENTWISE = 2.0 ** -6
+
+
+@pytest.mark.parametrize("B,H,Wd", [(2, 16, 16), (1, 32, 96), (1, 40, 48)])
+def test_network_forward_elementwise_against_bf16_oracle(B, H, Wd):
+    """Every output element of the BF16 / FP32-accumulate GPU forward pass
+    (training and inference forms) against the oracle network evaluated with
+    the matrix cores' bfloat16 rounding points."""
+    torch = _torch()
+    from paper_2412_16843_amd import learned
+    rng = np.random.default_rng(17)
+    p = _rand_params(2)
+    x = rng.standard_normal((B, 3, H, Wd))
+    y16, _ = unet.forward(p, x, bf16=True)
+    y16 = y16[:, 0]
+    scale = np.abs(y16) + np.sqrt(np.mean(y16 ** 2))
+    for train in (True, False):
+        net = learned.GuessNet(B, H, Wd, params=learned.flatten(p), train=train)
+        y = net.forward(torch.as_tensor(x, dtype=torch.float32)).cpu().numpy()
+        net.close()
+        r = np.abs(y - y16) / scale
+        print(f"B{B} {H}x{Wd} train={train}: |y - y_bf16| / (|y| + rms): max {r.max():.2e}, "
+              f"99th percentile {np.percentile(r, 99):.2e}, median {np.median(r):.2e}")
+        assert r.max() <= BF16_ELEMENTWISE, (train, r.max())
+
+
+def test_gpu_adam_matches_oracle_adam():
+    """Three Adam steps of the library kernel (FP32 master parameters and
+    moments) against the oracle's Adam in FP64 on the same parameters and
+    gradients: the parameters agree to FP32 round-off of the update."""
+    torch = _torch()
+    from paper_2412_16843_amd import learned
+    rng = np.random.default_rng(23)
+    p0 = learned.init_params(4).astype(np.float64)
+    net = learned.GuessNet(1, 16, 16, params=p0)
+    po = {"w": p0.astype(np.float32).astype(np.float64)}
+    mo = {"w": np.zeros_like(po["w"])}
+    vo = {"w": np.zeros_like(po["w"])}
+    # the first moment of |g|: the scale of the terms m is a sum of
+    pa, ma, va = {"w": po["w"].copy()}, {"w": np.zeros_like(po["w"])}, {"w": np.zeros_like(po["w"])}
+    lr = 1e-3
+    for step in range(1, 4):
+        g = (rng.standard_normal(p0.size) * 10.0 ** rng.uniform(-4, 0, p0.size)).astype(np.float32)
+        net.grads.copy_(torch.as_tensor(g))
+        net.adam(lr)
+        unet.adam(po, {"w": g.astype(np.float64)}, mo, vo, step, lr=lr)
+        unet.adam(pa, {"w": np.abs(g).astype(np.float64)}, ma, va, step, lr=lr)
+    pg = net.params.cpu().numpy().astype(np.float64)
+    mg = net.m.cpu().numpy().astype(np.float64)
+    net.close()
+    # each update moves a parameter by at most ~lr; FP32 evaluates it to a
+    # few ulps of the update and rounds the parameter (|p| ulp)
+    err = np.abs(pg - po["w"])
+    bound = 4 * np.finfo(np.float32).eps * (np.abs(po["w"]) + 3 * lr)
+    print("Adam: max |dp| / bound", float((err / bound).max()))
+    assert (err <= bound).all(), float((err / bound).max())
+    assert (np.abs(mg - mo["w"]) <= 8 * np.finfo(np.float32).eps * ma["w"]).all()

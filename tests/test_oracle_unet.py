@@ -107,3 +107,23 @@ def test_adam_two_steps_match_hand_computed_values():
     unet.adam(p, {"w": np.array([-1.0])}, m, v, 2, lr=0.1)
     assert abs(m["w"][0] / 0.08 - 1) < 1e-14 and abs(v["w"][0] / 0.004996 - 1) < 1e-14
     assert abs(p["w"][0] - 0.8733662967024313) < 2e-15
+
+
+def test_bf16_rounding_of_the_network_oracle():
+    """Round to nearest bfloat16, ties to even, worked by hand: 1 + 2^-8 is
+    halfway between 1 and 1 + 2^-7 and goes to the even 1; 1 + 3 2^-8 is
+    halfway between 1 + 2^-7 and 1 + 2^-6 and goes to the even 1 + 2^-6;
+    1 + 3 2^-9 is nearer 1 + 2^-7; pi -> 3.140625 (0x4049); 65504 -> 65536;
+    the sign is kept."""
+    v = np.array([1.0, 1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, 1.0 + 3 * 2 ** -9, np.pi, 65504.0,
+                  -1.0 - 2 ** -7])
+    ref = np.array([1.0, 1.0, 1.0 + 2 ** -6, 1.0 + 2 ** -7, 3.140625, 65536.0, -1.0 - 2 ** -7])
+    assert np.array_equal(unet.bf16_round(v), ref)
+    # rounded forward: the same network with its operands rounded, close to FP64
+    rng = np.random.default_rng(9)
+    p = unet.init_params(3)
+    x = rng.standard_normal((1, 3, 16, 16))
+    y, _ = unet.forward(p, x)
+    y16, c16 = unet.forward(p, x, bf16=True)
+    assert np.array_equal(unet.bf16_round(c16["d1"]), c16["d1"])
+    assert np.linalg.norm(y16 - y) / np.linalg.norm(y) < 3e-2
