@@ -2,7 +2,7 @@
 """Throughput of the CDI + GNBC time step on one MI355X.
 
 One "step" is one full RK4 time step of every instance of the workload: 4
-stage evaluations (phase-field preparation, fused CDI-flux / momentum / GNBC
+stage evaluations (fused phase-field preparation, CDI-flux / momentum / GNBC
 stage kernel, projection right-hand side) and 4 variable-density pressure
 projections by multigrid-preconditioned flexible CG to a relative residual of
 1e-10.  The default workload is the seeded 64-instance ensemble of uneven
@@ -50,11 +50,11 @@ HBM_PEAK_GBS = 8000.0
 # Algorithmic HBM bytes per cell and launch of each kernel family (FP64
 # path): every array element the kernel must read or write, counted once.
 ALGO_BYTES_PER_CELL = {
-    # phi read; n_x, n_y, mu_c written
-    "phase_prep": 8 + 3 * 8,
-    # stage phi, n, mu_c, u, v; base phi, u, v; RK accumulators read+write
-    # (stages 1-2), next phi and (rho u)* written: mean over the 4 stages
-    "stage": (96 + 144 + 144 + 120) / 4,
+    # the stage kernel with the phase preparation fused in: stage phi, u, v;
+    # base phi, u, v; RK accumulators read+write (stages 1-2), next phi and
+    # (rho u)* written: mean over the 4 stages (n, mu_c and the wall values
+    # are formed in LDS)
+    "stage": (72 + 120 + 120 + 96) / 4,
     # (rho u)*, next phi read; u*, v*, b, a_x, a_y written
     "rhs": 3 * 8 + 5 * 8,
     # CG step fused in (x, d, r, q read; x, r written), then r, a_x, a_y read,
@@ -74,7 +74,7 @@ ALGO_BYTES_PER_CELL = {
 }
 
 # every family the library can time (cdi_timing_enable)
-FAMILIES = ("phase_prep", "stage", "rhs", "pcg_init", "pcg_spmv", "mg_down", "mg_down_other",
+FAMILIES = ("stage", "rhs", "pcg_init", "pcg_spmv", "mg_down", "mg_down_other",
             "mg_coarse", "mg_up", "mg_up_other", "mg_coef", "pcg_xmean", "project")
 
 
@@ -139,7 +139,7 @@ def step_bytes_per_cell(iters_per_step: float) -> float:
     """Algorithmic bytes per cell of one RK4 step with `iters_per_step` CG
     iterations summed over its 4 solves."""
     b = ALGO_BYTES_PER_CELL
-    per_stage = b["phase_prep"] + b["stage"] + b["rhs"] + b["pcg_init"] + b["project"]
+    per_stage = b["stage"] + b["rhs"] + b["pcg_init"] + b["project"]
     per_iter = b["pcg_spmv"] + b["mg_down"] + b["mg_up"] + MG_COARSE_BYTES_PER_FINE_CELL
     return 4 * per_stage + iters_per_step * per_iter
 
@@ -172,8 +172,7 @@ def hbm_case(CDISolver, nx: int = 2048, steps: int = 10):
     out = {"workload": case.name, "peak": HBM_PEAK_GBS, "unit": "GB/s", "kernels": {}}
     probe = 2
     iters_per_step = None
-    for fam in ("stage", "phase_prep", "rhs", "pcg_init", "mg_down", "mg_up", "pcg_spmv",
-                "project"):
+    for fam in ("stage", "rhs", "pcg_init", "mg_down", "mg_up", "pcg_spmv", "project"):
         s.timing_enable(fam)
         s.step(probe)
         ms, n = s.timing_read()

@@ -226,13 +226,14 @@ cdi_status cdi_eval_rhs(cdi_ctx* ctx, double* l_phi, double* l_mx, double* l_my,
  * u^Y and u_wall - U_wall per wall corner (2*nx each, bottom then top).  All
  * work is enqueued on hip_stream (NULL = default stream) and the call
  * returns without synchronising.
- * Its scratch (instance descriptor, tile list, the phase-field quantities n
- * and mu_c, wall extrapolations, reduction partials and counters) lives in a
- * file-scope device array of CDI_NOALLOC_SCRATCH_BYTES bytes that every GPU
- * the library runs on holds until the process ends; the call performs no
- * device or pinned-host allocation and no memset (a kernel clears the
- * counters).  A grid whose scratch does not fit (about 2.6 M cells in FP64,
- * more on the mixed path) returns CDI_ERR_SHAPE.  Every call on one GPU
+ * Its scratch (instance descriptor, tile list, CG scalars, reduction
+ * partials and counters, wall values when u_y / u_slip are NULL; the
+ * phase-field quantities n and mu_c are formed in the kernel's LDS) lives in
+ * a file-scope device array of CDI_NOALLOC_SCRATCH_BYTES bytes that every
+ * GPU the library runs on holds until the process ends; the call performs
+ * no device or pinned-host allocation and no memset (a kernel clears the
+ * counters).  A grid whose scratch does not fit (about 0.4 bytes per cell:
+ * beyond ~170 M cells) returns CDI_ERR_SHAPE.  Every call on one GPU
  * shares that GPU's array and keeps the last call's contents: calls that
  * overlap on one GPU (different streams or host threads without ordering)
  * race. */

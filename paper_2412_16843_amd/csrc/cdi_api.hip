@@ -644,15 +644,11 @@ cdi_status run_step(cdi_ctx* c) {
   for (int k = 0; k < 4; ++k) {
     const int src = k == 0 ? 0 : (k == 2 ? 2 : 1);
     const int dst = (k == 0 || k == 2) ? 1 : 2;
-    timed(c, "phase_prep", [&] {
-      with_rows(c->wide_rows, [&](auto R) {
-        CDI_LAUNCH(c, (k_phase_prep<S, decltype(R)::value>), nwide, kNT, c->d_wide, c->d_inst, src);
-      });
-    });
-    // per-instance dt: c_next and tau are passed as multiples of the instance dt
+    // phase preparation and stage operator in one launch; per-instance dt:
+    // c_next and tau are passed as multiples of the instance dt
     timed(c, "stage", [&] {
-      CDI_LAUNCH(c, k_stage<S>, ncell, kNT, c->d_cell, c->d_inst, k, src, dst,
-                                                k < 3 ? RK_C[k + 1] : 1.0, RK_B[k], k == 3);
+      CDI_LAUNCH(c, k_stage_fused<S>, ncell, kNT, c->d_cell, c->d_inst, k, src, dst,
+                 k < 3 ? RK_C[k + 1] : 1.0, RK_B[k], k == 3);
     });
     const double tfac = k < 3 ? RK_C[k + 1] : 1.0;
     timed(c, "rhs", [&] {
@@ -777,10 +773,8 @@ cdi_status graph_capture(cdi_ctx* c, int budget) {
       const int src = k == 0 ? 0 : (k == 2 ? 2 : 1);
       const int dst = (k == 0 || k == 2) ? 1 : 2;
       const double tfac = k < 3 ? RK_C[k + 1] : 1.0;
-      with_rows(c->wide_rows, [&](auto R) {
-        k_phase_prep<S, decltype(R)::value><<<nwide, kNT, 0, c->stream>>>(c->d_wide, c->d_inst, src);
-      });
-      k_stage<S><<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, k, src, dst, tfac, RK_B[k], k == 3);
+      k_stage_fused<S><<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, k, src, dst, tfac, RK_B[k],
+                                                      k == 3);
       with_rows(c->wide_rows, [&](auto R) {
         k_rhs<S, decltype(R)::value><<<nwide, kNT, 0, c->stream>>>(c->d_wide, c->d_inst, dst, tfac,
                                                                    c->rtol, c->maxit);
@@ -1139,13 +1133,10 @@ cdi_status cdi_eval_rhs(cdi_ctx* c, double* l_phi, double* l_mx, double* l_my, d
   const size_t nc = (size_t)I.nx * I.ny;
   // the regularisation velocity of a step that would start from this state
   if (c->dyn_gamma) k_gamma_step<<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst);
-  if (c->mixed) {
-    k_phase_prep<float, 1><<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, 0);
-    k_stage<float><<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, -1, 0, 0, 0.0, 0.0, 1);
-  } else {
-    k_phase_prep<double, 1><<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, 0);
-    k_stage<double><<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, -1, 0, 0, 0.0, 0.0, 1);
-  }
+  if (c->mixed)
+    k_stage_fused<float><<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, -1, 0, 0, 0.0, 0.0, 1);
+  else
+    k_stage_fused<double><<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, -1, 0, 0, 0.0, 0.0, 1);
   HIPCHK(hipGetLastError());
   HIPCHK(hipMemcpyAsync(l_phi, I.acc_phi, nc * 8, hipMemcpyDeviceToDevice, c->stream));
   HIPCHK(hipMemcpyAsync(l_mx, I.acc_mx, nc * 8, hipMemcpyDeviceToDevice, c->stream));
@@ -1530,8 +1521,9 @@ void cdi_destroy(cdi_ctx* c) {
 // ============================================== allocation-free stage operator
 // cdi_eval_rhs_noalloc: the stage operator of cdi_eval_rhs with its scratch
 // (instance descriptor, tile list, CG scalars, reduction partials and
-// counters, n, mu_c, wall extrapolations) in a file-scope device array
-// instead of a caller workspace, and no context.
+// counters) in a file-scope device array instead of a caller workspace, and
+// no context.  The fused stage kernel forms n, mu_c and the wall
+// extrapolations in LDS.
 namespace {
 
 constexpr int kMaxDevices = 64;
@@ -1539,12 +1531,10 @@ constexpr int kMaxDevices = 64;
 // Scratch layout of one call (offsets in bytes from the array's device
 // address); with base == nullptr only the size is computed.
 struct NoAllocLayout {
-  size_t inst, pcg, counters, part, tiles, nhx, nhy, muc, wall, uY, uslip, total;
+  size_t inst, pcg, counters, part, tiles, uY, uslip, total;
 };
 
 NoAllocLayout noalloc_layout(const Resolved& R) {
-  const size_t nc = (size_t)R.p.nx * R.p.ny;
-  const size_t S = R.p.precision == CDI_MIXED ? sizeof(float) : sizeof(double);
   const size_t nt = (size_t)cell_tiles(R);
   NoAllocLayout L;
   size_t off = 0;
@@ -1554,10 +1544,6 @@ NoAllocLayout noalloc_layout(const Resolved& R) {
   L.counters = take(sizeof(unsigned) * 8 * kCounterStride);
   L.part = take(sizeof(double) * 8 * nt);
   L.tiles = take(sizeof(Tile) * nt);
-  L.nhx = take(nc * S);
-  L.nhy = take(nc * S);
-  L.muc = take(nc * S);
-  L.wall = take(sizeof(double) * 10 * (size_t)R.p.nx);
   L.uY = take(sizeof(double) * 2 * (size_t)R.p.nx);
   L.uslip = take(sizeof(double) * 2 * (size_t)R.p.nx);
   L.total = off;
@@ -1646,10 +1632,6 @@ cdi_status cdi_eval_rhs_noalloc(const cdi_params* params, const cdi_fields* fiel
   I.pcg = (PcgScalars*)(base + Lo.pcg);
   I.counters = (unsigned*)(base + Lo.counters);
   I.part = (double*)(base + Lo.part);
-  I.nhx = base + Lo.nhx;
-  I.nhy = base + Lo.nhy;
-  I.muc = base + Lo.muc;
-  I.wall = (double*)(base + Lo.wall);
   I.uY = u_y ? u_y : (double*)(base + Lo.uY);
   I.uslip = u_slip ? u_slip : (double*)(base + Lo.uslip);
   I.acc_phi = l_phi;
@@ -1663,13 +1645,10 @@ cdi_status cdi_eval_rhs_noalloc(const cdi_params* params, const cdi_fields* fiel
       I, d_inst, d_tiles, ntx, ntiles, I.counters, ncount, l_my);
   if (R.p.gamma_factor > 0)
     k_gamma_step<<<(unsigned)ntiles, kNT, 0, st>>>(d_tiles, d_inst);
-  if (R.p.precision == CDI_MIXED) {
-    k_phase_prep<float, 1><<<(unsigned)ntiles, kNT, 0, st>>>(d_tiles, d_inst, 0);
-    k_stage<float><<<(unsigned)ntiles, kNT, 0, st>>>(d_tiles, d_inst, -1, 0, 0, 0.0, 0.0, 1);
-  } else {
-    k_phase_prep<double, 1><<<(unsigned)ntiles, kNT, 0, st>>>(d_tiles, d_inst, 0);
-    k_stage<double><<<(unsigned)ntiles, kNT, 0, st>>>(d_tiles, d_inst, -1, 0, 0, 0.0, 0.0, 1);
-  }
+  if (R.p.precision == CDI_MIXED)
+    k_stage_fused<float><<<(unsigned)ntiles, kNT, 0, st>>>(d_tiles, d_inst, -1, 0, 0, 0.0, 0.0, 1);
+  else
+    k_stage_fused<double><<<(unsigned)ntiles, kNT, 0, st>>>(d_tiles, d_inst, -1, 0, 0, 0.0, 0.0, 1);
   HIPCHK(hipGetLastError());
   return CDI_OK;
 }

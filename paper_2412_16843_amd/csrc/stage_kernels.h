@@ -24,19 +24,18 @@ __device__ __forceinline__ int wide_ty(int r) { return threadIdx.x / TX + r * TY
 // Contact-line slip u^Y at wall corner i (Sec. 2 eq. u_slip_Y; Sec. 3 Models
 // 1A..4B).  Wall quantities are linear extrapolations per column (Sec. 4)
 // averaged to the corner; n points into the fluid, tau = +x on both walls.
-__device__ __forceinline__ double slip_uY(const Inst& I, int wall, int i, double& phc_out,
-                                          double& beta_out) {
-  const int nx = I.nx;
-  const double* W = I.wall + (size_t)wall * 5 * nx;
-  const int im = wrap(i - 1, nx);
+// W: the wall's 5 quantities, quantity q of column c at W[q * ws + c]; the
+// corner lies between columns im (west) and i (east).
+__device__ __forceinline__ double slip_uY_w(const Inst& I, const double* W, int ws, int wall,
+                                            int im, int i, double& phc_out, double& beta_out) {
   const double sgn = wall == 0 ? 1.0 : -1.0;
   double phc = 0.5 * (W[im] + W[i]);
   phc = fmin(fmax(phc, 0.0), 1.0);
-  const double psc = 0.5 * (W[nx + im] + W[nx + i]);
-  const double dpn = sgn * 0.5 * (W[2 * nx + im] + W[2 * nx + i]);
-  const double kac = 0.5 * (W[3 * nx + im] + W[3 * nx + i]);
-  const double dphn = sgn * 0.5 * (W[4 * nx + im] + W[4 * nx + i]);
-  const double dpt = (W[nx + i] - W[nx + im]) * I.inv_h;
+  const double psc = 0.5 * (W[ws + im] + W[ws + i]);
+  const double dpn = sgn * 0.5 * (W[2 * ws + im] + W[2 * ws + i]);
+  const double kac = 0.5 * (W[3 * ws + im] + W[3 * ws + i]);
+  const double dphn = sgn * 0.5 * (W[4 * ws + im] + W[4 * ws + i]);
+  const double dpt = (W[ws + i] - W[ws + im]) * I.inv_h;
   const double dpht = (W[i] - W[im]) * I.inv_h;
   const double g = phc * (1.0 - phc);
   const double beta = I.beta2 + (I.beta1 - I.beta2) * phc;
@@ -60,19 +59,36 @@ __device__ __forceinline__ double slip_uY(const Inst& I, int wall, int i, double
   return uY;
 }
 
+// u^Y at wall corner i from the instance's wall arrays (I.wall).
+__device__ __forceinline__ double slip_uY(const Inst& I, int wall, int i, double& phc_out,
+                                          double& beta_out) {
+  const int nx = I.nx;
+  return slip_uY_w(I, I.wall + (size_t)wall * 5 * nx, nx, wall, wrap(i - 1, nx), i, phc_out,
+                   beta_out);
+}
+
 // Robin form of the slip condition: u_wall - U = (mu/beta) du/dn + u^Y with
 // du/dn = 2 (u_row - u_wall)/h along the inward normal.  Returns the wall
-// shear stress mu du/dy at the corner.
-__device__ __forceinline__ double gnbc_corner(const Inst& I, int wall, int i, double urow,
-                                              double& uY, double& uslip) {
+// shear stress mu du/dy at the corner between wall columns im and i of W
+// (layout of slip_uY_w).
+__device__ __forceinline__ double gnbc_corner_w(const Inst& I, const double* W, int ws, int wall,
+                                                int im, int i, double urow, double& uY,
+                                                double& uslip) {
   double phc, beta;
-  uY = slip_uY(I, wall, i, phc, beta);
+  uY = slip_uY_w(I, W, ws, wall, im, i, phc, beta);
   const double U = wall == 0 ? I.uw_bot : I.uw_top;
   const double muw = I.mu2 + (I.mu1 - I.mu2) * phc;
   const double lam = 2.0 * muw / (beta * I.h);
   const double uw = (U + uY + lam * urow) / (1.0 + lam);
   uslip = uw - U;
   return wall == 0 ? 2.0 * muw * (urow - uw) * I.inv_h : 2.0 * muw * (uw - urow) * I.inv_h;
+}
+
+__device__ __forceinline__ double gnbc_corner(const Inst& I, int wall, int i, double urow,
+                                              double& uY, double& uslip) {
+  const int nx = I.nx;
+  return gnbc_corner_w(I, I.wall + (size_t)wall * 5 * nx, nx, wall, wrap(i - 1, nx), i, urow, uY,
+                       uslip);
 }
 
 template <typename T>
@@ -102,16 +118,13 @@ struct PrepLds {
   S psi[(WR * TY + 6) * PRX];
 };
 
-// Cell (ty, tx) of a phase-preparation tile whose LDS region has RY rows.
-template <typename S, int RY>
-__device__ __forceinline__ void phase_prep_cell(const Tile& t, const Inst& I,
-                                                const double* s_phi, const S* s_psi, int tx,
-                                                int ty) {
-  constexpr int RX = PRX;
-  const int nx = I.nx, ny = I.ny;
-  const int i = t.i0 + tx, j = t.j0 + ty;
-  if (i >= nx || j >= ny) return;
-  const int c = (ty + 3) * RX + (tx + 1);
+// n = G/(|G| + dN) and mu_c at the cell of LDS index c (row pitch RX) in
+// grid row j, from the FP64 phase field and psi (one-sided rows at the
+// walls, Sec. 4).
+template <typename S, int RX>
+__device__ __forceinline__ void prep_point(const Inst& I, const double* s_phi, const S* s_psi,
+                                           int c, int j, S& onx, S& ony, S& omu) {
+  const int ny = I.ny;
   const S inv2h = (S)(0.5 * I.inv_h), inv_h2 = (S)(I.inv_h * I.inv_h);
   const S eps = (S)I.eps;
   // normal from phi
@@ -131,47 +144,75 @@ __device__ __forceinline__ void phase_prep_cell(const Tile& t, const Inst& I,
   const S ph = (S)s_phi[c];
   const S g = ph * (S(1) - ph);
   const S grad2 = px * px + py * py;
-  const S mu = S(6) * (S)I.sigma * (g * (S(1) - S(2) * ph) * (S(1) - grad2) / eps - g * lap);
+  onx = gx / mag;
+  ony = gy / mag;
+  omu = S(6) * (S)I.sigma * (g * (S(1) - S(2) * ph) * (S(1) - grad2) / eps - g * lap);
+}
+
+// Wall quantities of the slip models for the column of a wall-row cell (LDS
+// index c, row pitch RX, grid row j = 0 or ny - 1): phi, psi, d psi/dy,
+// kappa and d phi/dy of the wall row and the next row, linearly
+// extrapolated to the wall per column (Sec. 4), in FP64.
+template <typename S, int RX>
+__device__ __forceinline__ void prep_wall(const Inst& I, const double* s_phi, const S* s_psi,
+                                          int c, int j, double out[5]) {
+  const int ny = I.ny;
+  const int dj = j == 0 ? 1 : -1;          // second cell row from the wall
+  const int c2 = c + dj * RX;
+  const int j2 = j + dj;
+  double vals[2][5];
+  for (int r = 0; r < 2; ++r) {
+    const int cc = r == 0 ? c : c2, jj = r == 0 ? j : j2;
+    // FP64 wall quantities from the psi tile
+    const S* qs = s_psi + cc;
+    const double i2h = 0.5 * I.inv_h, ih2 = I.inv_h * I.inv_h;
+    const double p0 = (double)qs[0];
+    double pyd, d2y;
+    if (jj == 0) {
+      pyd = (-3.0 * p0 + 4.0 * (double)qs[RX] - (double)qs[2 * RX]) * i2h;
+      d2y = (2.0 * p0 - 5.0 * (double)qs[RX] + 4.0 * (double)qs[2 * RX] - (double)qs[3 * RX]) * ih2;
+    } else if (jj == ny - 1) {
+      pyd = (3.0 * p0 - 4.0 * (double)qs[-RX] + (double)qs[-2 * RX]) * i2h;
+      d2y = (2.0 * p0 - 5.0 * (double)qs[-RX] + 4.0 * (double)qs[-2 * RX] - (double)qs[-3 * RX]) * ih2;
+    } else {
+      pyd = ((double)qs[RX] - (double)qs[-RX]) * i2h;
+      d2y = ((double)qs[RX] - 2.0 * p0 + (double)qs[-RX]) * ih2;
+    }
+    const double pxd = ((double)qs[1] - (double)qs[-1]) * i2h;
+    const double lapd = ((double)qs[1] - 2.0 * p0 + (double)qs[-1]) * ih2 + d2y;
+    const double phd = s_phi[cc];
+    const double kap = (1.0 - 2.0 * phd) * (1.0 - pxd * pxd - pyd * pyd) / I.eps - lapd;
+    double phy;
+    if (jj == 0) phy = (-3.0 * phd + 4.0 * s_phi[cc + RX] - s_phi[cc + 2 * RX]) * i2h;
+    else if (jj == ny - 1) phy = (3.0 * phd - 4.0 * s_phi[cc - RX] + s_phi[cc - 2 * RX]) * i2h;
+    else phy = (s_phi[cc + RX] - s_phi[cc - RX]) * i2h;
+    vals[r][0] = phd; vals[r][1] = p0; vals[r][2] = pyd; vals[r][3] = kap; vals[r][4] = phy;
+  }
+  for (int qk = 0; qk < 5; ++qk) out[qk] = 0.5 * (3.0 * vals[0][qk] - vals[1][qk]);
+}
+
+// Cell (ty, tx) of a phase-preparation tile whose LDS region has RY rows.
+template <typename S, int RY>
+__device__ __forceinline__ void phase_prep_cell(const Tile& t, const Inst& I,
+                                                const double* s_phi, const S* s_psi, int tx,
+                                                int ty) {
+  constexpr int RX = PRX;
+  const int nx = I.nx, ny = I.ny;
+  const int i = t.i0 + tx, j = t.j0 + ty;
+  if (i >= nx || j >= ny) return;
+  const int c = (ty + 3) * RX + (tx + 1);
+  S vnx, vny, vmu;
+  prep_point<S, RX>(I, s_phi, s_psi, c, j, vnx, vny, vmu);
   const size_t o = (size_t)j * nx + i;
-  ((S*)I.nhx)[o] = gx / mag;
-  ((S*)I.nhy)[o] = gy / mag;
-  ((S*)I.muc)[o] = mu;
+  ((S*)I.nhx)[o] = vnx;
+  ((S*)I.nhy)[o] = vny;
+  ((S*)I.muc)[o] = vmu;
   // wall rows: extrapolate phi, psi, d psi/dy, kappa, d phi/dy to the wall (per column)
   if (j == 0 || j == ny - 1) {
-    const int wall = j == 0 ? 0 : 1;
-    const int dj = j == 0 ? 1 : -1;          // second cell row from the wall
-    const int c2 = c + dj * RX;
-    const int j2 = j + dj;
-    double vals[2][5];
-    for (int r = 0; r < 2; ++r) {
-      const int cc = r == 0 ? c : c2, jj = r == 0 ? j : j2;
-      // FP64 wall quantities from the psi tile
-      const S* qs = s_psi + cc;
-      const double i2h = 0.5 * I.inv_h, ih2 = I.inv_h * I.inv_h;
-      const double p0 = (double)qs[0];
-      double pyd, d2y;
-      if (jj == 0) {
-        pyd = (-3.0 * p0 + 4.0 * (double)qs[RX] - (double)qs[2 * RX]) * i2h;
-        d2y = (2.0 * p0 - 5.0 * (double)qs[RX] + 4.0 * (double)qs[2 * RX] - (double)qs[3 * RX]) * ih2;
-      } else if (jj == ny - 1) {
-        pyd = (3.0 * p0 - 4.0 * (double)qs[-RX] + (double)qs[-2 * RX]) * i2h;
-        d2y = (2.0 * p0 - 5.0 * (double)qs[-RX] + 4.0 * (double)qs[-2 * RX] - (double)qs[-3 * RX]) * ih2;
-      } else {
-        pyd = ((double)qs[RX] - (double)qs[-RX]) * i2h;
-        d2y = ((double)qs[RX] - 2.0 * p0 + (double)qs[-RX]) * ih2;
-      }
-      const double pxd = ((double)qs[1] - (double)qs[-1]) * i2h;
-      const double lapd = ((double)qs[1] - 2.0 * p0 + (double)qs[-1]) * ih2 + d2y;
-      const double phd = s_phi[cc];
-      const double kap = (1.0 - 2.0 * phd) * (1.0 - pxd * pxd - pyd * pyd) / I.eps - lapd;
-      double phy;
-      if (jj == 0) phy = (-3.0 * phd + 4.0 * s_phi[cc + RX] - s_phi[cc + 2 * RX]) * i2h;
-      else if (jj == ny - 1) phy = (3.0 * phd - 4.0 * s_phi[cc - RX] + s_phi[cc - 2 * RX]) * i2h;
-      else phy = (s_phi[cc + RX] - s_phi[cc - RX]) * i2h;
-      vals[r][0] = phd; vals[r][1] = p0; vals[r][2] = pyd; vals[r][3] = kap; vals[r][4] = phy;
-    }
-    double* W = I.wall + (size_t)wall * 5 * nx;
-    for (int qk = 0; qk < 5; ++qk) W[qk * nx + i] = 0.5 * (3.0 * vals[0][qk] - vals[1][qk]);
+    double w[5];
+    prep_wall<S, RX>(I, s_phi, s_psi, c, j, w);
+    double* W = I.wall + (size_t)(j == 0 ? 0 : 1) * 5 * nx;
+    for (int qk = 0; qk < 5; ++qk) W[qk * nx + i] = w[qk];
   }
 }
 
@@ -247,30 +288,48 @@ constexpr int UY = TY + 2, UX = TX + 2;   // u/v: rows j0-1..j0+TY, cols i0-1..i
 constexpr int XY = TY + 1, XX = TX + 2;   // x-faces: rows j0-1..j0+TY-1, cols i0-1..i0+TX
 constexpr int YY = TY + 2, YX = TX + 1;   // y-faces: rows j0-1..j0+TY, cols i0-1..i0+TX-1
 constexpr int CRY = TY + 1, CRX = TX + 1; // corners: rows j0..j0+TY, cols i0..i0+TX
+constexpr int PY = TY + 5, PX = TX + 5;   // fused prep: phi rows j0-3..j0+TY+1, cols i0-3..i0+TX+1
+constexpr int WX = TX + 2;                // fused prep: wall columns i0-1..i0+TX
 }  // namespace st
 
 template <typename S>
 struct StageLds {
   S phi[st::CY * st::CX], nx[st::CY * st::CX], ny[st::CY * st::CX], mc[st::CY * st::CX];
   S u[st::UY * st::UX], v[st::UY * st::UX];
-  S fx[st::XY * st::XX], mx[st::XY * st::XX];
-  S fy[st::YY * st::YX], my[st::YY * st::YX];
-  S txy[st::CRY * st::CRX];
+  union {
+    struct {
+      S fx[st::XY * st::XX], mx[st::XY * st::XX];
+      S fy[st::YY * st::YX], my[st::YY * st::YX];
+      S txy[st::CRY * st::CRX];
+    } f;
+    // fused phase preparation: the FP64 phase field and psi of the region
+    // the tile's n and mu_c need, dead once those are formed
+    struct {
+      double phi[st::PY * st::PX];
+      S psi[st::PY * st::PX];
+    } p;
+  } x;
 };
 
 // One tile of the stage operator, run by kNT threads (tid in [0, kNT)).
 // Contains two block barriers: every thread of the block calls it, with
 // active = false for threads that have no tile in this pass over the tiles.
-template <typename S>
+// Fused = true (tiled kernel k_stage_fused): n and mu_c of the tile and its
+// halo, and the wall extrapolations of its columns, are formed here from the
+// phase field (the arithmetic of the phase preparation, prep_point and
+// prep_wall) instead of being read from the arrays k_phase_prep writes;
+// s_wall holds the wall quantities (5 x WX doubles).
+template <typename S, bool Fused = false>
 __device__ __forceinline__ void stage_tile(const Tile& t, const Inst& I, int k, int src, int dst,
                                            double c_next, double b_k, int write_wall,
-                                           StageLds<S>& L, int tid, bool active) {
+                                           StageLds<S>& L, int tid, bool active,
+                                           double* s_wall = nullptr) {
   using namespace st;
   S* s_phi = L.phi; S* s_nx = L.nx; S* s_ny = L.ny; S* s_mc = L.mc;
   S* s_u = L.u; S* s_v = L.v;
-  S* s_fx = L.fx; S* s_mx = L.mx;
-  S* s_fy = L.fy; S* s_my = L.my;
-  S* s_txy = L.txy;
+  S* s_fx = L.x.f.fx; S* s_mx = L.x.f.mx;
+  S* s_fy = L.x.f.fy; S* s_my = L.x.f.my;
+  S* s_txy = L.x.f.txy;
   const int nx = I.nx, ny = I.ny;
   const int i0 = t.i0, j0 = t.j0;
   const double* __restrict__ phs = src == 0 ? I.phi : (src == 1 ? I.phi_a : I.phi_b);
@@ -298,7 +357,77 @@ __device__ __forceinline__ void stage_tile(const Tile& t, const Inst& I, int k, 
     pre_v = I.v[co_];
   }
   // halo regions: every load of the thread first, then the LDS stores
-  {
+  if constexpr (Fused) {
+    // phase field of rows j0-3..j0+TY+1, columns i0-3..i0+TX+1 (FP64), psi
+    // from it, then n and mu_c on the stage region and the wall quantities
+    constexpr int NP = (PY * PX + kNT - 1) / kNT, NU = (UY * UX + kNT - 1) / kNT;
+    double fv[NP];
+    S vu[NU][2];
+#pragma unroll
+    for (int e = 0; e < NP; ++e) {
+      const int q = tid + e * kNT;
+      const int rj = q / PX, ri = q - rj * PX;
+      const int j = j0 - 3 + rj;
+      fv[e] = 0.0;
+      if (active && q < PY * PX && j >= 0 && j < ny)
+        fv[e] = phs[(size_t)j * nx + wrap_any(i0 - 3 + ri, nx)];
+    }
+#pragma unroll
+    for (int e = 0; e < NU; ++e) {
+      const int q = tid + e * kNT;
+      const int rj = q / UX, ri = q - rj * UX;
+      const int j = j0 - 1 + rj;
+      vu[e][0] = vu[e][1] = S(0);
+      if (active && q < UY * UX) {
+        const size_t o = (size_t)j * nx + wrap_any(i0 - 1 + ri, nx);
+        if (j >= 0 && j < ny) vu[e][0] = (S)us[o];
+        if (j >= 0 && j <= ny) vu[e][1] = (S)vs[o];
+      }
+    }
+    double* p_phi = L.x.p.phi;
+    S* p_psi = L.x.p.psi;
+#pragma unroll
+    for (int e = 0; e < NP; ++e) {
+      const int q = tid + e * kNT;
+      if (!active || q >= PY * PX) continue;
+      const int j = j0 - 3 + q / PX;
+      double ps = 0.0;
+      if (j >= 0 && j < ny) {
+        const double cl = fmin(fmax(fv[e], 0.0), 1.0);
+        ps = I.eps * log((cl + kDeltaPsi) / (1.0 - cl + kDeltaPsi));
+      }
+      p_phi[q] = fv[e];
+      p_psi[q] = (S)ps;
+    }
+#pragma unroll
+    for (int e = 0; e < NU; ++e) {
+      const int q = tid + e * kNT;
+      if (active && q < UY * UX) { s_u[q] = vu[e][0]; s_v[q] = vu[e][1]; }
+    }
+    __syncthreads();
+    for (int q = tid; active && q < CY * CX; q += kNT) {
+      const int rj = q / CX, ri = q - rj * CX;
+      const int j = j0 - 2 + rj;
+      S a0 = S(0), a1 = S(0), a2 = S(0), a3 = S(0);
+      if (j >= 0 && j < ny) {
+        const int c = (rj + 1) * PX + (ri + 1);   // the cell in the phi region
+        a0 = (S)p_phi[c];
+        prep_point<S, PX>(I, p_phi, p_psi, c, j, a1, a2, a3);
+      }
+      s_phi[q] = a0; s_nx[q] = a1; s_ny[q] = a2; s_mc[q] = a3;
+    }
+    // wall quantities of columns i0-1..i0+TX for the wall this tile touches
+    // (the bottom one when j0 = 0, the top one when its corner rows reach ny)
+    if (j0 == 0 || j0 + TY >= ny) {
+      const int jw = j0 == 0 ? 0 : ny - 1;
+      for (int lc = tid; active && lc < WX; lc += kNT) {
+        double w[5];
+        prep_wall<S, PX>(I, p_phi, p_psi, (jw - (j0 - 3)) * PX + (lc + 2), jw, w);
+        for (int qk = 0; qk < 5; ++qk) s_wall[qk * WX + lc] = w[qk];
+      }
+    }
+    __syncthreads();   // the flux arrays below reuse the phi / psi region
+  } else {
     constexpr int NC = (CY * CX + kNT - 1) / kNT, NU = (UY * UX + kNT - 1) / kNT;
     S va[NC][4];
     S vu[NU][2];
@@ -337,8 +466,8 @@ __device__ __forceinline__ void stage_tile(const Tile& t, const Inst& I, int k, 
       const int q = tid + e * kNT;
       if (active && q < UY * UX) { s_u[q] = vu[e][0]; s_v[q] = vu[e][1]; }
     }
+    __syncthreads();
   }
-  __syncthreads();
   const S gam = (S)I.pcg->gamma_step, eps = (S)I.eps, inv_h = (S)I.inv_h;
   const S drho = (S)(I.rho1 - I.rho2), rho2 = (S)I.rho2;
   // x-face fluxes (each face computed once per block by this one code path)
@@ -399,7 +528,10 @@ __device__ __forceinline__ void stage_tile(const Tile& t, const Inst& I, int k, 
         const int urow = wall == 0 ? 0 : ny - 1;
         const double ur = (double)s_u[(urow - (j0 - 1)) * UX + (ri + 1)];
         double uY, usl;
-        tau = (S)gnbc_corner(I, wall, ii, ur, uY, usl);
+        if constexpr (Fused)   // wall columns ic - 1 and ic are local columns ri and ri + 1
+          tau = (S)gnbc_corner_w(I, s_wall, WX, wall, ri, ri + 1, ur, uY, usl);
+        else
+          tau = (S)gnbc_corner(I, wall, ii, ur, uY, usl);
         if (write_wall && ri < TX && ic < nx) {
           I.uY[wall * nx + ic] = uY;
           I.uslip[wall * nx + ic] = usl;
@@ -507,13 +639,20 @@ __device__ __forceinline__ void stage_tile(const Tile& t, const Inst& I, int k, 
   }
 }
 
+// The stage kernel of the tiled launch, with the phase preparation fused in:
+// one launch per RK stage instead of two, and no n, mu_c and wall arrays
+// written and read back through memory (the persistent kernel runs the
+// preparation and the stage as two passes over its tiles).
 template <typename S>
-__global__ void __launch_bounds__(kNT) k_stage(const Tile* __restrict__ tiles,
-                                                const Inst* __restrict__ insts, int k, int src,
-                                                int dst, double c_next, double b_k, int write_wall) {
+__global__ void __launch_bounds__(kNT) k_stage_fused(const Tile* __restrict__ tiles,
+                                                      const Inst* __restrict__ insts, int k,
+                                                      int src, int dst, double c_next, double b_k,
+                                                      int write_wall) {
   __shared__ StageLds<S> L;
+  __shared__ double s_wall[5 * st::WX];
   const Tile t = tiles[blockIdx.x];
-  stage_tile<S>(t, insts[t.inst], k, src, dst, c_next, b_k, write_wall, L, threadIdx.x, true);
+  stage_tile<S, true>(t, insts[t.inst], k, src, dst, c_next, b_k, write_wall, L, threadIdx.x, true,
+                      s_wall);
 }
 
 }  // namespace cdi

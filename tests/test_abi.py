@@ -125,12 +125,13 @@ def test_smoothing_sweeps_validated_on_host():
 
 def test_noalloc_entry_point_rejects_a_grid_beyond_its_scratch():
     """cdi_eval_rhs_noalloc checks the scratch its grid needs against the
-    fixed array before any device work: a 4096 x 2048 grid (8.4 M cells)
-    does not fit the 64 MiB and returns CDI_ERR_SHAPE with a message."""
+    fixed array before any device work: a 32768 x 16384 grid (537 M cells,
+    2.1 M tiles) does not fit the 64 MiB and returns CDI_ERR_SHAPE with a
+    message."""
     L = _lib()
     lib = L.lib()
-    case = W.drop_case(4096, 2048, 60.0, 10.0)
-    cp = L.make_params(case.params)
+    big = W.config1().params.replace(nx=32768, ny=16384, eps=2.0 / 32768)
+    cp = L.make_params(big)
     dummy = 256   # never dereferenced: the size check comes first
     cf = L.cdi_fields(dummy, dummy, dummy, None)
     st = lib.cdi_eval_rhs_noalloc(C.byref(cp), C.byref(cf), dummy, dummy, dummy, None, None,
