@@ -127,3 +127,39 @@ class GuessNet:
             self.close()
         except Exception:
             pass
+
+
+def main(argv=None):
+    """Time the inference forward pass of a randomly initialised network on
+    an h x w image (the learned guess's cost per solve), e.g. under a
+    profiler:  python -m paper_2412_16843_amd.learned --h 1024 --w 2048"""
+    import argparse
+    import time
+    ap = argparse.ArgumentParser(description=main.__doc__.split("\n")[0])
+    ap.add_argument("--h", type=int, default=1024)
+    ap.add_argument("--w", type=int, default=2048)
+    ap.add_argument("--reps", type=int, default=20)
+    a = ap.parse_args(argv)
+    net = GuessNet(1, a.h, a.w, train=False)
+    x = torch.randn((1, 3, a.h, a.w), dtype=torch.float32, device=net.device)
+    net.forward(x)
+    torch.cuda.synchronize(net.device)
+    t0 = time.perf_counter()
+    for _ in range(a.reps):
+        net.forward(x)
+    torch.cuda.synchronize(net.device)
+    ms = (time.perf_counter() - t0) / a.reps * 1e3
+    net.close()
+    # 3x3 convolutions: 2 * co * ci * 9 per pixel of each level (decoder
+    # inputs include the skip channels), plus the 1x1 output layer
+    flops, hw = 0.0, a.h * a.w
+    for name, ci, co in CONV3:
+        lvl = {"e0": 0, "e1": 1, "e2": 2, "e3": 3, "d2": 2, "d1": 1, "d0": 0}[name]
+        flops += 2.0 * co * ci * 9 * hw / 4 ** lvl
+    flops += 2.0 * 32 * hw
+    print(f"forward {a.h}x{a.w}: {ms:.3f} ms, {flops / 1e9:.1f} GFLOP (3 input channels), "
+          f"{flops / ms / 1e9:.1f} TFLOP/s", flush=True)
+
+
+if __name__ == "__main__":
+    main()
