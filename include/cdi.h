@@ -72,7 +72,7 @@ enum { CDI_LAUNCH_TILED = 0, CDI_LAUNCH_PERSISTENT = 1, CDI_LAUNCH_GRAPH = 2 };
  * a default is stated takes that default. */
 typedef struct {
   int32_t abi_version;   /* must be CDI_ABI_VERSION                                  */
-  int32_t nx, ny;        /* cells; nx >= 8, ny >= 8, both even                        */
+  int32_t nx, ny;        /* cells; nx >= 8, ny >= 8, both even, nx (ny+1) < 2^31   */
   double lx, ly;         /* domain; lx/nx must equal ly/ny (uniform h)                */
   double eps;            /* interface thickness eps > 0               (eq. CDI)       */
   double gamma;          /* regularisation velocity gamma > 0         (eq. CDI)       */

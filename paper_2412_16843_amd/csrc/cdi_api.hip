@@ -72,6 +72,8 @@ cdi_status resolve(const cdi_params* in, Resolved& r) {
     return fail(CDI_ERR_ARG, "abi_version %d != %d", p.abi_version, CDI_ABI_VERSION);
   if (p.nx < 8 || p.ny < 8 || (p.nx & 1) || (p.ny & 1))
     return fail(CDI_ERR_SHAPE, "nx=%d ny=%d: both must be even and >= 8", p.nx, p.ny);
+  if ((long long)p.nx * (p.ny + 1) >= (1LL << 31))
+    return fail(CDI_ERR_SHAPE, "nx=%d ny=%d: more than 2^31 - 1 cells", p.nx, p.ny);
   if (!(p.lx > 0) || !(p.ly > 0)) return fail(CDI_ERR_ARG, "lx, ly must be > 0");
   const double hx = p.lx / p.nx, hy = p.ly / p.ny;
   if (std::fabs(hx - hy) > 1e-12 * hx) return fail(CDI_ERR_SHAPE, "lx/nx=%g != ly/ny=%g", hx, hy);
@@ -219,6 +221,8 @@ struct Batch {
   // tile lists (host), concatenated into one device array
   std::vector<Tile> cell;               // level-0 cell tiles of every instance
   std::vector<Tile> wide;               // level-0 wide tiles of every instance
+  std::vector<Tile> strip;              // level-0 strips of the FP64 stage kernel
+  int strip_rows = sr::SH;              // rows of a strip
   std::vector<std::vector<Tile>> mg;    // per level: multigrid tiles of instances with level < lc
   int max_lc = 0, max_nlev = 0, max_lg = 0;
   size_t shared_bytes = 0;
@@ -259,6 +263,23 @@ void build_mg(Batch& B) {
   }
 }
 
+int strip_tiles(const Resolved& R, int rows) { return ceil_div(R.p.nx, sr::TW) * ceil_div(R.p.ny, rows); }
+
+// Rows of the stage kernel's strips: the tallest of 64, 32, 16 that still
+// gives every CU several strips (each strip's first chunk recomputes a few
+// halo rows, so taller strips do less work, but fewer of them fill the GPU
+// less evenly).
+constexpr int kStripRows[3] = {64, 32, 16};
+constexpr long kStripBlocksMin = 256L * 3 * 3;   // CUs x resident strips x rounds
+int strip_rows(const std::vector<Resolved>& Rs) {
+  for (int r : kStripRows) {
+    long n = 0;
+    for (const Resolved& R : Rs) n += strip_tiles(R, r);
+    if (n >= kStripBlocksMin) return r;
+  }
+  return kStripRows[2];
+}
+
 void build_tiles(Batch& B, int wide_rows) {
   B.cell.clear();
   B.max_lc = 0;
@@ -275,6 +296,14 @@ void build_tiles(Batch& B, int wide_rows) {
     for (int j0 = 0; j0 < R.p.ny; j0 += TY)
       for (int i0 = 0; i0 < R.p.nx; i0 += TX) B.cell.push_back(Tile{k, i0, j0, 0, local++, {0, 0, 0}});
     I.ntiles = local;
+  }
+  B.strip.clear();
+  B.strip_rows = strip_rows(B.R);
+  for (int k = 0; k < B.n; ++k) {
+    const Resolved& R = B.R[k];
+    int local = 0;
+    for (int j0 = 0; j0 < R.p.ny; j0 += B.strip_rows)
+      for (int i0 = 0; i0 < R.p.nx; i0 += sr::TW) B.strip.push_back(Tile{k, i0, j0, 0, local++, {0, 0, 0}});
   }
   build_mg(B);
   build_wide(B, wide_rows);
@@ -314,9 +343,10 @@ int cell_tiles(const Resolved& R) { return ceil_div(R.p.nx, TX) * ceil_div(R.p.n
 size_t batch_bytes(const std::vector<Resolved>& Rs, Batch* B, char* base) {
   const int n = (int)Rs.size();
   // shared header: instances, diag outputs, tile lists
-  size_t ntile_cell = 0, ntile_mg = 0, ntile_wide = 0;
+  size_t ntile_cell = 0, ntile_mg = 0, ntile_wide = 0, ntile_strip = 0;
   for (auto& R : Rs) {
     ntile_cell += cell_tiles(R);
+    ntile_strip += strip_tiles(R, kStripRows[2]);   // room for the shortest strips
     ntile_wide += (size_t)cell_tiles(R);   // room for the shortest wide tile (1 row)
     int nx = R.p.nx, ny = R.p.ny;
     for (int l = 0; l < R.lc; ++l) { ntile_mg += (size_t)ceil_div(nx, FX) * ceil_div(ny, FY); nx /= 2; ny /= 2; }
@@ -325,7 +355,7 @@ size_t batch_bytes(const std::vector<Resolved>& Rs, Batch* B, char* base) {
   off = align256(off + sizeof(Inst) * n);
   off = align256(off + sizeof(DiagOut) * n);
   off = align256(off + sizeof(PcgScalars) * n);
-  off = align256(off + sizeof(Tile) * (2 * ntile_cell + ntile_wide + ntile_mg + 1));
+  off = align256(off + sizeof(Tile) * (2 * ntile_cell + ntile_wide + ntile_mg + ntile_strip + 1));
   for (int k = 0; k < n; ++k)
     off = carve(Rs[k], cell_tiles(Rs[k]), mg0_tiles(Rs[k]), base, off, B ? &B->inst[k] : nullptr);
   (void)B;
@@ -340,7 +370,7 @@ void fill_inst(const Resolved& R, const cdi_fields& f, Inst& I) {
   I.slip_model = p.slip_model;
   I.mixed = p.precision == CDI_MIXED;
   I.h = R.h; I.inv_h = 1.0 / R.h;
-  I.eps = p.eps; I.gamma = p.gamma; I.sigma = p.sigma; I.cos_eq = std::cos(p.theta_eq);
+  I.eps = p.eps; I.inv_eps = 1.0 / p.eps; I.gamma = p.gamma; I.sigma = p.sigma; I.cos_eq = std::cos(p.theta_eq);
   I.gamma_factor = p.gamma_factor;
   I.rho1 = p.rho1; I.rho2 = p.rho2; I.mu1 = p.mu1; I.mu2 = p.mu2;
   I.beta1 = p.beta1; I.beta2 = p.beta2;
@@ -361,6 +391,7 @@ struct cdi_ctx {
   Tile* d_cell = nullptr;          // level-0 tiles, XCD-banded order (tiled launches)
   Tile* d_cell_inst = nullptr;     // level-0 tiles, instance by instance (persistent launch)
   Tile* d_wide = nullptr;          // level-0 wide tiles, XCD-banded order
+  Tile* d_strip = nullptr;         // level-0 strips of the stage kernel, XCD-banded order
   std::vector<Tile*> d_mg;
   bool mixed = false;
   bool uniform_rho = true;
@@ -459,6 +490,20 @@ void timed(cdi_ctx* c, const char* name, F&& body, bool single = true) {
 #define CDI_LAUNCH(c, kern, grid, block, ...)                                          \
   hipExtLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, (c)->stream, (c)->kev0,     \
                         (c)->kev1, 0, __VA_ARGS__)
+
+// The stage operator of every instance (phase preparation fused in): the
+// strip kernel in FP64; in mixed precision the 64 x 4 tile kernel, whose
+// lower register count keeps more waves resident.
+template <typename S>
+void launch_stage(cdi_ctx* c, int k, int src, int dst, double c_next, double b_k, int write_wall) {
+  const Batch& B = c->B;
+  if constexpr (std::is_same<S, double>::value)
+    CDI_LAUNCH(c, k_stage_strip<double>, (unsigned)B.strip.size(), kNT, c->d_strip, c->d_inst, k,
+               src, dst, c_next, b_k, write_wall, B.strip_rows);
+  else
+    CDI_LAUNCH(c, k_stage_fused<float>, (unsigned)B.cell.size(), kNT, c->d_cell, c->d_inst, k, src,
+               dst, c_next, b_k, write_wall);
+}
 
 // V-cycle z = M r over every instance.  update: the first kernel applies the
 // CG step (d from buffer dpar) and the stopping test; rsel: residual buffer
@@ -647,8 +692,7 @@ cdi_status run_step(cdi_ctx* c) {
     // phase preparation and stage operator in one launch; per-instance dt:
     // c_next and tau are passed as multiples of the instance dt
     timed(c, "stage", [&] {
-      CDI_LAUNCH(c, k_stage_fused<S>, ncell, kNT, c->d_cell, c->d_inst, k, src, dst,
-                 k < 3 ? RK_C[k + 1] : 1.0, RK_B[k], k == 3);
+      launch_stage<S>(c, k, src, dst, k < 3 ? RK_C[k + 1] : 1.0, RK_B[k], k == 3);
     });
     const double tfac = k < 3 ? RK_C[k + 1] : 1.0;
     timed(c, "rhs", [&] {
@@ -773,8 +817,7 @@ cdi_status graph_capture(cdi_ctx* c, int budget) {
       const int src = k == 0 ? 0 : (k == 2 ? 2 : 1);
       const int dst = (k == 0 || k == 2) ? 1 : 2;
       const double tfac = k < 3 ? RK_C[k + 1] : 1.0;
-      k_stage_fused<S><<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, k, src, dst, tfac, RK_B[k],
-                                                      k == 3);
+      launch_stage<S>(c, k, src, dst, tfac, RK_B[k], k == 3);
       with_rows(c->wide_rows, [&](auto R) {
         k_rhs<S, decltype(R)::value><<<nwide, kNT, 0, c->stream>>>(c->d_wide, c->d_inst, dst, tfac,
                                                                    c->rtol, c->maxit);
@@ -1004,6 +1047,12 @@ cdi_status cdi_init_batch(const cdi_params* params, int32_t n, const cdi_fields*
       if (l < Rs[k].lc)
         pos += (size_t)ceil_div(Rs[k].lnx[l], FX) * ceil_div(Rs[k].lny[l], FY);
   }
+  c->d_strip = tl + pos;
+  {
+    const std::vector<Tile> sv = xcd_order(B.strip);
+    all.resize(pos, Tile{});
+    all.insert(all.end(), sv.begin(), sv.end());
+  }
   c->h_pcg = nullptr;
   hipError_t e = hipHostMalloc((void**)&c->h_pcg, sizeof(PcgScalars) * n, hipHostMallocDefault);
   if (e != hipSuccess) { delete c; return fail(CDI_ERR_DEVICE, "hipHostMalloc: %s", hipGetErrorString(e)); }
@@ -1134,9 +1183,9 @@ cdi_status cdi_eval_rhs(cdi_ctx* c, double* l_phi, double* l_mx, double* l_my, d
   // the regularisation velocity of a step that would start from this state
   if (c->dyn_gamma) k_gamma_step<<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst);
   if (c->mixed)
-    k_stage_fused<float><<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, -1, 0, 0, 0.0, 0.0, 1);
+    launch_stage<float>(c, -1, 0, 0, 0.0, 0.0, 1);
   else
-    k_stage_fused<double><<<ncell, kNT, 0, c->stream>>>(c->d_cell, c->d_inst, -1, 0, 0, 0.0, 0.0, 1);
+    launch_stage<double>(c, -1, 0, 0, 0.0, 0.0, 1);
   HIPCHK(hipGetLastError());
   HIPCHK(hipMemcpyAsync(l_phi, I.acc_phi, nc * 8, hipMemcpyDeviceToDevice, c->stream));
   HIPCHK(hipMemcpyAsync(l_mx, I.acc_mx, nc * 8, hipMemcpyDeviceToDevice, c->stream));
@@ -1522,8 +1571,8 @@ void cdi_destroy(cdi_ctx* c) {
 // cdi_eval_rhs_noalloc: the stage operator of cdi_eval_rhs with its scratch
 // (instance descriptor, tile list, CG scalars, reduction partials and
 // counters) in a file-scope device array instead of a caller workspace, and
-// no context.  The fused stage kernel forms n, mu_c and the wall
-// extrapolations in LDS.
+// no context.  The stage kernel (strip kernel in FP64, tile kernel in mixed
+// precision) forms n, mu_c and the wall extrapolations in LDS.
 namespace {
 
 constexpr int kMaxDevices = 64;
@@ -1543,7 +1592,7 @@ NoAllocLayout noalloc_layout(const Resolved& R) {
   L.pcg = take(sizeof(PcgScalars));
   L.counters = take(sizeof(unsigned) * 8 * kCounterStride);
   L.part = take(sizeof(double) * 8 * nt);
-  L.tiles = take(sizeof(Tile) * nt);
+  L.tiles = take(sizeof(Tile) * (nt + (size_t)strip_tiles(R, kStripRows[2])));
   L.uY = take(sizeof(double) * 2 * (size_t)R.p.nx);
   L.uslip = take(sizeof(double) * 2 * (size_t)R.p.nx);
   L.total = off;
@@ -1582,10 +1631,12 @@ cdi_status scratch_address(void** out) {
 
 // One launch that prepares a call in the scratch: the instance descriptor
 // (passed by value), its CG scalars' regularisation velocity, the level-0
-// cell tile list, cleared arrival counters (their reductions start from
-// zero), and the two wall rows of L_my, which the stage kernel leaves alone.
+// cell tile list followed by the strip list of the stage kernel, cleared
+// arrival counters (their reductions start from zero), and the two wall rows
+// of L_my, which the stage kernel leaves alone.
 __global__ void k_noalloc_setup(Inst I, Inst* __restrict__ dst, Tile* __restrict__ tiles,
-                                int ntx, int ntiles, unsigned* __restrict__ counters,
+                                int ntx, int ntiles, int ntxs, int nstrips, int srows,
+                                unsigned* __restrict__ counters,
                                 int ncounters, double* __restrict__ l_my) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g == 0) {
@@ -1593,6 +1644,8 @@ __global__ void k_noalloc_setup(Inst I, Inst* __restrict__ dst, Tile* __restrict
     I.pcg->gamma_step = I.gamma;
   }
   if (g < ntiles) tiles[g] = Tile{0, (g % ntx) * TX, (g / ntx) * TY, 0, g, {0, 0, 0}};
+  if (g < nstrips)
+    tiles[ntiles + g] = Tile{0, (g % ntxs) * sr::TW, (g / ntxs) * srows, 0, g, {0, 0, 0}};
   if (g < ncounters) counters[g] = 0u;
   if (g < I.nx) {
     l_my[g] = 0.0;
@@ -1627,6 +1680,8 @@ cdi_status cdi_eval_rhs_noalloc(const cdi_params* params, const cdi_fields* fiel
   Inst I{};
   fill_inst(R, *fields, I);
   const int ntx = ceil_div(R.p.nx, TX), ntiles = cell_tiles(R);
+  const int srows = strip_rows({R});
+  const int ntxs = ceil_div(R.p.nx, sr::TW), nstrips = strip_tiles(R, srows);
   I.first_tile = 0;
   I.ntiles = ntiles;
   I.pcg = (PcgScalars*)(base + Lo.pcg);
@@ -1640,15 +1695,16 @@ cdi_status cdi_eval_rhs_noalloc(const cdi_params* params, const cdi_fields* fiel
   Inst* d_inst = (Inst*)(base + Lo.inst);
   Tile* d_tiles = (Tile*)(base + Lo.tiles);
   const int ncount = 8 * kCounterStride;
-  const int nset = std::max(std::max(ntiles, ncount), R.p.nx);
+  const int nset = std::max(std::max(std::max(ntiles, nstrips), ncount), R.p.nx);
   k_noalloc_setup<<<(unsigned)ceil_div(nset, kNT), kNT, 0, st>>>(
-      I, d_inst, d_tiles, ntx, ntiles, I.counters, ncount, l_my);
+      I, d_inst, d_tiles, ntx, ntiles, ntxs, nstrips, srows, I.counters, ncount, l_my);
   if (R.p.gamma_factor > 0)
     k_gamma_step<<<(unsigned)ntiles, kNT, 0, st>>>(d_tiles, d_inst);
   if (R.p.precision == CDI_MIXED)
     k_stage_fused<float><<<(unsigned)ntiles, kNT, 0, st>>>(d_tiles, d_inst, -1, 0, 0, 0.0, 0.0, 1);
   else
-    k_stage_fused<double><<<(unsigned)ntiles, kNT, 0, st>>>(d_tiles, d_inst, -1, 0, 0, 0.0, 0.0, 1);
+    k_stage_strip<double><<<(unsigned)nstrips, kNT, 0, st>>>(d_tiles + ntiles, d_inst, -1, 0, 0,
+                                                              0.0, 0.0, 1, srows);
   HIPCHK(hipGetLastError());
   return CDI_OK;
 }

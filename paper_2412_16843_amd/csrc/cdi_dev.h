@@ -66,7 +66,7 @@ struct Inst {
   int slip_model, mixed;
   int first_tile, ntiles;   // tiles of level 0 in the cell tile list
   int first_wide, nwide;    // tiles of level 0 in the wide tile list
-  double h, inv_h, eps, gamma, sigma, cos_eq;
+  double h, inv_h, eps, inv_eps, gamma, sigma, cos_eq;
   double gamma_factor;      // > 0: gamma of a step = min(gamma, gamma_factor max|u|)
   double rho1, rho2, mu1, mu2, beta1, beta2, uw_bot, uw_top, dt;
   // caller state (FP64)

@@ -91,19 +91,20 @@ __device__ __forceinline__ double gnbc_corner(const Inst& I, int wall, int i, do
                        uslip);
 }
 
+// Stencil views of an LDS region: at(dr, dc) is the value dr rows above and
+// dc columns right of the centre cell.  FlatView: a region of row pitch RX;
+// RingView: rows j-3..j+3 of a ring of row buffers (row offsets per row).
+template <typename T, int RX>
+struct FlatView {
+  const T* c;
+  __device__ __forceinline__ T at(int dr, int dc) const { return c[dr * RX + dc]; }
+};
 template <typename T>
-__device__ __forceinline__ T ddy_cell(const T* q, int stride, int j, int ny, T inv2h) {
-  // q points at the cell; stride = LDS row pitch
-  if (j == 0) return (T(-3) * q[0] + T(4) * q[stride] - q[2 * stride]) * inv2h;
-  if (j == ny - 1) return (T(3) * q[0] - T(4) * q[-stride] + q[-2 * stride]) * inv2h;
-  return (q[stride] - q[-stride]) * inv2h;
-}
-template <typename T>
-__device__ __forceinline__ T d2dy2_cell(const T* q, int stride, int j, int ny, T inv_h2) {
-  if (j == 0) return (T(2) * q[0] - T(5) * q[stride] + T(4) * q[2 * stride] - q[3 * stride]) * inv_h2;
-  if (j == ny - 1) return (T(2) * q[0] - T(5) * q[-stride] + T(4) * q[-2 * stride] - q[-3 * stride]) * inv_h2;
-  return (q[stride] - T(2) * q[0] + q[-stride]) * inv_h2;
-}
+struct RingView {
+  const T* base;
+  int off[7];
+  __device__ __forceinline__ T at(int dr, int dc) const { return base[off[dr + 3] + dc]; }
+};
 
 // ------------------------------------------------------------ phase prep
 // n = G/(|G| + dN), psi, kappa, mu_c (Sec. 2, eqs. CDI, psi, curvature,
@@ -118,77 +119,96 @@ struct PrepLds {
   S psi[(WR * TY + 6) * PRX];
 };
 
-// n = G/(|G| + dN) and mu_c at the cell of LDS index c (row pitch RX) in
-// grid row j, from the FP64 phase field and psi (one-sided rows at the
-// walls, Sec. 4).
+// n = G/(|G| + dN) and mu_c at the centre cell of the views (grid row j) from
+// the FP64 phase field P and psi Q (one-sided rows at the walls, Sec. 4).
+template <typename S, typename VP, typename VQ>
+__device__ __forceinline__ void prep_point_v(const Inst& I, const VP& P, const VQ& Q, int j,
+                                             S& onx, S& ony, S& omu) {
+  const int ny = I.ny;
+  const S inv2h = (S)(0.5 * I.inv_h), inv_h2 = (S)(I.inv_h * I.inv_h);
+  // normal from phi
+  const S gx = ((S)P.at(0, 1) - (S)P.at(0, -1)) * inv2h;
+  S gy;
+  if (j == 0) gy = (S(-3) * (S)P.at(0, 0) + S(4) * (S)P.at(1, 0) - (S)P.at(2, 0)) * inv2h;
+  else if (j == ny - 1) gy = (S(3) * (S)P.at(0, 0) - S(4) * (S)P.at(-1, 0) + (S)P.at(-2, 0)) * inv2h;
+  else gy = ((S)P.at(1, 0) - (S)P.at(-1, 0)) * inv2h;
+  const S mag = sqrt(gx * gx + gy * gy) + (S)kDeltaN;
+  // psi derivatives, curvature, chemical potential
+  const S q0 = Q.at(0, 0), qe = Q.at(0, 1), qw = Q.at(0, -1);
+  const S px = (qe - qw) * inv2h;
+  S py, d2y;
+  if (j == 0) {
+    py = (S(-3) * q0 + S(4) * Q.at(1, 0) - Q.at(2, 0)) * inv2h;
+    d2y = (S(2) * q0 - S(5) * Q.at(1, 0) + S(4) * Q.at(2, 0) - Q.at(3, 0)) * inv_h2;
+  } else if (j == ny - 1) {
+    py = (S(3) * q0 - S(4) * Q.at(-1, 0) + Q.at(-2, 0)) * inv2h;
+    d2y = (S(2) * q0 - S(5) * Q.at(-1, 0) + S(4) * Q.at(-2, 0) - Q.at(-3, 0)) * inv_h2;
+  } else {
+    py = (Q.at(1, 0) - Q.at(-1, 0)) * inv2h;
+    d2y = (Q.at(1, 0) - S(2) * q0 + Q.at(-1, 0)) * inv_h2;
+  }
+  const S lap = (qe - S(2) * q0 + qw) * inv_h2 + d2y;
+  const S ph = (S)P.at(0, 0);
+  const S g = ph * (S(1) - ph);
+  const S grad2 = px * px + py * py;
+  const S rmag = S(1) / mag;
+  onx = gx * rmag;
+  ony = gy * rmag;
+  omu = S(6) * (S)I.sigma * (g * (S(1) - S(2) * ph) * (S(1) - grad2) * (S)I.inv_eps - g * lap);
+}
+
+// prep_point_v on a flat LDS region of row pitch RX, centre cell index c.
 template <typename S, int RX>
 __device__ __forceinline__ void prep_point(const Inst& I, const double* s_phi, const S* s_psi,
                                            int c, int j, S& onx, S& ony, S& omu) {
-  const int ny = I.ny;
-  const S inv2h = (S)(0.5 * I.inv_h), inv_h2 = (S)(I.inv_h * I.inv_h);
-  const S eps = (S)I.eps;
-  // normal from phi
-  const S gx = ((S)s_phi[c + 1] - (S)s_phi[c - 1]) * inv2h;
-  S gy;
-  {
-    if (j == 0) gy = (S(-3) * (S)s_phi[c] + S(4) * (S)s_phi[c + RX] - (S)s_phi[c + 2 * RX]) * inv2h;
-    else if (j == ny - 1) gy = (S(3) * (S)s_phi[c] - S(4) * (S)s_phi[c - RX] + (S)s_phi[c - 2 * RX]) * inv2h;
-    else gy = ((S)s_phi[c + RX] - (S)s_phi[c - RX]) * inv2h;
-  }
-  const S mag = sqrt(gx * gx + gy * gy) + (S)kDeltaN;
-  // psi derivatives, curvature, chemical potential
-  const S* q = s_psi + c;
-  const S px = (q[1] - q[-1]) * inv2h;
-  const S py = ddy_cell<S>(q, RX, j, ny, inv2h);
-  const S lap = (q[1] - S(2) * q[0] + q[-1]) * inv_h2 + d2dy2_cell<S>(q, RX, j, ny, inv_h2);
-  const S ph = (S)s_phi[c];
-  const S g = ph * (S(1) - ph);
-  const S grad2 = px * px + py * py;
-  onx = gx / mag;
-  ony = gy / mag;
-  omu = S(6) * (S)I.sigma * (g * (S(1) - S(2) * ph) * (S(1) - grad2) / eps - g * lap);
+  prep_point_v<S>(I, FlatView<double, RX>{s_phi + c}, FlatView<S, RX>{s_psi + c}, j, onx, ony,
+                  omu);
 }
 
-// Wall quantities of the slip models for the column of a wall-row cell (LDS
-// index c, row pitch RX, grid row j = 0 or ny - 1): phi, psi, d psi/dy,
-// kappa and d phi/dy of the wall row and the next row, linearly
-// extrapolated to the wall per column (Sec. 4), in FP64.
-template <typename S, int RX>
-__device__ __forceinline__ void prep_wall(const Inst& I, const double* s_phi, const S* s_psi,
-                                          int c, int j, double out[5]) {
+// Wall quantities of the slip models for the column of a wall-row cell (the
+// centre of the views, grid row j = 0 or ny - 1): phi, psi, d psi/dy, kappa
+// and d phi/dy of the wall row and the next row, linearly extrapolated to the
+// wall per column (Sec. 4), in FP64.
+template <typename S, typename VP, typename VQ>
+__device__ __forceinline__ void prep_wall_v(const Inst& I, const VP& P, const VQ& Q, int j,
+                                            double out[5]) {
   const int ny = I.ny;
   const int dj = j == 0 ? 1 : -1;          // second cell row from the wall
-  const int c2 = c + dj * RX;
-  const int j2 = j + dj;
   double vals[2][5];
   for (int r = 0; r < 2; ++r) {
-    const int cc = r == 0 ? c : c2, jj = r == 0 ? j : j2;
-    // FP64 wall quantities from the psi tile
-    const S* qs = s_psi + cc;
+    const int o = r == 0 ? 0 : dj, jj = j + o;   // row offset of this cell from the centre
     const double i2h = 0.5 * I.inv_h, ih2 = I.inv_h * I.inv_h;
-    const double p0 = (double)qs[0];
+    const double p0 = (double)Q.at(o, 0);
     double pyd, d2y;
     if (jj == 0) {
-      pyd = (-3.0 * p0 + 4.0 * (double)qs[RX] - (double)qs[2 * RX]) * i2h;
-      d2y = (2.0 * p0 - 5.0 * (double)qs[RX] + 4.0 * (double)qs[2 * RX] - (double)qs[3 * RX]) * ih2;
+      pyd = (-3.0 * p0 + 4.0 * (double)Q.at(o + 1, 0) - (double)Q.at(o + 2, 0)) * i2h;
+      d2y = (2.0 * p0 - 5.0 * (double)Q.at(o + 1, 0) + 4.0 * (double)Q.at(o + 2, 0) -
+             (double)Q.at(o + 3, 0)) * ih2;
     } else if (jj == ny - 1) {
-      pyd = (3.0 * p0 - 4.0 * (double)qs[-RX] + (double)qs[-2 * RX]) * i2h;
-      d2y = (2.0 * p0 - 5.0 * (double)qs[-RX] + 4.0 * (double)qs[-2 * RX] - (double)qs[-3 * RX]) * ih2;
+      pyd = (3.0 * p0 - 4.0 * (double)Q.at(o - 1, 0) + (double)Q.at(o - 2, 0)) * i2h;
+      d2y = (2.0 * p0 - 5.0 * (double)Q.at(o - 1, 0) + 4.0 * (double)Q.at(o - 2, 0) -
+             (double)Q.at(o - 3, 0)) * ih2;
     } else {
-      pyd = ((double)qs[RX] - (double)qs[-RX]) * i2h;
-      d2y = ((double)qs[RX] - 2.0 * p0 + (double)qs[-RX]) * ih2;
+      pyd = ((double)Q.at(o + 1, 0) - (double)Q.at(o - 1, 0)) * i2h;
+      d2y = ((double)Q.at(o + 1, 0) - 2.0 * p0 + (double)Q.at(o - 1, 0)) * ih2;
     }
-    const double pxd = ((double)qs[1] - (double)qs[-1]) * i2h;
-    const double lapd = ((double)qs[1] - 2.0 * p0 + (double)qs[-1]) * ih2 + d2y;
-    const double phd = s_phi[cc];
+    const double pxd = ((double)Q.at(o, 1) - (double)Q.at(o, -1)) * i2h;
+    const double lapd = ((double)Q.at(o, 1) - 2.0 * p0 + (double)Q.at(o, -1)) * ih2 + d2y;
+    const double phd = P.at(o, 0);
     const double kap = (1.0 - 2.0 * phd) * (1.0 - pxd * pxd - pyd * pyd) / I.eps - lapd;
     double phy;
-    if (jj == 0) phy = (-3.0 * phd + 4.0 * s_phi[cc + RX] - s_phi[cc + 2 * RX]) * i2h;
-    else if (jj == ny - 1) phy = (3.0 * phd - 4.0 * s_phi[cc - RX] + s_phi[cc - 2 * RX]) * i2h;
-    else phy = (s_phi[cc + RX] - s_phi[cc - RX]) * i2h;
+    if (jj == 0) phy = (-3.0 * phd + 4.0 * P.at(o + 1, 0) - P.at(o + 2, 0)) * i2h;
+    else if (jj == ny - 1) phy = (3.0 * phd - 4.0 * P.at(o - 1, 0) + P.at(o - 2, 0)) * i2h;
+    else phy = (P.at(o + 1, 0) - P.at(o - 1, 0)) * i2h;
     vals[r][0] = phd; vals[r][1] = p0; vals[r][2] = pyd; vals[r][3] = kap; vals[r][4] = phy;
   }
   for (int qk = 0; qk < 5; ++qk) out[qk] = 0.5 * (3.0 * vals[0][qk] - vals[1][qk]);
+}
+
+template <typename S, int RX>
+__device__ __forceinline__ void prep_wall(const Inst& I, const double* s_phi, const S* s_psi,
+                                          int c, int j, double out[5]) {
+  prep_wall_v<S>(I, FlatView<double, RX>{s_phi + c}, FlatView<S, RX>{s_psi + c}, j, out);
 }
 
 // Cell (ty, tx) of a phase-preparation tile whose LDS region has RY rows.
@@ -653,6 +673,424 @@ __global__ void __launch_bounds__(kNT) k_stage_fused(const Tile* __restrict__ ti
   const Tile t = tiles[blockIdx.x];
   stage_tile<S, true>(t, insts[t.inst], k, src, dst, c_next, b_k, write_wall, L, threadIdx.x, true,
                       s_wall);
+}
+
+// ------------------------------------------------------------ stage strip
+// The stage operator over a strip of TW columns and up to sh rows, advanced
+// NW rows (one chunk) at a time, with the phase preparation fused in.  Each
+// of the NW waves of a block works on whole rows: lane l holds grid column
+// i0 - 3 + l of every quantity (the phase field and psi of columns
+// i0-3..i0+TW+1, n, mu_c, u, v, fluxes and corner stresses of the columns
+// each needs), so that row indices are wave-uniform and every phase is one
+// row per wave.  Rows that a chunk shares with the next (phase field, psi,
+// u, v, n, mu_c, face fluxes and corner stresses) stay in rings of LDS rows:
+// psi, n and mu_c of a cell, its faces and corners are each formed once per
+// strip (apart from the first chunk's halo rows and ~8 % of halo columns).
+// The arithmetic of every face, corner and cell is that of stage_tile.
+namespace sr {
+constexpr int NW = kNT / 64;       // waves of a block = rows of a chunk
+constexpr int TW = 64 - 5;         // owned columns of a strip
+constexpr int RW = 66;             // LDS row pitch: lane l at entry 1 + l, one pad entry each side
+constexpr int SH = 32;             // rows of a strip in the tile lists
+// Rows of each ring, for the chunk of rows jc..jc+NW-1 (the next chunk's
+// phase-field, u and v rows are stored while this chunk's update still runs,
+// without a barrier; fluxes, corners, n and mu_c of the next chunk are formed
+// after its first barrier):
+//   phi      rows jc-3..jc+NW+1 prepared, jc-1..jc+NW-1 read by the update,
+//            next rows jc+NW+2..jc+2NW+1 arriving                -> 2NW+3
+//   psi      shares the phase field's ring rows
+//   u, v     rows jc-1..jc+NW in use, next jc+NW+1..jc+2NW arriving -> 2NW+2
+//   n, mu_c  rows jc-2..jc+NW                                     -> NW+3
+//   x-faces  rows jc-1..jc+NW-1 -> NW+1;  y-faces rows jc-1..jc+NW -> NW+2;
+//   corners  rows jc..jc+NW     -> NW+1
+constexpr int RP = 2 * NW + 3, RU = 2 * NW + 2, RC = NW + 3;
+constexpr int RFX = NW + 1, RFY = NW + 2, RCO = NW + 1;
+}  // namespace sr
+
+template <typename S>
+struct StripLds {
+  double phi[sr::RP * sr::RW];   // phase field and psi share their ring rows
+  S psi[sr::RP * sr::RW];
+  S u[sr::RU * sr::RW], v[sr::RU * sr::RW];
+  S nx[sr::RC * sr::RW], ny[sr::RC * sr::RW], mc[sr::RC * sr::RW];
+  S fx[sr::RFX * sr::RW], mx[sr::RFX * sr::RW];
+  S fy[sr::RFY * sr::RW], my[sr::RFY * sr::RW];
+  S txy[sr::RCO * sr::RW];
+  double wall[5 * sr::RW];   // wall quantities of the wall this chunk touches
+};
+
+// Position of one wave's rows in a ring of R rows: b is the LDS offset of
+// row j = jc + w (this chunk's row of the wave); at<d>() the offset of row
+// j + d, advance() moves to the next chunk.  All wave-uniform (scalar).
+template <int R>
+struct RingPos {
+  int b;
+  template <int d>
+  __device__ __forceinline__ int at() const {
+    static_assert(d > -R && d < R, "ring offset out of range");
+    constexpr int span = R * sr::RW, dd = d * sr::RW;
+    const int x = b + dd;
+    if constexpr (d >= 0) return x >= span ? x - span : x;
+    else return x < 0 ? x + span : x;
+  }
+  __device__ __forceinline__ void advance() {
+    constexpr int span = R * sr::RW;
+    b += sr::NW * sr::RW;
+    if (b >= span) b -= span;
+  }
+};
+
+// Tiles: one per strip (i0 a multiple of TW, j0 a multiple of sh).  Other
+// arguments as k_stage_fused.  Element offsets are 32-bit (global accesses
+// then take a scalar base and a 32-bit vector offset): the host keeps every
+// level-0 array of an instance below 2^31 elements.
+template <typename S>
+__global__ void __launch_bounds__(kNT) k_stage_strip(const Tile* __restrict__ tiles,
+                                                      const Inst* __restrict__ insts, int k,
+                                                      int src, int dst, double c_next, double b_k,
+                                                      int write_wall, int sh) {
+  using sr::NW; using sr::TW; using sr::RW;
+  using sr::RP; using sr::RU; using sr::RC;
+  using sr::RFX; using sr::RFY; using sr::RCO;
+  __shared__ StripLds<S> L;
+  const Tile t = tiles[blockIdx.x];
+  const Inst& I = insts[t.inst];
+  const int nx = I.nx, ny = I.ny;
+  const int i0 = t.i0, js = t.j0;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave = row of a chunk
+  const int l = threadIdx.x & 63;                                   // lane = column i0 - 3 + l
+  const int e = 1 + l;                                              // LDS entry of the lane
+  const int nch = (min(sh, ny - js) + NW - 1) / NW;
+  const double* __restrict__ phs = src == 0 ? I.phi : (src == 1 ? I.phi_a : I.phi_b);
+  const double* __restrict__ us = k <= 0 ? I.u : I.us;
+  const double* __restrict__ vs = k <= 0 ? I.v : I.vs;
+  double* __restrict__ pdst = dst == 0 ? I.phi : (dst == 1 ? I.phi_a : I.phi_b);
+  const int gcol = wrap_any(i0 - 3 + l, nx);   // periodic column of the lane
+  // LDS row offset of grid row j of a ring of n rows whose lowest row is js - low
+  auto ring = [&](int j, int low, unsigned n) { return (int)((unsigned)(j - js + low + (int)n) % n) * RW; };
+  auto rp = [&](int j) { return ring(j, 3, RP); };
+  auto ru = [&](int j) { return ring(j, 1, RU); };
+  auto rc = [&](int j) { return ring(j, 2, RC); };
+  auto rfx = [&](int j) { return ring(j, 1, RFX); };
+  auto rfy = [&](int j) { return ring(j, 1, RFY); };
+  auto rco = [&](int j) { return ring(j, 0, RCO); };
+  auto load_phi = [&](int j) {
+    return (j >= 0 && j < ny) ? phs[(unsigned)(j * nx + gcol)] : 0.0;
+  };
+  auto store_phi = [&](int off, int j, double f) {   // phase field and psi of row j at offset off
+    double ps = 0.0;
+    if (j >= 0 && j < ny) {
+      const double cl = fmin(fmax(f, 0.0), 1.0);
+      ps = I.eps * log((cl + kDeltaPsi) / (1.0 - cl + kDeltaPsi));
+    }
+    L.phi[off + e] = f;
+    L.psi[off + e] = (S)ps;
+  };
+  auto load_u = [&](int j) { return (j >= 0 && j < ny) ? (S)us[(unsigned)(j * nx + gcol)] : S(0); };
+  auto load_v = [&](int j) { return (j >= 0 && j <= ny) ? (S)vs[(unsigned)(j * nx + gcol)] : S(0); };
+  const S gam = (S)I.pcg->gamma_step, eps = (S)I.eps, inv_h = (S)I.inv_h;
+  const S drho = (S)(I.rho1 - I.rho2), rho2 = (S)I.rho2;
+  const S mud = (S)(I.mu1 - I.mu2), mu2 = (S)I.mu2;
+  const int i = i0 - 3 + l;   // grid column of the lane (unwrapped)
+  const bool ocol = l >= 3 && l < 3 + TW && i < nx;   // the lane owns its column
+
+  // one cell's n and mu_c (grid row jr, ring offsets of rows jr-3..jr+3)
+  auto prep_row = [&](int jr, const int (&po)[7], int co) {
+    S a1 = S(0), a2 = S(0), a3 = S(0);
+    if (jr >= 0 && jr < ny) {
+      RingView<double> P{L.phi, {}};
+      RingView<S> Q{L.psi, {}};
+#pragma unroll
+      for (int d = 0; d < 7; ++d) { P.off[d] = po[d] + e; Q.off[d] = po[d] + e; }
+      prep_point_v<S>(I, P, Q, jr, a1, a2, a3);
+    }
+    L.nx[co + e] = a1; L.ny[co + e] = a2; L.mc[co + e] = a3;
+  };
+  // x-face flux of row jr (face i between cells i-1 and i)
+  auto xface = [&](int jr, int op, int oc, int ou, int of) {
+    S F = 0, m = 0;
+    if (jr >= 0 && jr < ny) {
+      const double* ph = L.phi + op + e;
+      const S* nr = L.nx + oc + e;
+      const S pl = (S)ph[-1], pr = (S)ph[0];
+      const S pfc = S(0.5) * (pl + pr);
+      const S nf = S(0.5) * (nr[-1] + nr[0]);
+      const S R = gam * (eps * (pr - pl) * inv_h - pfc * (S(1) - pfc) * nf);
+      const S u = L.u[ou + e];
+      F = u * pfc - R;
+      m = rho2 * u + drho * F;
+    }
+    L.fx[of + e] = F; L.mx[of + e] = m;
+  };
+  // y-face flux of face row f (between cell rows f-1 and f); wall faces carry no flux
+  auto yface = [&](int f, int opb, int opt, int ocb, int oct, int ou, int of) {
+    S F = 0, m = 0;
+    if (f >= 1 && f <= ny - 1) {
+      const S pb = (S)L.phi[opb + e], pt = (S)L.phi[opt + e];
+      const S pfc = S(0.5) * (pb + pt);
+      const S nf = S(0.5) * (L.ny[ocb + e] + L.ny[oct + e]);
+      const S R = gam * (eps * (pt - pb) * inv_h - pfc * (S(1) - pfc) * nf);
+      const S v = L.v[ou + e];
+      F = v * pfc - R;
+      m = rho2 * v + drho * F;
+    }
+    L.fy[of + e] = F; L.my[of + e] = m;
+  };
+  // corner shear stress at (row jcr, column i): interior mu4 (du/dy + dv/dx); walls GNBC
+  auto corner = [&](int jcr, int opb, int opt, int oub, int out, int oco) {
+    S tau = 0;
+    if (jcr >= 1 && jcr <= ny - 1) {
+      const double* pT = L.phi + opt + e;   // cell (jcr, i)
+      const double* pB = L.phi + opb + e;
+      const S mu4 = S(0.25) * ((mud * (S)pB[0] + mu2) + (mud * (S)pB[-1] + mu2) +
+                               (mud * (S)pT[0] + mu2) + (mud * (S)pT[-1] + mu2));
+      const S dudy = (L.u[out + e] - L.u[oub + e]) * inv_h;
+      const S dvdx = (L.v[out + e] - L.v[out + e - 1]) * inv_h;
+      tau = mu4 * (dudy + dvdx);
+    } else if ((jcr == 0 || jcr == ny) && i <= nx) {
+      const int wall = jcr == 0 ? 0 : 1;
+      const int urow = wall == 0 ? 0 : ny - 1;
+      const double ur = (double)L.u[ru(urow) + e];
+      double uY, usl;
+      tau = (S)gnbc_corner_w(I, L.wall, RW, wall, e - 1, e, ur, uY, usl);
+      if (write_wall && ocol) {
+        I.uY[wall * nx + i] = uY;
+        I.uslip[wall * nx + i] = usl;
+      }
+    }
+    L.txy[oco + e] = tau;
+  };
+
+  // Loads run a chunk ahead of their use: the operands of the RK update (own
+  // cell; west and south base densities) of the next chunk, and the phase
+  // field, u and v rows of the chunk after it.
+  struct Pre { double acc[3], phn, phw, phs, u, v; };
+  auto load_pre = [&](int j, Pre& p) {
+    p.acc[0] = p.acc[1] = p.acc[2] = p.phn = p.phw = p.phs = p.u = p.v = 0.0;
+    if (ocol && j < ny && k >= 0) {
+      const unsigned o = (unsigned)(j * nx + i);
+      const double* __restrict__ phn0 = I.phi;
+      if (k > 0) { p.acc[0] = I.acc_phi[o]; p.acc[1] = I.acc_mx[o]; p.acc[2] = I.acc_my[o]; }
+      p.phn = phn0[o];
+      p.phw = phn0[(unsigned)(j * nx + wrap(i - 1, nx))];
+      if (j >= 1) p.phs = phn0[o - nx];
+      p.u = I.u[o];
+      p.v = I.v[o];
+    }
+  };
+  Pre cur, nxt;
+  load_pre(js + w, cur);
+  // first chunk: phase field rows js-3..js+NW+1, u / v rows js-1..js+NW
+  {
+    double f[2];
+    S a[2], b[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int rf = w + q * NW, ru_ = w + q * NW;
+      f[q] = rf < NW + 5 ? load_phi(js - 3 + rf) : 0.0;
+      a[q] = b[q] = S(0);
+      if (ru_ < NW + 2) { a[q] = load_u(js - 1 + ru_); b[q] = load_v(js - 1 + ru_); }
+    }
+    const double f2 = w == 0 ? load_phi(js - 3 + 2 * NW) : 0.0;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int rf = w + q * NW, ru_ = w + q * NW;
+      if (rf < NW + 5) store_phi(rp(js - 3 + rf), js - 3 + rf, f[q]);
+      if (ru_ < NW + 2) { L.u[ru(js - 1 + ru_) + e] = a[q]; L.v[ru(js - 1 + ru_) + e] = b[q]; }
+    }
+    static_assert(NW + 5 <= 3 * NW, "first-chunk rows: at most three per wave");
+    if (w == 0 && 2 * NW < NW + 5) store_phi(rp(js - 3 + 2 * NW), js - 3 + 2 * NW, f2);
+  }
+  double r1phi = 0.0, r2phi = 0.0;   // phase-field row of the next chunk / the one after
+  S r1u = S(0), r1v = S(0), r2u = S(0), r2v = S(0);
+  if (nch > 1) {
+    r1phi = load_phi(js + NW + 2 + w);
+    r1u = load_u(js + NW + 1 + w);
+    r1v = load_v(js + NW + 1 + w);
+  }
+  // ring positions of row js + w (row jc + w of each chunk as the strip advances)
+  RingPos<RP> P{(w + 3) * RW};
+  RingPos<RU> U{(w + 1) * RW};
+  RingPos<RC> C{(w + 2) * RW};
+  RingPos<RFX> FXr{(w + 1) * RW};
+  RingPos<RFY> FYr{(w + 1) * RW};
+  RingPos<RCO> COr{w * RW};
+
+  for (int c = 0; c < nch; ++c) {
+    const int jc = js + c * NW;
+    const int j = jc + w;
+    const bool own = ocol && j < ny;
+    const unsigned o = own ? (unsigned)(j * nx + i) : 0u;
+    __syncthreads();   // this chunk's phase-field, psi, u and v rows are in the rings
+
+    // n and mu_c of the rows new to this chunk (row j + 1 of each wave; the
+    // first chunk also rows jc-2..jc); wall quantities at a wall
+    if (c == 0) {
+      for (int r = w; r < 3; r += NW) {
+        const int jr = jc - 2 + r;
+        int po[7];
+#pragma unroll
+        for (int d = 0; d < 7; ++d) po[d] = rp(jr + d - 3);
+        prep_row(jr, po, rc(jr));
+      }
+    }
+    {
+      const int jr = j + 1;
+      int po[7];
+      po[2] = P.at<0>(); po[3] = P.at<1>(); po[4] = P.at<2>();
+      if (jr == 0 || jr >= ny - 1) {   // one-sided wall rows reach three rows out
+        po[0] = P.at<-2>(); po[1] = P.at<-1>(); po[5] = P.at<3>(); po[6] = P.at<4>();
+      } else {
+        po[0] = po[1] = po[5] = po[6] = 0;
+      }
+      prep_row(jr, po, C.at<1>());
+    }
+    {
+      // the wall whose corner row is new to this chunk (bottom: row 0 of the
+      // first chunk of the first strip; top: row ny)
+      const int cra = c == 0 ? jc : jc + 1;
+      const bool bot = cra == 0, top = cra <= ny && ny <= jc + NW;
+      if (w == NW - 1 && (bot || top)) {
+        const int jw = bot ? 0 : ny - 1;
+        RingView<double> PV{L.phi, {}};
+        RingView<S> QV{L.psi, {}};
+#pragma unroll
+        for (int d = 0; d < 7; ++d) {
+          PV.off[d] = rp(jw + d - 3) + e;
+          QV.off[d] = PV.off[d];
+        }
+        double wq[5];
+        prep_wall_v<S>(I, PV, QV, jw, wq);
+        for (int qk = 0; qk < 5; ++qk) L.wall[qk * RW + e] = wq[qk];
+      }
+    }
+    __syncthreads();
+
+    // loads for the chunks ahead
+    const bool more = c + 1 < nch;
+    const int jn = jc + NW;
+    if (more) load_pre(jn + w, nxt);
+    if (c + 2 < nch) {
+      r2phi = load_phi(jn + NW + 2 + w);
+      r2u = load_u(jn + NW + 1 + w);
+      r2v = load_v(jn + NW + 1 + w);
+    }
+
+    // fluxes and corner stresses new to this chunk: x-faces of row j, y-faces
+    // of face row j + 1, corners of row j + 1 (the first chunk also x-faces of
+    // row jc - 1, y-faces of rows jc - 1 and jc, corners of row jc)
+    if (c == 0 && w < 2) {
+      if (w == 0) xface(jc - 1, rp(jc - 1), rc(jc - 1), ru(jc - 1), rfx(jc - 1));
+      const int f = jc - 1 + w;
+      yface(f, rp(f - 1), rp(f), rc(f - 1), rc(f), ru(f), rfy(f));
+      if (w == 1) corner(jc, rp(jc - 1), rp(jc), ru(jc - 1), ru(jc), rco(jc));
+    }
+    xface(j, P.at<0>(), C.at<0>(), U.at<0>(), FXr.at<0>());
+    yface(j + 1, P.at<0>(), P.at<1>(), C.at<0>(), C.at<1>(), U.at<1>(), FYr.at<1>());
+    corner(j + 1, P.at<0>(), P.at<1>(), U.at<0>(), U.at<1>(), COr.at<1>());
+    __syncthreads();
+
+    if (own) {
+      const double* phr = L.phi + P.at<0>() + e;    // cell (j, i)
+      const double* phb = L.phi + P.at<-1>() + e;   // cell (j-1, i)
+      const S* mcr = L.mc + C.at<0>() + e;
+      const S* mcb = L.mc + C.at<-1>() + e;
+      const S* U0 = L.u + U.at<0>() + e;
+      const S* UN = L.u + U.at<1>() + e;
+      const S* US = L.u + U.at<-1>() + e;
+      const S* V0 = L.v + U.at<0>() + e;
+      const S* VN = L.v + U.at<1>() + e;
+      const S* VS = L.v + U.at<-1>() + e;
+      const S* FX = L.fx + FXr.at<0>() + e;
+      const S* MX = L.mx + FXr.at<0>() + e;
+      const S* MXS = L.mx + FXr.at<-1>() + e;
+      const S* FY = L.fy + FYr.at<0>() + e;
+      const S* FYN = L.fy + FYr.at<1>() + e;
+      const S* MY = L.my + FYr.at<0>() + e;
+      const S* MYN = L.my + FYr.at<1>() + e;
+      const S* MYS = L.my + FYr.at<-1>() + e;
+      const S* TS = L.txy + COr.at<0>() + e;   // corner (j, i)
+      const S* TN = L.txy + COr.at<1>() + e;   // corner (j+1, i)
+      // ---- phase field: L_phi = -div F, face values differenced in FP64
+      const double Lphi = -(((double)FX[1] - (double)FX[0]) + ((double)FYN[0] - (double)FY[0])) *
+                          I.inv_h;
+      // ---- x-momentum at u[j, i]
+      S Lmx;
+      {
+        const S fcE = S(0.5) * (MX[0] + MX[1]) * S(0.5) * (U0[0] + U0[1]);
+        const S fcW = S(0.5) * (MX[-1] + MX[0]) * S(0.5) * (U0[-1] + U0[0]);
+        const S fcN = (j + 1 >= ny) ? S(0) : S(0.5) * (MYN[-1] + MYN[0]) * S(0.5) * (U0[0] + UN[0]);
+        const S fcS = (j == 0) ? S(0) : S(0.5) * (MY[-1] + MY[0]) * S(0.5) * (US[0] + U0[0]);
+        const S muE = mud * (S)phr[0] + mu2, muW = mud * (S)phr[-1] + mu2;
+        const S txxE = S(2) * muE * (U0[1] - U0[0]) * inv_h;
+        const S txxW = S(2) * muW * (U0[0] - U0[-1]) * inv_h;
+        const S tN = TN[0], tS = TS[0];
+        const S st = S(0.5) * (mcr[-1] + mcr[0]) * ((S)phr[0] - (S)phr[-1]) * inv_h;
+        Lmx = -((fcE - fcW) + (fcN - fcS)) * inv_h + (txxE - txxW) * inv_h + (tN - tS) * inv_h + st;
+      }
+      // ---- y-momentum at interior v[j, i]
+      S Lmy = 0;
+      if (j >= 1) {
+        const S gN = S(0.5) * (MY[0] + MYN[0]) * S(0.5) * (V0[0] + VN[0]);
+        const S gS = S(0.5) * (MYS[0] + MY[0]) * S(0.5) * (VS[0] + V0[0]);
+        const S fcE = S(0.5) * (MXS[1] + MX[1]) * S(0.5) * (V0[0] + V0[1]);
+        const S fcW = S(0.5) * (MXS[0] + MX[0]) * S(0.5) * (V0[-1] + V0[0]);
+        const S muN = mud * (S)phr[0] + mu2, muS = mud * (S)phb[0] + mu2;
+        const S tyyN = S(2) * muN * (VN[0] - V0[0]) * inv_h;
+        const S tyyS = S(2) * muS * (V0[0] - VS[0]) * inv_h;
+        const S tE = TS[1], tW = TS[0];
+        const S st = S(0.5) * (mcb[0] + mcr[0]) * ((S)phr[0] - (S)phb[0]) * inv_h;
+        Lmy = -((fcE - fcW) + (gN - gS)) * inv_h + (tyyN - tyyS) * inv_h + (tE - tW) * inv_h + st;
+      }
+      if (k < 0) {   // operator evaluation only: publish L_phi, L_mx, L_my
+        I.acc_phi[o] = Lphi;
+        I.acc_mx[o] = (double)Lmx;
+        I.acc_my[o] = (double)Lmy;
+      } else {
+        // ---- RK4 accumulation and next stage
+        double ap, am, an;
+        if (k == 0) {
+          ap = b_k * Lphi; am = b_k * (double)Lmx; an = b_k * (double)Lmy;
+        } else {
+          ap = cur.acc[0] + b_k * Lphi;
+          am = cur.acc[1] + b_k * (double)Lmx;
+          an = cur.acc[2] + b_k * (double)Lmy;
+        }
+        const double cn = c_next * I.dt;   // RK c_{k+1} dt of this instance
+        const double r1 = I.rho1, r2 = I.rho2;
+        const double rl = (r1 - r2) * cur.phw + r2;
+        const double rcn = (r1 - r2) * cur.phn + r2;
+        const double mx0 = 0.5 * (rl + rcn) * cur.u;
+        if (k < 3) {
+          I.acc_phi[o] = ap; I.acc_mx[o] = am;
+          pdst[o] = cur.phn + cn * Lphi;
+          I.mx[o] = mx0 + cn * (double)Lmx;
+        } else {
+          pdst[o] = cur.phn + I.dt * ap;
+          I.mx[o] = mx0 + I.dt * am;
+        }
+        if (j >= 1) {
+          const double rb = (r1 - r2) * cur.phs + r2;
+          const double my0 = 0.5 * (rb + rcn) * cur.v;
+          if (k < 3) {
+            I.acc_my[o] = an;
+            I.my[o] = my0 + cn * (double)Lmy;
+          } else {
+            I.my[o] = my0 + I.dt * an;
+          }
+        }
+      }
+    }
+    // the next chunk's rows into the rings (slots this chunk's update does not read)
+    if (more) {
+      store_phi(P.at<NW + 2>(), jn + 2 + w, r1phi);
+      L.u[U.at<NW + 1>() + e] = r1u;
+      L.v[U.at<NW + 1>() + e] = r1v;
+    }
+    cur = nxt;
+    r1phi = r2phi; r1u = r2u; r1v = r2v;
+    P.advance(); U.advance(); C.advance(); FXr.advance(); FYr.advance(); COr.advance();
+  }
 }
 
 }  // namespace cdi
