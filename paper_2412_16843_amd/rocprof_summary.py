@@ -7,6 +7,11 @@ Two uses:
       python -m paper_2412_16843_amd.rocprof_summary stats <run>_kernel_stats.csv
       python -m paper_2412_16843_amd.rocprof_summary grid <run>_kernel_trace.csv
 
+  instruction counters per launch of the kernels whose name contains a
+  string (any number of ``--pmc`` runs of the same command):
+      python -m paper_2412_16843_amd.rocprof_summary counters --kernel k_stage \\
+          <pass1>_counter_collection.csv <pass2>_counter_collection.csv ...
+
   HBM traffic per launch (two ``--pmc`` runs of the same command, one with
   FETCH_SIZE, one with WRITE_SIZE; each must also run a plain device copy of
   known size, which bench.py does with ``--copy-calibration``):
@@ -129,6 +134,44 @@ def traffic(fetch_csv: str, write_csv: str, kernel: str, copy_bytes: int, worklo
     return "\n".join(lines)
 
 
+def counters(paths, kernel: str) -> str:
+    """Mean of every counter per launch of each kernel matching `kernel`, and
+    the issue shares they imply.  SQ_WAVE_CYCLES, SQ_ACTIVE_INST_* and
+    SQ_WAIT_* count quad-cycles (4 clocks) summed over waves; GRBM_GUI_ACTIVE
+    counts clocks summed over the 8 XCDs; the MI355X has 1024 SIMDs."""
+    tot = collections.defaultdict(lambda: collections.defaultdict(float))
+    disp = collections.defaultdict(lambda: collections.defaultdict(set))
+    for path in paths:
+        for r in csv.DictReader(open(path)):
+            name = _short(r["Kernel_Name"])
+            if kernel not in name:
+                continue
+            c = r["Counter_Name"]
+            tot[name][c] += float(r["Counter_Value"])
+            disp[name][c].add((path, r["Dispatch_Id"]))
+    lines = []
+    for name in sorted(tot):
+        per = {c: v / max(len(disp[name][c]), 1) for c, v in tot[name].items()}
+        n = max(len(d) for d in disp[name].values())
+        lines += [f"### `{name}` ({n} launches per pass)", "", "| counter | per launch |", "|---|---:|"]
+        lines += [f"| {c} | {v:.4g} |" for c, v in sorted(per.items())]
+        if "GRBM_GUI_ACTIVE" in per:
+            clocks = per["GRBM_GUI_ACTIVE"] / 8.0
+            lines += ["", f"- kernel clocks (GRBM_GUI_ACTIVE / 8 XCDs): {clocks:.4g}"]
+            simd = clocks * 1024
+            for c, what in (("SQ_ACTIVE_INST_VALU", "VALU busy"),
+                            ("SQ_ACTIVE_INST_ANY", "instruction issue (all types, summed over waves)"),
+                            ("SQ_WAIT_ANY", "waves waiting (summed over waves)")):
+                if c in per:
+                    lines.append(f"- {what}: {4 * per[c] / simd:.3f} of SIMD clocks")
+            if "SQ_WAVE_CYCLES" in per:
+                lines.append(f"- resident waves per SIMD: {4 * per['SQ_WAVE_CYCLES'] / simd:.2f}")
+        lines.append("")
+    if not lines:
+        raise SystemExit(f"kernel {kernel} not found")
+    return "\n".join(lines)
+
+
 def read_record(path: str):
     """The traffic record of a summary file, or None."""
     try:
@@ -149,6 +192,9 @@ def main(argv=None):
     gsub = sub.add_parser("grid")
     gsub.add_argument("trace_csv")
     gsub.add_argument("--top", type=int, default=24)
+    cs = sub.add_parser("counters")
+    cs.add_argument("csv", nargs="+")
+    cs.add_argument("--kernel", required=True)
     t = sub.add_parser("traffic")
     t.add_argument("fetch_csv")
     t.add_argument("write_csv")
@@ -160,6 +206,8 @@ def main(argv=None):
         print(stats(a.csv, a.top))
     elif a.cmd == "grid":
         print(by_grid(a.trace_csv, a.top))
+    elif a.cmd == "counters":
+        print(counters(a.csv, a.kernel))
     else:
         print(traffic(a.fetch_csv, a.write_csv, a.kernel, a.copy_bytes, a.workload))
 
