@@ -6,7 +6,9 @@ diffuse-interface phase-field flux with its sharpening term, no-flux walls,
 one-sided wall stencils and linear extrapolation to the wall, the GNBC slip
 (Models 1A..4B), the consistent momentum and energy-based surface-tension
 stencils, RK4 with a projection at every stage, an exact pressure solve and
-the diagnostics.
+the diagnostics; cdi3d carries the same discretisation to three dimensions
+(x and z periodic), with the slip as a wall-plane vector and the in-plane
+curvature kappa_p of the curvature correction.
 
 Only tests/, __graft_entry__.smoke() and bench.py's cpu_baseline leg may
 import it.  It shares no code with the HIP product path; both take their
@@ -18,4 +20,4 @@ except the coupled dynamic contact-angle / steady Couette shape, whose only
 published reference (molecular-dynamics data) is not available -- that
 comparison is "parity unpinned" beyond the invariants it must satisfy.
 """
-from . import cdi, poisson  # noqa: F401
+from . import cdi, cdi3d, poisson  # noqa: F401

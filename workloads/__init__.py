@@ -270,3 +270,72 @@ def random_fields(nx: int, ny: int, seed: int, amp: float = 0.1):
     v[0] = 0.0
     v[-1] = 0.0
     return u, v
+
+
+# ---------------------------------------------------------------------------
+# three-dimensional set-up (x and z periodic, walls at y = 0 and y = Ly)
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class Params3(Params):
+    """Parameters of a 3-D problem: those of Params plus the z extent (nz
+    cells over lz, the same spacing h as x and y) and the z components of
+    the tangential wall speeds."""
+    nz: int = 8
+    lz: float = 1.0
+    w_wall_bot: float = 0.0
+    w_wall_top: float = 0.0
+
+
+def cell_centres3(nx: int, ny: int, nz: int, h: float):
+    """(X, Y, Z) of cell centres, arrays of shape (nz, ny, nx), x fastest."""
+    x = (np.arange(nx) + 0.5) * h
+    y = (np.arange(ny) + 0.5) * h
+    z = (np.arange(nz) + 0.5) * h
+    Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+    return X, Y, Z
+
+
+def equal_volume_radius(r0: float, theta: float) -> float:
+    """Radius of a spherical cap with contact angle theta and the volume of a
+    half ball of radius r0 (the 3-D analogue of the equal-area reading)."""
+    c = math.cos(theta)
+    return r0 * (2.0 / (2.0 - 3.0 * c + c ** 3)) ** (1.0 / 3.0)
+
+
+def cap_phi3(nx: int, ny: int, nz: int, h: float, r0: float, theta: float, eps: float,
+             xc: float, zc: float) -> np.ndarray:
+    """Spherical-cap drop on the bottom wall: tanh profile of a sphere of
+    radius R centred at (xc, -R cos(theta), zc), sampled at cell centres."""
+    X, Y, Z = cell_centres3(nx, ny, nz, h)
+    R = equal_volume_radius(r0, theta)
+    r = np.sqrt((X - xc) ** 2 + (Y + R * math.cos(theta)) ** 2 + (Z - zc) ** 2)
+    return 0.5 * (1.0 + np.tanh((R - r) / (2.0 * eps)))
+
+
+def drop3_case(nx: int, ny: int, nz: int, theta_eq_deg: float = 60.0, ratio: float = 1.0,
+               r0: float = 0.3, steps: int = 100, h: float | None = None,
+               name: str | None = None) -> "Case":
+    """Spherical-cap drop relaxing on the bottom wall of a periodic box
+    (the 3-D counterpart of drop_case)."""
+    h = h if h is not None else 2.0 / nx
+    lx, ly, lz = nx * h, ny * h, nz * h
+    eps = 0.75 * h
+    p = Params3(nx=nx, ny=ny, lx=lx, ly=ly, eps=eps, gamma=1.0, sigma=1.0,
+                theta_eq=math.radians(theta_eq_deg), rho1=ratio, rho2=1.0, mu1=0.1, mu2=0.1,
+                beta1=10.0, beta2=10.0, nz=nz, lz=lz)
+    p = p.replace(dt=dt_from_cfl(p))
+    phi0 = cap_phi3(nx, ny, nz, h, r0, math.radians(90.0), eps, lx / 2.0, lz / 2.0)
+    return Case(name or f"drop3d{nx}x{ny}x{nz}", p, phi0, steps, "drop3", r0)
+
+
+def random_fields3(nx: int, ny: int, nz: int, seed: int, amp: float = 0.1):
+    """Seeded random velocity fields of a 3-D grid (u, w: (nz, ny, nx); v:
+    (nz, ny+1, nx) with v = 0 on both walls) for parity tests."""
+    rng = np.random.default_rng(seed)
+    u = amp * rng.standard_normal((nz, ny, nx))
+    v = amp * rng.standard_normal((nz, ny + 1, nx))
+    w = amp * rng.standard_normal((nz, ny, nx))
+    v[:, 0] = 0.0
+    v[:, -1] = 0.0
+    return u, v, w
