@@ -30,6 +30,8 @@ EXPORTS = ("cdi_workspace_bytes", "cdi_default_dt", "cdi_init", "cdi_init_batch"
            "cdi_tune", "cdi_graph_stats", "cdi_set_coarse_cells", "cdi_get_coarse_cells",
            "cdi_set_mg_smooth", "cdi_get_mg_smooth", "cdi_set_extrapolation",
            "cdi_get_extrapolation", "cdi_eval_rhs_noalloc")
+EXPORTS3 = ("cdi3_workspace_bytes", "cdi3_init", "cdi3_step", "cdi3_eval_rhs", "cdi3_kappa_p",
+            "cdi3_diagnostics", "cdi3_time_stage", "cdi3_destroy")
 
 
 class cdi_params(C.Structure):
@@ -75,6 +77,23 @@ class CDIError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"{STATUS.get(status, status)}: {msg}")
         self.status = status
+
+
+class cdi3_params(C.Structure):
+    _fields_ = [("base", cdi_params), ("nz", C.c_int32), ("pad", C.c_int32), ("lz", C.c_double),
+                ("w_wall_bot", C.c_double), ("w_wall_top", C.c_double)]
+
+
+class cdi3_fields(C.Structure):
+    _fields_ = [("phi", C.c_void_p), ("u", C.c_void_p), ("v", C.c_void_p), ("w", C.c_void_p),
+                ("p", C.c_void_p)]
+
+
+class cdi3_diag(C.Structure):
+    _fields_ = [("t", C.c_double), ("step", C.c_int64), ("mass", C.c_double),
+                ("phi_min", C.c_double), ("phi_max", C.c_double), ("max_div", C.c_double),
+                ("max_slip", C.c_double * 2), ("max_uY", C.c_double * 2), ("ke", C.c_double),
+                ("last_iters", C.c_int32), ("pad", C.c_int32), ("last_relres", C.c_double)]
 
 
 _lib = None
@@ -167,6 +186,22 @@ def lib() -> C.CDLL:
     L.cdi_destroy.restype = None
     L.cdi_last_error.argtypes = []
     L.cdi_last_error.restype = C.c_char_p
+    L.cdi3_workspace_bytes.argtypes = [P(cdi3_params), P(C.c_size_t)]
+    L.cdi3_workspace_bytes.restype = i32
+    L.cdi3_init.argtypes = [P(cdi3_params), P(cdi3_fields), vp, C.c_size_t, vp, P(vp)]
+    L.cdi3_init.restype = i32
+    L.cdi3_step.argtypes = [vp, i32]
+    L.cdi3_step.restype = i32
+    L.cdi3_eval_rhs.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    L.cdi3_eval_rhs.restype = i32
+    L.cdi3_kappa_p.argtypes = [vp, vp]
+    L.cdi3_kappa_p.restype = i32
+    L.cdi3_diagnostics.argtypes = [vp, P(cdi3_diag)]
+    L.cdi3_diagnostics.restype = i32
+    L.cdi3_time_stage.argtypes = [vp, i32, P(f64)]
+    L.cdi3_time_stage.restype = i32
+    L.cdi3_destroy.argtypes = [vp]
+    L.cdi3_destroy.restype = None
     _lib = L
     return L
 
@@ -194,3 +229,10 @@ def make_params(p, precision: str = "fp64", guess: str = "prev", rtol: float = 0
         precision=CDI_MIXED if precision == "mixed" else CDI_FP64, guess=GUESS[guess],
         poisson_rtol=rtol, poisson_maxit=maxit, mg_smooth=mg_smooth,
         gamma_factor=getattr(p, "gamma_factor", 0.0))
+
+
+def make_params3(p, guess: str = "prev", rtol: float = 0.0, maxit: int = 0) -> cdi3_params:
+    """Marshal a 3-D parameter object (attributes as in workloads.Params3)."""
+    return cdi3_params(base=make_params(p, guess=guess, rtol=rtol, maxit=maxit), nz=p.nz, pad=0,
+                       lz=p.lz, w_wall_bot=getattr(p, "w_wall_bot", 0.0),
+                       w_wall_top=getattr(p, "w_wall_top", 0.0))

@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcdi.so")
-SOURCES = ["cdi_api.hip", "cdi_net.hip"]
+SOURCES = ["cdi_api.hip", "cdi_net.hip", "cdi3_api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # -packed-fp32-ops: no packed FP32 instructions in any generated code.

@@ -16,16 +16,17 @@
 #include <vector>
 
 #include "../../include/cdi.h"
+#include "host_util.h"
 #include "persistent_kernels.h"
 #include "net_internal.h"
 
 using namespace cdi;
 
 namespace {
-
 thread_local std::string g_err;
+}  // namespace
 
-cdi_status fail(cdi_status s, const char* fmt, ...) {
+cdi_status cdi_host::fail(cdi_status s, const char* fmt, ...) {
   char buf[512];
   va_list ap;
   va_start(ap, fmt);
@@ -35,12 +36,9 @@ cdi_status fail(cdi_status s, const char* fmt, ...) {
   return s;
 }
 
-#define HIPCHK(x)                                                                 \
-  do {                                                                            \
-    hipError_t e_ = (x);                                                          \
-    if (e_ != hipSuccess)                                                         \
-      return fail(CDI_ERR_DEVICE, "%s failed: %s", #x, hipGetErrorString(e_));    \
-  } while (0)
+namespace {
+
+using cdi_host::fail;
 
 constexpr double RK_C[4] = {0.0, 0.5, 0.5, 1.0};
 constexpr double RK_B[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};

@@ -12,6 +12,7 @@ import workloads as W
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "cdi.h")
+HEADER3 = os.path.join(ROOT, "include", "cdi3.h")
 
 
 def _lib():
@@ -30,6 +31,12 @@ def test_header_declarations_are_exported():
     for name in sorted(decl):
         assert hasattr(lib, name), name
     assert set(L.EXPORTS) == decl
+    text3 = re.sub(r"/\*.*?\*/", "", open(HEADER3).read(), flags=re.S)
+    decl3 = set(re.findall(r"\b(cdi3_[a-z_]+)\s*\(", text3))
+    assert {"cdi3_init", "cdi3_step", "cdi3_eval_rhs", "cdi3_kappa_p"} <= decl3
+    for name in sorted(decl3):
+        assert hasattr(lib, name), name
+    assert set(L.EXPORTS3) == decl3
 
 
 def test_struct_layouts_match_header():
@@ -52,6 +59,43 @@ def test_struct_layouts_match_header():
             for tok in " ".join(parts[1:]).split(","):
                 names.append(re.sub(r"\[.*\]", "", tok).strip())
         assert names == [f[0] for f in py._fields_], (cname, names)
+
+
+def test_3d_struct_layouts_match_header():
+    L = _lib()
+    text = open(HEADER3).read()
+    structs = {m.group(2): m.group(1)
+               for m in re.finditer(r"typedef struct \{([^}]*)\}\s*(\w+);", text)}
+    for cname, py in (("cdi3_params", L.cdi3_params), ("cdi3_fields", L.cdi3_fields),
+                      ("cdi3_diag", L.cdi3_diag)):
+        body = re.sub(r"/\*.*?\*/", "", structs[cname], flags=re.S)
+        names = []
+        for stmt in body.split(";"):
+            stmt = stmt.strip()
+            if stmt:
+                parts = stmt.replace("*", " ").split()
+                names += [re.sub(r"\[.*\]", "", t).strip() for t in " ".join(parts[1:]).split(",")]
+        assert names == [f[0] for f in py._fields_], (cname, names)
+
+
+@pytest.mark.parametrize("kw,status", [(dict(nz=7), -2), (dict(nz=6), -2), (dict(lz=0.9), -2),
+                                       (dict(precision="mixed"), -1), (dict(slip_model="5Z"), -1)])
+def test_3d_invalid_parameters_rejected_on_the_host(kw, status):
+    L = _lib()
+    case = W.drop3_case(16, 8, 8)
+    p = case.params
+    prec = kw.pop("precision", "fp64")
+    if "slip_model" in kw:
+        cp = L.make_params3(p)
+        cp.base.slip_model = 17
+    else:
+        p = p.replace(**kw)
+        cp = L.make_params3(p)
+        cp.base.precision = L.CDI_MIXED if prec == "mixed" else L.CDI_FP64
+    n = C.c_size_t(0)
+    assert L.lib().cdi3_workspace_bytes(C.byref(cp), C.byref(n)) == status
+    ok = L.make_params3(case.params)
+    assert L.lib().cdi3_workspace_bytes(C.byref(ok), C.byref(n)) == 0 and n.value > 0
 
 
 def _params(**kw):
