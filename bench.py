@@ -253,6 +253,46 @@ def secondary_rate(CDISolver, name: str, precision: str, steps: int, warmup: int
     return out
 
 
+# ------------------------------------------------------- three dimensions
+# Algorithmic bytes per cell of one 3-D stage-operator evaluation in its
+# unfused kernel sequence (FP64): psi (phi in, psi out), phase preparation
+# (phi, psi in; n, mu_c out), fluxes (phi, n, u, v, w in; three face fluxes
+# and three mass fluxes out), edge stresses (phi, u, v, w in; three edge
+# stresses out), momentum and RK4 (fluxes, mass fluxes, u, v, w, phi, mu_c,
+# edge stresses, four accumulators, base phi, u, v, w in; four
+# accumulators, next phi and three momenta out).  The per-column wall
+# quantities are O(nx nz) and left out.
+ALGO_BYTES_3D_STAGE = 8 * ((1 + 1) + (2 + 4) + (5 + 6) + (4 + 3) + (20 + 8))
+
+
+def three_d_case(CDISolver3, nx: int = 256, steps: int = 4):
+    """3-D spherical-cap drop relaxing on the bottom wall of an nx x nx/2 x
+    nx/2 periodic box (FP64, Model 4A with the in-plane curvature kappa_p):
+    whole-step throughput, CG iterations, and the stage operator's
+    algorithmic bandwidth."""
+    import torch
+    case = W.drop3_case(nx, nx // 2, nx // 2, theta_eq_deg=60.0, ratio=10.0, r0=0.3)
+    s = CDISolver3(case.params, case.phi0, rtol=1e-10)
+    s.step(2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    d = s.diagnostics()
+    ms = s.time_stage(10)
+    cells = nx * (nx // 2) * (nx // 2)
+    gbs = ALGO_BYTES_3D_STAGE * cells / (ms * 1e-3) / 1e9
+    s.close()
+    return {"workload": f"drop3d{nx}x{nx // 2}x{nx // 2}_r10", "cells": cells,
+            "value": round(cells * steps / dt / 1e6, 3), "unit": "Mcell-steps/s",
+            "steps": steps, "ms_per_step": round(dt / steps * 1e3, 3),
+            "last_pcg_iters": d["last_iters"], "mass_drift": abs(d["mass"] - case.phi0.sum() * case.params.h ** 3),
+            "stage": {"ms": round(ms, 4), "algo_bytes_per_cell": ALGO_BYTES_3D_STAGE,
+                      "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                      "frac": round(gbs / HBM_PEAK_GBS, 4)}}
+
+
 # ----------------------------------------------------------- CPU baseline
 def _oracle_instance_step(args):
     """One oracle step of ensemble instance k from its initial state (CPU
@@ -407,6 +447,8 @@ def main():
                     help="skip the per-kernel HBM fractions on the 2048x1024 and 8192x4096 grids")
     ap.add_argument("--no-secondary", action="store_true",
                     help="skip the mixed-precision ensemble and the Couette 256x64 lines")
+    ap.add_argument("--no-3d", action="store_true",
+                    help="skip the 3-D drop (in-plane curvature) throughput record")
     ap.add_argument("--no-poisson", action="store_true",
                     help="skip the learned-vs-plain pressure time-to-solution at 2048x1024")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -536,6 +578,11 @@ def main():
         # 8192x4096: ~8 GB, DRAM bound
         log("HBM cases: 2048x1024 and 8192x4096 drops")
         out["roofline_hbm_case"] = [hbm_case(CDISolver, 2048), hbm_case(CDISolver, 8192, steps=5)]
+        torch.cuda.empty_cache()
+    if not args.no_3d:
+        from paper_2412_16843_amd.solver3 import CDISolver3
+        log("3-D drop 256x128x128")
+        out["three_d"] = three_d_case(CDISolver3)
         torch.cuda.empty_cache()
     if not args.no_poisson:
         log("learned vs plain pressure guess at 2048x1024")

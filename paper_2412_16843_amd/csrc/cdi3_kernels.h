@@ -873,35 +873,45 @@ __global__ void __launch_bounds__(kNT3) k3_mg_prolong(const Ctx3* __restrict__ C
 
 // The coarsest level in one block (at most kCoarseMax3 cells, one per
 // thread): 2 kCoarseSweeps3 + 1 red-black half-sweeps from zero, red first
-// and last (a palindromic sequence keeps the preconditioner symmetric).
+// and last (a palindromic sequence keeps the preconditioner symmetric).  Each
+// thread keeps its cell's six face coefficients, neighbour indices and
+// right-hand side in registers; the correction lives in LDS.
 __global__ void __launch_bounds__(kCoarseMax3) k3_mg_coarse(const Ctx3* __restrict__ C, int l) {
+  __shared__ double sx[kCoarseMax3];
   const Lev3& L = C->lev[l];
-  const int n = L.nx * L.ny * L.nz;
+  const int nx = L.nx, ny = L.ny, nz = L.nz;
+  const int n = nx * ny * nz;
   const int t = threadIdx.x;
-  int k = 0, j = 0, i = 0;
   const bool in = t < n;
-  double D = 1.0, rr = 0.0;
+  double a[6] = {0, 0, 0, 0, 0, 0}, D = 1.0, rr = 0.0;
+  int nb[6] = {0, 0, 0, 0, 0, 0};
   int color = 0;
   if (in) {
-    i = t % L.nx;
-    j = (t / L.nx) % L.ny;
-    k = t / (L.nx * L.ny);
+    const int i = t % nx, j = (t / nx) % ny, k = t / (nx * ny);
     color = (i + j + k) & 1;
-    double s;
-    L.x[t] = 0.0;
-    (void)applyK3(L, L.x, k, j, i, D, s);
+    const unsigned e = iv3(nx, ny, k, j, i);
+    nb[0] = (int)ic3(nx, ny, k, j, wrap3(i - 1, nx));
+    nb[1] = (int)ic3(nx, ny, k, j, wrap3(i + 1, nx));
+    nb[2] = (int)ic3(nx, ny, wrap3(k - 1, nz), j, i);
+    nb[3] = (int)ic3(nx, ny, wrap3(k + 1, nz), j, i);
+    nb[4] = j >= 1 ? t - nx : t;          // wall faces carry a zero coefficient
+    nb[5] = j + 1 < ny ? t + nx : t;
+    a[0] = L.ax[t]; a[1] = L.ax[nb[1]]; a[2] = L.az[t]; a[3] = L.az[nb[3]];
+    a[4] = L.ay[e]; a[5] = L.ay[e + nx];
+    D = a[0] + a[1] + a[2] + a[3] + a[4] + a[5];
     rr = L.r[t];
   }
+  sx[t] = 0.0;
   __syncthreads();
   for (int it = 0; it < 2 * kCoarseSweeps3 + 1; ++it) {
-    const int cur = it & 1;
-    if (in && color == cur) {
-      double dg, s;
-      (void)applyK3(L, L.x, k, j, i, dg, s);
-      L.x[t] = D > 0.0 ? (rr + s) / D : 0.0;
+    if (in && color == (it & 1)) {
+      const double s = a[0] * sx[nb[0]] + a[1] * sx[nb[1]] + a[2] * sx[nb[2]] + a[3] * sx[nb[3]] +
+                       a[4] * sx[nb[4]] + a[5] * sx[nb[5]];
+      sx[t] = D > 0.0 ? (rr + s) / D : 0.0;
     }
     __syncthreads();
   }
+  if (in) L.x[t] = sx[t];
 }
 
 // ------------------------------------------------------------ diagnostics
