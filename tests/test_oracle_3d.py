@@ -274,3 +274,42 @@ def test_slip_vector_converges_to_the_continuum_formula(model):
         errs.append(err)
     assert errs[-1] < 2e-3, errs
     assert errs[0] / errs[1] > 3.0 and errs[1] / errs[2] > 3.0, errs
+
+
+def _prescribed_cap(n, theta_deg=60.0, R=0.5):
+    """The paper's prescribed equilibrium field (Sec. 3.1) in three
+    dimensions: the tanh profile of a sphere of radius R whose cap meets the
+    bottom wall at theta_eq (eps = h)."""
+    h = 2.0 / n
+    nx, ny, nz = n, n // 2, n
+    th = math.radians(theta_deg)
+    p = W.Params3(nx=nx, ny=ny, lx=nx * h, ly=ny * h, eps=h, gamma=1, sigma=1, theta_eq=th,
+                  rho1=1, rho2=1, mu1=0.1, mu2=0.1, beta1=10, beta2=10, nz=nz, lz=nz * h)
+    X, Y, Z = W.cell_centres3(nx, ny, nz, h)
+    r = np.sqrt((X - nx * h / 2) ** 2 + (Y + R * math.cos(th)) ** 2 + (Z - nz * h / 2) ** 2)
+    return p, 0.5 * (1.0 + np.tanh((R - r) / (2.0 * h)))
+
+
+def _max_slip(phi, p, model, fields):
+    s = cdi3d.slip_velocity_Y(phi, p.replace(slip_model=model), "bot", fields=fields)
+    return max(np.abs(s["uYx"]).max(), np.abs(s["uYz"]).max())
+
+
+def test_curvature_correction_needs_the_inplane_curvature():
+    """Sec. 3.1.2 derives the correction 1 + kappa_p psi from the in-plane
+    section of the contact line.  On the prescribed 3-D cap at theta_eq the
+    spurious slip of Model 4A must therefore fall under refinement with
+    kappa_p, but not with the full (two principal curvatures) kappa in its
+    place, nor for Model 2A without the correction."""
+    res = {}
+    for n in (24, 48):
+        p, phi = _prescribed_cap(n)
+        f = cdi3d.phase_fields(phi, p)
+        full = dict(f)
+        full["kappa_p"] = f["kappa"]
+        res[n] = (_max_slip(phi, p, "4A", f), _max_slip(phi, p, "4A", full),
+                  _max_slip(phi, p, "2A", f))
+    (a1, b1, c1), (a2, b2, c2) = res[24], res[48]
+    assert a1 / a2 > 1.6, res            # converges with kappa_p
+    assert b1 / b2 < 1.25 and c1 / c2 < 1.4, res   # does not with kappa or without the correction
+    assert a2 < 0.3 * b2 and a2 < 0.3 * c2, res
