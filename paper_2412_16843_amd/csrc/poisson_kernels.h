@@ -635,6 +635,20 @@ __device__ __forceinline__ S ldS(const void* p, size_t o) { return ((const S*)p)
 // [m, RY - m) x [m, RX - m), 0 on rows outside the grid.  A cell of one colour
 // reads only cells of the other, so each thread issues the LDS reads of all
 // its cells before the first of its writes.
+// Reciprocal of a smoother's diagonal: the hardware estimate refined by
+// Newton steps (within an ulp or two of the quotient; the smoother is a
+// preconditioner, so its rounding changes only the CG path, never the
+// converged solution) instead of the longer correctly rounded division.
+__device__ __forceinline__ double mg_rcp(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  r = fma(fma(-d, r, 1.0), r, r);
+  return fma(fma(-d, r, 1.0), r, r);
+}
+__device__ __forceinline__ float mg_rcp(float d) {
+  const float r = __builtin_amdgcn_rcpf(d);
+  return fmaf(fmaf(-d, r, 1.0f), r, r);
+}
+
 template <typename S, int RY, int RX, typename ValidF>
 __device__ __forceinline__ void lds_half_sweep(S* s_z, const S* s_r, const S* s_ax, const S* s_ay,
                                                int m, int color, const ValidF& valid) {
@@ -655,7 +669,7 @@ __device__ __forceinline__ void lds_half_sweep(S* s_z, const S* s_r, const S* s_
       const S aw = s_ax[rj * (RX + 1) + ri], ae = s_ax[rj * (RX + 1) + ri + 1];
       const S as = s_ay[rj * RX + ri], an = s_ay[(rj + 1) * RX + ri];
       const S nb = aw * s_z[k - 1] + ae * s_z[k + 1] + as * s_z[k - RX] + an * s_z[k + RX];
-      val[e] = (s_r[k] + nb) / (aw + ae + as + an);
+      val[e] = (s_r[k] + nb) * mg_rcp(aw + ae + as + an);
     }
   }
 #pragma unroll
@@ -804,7 +818,7 @@ __global__ void __launch_bounds__(kNT) k_mg_down(const Tile* __restrict__ tiles,
   for (int e = 0; e < (RY * HX + kNT - 1) / kNT; ++e) {
     const int h = threadIdx.x + e * kNT;
     const int rj = h / HX, ri = 2 * (h - rj * HX) + (rj & 1);
-    if (h < RY * HX) s_z[rj * RX + ri] = valid(rj) ? s_r[rj * RX + ri] / diag(rj, ri) : S(0);
+    if (h < RY * HX) s_z[rj * RX + ri] = valid(rj) ? s_r[rj * RX + ri] * mg_rcp(diag(rj, ri)) : S(0);
   }
   __syncthreads();
   // then Gauss-Seidel half-sweeps black, red, black, ... (half-sweep sw on
@@ -1204,12 +1218,12 @@ __device__ __forceinline__ void mg_cycle(const Inst& I, const ViewF& V, int lo, 
       const int c = j * nx + i;
       const int ie = wrap(i + 1, nx), iw = wrap(i - 1, nx);
       const S aw = ax[c], ae = ax[j * nx + ie], as = ay[c], an = ay[c + nx];
-      const S D = aw + ae + as + an;
-      if (from_zero) { z[c] = r[c] / D; continue; }
+      const S rD = mg_rcp(aw + ae + as + an);
+      if (from_zero) { z[c] = r[c] * rD; continue; }
       S nb = aw * z[j * nx + iw] + ae * z[j * nx + ie];
       if (j >= 1) nb += as * z[c - nx];
       if (j + 1 < ny) nb += an * z[c + nx];
-      z[c] = (r[c] + nb) / D;
+      z[c] = (r[c] + nb) * rD;
     }
   };
   // ---- down

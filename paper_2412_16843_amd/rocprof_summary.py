@@ -37,13 +37,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 
 
 def source_hash() -> str:
-    """sha256 over the solver's device code: every solver kernel lives in the
-    csrc/*.h headers (the .hip files hold host code only); the network's
-    headers (net_*.h) are left out, their kernels are not in these records."""
+    """sha256 over the two-dimensional solver's device code: its kernels live
+    in the csrc/*.h headers (the .hip files hold host code only); the
+    network's (net_*.h) and the three-dimensional path's (cdi3_*.h) headers
+    are left out, their kernels are not in these records."""
     h = hashlib.sha256()
     csrc = os.path.join(HERE, "csrc")
     for name in sorted(os.listdir(csrc)):
-        if name.endswith(".h") and not name.startswith("net_"):
+        if name.endswith(".h") and not name.startswith(("net_", "cdi3_")) and name != "host_util.h":
             with open(os.path.join(csrc, name), "rb") as f:
                 h.update(name.encode())
                 h.update(f.read())
