@@ -346,6 +346,15 @@ cdi_status cdi_graph_stats(cdi_ctx* ctx, int64_t* replays, int64_t* redone, int3
 cdi_status cdi_set_tile_rows(cdi_ctx* ctx, int32_t rows);
 cdi_status cdi_get_tile_rows(cdi_ctx* ctx, int32_t* rows);
 
+/* Rows of the strips of the FP64 stage kernel (59 columns each, advanced
+ * four rows at a time): 16, 32 or 64.  Taller strips recompute fewer halo
+ * rows; shorter ones give the GPU more workgroups.  cdi_init picks the
+ * tallest that gives every compute unit several strips (about 2300 per
+ * batch).  Results agree across strip heights to rounding.  Other values
+ * return CDI_ERR_ARG. */
+cdi_status cdi_set_strip_rows(cdi_ctx* ctx, int32_t rows);
+cdi_status cdi_get_strip_rows(cdi_ctx* ctx, int32_t* rows);
+
 /* Start of the one-block coarse kernel of the V-cycle: it runs every level
  * with at most `cells` cells (levels up to 1024 cells in its LDS; a start
  * level just above those, at most 4096 cells, with its correction and

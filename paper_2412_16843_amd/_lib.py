@@ -29,7 +29,8 @@ EXPORTS = ("cdi_workspace_bytes", "cdi_default_dt", "cdi_init", "cdi_init_batch"
            "cdi_get_launch", "cdi_set_tile_rows", "cdi_get_tile_rows", "cdi_tune_bytes",
            "cdi_tune", "cdi_graph_stats", "cdi_set_coarse_cells", "cdi_get_coarse_cells",
            "cdi_set_mg_smooth", "cdi_get_mg_smooth", "cdi_set_extrapolation",
-           "cdi_get_extrapolation", "cdi_eval_rhs_noalloc")
+           "cdi_get_extrapolation", "cdi_eval_rhs_noalloc", "cdi_set_strip_rows",
+           "cdi_get_strip_rows")
 EXPORTS3 = ("cdi3_workspace_bytes", "cdi3_init", "cdi3_step", "cdi3_eval_rhs", "cdi3_kappa_p",
             "cdi3_diagnostics", "cdi3_time_stage", "cdi3_destroy")
 
@@ -160,6 +161,10 @@ def lib() -> C.CDLL:
     L.cdi_set_launch.restype = i32
     L.cdi_get_launch.argtypes = [vp, P(i32)]
     L.cdi_get_launch.restype = i32
+    L.cdi_set_strip_rows.argtypes = [vp, i32]
+    L.cdi_set_strip_rows.restype = i32
+    L.cdi_get_strip_rows.argtypes = [vp, P(i32)]
+    L.cdi_get_strip_rows.restype = i32
     L.cdi_set_tile_rows.argtypes = [vp, i32]
     L.cdi_set_tile_rows.restype = i32
     L.cdi_get_tile_rows.argtypes = [vp, P(i32)]

@@ -278,6 +278,18 @@ int strip_rows(const std::vector<Resolved>& Rs) {
   return kStripRows[2];
 }
 
+// Strips of the FP64 stage kernel: TW columns x `rows` rows.
+void build_strips(Batch& B, int rows) {
+  B.strip.clear();
+  B.strip_rows = rows;
+  for (int k = 0; k < B.n; ++k) {
+    const Resolved& R = B.R[k];
+    int local = 0;
+    for (int j0 = 0; j0 < R.p.ny; j0 += rows)
+      for (int i0 = 0; i0 < R.p.nx; i0 += sr::TW) B.strip.push_back(Tile{k, i0, j0, 0, local++, {0, 0, 0}});
+  }
+}
+
 void build_tiles(Batch& B, int wide_rows) {
   B.cell.clear();
   B.max_lc = 0;
@@ -295,14 +307,7 @@ void build_tiles(Batch& B, int wide_rows) {
       for (int i0 = 0; i0 < R.p.nx; i0 += TX) B.cell.push_back(Tile{k, i0, j0, 0, local++, {0, 0, 0}});
     I.ntiles = local;
   }
-  B.strip.clear();
-  B.strip_rows = strip_rows(B.R);
-  for (int k = 0; k < B.n; ++k) {
-    const Resolved& R = B.R[k];
-    int local = 0;
-    for (int j0 = 0; j0 < R.p.ny; j0 += B.strip_rows)
-      for (int i0 = 0; i0 < R.p.nx; i0 += sr::TW) B.strip.push_back(Tile{k, i0, j0, 0, local++, {0, 0, 0}});
-  }
+  build_strips(B, strip_rows(B.R));
   build_mg(B);
   build_wide(B, wide_rows);
 }
@@ -1292,6 +1297,20 @@ static cdi_status apply_shape(cdi_ctx* c, int rows, long coarse_cells, int nu) {
   return upload_shape(c);
 }
 
+// Rows of the stage kernel's strips (16, 32 or 64): rebuild and upload the
+// strip list (its slot holds the 16-row count, the largest).
+static cdi_status apply_strip_rows(cdi_ctx* c, int rows) {
+  if (rows == c->B.strip_rows) return CDI_OK;
+  graph_drop(c);
+  HIPCHK(hipStreamSynchronize(c->stream));
+  build_strips(c->B, rows);
+  const std::vector<Tile> sv = xcd_order(c->B.strip);
+  HIPCHK(hipMemcpyAsync(c->d_strip, sv.data(), sizeof(Tile) * sv.size(), hipMemcpyHostToDevice,
+                        c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return CDI_OK;
+}
+
 static cdi_status apply_wide_rows(cdi_ctx* c, int rows) {
   return apply_shape(c, rows, c->coarse_cells, c->nu);
 }
@@ -1333,6 +1352,20 @@ cdi_status cdi_set_coarse_cells(cdi_ctx* c, int32_t cells) {
 cdi_status cdi_get_coarse_cells(cdi_ctx* c, int32_t* cells) {
   if (!c || !cells) return fail(CDI_ERR_ARG, "NULL argument");
   *cells = (int32_t)c->coarse_cells;
+  return CDI_OK;
+}
+
+cdi_status cdi_set_strip_rows(cdi_ctx* c, int32_t rows) {
+  if (!c) return fail(CDI_ERR_ARG, "ctx is NULL");
+  if (rows != kStripRows[0] && rows != kStripRows[1] && rows != kStripRows[2])
+    return fail(CDI_ERR_ARG, "strip rows must be %d, %d or %d", kStripRows[2], kStripRows[1],
+                kStripRows[0]);
+  return apply_strip_rows(c, rows);
+}
+
+cdi_status cdi_get_strip_rows(cdi_ctx* c, int32_t* rows) {
+  if (!c || !rows) return fail(CDI_ERR_ARG, "NULL argument");
+  *rows = c->B.strip_rows;
   return CDI_OK;
 }
 

@@ -131,6 +131,14 @@ class CDISolver:
         L.check(self.lib.cdi_graph_stats(self.ctx, C.byref(r), C.byref(m), C.byref(b)))
         return dict(replays=r.value, redone=m.value, budget=b.value)
 
+    def set_strip_rows(self, rows: int) -> None:
+        L.check(self.lib.cdi_set_strip_rows(self.ctx, rows))
+
+    def get_strip_rows(self) -> int:
+        r = C.c_int32(0)
+        L.check(self.lib.cdi_get_strip_rows(self.ctx, C.byref(r)))
+        return r.value
+
     def set_tile_rows(self, rows: int) -> None:
         """Rows per thread of the wide-tile CG kernels (1 or 4)."""
         L.check(self.lib.cdi_set_tile_rows(self.ctx, int(rows)))

@@ -157,3 +157,41 @@ def test_slip_mesh_study_matches_oracle_at_every_resolution():
             worst = max(worst, err)
             assert err < 1e-12, (model, nx, err)
     print("slip mesh study, worst GPU vs oracle:", worst)
+
+
+@pytest.mark.parametrize("rows", [16, 32, 64])
+def test_every_strip_height_matches_oracle(rows):
+    """The stage kernel's strip forms (16, 32, 64 rows; a grid taller than
+    one strip with a ragged last strip and a ragged last column block) each
+    equal the oracle's stage operator, and a short run with that form equals
+    the oracle's run."""
+    case = W.drop_case(132, 68, 60.0, 10.0, lx=132 / 68, ly=1.0)
+    p = case.params.replace(slip_model="3B")
+    phi, u, v = _perturbed(case, 5)
+    s = _solver(p, phi, u0=u, v0=v)
+    s.set_strip_rows(rows)
+    assert s.get_strip_rows() == rows
+    lphi, lmx, lmy, uy, _ = [t.cpu().numpy() for t in s.eval_rhs()]
+    s.close()
+    Lphi, Lmx, Lmy, walls = cdi.stage_rhs(phi, u, v, p)
+    uy_ref = np.stack([walls["bot"]["uY"], walls["top"]["uY"]])
+    errs = dict(phi=relerr(lphi, Lphi), mx=relerr(lmx, Lmx), my=relerr(lmy, Lmy),
+                uY=relerr(uy, uy_ref))
+    assert max(errs.values()) < 1e-12, errs
+    s = _solver(case.params, case.phi0, rtol=1e-13, maxit=400)
+    s.set_strip_rows(rows)
+    s.step(3)
+    g = s.state()
+    s.close()
+    o = cdi.run(case.phi0, case.params, 3)
+    for k, ref in (("phi", o.phi), ("u", o.u), ("v", o.v)):
+        assert relerr(g[k], ref) < 1e-10, (rows, k, relerr(g[k], ref))
+
+
+def test_strip_height_rejects_other_values():
+    case = W.drop_case(64, 32, 60.0)
+    s = _solver(case.params, case.phi0)
+    from paper_2412_16843_amd import _lib as L
+    with pytest.raises(L.CDIError):
+        s.set_strip_rows(48)
+    s.close()
