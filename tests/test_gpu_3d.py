@@ -134,3 +134,35 @@ def test_z_invariant_step_equals_two_dimensional_library_step():
         ok, err = _close(b[name], np.repeat(a[name][None], nz, axis=0), 1e-9)
         assert ok, (name, err)
     assert np.abs(b["w"]).max() <= 1e-12
+
+
+def test_velocity_dependent_gamma_and_zero_guess_match_oracle():
+    """gamma = min(gamma, 2.5 max |u|) per step (the paper's rule, Sec. 5)
+    and solves started from zero instead of the previous pressure."""
+    p, phi, u, v, w = _case(20, 10, 12, model="3A", ratio=4.0, seed=21)
+    p = p.replace(gamma_factor=2.5)
+    u, v, w, _ = cdi3d.project(u, v, w, phi, p.dt, p)
+    s = _solver(p, phi, u, v, w, rtol=1e-13, guess="zero")
+    s.step(2)
+    g = s.state()
+    s.close()
+    st = cdi3d.State3(phi, u, v, w, np.zeros_like(phi))
+    for _ in range(2):
+        st = cdi3d.step(st, p)
+    for name in ("phi", "u", "v", "w"):
+        ok, err = _close(g[name], getattr(st, name), 1e-9)
+        assert ok, (name, err)
+
+
+def test_nonfinite_state_is_reported():
+    """A NaN in the phase field makes the step return CDI_ERR_NONFINITE (the
+    pressure solve sees a non-finite residual) instead of running on."""
+    from paper_2412_16843_amd import _lib as L
+    p, phi, u, v, w = _case(20, 10, 12)
+    phi = phi.copy()
+    phi[3, 4, 5] = np.nan
+    s = _solver(p, phi)
+    with pytest.raises(L.CDIError) as e:
+        s.step(1)
+    s.close()
+    assert "NONFINITE" in str(e.value)
