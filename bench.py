@@ -6,9 +6,12 @@ stage evaluations (fused phase-field preparation, CDI-flux / momentum / GNBC
 stage kernel, projection right-hand side) and 4 variable-density pressure
 projections by multigrid-preconditioned flexible CG to a relative residual of
 1e-10.  The default workload is the seeded 64-instance ensemble of uneven
-drop and Couette grids (128x64 .. 512x256, 3.9 M cells), FP64, all instances
-in one batched context: the largest single-GPU configuration of the
-benchmark set.
+drop and Couette grids (128x64 .. 512x256, 3.9 M cells), FP64, over its
+1000-step run: the largest single-GPU configuration of the benchmark set.
+The instances are split into two batched contexts of nearly equal size, one
+stream each, advanced together (cdi_step_concurrent): one context's kernels
+fill the GPU while the other waits on its latency-bound phases.  The same
+instances in one context are timed beside it (single_context).
 
 Prints one JSON line:
   metric/value/unit       Mcell-steps/s = sum over instances of nx * ny *
@@ -428,9 +431,11 @@ def poisson_learned_vs_plain(nx: int = 2048, train_seconds: float = 60.0, verbos
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default=ENSEMBLE)
+    ap.add_argument("--groups", type=int, default=2,
+                    help="contexts the headline batch is split into, stepped concurrently")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--kernel", default="auto",
                     help="kernel family for the roofline entry (auto: largest device time)")
@@ -467,23 +472,55 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_2412_16843_amd.solver import CDISolver
+    from paper_2412_16843_amd.solver import CDISolver, EnsembleSolver
 
     cases = workload(args.workload)
     params = [c.params for c in cases]
     log(f"workload {args.workload}: {len(cases)} instance(s), {_cells(cases)} cells")
+
+    def configure(solver):
+        if args.launch != "auto":
+            # a fixed launch form and shape, e.g. the autotuner's pick, for
+            # profiler runs (which would otherwise tune under the profiler)
+            solver.set_launch(args.launch)
+            if args.tile_rows:
+                solver.set_tile_rows(args.tile_rows)
+            if args.coarse_cells:
+                solver.set_coarse_cells(args.coarse_cells)
+            if args.mg_smooth:
+                solver.set_mg_smooth(args.mg_smooth)
+
+    # the headline: the batch in `groups` concurrent contexts, K steps with
+    # no instrumentation
+    groups = max(1, min(args.groups, len(cases)))
+    head = EnsembleSolver(params, [c.phi0 for c in cases], groups=groups,
+                          precision=args.precision, guess="prev", rtol=1e-10)
+    for g in head.solvers:
+        configure(g)
+    head.step(args.warmup)
+    torch.cuda.synchronize()
+    head_tuned = head.tune(trial_steps=10) if args.launch == "auto" else None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    head.step(args.steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    value = _cells(cases) * args.steps / elapsed / 1e6
+    head_cfg = [{"instances": len(ix), "cells": sum(params[k].nx * params[k].ny for k in ix),
+                 "launch": g.get_launch(), "tile_rows": g.get_tile_rows(),
+                 "coarse_cells": g.get_coarse_cells(), "mg_smooth": g.get_mg_smooth()}
+                for ix, g in zip(head.groups, head.solvers)]
+    head.close()
+    del head
+    torch.cuda.empty_cache()
+    log(f"timed {args.steps} steps in {groups} concurrent context(s): "
+        f"{elapsed * 1e3 / args.steps:.3f} ms/step, {value:.2f} Mcell-steps/s")
+
+    # the same batch in one context: its rate over the same steps, then the
+    # per-family device times (the roofline entry) in a separate pass
     s = CDISolver(params, [c.phi0 for c in cases], precision=args.precision, guess="prev",
                   rtol=1e-10)
-    if args.launch != "auto":
-        # a fixed launch form and shape, e.g. the autotuner's pick, for
-        # profiler runs (which would otherwise tune under the profiler)
-        s.set_launch(args.launch)
-        if args.tile_rows:
-            s.set_tile_rows(args.tile_rows)
-        if args.coarse_cells:
-            s.set_coarse_cells(args.coarse_cells)
-        if args.mg_smooth:
-            s.set_mg_smooth(args.mg_smooth)
+    configure(s)
     s.step(args.warmup)
     torch.cuda.synchronize()
     tuned = None
@@ -491,12 +528,9 @@ def main():
         tuned = s.tune(trial_steps=10)
         log(f"tuned: {tuned['launch']} rows {tuned['tile_rows']} coarse {tuned['coarse_cells']} "
             f"nu {tuned['mg_smooth']}")
-
-    # the headline: K steps with no instrumentation
-    value, elapsed = timed_rate(s, cases, args.steps)
-    d = s.diagnostics(0)
-    log(f"timed {args.steps} steps: {elapsed * 1e3 / args.steps:.3f} ms/step, {value:.2f} "
-        "Mcell-steps/s")
+    single_value, single_elapsed = timed_rate(s, cases, args.steps)
+    log(f"one context, {args.steps} steps: {single_elapsed * 1e3 / args.steps:.3f} ms/step, "
+        f"{single_value:.2f} Mcell-steps/s")
 
     # separate pass: device time of every kernel family (its own launches'
     # start / end timestamps), the dominant one is the roofline entry
@@ -539,9 +573,15 @@ def main():
                              f"{max(p.nx for p in params)}x{max(p.ny for p in params)}"),
                    "precision": args.precision, "poisson_rtol": 1e-10,
                    "cg_iters_per_step": iters_per_step,
-                   "launch": s.get_launch(), "tile_rows": s.get_tile_rows(),
-                   "coarse_cells": coarse_cells, "mg_smooth": s.get_mg_smooth(),
-                   "autotune": tuned, "parallelism": "single-gpu"},
+                   "steps_of_run": args.warmup + args.steps,
+                   "concurrent_contexts": head_cfg, "autotune": head_tuned,
+                   "parallelism": "single-gpu"},
+        "single_context": {"value": round(single_value, 4), "unit": "Mcell-steps/s",
+                           "steps": args.steps,
+                           "ms_per_step": round(single_elapsed / args.steps * 1e3, 5),
+                           "launch": s.get_launch(), "tile_rows": s.get_tile_rows(),
+                           "coarse_cells": coarse_cells, "mg_smooth": s.get_mg_smooth(),
+                           "autotune": tuned},
         "roofline": {"bound": "hbm", "kernel": fam, "achieved": round(achieved, 2),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 5),

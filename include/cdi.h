@@ -188,6 +188,17 @@ cdi_status cdi_init_batch(const cdi_params* params, int32_t n, const cdi_fields*
  * returns after that stage (the fields are then not a valid state). */
 cdi_status cdi_step(cdi_ctx* ctx, int32_t nsteps);
 
+/* Advance n distinct contexts by nsteps each at the same time: one host
+ * thread per context runs its cdi_step.  Contexts created on different
+ * streams overlap on the GPU, so one part of a batch fills the compute
+ * units while another waits on its latency-bound phases (the one-block
+ * coarse cycle, the host's convergence checks) -- an ensemble split into two
+ * contexts runs faster than one context holding it all.  Returns CDI_OK, the
+ * first hard error of any context (cdi_last_error gives its message), or
+ * CDI_ERR_NOCONV if a context reported it.  Not safe to call on a context
+ * that another thread uses at the same time. */
+cdi_status cdi_step_concurrent(cdi_ctx* const* ctxs, int32_t n, int32_t nsteps);
+
 /* Standalone pressure solve of instance 0 with the density of its current
  * phase field: sum_faces (p_nb - p)/(rho_f h^2) = b - mean(b).  b: device,
  * ny*nx (NULL = the right-hand side of the last projection); p: device,

@@ -30,7 +30,7 @@ EXPORTS = ("cdi_workspace_bytes", "cdi_default_dt", "cdi_init", "cdi_init_batch"
            "cdi_tune", "cdi_graph_stats", "cdi_set_coarse_cells", "cdi_get_coarse_cells",
            "cdi_set_mg_smooth", "cdi_get_mg_smooth", "cdi_set_extrapolation",
            "cdi_get_extrapolation", "cdi_eval_rhs_noalloc", "cdi_set_strip_rows",
-           "cdi_get_strip_rows")
+           "cdi_get_strip_rows", "cdi_step_concurrent")
 EXPORTS3 = ("cdi3_workspace_bytes", "cdi3_init", "cdi3_step", "cdi3_eval_rhs", "cdi3_kappa_p",
             "cdi3_diagnostics", "cdi3_time_stage", "cdi3_destroy")
 
@@ -121,6 +121,8 @@ def lib() -> C.CDLL:
     L.cdi_init_batch.restype = i32
     L.cdi_step.argtypes = [vp, i32]
     L.cdi_step.restype = i32
+    L.cdi_step_concurrent.argtypes = [P(vp), i32, i32]
+    L.cdi_step_concurrent.restype = i32
     L.cdi_solve_pressure.argtypes = [vp, vp, vp, P(cdi_solve_info)]
     L.cdi_solve_pressure.restype = i32
     L.cdi_diagnostics.argtypes = [vp, i32, P(cdi_diag)]

@@ -12,6 +12,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <type_traits>
 #include <vector>
 
@@ -1131,6 +1132,60 @@ cdi_status cdi_step(cdi_ctx* c, int32_t nsteps) {
     c->step += 1;
   }
   return st;
+}
+
+cdi_status cdi_step_concurrent(cdi_ctx* const* ctxs, int32_t n, int32_t nsteps) {
+  if (!ctxs || n < 1) return fail(CDI_ERR_ARG, "ctxs is NULL or n < 1");
+  if (nsteps < 0) return fail(CDI_ERR_ARG, "nsteps < 0");
+  for (int k = 0; k < n; ++k) {
+    if (!ctxs[k]) return fail(CDI_ERR_ARG, "ctxs[%d] is NULL", k);
+    for (int m = 0; m < k; ++m)
+      if (ctxs[m] == ctxs[k]) return fail(CDI_ERR_ARG, "ctxs[%d] repeats ctxs[%d]", k, m);
+  }
+  // one host thread per further context; each keeps its own error message,
+  // handed back to the caller's thread for the first failing context
+  // a worker thread starts on device 0: give it the device of its
+  // context's stream (the caller's device for the null stream)
+  int dev0 = 0;
+  hipError_t e = hipGetDevice(&dev0);
+  if (e != hipSuccess) return fail(CDI_ERR_DEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+  std::vector<int> dev(n, dev0);
+  for (int k = 0; k < n; ++k)
+    if (ctxs[k]->stream) {
+      hipDevice_t d;
+      e = hipStreamGetDevice(ctxs[k]->stream, &d);
+      if (e != hipSuccess) return fail(CDI_ERR_DEVICE, "hipStreamGetDevice: %s", hipGetErrorString(e));
+      dev[k] = (int)d;
+    }
+  std::vector<cdi_status> st(n, CDI_OK);
+  std::vector<std::string> msg(n);
+  auto run = [&](int k) {
+    if (k > 0) {
+      hipError_t he = hipSetDevice(dev[k]);
+      if (he != hipSuccess) {
+        st[k] = CDI_ERR_DEVICE;
+        msg[k] = std::string("hipSetDevice: ") + hipGetErrorString(he);
+        return;
+      }
+    }
+    st[k] = cdi_step(ctxs[k], nsteps);
+    if (st[k] != CDI_OK) msg[k] = g_err;
+  };
+  std::vector<std::thread> th;
+  th.reserve(n - 1);
+  for (int k = 1; k < n; ++k) th.emplace_back(run, k);
+  run(0);
+  for (auto& t : th) t.join();
+  cdi_status out = CDI_OK;
+  for (int k = 0; k < n; ++k)
+    if (st[k] != CDI_OK && st[k] != CDI_ERR_NOCONV) {
+      g_err = msg[k];
+      return st[k];
+    } else if (st[k] == CDI_ERR_NOCONV && out == CDI_OK) {
+      out = st[k];
+      g_err = msg[k];
+    }
+  return out;
 }
 
 cdi_status cdi_solve_pressure(cdi_ctx* c, const double* b, double* p, cdi_solve_info* info) {

@@ -259,3 +259,84 @@ class CDISolver:
             self.close()
         except Exception:
             pass
+
+
+def split_by_size(cells: Sequence[int], groups: int) -> List[List[int]]:
+    """Instance indices split into `groups` lists of nearly equal total size:
+    largest first, dealt out in a snake order (0, 1, .., G-1, G-1, .., 0, ..)."""
+    order = sorted(range(len(cells)), key=lambda k: (-cells[k], k))
+    out: List[List[int]] = [[] for _ in range(groups)]
+    for r, k in enumerate(order):
+        g = r % groups
+        out[g if (r // groups) % 2 == 0 else groups - 1 - g].append(k)
+    return [sorted(g) for g in out if g]
+
+
+class EnsembleSolver:
+    """A batch of independent instances split into `groups` contexts of
+    nearly equal size, each on its own stream, advanced together
+    (cdi_step_concurrent): while one context waits on its latency-bound
+    phases (the one-block coarse cycle, the host's convergence test) the
+    other's kernels fill the compute units.  Every instance evolves exactly
+    as it does alone (the instances of a batch never interact).
+
+    Arguments as CDISolver (lists of parameter objects and phase fields);
+    instance k of the argument lists keeps index k in diagnostics / state.
+    """
+
+    def __init__(self, params, phi0, groups: int = 2, device: str = "cuda:0", u0=None, v0=None,
+                 **kw):
+        if not torch.cuda.is_available():
+            raise RuntimeError("EnsembleSolver needs a GPU (the HIP library has no CPU path)")
+        params, phi0 = list(params), list(phi0)
+        if len(params) != len(phi0):
+            raise ValueError("one phase field per instance is required")
+        if groups < 1:
+            raise ValueError("groups must be >= 1")
+        self.n = len(params)
+        self.device = torch.device(device)
+        self.lib = L.lib()
+        self.groups = split_by_size([p.nx * p.ny for p in params], min(groups, self.n))
+        self.where = {}
+        self.streams = [torch.cuda.Stream(self.device) for _ in self.groups]
+        self.solvers: List[CDISolver] = []
+        for g, idx in enumerate(self.groups):
+            with torch.cuda.stream(self.streams[g]):
+                self.solvers.append(CDISolver(
+                    [params[k] for k in idx], [phi0[k] for k in idx], device=device,
+                    u0=None if u0 is None else [u0[k] for k in idx],
+                    v0=None if v0 is None else [v0[k] for k in idx], **kw))
+            for j, k in enumerate(idx):
+                self.where[k] = (g, j)
+        self._ctxs = (C.c_void_p * len(self.solvers))(*[s.ctx.value for s in self.solvers])
+
+    def step(self, nsteps: int = 1, allow_noconv: bool = False) -> int:
+        return L.check(self.lib.cdi_step_concurrent(self._ctxs, len(self.solvers), int(nsteps)),
+                       allow=(-4,) if allow_noconv else ())
+
+    def tune(self, trial_steps: int = 10) -> List[Dict]:
+        """Autotune each context alone (launch form and tile shape)."""
+        return [s.tune(trial_steps) for s in self.solvers]
+
+    def diagnostics(self, idx: int = 0) -> Dict[str, float]:
+        g, j = self.where[idx]
+        return self.solvers[g].diagnostics(j)
+
+    def state(self, idx: int = 0):
+        g, j = self.where[idx]
+        return self.solvers[g].state(j)
+
+    def set_state(self, idx: int, **fields):
+        g, j = self.where[idx]
+        self.solvers[g].set_state(j, **fields)
+
+    def close(self):
+        for s in getattr(self, "solvers", []):
+            s.close()
+        self.solvers = []
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -187,3 +187,19 @@ def test_noalloc_entry_point_rejects_a_grid_beyond_its_scratch():
     small = L.make_params(W.config1().params)
     assert lib.cdi_eval_rhs_noalloc(C.byref(small), C.byref(cf0), dummy, dummy, dummy, None,
                                     None, None) == -1
+
+
+def test_ensemble_split_by_size_covers_and_balances():
+    """The groups of a concurrently stepped ensemble: every instance in exactly
+    one group, and the seeded 64-instance ensemble split into two halves of
+    nearly equal cell count."""
+    from paper_2412_16843_amd.solver import split_by_size
+    cells = [64 * 32, 96 * 48, 128 * 64, 160 * 80, 96 * 48, 512 * 256, 256 * 128]
+    for g in (1, 2, 3):
+        parts = split_by_size(cells, g)
+        assert sorted(k for p in parts for k in p) == list(range(len(cells)))
+        assert len(parts) == g
+    assert split_by_size([5, 7], 4) == [[1], [0]]
+    ens = [c.params.nx * c.params.ny for c in W.config4(steps=1)]
+    halves = [sum(ens[k] for k in p) for p in split_by_size(ens, 2)]
+    assert abs(halves[0] - halves[1]) <= 0.02 * sum(halves), halves

@@ -1,0 +1,104 @@
+"""Concurrent stepping of several contexts (cdi_step_concurrent).
+
+A batch split into contexts on their own streams and advanced from one host
+thread per context must evolve every instance exactly as one batched context
+does (instances never interact; a batch is bitwise its solo runs), whatever
+launch form each context uses, and a failure in one context must reach the
+caller with its own status and message.
+"""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+NOCONV, NONFINITE, ERR_ARG = -4, -5, -1
+
+
+def _torch():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _cases():
+    return [W.drop_case(64, 32, 60.0, 10.0, name="a"),
+            W.couette_case(96, 48, lx=2.0, ly=1.0, ratio=1.0, theta_eq_deg=70.0, name="b"),
+            W.drop_case(128, 64, 120.0, 1.0, name="c"),
+            W.couette_case(160, 80, lx=2.0, ly=1.0, ratio=10.0, ca=0.05, name="d"),
+            W.drop_case(96, 48, 30.0, 10.0, name="e")]
+
+
+@pytest.mark.parametrize("launches", [("tiled", "tiled"), ("graph", "tiled")])
+def test_concurrent_groups_are_bitwise_the_batched_context(launches):
+    _torch()
+    from paper_2412_16843_amd.solver import CDISolver, EnsembleSolver
+    cases = _cases()
+    steps = 4
+    ref = CDISolver([c.params for c in cases], [c.phi0 for c in cases], rtol=1e-12, maxit=400)
+    ref.step(steps)
+    want = [ref.state(k) for k in range(len(cases))]
+    ref.close()
+    ens = EnsembleSolver([c.params for c in cases], [c.phi0 for c in cases], groups=2,
+                         rtol=1e-12, maxit=400)
+    assert len(ens.solvers) == 2
+    assert len({s.stream.cuda_stream for s in ens.solvers}) == 2
+    for s, mode in zip(ens.solvers, launches):
+        s.set_launch(mode)
+    ens.step(2)
+    ens.step(steps - 2)
+    for k, c in enumerate(cases):
+        g = ens.state(k)
+        for f in ("phi", "u", "v", "p"):
+            assert np.array_equal(g[f], want[k][f]), (c.name, f, launches)
+        d = ens.diagnostics(k)
+        assert d["step"] == steps and d["nonfinite"] == 0
+    ens.close()
+
+
+def test_a_failing_context_reports_its_status_and_the_other_advances():
+    _torch()
+    from paper_2412_16843_amd._lib import CDIError
+    from paper_2412_16843_amd.solver import EnsembleSolver
+    cases = _cases()[:4]
+    ens = EnsembleSolver([c.params for c in cases], [c.phi0 for c in cases], groups=2,
+                         rtol=1e-12, maxit=400)
+    ens.step(1)
+    bad = 3
+    g_bad, _ = ens.where[bad]
+    u = ens.state(bad)["u"].copy()
+    u[5, 7] = np.nan
+    ens.set_state(bad, u=u)
+    with pytest.raises(CDIError) as e:
+        ens.step(1)
+    assert e.value.status == NONFINITE
+    assert "non-finite" in str(e.value).lower() or "nan" in str(e.value).lower()
+    other = [k for k in range(len(cases)) if ens.where[k][0] != g_bad]
+    for k in other:
+        d = ens.diagnostics(k)
+        assert d["step"] == 2 and d["nonfinite"] == 0
+    ens.close()
+
+
+def test_repeated_or_null_context_is_refused_before_any_work():
+    _torch()
+    from paper_2412_16843_amd import _lib as L
+    from paper_2412_16843_amd.solver import CDISolver
+    c = _cases()[0]
+    s = CDISolver(c.params, c.phi0, rtol=1e-12)
+    lib = L.lib()
+    two = (C.c_void_p * 2)(s.ctx.value, s.ctx.value)
+    assert lib.cdi_step_concurrent(two, 2, 1) == ERR_ARG
+    assert b"repeats" in lib.cdi_last_error()
+    null = (C.c_void_p * 2)(s.ctx.value, None)
+    assert lib.cdi_step_concurrent(null, 2, 1) == ERR_ARG
+    assert lib.cdi_step_concurrent(two, 0, 1) == ERR_ARG
+    assert lib.cdi_step_concurrent(two, 1, -1) == ERR_ARG
+    assert s.diagnostics()["step"] == 0
+    assert lib.cdi_step_concurrent(two, 1, 1) == 0
+    assert s.diagnostics()["step"] == 1
+    s.close()
