@@ -31,11 +31,11 @@ enum { S_GAMMA = 0, S_BMEAN, S_FF, S_RR, S_RZ, S_RZOLD, S_DQ, S_ALPHA, S_ZQ, S_X
 
 struct Lev3 {
   int nx, ny, nz;
-  double* ax;   // x-faces, cell layout
-  double* ay;   // y-faces, v layout (wall rows 0)
-  double* az;   // z-faces, cell layout
-  double* r;    // right-hand side of the level
-  double* x;    // correction of the level
+  cdi::gptr<double> ax;   // x-faces, cell layout
+  cdi::gptr<double> ay;   // y-faces, v layout (wall rows 0)
+  cdi::gptr<double> az;   // z-faces, cell layout
+  cdi::gptr<double> r;    // right-hand side of the level
+  cdi::gptr<double> x;    // correction of the level
 };
 
 struct Ctx3 {
@@ -44,18 +44,18 @@ struct Ctx3 {
   double rho1, rho2, mu1, mu2, beta1, beta2;
   double uwb, uwt, wwb, wwt;   // wall speeds: x bottom / top, z bottom / top
   double dt;
-  double *phi, *u, *v, *w, *p;                     // caller state
-  double *phi_a, *phi_b, *us, *vs, *ws;            // stage phase field and velocity
-  double *acc_phi, *acc_mx, *acc_my, *acc_mz;      // RK accumulators (acc_my: v layout)
-  double *mx, *my, *mz;                            // next-stage momentum (my: v layout)
-  double *psi, *nxv, *nyv, *nzv, *muc, *kap_p;
-  double *wall;                                    // [2][5][nz][nx]: phi, psi, psi_y, kappa_p, phi_y
-  double *Fx, *Fy, *Fz, *fmx, *fmy, *fmz;           // face fluxes and mass fluxes (Fy, fmy: v layout)
-  double *txy, *tyz, *txz;                         // edge stresses
-  double *uYx, *uYz, *slx, *slz;                   // [2][nz][nx] Young slip and total slip
-  double *b, *x, *r, *z, *d, *q;
-  double *part;                                    // block partials
-  double *scal;                                    // S_* scalars
+  cdi::gptr<double> phi, u, v, w, p;                     // caller state
+  cdi::gptr<double> phi_a, phi_b, us, vs, ws;            // stage phase field and velocity
+  cdi::gptr<double> acc_phi, acc_mx, acc_my, acc_mz;      // RK accumulators (acc_my: v layout)
+  cdi::gptr<double> mx, my, mz;                            // next-stage momentum (my: v layout)
+  cdi::gptr<double> psi, nxv, nyv, nzv, muc, kap_p;
+  cdi::gptr<double> wall;                                    // [2][5][nz][nx]: phi, psi, psi_y, kappa_p, phi_y
+  cdi::gptr<double> Fx, Fy, Fz, fmx, fmy, fmz;           // face fluxes and mass fluxes (Fy, fmy: v layout)
+  cdi::gptr<double> txy, tyz, txz;                         // edge stresses
+  cdi::gptr<double> uYx, uYz, slx, slz;                   // [2][nz][nx] Young slip and total slip
+  cdi::gptr<double> b, x, r, z, d, q;
+  cdi::gptr<double> part;                                    // block partials
+  cdi::gptr<double> scal;                                    // S_* scalars
   int nlev;
   Lev3 lev[kMaxLev3];
 };
@@ -104,7 +104,7 @@ __global__ void __launch_bounds__(kNT3) k3_psi(const Ctx3* __restrict__ C, int s
   const long g = (long)blockIdx.x * kNT3 + threadIdx.x;
   const int n = C->nx * C->ny * C->nz;
   if (g >= n) return;
-  const double* ph = src == 0 ? C->phi : (src == 1 ? C->phi_a : C->phi_b);
+  const CDI_GLOBAL double* ph = src == 0 ? C->phi : (src == 1 ? C->phi_a : C->phi_b);
   const double cl = fmin(fmax(ph[g], 0.0), 1.0);
   C->psi[g] = C->eps * log((cl + cdi::kDeltaPsi) / (1.0 - cl + cdi::kDeltaPsi));
 }
@@ -126,7 +126,7 @@ __global__ void __launch_bounds__(kNT3) k3_prep(const Ctx3* __restrict__ C, int 
   const int nx = C->nx, ny = C->ny, nz = C->nz;
   int k, j, i;
   if (!unflat3((long)blockIdx.x * kNT3 + threadIdx.x, nx, ny, nz, k, j, i)) return;
-  const double* ph = src == 0 ? C->phi : (src == 1 ? C->phi_a : C->phi_b);
+  const CDI_GLOBAL double* ph = src == 0 ? C->phi : (src == 1 ? C->phi_a : C->phi_b);
   const double* ps = C->psi;
   const unsigned c = ic3(nx, ny, k, j, i);
   const unsigned ce = ic3(nx, ny, k, j, wrap3(i + 1, nx)), cw = ic3(nx, ny, k, j, wrap3(i - 1, nx));
@@ -179,7 +179,7 @@ __global__ void __launch_bounds__(kNT3) k3_kappa_p(const Ctx3* __restrict__ C, i
                                                    double* __restrict__ out) {
   int k, j, i;
   if (!unflat3((long)blockIdx.x * kNT3 + threadIdx.x, C->nx, C->ny, C->nz, k, j, i)) return;
-  const double* ph = src == 0 ? C->phi : (src == 1 ? C->phi_a : C->phi_b);
+  const CDI_GLOBAL double* ph = src == 0 ? C->phi : (src == 1 ? C->phi_a : C->phi_b);
   out[ic3(C->nx, C->ny, k, j, i)] = kappa_p_at(C, ph, k, j, i);
 }
 
@@ -190,7 +190,7 @@ __global__ void __launch_bounds__(kNT3) k3_wall(const Ctx3* __restrict__ C, int 
   const long g = (long)blockIdx.x * kNT3 + threadIdx.x;
   if (g >= 2L * nz * nx) return;
   const int i = (int)(g % nx), k = (int)((g / nx) % nz), wall = (int)(g / ((long)nx * nz));
-  const double* ph = src == 0 ? C->phi : (src == 1 ? C->phi_a : C->phi_b);
+  const CDI_GLOBAL double* ph = src == 0 ? C->phi : (src == 1 ? C->phi_a : C->phi_b);
   const double i2h = 0.5 * C->inv_h;
   double val[2][5];
   for (int r = 0; r < 2; ++r) {
@@ -260,10 +260,10 @@ __global__ void __launch_bounds__(kNT3) k3_flux(const Ctx3* __restrict__ C, int 
   const int nx = C->nx, ny = C->ny, nz = C->nz;
   int k, j, i;
   if (!unflat3((long)blockIdx.x * kNT3 + threadIdx.x, nx, ny, nz, k, j, i)) return;
-  const double* ph = src == 0 ? C->phi : (src == 1 ? C->phi_a : C->phi_b);
-  const double* uu = kst <= 0 ? C->u : C->us;
-  const double* vv = kst <= 0 ? C->v : C->vs;
-  const double* ww = kst <= 0 ? C->w : C->ws;
+  const CDI_GLOBAL double* ph = src == 0 ? C->phi : (src == 1 ? C->phi_a : C->phi_b);
+  const CDI_GLOBAL double* uu = kst <= 0 ? C->u : C->us;
+  const CDI_GLOBAL double* vv = kst <= 0 ? C->v : C->vs;
+  const CDI_GLOBAL double* ww = kst <= 0 ? C->w : C->ws;
   const double gam = C->scal[S_GAMMA], eps = C->eps, inv_h = C->inv_h;
   const double drho = C->rho1 - C->rho2, rho2 = C->rho2;
   const unsigned c = ic3(nx, ny, k, j, i);
@@ -314,10 +314,10 @@ __global__ void __launch_bounds__(kNT3) k3_edges(const Ctx3* __restrict__ C, int
   const int nx = C->nx, ny = C->ny, nz = C->nz;
   int k, j, i;
   if (!unflat3((long)blockIdx.x * kNT3 + threadIdx.x, nx, ny + 1, nz, k, j, i)) return;
-  const double* ph = src == 0 ? C->phi : (src == 1 ? C->phi_a : C->phi_b);
-  const double* uu = kst <= 0 ? C->u : C->us;
-  const double* vv = kst <= 0 ? C->v : C->vs;
-  const double* ww = kst <= 0 ? C->w : C->ws;
+  const CDI_GLOBAL double* ph = src == 0 ? C->phi : (src == 1 ? C->phi_a : C->phi_b);
+  const CDI_GLOBAL double* uu = kst <= 0 ? C->u : C->us;
+  const CDI_GLOBAL double* vv = kst <= 0 ? C->v : C->vs;
+  const CDI_GLOBAL double* ww = kst <= 0 ? C->w : C->ws;
   const double mud = C->mu1 - C->mu2, mu2 = C->mu2, inv_h = C->inv_h;
   const int iw = wrap3(i - 1, nx), kb = wrap3(k - 1, nz);
   const unsigned e = iv3(nx, ny, k, j, i);
@@ -409,10 +409,10 @@ __global__ void __launch_bounds__(kNT3) k3_mom(const Ctx3* __restrict__ C, int k
   const int nx = C->nx, ny = C->ny, nz = C->nz;
   int k, j, i;
   if (!unflat3((long)blockIdx.x * kNT3 + threadIdx.x, nx, ny, nz, k, j, i)) return;
-  const double* ph = src == 0 ? C->phi : (src == 1 ? C->phi_a : C->phi_b);
-  const double* uu = kst <= 0 ? C->u : C->us;
-  const double* vv = kst <= 0 ? C->v : C->vs;
-  const double* ww = kst <= 0 ? C->w : C->ws;
+  const CDI_GLOBAL double* ph = src == 0 ? C->phi : (src == 1 ? C->phi_a : C->phi_b);
+  const CDI_GLOBAL double* uu = kst <= 0 ? C->u : C->us;
+  const CDI_GLOBAL double* vv = kst <= 0 ? C->v : C->vs;
+  const CDI_GLOBAL double* ww = kst <= 0 ? C->w : C->ws;
   const double mud = C->mu1 - C->mu2, mu2 = C->mu2, inv_h = C->inv_h;
   const int ie = wrap3(i + 1, nx), iw = wrap3(i - 1, nx);
   const int kf = wrap3(k + 1, nz), kb = wrap3(k - 1, nz);
@@ -487,7 +487,7 @@ __global__ void __launch_bounds__(kNT3) k3_mom(const Ctx3* __restrict__ C, int k
     if (j >= 1) C->acc_my[e] = Lmy;
     return;
   }
-  double* pdst = dst == 1 ? C->phi_a : C->phi_b;
+  CDI_GLOBAL double* pdst = dst == 1 ? C->phi_a : C->phi_b;
   const double* p0 = C->phi;
   const double r1 = C->rho1, r2 = C->rho2;
   const double rc = (r1 - r2) * p0[c] + r2;
@@ -534,7 +534,7 @@ __global__ void __launch_bounds__(kNT3) k3_rhs(const Ctx3* __restrict__ C, int s
   const bool in = unflat3((long)blockIdx.x * kNT3 + threadIdx.x, nx, ny, nz, k, j, i);
   double s[1] = {0.0};
   if (in) {
-    const double* ph = src == 1 ? C->phi_a : C->phi_b;
+    const CDI_GLOBAL double* ph = src == 1 ? C->phi_a : C->phi_b;
     const double r1 = C->rho1, r2 = C->rho2;
     auto rho = [&](unsigned o) { return (r1 - r2) * ph[o] + r2; };
     const unsigned c = ic3(nx, ny, k, j, i);
@@ -756,7 +756,7 @@ __global__ void __launch_bounds__(kNT3) k3_project(const Ctx3* __restrict__ C, i
   const int nx = C->nx, ny = C->ny, nz = C->nz;
   int k, j, i;
   if (!unflat3((long)blockIdx.x * kNT3 + threadIdx.x, nx, ny, nz, k, j, i)) return;
-  const double* ph = src == 1 ? C->phi_a : C->phi_b;
+  const CDI_GLOBAL double* ph = src == 1 ? C->phi_a : C->phi_b;
   const double r1 = C->rho1, r2 = C->rho2;
   auto rho = [&](unsigned o) { return (r1 - r2) * ph[o] + r2; };
   const double xm = C->scal[S_XMEAN];
@@ -770,9 +770,9 @@ __global__ void __launch_bounds__(kNT3) k3_project(const Ctx3* __restrict__ C, i
   const double wn = C->ws[c] - fac * (pc - (C->x[cb] - xm)) / (0.5 * (rho(cb) + rc));
   double vn = 0.0;
   if (j >= 1) vn = C->vs[e] - fac * (pc - (C->x[c - nx] - xm)) / (0.5 * (rho(c - nx) + rc));
-  double* uo = final_stage ? C->u : C->us;
-  double* vo = final_stage ? C->v : C->vs;
-  double* wo = final_stage ? C->w : C->ws;
+  CDI_GLOBAL double* uo = final_stage ? C->u : C->us;
+  CDI_GLOBAL double* vo = final_stage ? C->v : C->vs;
+  CDI_GLOBAL double* wo = final_stage ? C->w : C->ws;
   uo[c] = un;
   wo[c] = wn;
   vo[e] = vn;                       // row 0: the wall (v = 0)

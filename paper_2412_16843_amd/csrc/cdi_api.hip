@@ -192,8 +192,8 @@ size_t carve(const Resolved& R, int ntiles_cell, int ntiles_mg0, char* base, siz
     L.ny = R.lny[l];
     const size_t lc = (size_t)L.nx * L.ny, lf = (size_t)(L.ny + 1) * L.nx;
     if (l == 0 && !mixed) {
-      L.ax = D.ax0;
-      L.ay = D.ay0;
+      L.ax = D.ax0.p;
+      L.ay = D.ay0.p;
     } else {
       L.ax = take(lc * S);
       L.ay = take(lf * S);
@@ -1083,7 +1083,7 @@ cdi_status cdi_init_batch(const cdi_params* params, int32_t n, const cdi_fields*
   }
   // zero the whole per-instance workspace once (walls of v-type arrays,
   // counters, flags); every later write stays inside the domain
-  const size_t hdr = (size_t)((char*)B.inst[0].phi_a - c->ws);
+  const size_t hdr = (size_t)((char*)B.inst[0].phi_a.p - c->ws);
   if ((e = hipMemsetAsync(c->ws + hdr, 0, need - hdr, c->stream)) != hipSuccess)
     return cleanup_fail(e, "clear workspace");
   k_gamma_init<<<(unsigned)ceil_div(n, 64), 64, 0, c->stream>>>(c->d_inst, n);

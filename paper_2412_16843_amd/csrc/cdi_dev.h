@@ -16,6 +16,32 @@ constexpr int kNT = 256;          // threads per block of every tiled kernel
 constexpr double kDeltaN = 1e-12; // normal-vector regularisation: n = G/(|G| + dN)
 constexpr double kDeltaPsi = 1e-12;
 
+// Pointer to device global memory held in a descriptor struct.  The host
+// stores and reads it as a plain pointer; device code reads it as a pointer
+// into the global address space, so that every access through it is a
+// global (not flat) memory instruction: a flat access also counts against the
+// LDS wait counter, so an LDS wait of a kernel with flat loads in flight
+// would wait for those loads too.  (The global-space pointer must leave the
+// conversion function as such: converted back to a generic pointer inside
+// the same function, the compiler folds the pair of casts away.)
+#if defined(__HIP_DEVICE_COMPILE__)
+#define CDI_GLOBAL __attribute__((address_space(1)))
+#else
+#define CDI_GLOBAL
+#endif
+template <typename T>
+struct gptr {
+  T* p;
+  gptr() = default;
+  __host__ __device__ constexpr gptr(T* q) : p(q) {}
+  __host__ __device__ __forceinline__ operator CDI_GLOBAL T*() const { return (CDI_GLOBAL T*)p; }
+  __host__ __device__ __forceinline__ CDI_GLOBAL T* operator->() const { return (CDI_GLOBAL T*)p; }
+};
+// Typed view of an untyped global pointer (arrays whose element type S is
+// the instance's storage precision).
+template <typename U>
+__host__ __device__ __forceinline__ CDI_GLOBAL U* gas(gptr<void> g) { return (CDI_GLOBAL U*)g.p; }
+
 // One multigrid level of one instance.  Coefficients a = 1/(rho_f h_l^2) on
 // x-faces (ny_l * nx_l, face i = west face of cell i) and y-faces
 // ((ny_l+1) * nx_l, face j = south face of cell j; rows 0 and ny_l are walls
@@ -23,11 +49,11 @@ constexpr double kDeltaPsi = 1e-12;
 struct Level {
   int nx, ny;
   int first_tile, ntiles;   // tiles of this level in the level's tile list
-  void* ax;                 // S[ny*nx]
-  void* ay;                 // S[(ny+1)*nx]
-  void* r;                  // S[ny*nx]  residual / right-hand side of the level
-  void* z;                  // S[ny*nx]  correction of the level (pre-smoothed on tiled levels)
-  void* zo;                 // S[ny*nx]  post-smoothed correction written by the tiled up-sweep
+  gptr<void> ax;                 // S[ny*nx]
+  gptr<void> ay;                 // S[(ny+1)*nx]
+  gptr<void> r;                  // S[ny*nx]  residual / right-hand side of the level
+  gptr<void> z;                  // S[ny*nx]  correction of the level (pre-smoothed on tiled levels)
+  gptr<void> zo;                 // S[ny*nx]  post-smoothed correction written by the tiled up-sweep
                             //           (levels 1..lg-1; a launch never reads what it writes)
 };
 
@@ -70,31 +96,31 @@ struct Inst {
   double gamma_factor;      // > 0: gamma of a step = min(gamma, gamma_factor max|u|)
   double rho1, rho2, mu1, mu2, beta1, beta2, uw_bot, uw_top, dt;
   // caller state (FP64)
-  double* phi; double* u; double* v; double* p;
+  gptr<double> phi; gptr<double> u; gptr<double> v; gptr<double> p;
   // workspace: stage state and RK accumulators (FP64)
-  double* phi_a; double* phi_b;        // ping-pong stage phase field
-  double* us; double* vs;              // stage velocity after projection
-  double* mx; double* my;              // (rho u)* before division
-  double* ustar; double* vstar;        // u* before projection
-  double* acc_phi; double* acc_mx; double* acc_my;
+  gptr<double> phi_a; gptr<double> phi_b;        // ping-pong stage phase field
+  gptr<double> us; gptr<double> vs;              // stage velocity after projection
+  gptr<double> mx; gptr<double> my;              // (rho u)* before division
+  gptr<double> ustar; gptr<double> vstar;        // u* before projection
+  gptr<double> acc_phi; gptr<double> acc_mx; gptr<double> acc_my;
   // phase-field quantities (S)
-  void* nhx; void* nhy; void* muc;
-  double* wall;                        // [2 walls][5 q][nx]: phi_w, psi_w, dpsi_w, kappa_w, dphi_w
-  double* uY; double* uslip;           // [2][nx] wall corner diagnostics
+  gptr<void> nhx; gptr<void> nhy; gptr<void> muc;
+  gptr<double> wall;                        // [2 walls][5 q][nx]: phi_w, psi_w, dpsi_w, kappa_w, dphi_w
+  gptr<double> uY; gptr<double> uslip;           // [2][nx] wall corner diagnostics
   // level-0 FP64 coefficients a = 1/(rho_f h^2) of the pressure operator
-  double* ax0; double* ay0;
+  gptr<double> ax0; gptr<double> ay0;
   // pressure (FP64 CG vectors)
-  double* b; double* x; double* rr; double* rr2; double* d0; double* d1; double* q;
-  double* zf;                          // FP64 copy of level-0 correction (mixed path)
-  double* hp[kHistDepth][4];           // pressure of each RK stage d + 1 steps back (d = 0: the last step)
-  double* part;                        // reduction partials, [8][ntiles]
-  PcgScalars* pcg;
-  unsigned* counters;                  // [8 kinds][kCounterStride] arrival counters
+  gptr<double> b; gptr<double> x; gptr<double> rr; gptr<double> rr2; gptr<double> d0; gptr<double> d1; gptr<double> q;
+  gptr<double> zf;                          // FP64 copy of level-0 correction (mixed path)
+  gptr<double> hp[kHistDepth][4];           // pressure of each RK stage d + 1 steps back (d = 0: the last step)
+  gptr<double> part;                        // reduction partials, [8][ntiles]
+  gptr<PcgScalars> pcg;
+  gptr<unsigned> counters;                  // [8 kinds][kCounterStride] arrival counters
   Level lev[kMaxLevels];
-  double* snap;                        // graph path: state at the start of the step
-  void* mg_t;                          // S [ny*nx] residual scratch of the one-block V-cycle
-  void* mg_r0;                         // S [ny*nx] level-0 residual copy (mixed, one-block V-cycle)
-  double* cinv;                        // dense inverse of the coarsest operator (n <= 64)
+  gptr<double> snap;                        // graph path: state at the start of the step
+  gptr<void> mg_t;                          // S [ny*nx] residual scratch of the one-block V-cycle
+  gptr<void> mg_r0;                         // S [ny*nx] level-0 residual copy (mixed, one-block V-cycle)
+  gptr<double> cinv;                        // dense inverse of the coarsest operator (n <= 64)
   int cdense;                          // 1 if cinv is used for the coarsest solve
   int coef_const;                      // 1: uniform density, operator coefficients constant
 };

@@ -247,8 +247,8 @@ __global__ void __launch_bounds__(kNT) k_solve_setup(const Tile* __restrict__ ti
     I.ax0[o] = ax;
     I.ay0[o] = ay;
     if (I.mixed) {
-      ((S*)I.lev[0].ax)[o] = (S)ax;
-      ((S*)I.lev[0].ay)[o] = (S)ay;
+      (gas<S>(I.lev[0].ax))[o] = (S)ax;
+      (gas<S>(I.lev[0].ay))[o] = (S)ay;
     }
     const double b = bin ? bin[o] : I.b[o];
     I.b[o] = b;

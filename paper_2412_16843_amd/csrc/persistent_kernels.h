@@ -65,7 +65,7 @@ __device__ int persist_solve(const Inst& I, PersistLds<S>& L, int guess,
   const double fnorm = sqrt(s2[0]);
   zero = s2[0] == 0.0;
   relres = zero ? 0.0 : sqrt(s2[1]) / fnorm;
-  S* r0 = I.mixed ? (S*)I.mg_r0 : (S*)(void*)r;
+  S* r0 = I.mixed ? gas<S>(I.mg_r0) : (S*)(void*)r;
   const bool lds0 = I.lc == 0;
   auto view = [&](int l) { return mixed_view<S>(I, L.u.coarse, r0, l); };
   int it = 0;
@@ -145,7 +145,7 @@ __global__ void __launch_bounds__(PNT) k_step_persistent(const Tile* __restrict_
     for (int k = 0; k < 4; ++k) {
       const int src = k == 0 ? 0 : (k == 2 ? 2 : 1);
       const int dst = (k == 0 || k == 2) ? 1 : 2;
-      const double* phd = dst == 1 ? I.phi_a : I.phi_b;
+      const CDI_GLOBAL double* phd = dst == 1 ? I.phi_a : I.phi_b;
       // phase preparation and stage operator, PQ tiles at a time
       for (int base = 0; base < I.ntiles; base += PQ) {
         const int ti = base + q4;

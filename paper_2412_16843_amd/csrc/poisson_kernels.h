@@ -121,8 +121,8 @@ __device__ __forceinline__ double rhs_store(const Inst& I, const RhsIn& v, int j
   I.ax0[o] = ax;
   I.ay0[o] = ay;
   if (I.mixed) {
-    ((S*)I.lev[0].ax)[o] = (S)ax;
-    ((S*)I.lev[0].ay)[o] = (S)ay;
+    (gas<S>(I.lev[0].ax))[o] = (S)ax;
+    (gas<S>(I.lev[0].ay))[o] = (S)ay;
   }
   return b;
 }
@@ -141,7 +141,7 @@ __global__ void __launch_bounds__(kNT) k_rhs(const Tile* __restrict__ tiles,
   const Tile t = tiles[blockIdx.x];
   const Inst& I = insts[t.inst];
   const int nx = I.nx, ny = I.ny;
-  const double* __restrict__ ph = src == 0 ? I.phi : (src == 1 ? I.phi_a : I.phi_b);
+  const CDI_GLOBAL double* __restrict__ ph = src == 0 ? I.phi : (src == 1 ? I.phi_a : I.phi_b);
   double bsum[2] = {0.0, 0.0};
   RhsIn v[WR];
 #pragma unroll
@@ -364,10 +364,10 @@ __global__ void __launch_bounds__(kNT) k_pcg_spmv(const Tile* __restrict__ tiles
   const Inst& I = insts[t.inst];
   if (I.pcg->done) return;
   const int nx = I.nx, ny = I.ny;
-  const double* __restrict__ dold = parity ? I.d0 : I.d1;
-  double* __restrict__ dnew = parity ? I.d1 : I.d0;
+  const CDI_GLOBAL double* __restrict__ dold = parity ? I.d0 : I.d1;
+  CDI_GLOBAL double* __restrict__ dnew = parity ? I.d1 : I.d0;
   const double* __restrict__ z = I.zf;
-  const double* __restrict__ rv = rsel ? I.rr2 : I.rr;
+  const CDI_GLOBAL double* __restrict__ rv = rsel ? I.rr2 : I.rr;
   const bool first = I.pcg->first != 0;
   const double beta = first ? 0.0 : I.pcg->beta;
   // every global read of the thread first: d over the tile and its halo,
@@ -581,8 +581,8 @@ __device__ __forceinline__ void project_store(const Inst& I, const ProjIn& v, do
   const int nx = I.nx;
   const size_t o = (size_t)j * nx + i;
   const double scale = tau * I.dt * I.h;   // tau grad(p)/rho_f = tau (p_c - p_w) h a_f
-  double* __restrict__ uo = final_stage ? I.u : I.us;
-  double* __restrict__ vo = final_stage ? I.v : I.vs;
+  CDI_GLOBAL double* __restrict__ uo = final_stage ? I.u : I.us;
+  CDI_GLOBAL double* __restrict__ vo = final_stage ? I.v : I.vs;
   uo[o] = v.us - scale * (v.xc - v.xw) * v.ax;
   vo[o] = j >= 1 ? v.vs - scale * (v.xc - v.xs) * v.ay : 0.0;
   const double pn = v.xc - (zero ? 0.0 : xmean);
@@ -609,7 +609,7 @@ __global__ void __launch_bounds__(kNT) k_project(const Tile* __restrict__ tiles,
   const Tile t = tiles[blockIdx.x];
   const Inst& I = insts[t.inst];
   const int nx = I.nx, ny = I.ny;
-  const double* __restrict__ ph = src == 1 ? I.phi_a : I.phi_b;
+  const CDI_GLOBAL double* __restrict__ ph = src == 1 ? I.phi_a : I.phi_b;
   const bool zero = I.pcg->zero_rhs != 0;
   const double xmean = I.pcg->xmean;
   ProjIn v[WR];
@@ -709,7 +709,7 @@ __global__ void __launch_bounds__(kNT) k_mg_down(const Tile* __restrict__ tiles,
   const double alpha = upd ? I.pcg->alpha : 0.0;
   // level-0 residual: read the previous buffer when updating, write the current one
   const double* __restrict__ rin = (upd ? (rsel ? I.rr : I.rr2) : (rsel ? I.rr2 : I.rr));
-  double* __restrict__ rout = rsel ? I.rr2 : I.rr;
+  CDI_GLOBAL double* __restrict__ rout = rsel ? I.rr2 : I.rr;
   // Every global read of the thread (coefficients, right-hand side and, with
   // the CG update, q, x, d) is issued before the first LDS store, so a block
   // waits for one memory latency, not one per loop trip.  Rows outside the
@@ -734,7 +734,7 @@ __global__ void __launch_bounds__(kNT) k_mg_down(const Tile* __restrict__ tiles,
     ayl[e] = (k < (RY + 1) * RX && j >= 0 && j <= ny)
                  ? ldS<S>(L.ay, (size_t)j * nx + wrap_any(i0 - H + ri, nx)) : S(0);
   }
-  const double* __restrict__ dvec = parity ? I.d1 : I.d0;
+  const CDI_GLOBAL double* __restrict__ dvec = parity ? I.d1 : I.d0;
   const double* __restrict__ qv = I.q;
   double* __restrict__ xv = I.x;
   double rl[NPT], ql[NPT], xl[NPT], dl[NPT];
@@ -832,7 +832,7 @@ __global__ void __launch_bounds__(kNT) k_mg_down(const Tile* __restrict__ tiles,
   for (int k = threadIdx.x; k < FX * FY; k += kNT) {
     const int ty = k / FX, tx = k - ty * FX;
     const int j = j0 + ty, i = i0 + tx;
-    if (j < ny && i < nx) ((S*)L.z)[(size_t)j * nx + i] = s_z[(ty + H) * RX + (tx + H)];
+    if (j < ny && i < nx) (gas<S>(L.z))[(size_t)j * nx + i] = s_z[(ty + H) * RX + (tx + H)];
   }
   // residual r - K z on the tile + halo 1: into registers, then (after every
   // thread's reads of s_r) into s_rp = s_r
@@ -882,7 +882,7 @@ __global__ void __launch_bounds__(kNT) k_mg_down(const Tile* __restrict__ tiles,
       for (int dx = 0; dx < 4; ++dx) row += wx[dx] * s_rp[pj * PX + 2 * cx + dx];
       acc += wy[dy] * row;
     }
-    ((S*)C.r)[(size_t)J * C.nx + Ic] = S(0.25) * acc;
+    (gas<S>(C.r))[(size_t)J * C.nx + Ic] = S(0.25) * acc;
   }
   if (upd && arrive_last(I.counters + 3 * kCounterStride, L.ntiles, t.local)) {
     double ss[2];
@@ -959,7 +959,7 @@ __global__ void __launch_bounds__(kNT) k_mg_up(const Tile* __restrict__ tiles,
   }
   // the finished correction of the coarser level: zo where this kernel
   // produced it, z where the one-block coarse kernel did (level lg)
-  const S* __restrict__ ec = (const S*)(level + 1 < I.lg ? C.zo : C.z);
+  const S* __restrict__ ec = (level + 1 < I.lg ? gas<const S>(C.zo) : gas<const S>(C.z));
 #pragma unroll
   for (int e = 0; e < NE; ++e) {
     const int k = threadIdx.x + e * kNT;
@@ -968,7 +968,7 @@ __global__ void __launch_bounds__(kNT) k_mg_up(const Tile* __restrict__ tiles,
     el[e] = (k < EY * EX && J >= 0 && J < C.ny)
                 ? ec[(size_t)J * C.nx + wrap_any(Ib + ci, C.nx)] : S(0);
   }
-  const double* __restrict__ rin = rsel ? I.rr2 : I.rr;
+  const CDI_GLOBAL double* __restrict__ rin = rsel ? I.rr2 : I.rr;
 #pragma unroll
   for (int e = 0; e < NPT; ++e) {
     const int k = threadIdx.x + e * kNT;
@@ -1047,7 +1047,7 @@ __global__ void __launch_bounds__(kNT) k_mg_up(const Tile* __restrict__ tiles,
       const int k = threadIdx.x + e * kNT;
       const int ty = k / FX, tx = k - ty * FX;
       const int j = j0 + ty, i = i0 + tx;
-      if (j < ny && i < nx) ((S*)L.zo)[(size_t)j * nx + i] = s_z[(ty + H) * RX + (tx + H)];
+      if (j < ny && i < nx) (gas<S>(L.zo))[(size_t)j * nx + i] = s_z[(ty + H) * RX + (tx + H)];
     }
     return;
   }
@@ -1445,7 +1445,7 @@ __device__ __forceinline__ void coarse_load_coef(const Inst& I, CoarseLds<S>& C,
     for (int l = I.lc; l < I.nlev; ++l) {
       const Level& L = I.lev[l];
       const int n = yf ? (L.ny + 1) * L.nx : L.nx * L.ny;
-      if (f < n) { src = (const S*)(yf ? L.ay : L.ax) + f; return true; }
+      if (f < n) { src = (yf ? gas<const S>(L.ay) : gas<const S>(L.ax)) + f; return true; }
       f -= n;
     }
     return false;
@@ -1560,10 +1560,10 @@ __device__ __forceinline__ MgView<S> mixed_view(const Inst& I, CoarseLds<S>& C, 
   const Level& L = I.lev[l];
   MgView<S> v;
   v.nx = L.nx; v.ny = L.ny;
-  v.ax = (const S*)L.ax; v.ay = (const S*)L.ay;
-  v.r = l == 0 ? r0 : (S*)L.r;
-  v.z = (S*)L.z;
-  v.t = (S*)I.mg_t;
+  v.ax = gas<const S>(L.ax); v.ay = gas<const S>(L.ay);
+  v.r = l == 0 ? r0 : gas<S>(L.r);
+  v.z = gas<S>(L.z);
+  v.t = gas<S>(I.mg_t);
   return v;
 }
 
@@ -1592,8 +1592,8 @@ __global__ void __launch_bounds__(kCoarseNT) k_mg_coarse(const Inst* __restrict_
     const Level& L0 = I.lev[0];
     const int n = L0.nx * L0.ny;
     const double alpha = I.pcg->alpha;
-    const double* __restrict__ d = parity ? I.d1 : I.d0;
-    const double* __restrict__ rin = rsel ? I.rr : I.rr2;
+    const CDI_GLOBAL double* __restrict__ d = parity ? I.d1 : I.d0;
+    const CDI_GLOBAL double* __restrict__ rin = rsel ? I.rr : I.rr2;
     double red[2] = {0.0, 0.0};
     for (int c = tid; c < n; c += kCoarseNT) {
       const double x = I.x[c] + alpha * d[c];
@@ -1616,7 +1616,7 @@ __global__ void __launch_bounds__(kCoarseNT) k_mg_coarse(const Inst* __restrict_
   static_assert(kDenseMax * 16 <= kCoarseNT, "16 threads per dense row");
   DensePart dp;
   dense_part_load(I, dp);
-  S* r0 = I.mixed ? (S*)I.mg_r0 : (S*)(void*)rcur;
+  S* r0 = I.mixed ? gas<S>(I.mg_r0) : (S*)(void*)rcur;
   auto view = [&](int l) { return mixed_view<S>(I, C, r0, l); };
   // the wide level's cells, read before the LDS levels' coefficients so
   // that the block waits for one memory latency; on level 0 the right-hand
@@ -1636,7 +1636,7 @@ __global__ void __launch_bounds__(kCoarseNT) k_mg_coarse(const Inst* __restrict_
     const Level& L = I.lev[lg];
     const int n = L.nx * L.ny;
     if (lg >= lc) {
-      coarse_load_coef<S>(I, C, coarse_view<S>(I, C, lg).r, (const S*)L.r,
+      coarse_load_coef<S>(I, C, coarse_view<S>(I, C, lg).r, gas<const S>(L.r),
                           lg == 0 ? rcur : nullptr, n);
     } else {
       coarse_load_coef<S>(I, C);
@@ -1658,7 +1658,7 @@ __global__ void __launch_bounds__(kCoarseNT) k_mg_coarse(const Inst* __restrict_
     const S* z = wide ? W.z : view(lg).z;
     if (lg > 0) {
       if (lg >= lc || wide)
-        for (int c = tid; c < n; c += kCoarseNT) ((S*)L.z)[c] = z[c];
+        for (int c = tid; c < n; c += kCoarseNT) (gas<S>(L.z))[c] = z[c];
     } else {
       double zq[1] = {0.0};
       for (int c = tid; c < n; c += kCoarseNT) {
@@ -1684,18 +1684,18 @@ template <typename S>
 __device__ __forceinline__ void mg_coef_level(const Inst& I, int l, int start, int stride) {
   const Level& F = I.lev[l - 1];
   const Level& C = I.lev[l];
-  const S* fax = (const S*)F.ax;
-  const S* fay = (const S*)F.ay;
+  const S* fax = gas<const S>(F.ax);
+  const S* fay = gas<const S>(F.ay);
   const int n = C.nx * (C.ny + 1);
   for (int c = start; c < n; c += stride) {
     const int J = c / C.nx, Ic = c - J * C.nx;
     if (J < C.ny)
-      ((S*)C.ax)[c] = (fax[(size_t)(2 * J) * F.nx + 2 * Ic] + fax[(size_t)(2 * J + 1) * F.nx + 2 * Ic]) *
+      (gas<S>(C.ax))[c] = (fax[(size_t)(2 * J) * F.nx + 2 * Ic] + fax[(size_t)(2 * J + 1) * F.nx + 2 * Ic]) *
                       S(0.125);
     S b = 0;
     if (J >= 1 && J < C.ny)
       b = (fay[(size_t)(2 * J) * F.nx + 2 * Ic] + fay[(size_t)(2 * J) * F.nx + 2 * Ic + 1]) * S(0.125);
-    ((S*)C.ay)[c] = b;
+    (gas<S>(C.ay))[c] = b;
   }
 }
 
@@ -1718,8 +1718,8 @@ __device__ __forceinline__ void coarse_inverse(const Inst& I, double* B, double*
   if (!I.cdense) return;
   const Level& L = I.lev[I.nlev - 1];
   const int nx = L.nx, ny = L.ny, n = nx * ny;
-  const S* ax = (const S*)L.ax;
-  const S* ay = (const S*)L.ay;
+  const S* ax = gas<const S>(L.ax);
+  const S* ay = gas<const S>(L.ay);
   const int tid = threadIdx.x;
   for (int k = tid; k < n * n; k += kCoarseNT) B[k] = 0.0;
   __syncthreads();

@@ -224,9 +224,9 @@ __device__ __forceinline__ void phase_prep_cell(const Tile& t, const Inst& I,
   S vnx, vny, vmu;
   prep_point<S, RX>(I, s_phi, s_psi, c, j, vnx, vny, vmu);
   const size_t o = (size_t)j * nx + i;
-  ((S*)I.nhx)[o] = vnx;
-  ((S*)I.nhy)[o] = vny;
-  ((S*)I.muc)[o] = vmu;
+  (gas<S>(I.nhx))[o] = vnx;
+  (gas<S>(I.nhy))[o] = vny;
+  (gas<S>(I.muc))[o] = vmu;
   // wall rows: extrapolate phi, psi, d psi/dy, kappa, d phi/dy to the wall (per column)
   if (j == 0 || j == ny - 1) {
     double w[5];
@@ -352,12 +352,12 @@ __device__ __forceinline__ void stage_tile(const Tile& t, const Inst& I, int k, 
   S* s_txy = L.x.f.txy;
   const int nx = I.nx, ny = I.ny;
   const int i0 = t.i0, j0 = t.j0;
-  const double* __restrict__ phs = src == 0 ? I.phi : (src == 1 ? I.phi_a : I.phi_b);
-  const double* __restrict__ us = k <= 0 ? I.u : I.us;
-  const double* __restrict__ vs = k <= 0 ? I.v : I.vs;
-  const S* __restrict__ gnx = (const S*)I.nhx;
-  const S* __restrict__ gny = (const S*)I.nhy;
-  const S* __restrict__ gmc = (const S*)I.muc;
+  const CDI_GLOBAL double* __restrict__ phs = src == 0 ? I.phi : (src == 1 ? I.phi_a : I.phi_b);
+  const CDI_GLOBAL double* __restrict__ us = k <= 0 ? I.u : I.us;
+  const CDI_GLOBAL double* __restrict__ vs = k <= 0 ? I.v : I.vs;
+  const S* __restrict__ gnx = gas<const S>(I.nhx);
+  const S* __restrict__ gny = gas<const S>(I.nhy);
+  const S* __restrict__ gmc = gas<const S>(I.muc);
 
   // operands of this thread's RK update, fetched now so that their latency
   // hides behind the LDS phases (own cell; west and south base densities)
@@ -568,7 +568,7 @@ __device__ __forceinline__ void stage_tile(const Tile& t, const Inst& I, int k, 
   if (i >= nx || j >= ny) return;
   const size_t o = (size_t)j * nx + i;
   const double* __restrict__ phn = I.phi;   // base phase field of the step
-  double* __restrict__ pdst = dst == 0 ? I.phi : (dst == 1 ? I.phi_a : I.phi_b);
+  CDI_GLOBAL double* __restrict__ pdst = dst == 0 ? I.phi : (dst == 1 ? I.phi_a : I.phi_b);
 
   // ---- phase field: L_phi = -div F, face values differenced in FP64
   const int fxo = (ty + 1) * XX + (tx + 1);   // x-face i at row j
@@ -761,10 +761,10 @@ __global__ void __launch_bounds__(kNT) k_stage_strip(const Tile* __restrict__ ti
   const int l = threadIdx.x & 63;                                   // lane = column i0 - 3 + l
   const int e = 1 + l;                                              // LDS entry of the lane
   const int nch = (min(sh, ny - js) + NW - 1) / NW;
-  const double* __restrict__ phs = src == 0 ? I.phi : (src == 1 ? I.phi_a : I.phi_b);
-  const double* __restrict__ us = k <= 0 ? I.u : I.us;
-  const double* __restrict__ vs = k <= 0 ? I.v : I.vs;
-  double* __restrict__ pdst = dst == 0 ? I.phi : (dst == 1 ? I.phi_a : I.phi_b);
+  const CDI_GLOBAL double* __restrict__ phs = src == 0 ? I.phi : (src == 1 ? I.phi_a : I.phi_b);
+  const CDI_GLOBAL double* __restrict__ us = k <= 0 ? I.u : I.us;
+  const CDI_GLOBAL double* __restrict__ vs = k <= 0 ? I.v : I.vs;
+  CDI_GLOBAL double* __restrict__ pdst = dst == 0 ? I.phi : (dst == 1 ? I.phi_a : I.phi_b);
   const int gcol = wrap_any(i0 - 3 + l, nx);   // periodic column of the lane
   // LDS row offset of grid row j of a ring of n rows whose lowest row is js - low
   auto ring = [&](int j, int low, unsigned n) { return (int)((unsigned)(j - js + low + (int)n) % n) * RW; };
