@@ -8,9 +8,10 @@ projections by multigrid-preconditioned flexible CG to a relative residual of
 1e-10.  The default workload is the seeded 64-instance ensemble of uneven
 drop and Couette grids (128x64 .. 512x256, 3.9 M cells), FP64, over its
 1000-step run: the largest single-GPU configuration of the benchmark set.
-The instances are split into two batched contexts of nearly equal size, one
-stream each, advanced together (cdi_step_concurrent): one context's kernels
-fill the GPU while the other waits on its latency-bound phases.  The same
+The instances are split into four batched contexts of nearly equal size, one
+stream each, advanced together (cdi_step_concurrent) with one tiled shape
+tuned under concurrency (cdi_tune_concurrent): one context's kernels fill the
+GPU while another waits on its latency-bound phases.  The same
 instances in one context are timed beside it (single_context).
 
 Prints one JSON line:
@@ -434,7 +435,7 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default=ENSEMBLE)
-    ap.add_argument("--groups", type=int, default=2,
+    ap.add_argument("--groups", type=int, default=4,
                     help="contexts the headline batch is split into, stepped concurrently")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--kernel", default="auto",

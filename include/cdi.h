@@ -420,6 +420,21 @@ size_t cdi_tune_bytes(const cdi_ctx* ctx);
 cdi_status cdi_tune(cdi_ctx* ctx, int32_t trial_steps, void* scratch, size_t scratch_bytes,
                     cdi_tune_info* out);
 
+/* Autotuner for contexts advanced together by cdi_step_concurrent: one tiled
+ * shape (sweep pairs, rows per thread, coarse-kernel threshold; the 12 tiled
+ * candidates of cdi_tune) for all n contexts, each candidate timed as the
+ * host wall time of `trial_steps` concurrent steps (after one warm-up step)
+ * between device synchronisations of every context's stream, and every
+ * context restored to its saved state after each candidate, as cdi_tune
+ * does.  The shape that is fastest alone is not the fastest when the
+ * contexts share the GPU.  scratch[k]: device memory of at least
+ * cdi_tune_bytes(ctxs[k]) bytes (scratch_bytes[k]); out (may be NULL) as
+ * cdi_tune (ms_per_step slots 12 and 13 are -1).  Sets the tiled launch on
+ * every context.  Synchronises every stream. */
+cdi_status cdi_tune_concurrent(cdi_ctx* const* ctxs, int32_t n, int32_t trial_steps,
+                               void* const* scratch, const size_t* scratch_bytes,
+                               cdi_tune_info* out);
+
 /* Switch the initial-guess mode (CDI_GUESS_*) of later pressure solves. */
 cdi_status cdi_set_guess(cdi_ctx* ctx, int32_t guess);
 

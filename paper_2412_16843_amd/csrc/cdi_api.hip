@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -1473,6 +1474,33 @@ static cdi_status tune_copy(cdi_ctx* c, char* scratch, bool save) {
   return CDI_OK;
 }
 
+// Host-side state a step advances (restored after every tuning candidate).
+struct HostSnap {
+  double t = 0.0;
+  long step = 0;
+  int hist = 0, pred = 0;
+  int pred_stage[4] = {0, 0, 0, 0};
+  std::vector<int> iters, conv;
+  std::vector<double> relres;
+  std::string timed;
+  explicit HostSnap(const cdi_ctx* c)
+      : t(c->t), step(c->step), hist(c->hist_steps), pred(c->pred_iters), iters(c->last_iters),
+        conv(c->last_conv), relres(c->last_relres), timed(c->timed) {
+    std::copy(c->pred_stage, c->pred_stage + 4, pred_stage);
+  }
+  // time, step and the iteration predictor (between candidates)
+  void rewind(cdi_ctx* c) const {
+    c->t = t; c->step = step; c->hist_steps = hist; c->pred_iters = pred;
+    std::copy(pred_stage, pred_stage + 4, c->pred_stage);
+  }
+  // everything (at the end)
+  void restore(cdi_ctx* c) const {
+    rewind(c);
+    c->last_iters = iters; c->last_conv = conv; c->last_relres = relres;
+    c->timed = timed;
+  }
+};
+
 constexpr long kPersistTuneCells = 16384;
 
 cdi_status cdi_tune(cdi_ctx* c, int32_t trial_steps, void* scratch, size_t scratch_bytes,
@@ -1485,15 +1513,7 @@ cdi_status cdi_tune(cdi_ctx* c, int32_t trial_steps, void* scratch, size_t scrat
   HIPCHK(hipStreamSynchronize(c->stream));
   cdi_status st = tune_copy(c, sc, true);
   if (st != CDI_OK) return st;
-  // host-side state a step advances
-  const double t0 = c->t;
-  const long step0 = c->step;
-  const int hist0 = c->hist_steps, pred0 = c->pred_iters;
-  int pred_stage0[4];
-  std::copy(c->pred_stage, c->pred_stage + 4, pred_stage0);
-  const std::vector<int> it0 = c->last_iters, conv0 = c->last_conv;
-  const std::vector<double> rel0 = c->last_relres;
-  const std::string timed0 = c->timed;
+  const HostSnap snap(c);
   c->timed.clear();
   c->wide_rows_pick = c->wide_rows;
   c->coarse_cells_pick = c->coarse_cells;
@@ -1555,14 +1575,10 @@ cdi_status cdi_tune(cdi_ctx* c, int32_t trial_steps, void* scratch, size_t scrat
     // back to the saved state for the next candidate
     cdi_status rs = tune_copy(c, sc, false);
     if (rs != CDI_OK) return rs;
-    c->t = t0; c->step = step0; c->hist_steps = hist0; c->pred_iters = pred0;
-    std::copy(pred_stage0, pred_stage0 + 4, c->pred_stage);
+    snap.rewind(c);
   }
   HIPCHK(hipStreamSynchronize(c->stream));
-  c->t = t0; c->step = step0; c->hist_steps = hist0; c->pred_iters = pred0;
-  std::copy(pred_stage0, pred_stage0 + 4, c->pred_stage);
-  c->last_iters = it0; c->last_conv = conv0; c->last_relres = rel0;
-  c->timed = timed0;
+  snap.restore(c);
   if (st != CDI_OK) {
     (void)tune_copy(c, sc, false);
     (void)hipStreamSynchronize(c->stream);
@@ -1574,6 +1590,85 @@ cdi_status cdi_tune(cdi_ctx* c, int32_t trial_steps, void* scratch, size_t scrat
   info.tile_rows = pick.rows;
   info.coarse_cells = (int32_t)pick.coarse;
   info.mg_smooth = pick.nu;
+  if (out) *out = info;
+  return CDI_OK;
+}
+
+cdi_status cdi_tune_concurrent(cdi_ctx* const* ctxs, int32_t n, int32_t trial_steps,
+                               void* const* scratch, const size_t* scratch_bytes,
+                               cdi_tune_info* out) {
+  if (!ctxs || n < 1 || !scratch || !scratch_bytes) return fail(CDI_ERR_ARG, "NULL argument or n < 1");
+  if (trial_steps < 1) return fail(CDI_ERR_ARG, "trial_steps must be >= 1");
+  for (int k = 0; k < n; ++k) {
+    if (!ctxs[k] || !scratch[k]) return fail(CDI_ERR_ARG, "ctxs[%d] or scratch[%d] is NULL", k, k);
+    for (int m = 0; m < k; ++m)
+      if (ctxs[m] == ctxs[k]) return fail(CDI_ERR_ARG, "ctxs[%d] repeats ctxs[%d]", k, m);
+    if (scratch_bytes[k] < tune_bytes(ctxs[k]))
+      return fail(CDI_ERR_ARG, "scratch[%d] too small: %zu < %zu bytes", k, scratch_bytes[k],
+                  tune_bytes(ctxs[k]));
+  }
+  auto sync_all = [&]() -> cdi_status {
+    for (int k = 0; k < n; ++k) HIPCHK(hipStreamSynchronize(ctxs[k]->stream));
+    return CDI_OK;
+  };
+  cdi_status st = sync_all();
+  if (st != CDI_OK) return st;
+  std::vector<HostSnap> snaps;
+  snaps.reserve(n);
+  for (int k = 0; k < n; ++k) {
+    if ((st = tune_copy(ctxs[k], (char*)scratch[k], true)) != CDI_OK) return st;
+    snaps.emplace_back(ctxs[k]);
+    ctxs[k]->timed.clear();
+  }
+  cdi_tune_info info{};
+  for (int q = 0; q < 14; ++q) info.ms_per_step[q] = -1.0;
+  double best = INFINITY;
+  int pick_rows = ctxs[0]->wide_rows, pick_nu = ctxs[0]->nu;
+  long pick_coarse = ctxs[0]->coarse_cells;
+  for (int v = 0; v < 2 && st == CDI_OK; ++v)
+    for (int r = 0; r < 2 && st == CDI_OK; ++r)
+      for (int q = 0; q < 3 && st == CDI_OK; ++q) {
+        const int rows = kWideRows[r], nu = v + 1;
+        const long coarse = kTuneCoarse[q];
+        for (int k = 0; k < n && st == CDI_OK; ++k) {
+          st = apply_shape(ctxs[k], rows, coarse, nu);
+          ctxs[k]->launch = CDI_LAUNCH_TILED;
+        }
+        if (st != CDI_OK) break;
+        // warm-up step (code load, iteration predictor), then the timed steps
+        cdi_status r1 = cdi_step_concurrent(ctxs, n, 1);
+        if (r1 != CDI_OK && r1 != CDI_ERR_NOCONV) { st = r1; break; }
+        if ((st = sync_all()) != CDI_OK) break;
+        const auto t0 = std::chrono::steady_clock::now();
+        r1 = cdi_step_concurrent(ctxs, n, trial_steps);
+        if (r1 != CDI_OK && r1 != CDI_ERR_NOCONV) { st = r1; break; }
+        if ((st = sync_all()) != CDI_OK) break;
+        const double per =
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count() /
+            trial_steps;
+        info.ms_per_step[v * 6 + r * 3 + q] = per;
+        info.ncand += 1;
+        if (per < best) { best = per; pick_rows = rows; pick_coarse = coarse; pick_nu = nu; }
+        for (int k = 0; k < n && st == CDI_OK; ++k) {
+          st = tune_copy(ctxs[k], (char*)scratch[k], false);
+          snaps[k].rewind(ctxs[k]);
+        }
+      }
+  for (int k = 0; k < n; ++k) {
+    if (st != CDI_OK) (void)tune_copy(ctxs[k], (char*)scratch[k], false);
+    snaps[k].restore(ctxs[k]);
+  }
+  cdi_status ss = sync_all();
+  if (st != CDI_OK) return st;
+  if (ss != CDI_OK) return ss;
+  for (int k = 0; k < n; ++k) {
+    if ((st = apply_shape(ctxs[k], pick_rows, pick_coarse, pick_nu)) != CDI_OK) return st;
+    ctxs[k]->launch = CDI_LAUNCH_TILED;
+  }
+  info.launch = CDI_LAUNCH_TILED;
+  info.tile_rows = pick_rows;
+  info.coarse_cells = (int32_t)pick_coarse;
+  info.mg_smooth = pick_nu;
   if (out) *out = info;
   return CDI_OK;
 }

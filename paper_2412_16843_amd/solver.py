@@ -282,9 +282,11 @@ class EnsembleSolver:
 
     Arguments as CDISolver (lists of parameter objects and phase fields);
     instance k of the argument lists keeps index k in diagnostics / state.
+    groups: 4 by default -- the HIP runtime gives a process 4 hardware queues,
+    and streams beyond that share queues and serialise.
     """
 
-    def __init__(self, params, phi0, groups: int = 2, device: str = "cuda:0", u0=None, v0=None,
+    def __init__(self, params, phi0, groups: int = 4, device: str = "cuda:0", u0=None, v0=None,
                  **kw):
         if not torch.cuda.is_available():
             raise RuntimeError("EnsembleSolver needs a GPU (the HIP library has no CPU path)")
@@ -314,9 +316,27 @@ class EnsembleSolver:
         return L.check(self.lib.cdi_step_concurrent(self._ctxs, len(self.solvers), int(nsteps)),
                        allow=(-4,) if allow_noconv else ())
 
-    def tune(self, trial_steps: int = 10) -> List[Dict]:
-        """Autotune each context alone (launch form and tile shape)."""
-        return [s.tune(trial_steps) for s in self.solvers]
+    def tune(self, trial_steps: int = 10) -> Dict:
+        """One tiled shape for all contexts, timed with every context
+        stepping at once (cdi_tune_concurrent); the state is restored."""
+        n = len(self.solvers)
+        nbytes = [self.lib.cdi_tune_bytes(s.ctx) for s in self.solvers]
+        bufs = [torch.empty(b + 256, dtype=torch.uint8, device=self.device) for b in nbytes]
+        ptrs = (C.c_void_p * n)(*[t.data_ptr() + (-t.data_ptr()) % 256 for t in bufs])
+        sizes = (C.c_size_t * n)(*nbytes)
+        info = L.cdi_tune_info()
+        torch.cuda.synchronize(self.device)
+        L.check(self.lib.cdi_tune_concurrent(self._ctxs, n, int(trial_steps), ptrs, sizes,
+                                             C.byref(info)))
+        torch.cuda.synchronize(self.device)
+        del bufs
+        ms = {}
+        for v, nu in enumerate((1, 2)):
+            for r, rows in enumerate((1, 4)):
+                for q, cc in enumerate((1024, 4096, 16384)):
+                    ms[f"tiled_nu{nu}_rows{rows}_coarse{cc}"] = info.ms_per_step[v * 6 + r * 3 + q]
+        return dict(launch="tiled", tile_rows=info.tile_rows, coarse_cells=info.coarse_cells,
+                    mg_smooth=info.mg_smooth, ms_per_step=ms)
 
     def diagnostics(self, idx: int = 0) -> Dict[str, float]:
         g, j = self.where[idx]

@@ -102,3 +102,37 @@ def test_repeated_or_null_context_is_refused_before_any_work():
     assert lib.cdi_step_concurrent(two, 1, 1) == 0
     assert s.diagnostics()["step"] == 1
     s.close()
+
+
+def test_concurrent_tune_restores_the_state_and_sets_one_shape():
+    _torch()
+    from paper_2412_16843_amd import _lib as L
+    from paper_2412_16843_amd.solver import EnsembleSolver
+    cases = _cases()
+    ens = EnsembleSolver([c.params for c in cases], [c.phi0 for c in cases], groups=2,
+                         rtol=1e-12, maxit=400)
+    ens.step(2)
+    before = [ens.state(k) for k in range(len(cases))]
+    info = ens.tune(trial_steps=2)
+    for k in range(len(cases)):
+        g = ens.state(k)
+        for f in ("phi", "u", "v", "p"):
+            assert np.array_equal(g[f], before[k][f]), (k, f)
+        assert ens.diagnostics(k)["step"] == 2
+    timed = [v for v in info["ms_per_step"].values() if v > 0]
+    assert len(timed) == 12
+    for s in ens.solvers:
+        assert s.get_launch() == "tiled"
+        assert s.get_tile_rows() == info["tile_rows"]
+        assert s.get_coarse_cells() == info["coarse_cells"]
+        assert s.get_mg_smooth() == info["mg_smooth"]
+    ens.step(1)
+    assert all(ens.diagnostics(k)["step"] == 3 for k in range(len(cases)))
+    # a scratch buffer below cdi_tune_bytes is refused before any work
+    lib = L.lib()
+    n = len(ens.solvers)
+    sizes = (C.c_size_t * n)(*[lib.cdi_tune_bytes(s.ctx) - 1 for s in ens.solvers])
+    ptrs = (C.c_void_p * n)(*[1] * n)
+    assert lib.cdi_tune_concurrent(ens._ctxs, n, 1, ptrs, sizes, None) == ERR_ARG
+    assert b"too small" in lib.cdi_last_error()
+    ens.close()
