@@ -106,7 +106,7 @@ __global__ void __launch_bounds__(kNT3) k3_psi(const Ctx3* __restrict__ C, int s
   if (g >= n) return;
   const CDI_GLOBAL double* ph = src == 0 ? C->phi : (src == 1 ? C->phi_a : C->phi_b);
   const double cl = fmin(fmax(ph[g], 0.0), 1.0);
-  C->psi[g] = C->eps * log((cl + cdi::kDeltaPsi) / (1.0 - cl + cdi::kDeltaPsi));
+  C->psi[g] = C->eps * cdi::cdi_log((cl + cdi::kDeltaPsi) / (1.0 - cl + cdi::kDeltaPsi));
 }
 
 // d/dy of q at row j of a column (one-sided second order on the wall rows)

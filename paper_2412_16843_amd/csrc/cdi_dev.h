@@ -8,6 +8,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "cdi_math.h"
+
 namespace cdi {
 
 constexpr int kMaxLevels = 14;

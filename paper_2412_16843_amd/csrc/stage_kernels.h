@@ -6,6 +6,8 @@
 // path).  The phase field, its RK accumulation, the flux differences of the
 // phi update and every reduction stay in FP64 on both paths.
 #pragma once
+#include <type_traits>
+
 #include "cdi_dev.h"
 
 namespace cdi {
@@ -121,26 +123,28 @@ struct PrepLds {
 
 // n = G/(|G| + dN) and mu_c at the centre cell of the views (grid row j) from
 // the FP64 phase field P and psi Q (one-sided rows at the walls, Sec. 4).
-template <typename S, typename VP, typename VQ>
+// INTERIOR: the caller guarantees 0 < j < ny - 1 (central rows only).
+template <typename S, bool INTERIOR = false, typename VP, typename VQ>
 __device__ __forceinline__ void prep_point_v(const Inst& I, const VP& P, const VQ& Q, int j,
                                              S& onx, S& ony, S& omu) {
   const int ny = I.ny;
+  const bool bot = !INTERIOR && j == 0, top = !INTERIOR && j == ny - 1;
   const S inv2h = (S)(0.5 * I.inv_h), inv_h2 = (S)(I.inv_h * I.inv_h);
   // normal from phi
   const S gx = ((S)P.at(0, 1) - (S)P.at(0, -1)) * inv2h;
   S gy;
-  if (j == 0) gy = (S(-3) * (S)P.at(0, 0) + S(4) * (S)P.at(1, 0) - (S)P.at(2, 0)) * inv2h;
-  else if (j == ny - 1) gy = (S(3) * (S)P.at(0, 0) - S(4) * (S)P.at(-1, 0) + (S)P.at(-2, 0)) * inv2h;
+  if (bot) gy = (S(-3) * (S)P.at(0, 0) + S(4) * (S)P.at(1, 0) - (S)P.at(2, 0)) * inv2h;
+  else if (top) gy = (S(3) * (S)P.at(0, 0) - S(4) * (S)P.at(-1, 0) + (S)P.at(-2, 0)) * inv2h;
   else gy = ((S)P.at(1, 0) - (S)P.at(-1, 0)) * inv2h;
   const S mag = sqrt(gx * gx + gy * gy) + (S)kDeltaN;
   // psi derivatives, curvature, chemical potential
   const S q0 = Q.at(0, 0), qe = Q.at(0, 1), qw = Q.at(0, -1);
   const S px = (qe - qw) * inv2h;
   S py, d2y;
-  if (j == 0) {
+  if (bot) {
     py = (S(-3) * q0 + S(4) * Q.at(1, 0) - Q.at(2, 0)) * inv2h;
     d2y = (S(2) * q0 - S(5) * Q.at(1, 0) + S(4) * Q.at(2, 0) - Q.at(3, 0)) * inv_h2;
-  } else if (j == ny - 1) {
+  } else if (top) {
     py = (S(3) * q0 - S(4) * Q.at(-1, 0) + Q.at(-2, 0)) * inv2h;
     d2y = (S(2) * q0 - S(5) * Q.at(-1, 0) + S(4) * Q.at(-2, 0) - Q.at(-3, 0)) * inv_h2;
   } else {
@@ -268,7 +272,7 @@ __device__ __forceinline__ void phase_prep_tile(const Tile& t, const Inst& I, in
     double ps = 0.0;
     if (j >= 0 && j < ny) {
       const double c = fmin(fmax(fv[e], 0.0), 1.0);
-      ps = I.eps * log((c + kDeltaPsi) / (1.0 - c + kDeltaPsi));
+      ps = I.eps * cdi_log((c + kDeltaPsi) / (1.0 - c + kDeltaPsi));
     }
     s_phi[k] = fv[e];
     s_psi[k] = (S)ps;
@@ -414,7 +418,7 @@ __device__ __forceinline__ void stage_tile(const Tile& t, const Inst& I, int k, 
       double ps = 0.0;
       if (j >= 0 && j < ny) {
         const double cl = fmin(fmax(fv[e], 0.0), 1.0);
-        ps = I.eps * log((cl + kDeltaPsi) / (1.0 - cl + kDeltaPsi));
+        ps = I.eps * cdi_log((cl + kDeltaPsi) / (1.0 - cl + kDeltaPsi));
       }
       p_phi[q] = fv[e];
       p_psi[q] = (S)ps;
@@ -774,20 +778,34 @@ __global__ void __launch_bounds__(kNT) k_stage_strip(const Tile* __restrict__ ti
   auto rfx = [&](int j) { return ring(j, 1, RFX); };
   auto rfy = [&](int j) { return ring(j, 1, RFY); };
   auto rco = [&](int j) { return ring(j, 0, RCO); };
-  auto load_phi = [&](int j) {
-    return (j >= 0 && j < ny) ? phs[(unsigned)(j * nx + gcol)] : 0.0;
+  // Row helpers take a compile-time tag: with IN (std::true_type) the caller
+  // guarantees an interior row (the chunk's rows and everything they reach
+  // lie strictly between the walls), so the row-range tests and the
+  // one-sided wall branches are compiled out.
+  auto load_phi = [&](auto in, int j) {
+    constexpr bool IN = decltype(in)::value;
+    return (IN || (j >= 0 && j < ny)) ? phs[(unsigned)(j * nx + gcol)] : 0.0;
   };
-  auto store_phi = [&](int off, int j, double f) {   // phase field and psi of row j at offset off
+  auto store_phi = [&](auto in, int off, int j, double f) {   // phase field and psi of row j at offset off
+    constexpr bool IN = decltype(in)::value;
     double ps = 0.0;
-    if (j >= 0 && j < ny) {
+    if (IN || (j >= 0 && j < ny)) {
       const double cl = fmin(fmax(f, 0.0), 1.0);
-      ps = I.eps * log((cl + kDeltaPsi) / (1.0 - cl + kDeltaPsi));
+      ps = I.eps * cdi_log((cl + kDeltaPsi) / (1.0 - cl + kDeltaPsi));
     }
     L.phi[off + e] = f;
     L.psi[off + e] = (S)ps;
   };
-  auto load_u = [&](int j) { return (j >= 0 && j < ny) ? (S)us[(unsigned)(j * nx + gcol)] : S(0); };
-  auto load_v = [&](int j) { return (j >= 0 && j <= ny) ? (S)vs[(unsigned)(j * nx + gcol)] : S(0); };
+  auto load_u = [&](auto in, int j) {
+    constexpr bool IN = decltype(in)::value;
+    return (IN || (j >= 0 && j < ny)) ? (S)us[(unsigned)(j * nx + gcol)] : S(0);
+  };
+  auto load_v = [&](auto in, int j) {
+    constexpr bool IN = decltype(in)::value;
+    return (IN || (j >= 0 && j <= ny)) ? (S)vs[(unsigned)(j * nx + gcol)] : S(0);
+  };
+  const std::false_type edge{};
+  const std::true_type inner{};
   const S gam = (S)I.pcg->gamma_step, eps = (S)I.eps, inv_h = (S)I.inv_h;
   const S drho = (S)(I.rho1 - I.rho2), rho2 = (S)I.rho2;
   const S mud = (S)(I.mu1 - I.mu2), mu2 = (S)I.mu2;
@@ -795,21 +813,23 @@ __global__ void __launch_bounds__(kNT) k_stage_strip(const Tile* __restrict__ ti
   const bool ocol = l >= 3 && l < 3 + TW && i < nx;   // the lane owns its column
 
   // one cell's n and mu_c (grid row jr, ring offsets of rows jr-3..jr+3)
-  auto prep_row = [&](int jr, const int (&po)[7], int co) {
+  auto prep_row = [&](auto in, int jr, const int (&po)[7], int co) {
+    constexpr bool IN = decltype(in)::value;
     S a1 = S(0), a2 = S(0), a3 = S(0);
-    if (jr >= 0 && jr < ny) {
+    if (IN || (jr >= 0 && jr < ny)) {
       RingView<double> P{L.phi, {}};
       RingView<S> Q{L.psi, {}};
 #pragma unroll
       for (int d = 0; d < 7; ++d) { P.off[d] = po[d] + e; Q.off[d] = po[d] + e; }
-      prep_point_v<S>(I, P, Q, jr, a1, a2, a3);
+      prep_point_v<S, IN>(I, P, Q, jr, a1, a2, a3);
     }
     L.nx[co + e] = a1; L.ny[co + e] = a2; L.mc[co + e] = a3;
   };
   // x-face flux of row jr (face i between cells i-1 and i)
-  auto xface = [&](int jr, int op, int oc, int ou, int of) {
+  auto xface = [&](auto in, int jr, int op, int oc, int ou, int of) {
+    constexpr bool IN = decltype(in)::value;
     S F = 0, m = 0;
-    if (jr >= 0 && jr < ny) {
+    if (IN || (jr >= 0 && jr < ny)) {
       const double* ph = L.phi + op + e;
       const S* nr = L.nx + oc + e;
       const S pl = (S)ph[-1], pr = (S)ph[0];
@@ -823,9 +843,10 @@ __global__ void __launch_bounds__(kNT) k_stage_strip(const Tile* __restrict__ ti
     L.fx[of + e] = F; L.mx[of + e] = m;
   };
   // y-face flux of face row f (between cell rows f-1 and f); wall faces carry no flux
-  auto yface = [&](int f, int opb, int opt, int ocb, int oct, int ou, int of) {
+  auto yface = [&](auto in, int f, int opb, int opt, int ocb, int oct, int ou, int of) {
+    constexpr bool IN = decltype(in)::value;
     S F = 0, m = 0;
-    if (f >= 1 && f <= ny - 1) {
+    if (IN || (f >= 1 && f <= ny - 1)) {
       const S pb = (S)L.phi[opb + e], pt = (S)L.phi[opt + e];
       const S pfc = S(0.5) * (pb + pt);
       const S nf = S(0.5) * (L.ny[ocb + e] + L.ny[oct + e]);
@@ -837,9 +858,10 @@ __global__ void __launch_bounds__(kNT) k_stage_strip(const Tile* __restrict__ ti
     L.fy[of + e] = F; L.my[of + e] = m;
   };
   // corner shear stress at (row jcr, column i): interior mu4 (du/dy + dv/dx); walls GNBC
-  auto corner = [&](int jcr, int opb, int opt, int oub, int out, int oco) {
+  auto corner = [&](auto in, int jcr, int opb, int opt, int oub, int out, int oco) {
+    constexpr bool IN = decltype(in)::value;
     S tau = 0;
-    if (jcr >= 1 && jcr <= ny - 1) {
+    if (IN || (jcr >= 1 && jcr <= ny - 1)) {
       const double* pT = L.phi + opt + e;   // cell (jcr, i)
       const double* pB = L.phi + opb + e;
       const S mu4 = S(0.25) * ((mud * (S)pB[0] + mu2) + (mud * (S)pB[-1] + mu2) +
@@ -847,15 +869,17 @@ __global__ void __launch_bounds__(kNT) k_stage_strip(const Tile* __restrict__ ti
       const S dudy = (L.u[out + e] - L.u[oub + e]) * inv_h;
       const S dvdx = (L.v[out + e] - L.v[out + e - 1]) * inv_h;
       tau = mu4 * (dudy + dvdx);
-    } else if ((jcr == 0 || jcr == ny) && i <= nx) {
-      const int wall = jcr == 0 ? 0 : 1;
-      const int urow = wall == 0 ? 0 : ny - 1;
-      const double ur = (double)L.u[ru(urow) + e];
-      double uY, usl;
-      tau = (S)gnbc_corner_w(I, L.wall, RW, wall, e - 1, e, ur, uY, usl);
-      if (write_wall && ocol) {
-        I.uY[wall * nx + i] = uY;
-        I.uslip[wall * nx + i] = usl;
+    } else if constexpr (!IN) {
+      if ((jcr == 0 || jcr == ny) && i <= nx) {
+        const int wall = jcr == 0 ? 0 : 1;
+        const int urow = wall == 0 ? 0 : ny - 1;
+        const double ur = (double)L.u[ru(urow) + e];
+        double uY, usl;
+        tau = (S)gnbc_corner_w(I, L.wall, RW, wall, e - 1, e, ur, uY, usl);
+        if (write_wall && ocol) {
+          I.uY[wall * nx + i] = uY;
+          I.uslip[wall * nx + i] = usl;
+        }
       }
     }
     L.txy[oco + e] = tau;
@@ -865,21 +889,22 @@ __global__ void __launch_bounds__(kNT) k_stage_strip(const Tile* __restrict__ ti
   // cell; west and south base densities) of the next chunk, and the phase
   // field, u and v rows of the chunk after it.
   struct Pre { double acc[3], phn, phw, phs, u, v; };
-  auto load_pre = [&](int j, Pre& p) {
+  auto load_pre = [&](auto in, int j, Pre& p) {
+    constexpr bool IN = decltype(in)::value;
     p.acc[0] = p.acc[1] = p.acc[2] = p.phn = p.phw = p.phs = p.u = p.v = 0.0;
-    if (ocol && j < ny && k >= 0) {
+    if (ocol && (IN || j < ny) && k >= 0) {
       const unsigned o = (unsigned)(j * nx + i);
-      const double* __restrict__ phn0 = I.phi;
+      const CDI_GLOBAL double* __restrict__ phn0 = I.phi;
       if (k > 0) { p.acc[0] = I.acc_phi[o]; p.acc[1] = I.acc_mx[o]; p.acc[2] = I.acc_my[o]; }
       p.phn = phn0[o];
       p.phw = phn0[(unsigned)(j * nx + wrap(i - 1, nx))];
-      if (j >= 1) p.phs = phn0[o - nx];
+      if (IN || j >= 1) p.phs = phn0[o - nx];
       p.u = I.u[o];
       p.v = I.v[o];
     }
   };
   Pre cur, nxt;
-  load_pre(js + w, cur);
+  load_pre(edge, js + w, cur);
   // first chunk: phase field rows js-3..js+NW+1, u / v rows js-1..js+NW
   {
     double f[2];
@@ -887,26 +912,26 @@ __global__ void __launch_bounds__(kNT) k_stage_strip(const Tile* __restrict__ ti
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       const int rf = w + q * NW, ru_ = w + q * NW;
-      f[q] = rf < NW + 5 ? load_phi(js - 3 + rf) : 0.0;
+      f[q] = rf < NW + 5 ? load_phi(edge, js - 3 + rf) : 0.0;
       a[q] = b[q] = S(0);
-      if (ru_ < NW + 2) { a[q] = load_u(js - 1 + ru_); b[q] = load_v(js - 1 + ru_); }
+      if (ru_ < NW + 2) { a[q] = load_u(edge, js - 1 + ru_); b[q] = load_v(edge, js - 1 + ru_); }
     }
-    const double f2 = w == 0 ? load_phi(js - 3 + 2 * NW) : 0.0;
+    const double f2 = w == 0 ? load_phi(edge, js - 3 + 2 * NW) : 0.0;
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       const int rf = w + q * NW, ru_ = w + q * NW;
-      if (rf < NW + 5) store_phi(rp(js - 3 + rf), js - 3 + rf, f[q]);
+      if (rf < NW + 5) store_phi(edge, rp(js - 3 + rf), js - 3 + rf, f[q]);
       if (ru_ < NW + 2) { L.u[ru(js - 1 + ru_) + e] = a[q]; L.v[ru(js - 1 + ru_) + e] = b[q]; }
     }
     static_assert(NW + 5 <= 3 * NW, "first-chunk rows: at most three per wave");
-    if (w == 0 && 2 * NW < NW + 5) store_phi(rp(js - 3 + 2 * NW), js - 3 + 2 * NW, f2);
+    if (w == 0 && 2 * NW < NW + 5) store_phi(edge, rp(js - 3 + 2 * NW), js - 3 + 2 * NW, f2);
   }
   double r1phi = 0.0, r2phi = 0.0;   // phase-field row of the next chunk / the one after
   S r1u = S(0), r1v = S(0), r2u = S(0), r2v = S(0);
   if (nch > 1) {
-    r1phi = load_phi(js + NW + 2 + w);
-    r1u = load_u(js + NW + 1 + w);
-    r1v = load_v(js + NW + 1 + w);
+    r1phi = load_phi(edge, js + NW + 2 + w);
+    r1u = load_u(edge, js + NW + 1 + w);
+    r1v = load_v(edge, js + NW + 1 + w);
   }
   // ring positions of row js + w (row jc + w of each chunk as the strip advances)
   RingPos<RP> P{(w + 3) * RW};
@@ -916,36 +941,42 @@ __global__ void __launch_bounds__(kNT) k_stage_strip(const Tile* __restrict__ ti
   RingPos<RFY> FYr{(w + 1) * RW};
   RingPos<RCO> COr{w * RW};
 
-  for (int c = 0; c < nch; ++c) {
+  // One chunk.  IN: an interior chunk -- not the first of the strip, and
+  // every row it prepares, reads, loads ahead or stores (rows jc .. jc +
+  // 3 NW + 1) lies strictly between the walls.
+  auto chunk = [&](auto in, int c) {
+    constexpr bool IN = decltype(in)::value;
     const int jc = js + c * NW;
     const int j = jc + w;
-    const bool own = ocol && j < ny;
+    const bool own = ocol && (IN || j < ny);
     const unsigned o = own ? (unsigned)(j * nx + i) : 0u;
     __syncthreads();   // this chunk's phase-field, psi, u and v rows are in the rings
 
     // n and mu_c of the rows new to this chunk (row j + 1 of each wave; the
     // first chunk also rows jc-2..jc); wall quantities at a wall
-    if (c == 0) {
-      for (int r = w; r < 3; r += NW) {
-        const int jr = jc - 2 + r;
-        int po[7];
+    if constexpr (!IN) {
+      if (c == 0) {
+        for (int r = w; r < 3; r += NW) {
+          const int jr = jc - 2 + r;
+          int po[7];
 #pragma unroll
-        for (int d = 0; d < 7; ++d) po[d] = rp(jr + d - 3);
-        prep_row(jr, po, rc(jr));
+          for (int d = 0; d < 7; ++d) po[d] = rp(jr + d - 3);
+          prep_row(edge, jr, po, rc(jr));
+        }
       }
     }
     {
       const int jr = j + 1;
       int po[7];
       po[2] = P.at<0>(); po[3] = P.at<1>(); po[4] = P.at<2>();
-      if (jr == 0 || jr >= ny - 1) {   // one-sided wall rows reach three rows out
+      if (!IN && (jr == 0 || jr >= ny - 1)) {   // one-sided wall rows reach three rows out
         po[0] = P.at<-2>(); po[1] = P.at<-1>(); po[5] = P.at<3>(); po[6] = P.at<4>();
       } else {
         po[0] = po[1] = po[5] = po[6] = 0;
       }
-      prep_row(jr, po, C.at<1>());
+      prep_row(in, jr, po, C.at<1>());
     }
-    {
+    if constexpr (!IN) {
       // the wall whose corner row is new to this chunk (bottom: row 0 of the
       // first chunk of the first strip; top: row ny)
       const int cra = c == 0 ? jc : jc + 1;
@@ -969,25 +1000,27 @@ __global__ void __launch_bounds__(kNT) k_stage_strip(const Tile* __restrict__ ti
     // loads for the chunks ahead
     const bool more = c + 1 < nch;
     const int jn = jc + NW;
-    if (more) load_pre(jn + w, nxt);
+    if (more) load_pre(in, jn + w, nxt);
     if (c + 2 < nch) {
-      r2phi = load_phi(jn + NW + 2 + w);
-      r2u = load_u(jn + NW + 1 + w);
-      r2v = load_v(jn + NW + 1 + w);
+      r2phi = load_phi(in, jn + NW + 2 + w);
+      r2u = load_u(in, jn + NW + 1 + w);
+      r2v = load_v(in, jn + NW + 1 + w);
     }
 
     // fluxes and corner stresses new to this chunk: x-faces of row j, y-faces
     // of face row j + 1, corners of row j + 1 (the first chunk also x-faces of
     // row jc - 1, y-faces of rows jc - 1 and jc, corners of row jc)
-    if (c == 0 && w < 2) {
-      if (w == 0) xface(jc - 1, rp(jc - 1), rc(jc - 1), ru(jc - 1), rfx(jc - 1));
-      const int f = jc - 1 + w;
-      yface(f, rp(f - 1), rp(f), rc(f - 1), rc(f), ru(f), rfy(f));
-      if (w == 1) corner(jc, rp(jc - 1), rp(jc), ru(jc - 1), ru(jc), rco(jc));
+    if constexpr (!IN) {
+      if (c == 0 && w < 2) {
+        if (w == 0) xface(edge, jc - 1, rp(jc - 1), rc(jc - 1), ru(jc - 1), rfx(jc - 1));
+        const int f = jc - 1 + w;
+        yface(edge, f, rp(f - 1), rp(f), rc(f - 1), rc(f), ru(f), rfy(f));
+        if (w == 1) corner(edge, jc, rp(jc - 1), rp(jc), ru(jc - 1), ru(jc), rco(jc));
+      }
     }
-    xface(j, P.at<0>(), C.at<0>(), U.at<0>(), FXr.at<0>());
-    yface(j + 1, P.at<0>(), P.at<1>(), C.at<0>(), C.at<1>(), U.at<1>(), FYr.at<1>());
-    corner(j + 1, P.at<0>(), P.at<1>(), U.at<0>(), U.at<1>(), COr.at<1>());
+    xface(in, j, P.at<0>(), C.at<0>(), U.at<0>(), FXr.at<0>());
+    yface(in, j + 1, P.at<0>(), P.at<1>(), C.at<0>(), C.at<1>(), U.at<1>(), FYr.at<1>());
+    corner(in, j + 1, P.at<0>(), P.at<1>(), U.at<0>(), U.at<1>(), COr.at<1>());
     __syncthreads();
 
     if (own) {
@@ -1019,8 +1052,8 @@ __global__ void __launch_bounds__(kNT) k_stage_strip(const Tile* __restrict__ ti
       {
         const S fcE = S(0.5) * (MX[0] + MX[1]) * S(0.5) * (U0[0] + U0[1]);
         const S fcW = S(0.5) * (MX[-1] + MX[0]) * S(0.5) * (U0[-1] + U0[0]);
-        const S fcN = (j + 1 >= ny) ? S(0) : S(0.5) * (MYN[-1] + MYN[0]) * S(0.5) * (U0[0] + UN[0]);
-        const S fcS = (j == 0) ? S(0) : S(0.5) * (MY[-1] + MY[0]) * S(0.5) * (US[0] + U0[0]);
+        const S fcN = (!IN && j + 1 >= ny) ? S(0) : S(0.5) * (MYN[-1] + MYN[0]) * S(0.5) * (U0[0] + UN[0]);
+        const S fcS = (!IN && j == 0) ? S(0) : S(0.5) * (MY[-1] + MY[0]) * S(0.5) * (US[0] + U0[0]);
         const S muE = mud * (S)phr[0] + mu2, muW = mud * (S)phr[-1] + mu2;
         const S txxE = S(2) * muE * (U0[1] - U0[0]) * inv_h;
         const S txxW = S(2) * muW * (U0[0] - U0[-1]) * inv_h;
@@ -1030,7 +1063,7 @@ __global__ void __launch_bounds__(kNT) k_stage_strip(const Tile* __restrict__ ti
       }
       // ---- y-momentum at interior v[j, i]
       S Lmy = 0;
-      if (j >= 1) {
+      if (IN || j >= 1) {
         const S gN = S(0.5) * (MY[0] + MYN[0]) * S(0.5) * (V0[0] + VN[0]);
         const S gS = S(0.5) * (MYS[0] + MY[0]) * S(0.5) * (VS[0] + V0[0]);
         const S fcE = S(0.5) * (MXS[1] + MX[1]) * S(0.5) * (V0[0] + V0[1]);
@@ -1069,7 +1102,7 @@ __global__ void __launch_bounds__(kNT) k_stage_strip(const Tile* __restrict__ ti
           pdst[o] = cur.phn + I.dt * ap;
           I.mx[o] = mx0 + I.dt * am;
         }
-        if (j >= 1) {
+        if (IN || j >= 1) {
           const double rb = (r1 - r2) * cur.phs + r2;
           const double my0 = 0.5 * (rb + rcn) * cur.v;
           if (k < 3) {
@@ -1083,13 +1116,18 @@ __global__ void __launch_bounds__(kNT) k_stage_strip(const Tile* __restrict__ ti
     }
     // the next chunk's rows into the rings (slots this chunk's update does not read)
     if (more) {
-      store_phi(P.at<NW + 2>(), jn + 2 + w, r1phi);
+      store_phi(in, P.at<NW + 2>(), jn + 2 + w, r1phi);
       L.u[U.at<NW + 1>() + e] = r1u;
       L.v[U.at<NW + 1>() + e] = r1v;
     }
     cur = nxt;
     r1phi = r2phi; r1u = r2u; r1v = r2v;
     P.advance(); U.advance(); C.advance(); FXr.advance(); FYr.advance(); COr.advance();
+  };
+
+  for (int c = 0; c < nch; ++c) {
+    if (c >= 1 && js + c * NW + 3 * NW + 3 <= ny - 1) chunk(inner, c);
+    else chunk(edge, c);
   }
 }
 
