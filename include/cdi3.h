@@ -38,8 +38,9 @@ extern "C" {
  * parameters, dt / cfl, slip_model, poisson_rtol / poisson_maxit, guess =
  * CDI_GUESS_ZERO or CDI_GUESS_PREV, gamma_factor), plus the z extent and the
  * z components of the wall speeds.  base.precision must be CDI_FP64 and
- * base.mg_smooth 0 or 1.  nx, ny, nz even and >= 8; lz / nz must equal the x
- * and y spacing; nx (ny+1) nz < 2^31; the multigrid hierarchy (halving all
+ * base.mg_smooth 1 (V(1,1)) or 2 (V(2,2); also 0).  nx, ny, nz even and
+ * >= 8; lz / nz must equal the x and y spacing; nx (ny+1) nz < 2^31; the
+ * multigrid hierarchy (halving all
  * three directions while all stay even and the level has more than 1024
  * cells) must end on at most 1024 cells (else CDI_ERR_SHAPE). */
 typedef struct {
@@ -87,8 +88,12 @@ cdi_status cdi3_init(const cdi3_params* params, const cdi3_fields* fields, void*
                      size_t workspace_bytes, void* hip_stream, cdi3_ctx** out);
 
 /* Advance by nsteps RK4 steps (4 stage evaluations and 4 projections each;
- * Sec. 4).  Each pressure solve is a CG with a geometric multigrid V(1,1)
- * preconditioner; CDI_ERR_NOCONV if a solve stops at poisson_maxit,
+ * Sec. 4).  Each pressure solve is a CG with a geometric multigrid V-cycle
+ * preconditioner (base.mg_smooth red-black pairs each way), started
+ * (CDI_GUESS_PREV) from the extrapolation in time of the same RK stage's
+ * pressure through the last up to four steps (order up to cubic; the
+ * state's pressure before the first step) or from zero (CDI_GUESS_ZERO);
+ * CDI_ERR_NOCONV if a solve stops at poisson_maxit,
  * CDI_ERR_NONFINITE on a NaN / Inf residual.  Synchronises the stream (the
  * host reads each solve's residual). */
 cdi_status cdi3_step(cdi3_ctx* ctx, int32_t nsteps);

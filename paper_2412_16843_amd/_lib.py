@@ -241,8 +241,10 @@ def make_params(p, precision: str = "fp64", guess: str = "prev", rtol: float = 0
         gamma_factor=getattr(p, "gamma_factor", 0.0))
 
 
-def make_params3(p, guess: str = "prev", rtol: float = 0.0, maxit: int = 0) -> cdi3_params:
+def make_params3(p, guess: str = "prev", rtol: float = 0.0, maxit: int = 0,
+                 mg_smooth: int = 0) -> cdi3_params:
     """Marshal a 3-D parameter object (attributes as in workloads.Params3)."""
-    return cdi3_params(base=make_params(p, guess=guess, rtol=rtol, maxit=maxit), nz=p.nz, pad=0,
+    return cdi3_params(base=make_params(p, guess=guess, rtol=rtol, maxit=maxit,
+                                        mg_smooth=mg_smooth), nz=p.nz, pad=0,
                        lz=p.lz, w_wall_bot=getattr(p, "w_wall_bot", 0.0),
                        w_wall_top=getattr(p, "w_wall_top", 0.0))

@@ -1,7 +1,7 @@
 // Host side of the three-dimensional C ABI (include/cdi3.h): validation,
 // workspace layout and the stream-ordered launch sequence of one RK4 step
 // (4 stage evaluations, 4 variable-density projections by a CG with a
-// geometric multigrid V(1,1) preconditioner).
+// geometric multigrid V-cycle preconditioner).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -21,8 +21,10 @@ struct cdi3_ctx {
   hipStream_t stream = nullptr;
   double gamma = 0.0, gamma_factor = 0.0, rtol = 1e-10;
   int maxit = 200, guess = CDI_GUESS_PREV;
+  int nu = 1;                // red-black sweep pairs before and after the coarse correction
   double t = 0.0;
   int64_t step = 0;
+  int hist = 0;              // completed steps in the pressure history (<= 4)
   int last_iters = 0;
   double last_relres = 0.0;
   double* pinned = nullptr;  // host-visible scalars
@@ -66,7 +68,7 @@ cdi_status resolve3(const cdi3_params* in, Shape3& S) {
   if (p.slip_model < CDI_SLIP_1A || p.slip_model > CDI_SLIP_4B) return fail(CDI_ERR_ARG, "bad slip_model");
   if (p.precision != CDI_FP64) return fail(CDI_ERR_ARG, "the 3-D path computes in FP64 only");
   if (p.guess != CDI_GUESS_ZERO && p.guess != CDI_GUESS_PREV) return fail(CDI_ERR_ARG, "guess: zero or prev");
-  if (p.mg_smooth < 0 || p.mg_smooth > 1) return fail(CDI_ERR_ARG, "mg_smooth: 0 or 1 in 3-D");
+  if (p.mg_smooth < 0 || p.mg_smooth > 2) return fail(CDI_ERR_ARG, "mg_smooth: 0, 1 or 2 in 3-D");
   if (p.poisson_rtol < 0 || p.poisson_maxit < 0 || p.gamma_factor < 0 || p.dt < 0 || p.cfl < 0)
     return fail(CDI_ERR_ARG, "bad solver limits or time step");
   S.nx = p.nx; S.ny = p.ny; S.nz = in->nz; S.h = h;
@@ -124,6 +126,8 @@ size_t carve3(const Shape3& S, char* base, Ctx3* C) {
   c.b = take(N); c.x = take(N); c.r = take(N); c.z = take(N); c.d = take(N); c.q = take(N);
   c.part = take(5L * blocks(NV) + 16);
   c.scal = take(S_NSCAL);
+  for (int d = 0; d < 4; ++d)
+    for (int st = 0; st < 4; ++st) c.hp[d][st] = take(N);
   c.nlev = S.nlev;
   for (int l = 0; l < S.nlev; ++l) {
     Lev3& L = c.lev[l];
@@ -142,21 +146,27 @@ size_t carve3(const Shape3& S, char* base, Ctx3* C) {
   return off;
 }
 
-// One V(1,1) cycle: z = M r on level 0 (the CG residual and correction).
+// One V(nu,nu) cycle: z = M r on level 0 (the CG residual and correction);
+// nu red-black sweep pairs on the way down (the first red half-sweep from
+// zero) and nu black-red pairs on the way up.
 void vcycle(cdi3_ctx* c) {
   const Ctx3& H = c->h;
   const int nl = H.nlev;
   auto cells = [&](int l) { return (long)H.lev[l].nx * H.lev[l].ny * H.lev[l].nz; };
   for (int l = 0; l < nl - 1; ++l) {
-    k3_mg_smooth<<<blocks(cells(l)), kNT3, 0, c->stream>>>(c->d, l, 0, 1);
-    k3_mg_smooth<<<blocks(cells(l)), kNT3, 0, c->stream>>>(c->d, l, 1, 0);
+    for (int s = 0; s < c->nu; ++s) {
+      k3_mg_smooth<<<blocks(cells(l) / 2), kNT3, 0, c->stream>>>(c->d, l, 0, s == 0 ? 1 : 0);
+      k3_mg_smooth<<<blocks(cells(l) / 2), kNT3, 0, c->stream>>>(c->d, l, 1, 0);
+    }
     k3_mg_restrict<<<blocks(cells(l + 1)), kNT3, 0, c->stream>>>(c->d, l);
   }
   k3_mg_coarse<<<1, kCoarseMax3, 0, c->stream>>>(c->d, nl - 1);
   for (int l = nl - 2; l >= 0; --l) {
     k3_mg_prolong<<<blocks(cells(l)), kNT3, 0, c->stream>>>(c->d, l);
-    k3_mg_smooth<<<blocks(cells(l)), kNT3, 0, c->stream>>>(c->d, l, 1, 0);
-    k3_mg_smooth<<<blocks(cells(l)), kNT3, 0, c->stream>>>(c->d, l, 0, 0);
+    for (int s = 0; s < c->nu; ++s) {
+      k3_mg_smooth<<<blocks(cells(l) / 2), kNT3, 0, c->stream>>>(c->d, l, 1, 0);
+      k3_mg_smooth<<<blocks(cells(l) / 2), kNT3, 0, c->stream>>>(c->d, l, 0, 0);
+    }
   }
 }
 
@@ -168,8 +178,11 @@ cdi_status read_relres(cdi3_ctx* c, double& relres) {
   return CDI_OK;
 }
 
-// Pressure solve of K x = -(b - mean b) into h.x (guess: the state's p).
-cdi_status solve3(cdi3_ctx* c, int& iters, double& relres) {
+// Pressure solve of K x = -(b - mean b) into h.x for RK stage `stage`.  The
+// initial guess (CDI_GUESS_PREV): the extrapolation in time of the stage's
+// pressure through the last min(hist, 4) steps (order hist - 1, at most
+// cubic), the state's pressure before the first step; CDI_GUESS_ZERO: 0.
+cdi_status solve3(cdi3_ctx* c, int stage, int& iters, double& relres) {
   const Ctx3& H = c->h;
   const long N = (long)H.nx * H.ny * H.nz;
   const unsigned nb = blocks(N);
@@ -177,7 +190,15 @@ cdi_status solve3(cdi3_ctx* c, int& iters, double& relres) {
     const Lev3& G = H.lev[l + 1];
     k3_mg_coef<<<blocks((long)G.nx * (G.ny + 1) * G.nz), kNT3, 0, c->stream>>>(c->d, l);
   }
-  k3_pcg_init<<<nb, kNT3, 0, c->stream>>>(c->d, c->guess == CDI_GUESS_PREV ? 1 : 0);
+  const bool prev = c->guess == CDI_GUESS_PREV;
+  if (prev) {
+    Guess3 g{};
+    g.stage = stage;
+    g.q = std::min(c->hist, 4) - 1;
+    for (int d = 0; d <= g.q; ++d) g.slot[d] = (int)((c->step - 1 - d) & 3);
+    k3_guess<<<nb, kNT3, 0, c->stream>>>(c->d, g);
+  }
+  k3_pcg_init<<<nb, kNT3, 0, c->stream>>>(c->d, prev ? 1 : 0);
   k3_finalize<<<1, 1024, 0, c->stream>>>(c->d, (int)nb, 1);
   iters = 0;
   cdi_status s = read_relres(c, relres);
@@ -242,16 +263,17 @@ cdi_status step3(cdi3_ctx* c) {
     k3_finalize<<<1, 1024, 0, c->stream>>>(c->d, (int)blocks(N), 0);
     int it = 0;
     double rel = 0.0;
-    cdi_status s = solve3(c, it, rel);
+    cdi_status s = solve3(c, k, it, rel);
     if (s != CDI_OK) return s;
     c->last_iters = it;
     c->last_relres = rel;
-    k3_project<<<blocks(N), kNT3, 0, c->stream>>>(c->d, dst, tfac, k == 3);
+    k3_project<<<blocks(N), kNT3, 0, c->stream>>>(c->d, dst, tfac, k == 3, (int)(c->step & 3), k);
     HIPCHK(hipGetLastError());
     if (rel > c->rtol) return fail(CDI_ERR_NOCONV, "3-D pressure solve: relres %.3e after %d iterations", rel, it);
   }
   c->t += H.dt;
   c->step += 1;
+  c->hist = std::min(c->hist + 1, 4);
   return CDI_OK;
 }
 
@@ -298,6 +320,7 @@ cdi_status cdi3_init(const cdi3_params* params, const cdi3_fields* fields, void*
   c->gamma_factor = p.gamma_factor;
   c->rtol = p.poisson_rtol > 0 ? p.poisson_rtol : 1e-10;
   c->maxit = p.poisson_maxit > 0 ? p.poisson_maxit : 200;
+  c->nu = p.mg_smooth > 0 ? p.mg_smooth : 2;   // V(2,2) unless asked otherwise
   c->guess = p.guess;
   auto bail = [&](hipError_t e, const char* what) {
     if (c->pinned) (void)hipHostFree(c->pinned);

@@ -56,6 +56,8 @@ struct Ctx3 {
   cdi::gptr<double> b, x, r, z, d, q;
   cdi::gptr<double> part;                                    // block partials
   cdi::gptr<double> scal;                                    // S_* scalars
+  cdi::gptr<double> hp[4][4];   // [slot][RK stage] mean-free pressure of the last four steps
+                                // (ring: step n writes slot n mod 4)
   int nlev;
   Lev3 lev[kMaxLev3];
 };
@@ -583,7 +585,38 @@ __device__ __forceinline__ double applyK3(const Lev3& L, const double* __restric
   return diag * x[c] - s;
 }
 
-// x0, r0 = f - K x0 with f = -(b - mean b); partial sums of f^2, r^2.
+// Initial guess x0 of a solve into C->x: the state's pressure (q < 0), or
+// the polynomial extrapolation in time of order q (0..3) of the same RK
+// stage's pressure through the last q + 1 steps, slot[0] the newest (0: the
+// last step's pressure, 1: 2 p1 - p2, 2: 3 p1 - 3 p2 + p3, 3: 4 p1 - 6 p2 +
+// 4 p3 - p4).  Only the starting point of the solve depends on it.
+struct Guess3 {
+  int stage, q;
+  int slot[4];
+};
+__global__ void __launch_bounds__(kNT3) k3_guess(const Ctx3* __restrict__ C, Guess3 g) {
+  const long n = (long)C->nx * C->ny * C->nz;
+  const long c = (long)blockIdx.x * kNT3 + threadIdx.x;
+  if (c >= n) return;
+  if (g.q < 0) {
+    C->x[c] = C->p[c];
+    return;
+  }
+  const double p1 = C->hp[g.slot[0]][g.stage][c];
+  double x = p1;
+  if (g.q == 1) {
+    x = 2.0 * p1 - C->hp[g.slot[1]][g.stage][c];
+  } else if (g.q == 2) {
+    x = 3.0 * (p1 - C->hp[g.slot[1]][g.stage][c]) + C->hp[g.slot[2]][g.stage][c];
+  } else if (g.q == 3) {
+    const double p2 = C->hp[g.slot[1]][g.stage][c], p3 = C->hp[g.slot[2]][g.stage][c];
+    x = 4.0 * (p1 + p3) - 6.0 * p2 - C->hp[g.slot[3]][g.stage][c];
+  }
+  C->x[c] = x;
+}
+
+// r0 = f - K x0 with f = -(b - mean b); guess != 0: x0 is in C->x (k3_guess),
+// else x0 = 0.  Partial sums of f^2, r^2.
 __global__ void __launch_bounds__(kNT3) k3_pcg_init(const Ctx3* __restrict__ C, int guess) {
   const Lev3& L = C->lev[0];
   int k, j, i;
@@ -595,8 +628,7 @@ __global__ void __launch_bounds__(kNT3) k3_pcg_init(const Ctx3* __restrict__ C, 
     double r = f;
     if (guess) {
       double dg, of;
-      r = f - applyK3(L, C->p, k, j, i, dg, of);
-      C->x[c] = C->p[c];
+      r = f - applyK3(L, C->x, k, j, i, dg, of);
     } else {
       C->x[c] = 0.0;
     }
@@ -749,10 +781,12 @@ __global__ void __launch_bounds__(1024) k3_finalize(const Ctx3* __restrict__ C, 
 }
 
 // u = u* - tau grad p / rho_f on every face (v on interior y-faces); p = x -
-// mean(x) is stored as the state's pressure.  final: the new state (caller
-// u, v, w; phi copied from phi_b), else the next stage's velocity (in place).
+// mean(x) is stored as the state's pressure and, with hslot >= 0, as RK stage
+// `stage`'s entry hp[hslot] of the pressure history.  final: the new state
+// (caller u, v, w; phi copied from phi_b), else the next stage's velocity (in
+// place).
 __global__ void __launch_bounds__(kNT3) k3_project(const Ctx3* __restrict__ C, int src, double tau,
-                                                   int final_stage) {
+                                                   int final_stage, int hslot, int stage) {
   const int nx = C->nx, ny = C->ny, nz = C->nz;
   int k, j, i;
   if (!unflat3((long)blockIdx.x * kNT3 + threadIdx.x, nx, ny, nz, k, j, i)) return;
@@ -778,6 +812,7 @@ __global__ void __launch_bounds__(kNT3) k3_project(const Ctx3* __restrict__ C, i
   vo[e] = vn;                       // row 0: the wall (v = 0)
   if (j == ny - 1) vo[e + nx] = 0.0;
   C->p[c] = pc;
+  if (hslot >= 0) C->hp[hslot][stage][c] = pc;
   if (final_stage) C->phi[c] = ph[c];
 }
 
@@ -808,24 +843,29 @@ __global__ void __launch_bounds__(kNT3) k3_mg_coef(const Ctx3* __restrict__ C, i
 }
 
 // One red-black Gauss-Seidel half-sweep on level l: cells of colour
-// (i + j + k) & 1 == color take x = (r + sum a x_nb) / sum a.  zero: the
-// first half-sweep from x = 0 (colour cells r / D, the others 0).
+// (i + j + k) & 1 == color take x = (r + sum a x_nb) / sum a.  One thread per
+// pair of cells (2m, 2m + 1) of a row (the level's nx is even), updating the
+// one of the colour; zero: the first half-sweep from x = 0 (the colour cell
+// r / D, the other cell of the pair 0).
 __global__ void __launch_bounds__(kNT3) k3_mg_smooth(const Ctx3* __restrict__ C, int l, int color,
                                                      int zero) {
   const Lev3& L = C->lev[l];
-  int k, j, i;
-  if (!unflat3((long)blockIdx.x * kNT3 + threadIdx.x, L.nx, L.ny, L.nz, k, j, i)) return;
+  const int hx = L.nx >> 1;
+  const long t = (long)blockIdx.x * kNT3 + threadIdx.x;
+  if (t >= (long)hx * L.ny * L.nz) return;
+  const long row = t / hx;
+  const int m = (int)(t - row * hx);
+  const int j = (int)(row % L.ny), k = (int)(row / L.ny);
+  const int i = 2 * m + ((j + k + color) & 1);
   const unsigned c = ic3(L.nx, L.ny, k, j, i);
-  const bool mine = ((i + j + k) & 1) == color;
   if (zero) {
-    if (!mine) { L.x[c] = 0.0; return; }
     const unsigned e = iv3(L.nx, L.ny, k, j, i);
     const double D = L.ax[c] + L.ax[ic3(L.nx, L.ny, k, j, wrap3(i + 1, L.nx))] + L.az[c] +
                      L.az[ic3(L.nx, L.ny, wrap3(k + 1, L.nz), j, i)] + L.ay[e] + L.ay[e + L.nx];
     L.x[c] = L.r[c] / D;
+    L.x[c ^ 1u] = 0.0;   // the other cell of the pair (row offsets are even)
     return;
   }
-  if (!mine) return;
   double D, s;
   (void)applyK3(L, L.x, k, j, i, D, s);
   L.x[c] = (L.r[c] + s) / D;

@@ -23,7 +23,7 @@ class CDISolver3:
     (nz, ny, nx))."""
 
     def __init__(self, params, phi0, u0=None, v0=None, w0=None, guess: str = "prev",
-                 rtol: float = 1e-10, maxit: int = 0, device: str = "cuda:0"):
+                 rtol: float = 1e-10, maxit: int = 0, device: str = "cuda:0", mg_smooth: int = 0):
         self.lib = L.lib()
         self.device = torch.device(device)
         self.p = params
@@ -36,7 +36,8 @@ class CDISolver3:
         self.fields = {"phi": t(phi0, (nz, ny, nx)), "u": t(u0, (nz, ny, nx)),
                        "v": t(v0, (nz, ny + 1, nx)), "w": t(w0, (nz, ny, nx)),
                        "p": torch.zeros((nz, ny, nx), dtype=torch.float64, device=dev)}
-        self.cparams = L.make_params3(params, guess=guess, rtol=rtol, maxit=maxit)
+        self.cparams = L.make_params3(params, guess=guess, rtol=rtol, maxit=maxit,
+                                     mg_smooth=mg_smooth)
         nbytes = C.c_size_t(0)
         L.check(self.lib.cdi3_workspace_bytes(C.byref(self.cparams), C.byref(nbytes)))
         self.ws = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=dev)

@@ -203,3 +203,17 @@ def test_ensemble_split_by_size_covers_and_balances():
     ens = [c.params.nx * c.params.ny for c in W.config4(steps=1)]
     halves = [sum(ens[k] for k in p) for p in split_by_size(ens, 2)]
     assert abs(halves[0] - halves[1]) <= 0.02 * sum(halves), halves
+
+
+def test_3d_mg_smooth_validated_on_the_host():
+    """3-D multigrid smoothing: 0 (the default V(2,2)), 1 and 2 accepted, 3
+    rejected before any device work."""
+    L = _lib()
+    p = W.drop3_case(16, 8, 8).params
+    n = C.c_size_t(0)
+    for nu in (0, 1, 2):
+        cp = L.make_params3(p, mg_smooth=nu)
+        assert L.lib().cdi3_workspace_bytes(C.byref(cp), C.byref(n)) == 0
+    cp = L.make_params3(p, mg_smooth=3)
+    assert L.lib().cdi3_workspace_bytes(C.byref(cp), C.byref(n)) == -1
+    assert b"mg_smooth" in L.lib().cdi_last_error()

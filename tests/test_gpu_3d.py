@@ -154,6 +154,34 @@ def test_velocity_dependent_gamma_and_zero_guess_match_oracle():
         assert ok, (name, err)
 
 
+def test_history_guess_and_smoothing_change_only_the_iteration_count():
+    """Solves started from the cubic extrapolation of each RK stage's pressure
+    history (CDI_GUESS_PREV, four steps deep after the fourth step) and from
+    zero, with V(1,1) and V(2,2) smoothing, reach the same state; the history
+    start needs fewer iterations once the history is full."""
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2412_16843_amd.solver3 import CDISolver3
+    case = W.drop3_case(32, 16, 16, theta_eq_deg=70.0, ratio=4.0, r0=0.35)
+    runs = {}
+    for guess, nu in (("prev", 2), ("zero", 2), ("prev", 1)):
+        s = CDISolver3(case.params, case.phi0, rtol=1e-13, guess=guess, mg_smooth=nu)
+        its = []
+        for _ in range(7):
+            s.step(1)
+            its.append(s.diagnostics()["last_iters"])
+        runs[(guess, nu)] = (s.state(), its)
+        s.close()
+    ref = runs[("zero", 2)][0]
+    for key in (("prev", 2), ("prev", 1)):
+        for name in ("phi", "u", "v", "w", "p"):
+            ok, err = _close(runs[key][0][name], ref[name], 1e-9)
+            assert ok, (key, name, err)
+    assert runs[("prev", 2)][1][-1] < runs[("zero", 2)][1][-1], runs
+    assert runs[("prev", 2)][1][-1] <= runs[("prev", 1)][1][-1], runs
+
+
 def test_nonfinite_state_is_reported():
     """A NaN in the phase field makes the step return CDI_ERR_NONFINITE (the
     pressure solve sees a non-finite residual) instead of running on."""
