@@ -19,6 +19,10 @@ Prints one JSON line:
                           steps / wall time / 1e6, inputs resident in HBM,
                           timed between two device synchronisations with no
                           per-kernel instrumentation
+  step_roofline           the whole step's algorithmic bytes (stages,
+                          projections and every CG iteration each instance
+                          ran in the timed steps, cdi_cg_iterations) over
+                          the timed wall time, against 8 TB/s
   roofline                the bandwidth-bound kernel family with the most
                           device time: its algorithmic bytes per launch over
                           its average launch time (start / end timestamps of
@@ -502,12 +506,27 @@ def main():
     head.step(args.warmup)
     torch.cuda.synchronize()
     head_tuned = head.tune(trial_steps=10) if args.launch == "auto" else None
+    it0 = head.cg_iterations()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     head.step(args.steps)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     value = _cells(cases) * args.steps / elapsed / 1e6
+    # whole-step algorithmic bytes of the timed steps: every instance's
+    # stages, projections and the CG iterations it actually ran
+    it1 = head.cg_iterations()
+    cells_k = [p.nx * p.ny for p in params]
+    b = ALGO_BYTES_PER_CELL
+    per_stage = b["stage"] + b["rhs"] + b["pcg_init"] + b["project"]
+    per_iter = b["pcg_spmv"] + b["mg_down"] + b["mg_up"] + MG_COARSE_BYTES_PER_FINE_CELL
+    cell_iters = sum(c * (e1 - e0) for c, e0, e1 in zip(cells_k, it0, it1))
+    step_bytes = 4 * per_stage * _cells(cases) * args.steps + per_iter * cell_iters
+    step_gbs = step_bytes / elapsed / 1e9
+    step_roofline = {"cg_iters_per_step": round(cell_iters / (_cells(cases) * args.steps), 3),
+                     "algo_bytes_per_cell_step": round(step_bytes / (_cells(cases) * args.steps), 1),
+                     "achieved": round(step_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(step_gbs / HBM_PEAK_GBS, 4)}
     head_cfg = [{"instances": len(ix), "cells": sum(params[k].nx * params[k].ny for k in ix),
                  "launch": g.get_launch(), "tile_rows": g.get_tile_rows(),
                  "coarse_cells": g.get_coarse_cells(), "mg_smooth": g.get_mg_smooth()}
@@ -584,6 +603,7 @@ def main():
                            "launch": s.get_launch(), "tile_rows": s.get_tile_rows(),
                            "coarse_cells": coarse_cells, "mg_smooth": s.get_mg_smooth(),
                            "autotune": tuned},
+        "step_roofline": step_roofline,
         "roofline": {"bound": "hbm", "kernel": fam, "achieved": round(achieved, 2),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 5),

@@ -210,6 +210,13 @@ cdi_status cdi_step_concurrent(cdi_ctx* const* ctxs, int32_t n, int32_t nsteps);
  * zero gives p = 0 without an iteration. */
 cdi_status cdi_solve_pressure(cdi_ctx* ctx, const double* b, double* p, cdi_solve_info* info);
 
+/* CG iterations each instance has run since the context was set up
+ * (per_instance: host array of n_instances entries), every launch form,
+ * autotuning trials and redone graph steps included: with the algorithmic
+ * bytes of an iteration, the memory traffic of a run's pressure solves.
+ * Synchronises the stream. */
+cdi_status cdi_cg_iterations(cdi_ctx* ctx, int64_t* per_instance);
+
 /* Diagnostics of instance `idx` for its current state, computed on the device
  * (FP64 reductions; contact-line positions, wetted length and cap angle of
  * Sec. 5.1): mass and phase-field bounds (Sec. 2, conservation and

@@ -31,7 +31,7 @@ EXPORTS = ("cdi_workspace_bytes", "cdi_default_dt", "cdi_init", "cdi_init_batch"
            "cdi_set_mg_smooth", "cdi_get_mg_smooth", "cdi_set_extrapolation",
            "cdi_get_extrapolation", "cdi_eval_rhs_noalloc", "cdi_set_strip_rows",
            "cdi_get_strip_rows", "cdi_step_concurrent",
-           "cdi_tune_concurrent")
+           "cdi_tune_concurrent", "cdi_cg_iterations")
 EXPORTS3 = ("cdi3_workspace_bytes", "cdi3_init", "cdi3_step", "cdi3_eval_rhs", "cdi3_kappa_p",
             "cdi3_diagnostics", "cdi3_time_stage", "cdi3_destroy")
 
@@ -192,6 +192,8 @@ def lib() -> C.CDLL:
     L.cdi_tune.restype = i32
     L.cdi_tune_concurrent.argtypes = [P(vp), i32, i32, P(vp), P(C.c_size_t), P(cdi_tune_info)]
     L.cdi_tune_concurrent.restype = i32
+    L.cdi_cg_iterations.argtypes = [vp, P(C.c_int64)]
+    L.cdi_cg_iterations.restype = i32
     L.cdi_destroy.argtypes = [vp]
     L.cdi_destroy.restype = None
     L.cdi_last_error.argtypes = []

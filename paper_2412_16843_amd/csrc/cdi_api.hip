@@ -1257,6 +1257,15 @@ cdi_status cdi_eval_rhs(cdi_ctx* c, double* l_phi, double* l_mx, double* l_my, d
   return CDI_OK;
 }
 
+cdi_status cdi_cg_iterations(cdi_ctx* c, int64_t* per_instance) {
+  if (!c || !per_instance) return fail(CDI_ERR_ARG, "NULL argument");
+  cdi_status st = pcg_to_host(c);
+  if (st != CDI_OK) return st;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  for (int k = 0; k < c->B.n; ++k) per_instance[k] = c->h_pcg[k].iters_total;
+  return CDI_OK;
+}
+
 cdi_status cdi_diagnostics(cdi_ctx* c, int32_t idx, cdi_diag* out) {
   if (!c || !out) return fail(CDI_ERR_ARG, "NULL argument");
   Batch& B = c->B;

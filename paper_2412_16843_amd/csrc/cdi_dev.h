@@ -83,6 +83,8 @@ struct PcgScalars {
   int nonfinite;            // 1 once a norm of the solve was NaN or Inf (the solve stops)
   int gbase;                // guess mode of the fitted base of the learned guess (1, 3..6)
   int pad;
+  long long iters_total;    // CG iterations run since the context was set up (every launch
+                            // form, tuning trials and redone graph steps included)
 };
 
 struct Inst {

@@ -192,6 +192,7 @@ __global__ void __launch_bounds__(PNT) k_step_persistent(const Tile* __restrict_
       if (tid == 0) {
         P->bmean = bmean;
         P->iters = it;
+        P->iters_total += it;
         P->relres = relres;
         P->nonfinite = isfinite(relres) ? 0 : 1;
         P->converged = conv ? 1 : 0;

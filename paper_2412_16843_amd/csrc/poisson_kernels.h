@@ -59,14 +59,14 @@ struct RhsIn {
 __device__ __forceinline__ RhsIn rhs_load(const Inst& I, const double* __restrict__ ph, int j,
                                           int i) {
   const int nx = I.nx, ny = I.ny;
-  const size_t o = (size_t)j * nx + i;
+  const unsigned o = (unsigned)(j * nx) + i;
   const int ie = wrap(i + 1, nx), iw = wrap(i - 1, nx);
   RhsIn v;
   v.pc = ph[o];
-  v.pw = ph[(size_t)j * nx + iw];
-  v.pe = ph[(size_t)j * nx + ie];
+  v.pw = ph[(unsigned)(j * nx) + iw];
+  v.pe = ph[(unsigned)(j * nx) + ie];
   v.mxo = I.mx[o];
-  v.mxe = I.mx[(size_t)j * nx + ie];
+  v.mxe = I.mx[(unsigned)(j * nx) + ie];
   v.ps = v.myo = v.pn = v.myn = 0.0;
   if (j >= 1) { v.ps = ph[o - nx]; v.myo = I.my[o]; }
   if (j + 1 <= ny - 1) { v.pn = ph[o + nx]; v.myn = I.my[o + nx]; }
@@ -99,7 +99,7 @@ template <typename S>
 __device__ __forceinline__ double rhs_store(const Inst& I, const RhsIn& v, int j, int i,
                                             double tau) {
   const int nx = I.nx;
-  const size_t o = (size_t)j * nx + i;
+  const unsigned o = (unsigned)(j * nx) + i;
   const double r1 = I.rho1, r2 = I.rho2;
   const double rc = (r1 - r2) * v.pc + r2;
   const double rw = (r1 - r2) * v.pw + r2;
@@ -182,11 +182,11 @@ __global__ void __launch_bounds__(kNT) k_rhs(const Tile* __restrict__ tiles,
 // K x on a cell from FP64 neighbours (x periodic, wall faces omitted)
 __device__ __forceinline__ double apply_K(const Inst& I, const double* __restrict__ x, int j, int i) {
   const int nx = I.nx, ny = I.ny;
-  const size_t o = (size_t)j * nx + i;
+  const unsigned o = (unsigned)(j * nx) + i;
   const int ie = wrap(i + 1, nx), iw = wrap(i - 1, nx);
   const double xc = x[o];
-  const double aw = I.ax0[o], ae = I.ax0[(size_t)j * nx + ie];
-  double s = aw * (xc - x[(size_t)j * nx + iw]) + ae * (xc - x[(size_t)j * nx + ie]);
+  const double aw = I.ax0[o], ae = I.ax0[(unsigned)(j * nx) + ie];
+  double s = aw * (xc - x[(unsigned)(j * nx) + iw]) + ae * (xc - x[(unsigned)(j * nx) + ie]);
   if (j >= 1) s += I.ay0[o] * (xc - x[o - nx]);
   if (j + 1 < ny) s += I.ay0[o + nx] * (xc - x[o + nx]);
   return s;
@@ -199,7 +199,7 @@ __device__ __forceinline__ double apply_K(const Inst& I, const double* __restric
 // 1; 2, -1; 3, -3, 1; 4, -6, 4, -1); 2: the learned guess, the fitted
 // combination gscale * base + gscale2 * g of a base of mode gbase (one of the
 // above) and the network output g held in zf.
-__device__ __forceinline__ double base_guess(const Inst& I, int guess, int stage, size_t o) {
+__device__ __forceinline__ double base_guess(const Inst& I, int guess, int stage, unsigned o) {
   switch (guess) {
     case 1: return I.p[o];
     case 3: return I.hp[0][stage][o];
@@ -211,7 +211,7 @@ __device__ __forceinline__ double base_guess(const Inst& I, int guess, int stage
   }
 }
 
-__device__ __forceinline__ double guess_value(const Inst& I, int guess, int stage, size_t o) {
+__device__ __forceinline__ double guess_value(const Inst& I, int guess, int stage, unsigned o) {
   if (guess == 2) {
     const double b = I.pcg->gscale * base_guess(I, I.pcg->gbase, stage, o);
     const double c = I.pcg->gscale2;   // 0 when the network output was dropped
@@ -224,14 +224,14 @@ __device__ __forceinline__ double guess_value(const Inst& I, int guess, int stag
 __device__ __forceinline__ void pcg_init_cell(const Inst& I, int guess, int stage, int j, int i,
                                               double bmean, double& f, double& r) {
   const int nx = I.nx, ny = I.ny;
-  const size_t o = (size_t)j * nx + i;
+  const unsigned o = (unsigned)(j * nx) + i;
   f = -(I.b[o] - bmean);
   r = f;
   if (guess) {
     const int ie = wrap(i + 1, nx), iw = wrap(i - 1, nx);
     const double xc = guess_value(I, guess, stage, o);
-    double kx = I.ax0[o] * (xc - guess_value(I, guess, stage, (size_t)j * nx + iw)) +
-                I.ax0[(size_t)j * nx + ie] * (xc - guess_value(I, guess, stage, (size_t)j * nx + ie));
+    double kx = I.ax0[o] * (xc - guess_value(I, guess, stage, (unsigned)(j * nx) + iw)) +
+                I.ax0[(unsigned)(j * nx) + ie] * (xc - guess_value(I, guess, stage, (unsigned)(j * nx) + ie));
     if (j >= 1) kx += I.ay0[o] * (xc - guess_value(I, guess, stage, o - nx));
     if (j + 1 < ny) kx += I.ay0[o + nx] * (xc - guess_value(I, guess, stage, o + nx));
     r = f - kx;
@@ -265,7 +265,7 @@ __global__ void __launch_bounds__(kNT) k_pcg_init(const Tile* __restrict__ tiles
       const int rj = k / RX, ri = k - rj * RX;
       const int j = t.j0 - 1 + rj;
       gv[e] = (k < RY * RX && j >= 0 && j < ny)
-                  ? guess_value(I, guess, stage, (size_t)j * nx + wrap_any(t.i0 - 1 + ri, nx)) : 0.0;
+                  ? guess_value(I, guess, stage, (unsigned)(j * nx) + wrap_any(t.i0 - 1 + ri, nx)) : 0.0;
     }
 #pragma unroll
     for (int e = 0; e < NG; ++e) {
@@ -282,11 +282,11 @@ __global__ void __launch_bounds__(kNT) k_pcg_init(const Tile* __restrict__ tiles
     const int i = t.i0 + wide_tx(), j = t.j0 + wide_ty(r);
     bv[r] = aw[r] = ae[r] = as[r] = an[r] = 0.0;
     if (i < nx && j < ny) {
-      const size_t o = (size_t)j * nx + i;
+      const unsigned o = (unsigned)(j * nx) + i;
       bv[r] = I.b[o];
       if (guess) {
         aw[r] = I.ax0[o];
-        ae[r] = I.ax0[(size_t)j * nx + wrap(i + 1, nx)];
+        ae[r] = I.ax0[(unsigned)(j * nx) + wrap(i + 1, nx)];
         if (j >= 1) as[r] = I.ay0[o];
         if (j + 1 < ny) an[r] = I.ay0[o + nx];
       }
@@ -319,7 +319,7 @@ __global__ void __launch_bounds__(kNT) k_pcg_init(const Tile* __restrict__ tiles
   for (int r = 0; r < WR; ++r) {
     const int i = t.i0 + wide_tx(), j = t.j0 + wide_ty(r);
     if (i < nx && j < ny) {
-      const size_t o = (size_t)j * nx + i;
+      const unsigned o = (unsigned)(j * nx) + i;
       I.x[o] = xo[r];
       I.rr[o] = ro[r];
     }
@@ -381,7 +381,7 @@ __global__ void __launch_bounds__(kNT) k_pcg_spmv(const Tile* __restrict__ tiles
     const int j = t.j0 - 1 + rj;
     zl[e] = dl[e] = 0.0;
     if (k < RY * RX && j >= 0 && j < ny) {
-      const size_t o = (size_t)j * nx + wrap_any(t.i0 - 1 + ri, nx);
+      const unsigned o = (unsigned)(j * nx) + wrap_any(t.i0 - 1 + ri, nx);
       zl[e] = z[o];
       if (!first) dl[e] = dold[o];
     }
@@ -393,9 +393,9 @@ __global__ void __launch_bounds__(kNT) k_pcg_spmv(const Tile* __restrict__ tiles
     const int i = t.i0 + wide_tx(), j = t.j0 + wide_ty(r);
     aw[r] = ae[r] = as[r] = an[r] = rr[r] = 0.0;
     if (i < nx && j < ny) {
-      const size_t o = (size_t)j * nx + i;
+      const unsigned o = (unsigned)(j * nx) + i;
       aw[r] = I.ax0[o];
-      ae[r] = I.ax0[(size_t)j * nx + wrap(i + 1, nx)];
+      ae[r] = I.ax0[(unsigned)(j * nx) + wrap(i + 1, nx)];
       if (j >= 1) as[r] = I.ay0[o];
       if (j + 1 < ny) an[r] = I.ay0[o + nx];
       rr[r] = rv[o];
@@ -429,7 +429,7 @@ __global__ void __launch_bounds__(kNT) k_pcg_spmv(const Tile* __restrict__ tiles
   for (int r = 0; r < WR; ++r) {
     const int i = t.i0 + wide_tx(), j = t.j0 + wide_ty(r);
     if (i < nx && j < ny) {
-      const size_t o = (size_t)j * nx + i;
+      const unsigned o = (unsigned)(j * nx) + i;
       dnew[o] = dco[r];
       I.q[o] = qo[r];
     }
@@ -468,13 +468,13 @@ __global__ void __launch_bounds__(kNT) k_guess_fit(const Tile* __restrict__ tile
   for (int r = 0; r < WR; ++r) {
     const int i = t.i0 + wide_tx(), j = t.j0 + wide_ty(r);
     if (i < nx && j < ny) {
-      const size_t o = (size_t)j * nx + i;
+      const unsigned o = (unsigned)(j * nx) + i;
       const double f = -(I.b[o] - I.pcg->bmean);
       const int ie = wrap(i + 1, nx), iw = wrap(i - 1, nx);
       const double pv = base_guess(I, base, stage, o), gv = I.zf[o];
       // K applied to the base (apply_K's terms, with base values)
-      double kp = I.ax0[o] * (pv - base_guess(I, base, stage, (size_t)j * nx + iw)) +
-                  I.ax0[(size_t)j * nx + ie] * (pv - base_guess(I, base, stage, (size_t)j * nx + ie));
+      double kp = I.ax0[o] * (pv - base_guess(I, base, stage, (unsigned)(j * nx) + iw)) +
+                  I.ax0[(unsigned)(j * nx) + ie] * (pv - base_guess(I, base, stage, (unsigned)(j * nx) + ie));
       if (j >= 1) kp += I.ay0[o] * (pv - base_guess(I, base, stage, o - nx));
       if (j + 1 < ny) kp += I.ay0[o + nx] * (pv - base_guess(I, base, stage, o + nx));
       const double kg = apply_K(I, I.zf, j, i);
@@ -515,6 +515,7 @@ __device__ __forceinline__ void pcg_stop_test(PcgScalars* P, double rr, double s
   P->rr = rr;
   P->xmean = sx / n;
   P->iters += 1;
+  P->iters_total += 1;
   P->relres = sqrt(rr) / P->fnorm;
   if (!isfinite(rr)) { P->done = 1; P->nonfinite = 1; }
   else if (P->relres <= P->rtol) { P->done = 1; P->converged = 1; }
@@ -533,7 +534,7 @@ __global__ void __launch_bounds__(kNT) k_pcg_xmean(const Tile* __restrict__ tile
   double s[1] = {0.0};
   for (int r = 0; r < WR; ++r) {
     const int i = t.i0 + wide_tx(), j = t.j0 + wide_ty(r);
-    if (i < nx && j < ny) s[0] += I.x[(size_t)j * nx + i];
+    if (i < nx && j < ny) s[0] += I.x[(unsigned)(j * nx) + i];
   }
   block_sum<1>(s, sh);
   if (threadIdx.x == 0) st_agent(&I.part[t.local], s[0]);
@@ -560,10 +561,10 @@ __device__ __forceinline__ ProjIn project_load(const Inst& I, int final_stage,
                                                const double* __restrict__ ph, int stage,
                                                bool zero, int j, int i) {
   const int nx = I.nx;
-  const size_t o = (size_t)j * nx + i;
+  const unsigned o = (unsigned)(j * nx) + i;
   ProjIn v;
   v.xc = zero ? 0.0 : I.x[o];
-  v.xw = zero ? 0.0 : I.x[(size_t)j * nx + wrap(i - 1, nx)];
+  v.xw = zero ? 0.0 : I.x[(unsigned)(j * nx) + wrap(i - 1, nx)];
   v.xs = (zero || j < 1) ? 0.0 : I.x[o - nx];
   v.us = I.ustar[o];
   v.ax = I.ax0[o];
@@ -579,7 +580,7 @@ __device__ __forceinline__ void project_store(const Inst& I, const ProjIn& v, do
                                               int final_stage, int stage, bool zero,
                                               double xmean, int j, int i) {
   const int nx = I.nx;
-  const size_t o = (size_t)j * nx + i;
+  const unsigned o = (unsigned)(j * nx) + i;
   const double scale = tau * I.dt * I.h;   // tau grad(p)/rho_f = tau (p_c - p_w) h a_f
   CDI_GLOBAL double* __restrict__ uo = final_stage ? I.u : I.us;
   CDI_GLOBAL double* __restrict__ vo = final_stage ? I.v : I.vs;
@@ -627,7 +628,7 @@ __global__ void __launch_bounds__(kNT) k_project(const Tile* __restrict__ tiles,
 
 // ================================================================ multigrid
 template <typename S>
-__device__ __forceinline__ S ldS(const void* p, size_t o) { return ((const S*)p)[o]; }
+__device__ __forceinline__ S ldS(const void* p, unsigned o) { return ((const S*)p)[o]; }
 
 // One red-black Gauss-Seidel half-sweep on an LDS region of RY x RX cells
 // (coefficients s_ax with RX + 1 per row, s_ay with RX per row and RY + 1
@@ -724,7 +725,7 @@ __global__ void __launch_bounds__(kNT) k_mg_down(const Tile* __restrict__ tiles,
     const int rj = k / (RX + 1), ri = k - rj * (RX + 1);
     const int j = j0 - H + rj;
     axl[e] = (k < RY * (RX + 1) && j >= 0 && j < ny)
-                 ? ldS<S>(L.ax, (size_t)j * nx + wrap_any(i0 - H + ri, nx)) : S(0);
+                 ? ldS<S>(L.ax, (unsigned)(j * nx) + wrap_any(i0 - H + ri, nx)) : S(0);
   }
 #pragma unroll
   for (int e = 0; e < NAY; ++e) {
@@ -732,13 +733,13 @@ __global__ void __launch_bounds__(kNT) k_mg_down(const Tile* __restrict__ tiles,
     const int rj = k / RX, ri = k - rj * RX;
     const int j = j0 - H + rj;
     ayl[e] = (k < (RY + 1) * RX && j >= 0 && j <= ny)
-                 ? ldS<S>(L.ay, (size_t)j * nx + wrap_any(i0 - H + ri, nx)) : S(0);
+                 ? ldS<S>(L.ay, (unsigned)(j * nx) + wrap_any(i0 - H + ri, nx)) : S(0);
   }
   const CDI_GLOBAL double* __restrict__ dvec = parity ? I.d1 : I.d0;
   const double* __restrict__ qv = I.q;
   double* __restrict__ xv = I.x;
   double rl[NPT], ql[NPT], xl[NPT], dl[NPT];
-  size_t ol[NPT];
+  unsigned ol[NPT];
   bool inl[NPT], own[NPT];
 #pragma unroll
   for (int e = 0; e < NPT; ++e) {
@@ -747,7 +748,7 @@ __global__ void __launch_bounds__(kNT) k_mg_down(const Tile* __restrict__ tiles,
     const int j = j0 - H + rj, iu = i0 - H + ri;
     inl[e] = k < RY * RX && j >= 0 && j < ny;
     own[e] = upd && inl[e] && rj >= H && rj < H + FY && ri >= H && ri < H + FX && iu < nx;
-    ol[e] = inl[e] ? (size_t)j * nx + wrap_any(iu, nx) : 0;
+    ol[e] = inl[e] ? (unsigned)(j * nx) + wrap_any(iu, nx) : 0;
     if (level == 0) rl[e] = inl[e] ? rin[ol[e]] : 0.0;
     else rl[e] = inl[e] ? (double)ldS<S>(L.r, ol[e]) : 0.0;
     ql[e] = (upd && inl[e]) ? qv[ol[e]] : 0.0;
@@ -832,7 +833,7 @@ __global__ void __launch_bounds__(kNT) k_mg_down(const Tile* __restrict__ tiles,
   for (int k = threadIdx.x; k < FX * FY; k += kNT) {
     const int ty = k / FX, tx = k - ty * FX;
     const int j = j0 + ty, i = i0 + tx;
-    if (j < ny && i < nx) (gas<S>(L.z))[(size_t)j * nx + i] = s_z[(ty + H) * RX + (tx + H)];
+    if (j < ny && i < nx) (gas<S>(L.z))[(unsigned)(j * nx) + i] = s_z[(ty + H) * RX + (tx + H)];
   }
   // residual r - K z on the tile + halo 1: into registers, then (after every
   // thread's reads of s_r) into s_rp = s_r
@@ -882,7 +883,7 @@ __global__ void __launch_bounds__(kNT) k_mg_down(const Tile* __restrict__ tiles,
       for (int dx = 0; dx < 4; ++dx) row += wx[dx] * s_rp[pj * PX + 2 * cx + dx];
       acc += wy[dy] * row;
     }
-    (gas<S>(C.r))[(size_t)J * C.nx + Ic] = S(0.25) * acc;
+    (gas<S>(C.r))[(unsigned)(J * C.nx) + Ic] = S(0.25) * acc;
   }
   if (upd && arrive_last(I.counters + 3 * kCounterStride, L.ntiles, t.local)) {
     double ss[2];
@@ -899,8 +900,8 @@ __device__ __forceinline__ S prolong(const S* e, int cnx, int cny, int j, int i)
   const int I2 = (i & 1) ? wrap(Ic + 1, cnx) : wrap(Ic - 1, cnx);
   int J2 = (j & 1) ? J + 1 : J - 1;
   if (J2 < 0 || J2 >= cny) J2 = J;
-  const S a = e[(size_t)J * cnx + Ic], b = e[(size_t)J * cnx + I2];
-  const S c = e[(size_t)J2 * cnx + Ic], d = e[(size_t)J2 * cnx + I2];
+  const S a = e[(unsigned)(J * cnx) + Ic], b = e[(unsigned)(J * cnx) + I2];
+  const S c = e[(unsigned)(J2 * cnx) + Ic], d = e[(unsigned)(J2 * cnx) + I2];
   return S(0.5625) * a + S(0.1875) * b + S(0.1875) * c + S(0.0625) * d;
 }
 
@@ -947,7 +948,7 @@ __global__ void __launch_bounds__(kNT) k_mg_up(const Tile* __restrict__ tiles,
     const int rj = k / (RX + 1), ri = k - rj * (RX + 1);
     const int j = j0 - H + rj;
     axl[e] = (k < RY * (RX + 1) && j >= 0 && j < ny)
-                 ? ldS<S>(L.ax, (size_t)j * nx + wrap_any(i0 - H + ri, nx)) : S(0);
+                 ? ldS<S>(L.ax, (unsigned)(j * nx) + wrap_any(i0 - H + ri, nx)) : S(0);
   }
 #pragma unroll
   for (int e = 0; e < NAY; ++e) {
@@ -955,7 +956,7 @@ __global__ void __launch_bounds__(kNT) k_mg_up(const Tile* __restrict__ tiles,
     const int rj = k / RX, ri = k - rj * RX;
     const int j = j0 - H + rj;
     ayl[e] = (k < (RY + 1) * RX && j >= 0 && j <= ny)
-                 ? ldS<S>(L.ay, (size_t)j * nx + wrap_any(i0 - H + ri, nx)) : S(0);
+                 ? ldS<S>(L.ay, (unsigned)(j * nx) + wrap_any(i0 - H + ri, nx)) : S(0);
   }
   // the finished correction of the coarser level: zo where this kernel
   // produced it, z where the one-block coarse kernel did (level lg)
@@ -966,7 +967,7 @@ __global__ void __launch_bounds__(kNT) k_mg_up(const Tile* __restrict__ tiles,
     const int cj = k / EX, ci = k - cj * EX;
     const int J = Jb + cj;
     el[e] = (k < EY * EX && J >= 0 && J < C.ny)
-                ? ec[(size_t)J * C.nx + wrap_any(Ib + ci, C.nx)] : S(0);
+                ? ec[(unsigned)(J * C.nx) + wrap_any(Ib + ci, C.nx)] : S(0);
   }
   const CDI_GLOBAL double* __restrict__ rin = rsel ? I.rr2 : I.rr;
 #pragma unroll
@@ -975,7 +976,7 @@ __global__ void __launch_bounds__(kNT) k_mg_up(const Tile* __restrict__ tiles,
     const int rj = k / RX, ri = k - rj * RX;
     const int j = j0 - H + rj;
     const bool in = k < RY * RX && j >= 0 && j < ny;
-    const size_t o = in ? (size_t)j * nx + wrap_any(i0 - H + ri, nx) : 0;
+    const unsigned o = in ? (unsigned)(j * nx) + wrap_any(i0 - H + ri, nx) : 0;
     rl[e] = !in ? 0.0 : level == 0 ? rin[o] : (double)ldS<S>(L.r, o);
     zl[e] = in ? ldS<S>(L.z, o) : S(0);
   }
@@ -984,7 +985,7 @@ __global__ void __launch_bounds__(kNT) k_mg_up(const Tile* __restrict__ tiles,
     const int k = threadIdx.x + e * kNT;
     const int ty = k / FX, tx = k - ty * FX;
     const int j = j0 + ty, i = i0 + tx;
-    qt[e] = (level == 0 && j < ny && i < nx) ? I.q[(size_t)j * nx + i] : 0.0;
+    qt[e] = (level == 0 && j < ny && i < nx) ? I.q[(unsigned)(j * nx) + i] : 0.0;
   }
 #pragma unroll
   for (int e = 0; e < NAX; ++e) {
@@ -1047,7 +1048,7 @@ __global__ void __launch_bounds__(kNT) k_mg_up(const Tile* __restrict__ tiles,
       const int k = threadIdx.x + e * kNT;
       const int ty = k / FX, tx = k - ty * FX;
       const int j = j0 + ty, i = i0 + tx;
-      if (j < ny && i < nx) (gas<S>(L.zo))[(size_t)j * nx + i] = s_z[(ty + H) * RX + (tx + H)];
+      if (j < ny && i < nx) (gas<S>(L.zo))[(unsigned)(j * nx) + i] = s_z[(ty + H) * RX + (tx + H)];
     }
     return;
   }
@@ -1060,7 +1061,7 @@ __global__ void __launch_bounds__(kNT) k_mg_up(const Tile* __restrict__ tiles,
     const int j = j0 + ty, i = i0 + tx;
     if (j < ny && i < nx) {
       const S z = s_z[(ty + H) * RX + (tx + H)];
-      I.zf[(size_t)j * nx + i] = (double)z;
+      I.zf[(unsigned)(j * nx) + i] = (double)z;
       zq[0] += (double)z * qt[e];
     }
   }
@@ -1690,11 +1691,11 @@ __device__ __forceinline__ void mg_coef_level(const Inst& I, int l, int start, i
   for (int c = start; c < n; c += stride) {
     const int J = c / C.nx, Ic = c - J * C.nx;
     if (J < C.ny)
-      (gas<S>(C.ax))[c] = (fax[(size_t)(2 * J) * F.nx + 2 * Ic] + fax[(size_t)(2 * J + 1) * F.nx + 2 * Ic]) *
+      (gas<S>(C.ax))[c] = (fax[(unsigned)((2 * J) * F.nx) + 2 * Ic] + fax[(unsigned)((2 * J + 1) * F.nx) + 2 * Ic]) *
                       S(0.125);
     S b = 0;
     if (J >= 1 && J < C.ny)
-      b = (fay[(size_t)(2 * J) * F.nx + 2 * Ic] + fay[(size_t)(2 * J) * F.nx + 2 * Ic + 1]) * S(0.125);
+      b = (fay[(unsigned)((2 * J) * F.nx) + 2 * Ic] + fay[(unsigned)((2 * J) * F.nx) + 2 * Ic + 1]) * S(0.125);
     (gas<S>(C.ay))[c] = b;
   }
 }

@@ -78,6 +78,12 @@ class CDISolver:
         return L.check(self.lib.cdi_step(self.ctx, int(nsteps)),
                        allow=(-4,) if allow_noconv else ())
 
+    def cg_iterations(self) -> List[int]:
+        """CG iterations each instance has run since the context was set up."""
+        out = (C.c_int64 * self.n)()
+        L.check(self.lib.cdi_cg_iterations(self.ctx, out))
+        return list(out)
+
     def diagnostics(self, idx: int = 0) -> Dict[str, float]:
         d = L.cdi_diag()
         L.check(self.lib.cdi_diagnostics(self.ctx, idx, C.byref(d)), allow=(-5,))
@@ -341,6 +347,11 @@ class EnsembleSolver:
     def diagnostics(self, idx: int = 0) -> Dict[str, float]:
         g, j = self.where[idx]
         return self.solvers[g].diagnostics(j)
+
+    def cg_iterations(self) -> List[int]:
+        """CG iterations of every instance (argument order) since set-up."""
+        per = [s.cg_iterations() for s in self.solvers]
+        return [per[self.where[k][0]][self.where[k][1]] for k in range(self.n)]
 
     def state(self, idx: int = 0):
         g, j = self.where[idx]

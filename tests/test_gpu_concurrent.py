@@ -136,3 +136,33 @@ def test_concurrent_tune_restores_the_state_and_sets_one_shape():
     assert lib.cdi_tune_concurrent(ens._ctxs, n, 1, ptrs, sizes, None) == ERR_ARG
     assert b"too small" in lib.cdi_last_error()
     ens.close()
+
+
+def test_cg_iteration_totals_count_every_solve_in_every_form():
+    """cdi_cg_iterations: a standalone solve adds exactly its reported
+    iterations; stepping adds the iterations of every solve; and each
+    instance's total is the same alone, in a batch and in concurrent
+    contexts (the three evolve bitwise alike)."""
+    torch = _torch()
+    from paper_2412_16843_amd.solver import CDISolver, EnsembleSolver
+    cases = _cases()[:3]
+    solo = []
+    for c in cases:
+        s = CDISolver(c.params, c.phi0, rtol=1e-12, maxit=400)
+        assert s.cg_iterations() == [0]
+        s.step(3)
+        solo.append(s.cg_iterations()[0])
+        assert solo[-1] > 0
+        b = torch.as_tensor(np.random.default_rng(3).standard_normal((c.params.ny, c.params.nx)))
+        _, info = s.solve_pressure(b)
+        assert s.cg_iterations()[0] == solo[-1] + info["iterations"]
+        s.close()
+    batch = CDISolver([c.params for c in cases], [c.phi0 for c in cases], rtol=1e-12, maxit=400)
+    batch.step(3)
+    assert batch.cg_iterations() == solo
+    batch.close()
+    ens = EnsembleSolver([c.params for c in cases], [c.phi0 for c in cases], groups=2,
+                         rtol=1e-12, maxit=400)
+    ens.step(3)
+    assert ens.cg_iterations() == solo
+    ens.close()
