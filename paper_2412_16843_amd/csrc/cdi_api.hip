@@ -519,12 +519,15 @@ void launch_vcycle(cdi_ctx* c, int update, int dpar, int rsel) {
   for (int l = 0; l < B.max_lg; ++l)
     if (!B.mg[l].empty())
       timed(c, (l == 0 && update) ? "mg_down" : "mg_down_other", [&] {
-        if (c->nu == 2)
-          CDI_LAUNCH(c, (k_mg_down<S, 2>), (unsigned)B.mg[l].size(), kNT, c->d_mg[l], c->d_inst, l,
-                     update, dpar, rsel);
+        const unsigned nb = (unsigned)B.mg[l].size();
+        if (c->nu == 2 && l == 0)
+          CDI_LAUNCH(c, (k_mg_down<S, 2, true>), nb, kNT, c->d_mg[l], c->d_inst, l, update, dpar, rsel);
+        else if (c->nu == 2)
+          CDI_LAUNCH(c, (k_mg_down<S, 2, false>), nb, kNT, c->d_mg[l], c->d_inst, l, update, dpar, rsel);
+        else if (l == 0)
+          CDI_LAUNCH(c, (k_mg_down<S, 1, true>), nb, kNT, c->d_mg[l], c->d_inst, l, update, dpar, rsel);
         else
-          CDI_LAUNCH(c, (k_mg_down<S, 1>), (unsigned)B.mg[l].size(), kNT, c->d_mg[l], c->d_inst, l,
-                                                                      update, dpar, rsel);
+          CDI_LAUNCH(c, (k_mg_down<S, 1, false>), nb, kNT, c->d_mg[l], c->d_inst, l, update, dpar, rsel);
       });
   timed(c, "mg_coarse", [&] {
     CDI_LAUNCH(c, k_mg_coarse<S>, (unsigned)B.n, kCoarseNT, c->d_inst, update, dpar, rsel);
@@ -532,10 +535,15 @@ void launch_vcycle(cdi_ctx* c, int update, int dpar, int rsel) {
   for (int l = B.max_lg - 1; l >= 0; --l)
     if (!B.mg[l].empty())
       timed(c, l == 0 ? "mg_up" : "mg_up_other", [&] {
-        if (c->nu == 2)
-          CDI_LAUNCH(c, (k_mg_up<S, 2>), (unsigned)B.mg[l].size(), kNT, c->d_mg[l], c->d_inst, l, rsel);
+        const unsigned nb = (unsigned)B.mg[l].size();
+        if (c->nu == 2 && l == 0)
+          CDI_LAUNCH(c, (k_mg_up<S, 2, true>), nb, kNT, c->d_mg[l], c->d_inst, l, rsel);
+        else if (c->nu == 2)
+          CDI_LAUNCH(c, (k_mg_up<S, 2, false>), nb, kNT, c->d_mg[l], c->d_inst, l, rsel);
+        else if (l == 0)
+          CDI_LAUNCH(c, (k_mg_up<S, 1, true>), nb, kNT, c->d_mg[l], c->d_inst, l, rsel);
         else
-          CDI_LAUNCH(c, (k_mg_up<S, 1>), (unsigned)B.mg[l].size(), kNT, c->d_mg[l], c->d_inst, l, rsel);
+          CDI_LAUNCH(c, (k_mg_up<S, 1, false>), nb, kNT, c->d_mg[l], c->d_inst, l, rsel);
       });
 }
 

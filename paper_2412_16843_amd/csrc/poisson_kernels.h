@@ -653,16 +653,24 @@ __device__ __forceinline__ float mg_rcp(float d) {
 template <typename S, int RY, int RX, typename ValidF>
 __device__ __forceinline__ void lds_half_sweep(S* s_z, const S* s_r, const S* s_ax, const S* s_ay,
                                                int m, int color, const ValidF& valid) {
+  // Thread layout: thread tid takes colour cell hx of region row m + hy (tid
+  // = hy HX + hx, hy < CR) and, element by element, the same cell CR rows
+  // further down, so the index arithmetic is done once; a row's colour parity
+  // changes by CR each element (a compile-time amount).
   constexpr int HX = RX / 2;
-  constexpr int NC = (RY * HX + kNT - 1) / kNT;
+  constexpr int CR = kNT / HX;
+  constexpr int NC = (RY + CR - 1) / CR;
+  const int hy = (int)threadIdx.x / HX, hx = (int)threadIdx.x - hy * HX;
+  const bool tact = hy < CR;
+  const int p0 = (hy + m + color) & 1;
   S val[NC];
   int kk[NC];
   bool act[NC];
 #pragma unroll
   for (int e = 0; e < NC; ++e) {
-    const int h = threadIdx.x + e * kNT;
-    const int rj = m + h / HX, ri = 2 * (h % HX) + ((rj + color) & 1);
-    act[e] = h < (RY - 2 * m) * HX && ri >= m && ri < RX - m;
+    const int rj = m + hy + e * CR;
+    const int ri = 2 * hx + (p0 ^ ((e * CR) & 1));
+    act[e] = tact && rj < RY - m && ri >= m && ri < RX - m;
     kk[e] = rj * RX + ri;
     val[e] = S(0);
     if (act[e] && valid(rj)) {
@@ -680,10 +688,10 @@ __device__ __forceinline__ void lds_half_sweep(S* s_z, const S* s_r, const S* s_
 
 // Pre-smoothing from z = 0 (red z = r/D, black Gauss-Seidel), residual
 // r - K z and restriction R = P^T/4 to the next level, on one fine tile.
-// Level 0 reads the FP64 CG residual; with `update` it first applies the CG
-// step x += alpha d, r -= alpha q (d from buffer `parity`) and takes the
-// stopping test.
-template <typename S, int NU>
+// Level 0 (L0, which must equal level == 0) reads the FP64 CG residual; with
+// `update` it first applies the CG step x += alpha d, r -= alpha q (d from
+// buffer `parity`) and takes the stopping test.
+template <typename S, int NU, bool L0>
 __global__ void __launch_bounds__(kNT) k_mg_down(const Tile* __restrict__ tiles,
                                                   const Inst* __restrict__ insts, int level,
                                                   int update, int parity, int rsel) {
@@ -706,7 +714,7 @@ __global__ void __launch_bounds__(kNT) k_mg_down(const Tile* __restrict__ tiles,
   const Level& L = I.lev[level];
   const int nx = L.nx, ny = L.ny;
   const int i0 = t.i0, j0 = t.j0;
-  const bool upd = update && level == 0;
+  const bool upd = update && L0;   // L0: level == 0 (the launch's every tile)
   const double alpha = upd ? I.pcg->alpha : 0.0;
   // level-0 residual: read the previous buffer when updating, write the current one
   const double* __restrict__ rin = (upd ? (rsel ? I.rr : I.rr2) : (rsel ? I.rr2 : I.rr));
@@ -715,64 +723,73 @@ __global__ void __launch_bounds__(kNT) k_mg_down(const Tile* __restrict__ tiles,
   // the CG update, q, x, d) is issued before the first LDS store, so a block
   // waits for one memory latency, not one per loop trip.  Rows outside the
   // grid hold zeros and are never used as cells.
-  constexpr int NAX = (RY * (RX + 1) + kNT - 1) / kNT;
-  constexpr int NAY = ((RY + 1) * RX + kNT - 1) / kNT;
-  constexpr int NPT = (RY * RX + kNT - 1) / kNT;
-  S axl[NAX], ayl[NAY];
+  // Thread layout of the region loops: thread tid holds column cx of region
+  // row cy (tid = cy RX + cx, cy < CR); its element e is the cell (cy + e CR,
+  // cx), so the index arithmetic is done once and the elements step by
+  // constant strides.  The x-faces' last column (RX) is one more value per
+  // row, taken by threads tid < RY.
+  constexpr int CR = kNT / RX;
+  constexpr int NE = (RY + CR - 1) / CR;            // region rows
+  constexpr int NEY = (RY + 1 + CR - 1) / CR;       // y-face rows
+  static_assert(RY <= kNT, "one thread per row for the last x-face column");
+  const int tid = threadIdx.x;
+  const int cy = tid / RX, cx = tid - cy * RX;
+  const bool tact = cy < CR;
+  const int gi = wrap_any(i0 - H + cx, nx);          // grid column of the thread
+  const bool ocx = cx >= H && cx < H + FX && i0 - H + cx < nx;   // the column is on the tile
+  S axl[NE], ayl[NEY], axe = S(0);
 #pragma unroll
-  for (int e = 0; e < NAX; ++e) {
-    const int k = threadIdx.x + e * kNT;
-    const int rj = k / (RX + 1), ri = k - rj * (RX + 1);
-    const int j = j0 - H + rj;
-    axl[e] = (k < RY * (RX + 1) && j >= 0 && j < ny)
-                 ? ldS<S>(L.ax, (unsigned)(j * nx) + wrap_any(i0 - H + ri, nx)) : S(0);
+  for (int e = 0; e < NE; ++e) {
+    const int rj = cy + e * CR, j = j0 - H + rj;
+    axl[e] = (tact && rj < RY && j >= 0 && j < ny) ? ldS<S>(L.ax, (unsigned)(j * nx) + gi) : S(0);
+  }
+  if (tid < RY) {
+    const int j = j0 - H + tid;
+    if (j >= 0 && j < ny) axe = ldS<S>(L.ax, (unsigned)(j * nx) + wrap_any(i0 - H + RX, nx));
   }
 #pragma unroll
-  for (int e = 0; e < NAY; ++e) {
-    const int k = threadIdx.x + e * kNT;
-    const int rj = k / RX, ri = k - rj * RX;
-    const int j = j0 - H + rj;
-    ayl[e] = (k < (RY + 1) * RX && j >= 0 && j <= ny)
-                 ? ldS<S>(L.ay, (unsigned)(j * nx) + wrap_any(i0 - H + ri, nx)) : S(0);
+  for (int e = 0; e < NEY; ++e) {
+    const int rj = cy + e * CR, j = j0 - H + rj;
+    ayl[e] = (tact && rj <= RY && j >= 0 && j <= ny) ? ldS<S>(L.ay, (unsigned)(j * nx) + gi) : S(0);
   }
   const CDI_GLOBAL double* __restrict__ dvec = parity ? I.d1 : I.d0;
   const double* __restrict__ qv = I.q;
   double* __restrict__ xv = I.x;
-  double rl[NPT], ql[NPT], xl[NPT], dl[NPT];
-  unsigned ol[NPT];
-  bool inl[NPT], own[NPT];
+  double rl[NE], ql[NE], xl[NE], dl[NE];
+  unsigned ol[NE];
+  bool inl[NE], own[NE];
 #pragma unroll
-  for (int e = 0; e < NPT; ++e) {
-    const int k = threadIdx.x + e * kNT;
-    const int rj = k / RX, ri = k - rj * RX;
-    const int j = j0 - H + rj, iu = i0 - H + ri;
-    inl[e] = k < RY * RX && j >= 0 && j < ny;
-    own[e] = upd && inl[e] && rj >= H && rj < H + FY && ri >= H && ri < H + FX && iu < nx;
-    ol[e] = inl[e] ? (unsigned)(j * nx) + wrap_any(iu, nx) : 0;
-    if (level == 0) rl[e] = inl[e] ? rin[ol[e]] : 0.0;
+  for (int e = 0; e < NE; ++e) {
+    const int rj = cy + e * CR, j = j0 - H + rj;
+    inl[e] = tact && rj < RY && j >= 0 && j < ny;
+    own[e] = upd && inl[e] && ocx && rj >= H && rj < H + FY;
+    ol[e] = inl[e] ? (unsigned)(j * nx) + gi : 0;
+    if constexpr (L0) rl[e] = inl[e] ? rin[ol[e]] : 0.0;
     else rl[e] = inl[e] ? (double)ldS<S>(L.r, ol[e]) : 0.0;
     ql[e] = (upd && inl[e]) ? qv[ol[e]] : 0.0;
     xl[e] = own[e] ? xv[ol[e]] : 0.0;
     dl[e] = own[e] ? dvec[ol[e]] : 0.0;
   }
 #pragma unroll
-  for (int e = 0; e < NAX; ++e) {
-    const int k = threadIdx.x + e * kNT;
-    if (k < RY * (RX + 1)) s_ax[k] = axl[e];
+  for (int e = 0; e < NE; ++e) {
+    const int rj = cy + e * CR;
+    if (tact && rj < RY) s_ax[rj * (RX + 1) + cx] = axl[e];
   }
+  if (tid < RY) s_ax[tid * (RX + 1) + RX] = axe;
 #pragma unroll
-  for (int e = 0; e < NAY; ++e) {
-    const int k = threadIdx.x + e * kNT;
-    if (k < (RY + 1) * RX) s_ay[k] = ayl[e];
+  for (int e = 0; e < NEY; ++e) {
+    const int rj = cy + e * CR;
+    if (tact && rj <= RY) s_ay[rj * RX + cx] = ayl[e];
   }
   // residual over the region; with the CG update (level 0) the new residual
   // r - alpha q is formed once per cell from a single read of r and q, and
   // on the tile itself x += alpha d, r is stored, ||r||^2 and sum(x) summed
   double red[2] = {0.0, 0.0};
 #pragma unroll
-  for (int e = 0; e < NPT; ++e) {
-    const int k = threadIdx.x + e * kNT;
-    if (k >= RY * RX) continue;
+  for (int e = 0; e < NE; ++e) {
+    const int rj = cy + e * CR;
+    if (!tact || rj >= RY) continue;
+    const int k = rj * RX + cx;
     if (!upd) {
       s_r[k] = (S)rl[e];
       continue;
@@ -789,7 +806,7 @@ __global__ void __launch_bounds__(kNT) k_mg_down(const Tile* __restrict__ tiles,
   }
   if (upd) {
 #pragma unroll
-    for (int e = 0; e < NPT; ++e)
+    for (int e = 0; e < NE; ++e)
       if (own[e]) {
         xv[ol[e]] = xl[e];
         rout[ol[e]] = rl[e];
@@ -815,11 +832,15 @@ __global__ void __launch_bounds__(kNT) k_mg_down(const Tile* __restrict__ tiles,
   // Black cells need no start value: the first black half-sweep reads only
   // red neighbours, and every later read stays inside the part of the region
   // that an earlier half-sweep has written.
+  {
+    constexpr int CRH = kNT / HX;
+    const int hy = tid / HX, hx = tid - hy * HX;
 #pragma unroll
-  for (int e = 0; e < (RY * HX + kNT - 1) / kNT; ++e) {
-    const int h = threadIdx.x + e * kNT;
-    const int rj = h / HX, ri = 2 * (h - rj * HX) + (rj & 1);
-    if (h < RY * HX) s_z[rj * RX + ri] = valid(rj) ? s_r[rj * RX + ri] * mg_rcp(diag(rj, ri)) : S(0);
+    for (int e = 0; e < (RY + CRH - 1) / CRH; ++e) {
+      const int rj = hy + e * CRH, ri = 2 * hx + (rj & 1);
+      if (hy < CRH && rj < RY)
+        s_z[rj * RX + ri] = valid(rj) ? s_r[rj * RX + ri] * mg_rcp(diag(rj, ri)) : S(0);
+    }
   }
   __syncthreads();
   // then Gauss-Seidel half-sweeps black, red, black, ... (half-sweep sw on
@@ -837,15 +858,16 @@ __global__ void __launch_bounds__(kNT) k_mg_down(const Tile* __restrict__ tiles,
   }
   // residual r - K z on the tile + halo 1: into registers, then (after every
   // thread's reads of s_r) into s_rp = s_r
-  constexpr int NR = (PY * PX + kNT - 1) / kNT;
+  constexpr int CRP = kNT / PX;
+  constexpr int NR = (PY + CRP - 1) / CRP;
+  const int py = tid / PX, px = tid - py * PX;
   S rpl[NR];
 #pragma unroll
   for (int e = 0; e < NR; ++e) {
-    const int k = threadIdx.x + e * kNT;
+    const int pj = py + e * CRP;
     S rp = 0;
-    if (k < PY * PX) {
-      const int pj = k / PX, pi = k - pj * PX;
-      const int rj = pj + H - 1, ri = pi + H - 1;
+    if (py < CRP && pj < PY) {
+      const int rj = pj + H - 1, ri = px + H - 1;
       const int c = rj * RX + ri;
       if (valid(rj)) {
         const S aw = s_ax[rj * (RX + 1) + ri], ae = s_ax[rj * (RX + 1) + ri + 1];
@@ -860,8 +882,8 @@ __global__ void __launch_bounds__(kNT) k_mg_down(const Tile* __restrict__ tiles,
   __syncthreads();
 #pragma unroll
   for (int e = 0; e < NR; ++e) {
-    const int k = threadIdx.x + e * kNT;
-    if (k < PY * PX) s_rp[k] = rpl[e];
+    const int pj = py + e * CRP;
+    if (py < CRP && pj < PY) s_rp[pj * PX + px] = rpl[e];
   }
   __syncthreads();
   // restriction to the coarse tile
@@ -910,7 +932,7 @@ __device__ __forceinline__ S prolong(const S* e, int cnx, int cny, int j, int i)
 // writes its result to zo, never to z: the blocks of one launch read the
 // pre-smoothed z of their neighbours' cells in their halos, and a block may
 // start after its neighbour has finished.
-template <typename S, int NU>
+template <typename S, int NU, bool L0>
 __global__ void __launch_bounds__(kNT) k_mg_up(const Tile* __restrict__ tiles,
                                                 const Inst* __restrict__ insts, int level,
                                                 int rsel) {
@@ -934,86 +956,95 @@ __global__ void __launch_bounds__(kNT) k_mg_up(const Tile* __restrict__ tiles,
   const int nx = L.nx, ny = L.ny;
   const int i0 = t.i0, j0 = t.j0;
   const int Jb = ((j0 - H) >> 1) - 1, Ib = ((i0 - H) >> 1) - 1;
-  // every global read of the thread is issued before the first LDS store
-  constexpr int NAX = (RY * (RX + 1) + kNT - 1) / kNT;
-  constexpr int NAY = ((RY + 1) * RX + kNT - 1) / kNT;
-  constexpr int NPT = (RY * RX + kNT - 1) / kNT;
-  constexpr int NE = (EY * EX + kNT - 1) / kNT;
+  // every global read of the thread is issued before the first LDS store.
+  // Thread layout of the region loops: thread tid holds column cx of region
+  // row cy (tid = cy RX + cx, cy < CR) and its element e is the cell (cy + e
+  // CR, cx); the coarse-correction loops likewise over EX columns.  The
+  // x-faces' last column (RX) is one more value per row, taken by threads
+  // tid < RY.
+  constexpr int CR = kNT / RX;
+  constexpr int NP = (RY + CR - 1) / CR;            // region rows
+  constexpr int NPY = (RY + 1 + CR - 1) / CR;       // y-face rows
+  constexpr int CRE = kNT / EX;
+  constexpr int NE = (EY + CRE - 1) / CRE;
   constexpr int NQ = FX * FY / kNT;
-  S axl[NAX], ayl[NAY], el[NE], zl[NPT];
-  double rl[NPT], qt[NQ];
+  static_assert(RY <= kNT, "one thread per row for the last x-face column");
+  const int tid = threadIdx.x;
+  const int cy = tid / RX, cx = tid - cy * RX;
+  const bool tact = cy < CR;
+  const int gi = wrap_any(i0 - H + cx, nx);          // grid column of the thread
+  const int ey = tid / EX, ex = tid - ey * EX;
+  const bool eact = ey < CRE;
+  S axl[NP], ayl[NPY], el[NE], zl[NP], axe = S(0);
+  double rl[NP], qt[NQ];
 #pragma unroll
-  for (int e = 0; e < NAX; ++e) {
-    const int k = threadIdx.x + e * kNT;
-    const int rj = k / (RX + 1), ri = k - rj * (RX + 1);
-    const int j = j0 - H + rj;
-    axl[e] = (k < RY * (RX + 1) && j >= 0 && j < ny)
-                 ? ldS<S>(L.ax, (unsigned)(j * nx) + wrap_any(i0 - H + ri, nx)) : S(0);
+  for (int e = 0; e < NP; ++e) {
+    const int rj = cy + e * CR, j = j0 - H + rj;
+    axl[e] = (tact && rj < RY && j >= 0 && j < ny) ? ldS<S>(L.ax, (unsigned)(j * nx) + gi) : S(0);
+  }
+  if (tid < RY) {
+    const int j = j0 - H + tid;
+    if (j >= 0 && j < ny) axe = ldS<S>(L.ax, (unsigned)(j * nx) + wrap_any(i0 - H + RX, nx));
   }
 #pragma unroll
-  for (int e = 0; e < NAY; ++e) {
-    const int k = threadIdx.x + e * kNT;
-    const int rj = k / RX, ri = k - rj * RX;
-    const int j = j0 - H + rj;
-    ayl[e] = (k < (RY + 1) * RX && j >= 0 && j <= ny)
-                 ? ldS<S>(L.ay, (unsigned)(j * nx) + wrap_any(i0 - H + ri, nx)) : S(0);
+  for (int e = 0; e < NPY; ++e) {
+    const int rj = cy + e * CR, j = j0 - H + rj;
+    ayl[e] = (tact && rj <= RY && j >= 0 && j <= ny) ? ldS<S>(L.ay, (unsigned)(j * nx) + gi) : S(0);
   }
   // the finished correction of the coarser level: zo where this kernel
   // produced it, z where the one-block coarse kernel did (level lg)
   const S* __restrict__ ec = (level + 1 < I.lg ? gas<const S>(C.zo) : gas<const S>(C.z));
+  const int gei = wrap_any(Ib + ex, C.nx);
 #pragma unroll
   for (int e = 0; e < NE; ++e) {
-    const int k = threadIdx.x + e * kNT;
-    const int cj = k / EX, ci = k - cj * EX;
-    const int J = Jb + cj;
-    el[e] = (k < EY * EX && J >= 0 && J < C.ny)
-                ? ec[(unsigned)(J * C.nx) + wrap_any(Ib + ci, C.nx)] : S(0);
+    const int cj = ey + e * CRE, J = Jb + cj;
+    el[e] = (eact && cj < EY && J >= 0 && J < C.ny) ? ec[(unsigned)(J * C.nx) + gei] : S(0);
   }
   const CDI_GLOBAL double* __restrict__ rin = rsel ? I.rr2 : I.rr;
 #pragma unroll
-  for (int e = 0; e < NPT; ++e) {
-    const int k = threadIdx.x + e * kNT;
-    const int rj = k / RX, ri = k - rj * RX;
-    const int j = j0 - H + rj;
-    const bool in = k < RY * RX && j >= 0 && j < ny;
-    const unsigned o = in ? (unsigned)(j * nx) + wrap_any(i0 - H + ri, nx) : 0;
-    rl[e] = !in ? 0.0 : level == 0 ? rin[o] : (double)ldS<S>(L.r, o);
+  for (int e = 0; e < NP; ++e) {
+    const int rj = cy + e * CR, j = j0 - H + rj;
+    const bool in = tact && rj < RY && j >= 0 && j < ny;
+    const unsigned o = in ? (unsigned)(j * nx) + gi : 0;
+    if constexpr (L0) rl[e] = in ? rin[o] : 0.0;
+    else rl[e] = in ? (double)ldS<S>(L.r, o) : 0.0;
     zl[e] = in ? ldS<S>(L.z, o) : S(0);
   }
 #pragma unroll
   for (int e = 0; e < NQ; ++e) {   // level 0: q on the tile, for z.q
-    const int k = threadIdx.x + e * kNT;
+    const int k = tid + e * kNT;
     const int ty = k / FX, tx = k - ty * FX;
     const int j = j0 + ty, i = i0 + tx;
-    qt[e] = (level == 0 && j < ny && i < nx) ? I.q[(unsigned)(j * nx) + i] : 0.0;
+    qt[e] = (L0 && j < ny && i < nx) ? I.q[(unsigned)(j * nx) + i] : 0.0;
   }
 #pragma unroll
-  for (int e = 0; e < NAX; ++e) {
-    const int k = threadIdx.x + e * kNT;
-    if (k < RY * (RX + 1)) s_ax[k] = axl[e];
+  for (int e = 0; e < NP; ++e) {
+    const int rj = cy + e * CR;
+    if (tact && rj < RY) s_ax[rj * (RX + 1) + cx] = axl[e];
   }
+  if (tid < RY) s_ax[tid * (RX + 1) + RX] = axe;
 #pragma unroll
-  for (int e = 0; e < NAY; ++e) {
-    const int k = threadIdx.x + e * kNT;
-    if (k < (RY + 1) * RX) s_ay[k] = ayl[e];
+  for (int e = 0; e < NPY; ++e) {
+    const int rj = cy + e * CR;
+    if (tact && rj <= RY) s_ay[rj * RX + cx] = ayl[e];
   }
 #pragma unroll
   for (int e = 0; e < NE; ++e) {
-    const int k = threadIdx.x + e * kNT;
-    if (k < EY * EX) s_e[k] = el[e];
+    const int cj = ey + e * CRE;
+    if (eact && cj < EY) s_e[cj * EX + ex] = el[e];
   }
   __syncthreads();
   // z += P e (bilinear prolongation from the staged coarse correction)
+  const int iu = i0 - H + cx;                 // unwrapped grid column of the thread
+  const int cI = (iu >> 1) - Ib, cI2 = cI + ((iu & 1) ? 1 : -1);   // staged coarse columns
 #pragma unroll
-  for (int e = 0; e < NPT; ++e) {
-    const int k = threadIdx.x + e * kNT;
-    if (k >= RY * RX) continue;
-    const int rj = k / RX, ri = k - rj * RX;
-    const int j = j0 - H + rj, iu = i0 - H + ri;
+  for (int e = 0; e < NP; ++e) {
+    const int rj = cy + e * CR;
+    if (!tact || rj >= RY) continue;
+    const int j = j0 - H + rj;
     S z = 0;
     if (j >= 0 && j < ny) {
-      const int J = j >> 1, Icu = iu >> 1;   // unwrapped coarse column (floor)
-      const int cI = Icu - Ib, cI2 = cI + ((iu & 1) ? 1 : -1);
+      const int J = j >> 1;
       int J2 = (j & 1) ? J + 1 : J - 1;
       if (J2 < 0 || J2 >= C.ny) J2 = J;
       const S a = s_e[(J - Jb) * EX + cI], b = s_e[(J - Jb) * EX + cI2];
@@ -1024,9 +1055,10 @@ __global__ void __launch_bounds__(kNT) k_mg_up(const Tile* __restrict__ tiles,
   }
   __syncthreads();   // every read of s_e (= s_r) is done
 #pragma unroll
-  for (int e = 0; e < NPT; ++e) {
-    const int k = threadIdx.x + e * kNT;
-    if (k >= RY * RX) continue;
+  for (int e = 0; e < NP; ++e) {
+    const int rj = cy + e * CR;
+    if (!tact || rj >= RY) continue;
+    const int k = rj * RX + cx;
     s_r[k] = (S)rl[e];
     s_z[k] = zl[e];
   }
@@ -1042,7 +1074,7 @@ __global__ void __launch_bounds__(kNT) k_mg_up(const Tile* __restrict__ tiles,
     lds_half_sweep<S, RY, RX>(s_z, s_r, s_ax, s_ay, sw + 1, (sw & 1) ? 0 : 1 /* black first */, valid);
     __syncthreads();
   }
-  if (level != 0) {   // uniform per launch
+  if constexpr (!L0) {
 #pragma unroll
     for (int e = 0; e < NQ; ++e) {
       const int k = threadIdx.x + e * kNT;
