@@ -630,7 +630,7 @@ __global__ void __launch_bounds__(kNT) k_project(const Tile* __restrict__ tiles,
 template <typename S>
 __device__ __forceinline__ S ldS(const void* p, unsigned o) { return ((const S*)p)[o]; }
 
-// One red-black Gauss-Seidel half-sweep on an LDS region of RY x RX cells
+// One red-black Gauss-Seidel half-sweep (m >= 1) on an LDS region of RY x RX cells
 // (coefficients s_ax with RX + 1 per row, s_ay with RX per row and RY + 1
 // rows): the cells of colour `color` ((rj + ri) & 1) in rows and columns
 // [m, RY - m) x [m, RX - m), 0 on rows outside the grid.  A cell of one colour
@@ -659,7 +659,7 @@ __device__ __forceinline__ void lds_half_sweep(S* s_z, const S* s_r, const S* s_
   // changes by CR each element (a compile-time amount).
   constexpr int HX = RX / 2;
   constexpr int CR = kNT / HX;
-  constexpr int NC = (RY + CR - 1) / CR;
+  constexpr int NC = (RY - 2 + CR - 1) / CR;   // rows m .. RY - m - 1, m >= 1
   const int hy = (int)threadIdx.x / HX, hx = (int)threadIdx.x - hy * HX;
   const bool tact = hy < CR;
   const int p0 = (hy + m + color) & 1;
