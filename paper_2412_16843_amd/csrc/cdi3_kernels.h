@@ -70,13 +70,29 @@ __device__ __forceinline__ unsigned iv3(int nx, int ny, int k, int j, int i) {
   return (unsigned)((k * (ny + 1) + j) * nx + i);
 }
 
-// (k, j, i) of a flat index over nz x rows x nx
+// n / d for 0 <= n < 2^31 and d >= 1: the quotient from the hardware
+// reciprocal refined by one Newton step (relative error far below 2^-31, so
+// off by at most one) and one exact integer correction -- a few operations
+// instead of the long integer division sequence.
+__device__ __forceinline__ int quot3(int n, int d) {
+  const double dd = (double)d;
+  double r = __builtin_amdgcn_rcp(dd);
+  r = fma(fma(-dd, r, 1.0), r, r);
+  int q = (int)((double)n * r);
+  const int rem = n - q * d;
+  q += (rem >= d) - (rem < 0);
+  return q;
+}
+
+// (k, j, i) of flat index g over nz x rows x nx (the host keeps the product
+// below 2^31); false beyond the grid.
 __device__ __forceinline__ bool unflat3(long g, int nx, int rows, int nz, int& k, int& j, int& i) {
   if (g >= (long)nx * rows * nz) return false;
-  i = (int)(g % nx);
-  const long t = g / nx;
-  j = (int)(t % rows);
-  k = (int)(t / rows);
+  const int gi = (int)g;
+  const int t = quot3(gi, nx);
+  i = gi - t * nx;
+  k = quot3(t, rows);
+  j = t - k * rows;
   return true;
 }
 
@@ -853,9 +869,9 @@ __global__ void __launch_bounds__(kNT3) k3_mg_smooth(const Ctx3* __restrict__ C,
   const int hx = L.nx >> 1;
   const long t = (long)blockIdx.x * kNT3 + threadIdx.x;
   if (t >= (long)hx * L.ny * L.nz) return;
-  const long row = t / hx;
-  const int m = (int)(t - row * hx);
-  const int j = (int)(row % L.ny), k = (int)(row / L.ny);
+  const int row = quot3((int)t, hx);
+  const int m = (int)t - row * hx;
+  const int k = quot3(row, L.ny), j = row - k * L.ny;
   const int i = 2 * m + ((j + k + color) & 1);
   const unsigned c = ic3(L.nx, L.ny, k, j, i);
   if (zero) {
