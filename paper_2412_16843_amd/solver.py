@@ -319,13 +319,19 @@ class EnsembleSolver:
                 self.where[k] = (g, j)
         self._ctxs = (C.c_void_p * len(self.solvers))(*[s.ctx.value for s in self.solvers])
 
+    def _live(self):
+        if not self.solvers:
+            raise RuntimeError("EnsembleSolver is closed")
+
     def step(self, nsteps: int = 1, allow_noconv: bool = False) -> int:
+        self._live()
         return L.check(self.lib.cdi_step_concurrent(self._ctxs, len(self.solvers), int(nsteps)),
                        allow=(-4,) if allow_noconv else ())
 
     def tune(self, trial_steps: int = 10) -> Dict:
         """One tiled shape for all contexts, timed with every context
         stepping at once (cdi_tune_concurrent); the state is restored."""
+        self._live()
         n = len(self.solvers)
         nbytes = [self.lib.cdi_tune_bytes(s.ctx) for s in self.solvers]
         bufs = [torch.empty(b + 256, dtype=torch.uint8, device=self.device) for b in nbytes]
@@ -366,6 +372,7 @@ class EnsembleSolver:
         for s in getattr(self, "solvers", []):
             s.close()
         self.solvers = []
+        self._ctxs = None
 
     def __del__(self):
         try:

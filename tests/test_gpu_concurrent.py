@@ -166,3 +166,17 @@ def test_cg_iteration_totals_count_every_solve_in_every_form():
     ens.step(3)
     assert ens.cg_iterations() == solo
     ens.close()
+
+
+def test_closed_ensemble_refuses_to_step():
+    _torch()
+    from paper_2412_16843_amd.solver import EnsembleSolver
+    cases = _cases()[:2]
+    ens = EnsembleSolver([c.params for c in cases], [c.phi0 for c in cases], groups=2)
+    ens.step(1)
+    ens.close()
+    with pytest.raises(RuntimeError):
+        ens.step(1)
+    with pytest.raises(RuntimeError):
+        ens.tune(1)
+    ens.close()   # idempotent
