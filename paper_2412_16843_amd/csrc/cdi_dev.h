@@ -202,11 +202,18 @@ __device__ __forceinline__ double lane_value(double v, int lane) {
 // 8, then mirrored halves of the row -- each lane adds the same two values as
 // its partner (addition is commutative), so the row's lanes agree bit for
 // bit; the four row sums are then added in a fixed order.
-__device__ __forceinline__ double wave_sum(double v) {
+// Sum over each row of 16 lanes (the four DPP exchanges of wave_sum): every
+// lane of a row holds its row's sum, the same bits in each.
+__device__ __forceinline__ double row16_sum(double v) {
   v += dpp_move<0xB1>(v);    // quad_perm [1,0,3,2]
   v += dpp_move<0x4E>(v);    // quad_perm [2,3,0,1]
   v += dpp_move<0x141>(v);   // row_half_mirror
   v += dpp_move<0x140>(v);   // row_mirror
+  return v;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+  v = row16_sum(v);
   return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
 }
 template <typename T>

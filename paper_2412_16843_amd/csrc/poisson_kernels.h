@@ -1137,13 +1137,19 @@ struct DensePart {
   double m[kDenseMax / 16];
 };
 
+// The reads are unconditional (index 0 of the instance's CG vector x stands in
+// where there is no entry), so that no branch separates them from the other
+// reads of the cycle's start and the block waits for one memory latency.
 __device__ __forceinline__ void dense_part_load(const Inst& I, DensePart& dp) {
   const int n = I.lev[I.nlev - 1].nx * I.lev[I.nlev - 1].ny;
   const int row = threadIdx.x >> 4, part = threadIdx.x & 15;
+  const CDI_GLOBAL double* src = I.cdense ? I.cinv : I.x;
 #pragma unroll
   for (int u = 0; u < kDenseMax / 16; ++u) {
     const int k = part + 16 * u;
-    dp.m[u] = (I.cdense && row < n && k < n) ? I.cinv[(size_t)row * n + k] : 0.0;
+    const bool has = I.cdense && row < n && k < n;
+    const double v = src[has ? row * n + k : 0];
+    dp.m[u] = has ? v : 0.0;
   }
 }
 
@@ -1183,6 +1189,51 @@ __device__ __forceinline__ OwnedCell<S> owned_cell(const MgView<S>& L, int c,
   o.iD = o.own ? S(1) / (o.aw + o.ae + o.as + o.an) : S(0);
   o.r = o.own ? (rd != nullptr ? (S)rd[o.c] : L.r[o.c]) : S(0);
   return o;
+}
+
+// A cell of the wide level read from global memory (level lg, right-hand
+// side rd when given, else the level's r) with unconditional reads (a cell
+// past the level reads cell 0), so that all of a thread's reads at the
+// cycle's start are in flight together; owned_finish clears a cell past the
+// level and forms the reciprocal diagonal once the reads have landed.
+template <typename S>
+__device__ __forceinline__ OwnedCell<S> wide_cell_load(const Level& L, int c, const double* rd) {
+  OwnedCell<S> o;
+  const int nx = L.nx, ny = L.ny;
+  o.own = c < nx * ny;
+  const int j = o.own ? FastDiv(nx).div(c) : 0, i = c - j * nx;
+  o.c = o.own ? c : 0;
+  o.w = j * nx + wrap(i - 1, nx);
+  o.e = j * nx + wrap(i + 1, nx);
+  o.hs = j >= 1;
+  o.hn = j + 1 < ny;
+  o.color = (i + j) & 1;
+  const CDI_GLOBAL S* ax = gas<const S>(L.ax);
+  const CDI_GLOBAL S* ay = gas<const S>(L.ay);
+  const S aw = ax[o.c], ae = ax[o.e], as = ay[o.c], an = ay[o.c + nx];
+  S rv;
+  if constexpr (std::is_same<S, double>::value) {
+    const double* rp = rd != nullptr ? rd : gas<const S>(L.r);
+    rv = rp[o.c];
+  } else {
+    rv = rd != nullptr ? (S)rd[o.c] : gas<const S>(L.r)[o.c];
+  }
+  o.aw = aw;
+  o.ae = ae;
+  o.as = as;
+  o.an = an;
+  o.r = rv;
+  return o;
+}
+
+template <typename S>
+__device__ __forceinline__ void owned_finish(OwnedCell<S>& o) {
+  o.aw = o.own ? o.aw : S(0);
+  o.ae = o.own ? o.ae : S(0);
+  o.as = o.own ? o.as : S(0);
+  o.an = o.own ? o.an : S(0);
+  o.r = o.own ? o.r : S(0);
+  o.iD = o.own ? S(1) / (o.aw + o.ae + o.as + o.an) : S(0);
 }
 
 // Gauss-Seidel update of an owned cell (colour `color` only).
@@ -1335,71 +1386,95 @@ __device__ __forceinline__ void mg_cycle(const Inst& I, const ViewF& V, int lo, 
       __syncthreads();
     } else {
       // Coarsest grids beyond the dense inverse (dimensions that stop halving,
-      // e.g. 30 x 15): CG with one cell per thread (n <= kCoarseNT) in FP64,
-      // in the single-reduction form of Chronopoulos and Gear (both inner
-      // products of an iteration in one block reduction: two barriers per
-      // iteration).  The residual is shared through an FP64 LDS vector, so
-      // the recurrence stays consistent on the mixed path.  As the coarsest
-      // solve inside the preconditioner it stops at a relative residual of
-      // kCoarseCgRtol; the flexible outer CG tolerates the inexact solve and
-      // still meets its own tolerance.
+      // e.g. 30 x 15, or a density that varies): Jacobi-preconditioned CG in
+      // FP64, in the single-reduction form of Chronopoulos and Gear (both
+      // inner products of an iteration in one reduction: two barriers per
+      // iteration), one cell per thread.  Only the waves that own cells work
+      // (up to 256 cells one to four waves, then eight, then all sixteen):
+      // the others neither repeat the scalar recurrence nor take issue slots
+      // from the working waves on their SIMD; they pass the barriers and read
+      // the stop flag that thread 0 publishes.  The preconditioned residual is
+      // shared through an FP64 LDS vector, so the recurrence stays consistent
+      // on the mixed path.  As the coarsest solve inside the preconditioner it
+      // stops when the preconditioned residual norm (r, D^-1 r) has fallen by
+      // kCoarseCgRtol^2; the flexible outer CG tolerates the inexact solve (and
+      // the constant the Jacobi scaling adds to the correction, which K does
+      // not see).
       double m[1] = {0.0};
       for (int c = tid; c < n; c += kCoarseNT) m[0] += (double)r[c];
       block_allsum<1, kCoarseNT>(m, s_red);
       const double mean = m[0] / n;
+      constexpr int NW = kCoarseNT / 64;
+      const int naw = n > 512 ? NW : n > 256 ? NW / 2 : (n + 63) >> 6;   // working waves
+      const bool act = (tid >> 6) < naw;
       const int c = tid;
       const bool own = c < n;
       const int j = own ? c / nx : 0, i = own ? c - j * nx : 0;
       const int cw = j * nx + wrap(i - 1, nx), ce = j * nx + wrap(i + 1, nx);
+      // wall neighbours stand in for themselves (their coefficient is 0)
+      const int cs = (own && j >= 1) ? c - nx : c, cn = (own && j + 1 < ny) ? c + nx : c;
       const double aw = own ? (double)L.ax[c] : 0.0, ae = own ? (double)L.ax[ce] : 0.0;
       const double as = (own && j >= 1) ? (double)L.ay[c] : 0.0;
       const double an = (own && j + 1 < ny) ? (double)L.ay[c + nx] : 0.0;
-      double xr = 0.0, rr = own ? (double)r[c] - mean : 0.0, pr = 0.0, sr = 0.0;
-      double gam_old = 0.0, alpha = 0.0, gam0 = 0.0;
-      // only the waves that own cells work; the others pass the barriers
-      // and read the same sums, so every thread takes the same branches
-      constexpr int NW = kCoarseNT / 64;
-      const int nwa = (n + 63) >> 6;
-      const bool act = (tid >> 6) < nwa;
-      for (int it = 0; it <= 2 * n; ++it) {
-        // the previous iteration's reads of s_vec (operator) and s_red
-        // (sums) happened before its second barrier and before the barrier
-        // below respectively
-        if (own) s_vec[c] = rr;
+      const double iD = own ? 1.0 / (aw + ae + as + an) : 0.0;
+      double xr = 0.0, rr = own ? (double)r[c] - mean : 0.0, ur = rr * iD, pr = 0.0, sr = 0.0;
+      double gam_old = 0.0, den_old = 0.0, gam0 = 0.0;
+      const int lane = tid & 63;
+      // partial sums a lane of a working wave reads: (r, D^-1 r) of wave
+      // `lane` in the first row of 16 lanes, (K u, u) in the second
+      const int pidx = lane < 16 ? lane : lane < 32 ? NW + lane - 16 : -1;
+      const bool pread = pidx >= 0 && (lane & 15) < naw;
+      if (tid == 0) s_sc[3] = 0.0;   // stop flag
+      for (int it = 0;; ++it) {
+        // u = D^-1 r to LDS; the previous iteration's reads of s_vec happened
+        // before its second barrier, the flag was written after it
+        if (own) s_vec[c] = ur;
         __syncthreads();
+        // the neighbours are read with the flag (one LDS round trip)
+        double uw = 0.0, ue = 0.0, us = 0.0, un = 0.0;
+        if (own) {
+          uw = s_vec[cw];
+          ue = s_vec[ce];
+          us = s_vec[cs];
+          un = s_vec[cn];
+        }
+        if (s_sc[3] != 0.0) break;
         double wv = 0.0;
         if (act) {
-          if (own) {
-            wv = aw * (rr - s_vec[cw]) + ae * (rr - s_vec[ce]);
-            if (j >= 1) wv += as * (rr - s_vec[c - nx]);
-            if (j + 1 < ny) wv += an * (rr - s_vec[c + nx]);
-          }
-          const double g0 = wave_sum(rr * rr), g1 = wave_sum(wv * rr);   // (r, r), (A r, r)
-          if ((tid & 63) == 0) {
+          wv = aw * (ur - uw) + ae * (ur - ue) + as * (ur - us) + an * (ur - un);
+          const double g0 = wave_sum(rr * ur), g1 = wave_sum(wv * ur);   // (r, D^-1 r), (K u, u)
+          if (lane == 0) {
             s_red[tid >> 6] = g0;
             s_red[NW + (tid >> 6)] = g1;
           }
         }
         __syncthreads();
-        double gam = 0.0, del = 0.0;
-        for (int ww = 0; ww < nwa; ++ww) {   // the same order in every thread
-          gam += s_red[ww];
-          del += s_red[NW + ww];
+        if (act) {
+          // the per-wave sums added in the same order in every lane
+          const double t = row16_sum(pread ? s_red[pidx] : 0.0);
+          const double gam = lane_value(t, 0), del = lane_value(t, 16);
+          if (it == 0) gam0 = gam;
+          bool stop = !(gam > kCoarseCgRtol * kCoarseCgRtol * gam0) || it >= 2 * n;
+          // beta = gam / gam_old; with alpha_old = gam_old / den_old the
+          // denominator del - beta gam / alpha_old is del - beta^2 den_old
+          double beta = 0.0, den = del;
+          if (!stop && it > 0) {
+            beta = gam / gam_old;
+            den = del - beta * beta * den_old;
+          }
+          stop = stop || !(den > 0.0);
+          if (!stop) {
+            const double alpha = gam / den;
+            pr = ur + beta * pr;   // p = u + beta p
+            sr = wv + beta * sr;   // s = K p
+            xr += alpha * pr;
+            rr -= alpha * sr;
+            ur = rr * iD;
+            gam_old = gam;
+            den_old = den;
+          }
+          if (tid == 0 && stop) s_sc[3] = 1.0;
         }
-        if (it == 0) gam0 = gam;
-        if (!(gam > kCoarseCgRtol * kCoarseCgRtol * gam0)) break;
-        double beta = 0.0, den = del;
-        if (it > 0) {
-          beta = gam / gam_old;
-          den = del - beta * gam / alpha;
-        }
-        if (!(den > 0.0)) break;
-        alpha = gam / den;
-        pr = rr + beta * pr;   // p = r + beta p
-        sr = wv + beta * sr;   // s = A p
-        xr += alpha * pr;
-        rr -= alpha * sr;
-        gam_old = gam;
       }
       if (own) z[c] = (S)xr;
       __syncthreads();
@@ -1473,33 +1548,46 @@ __device__ __forceinline__ void coarse_load_coef(const Inst& I, CoarseLds<S>& C,
                                                  const double* rd = nullptr, int rn = 0) {
   constexpr int NX = (kCLX + kCoarseNT - 1) / kCoarseNT;
   constexpr int NY = (kCLY + kCoarseNT - 1) / kCoarseNT;
-  // flat index f of the concatenated x (y) arrays -> level and offset
-  auto locate = [&](int f, bool yf, const S*& src) {
+  // flat index f of the concatenated x (y) arrays -> level and offset, by
+  // selects over the (uniform) levels, so that the reads that follow are
+  // unconditional: element 0 of level lc stands in past the last level
+  auto locate = [&](int f, bool yf, const CDI_GLOBAL S*& src) {
+    const Level& L0 = I.lev[I.lc];
+    src = yf ? gas<const S>(L0.ay) : gas<const S>(L0.ax);
+    bool found = false;
     for (int l = I.lc; l < I.nlev; ++l) {
       const Level& L = I.lev[l];
       const int n = yf ? (L.ny + 1) * L.nx : L.nx * L.ny;
-      if (f < n) { src = (yf ? gas<const S>(L.ay) : gas<const S>(L.ax)) + f; return true; }
-      f -= n;
+      const bool here = !found && f < n;
+      const CDI_GLOBAL S* base = yf ? gas<const S>(L.ay) : gas<const S>(L.ax);
+      src = here ? base + f : src;
+      found = found || here;
+      f -= found ? 0 : n;
     }
-    return false;
+    return found;
   };
   S gx[NX], gy[NY];
   bool hx[NX], hy[NY];
 #pragma unroll
   for (int e = 0; e < NX; ++e) {
-    const S* src = nullptr;
+    const CDI_GLOBAL S* src;
     hx[e] = locate(threadIdx.x + e * kCoarseNT, false, src);
-    gx[e] = hx[e] ? *src : S(0);
+    gx[e] = *src;
   }
 #pragma unroll
   for (int e = 0; e < NY; ++e) {
-    const S* src = nullptr;
+    const CDI_GLOBAL S* src;
     hy[e] = locate(threadIdx.x + e * kCoarseNT, true, src);
-    gy[e] = hy[e] ? *src : S(0);
+    gy[e] = *src;
   }
   S gr = S(0);
   const bool hr = rdst != nullptr && (int)threadIdx.x < rn;
-  if (hr) gr = rd != nullptr ? (S)rd[threadIdx.x] : rs[threadIdx.x];
+  if constexpr (std::is_same<S, double>::value) {
+    const double* rp = rd != nullptr ? rd : rs;
+    if (rdst != nullptr) gr = rp[hr ? threadIdx.x : 0];
+  } else {
+    if (hr) gr = rd != nullptr ? (S)rd[threadIdx.x] : rs[threadIdx.x];
+  }
 #pragma unroll
   for (int e = 0; e < NX; ++e)
     if (hx[e]) C.ax[threadIdx.x + e * kCoarseNT] = gx[e];
@@ -1656,11 +1744,11 @@ __global__ void __launch_bounds__(kCoarseNT) k_mg_coarse(const Inst* __restrict_
   // side is the FP64 residual itself (its S copy r0 is written below)
   OwnedCell<S> woc[kWideOwn];
   if (wide) {
-    const int nx = I.lev[lg].nx, ny = I.lev[lg].ny;
+    const Level& L = I.lev[lg];
 #pragma unroll
     for (int k = 0; k < kWideOwn; ++k)
-      woc[k] = owned_cell<S>(view(lg), wide_cell_index(tid + (k >> 1) * kCoarseNT, k & 1, nx, ny),
-                             lg == 0 ? rcur : nullptr);
+      woc[k] = wide_cell_load<S>(L, wide_cell_index(tid + (k >> 1) * kCoarseNT, k & 1, L.nx, L.ny),
+                                 lg == 0 ? rcur : nullptr);
   }
   {
     // right-hand side of level lg: into LDS with the coefficients when lg is
@@ -1678,6 +1766,10 @@ __global__ void __launch_bounds__(kCoarseNT) k_mg_coarse(const Inst* __restrict_
     }
   }
   __syncthreads();
+  if (wide) {
+#pragma unroll
+    for (int k = 0; k < kWideOwn; ++k) owned_finish<S>(woc[k]);
+  }
   if (lg >= lc)   // LDS levels only: views the compiler knows to be LDS (ds_ instructions)
     mg_cycle<S>(I, [&](int l) { return coarse_view<S>(I, C, l); }, lg, nl, C.red, C.sc, C.cg, &dp);
   else if (wide)
