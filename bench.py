@@ -72,10 +72,9 @@ ALGO_BYTES_PER_CELL = {
     "mg_up": 5 * 8 + 2 + 8,
     # z, d_old, a_x, a_y, r read; d, q written
     "pcg_spmv": 5 * 8 + 2 * 8,
-    # u*, v*, x, a_x, a_y read; u, v, p written; per-stage pressure history
-    # four steps deep (three read, shifted back, four written); final stage
-    # only: next phi copied (1/4)
-    "project": 5 * 8 + 3 * 8 + 7 * 8 + 16 / 4,
+    # u*, v*, x, a_x, a_y read; u, v, p written; the stage's slot of the
+    # pressure-history ring written; final stage only: next phi copied (1/4)
+    "project": 5 * 8 + 3 * 8 + 8 + 16 / 4,
     # b, guess (four history fields: cubic extrapolation), a_x, a_y read; x,
     # r written
     "pcg_init": 7 * 8 + 2 * 8,

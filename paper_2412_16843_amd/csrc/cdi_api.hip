@@ -428,9 +428,11 @@ struct cdi_ctx {
   // graph launch: captured step with a fixed CG budget per solve
   hipStream_t gstream = nullptr;   // capture / replay stream (the caller's may be the null stream)
   hipEvent_t gev0 = nullptr, gev1 = nullptr;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t gexec = nullptr;
-  int graph_budget = 0;            // CG iterations per solve in the captured step
+  // one captured step per pressure-history ring slot (step mod 4): a step's
+  // launches carry the slot it writes
+  hipGraph_t graph[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipGraphExec_t gexec[4] = {nullptr, nullptr, nullptr, nullptr};
+  int graph_budget = 0;            // CG iterations per solve in the captured steps
   int graph_slack = 0;             // consecutive steps that needed at most budget - 2
   long graph_replays = 0, graph_misses = 0;
   // measurement hook: events around every launch of one kernel family
@@ -590,6 +592,10 @@ bool any_nonfinite(const cdi_ctx* c) {
   return false;
 }
 
+// Pressure-history ring slot the current step writes (the step number mod
+// the history depth); the guess reads the slots before it.
+int hist_slot(const cdi_ctx* c) { return (int)(c->step & (kHistDepth - 1)); }
+
 // Flexible-CG loop after the right-hand side is in place.  Returns NOCONV
 // if an instance stopped at maxit.
 template <typename S>
@@ -602,7 +608,8 @@ cdi_status solve_loop(cdi_ctx* c, int guess, int stage) {
   }
   timed(c, "pcg_init", [&] {
     with_rows(c->wide_rows, [&](auto R) {
-      CDI_LAUNCH(c, k_pcg_init<decltype(R)::value>, nwide, kNT, c->d_wide, c->d_inst, guess, stage);
+      CDI_LAUNCH(c, k_pcg_init<decltype(R)::value>, nwide, kNT, c->d_wide, c->d_inst, guess, stage,
+                 hist_slot(c));
     });
   });
   // z0 = M r0 (residual in buffer 0)
@@ -686,8 +693,8 @@ void learned_guess(cdi_ctx* c, int src, int base, int stage) {
     cdinet::forward(c->net);
     CDI_LAUNCH(c, k_guess_apply, g, kNT, c->d_inst, cdinet::output(c->net));
     with_rows(c->wide_rows, [&](auto R) {
-      k_guess_fit<decltype(R)::value><<<(unsigned)c->B.wide.size(), kNT, 0, c->stream>>>(c->d_wide, c->d_inst,
-                                                                                          base, stage);
+      k_guess_fit<decltype(R)::value><<<(unsigned)c->B.wide.size(), kNT, 0, c->stream>>>(
+          c->d_wide, c->d_inst, base, stage, hist_slot(c));
     });
   }, false);
 }
@@ -726,7 +733,8 @@ cdi_status run_step(cdi_ctx* c) {
     else if (s != CDI_OK) return s;
     timed(c, "project", [&] {
       with_rows(c->wide_rows, [&](auto R) {
-        CDI_LAUNCH(c, k_project<decltype(R)::value>, nwide, kNT, c->d_wide, c->d_inst, tfac, k == 3, dst, k);
+        CDI_LAUNCH(c, k_project<decltype(R)::value>, nwide, kNT, c->d_wide, c->d_inst, tfac, k == 3, dst, k,
+                   hist_slot(c));
       });
     });
   }
@@ -748,7 +756,8 @@ void enqueue_solve_fixed(cdi_ctx* c, int guess, int stage, int budget) {
   const unsigned nwide = (unsigned)B.wide.size();
   if (!c->uniform_rho) launch_coef<S>(c);
   with_rows(c->wide_rows, [&](auto R) {
-    k_pcg_init<decltype(R)::value><<<nwide, kNT, 0, c->stream>>>(c->d_wide, c->d_inst, guess, stage);
+    k_pcg_init<decltype(R)::value><<<nwide, kNT, 0, c->stream>>>(c->d_wide, c->d_inst, guess, stage,
+                                                                 hist_slot(c));
   });
   launch_vcycle<S>(c, 0, 0, 0);
   for (int it = 0; it < budget; ++it) {
@@ -799,19 +808,27 @@ cdi_status upload_shape(cdi_ctx* c) {
   return CDI_OK;
 }
 
+void graph_drop_slot(cdi_ctx* c, int ph) {
+  if (c->gexec[ph]) (void)hipGraphExecDestroy(c->gexec[ph]);
+  if (c->graph[ph]) (void)hipGraphDestroy(c->graph[ph]);
+  c->gexec[ph] = nullptr;
+  c->graph[ph] = nullptr;
+}
+
 void graph_drop(cdi_ctx* c) {
-  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
-  if (c->graph) (void)hipGraphDestroy(c->graph);
-  c->gexec = nullptr;
-  c->graph = nullptr;
+  for (int ph = 0; ph < 4; ++ph) graph_drop_slot(c, ph);
   c->graph_budget = 0;
 }
 
 // Capture one RK4 step (snapshot, 4 stages with fixed-budget solves, copy of
-// the CG scalars to pinned memory) on the context's capture stream.
+// the CG scalars to pinned memory) on the context's capture stream, for the
+// history ring slot of the current step.  A new budget drops the steps
+// captured for the other slots.
 template <typename S>
 cdi_status graph_capture(cdi_ctx* c, int budget) {
-  graph_drop(c);
+  const int ph = hist_slot(c);
+  if (budget != c->graph_budget) graph_drop(c);
+  else graph_drop_slot(c, ph);
   Batch& B = c->B;
   const unsigned ncell = (unsigned)B.cell.size();
   const unsigned nwide = (unsigned)B.wide.size();
@@ -837,7 +854,8 @@ cdi_status graph_capture(cdi_ctx* c, int budget) {
       });
       enqueue_solve_fixed<S>(c, gm, k, budget);
       with_rows(c->wide_rows, [&](auto R) {
-        k_project<decltype(R)::value><<<nwide, kNT, 0, c->stream>>>(c->d_wide, c->d_inst, tfac, k == 3, dst, k);
+        k_project<decltype(R)::value><<<nwide, kNT, 0, c->stream>>>(c->d_wide, c->d_inst, tfac, k == 3, dst, k,
+                                                                    hist_slot(c));
       });
     }
     return pcg_to_host(c);
@@ -857,14 +875,14 @@ cdi_status graph_capture(cdi_ctx* c, int budget) {
     if (g) (void)hipGraphDestroy(g);
     return st;
   }
-  c->graph = g;
-  e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+  c->graph[ph] = g;
+  e = hipGraphInstantiate(&c->gexec[ph], g, nullptr, nullptr, 0);
   if (e != hipSuccess) {
     graph_drop(c);
     return fail(CDI_ERR_DEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
   }
+  if (c->graph_budget != budget) c->graph_slack = 0;
   c->graph_budget = budget;
-  c->graph_slack = 0;
   return CDI_OK;
 }
 
@@ -885,14 +903,17 @@ cdi_status run_graph_step(cdi_ctx* c) {
     if (c->uniform_rho) { launch_coef<S>(c); c->coef_ready = true; }
   }
   const int want = std::min(c->maxit, c->pred_iters + 1);
-  if (!c->gexec || want > c->graph_budget || (c->graph_slack >= 50 && want < c->graph_budget)) {
-    cdi_status st = graph_capture<S>(c, want);
+  const int ph = hist_slot(c);
+  const bool rebudget = c->graph_budget == 0 || want > c->graph_budget ||
+                        (c->graph_slack >= 50 && want < c->graph_budget);
+  if (rebudget || !c->gexec[ph]) {
+    cdi_status st = graph_capture<S>(c, rebudget ? want : c->graph_budget);
     if (st != CDI_OK) return st;
   }
   // order the replay after the caller's work and the caller's later work after it
   HIPCHK(hipEventRecord(c->gev0, c->stream));
   HIPCHK(hipStreamWaitEvent(c->gstream, c->gev0, 0));
-  HIPCHK(hipGraphLaunch(c->gexec, c->gstream));
+  HIPCHK(hipGraphLaunch(c->gexec[ph], c->gstream));
   HIPCHK(hipEventRecord(c->gev1, c->gstream));
   HIPCHK(hipStreamWaitEvent(c->stream, c->gev1, 0));
   HIPCHK(hipEventSynchronize(c->gev1));
@@ -938,7 +959,8 @@ cdi_status run_persistent(cdi_ctx* c, int nsteps) {
     const int m = std::min(kPersistChunk, nsteps - done);
     timed(c, "persistent", [&] {
       CDI_LAUNCH(c, k_step_persistent<S>, (unsigned)B.n, PNT, c->d_cell_inst, c->d_inst, m,
-                 c->hist_steps, gm, c->extrap_order, c->rtol, c->maxit, (int)(done > 0));
+                 (int)((c->step + done) & 3), c->hist_steps, gm, c->extrap_order, c->rtol, c->maxit,
+                 (int)(done > 0));
     });
     HIPCHK(hipGetLastError());
     c->hist_steps += m;

@@ -44,7 +44,7 @@ __device__ __forceinline__ void pall_sum(double (&v)[NV], double* red, double* s
 // x in I.x and returns the iteration count.
 template <typename S>
 __device__ int persist_solve(const Inst& I, PersistLds<S>& L, int guess,
-                             int stage, double bmean, double rtol, int maxit, bool& zero,
+                             int stage, int hw, double bmean, double rtol, int maxit, bool& zero,
                              double& xmean, double& relres, bool& converged) {
   const int nx = I.nx, ny = I.ny, n = nx * ny;
   const int tid = threadIdx.x;
@@ -57,7 +57,7 @@ __device__ int persist_solve(const Inst& I, PersistLds<S>& L, int guess,
   for (int c = tid; c < n; c += PNT) {
     const int j = dn.div(c), i = c - j * nx;
     double f, rv;
-    pcg_init_cell(I, guess, stage, j, i, bmean, f, rv);
+    pcg_init_cell(I, guess, stage, hw, j, i, bmean, f, rv);
     s2[0] += f * f;
     s2[1] += rv * rv;
   }
@@ -121,14 +121,16 @@ __device__ int persist_solve(const Inst& I, PersistLds<S>& L, int guess,
   return it;
 }
 
-// nsteps RK4 steps, one instance per workgroup.  guess: 0 zero, 1 previous
-// pressure (the per-stage history once `hist` + steps done >= 1, its linear
-// extrapolation once >= 2).  accumulate: add this launch's count of
+// nsteps RK4 steps, one instance per workgroup, the first of them step
+// number step0 (its pressure-history ring slot is step0 mod 4).  guess: 0
+// zero, 1 previous pressure (the per-stage history once `hist` + steps done
+// >= 1, its time extrapolation once >= 2).  accumulate: add this launch's count of
 // unconverged solves and its largest iteration count to the ones recorded.
 template <typename S>
 __global__ void __launch_bounds__(PNT) k_step_persistent(const Tile* __restrict__ tiles,
                                                          const Inst* __restrict__ insts,
-                                                         int nsteps, int hist, int guess, int order,
+                                                         int nsteps, int step0, int hist, int guess,
+                                                         int order,
                                                          double rtol, int maxit, int accumulate) {
   __shared__ PersistLds<S> L;
   const Inst& I = insts[blockIdx.x];
@@ -186,7 +188,8 @@ __global__ void __launch_bounds__(PNT) k_step_persistent(const Tile* __restrict_
       if (gm == 1 && hs >= 1) gm = history_mode(hs, order);
       bool zero, conv;
       double xmean, relres;
-      const int it = persist_solve<S>(I, L, gm, k, bmean, rtol, maxit, zero, xmean, relres, conv);
+      const int hw = (step0 + s) & 3;   // history ring slot of this step
+      const int it = persist_solve<S>(I, L, gm, k, hw, bmean, rtol, maxit, zero, xmean, relres, conv);
       if (!conv) ++nfail;
       max_it = it > max_it ? it : max_it;
       if (tid == 0) {
@@ -202,7 +205,7 @@ __global__ void __launch_bounds__(PNT) k_step_persistent(const Tile* __restrict_
       }
       for (int c = tid; c < n; c += PNT) {
         const int j = dn.div(c), i = c - j * nx;
-        project_cell(I, tfac, k == 3, phd, k, zero, xmean, j, i);
+        project_cell(I, tfac, k == 3, phd, k, hw, zero, xmean, j, i);
       }
       __syncthreads();
     }

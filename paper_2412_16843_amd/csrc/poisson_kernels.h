@@ -198,42 +198,49 @@ __device__ __forceinline__ double apply_K(const Inst& I, const double* __restric
 // linear, quadratic, cubic polynomial through equally spaced values: weights
 // 1; 2, -1; 3, -3, 1; 4, -6, 4, -1); 2: the learned guess, the fitted
 // combination gscale * base + gscale2 * g of a base of mode gbase (one of the
-// above) and the network output g held in zf.
-__device__ __forceinline__ double base_guess(const Inst& I, int guess, int stage, unsigned o) {
+// above) and the network output g held in zf.  The history is a ring of
+// kHistDepth slots: step s writes slot s mod kHistDepth (hw, the slot the
+// current step writes), so the pressure d + 1 steps back is in slot
+// hw - 1 - d and no step moves the older entries.
+__device__ __forceinline__ double base_guess(const Inst& I, int guess, int stage, int hw,
+                                             unsigned o) {
+  static_assert(kHistDepth == 4, "ring slots are taken mod 4");
+  auto H = [&](int d) { return I.hp[(hw + 3 - d) & 3][stage][o]; };
   switch (guess) {
     case 1: return I.p[o];
-    case 3: return I.hp[0][stage][o];
-    case 4: return 2.0 * I.hp[0][stage][o] - I.hp[1][stage][o];
-    case 5: return 3.0 * (I.hp[0][stage][o] - I.hp[1][stage][o]) + I.hp[2][stage][o];
-    case 6: return 4.0 * (I.hp[0][stage][o] + I.hp[2][stage][o]) - 6.0 * I.hp[1][stage][o] -
-                   I.hp[3][stage][o];
+    case 3: return H(0);
+    case 4: return 2.0 * H(0) - H(1);
+    case 5: return 3.0 * (H(0) - H(1)) + H(2);
+    case 6: return 4.0 * (H(0) + H(2)) - 6.0 * H(1) - H(3);
     default: return 0.0;
   }
 }
 
-__device__ __forceinline__ double guess_value(const Inst& I, int guess, int stage, unsigned o) {
+__device__ __forceinline__ double guess_value(const Inst& I, int guess, int stage, int hw,
+                                              unsigned o) {
   if (guess == 2) {
-    const double b = I.pcg->gscale * base_guess(I, I.pcg->gbase, stage, o);
+    const double b = I.pcg->gscale * base_guess(I, I.pcg->gbase, stage, hw, o);
     const double c = I.pcg->gscale2;   // 0 when the network output was dropped
     return c != 0.0 ? b + c * I.zf[o] : b;
   }
-  return base_guess(I, guess, stage, o);
+  return base_guess(I, guess, stage, hw, o);
 }
 
 // f = -(b - mean b), x0 and r0 = f - K x0 at cell (j, i).
-__device__ __forceinline__ void pcg_init_cell(const Inst& I, int guess, int stage, int j, int i,
-                                              double bmean, double& f, double& r) {
+__device__ __forceinline__ void pcg_init_cell(const Inst& I, int guess, int stage, int hw, int j,
+                                              int i, double bmean, double& f, double& r) {
   const int nx = I.nx, ny = I.ny;
   const unsigned o = (unsigned)(j * nx) + i;
   f = -(I.b[o] - bmean);
   r = f;
   if (guess) {
     const int ie = wrap(i + 1, nx), iw = wrap(i - 1, nx);
-    const double xc = guess_value(I, guess, stage, o);
-    double kx = I.ax0[o] * (xc - guess_value(I, guess, stage, (unsigned)(j * nx) + iw)) +
-                I.ax0[(unsigned)(j * nx) + ie] * (xc - guess_value(I, guess, stage, (unsigned)(j * nx) + ie));
-    if (j >= 1) kx += I.ay0[o] * (xc - guess_value(I, guess, stage, o - nx));
-    if (j + 1 < ny) kx += I.ay0[o + nx] * (xc - guess_value(I, guess, stage, o + nx));
+    const double xc = guess_value(I, guess, stage, hw, o);
+    double kx = I.ax0[o] * (xc - guess_value(I, guess, stage, hw, (unsigned)(j * nx) + iw)) +
+                I.ax0[(unsigned)(j * nx) + ie] *
+                    (xc - guess_value(I, guess, stage, hw, (unsigned)(j * nx) + ie));
+    if (j >= 1) kx += I.ay0[o] * (xc - guess_value(I, guess, stage, hw, o - nx));
+    if (j + 1 < ny) kx += I.ay0[o + nx] * (xc - guess_value(I, guess, stage, hw, o + nx));
     r = f - kx;
     I.x[o] = xc;
   } else {
@@ -247,7 +254,7 @@ __device__ __forceinline__ void pcg_init_cell(const Inst& I, int guess, int stag
 template <int WR>
 __global__ void __launch_bounds__(kNT) k_pcg_init(const Tile* __restrict__ tiles,
                                                   const Inst* __restrict__ insts, int guess,
-                                                  int stage) {
+                                                  int stage, int hw) {
   constexpr int RY = WR * TY + 2, RX = TX + 2;
   __shared__ double s_x[RY * RX];
   __shared__ double sh[2 * kNT / 64];
@@ -265,7 +272,8 @@ __global__ void __launch_bounds__(kNT) k_pcg_init(const Tile* __restrict__ tiles
       const int rj = k / RX, ri = k - rj * RX;
       const int j = t.j0 - 1 + rj;
       gv[e] = (k < RY * RX && j >= 0 && j < ny)
-                  ? guess_value(I, guess, stage, (unsigned)(j * nx) + wrap_any(t.i0 - 1 + ri, nx)) : 0.0;
+                  ? guess_value(I, guess, stage, hw, (unsigned)(j * nx) + wrap_any(t.i0 - 1 + ri, nx))
+                  : 0.0;
     }
 #pragma unroll
     for (int e = 0; e < NG; ++e) {
@@ -459,7 +467,7 @@ __global__ void __launch_bounds__(kNT) k_pcg_spmv(const Tile* __restrict__ tiles
 template <int WR>
 __global__ void __launch_bounds__(kNT) k_guess_fit(const Tile* __restrict__ tiles,
                                                    const Inst* __restrict__ insts, int base,
-                                                   int stage) {
+                                                   int stage, int hw) {
   __shared__ double sh[5 * kNT / 64];
   const Tile t = tiles[blockIdx.x];
   const Inst& I = insts[t.inst];
@@ -471,12 +479,13 @@ __global__ void __launch_bounds__(kNT) k_guess_fit(const Tile* __restrict__ tile
       const unsigned o = (unsigned)(j * nx) + i;
       const double f = -(I.b[o] - I.pcg->bmean);
       const int ie = wrap(i + 1, nx), iw = wrap(i - 1, nx);
-      const double pv = base_guess(I, base, stage, o), gv = I.zf[o];
+      const double pv = base_guess(I, base, stage, hw, o), gv = I.zf[o];
       // K applied to the base (apply_K's terms, with base values)
-      double kp = I.ax0[o] * (pv - base_guess(I, base, stage, (unsigned)(j * nx) + iw)) +
-                  I.ax0[(unsigned)(j * nx) + ie] * (pv - base_guess(I, base, stage, (unsigned)(j * nx) + ie));
-      if (j >= 1) kp += I.ay0[o] * (pv - base_guess(I, base, stage, o - nx));
-      if (j + 1 < ny) kp += I.ay0[o + nx] * (pv - base_guess(I, base, stage, o + nx));
+      double kp = I.ax0[o] * (pv - base_guess(I, base, stage, hw, (unsigned)(j * nx) + iw)) +
+                  I.ax0[(unsigned)(j * nx) + ie] *
+                      (pv - base_guess(I, base, stage, hw, (unsigned)(j * nx) + ie));
+      if (j >= 1) kp += I.ay0[o] * (pv - base_guess(I, base, stage, hw, o - nx));
+      if (j + 1 < ny) kp += I.ay0[o + nx] * (pv - base_guess(I, base, stage, hw, o + nx));
       const double kg = apply_K(I, I.zf, j, i);
       s[0] += pv * kp; s[1] += pv * kg; s[2] += gv * kg; s[3] += pv * f; s[4] += gv * f;
     }
@@ -553,8 +562,7 @@ __global__ void __launch_bounds__(kNT) k_pcg_xmean(const Tile* __restrict__ tile
 struct ProjIn {
   double xc, xw, xs;       // pressure iterate: cell, west, south
   double us, vs, ax, ay;   // u*, v*, face coefficients
-  double hist[kHistDepth - 1];   // stage pressure history, newest first
-  double ph;                     // next phase field (final stage)
+  double ph;               // next phase field (final stage)
 };
 
 __device__ __forceinline__ ProjIn project_load(const Inst& I, int final_stage,
@@ -570,14 +578,12 @@ __device__ __forceinline__ ProjIn project_load(const Inst& I, int final_stage,
   v.ax = I.ax0[o];
   v.vs = j >= 1 ? I.vstar[o] : 0.0;
   v.ay = j >= 1 ? I.ay0[o] : 0.0;
-#pragma unroll
-  for (int d = 0; d + 1 < kHistDepth; ++d) v.hist[d] = stage >= 0 ? I.hp[d][stage][o] : 0.0;
   v.ph = final_stage ? ph[o] : 0.0;
   return v;
 }
 
 __device__ __forceinline__ void project_store(const Inst& I, const ProjIn& v, double tau,
-                                              int final_stage, int stage, bool zero,
+                                              int final_stage, int stage, int hw, bool zero,
                                               double xmean, int j, int i) {
   const int nx = I.nx;
   const unsigned o = (unsigned)(j * nx) + i;
@@ -588,25 +594,23 @@ __device__ __forceinline__ void project_store(const Inst& I, const ProjIn& v, do
   vo[o] = j >= 1 ? v.vs - scale * (v.xc - v.xs) * v.ay : 0.0;
   const double pn = v.xc - (zero ? 0.0 : xmean);
   I.p[o] = pn;
-  if (stage >= 0) {   // pressure history of this RK stage (for the next step's guess)
-#pragma unroll
-    for (int d = 1; d < kHistDepth; ++d) I.hp[d][stage][o] = v.hist[d - 1];
-    I.hp[0][stage][o] = pn;
-  }
+  // pressure history of this RK stage (for the next steps' guesses): the
+  // ring slot of this step
+  if (stage >= 0) I.hp[hw][stage][o] = pn;
   if (final_stage) I.phi[o] = v.ph;
 }
 
 __device__ __forceinline__ void project_cell(const Inst& I, double tau, int final_stage,
-                                             const double* __restrict__ ph, int stage, bool zero,
-                                             double xmean, int j, int i) {
+                                             const double* __restrict__ ph, int stage, int hw,
+                                             bool zero, double xmean, int j, int i) {
   project_store(I, project_load(I, final_stage, ph, stage, zero, j, i), tau, final_stage, stage,
-                zero, xmean, j, i);
+                hw, zero, xmean, j, i);
 }
 
 template <int WR>
 __global__ void __launch_bounds__(kNT) k_project(const Tile* __restrict__ tiles,
                                                  const Inst* __restrict__ insts, double tau,
-                                                 int final_stage, int src, int stage) {
+                                                 int final_stage, int src, int stage, int hw) {
   const Tile t = tiles[blockIdx.x];
   const Inst& I = insts[t.inst];
   const int nx = I.nx, ny = I.ny;
@@ -622,7 +626,7 @@ __global__ void __launch_bounds__(kNT) k_project(const Tile* __restrict__ tiles,
 #pragma unroll
   for (int r = 0; r < WR; ++r) {
     const int i = t.i0 + wide_tx(), j = t.j0 + wide_ty(r);
-    if (i < nx && j < ny) project_store(I, v[r], tau, final_stage, stage, zero, xmean, j, i);
+    if (i < nx && j < ny) project_store(I, v[r], tau, final_stage, stage, hw, zero, xmean, j, i);
   }
 }
 
