@@ -237,7 +237,7 @@ void build_wide(Batch& B, int rows) {
     I.first_wide = (int)B.wide.size();
     int lw = 0;
     for (int j0 = 0; j0 < R.p.ny; j0 += wy)
-      for (int i0 = 0; i0 < R.p.nx; i0 += TX) B.wide.push_back(Tile{k, i0, j0, 0, lw++, {0, 0, 0}});
+      for (int i0 = 0; i0 < R.p.nx; i0 += TX) B.wide.push_back(Tile{k, i0, j0, 0, lw++, 0, nullptr});
     I.nwide = lw;
   }
 }
@@ -256,7 +256,7 @@ void build_mg(Batch& B) {
       L.first_tile = (int)B.mg[l].size();
       int loc = 0;
       for (int j0 = 0; j0 < L.ny; j0 += FY)
-        for (int i0 = 0; i0 < L.nx; i0 += FX) B.mg[l].push_back(Tile{k, i0, j0, l, loc++, {0, 0, 0}});
+        for (int i0 = 0; i0 < L.nx; i0 += FX) B.mg[l].push_back(Tile{k, i0, j0, l, loc++, 0, nullptr});
       L.ntiles = loc;
     }
     for (int l = R.lg; l < R.nlev; ++l) { I.lev[l].first_tile = 0; I.lev[l].ntiles = 0; }
@@ -288,7 +288,7 @@ void build_strips(Batch& B, int rows) {
     const Resolved& R = B.R[k];
     int local = 0;
     for (int j0 = 0; j0 < R.p.ny; j0 += rows)
-      for (int i0 = 0; i0 < R.p.nx; i0 += sr::TW) B.strip.push_back(Tile{k, i0, j0, 0, local++, {0, 0, 0}});
+      for (int i0 = 0; i0 < R.p.nx; i0 += sr::TW) B.strip.push_back(Tile{k, i0, j0, 0, local++, 0, nullptr});
   }
 }
 
@@ -306,7 +306,7 @@ void build_tiles(Batch& B, int wide_rows) {
     I.first_tile = (int)B.cell.size();
     int local = 0;
     for (int j0 = 0; j0 < R.p.ny; j0 += TY)
-      for (int i0 = 0; i0 < R.p.nx; i0 += TX) B.cell.push_back(Tile{k, i0, j0, 0, local++, {0, 0, 0}});
+      for (int i0 = 0; i0 < R.p.nx; i0 += TX) B.cell.push_back(Tile{k, i0, j0, 0, local++, 0, nullptr});
     I.ntiles = local;
   }
   build_strips(B, strip_rows(B.R));
@@ -794,11 +794,16 @@ cdi_status snapshot(cdi_ctx* c, bool save) {
 // the instance descriptors into their fixed slots.
 cdi_status upload_shape(cdi_ctx* c) {
   Batch& B = c->B;
-  const std::vector<Tile> w = xcd_order(B.wide);
+  // the wide and multigrid tiles carry their instance's CG-scalar address
+  auto with_pcg = [&](std::vector<Tile> v) {
+    for (Tile& t : v) t.pcg = B.inst[t.inst].pcg;   // gptr copy
+    return v;
+  };
+  const std::vector<Tile> w = with_pcg(xcd_order(B.wide));
   HIPCHK(hipMemcpyAsync(c->d_wide, w.data(), sizeof(Tile) * w.size(), hipMemcpyHostToDevice, c->stream));
   std::vector<std::vector<Tile>> lv(B.max_lg);
   for (int l = 0; l < B.max_lg; ++l) {
-    lv[l] = xcd_order(B.mg[l]);
+    lv[l] = with_pcg(xcd_order(B.mg[l]));
     if (!lv[l].empty())
       HIPCHK(hipMemcpyAsync(c->d_mg[l], lv[l].data(), sizeof(Tile) * lv[l].size(),
                             hipMemcpyHostToDevice, c->stream));
@@ -1863,9 +1868,9 @@ __global__ void k_noalloc_setup(Inst I, Inst* __restrict__ dst, Tile* __restrict
     *dst = I;
     I.pcg->gamma_step = I.gamma;
   }
-  if (g < ntiles) tiles[g] = Tile{0, (g % ntx) * TX, (g / ntx) * TY, 0, g, {0, 0, 0}};
+  if (g < ntiles) tiles[g] = Tile{0, (g % ntx) * TX, (g / ntx) * TY, 0, g, 0, nullptr};
   if (g < nstrips)
-    tiles[ntiles + g] = Tile{0, (g % ntxs) * sr::TW, (g / ntxs) * srows, 0, g, {0, 0, 0}};
+    tiles[ntiles + g] = Tile{0, (g % ntxs) * sr::TW, (g / ntxs) * srows, 0, g, 0, nullptr};
   if (g < ncounters) counters[g] = 0u;
   if (g < I.nx) {
     l_my[g] = 0.0;

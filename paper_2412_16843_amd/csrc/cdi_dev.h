@@ -134,8 +134,11 @@ struct Tile {
   int i0, j0;
   int level;
   int local;                // index of this tile among the instance's tiles of the level
-  int pad[3];
+  int pad;
+  gptr<PcgScalars> pcg;     // the instance's CG scalars (set on the multigrid and wide tiles):
+                            // its done flag is read with the instance's descriptor, not after it
 };
+static_assert(sizeof(Tile) == 32, "tile descriptor layout");
 
 // ---------------------------------------------------------------- helpers
 __device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
@@ -164,6 +167,27 @@ struct FastDiv {
     return q;
   }
 };
+
+// Scalar-memory values a block needs before its first vector read: one
+// empty asm makes them all ready at this point, so that their loads and the
+// done-flag load are in flight together (one latency) instead of being
+// issued one after another behind the flag's branch.
+template <typename A, typename B, typename C, typename D, typename E, typename F>
+__device__ __forceinline__ void scalars_ready(const A& a, const B& b, const C& c, const D& d,
+                                              const E& e, const F& f) {
+  asm volatile("" : : "s"(a), "s"(b), "s"(c), "s"(d), "s"(e), "s"(f));
+}
+template <typename A, typename B, typename C, typename D, typename E, typename F, typename G>
+__device__ __forceinline__ void scalars_ready(const A& a, const B& b, const C& c, const D& d,
+                                              const E& e, const F& f, const G& g) {
+  asm volatile("" : : "s"(a), "s"(b), "s"(c), "s"(d), "s"(e), "s"(f), "s"(g));
+}
+template <typename A, typename B, typename C, typename D, typename E, typename F, typename G,
+          typename H>
+__device__ __forceinline__ void scalars_ready(const A& a, const B& b, const C& c, const D& d,
+                                              const E& e, const F& f, const G& g, const H& h) {
+  asm volatile("" : : "s"(a), "s"(b), "s"(c), "s"(d), "s"(e), "s"(f), "s"(g), "s"(h));
+}
 
 // Periodic index for any offset: halo columns of a tile wider than the grid
 // can lie more than one period away.

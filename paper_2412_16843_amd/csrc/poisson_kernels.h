@@ -370,14 +370,16 @@ __global__ void __launch_bounds__(kNT) k_pcg_spmv(const Tile* __restrict__ tiles
   __shared__ double sh[2 * kNT / 64];
   const Tile t = tiles[blockIdx.x];
   const Inst& I = insts[t.inst];
-  if (I.pcg->done) return;
+  const int done = t.pcg->done;
   const int nx = I.nx, ny = I.ny;
+  scalars_ready(done, nx, ny, I.zf.p, I.d0.p, I.d1.p);
+  if (done) return;
   const CDI_GLOBAL double* __restrict__ dold = parity ? I.d0 : I.d1;
   CDI_GLOBAL double* __restrict__ dnew = parity ? I.d1 : I.d0;
   const double* __restrict__ z = I.zf;
   const CDI_GLOBAL double* __restrict__ rv = rsel ? I.rr2 : I.rr;
-  const bool first = I.pcg->first != 0;
-  const double beta = first ? 0.0 : I.pcg->beta;
+  const bool first = t.pcg->first != 0;
+  const double beta = first ? 0.0 : t.pcg->beta;
   // every global read of the thread first: d over the tile and its halo,
   // then the coefficients and r of its own rows
   constexpr int ND = (RY * RX + kNT - 1) / kNT;
@@ -714,12 +716,17 @@ __global__ void __launch_bounds__(kNT) k_mg_down(const Tile* __restrict__ tiles,
   S* const s_rp = s_r;
   const Tile t = tiles[blockIdx.x];
   const Inst& I = insts[t.inst];
-  if (I.pcg->done) return;
   const Level& L = I.lev[level];
+  // the done flag (its address is in the tile) and the level's scalars are
+  // read together
+  const int done = t.pcg->done;
   const int nx = L.nx, ny = L.ny;
+  if constexpr (L0) scalars_ready(done, nx, ny, L.ax.p, L.ay.p, I.rr.p, I.rr2.p);
+  else scalars_ready(done, nx, ny, L.ax.p, L.ay.p, L.r.p);
+  if (done) return;
   const int i0 = t.i0, j0 = t.j0;
   const bool upd = update && L0;   // L0: level == 0 (the launch's every tile)
-  const double alpha = upd ? I.pcg->alpha : 0.0;
+  const double alpha = upd ? t.pcg->alpha : 0.0;
   // level-0 residual: read the previous buffer when updating, write the current one
   const double* __restrict__ rin = (upd ? (rsel ? I.rr : I.rr2) : (rsel ? I.rr2 : I.rr));
   CDI_GLOBAL double* __restrict__ rout = rsel ? I.rr2 : I.rr;
@@ -954,10 +961,14 @@ __global__ void __launch_bounds__(kNT) k_mg_up(const Tile* __restrict__ tiles,
   S* const s_e = s_r;
   const Tile t = tiles[blockIdx.x];
   const Inst& I = insts[t.inst];
-  if (I.pcg->done) return;
   const Level& L = I.lev[level];
   const Level& C = I.lev[level + 1];
+  // the done flag (its address is in the tile) and the levels' scalars are
+  // read together
+  const int done = t.pcg->done;
   const int nx = L.nx, ny = L.ny;
+  scalars_ready(done, nx, ny, C.nx, C.ny, L.ax.p, L.ay.p, L.z.p);
+  if (done) return;
   const int i0 = t.i0, j0 = t.j0;
   const int Jb = ((j0 - H) >> 1) - 1, Ib = ((i0 - H) >> 1) - 1;
   // every global read of the thread is issued before the first LDS store.
@@ -1706,8 +1717,12 @@ __global__ void __launch_bounds__(kCoarseNT) k_mg_coarse(const Inst* __restrict_
   __shared__ CoarseLds<S> C;
   __shared__ WideLds<S> W;
   const Inst& I = insts[blockIdx.x];
-  if (I.pcg->done) return;
   const int lg = I.lg, lc = I.lc, nl = I.nlev;
+  // the done flag and the start level's scalars are read together
+  const int done = I.pcg->done;
+  const Level& Lg = I.lev[lg];
+  scalars_ready(done, lc, nl, Lg.nx, Lg.ny, Lg.ax.p, Lg.ay.p, Lg.r.p);
+  if (done) return;
   const bool wide = lg + 1 == lc && I.lev[lg].nx * I.lev[lg].ny <= kWideCells &&
                     (I.lev[lg].nx & 1) == 0;
   const int tid = threadIdx.x;
