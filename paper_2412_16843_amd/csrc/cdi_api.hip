@@ -123,6 +123,8 @@ cdi_status resolve(const cdi_params* in, Resolved& r) {
   }
   if (cells > kCLX || yfaces > kCLY)
     return fail(CDI_ERR_SHAPE, "coarse multigrid levels too large for one block");
+  if (r.nlev - r.lc > kMaxCoarseLevels)
+    return fail(CDI_ERR_SHAPE, "more than %d coarse multigrid levels", kMaxCoarseLevels);
   return CDI_OK;
 }
 
@@ -371,6 +373,18 @@ void fill_inst(const Resolved& R, const cdi_fields& f, Inst& I) {
   const cdi_params& p = R.p;
   I.nx = p.nx; I.ny = p.ny;
   I.nlev = R.nlev; I.lc = R.lc; I.lg = R.lg;
+  {
+    int a = 0, b = 0;
+    for (int m = 0; m <= kMaxCoarseLevels; ++m) {
+      I.cpre_x[m] = a;
+      I.cpre_y[m] = b;
+      const int l = R.lc + m;
+      if (m < kMaxCoarseLevels && l < R.nlev) {
+        a += R.lnx[l] * R.lny[l];
+        b += (R.lny[l] + 1) * R.lnx[l];
+      }
+    }
+  }
   I.nu = p.mg_smooth > 0 ? p.mg_smooth : 1;
   I.slip_model = p.slip_model;
   I.mixed = p.precision == CDI_MIXED;

@@ -13,6 +13,9 @@
 namespace cdi {
 
 constexpr int kMaxLevels = 14;
+// levels held in the one-block coarse kernel's LDS (from a level of at most
+// 1024 cells, halving while above 64: 1024, 256, 64)
+constexpr int kMaxCoarseLevels = 4;
 constexpr int kHistDepth = 4;    // steps of per-stage pressure kept for the initial guess
 constexpr int kNT = 256;          // threads per block of every tiled kernel
 constexpr double kDeltaN = 1e-12; // normal-vector regularisation: n = G/(|G| + dN)
@@ -92,6 +95,9 @@ struct Inst {
   int nx, ny;
   int nlev, lc;             // multigrid levels; first level held in the coarse kernel's LDS
   int lg;                   // first level done by the one-block coarse kernel (lg <= lc)
+  // LDS offsets of the coarse levels lc + m (cells, y-faces): prefix sums,
+  // the total repeated past the last level
+  int cpre_x[kMaxCoarseLevels + 1], cpre_y[kMaxCoarseLevels + 1];
   int nu;                   // red-black sweep pairs before and after the coarse correction
   int slip_model, mixed;
   int first_tile, ntiles;   // tiles of level 0 in the cell tile list

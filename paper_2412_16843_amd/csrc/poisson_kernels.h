@@ -1540,11 +1540,7 @@ struct CoarseLds {
 // levels are stored one after the other from lc.
 template <typename S>
 __device__ __forceinline__ MgView<S> coarse_view(const Inst& I, CoarseLds<S>& C, int l) {
-  int a = 0, b = 0;
-  for (int m = I.lc; m < l; ++m) {
-    a += I.lev[m].nx * I.lev[m].ny;
-    b += (I.lev[m].ny + 1) * I.lev[m].nx;
-  }
+  const int a = I.cpre_x[l - I.lc], b = I.cpre_y[l - I.lc];
   MgView<S> v;
   v.nx = I.lev[l].nx; v.ny = I.lev[l].ny;
   v.ax = C.ax + a; v.ay = C.ay + b;
@@ -1564,20 +1560,23 @@ __device__ __forceinline__ void coarse_load_coef(const Inst& I, CoarseLds<S>& C,
   constexpr int NX = (kCLX + kCoarseNT - 1) / kCoarseNT;
   constexpr int NY = (kCLY + kCoarseNT - 1) / kCoarseNT;
   // flat index f of the concatenated x (y) arrays -> level and offset, by
-  // selects over the (uniform) levels, so that the reads that follow are
-  // unconditional: element 0 of level lc stands in past the last level
+  // selects over the coarse levels' prefix sums (a fixed number of them, so
+  // the scalar reads of every level's base address are issued together and
+  // the vector reads that follow are unconditional: element 0 of level lc
+  // stands in past the last level)
   auto locate = [&](int f, bool yf, const CDI_GLOBAL S*& src) {
     const Level& L0 = I.lev[I.lc];
     src = yf ? gas<const S>(L0.ay) : gas<const S>(L0.ax);
     bool found = false;
-    for (int l = I.lc; l < I.nlev; ++l) {
-      const Level& L = I.lev[l];
-      const int n = yf ? (L.ny + 1) * L.nx : L.nx * L.ny;
-      const bool here = !found && f < n;
+#pragma unroll
+    for (int m = 0; m < kMaxCoarseLevels; ++m) {
+      const int lo = yf ? I.cpre_y[m] : I.cpre_x[m];
+      const int hi = yf ? I.cpre_y[m + 1] : I.cpre_x[m + 1];
+      const Level& L = I.lev[min(I.lc + m, kMaxLevels - 1)];
       const CDI_GLOBAL S* base = yf ? gas<const S>(L.ay) : gas<const S>(L.ax);
-      src = here ? base + f : src;
+      const bool here = f >= lo && f < hi;
+      src = here ? base + (f - lo) : src;
       found = found || here;
-      f -= found ? 0 : n;
     }
     return found;
   };
