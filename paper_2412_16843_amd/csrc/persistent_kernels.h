@@ -53,11 +53,12 @@ __device__ int persist_solve(const Inst& I, PersistLds<S>& L, int guess,
   double* r = I.rr;
   double* d = I.d0;
   double* q = I.q;
+  const GuessSrc G = guess_src(I, stage, hw);
   double s2[2] = {0.0, 0.0};
   for (int c = tid; c < n; c += PNT) {
     const int j = dn.div(c), i = c - j * nx;
     double f, rv;
-    pcg_init_cell(I, guess, stage, hw, j, i, bmean, f, rv);
+    pcg_init_cell(I, G, guess, j, i, bmean, f, rv);
     s2[0] += f * f;
     s2[1] += rv * rv;
   }

@@ -73,51 +73,43 @@ __device__ __forceinline__ RhsIn rhs_load(const Inst& I, const double* __restric
   return v;
 }
 
-// b at cell row j from the gathered values (the arithmetic of rhs_store).
-__device__ __forceinline__ double rhs_value(const Inst& I, const RhsIn& v, int j, double tau) {
-  const int ny = I.ny;
-  const double r1 = I.rho1, r2 = I.rho2;
-  const double rc = (r1 - r2) * v.pc + r2;
-  const double rw = (r1 - r2) * v.pw + r2;
-  const double re = (r1 - r2) * v.pe + r2;
-  const double rfw = 0.5 * (rw + rc), rfe = 0.5 * (rc + re);
-  const double uw = v.mxo / rfw;
-  const double ue = v.mxe / rfe;
-  double vs = 0.0, vn = 0.0;
-  if (j >= 1) {
-    const double rs = (r1 - r2) * v.ps + r2;
-    vs = v.myo / (0.5 * (rs + rc));
-  }
-  if (j + 1 <= ny - 1) {
-    const double rn = (r1 - r2) * v.pn + r2;
-    vn = v.myn / (0.5 * (rc + rn));
-  }
+// Arithmetic of the right-hand side: every face value is the face's momentum
+// times the reciprocal of its density rho_f = (rho_a + rho_b)/2, and the
+// same reciprocal times 1/h^2 is the face's operator coefficient.  A face is
+// shared by two cells; k_rhs forms each reciprocal once and hands it to the
+// neighbour (the per-cell form below forms both and gets the same bits).
+__device__ __forceinline__ double rho_of(const Inst& I, double phi) {
+  return (I.rho1 - I.rho2) * phi + I.rho2;
+}
+__device__ __forceinline__ double inv_face_rho(double ra, double rb) {
+  return 1.0 / (0.5 * (ra + rb));
+}
+// b from the four face velocities
+__device__ __forceinline__ double rhs_div(const Inst& I, double uw, double ue, double vs, double vn,
+                                          double tau) {
   return ((ue - uw) + (vn - vs)) * I.inv_h / (tau * I.dt);
 }
 
 template <typename S>
 __device__ __forceinline__ double rhs_store(const Inst& I, const RhsIn& v, int j, int i,
                                             double tau) {
-  const int nx = I.nx;
+  const int nx = I.nx, ny = I.ny;
   const unsigned o = (unsigned)(j * nx) + i;
-  const double r1 = I.rho1, r2 = I.rho2;
-  const double rc = (r1 - r2) * v.pc + r2;
-  const double rw = (r1 - r2) * v.pw + r2;
-  const double rfw = 0.5 * (rw + rc);
-  const double uw = v.mxo / rfw;
-  double vs = 0.0, rfs = 0.0;
-  if (j >= 1) {
-    const double rs = (r1 - r2) * v.ps + r2;
-    rfs = 0.5 * (rs + rc);
-    vs = v.myo / rfs;
-  }
-  const double b = rhs_value(I, v, j, tau);
+  const double rc = rho_of(I, v.pc);
+  const double irw = inv_face_rho(rho_of(I, v.pw), rc);
+  const double ire = inv_face_rho(rc, rho_of(I, v.pe));
+  const double irs = j >= 1 ? inv_face_rho(rho_of(I, v.ps), rc) : 0.0;
+  const double irn = j + 1 <= ny - 1 ? inv_face_rho(rc, rho_of(I, v.pn)) : 0.0;
+  const double uw = v.mxo * irw, ue = v.mxe * ire;
+  const double vs = j >= 1 ? v.myo * irs : 0.0;
+  const double vn = j + 1 <= ny - 1 ? v.myn * irn : 0.0;
+  const double b = rhs_div(I, uw, ue, vs, vn, tau);
   I.ustar[o] = uw;
   I.vstar[o] = vs;
   I.b[o] = b;
   const double ih2 = I.inv_h * I.inv_h;
-  const double ax = ih2 / rfw;
-  const double ay = j >= 1 ? ih2 / rfs : 0.0;
+  const double ax = ih2 * irw;
+  const double ay = j >= 1 ? ih2 * irs : 0.0;
   I.ax0[o] = ax;
   I.ay0[o] = ay;
   if (I.mixed) {
@@ -133,27 +125,84 @@ __device__ __forceinline__ double rhs_cell(const Inst& I, const double* __restri
   return rhs_store<S>(I, rhs_load(I, ph, j, i), j, i, tau);
 }
 
+// Wide-tile form: a wave holds TX = 64 consecutive cells of a row and each
+// thread WR consecutive rows, so the east face's reciprocal density comes
+// from the next lane (formed directly at the wave's last lane and where the
+// row wraps) and the north face's from the thread's next row (formed
+// directly for its last row): two divisions per cell instead of four.
 template <typename S, int WR>
 __global__ void __launch_bounds__(kNT) k_rhs(const Tile* __restrict__ tiles,
                                               const Inst* __restrict__ insts, int src, double tau,
                                               double rtol, int maxit) {
+  static_assert(TX == 64, "one wave per row of the tile");
   __shared__ double sh[2 * kNT / 64];
   const Tile t = tiles[blockIdx.x];
   const Inst& I = insts[t.inst];
   const int nx = I.nx, ny = I.ny;
   const CDI_GLOBAL double* __restrict__ ph = src == 0 ? I.phi : (src == 1 ? I.phi_a : I.phi_b);
-  double bsum[2] = {0.0, 0.0};
-  RhsIn v[WR];
+  const int lane = (int)threadIdx.x % TX;
+  const int i = t.i0 + lane;
+  const int jb = t.j0 + ((int)threadIdx.x / TX) * WR;   // the thread's first row
+  const bool col = i < nx;
+  const int ie = wrap(i + 1, nx), iw = wrap(i - 1, nx);
+  // every global read first: phi of column i on rows jb-1 .. jb+WR, phi of
+  // the west and east columns, the x-momentum on the west and east faces and
+  // the y-momentum on the south faces of rows jb .. jb+WR
+  double pc[WR + 2], pw[WR], pe[WR], mxo[WR], mxe[WR], myo[WR + 1];
 #pragma unroll
-  for (int r = 0; r < WR; ++r) {
-    const int i = t.i0 + wide_tx(), j = t.j0 + wide_ty(r);
-    if (i < nx && j < ny) v[r] = rhs_load(I, ph, j, i);
+  for (int k = 0; k < WR + 2; ++k) {
+    const int j = jb - 1 + k;
+    pc[k] = (col && j >= 0 && j < ny) ? ph[(unsigned)(j * nx) + i] : 0.0;
   }
 #pragma unroll
   for (int r = 0; r < WR; ++r) {
-    const int i = t.i0 + wide_tx(), j = t.j0 + wide_ty(r);
-    if (i < nx && j < ny) {
-      const double b = rhs_store<S>(I, v[r], j, i, tau);
+    const int j = jb + r;
+    const bool in = col && j < ny;
+    pw[r] = in ? ph[(unsigned)(j * nx) + iw] : 0.0;
+    pe[r] = in ? ph[(unsigned)(j * nx) + ie] : 0.0;
+    mxo[r] = in ? I.mx[(unsigned)(j * nx) + i] : 0.0;
+    mxe[r] = in ? I.mx[(unsigned)(j * nx) + ie] : 0.0;
+  }
+#pragma unroll
+  for (int r = 0; r < WR + 1; ++r) {
+    const int j = jb + r;
+    myo[r] = (col && j >= 1 && j < ny) ? I.my[(unsigned)(j * nx) + i] : 0.0;
+  }
+  double rho[WR + 2], irw[WR], irs[WR + 1];
+#pragma unroll
+  for (int k = 0; k < WR + 2; ++k) rho[k] = rho_of(I, pc[k]);
+#pragma unroll
+  for (int r = 0; r < WR; ++r) irw[r] = inv_face_rho(rho_of(I, pw[r]), rho[r + 1]);
+#pragma unroll
+  for (int r = 0; r < WR + 1; ++r) {   // south face of row jb + r (r = WR: north of the last row)
+    const int j = jb + r;
+    irs[r] = (j >= 1 && j < ny) ? inv_face_rho(rho[r], rho[r + 1]) : 0.0;
+  }
+  const double ih2 = I.inv_h * I.inv_h;
+  const bool own_e = lane + 1 < TX && i + 1 < nx;   // the east face is the next lane's west face
+  double bsum[2] = {0.0, 0.0};
+#pragma unroll
+  for (int r = 0; r < WR; ++r) {
+    const int j = jb + r;
+    double ire = __shfl_down(irw[r], 1, TX);
+    if (!own_e) ire = inv_face_rho(rho[r + 1], rho_of(I, pe[r]));
+    if (col && j < ny) {
+      const unsigned o = (unsigned)(j * nx) + i;
+      const double uw = mxo[r] * irw[r], ue = mxe[r] * ire;
+      const double vs = j >= 1 ? myo[r] * irs[r] : 0.0;
+      const double vn = j + 1 <= ny - 1 ? myo[r + 1] * irs[r + 1] : 0.0;
+      const double b = rhs_div(I, uw, ue, vs, vn, tau);
+      I.ustar[o] = uw;
+      I.vstar[o] = vs;
+      I.b[o] = b;
+      const double ax = ih2 * irw[r];
+      const double ay = j >= 1 ? ih2 * irs[r] : 0.0;
+      I.ax0[o] = ax;
+      I.ay0[o] = ay;
+      if (I.mixed) {
+        (gas<S>(I.lev[0].ax))[o] = (S)ax;
+        (gas<S>(I.lev[0].ay))[o] = (S)ay;
+      }
       bsum[0] += b;
       bsum[1] += b * b;
     }
@@ -202,32 +251,52 @@ __device__ __forceinline__ double apply_K(const Inst& I, const double* __restric
 // kHistDepth slots: step s writes slot s mod kHistDepth (hw, the slot the
 // current step writes), so the pressure d + 1 steps back is in slot
 // hw - 1 - d and no step moves the older entries.
-__device__ __forceinline__ double base_guess(const Inst& I, int guess, int stage, int hw,
-                                             unsigned o) {
+// The arrays and scalars a guess reads, gathered once per thread (uniform
+// values: one batch of scalar reads instead of one per cell and case).
+struct GuessSrc {
+  const CDI_GLOBAL double* p;      // last pressure
+  const CDI_GLOBAL double* h[4];   // the stage's pressure d + 1 steps back (ring slot hw - 1 - d)
+  const CDI_GLOBAL double* zf;     // network output (learned guess)
+  double gscale, gscale2;
+  int gbase;
+};
+
+__device__ __forceinline__ GuessSrc guess_src(const Inst& I, int stage, int hw) {
   static_assert(kHistDepth == 4, "ring slots are taken mod 4");
-  auto H = [&](int d) { return I.hp[(hw + 3 - d) & 3][stage][o]; };
+  GuessSrc g;
+  const int s = stage >= 0 ? stage : 0;   // no history outside a time step
+  g.p = I.p;
+#pragma unroll
+  for (int d = 0; d < 4; ++d) g.h[d] = I.hp[(hw + 3 - d) & 3][s];
+  g.zf = I.zf;
+  g.gscale = I.pcg->gscale;
+  g.gscale2 = I.pcg->gscale2;
+  g.gbase = I.pcg->gbase;
+  return g;
+}
+
+__device__ __forceinline__ double base_guess(const GuessSrc& G, int guess, unsigned o) {
   switch (guess) {
-    case 1: return I.p[o];
-    case 3: return H(0);
-    case 4: return 2.0 * H(0) - H(1);
-    case 5: return 3.0 * (H(0) - H(1)) + H(2);
-    case 6: return 4.0 * (H(0) + H(2)) - 6.0 * H(1) - H(3);
+    case 1: return G.p[o];
+    case 3: return G.h[0][o];
+    case 4: return 2.0 * G.h[0][o] - G.h[1][o];
+    case 5: return 3.0 * (G.h[0][o] - G.h[1][o]) + G.h[2][o];
+    case 6: return 4.0 * (G.h[0][o] + G.h[2][o]) - 6.0 * G.h[1][o] - G.h[3][o];
     default: return 0.0;
   }
 }
 
-__device__ __forceinline__ double guess_value(const Inst& I, int guess, int stage, int hw,
-                                              unsigned o) {
+__device__ __forceinline__ double guess_value(const GuessSrc& G, int guess, unsigned o) {
   if (guess == 2) {
-    const double b = I.pcg->gscale * base_guess(I, I.pcg->gbase, stage, hw, o);
-    const double c = I.pcg->gscale2;   // 0 when the network output was dropped
-    return c != 0.0 ? b + c * I.zf[o] : b;
+    const double b = G.gscale * base_guess(G, G.gbase, o);
+    const double c = G.gscale2;   // 0 when the network output was dropped
+    return c != 0.0 ? b + c * G.zf[o] : b;
   }
-  return base_guess(I, guess, stage, hw, o);
+  return base_guess(G, guess, o);
 }
 
 // f = -(b - mean b), x0 and r0 = f - K x0 at cell (j, i).
-__device__ __forceinline__ void pcg_init_cell(const Inst& I, int guess, int stage, int hw, int j,
+__device__ __forceinline__ void pcg_init_cell(const Inst& I, const GuessSrc& G, int guess, int j,
                                               int i, double bmean, double& f, double& r) {
   const int nx = I.nx, ny = I.ny;
   const unsigned o = (unsigned)(j * nx) + i;
@@ -235,12 +304,11 @@ __device__ __forceinline__ void pcg_init_cell(const Inst& I, int guess, int stag
   r = f;
   if (guess) {
     const int ie = wrap(i + 1, nx), iw = wrap(i - 1, nx);
-    const double xc = guess_value(I, guess, stage, hw, o);
-    double kx = I.ax0[o] * (xc - guess_value(I, guess, stage, hw, (unsigned)(j * nx) + iw)) +
-                I.ax0[(unsigned)(j * nx) + ie] *
-                    (xc - guess_value(I, guess, stage, hw, (unsigned)(j * nx) + ie));
-    if (j >= 1) kx += I.ay0[o] * (xc - guess_value(I, guess, stage, hw, o - nx));
-    if (j + 1 < ny) kx += I.ay0[o + nx] * (xc - guess_value(I, guess, stage, hw, o + nx));
+    const double xc = guess_value(G, guess, o);
+    double kx = I.ax0[o] * (xc - guess_value(G, guess, (unsigned)(j * nx) + iw)) +
+                I.ax0[(unsigned)(j * nx) + ie] * (xc - guess_value(G, guess, (unsigned)(j * nx) + ie));
+    if (j >= 1) kx += I.ay0[o] * (xc - guess_value(G, guess, o - nx));
+    if (j + 1 < ny) kx += I.ay0[o + nx] * (xc - guess_value(G, guess, o + nx));
     r = f - kx;
     I.x[o] = xc;
   } else {
@@ -262,6 +330,7 @@ __global__ void __launch_bounds__(kNT) k_pcg_init(const Tile* __restrict__ tiles
   const Inst& I = insts[t.inst];
   const int nx = I.nx, ny = I.ny;
   const double bmean = I.pcg->bmean;
+  const GuessSrc G = guess_src(I, stage, hw);
   if (guess) {
     // the guess over the tile and its halo: all reads of the thread first
     constexpr int NG = (RY * RX + kNT - 1) / kNT;
@@ -272,7 +341,7 @@ __global__ void __launch_bounds__(kNT) k_pcg_init(const Tile* __restrict__ tiles
       const int rj = k / RX, ri = k - rj * RX;
       const int j = t.j0 - 1 + rj;
       gv[e] = (k < RY * RX && j >= 0 && j < ny)
-                  ? guess_value(I, guess, stage, hw, (unsigned)(j * nx) + wrap_any(t.i0 - 1 + ri, nx))
+                  ? guess_value(G, guess, (unsigned)(j * nx) + wrap_any(t.i0 - 1 + ri, nx))
                   : 0.0;
     }
 #pragma unroll
@@ -474,6 +543,7 @@ __global__ void __launch_bounds__(kNT) k_guess_fit(const Tile* __restrict__ tile
   const Tile t = tiles[blockIdx.x];
   const Inst& I = insts[t.inst];
   const int nx = I.nx, ny = I.ny;
+  const GuessSrc G = guess_src(I, stage, hw);
   double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};   // pKp, pKg, gKg, p.f, g.f
   for (int r = 0; r < WR; ++r) {
     const int i = t.i0 + wide_tx(), j = t.j0 + wide_ty(r);
@@ -481,13 +551,12 @@ __global__ void __launch_bounds__(kNT) k_guess_fit(const Tile* __restrict__ tile
       const unsigned o = (unsigned)(j * nx) + i;
       const double f = -(I.b[o] - I.pcg->bmean);
       const int ie = wrap(i + 1, nx), iw = wrap(i - 1, nx);
-      const double pv = base_guess(I, base, stage, hw, o), gv = I.zf[o];
+      const double pv = base_guess(G, base, o), gv = I.zf[o];
       // K applied to the base (apply_K's terms, with base values)
-      double kp = I.ax0[o] * (pv - base_guess(I, base, stage, hw, (unsigned)(j * nx) + iw)) +
-                  I.ax0[(unsigned)(j * nx) + ie] *
-                      (pv - base_guess(I, base, stage, hw, (unsigned)(j * nx) + ie));
-      if (j >= 1) kp += I.ay0[o] * (pv - base_guess(I, base, stage, hw, o - nx));
-      if (j + 1 < ny) kp += I.ay0[o + nx] * (pv - base_guess(I, base, stage, hw, o + nx));
+      double kp = I.ax0[o] * (pv - base_guess(G, base, (unsigned)(j * nx) + iw)) +
+                  I.ax0[(unsigned)(j * nx) + ie] * (pv - base_guess(G, base, (unsigned)(j * nx) + ie));
+      if (j >= 1) kp += I.ay0[o] * (pv - base_guess(G, base, o - nx));
+      if (j + 1 < ny) kp += I.ay0[o + nx] * (pv - base_guess(G, base, o + nx));
       const double kg = apply_K(I, I.zf, j, i);
       s[0] += pv * kp; s[1] += pv * kg; s[2] += gv * kg; s[3] += pv * f; s[4] += gv * f;
     }
