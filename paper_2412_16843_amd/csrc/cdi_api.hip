@@ -571,13 +571,20 @@ void launch_vcycle(cdi_ctx* c, int update, int dpar, int rsel) {
 template <typename S>
 void launch_coef(cdi_ctx* c) {
   const int only_variable = c->coef_ready ? 1 : 0;
-  for (int l = 1; l < c->B.max_nlev; ++l) {
+  // the tiled levels 1 .. lg-1 one launch per level, then every level from
+  // lg in one launch (one block per instance)
+  for (int l = 1; l < c->B.max_lg; ++l) {
     int maxc = 0;
     for (int k = 0; k < c->B.n; ++k)
-      if (c->B.R[k].nlev > l) maxc = std::max(maxc, c->B.R[k].lnx[l] * (c->B.R[k].lny[l] + 1));
+      if (c->B.R[k].nlev > l && c->B.R[k].lg > l)
+        maxc = std::max(maxc, c->B.R[k].lnx[l] * (c->B.R[k].lny[l] + 1));
     const dim3 grid((unsigned)std::max(1, std::min(1024, ceil_div(maxc, kNT))), (unsigned)c->B.n);
     timed(c, "mg_coef", [&] { CDI_LAUNCH(c, k_mg_coef<S>, grid, kNT, c->d_inst, l, only_variable); });
   }
+  if (c->B.max_nlev > 1)
+    timed(c, "mg_coef", [&] {
+      CDI_LAUNCH(c, k_mg_coef_small<S>, (unsigned)c->B.n, kCoarseNT, c->d_inst, only_variable);
+    });
   if (!only_variable)
     timed(c, "mg_coef", [&] { CDI_LAUNCH(c, k_coarse_inv<S>, (unsigned)c->B.n, kCoarseNT, c->d_inst); });
 }

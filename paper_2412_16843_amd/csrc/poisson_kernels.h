@@ -1911,13 +1911,29 @@ __device__ __forceinline__ void mg_coef_level(const Inst& I, int l, int start, i
   }
 }
 
-// Level l of every instance that has it (grid.y = instance).
+// Level l (below the instance's coarse start level lg) of every instance
+// that has it (grid.y = instance).
 template <typename S>
 __global__ void __launch_bounds__(kNT) k_mg_coef(const Inst* __restrict__ insts, int l,
                                                  int only_variable) {
   const Inst& I = insts[blockIdx.y];
-  if (l >= I.nlev || (only_variable && I.coef_const)) return;
+  if (l >= I.nlev || l >= I.lg || (only_variable && I.coef_const)) return;
   mg_coef_level<S>(I, l, blockIdx.x * kNT + threadIdx.x, gridDim.x * kNT);
+}
+
+// The levels from lg (at least 1) of every instance (grid = instances), one
+// block each, level after level with a barrier between (the block's own
+// global writes are visible to it after the barrier): the small levels in
+// one launch instead of one launch per level.
+template <typename S>
+__global__ void __launch_bounds__(kCoarseNT) k_mg_coef_small(const Inst* __restrict__ insts,
+                                                             int only_variable) {
+  const Inst& I = insts[blockIdx.x];
+  if (only_variable && I.coef_const) return;
+  for (int l = I.lg > 1 ? I.lg : 1; l < I.nlev; ++l) {
+    mg_coef_level<S>(I, l, threadIdx.x, kCoarseNT);
+    __syncthreads();
+  }
 }
 
 // Dense inverse of the coarsest operator K_c + s 11^T / n (s its mean
