@@ -386,6 +386,7 @@ void fill_inst(const Resolved& R, const cdi_fields& f, Inst& I) {
     }
   }
   I.nu = p.mg_smooth > 0 ? p.mg_smooth : 1;
+  I.nu_c = I.nu + 1;
   I.slip_model = p.slip_model;
   I.mixed = p.precision == CDI_MIXED;
   I.h = R.h; I.inv_h = 1.0 / R.h;
@@ -1411,7 +1412,10 @@ static cdi_status apply_shape(cdi_ctx* c, int rows, long coarse_cells, int nu) {
   build_wide(B, rows);
   for (int k = 0; k < B.n; ++k) set_lg(B.R[k], coarse_cells);
   build_mg(B);
-  for (int k = 0; k < B.n; ++k) B.inst[k].nu = nu;
+  for (int k = 0; k < B.n; ++k) {
+    B.inst[k].nu = nu;
+    B.inst[k].nu_c = nu + 1;
+  }
   c->wide_rows = rows;
   c->coarse_cells = coarse_cells;
   c->nu = nu;

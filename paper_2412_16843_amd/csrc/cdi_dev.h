@@ -99,6 +99,9 @@ struct Inst {
   // the total repeated past the last level
   int cpre_x[kMaxCoarseLevels + 1], cpre_y[kMaxCoarseLevels + 1];
   int nu;                   // red-black sweep pairs before and after the coarse correction
+  int nu_c;                 // sweep pairs on the levels of the one-block coarse cycle: nu + 1
+                            // (its sweeps cost barrier latency, not bandwidth, and the extra
+                            // pair saves outer CG iterations)
   int slip_model, mixed;
   int first_tile, ntiles;   // tiles of level 0 in the cell tile list
   int first_wide, nwide;    // tiles of level 0 in the wide tile list

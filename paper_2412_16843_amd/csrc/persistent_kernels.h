@@ -79,7 +79,7 @@ __device__ int persist_solve(const Inst& I, PersistLds<S>& L, int guess,
       for (int c = tid; c < n; c += PNT) rl[c] = (S)r[c];
       __syncthreads();
     }
-    mg_cycle<S>(I, view, 0, I.nlev, L.red, L.sc, L.u.coarse.cg);
+    mg_cycle<S>(I, view, 0, I.nlev, I.nu, L.red, L.sc, L.u.coarse.cg);
     const S* z = view(0).z;
     // flexible CG: the new direction is K-orthogonalised against the last one
     double beta = 0.0;

@@ -1367,7 +1367,7 @@ __device__ __forceinline__ void restrict_block(const S* t, int nx, S* rc, int cn
 }
 
 template <typename S, typename ViewF>
-__device__ __forceinline__ void mg_cycle(const Inst& I, const ViewF& V, int lo, int nl,
+__device__ __forceinline__ void mg_cycle(const Inst& I, const ViewF& V, int lo, int nl, int nu,
                                          double* s_red, double* s_sc, double* s_vec,
                                          const DensePart* dp = nullptr) {
   const int tid = threadIdx.x;
@@ -1404,7 +1404,7 @@ __device__ __forceinline__ void mg_cycle(const Inst& I, const ViewF& V, int lo, 
       __syncthreads();
       owned_gs<S>(oc, Lv.z, nx, 1, false);
       __syncthreads();
-      for (int k = 1; k < I.nu; ++k) {
+      for (int k = 1; k < nu; ++k) {
         owned_gs<S>(oc, Lv.z, nx, 0, false);
         __syncthreads();
         owned_gs<S>(oc, Lv.z, nx, 1, false);
@@ -1416,7 +1416,7 @@ __device__ __forceinline__ void mg_cycle(const Inst& I, const ViewF& V, int lo, 
     __syncthreads();
     sweep(l, 1, false);
     __syncthreads();
-    for (int k = 1; k < I.nu; ++k) {
+    for (int k = 1; k < nu; ++k) {
       sweep(l, 0, false);
       __syncthreads();
       sweep(l, 1, false);
@@ -1579,14 +1579,14 @@ __device__ __forceinline__ void mg_cycle(const Inst& I, const ViewF& V, int lo, 
     __syncthreads();
     if (nx * ny <= kCoarseNT) {   // one cell per thread: coefficients in registers
       const OwnedCell<S> oc = owned_cell<S>(Lv, tid);
-      for (int k = 0; k < I.nu; ++k) {
+      for (int k = 0; k < nu; ++k) {
         owned_gs<S>(oc, z, nx, 1, false);
         __syncthreads();
         owned_gs<S>(oc, z, nx, 0, false);
         __syncthreads();
       }
     } else {
-      for (int k = 0; k < I.nu; ++k) {
+      for (int k = 0; k < nu; ++k) {
         sweep(l, 1, false);
         __syncthreads();
         sweep(l, 0, false);
@@ -1718,7 +1718,7 @@ __device__ __forceinline__ void wide_cycle(const Inst& I, int nx, int ny,
 #pragma unroll
     for (int m = 0; m < kWideOwn / 2; ++m) owned_gs<S>(oc[2 * m + 1], W.z, nx, 1, false);
     __syncthreads();
-    for (int s = 1; s < I.nu; ++s) {
+    for (int s = 1; s < I.nu_c; ++s) {
 #pragma unroll
       for (int m = 0; m < kWideOwn / 2; ++m) owned_gs<S>(oc[2 * m + 0], W.z, nx, 0, false);
       __syncthreads();
@@ -1733,7 +1733,7 @@ __device__ __forceinline__ void wide_cycle(const Inst& I, int nx, int ny,
   const MgView<S> Cv = coarse_view<S>(I, C, I.lc);
   restrict_block<S>(W.t, nx, Cv.r, Cv.nx, Cv.ny);
   __syncthreads();
-  mg_cycle<S>(I, [&](int l) { return coarse_view<S>(I, C, l); }, I.lc, I.nlev, C.red, C.sc,
+  mg_cycle<S>(I, [&](int l) { return coarse_view<S>(I, C, l); }, I.lc, I.nlev, I.nu_c, C.red, C.sc,
               C.cg, dp);
   // prolongation over all cells (the barrier below orders it before the
   // smoothing, whose cells are spread over the threads by colour)
@@ -1744,7 +1744,7 @@ __device__ __forceinline__ void wide_cycle(const Inst& I, int nx, int ny,
   }
   __syncthreads();
   {
-    for (int s = 0; s < I.nu; ++s) {
+    for (int s = 0; s < I.nu_c; ++s) {
 #pragma unroll
       for (int m = 0; m < kWideOwn / 2; ++m) owned_gs<S>(oc[2 * m + 1], W.z, nx, 1, false);
       __syncthreads();
@@ -1858,11 +1858,12 @@ __global__ void __launch_bounds__(kCoarseNT) k_mg_coarse(const Inst* __restrict_
     for (int k = 0; k < kWideOwn; ++k) owned_finish<S>(woc[k]);
   }
   if (lg >= lc)   // LDS levels only: views the compiler knows to be LDS (ds_ instructions)
-    mg_cycle<S>(I, [&](int l) { return coarse_view<S>(I, C, l); }, lg, nl, C.red, C.sc, C.cg, &dp);
+    mg_cycle<S>(I, [&](int l) { return coarse_view<S>(I, C, l); }, lg, nl, I.nu_c, C.red, C.sc, C.cg,
+                &dp);
   else if (wide)
     wide_cycle<S>(I, I.lev[lg].nx, I.lev[lg].ny, woc, W, C, &dp);
   else
-    mg_cycle<S>(I, view, lg, nl, C.red, C.sc, C.cg, &dp);
+    mg_cycle<S>(I, view, lg, nl, I.nu_c, C.red, C.sc, C.cg, &dp);
   // ---- publish the level-lg correction (and beta when it is level 0)
   {
     const Level& L = I.lev[lg];
