@@ -94,8 +94,10 @@ typedef struct {
   double poisson_rtol;   /* stop when ||f - K x||_2 <= rtol ||f||_2; 0 -> 1e-10       */
   int32_t poisson_maxit; /* 0 -> 200                                                  */
   int32_t mg_smooth;     /* red-black Gauss-Seidel sweep pairs before and after the
-                            coarse correction on every level: 1 or 2; 0 -> 1; larger
-                            values return CDI_ERR_ARG; equal across a batch           */
+                            coarse correction on the tiled levels (the levels of the
+                            one-block coarse cycle take one pair more; the persistent
+                            launch takes mg_smooth on every level): 1 or 2; 0 -> 1;
+                            larger values return CDI_ERR_ARG; equal across a batch   */
   double gamma_factor;   /* > 0: the regularisation velocity of each step is
                             min(gamma, gamma_factor * max |u|, |v| over the faces of
                             the state the step starts from), the paper's rule
@@ -394,8 +396,9 @@ cdi_status cdi_get_coarse_cells(cdi_ctx* ctx, int32_t* cells);
 cdi_status cdi_set_extrapolation(cdi_ctx* ctx, int32_t order);
 cdi_status cdi_get_extrapolation(cdi_ctx* ctx, int32_t* order);
 
-/* Red-black sweep pairs of the V-cycle (1 or 2; the value of mg_smooth at
- * init).  Changes the iteration count, not the converged solution. */
+/* Red-black sweep pairs of the V-cycle's tiled levels (1 or 2; the value of
+ * mg_smooth at init; the one-block coarse cycle takes one pair more).
+ * Changes the iteration count, not the converged solution. */
 cdi_status cdi_set_mg_smooth(cdi_ctx* ctx, int32_t nu);
 cdi_status cdi_get_mg_smooth(cdi_ctx* ctx, int32_t* nu);
 
