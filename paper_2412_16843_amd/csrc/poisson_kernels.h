@@ -686,8 +686,12 @@ __global__ void __launch_bounds__(kNT) k_project(const Tile* __restrict__ tiles,
   const Inst& I = insts[t.inst];
   const int nx = I.nx, ny = I.ny;
   const CDI_GLOBAL double* __restrict__ ph = src == 1 ? I.phi_a : I.phi_b;
-  const bool zero = I.pcg->zero_rhs != 0;
-  const double xmean = I.pcg->xmean;
+  // the CG scalars through the tile's address, read with the instance's
+  // fields in one batch (not again in every row's branch)
+  const int zero_rhs = t.pcg->zero_rhs;
+  const double xmean = t.pcg->xmean;
+  scalars_ready(nx, ny, zero_rhs, I.x.p, I.ustar.p, I.vstar.p, I.ax0.p, I.ay0.p);
+  const bool zero = zero_rhs != 0;
   ProjIn v[WR];
 #pragma unroll
   for (int r = 0; r < WR; ++r) {
