@@ -528,7 +528,8 @@ def main():
                      "frac": round(step_gbs / HBM_PEAK_GBS, 4)}
     head_cfg = [{"instances": len(ix), "cells": sum(params[k].nx * params[k].ny for k in ix),
                  "launch": g.get_launch(), "tile_rows": g.get_tile_rows(),
-                 "coarse_cells": g.get_coarse_cells(), "mg_smooth": g.get_mg_smooth()}
+                 "coarse_cells": g.get_coarse_cells(), "mg_smooth": g.get_mg_smooth(),
+                 "strip_rows": g.get_strip_rows()}
                 for ix, g in zip(head.groups, head.solvers)]
     head.close()
     del head

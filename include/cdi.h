@@ -420,7 +420,8 @@ typedef struct {
   int32_t coarse_cells;    /* chosen coarse-kernel threshold                       */
   int32_t mg_smooth;       /* chosen sweep pairs                                   */
   int32_t ncand;           /* candidates timed                                     */
-  int32_t pad;
+  int32_t strip_rows;      /* stage-kernel strip height (cdi_tune_concurrent only,
+                              else 0)                                              */
   double ms_per_step[14];  /* tiled [sweeps 1, 2] x [rows 1, 4] x [coarse 1024,
                               4096, 16384] (row-major), persistent, graph;
                               -1 = skipped                                         */
@@ -439,8 +440,10 @@ cdi_status cdi_tune(cdi_ctx* ctx, int32_t trial_steps, void* scratch, size_t scr
  * does.  The shape that is fastest alone is not the fastest when the
  * contexts share the GPU.  scratch[k]: device memory of at least
  * cdi_tune_bytes(ctxs[k]) bytes (scratch_bytes[k]); out (may be NULL) as
- * cdi_tune (ms_per_step slots 12 and 13 are -1).  Sets the tiled launch on
- * every context.  Synchronises every stream. */
+ * cdi_tune (ms_per_step slots 12 and 13 are -1).  With that shape it then
+ * times the stage kernel's strip heights (16, 32, 64 rows) the same way and
+ * keeps the fastest (out->strip_rows).  Sets the tiled launch on every
+ * context.  Synchronises every stream. */
 cdi_status cdi_tune_concurrent(cdi_ctx* const* ctxs, int32_t n, int32_t trial_steps,
                                void* const* scratch, const size_t* scratch_bytes,
                                cdi_tune_info* out);

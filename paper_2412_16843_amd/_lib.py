@@ -71,7 +71,7 @@ class cdi_diag(C.Structure):
 
 class cdi_tune_info(C.Structure):
     _fields_ = [("launch", C.c_int32), ("tile_rows", C.c_int32), ("coarse_cells", C.c_int32),
-                ("mg_smooth", C.c_int32), ("ncand", C.c_int32), ("pad", C.c_int32),
+                ("mg_smooth", C.c_int32), ("ncand", C.c_int32), ("strip_rows", C.c_int32),
                 ("ms_per_step", C.c_double * 14)]
 
 

@@ -1723,8 +1723,39 @@ cdi_status cdi_tune_concurrent(cdi_ctx* const* ctxs, int32_t n, int32_t trial_st
           snaps[k].rewind(ctxs[k]);
         }
       }
+  // then the stage kernel's strip height with that shape: the block-count
+  // rule that picks it for a context alone does not see the other contexts
+  // sharing the GPU
+  std::vector<int> strip0(n);
+  for (int k = 0; k < n; ++k) strip0[k] = ctxs[k]->B.strip_rows;
+  int pick_strip = -1;
+  for (int k = 0; k < n && st == CDI_OK; ++k) st = apply_shape(ctxs[k], pick_rows, pick_coarse, pick_nu);
+  for (int si = 0; si < 3 && st == CDI_OK; ++si) {
+    const int rows = kStripRows[si];
+    for (int k = 0; k < n && st == CDI_OK; ++k) st = apply_strip_rows(ctxs[k], rows);
+    if (st != CDI_OK) break;
+    cdi_status r1 = cdi_step_concurrent(ctxs, n, 1);
+    if (r1 != CDI_OK && r1 != CDI_ERR_NOCONV) { st = r1; break; }
+    if ((st = sync_all()) != CDI_OK) break;
+    const auto t0 = std::chrono::steady_clock::now();
+    r1 = cdi_step_concurrent(ctxs, n, trial_steps);
+    if (r1 != CDI_OK && r1 != CDI_ERR_NOCONV) { st = r1; break; }
+    if ((st = sync_all()) != CDI_OK) break;
+    const double per =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count() /
+        trial_steps;
+    info.ncand += 1;
+    if (pick_strip < 0 || per < best) { best = per; pick_strip = rows; }
+    for (int k = 0; k < n && st == CDI_OK; ++k) {
+      st = tune_copy(ctxs[k], (char*)scratch[k], false);
+      snaps[k].rewind(ctxs[k]);
+    }
+  }
   for (int k = 0; k < n; ++k) {
-    if (st != CDI_OK) (void)tune_copy(ctxs[k], (char*)scratch[k], false);
+    if (st != CDI_OK) {
+      (void)tune_copy(ctxs[k], (char*)scratch[k], false);
+      (void)apply_strip_rows(ctxs[k], strip0[k]);
+    }
     snaps[k].restore(ctxs[k]);
   }
   cdi_status ss = sync_all();
@@ -1732,12 +1763,14 @@ cdi_status cdi_tune_concurrent(cdi_ctx* const* ctxs, int32_t n, int32_t trial_st
   if (ss != CDI_OK) return ss;
   for (int k = 0; k < n; ++k) {
     if ((st = apply_shape(ctxs[k], pick_rows, pick_coarse, pick_nu)) != CDI_OK) return st;
+    if ((st = apply_strip_rows(ctxs[k], pick_strip)) != CDI_OK) return st;
     ctxs[k]->launch = CDI_LAUNCH_TILED;
   }
   info.launch = CDI_LAUNCH_TILED;
   info.tile_rows = pick_rows;
   info.coarse_cells = (int32_t)pick_coarse;
   info.mg_smooth = pick_nu;
+  info.strip_rows = pick_strip;
   if (out) *out = info;
   return CDI_OK;
 }

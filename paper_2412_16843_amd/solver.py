@@ -349,7 +349,7 @@ class EnsembleSolver:
                 for q, cc in enumerate((1024, 4096, 16384)):
                     ms[f"tiled_nu{nu}_rows{rows}_coarse{cc}"] = info.ms_per_step[v * 6 + r * 3 + q]
         return dict(launch="tiled", tile_rows=info.tile_rows, coarse_cells=info.coarse_cells,
-                    mg_smooth=info.mg_smooth, ms_per_step=ms)
+                    mg_smooth=info.mg_smooth, strip_rows=info.strip_rows, ms_per_step=ms)
 
     def diagnostics(self, idx: int = 0) -> Dict[str, float]:
         g, j = self.where[idx]

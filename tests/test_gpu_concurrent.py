@@ -126,6 +126,8 @@ def test_concurrent_tune_restores_the_state_and_sets_one_shape():
         assert s.get_tile_rows() == info["tile_rows"]
         assert s.get_coarse_cells() == info["coarse_cells"]
         assert s.get_mg_smooth() == info["mg_smooth"]
+        assert s.get_strip_rows() == info["strip_rows"]   # timed under concurrency too
+    assert info["strip_rows"] in (16, 32, 64)
     ens.step(1)
     assert all(ens.diagnostics(k)["step"] == 3 for k in range(len(cases)))
     # a scratch buffer below cdi_tune_bytes is refused before any work
